@@ -1,0 +1,112 @@
+"""CPU oracle for Brandes betweenness centrality -- TEST INFRASTRUCTURE.
+
+Only the test suite, the smoke check and the benchmark's CPU-baseline leg may
+import this package.  The GPU library never imports, links or calls it, and
+the two share no code.  The arithmetic lives in ``bc_oracle.c`` (plain C,
+IEEE double, no fast-math), which follows the paper's BC specification
+(Section "Background", the ComputeBC listing: forward sigma sums in BFS order,
+backward dependency sums in reverse BFS order, BC += delta for v != src), i.e.
+Brandes' algorithm for unweighted graphs.  Its readings of the listing are
+stated at the top of that file.
+
+Pins (tests/test_oracle_pins.py) tie it to facts fixed independently of it:
+brute-force path counting on tiny graphs, closed forms for path, star, cycle,
+tree, complete bipartite, complete and hypercube graphs, the distance-sum
+invariant, additivity over sources, and NetworkX's betweenness.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "bc_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "libbc_oracle.so")
+_lib = None
+
+OK = 0
+INVALID_ARG = 1
+RANGE = 4
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+def build() -> str:
+    """Compile libbc_oracle.so with gcc -O2 (OpenMP over sources; no fast-math)."""
+    tmp = _LIB_PATH + ".tmp"
+    cmd = ["gcc", "-O2", "-march=native", "-fno-fast-math", "-fopenmp", "-fPIC", "-shared",
+           "-std=c11", _SRC, "-o", tmp, "-lm"]
+    try:
+        subprocess.run(cmd, check=True)
+    except subprocess.CalledProcessError:
+        cmd.remove("-march=native")
+        subprocess.run(cmd, check=True)
+    os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        build()
+    lib = ctypes.CDLL(_LIB_PATH)
+    i32p = ctypes.POINTER(ctypes.c_int32)
+    f64p = ctypes.POINTER(ctypes.c_double)
+    lib.oracle_single_source.restype = ctypes.c_int
+    lib.oracle_single_source.argtypes = [ctypes.c_int32, i32p, i32p, ctypes.c_int32, i32p, f64p,
+                                         f64p]
+    lib.oracle_bc.restype = ctypes.c_int
+    lib.oracle_bc.argtypes = [ctypes.c_int32, i32p, i32p, i32p, ctypes.c_int32, ctypes.c_int,
+                              f64p]
+    lib.oracle_max_threads.restype = ctypes.c_int
+    lib.oracle_max_threads.argtypes = []
+    _lib = lib
+    return lib
+
+
+def _i32(a):
+    a = np.ascontiguousarray(a, dtype=np.int32)
+    return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+
+
+def max_threads() -> int:
+    return int(_load().oracle_max_threads())
+
+
+def single_source(row_ptr, col_idx, s: int, with_delta: bool = True):
+    """(dist int32[n], sigma float64[n], delta float64[n] or None, status) from source s."""
+    lib = _load()
+    rp, rpp = _i32(row_ptr)
+    ci, cip = _i32(col_idx)
+    n = rp.shape[0] - 1
+    dist = np.empty(n, dtype=np.int32)
+    sigma = np.empty(n, dtype=np.float64)
+    delta = np.empty(n, dtype=np.float64) if with_delta else None
+    st = lib.oracle_single_source(n, rpp, cip, int(s), dist.ctypes.data_as(ctypes.POINTER(
+        ctypes.c_int32)), sigma.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+        delta.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if with_delta else None)
+    if st == INVALID_ARG:
+        raise OracleError("invalid argument")
+    return dist, sigma, delta, st
+
+
+def bc(row_ptr, col_idx, sources, threads: int = 0):
+    """(BC float64[n], status): raw Brandes sum over `sources` (ordered pairs, no scaling)."""
+    lib = _load()
+    rp, rpp = _i32(row_ptr)
+    ci, cip = _i32(col_idx)
+    src, srcp = _i32(sources)
+    n = rp.shape[0] - 1
+    out = np.empty(n, dtype=np.float64)
+    st = lib.oracle_bc(n, rpp, cip, srcp if src.size else None, int(src.size), int(threads),
+                       out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    if st == INVALID_ARG:
+        raise OracleError("invalid argument")
+    return out, st

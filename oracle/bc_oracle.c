@@ -1,0 +1,195 @@
+/*
+ * CPU oracle for Brandes betweenness centrality on an unweighted CSR graph.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the plain, slow, obviously correct
+ * reference that the GPU library is checked against.  Only the test suite,
+ * the smoke check and the benchmark's CPU-baseline leg may load it; the GPU
+ * library neither links nor calls it, and it shares no code with the GPU
+ * library.
+ *
+ * What it computes follows the paper's BC specification (Section
+ * "Background", the ComputeBC listing), which runs Brandes' algorithm:
+ *
+ *   BC = 0 once per call.
+ *   For each source src of the source set, in the given order:
+ *     sigma = 0, delta = 0, sigma[src] = 1.
+ *     Forward pass (iterateInBFS): vertices are visited in BFS order from src
+ *       and each one sums sigma over its neighbours.
+ *     Backward pass (iterateInReverse, v != src): vertices are visited in
+ *       reverse BFS order and each one sums (sigma[v]/sigma[w]) * (1+delta[w])
+ *       over its neighbours w, then BC[v] += delta[v].
+ *
+ * Readings of points the listing leaves implicit:
+ *   - The neighbour loops run over the BFS DAG: the forward sum takes the
+ *     neighbours one level closer to src (the parents), the backward sum the
+ *     neighbours one level further (the children).  This is the only reading
+ *     that yields Brandes' dependencies, which the paper cites.
+ *   - Arithmetic is IEEE double (the listing declares float), the level of a
+ *     vertex is an int with -1 for "not reached", as in the generated BFS
+ *     kernel the paper prints.
+ *   - BC is the raw sum over the given sources: ordered pairs, no 1/2 and no
+ *     normalisation; a source repeated k times counts k times.
+ *   - A source does not add its own dependency to its BC (v != src).
+ *   - Parallel arcs count as distinct paths; self-loops never lie on a
+ *     shortest path and have no effect.
+ *
+ * Status codes: 0 = ok, 1 = invalid argument, 4 = some sigma is not finite
+ * (BC is then written but meaningless).
+ *
+ * Built with gcc -O2, no fast-math.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+enum { OR_OK = 0, OR_INVALID_ARG = 1, OR_RANGE = 4 };
+
+/* Breadth-first search from s.  dist[v] = hop distance or -1; order[] receives
+ * the reached vertices in the order they are dequeued (non-decreasing dist).
+ * Returns the number of reached vertices. */
+static int32_t bfs_order(int32_t n, const int32_t *row_ptr, const int32_t *col_idx, int32_t s,
+                         int32_t *dist, int32_t *order) {
+    for (int32_t v = 0; v < n; ++v) dist[v] = -1;
+    int32_t head = 0, tail = 0;
+    dist[s] = 0;
+    order[tail++] = s;
+    while (head < tail) {
+        int32_t v = order[head++];
+        for (int32_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {
+            int32_t w = col_idx[e];
+            if (dist[w] < 0) {
+                dist[w] = dist[v] + 1;
+                order[tail++] = w;
+            }
+        }
+    }
+    return tail;
+}
+
+/* One source: dist, sigma and delta for every vertex.  delta may be NULL
+ * (then only the forward pass runs).  bc, when not NULL, receives
+ * bc[v] += delta[v] for every reached v != s.  order is scratch of n int32.
+ * Returns OR_OK or OR_RANGE. */
+static int single_source(int32_t n, const int32_t *row_ptr, const int32_t *col_idx, int32_t s,
+                         int32_t *dist, double *sigma, double *delta, double *bc,
+                         int32_t *order) {
+    int32_t reached = bfs_order(n, row_ptr, col_idx, s, dist, order);
+
+    /* sigma = 0 everywhere, sigma[src] = 1. */
+    for (int32_t v = 0; v < n; ++v) sigma[v] = 0.0;
+    sigma[s] = 1.0;
+
+    /* Forward pass, BFS order: sigma[v] = sum of sigma over parents. */
+    int status = OR_OK;
+    for (int32_t i = 1; i < reached; ++i) {
+        int32_t v = order[i];
+        double acc = 0.0;
+        for (int32_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {
+            int32_t w = col_idx[e];
+            if (dist[w] == dist[v] - 1) acc = acc + sigma[w];
+        }
+        sigma[v] = acc;
+        if (!isfinite(acc)) status = OR_RANGE;
+    }
+    if (delta == NULL) return status;
+
+    /* Backward pass, reverse BFS order, v != src:
+     * delta[v] = sum over children w of (sigma[v]/sigma[w]) * (1 + delta[w]). */
+    for (int32_t v = 0; v < n; ++v) delta[v] = 0.0;
+    for (int32_t i = reached - 1; i >= 1; --i) {
+        int32_t v = order[i];
+        double acc = 0.0;
+        for (int32_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {
+            int32_t w = col_idx[e];
+            if (dist[w] == dist[v] + 1) acc = acc + (sigma[v] / sigma[w]) * (1.0 + delta[w]);
+        }
+        delta[v] = acc;
+        if (bc) bc[v] = bc[v] + delta[v];
+    }
+    return status;
+}
+
+static int check_graph_args(int32_t n, const int32_t *row_ptr, const int32_t *col_idx) {
+    if (n < 0 || (n > 0 && row_ptr == NULL)) return OR_INVALID_ARG;
+    if (n > 0 && row_ptr[n] > 0 && col_idx == NULL) return OR_INVALID_ARG;
+    return OR_OK;
+}
+
+/* dist[n], sigma[n], delta[n] (delta may be NULL) for one source. */
+int oracle_single_source(int32_t n, const int32_t *row_ptr, const int32_t *col_idx, int32_t s,
+                         int32_t *dist, double *sigma, double *delta) {
+    if (check_graph_args(n, row_ptr, col_idx) != OR_OK || s < 0 || s >= n || !dist || !sigma)
+        return OR_INVALID_ARG;
+    int32_t *order = (int32_t *)malloc((size_t)n * sizeof(int32_t));
+    int st = single_source(n, row_ptr, col_idx, s, dist, sigma, delta, NULL, order);
+    free(order);
+    return st;
+}
+
+/* bc[n] = sum over the k sources of their dependencies.  Sources are split
+ * statically over `threads` threads (0 = all available); each thread keeps its
+ * own partial BC, and the partials are added in thread order, so the result
+ * does not depend on scheduling.  With one thread the sources are processed in
+ * the given order. */
+int oracle_bc(int32_t n, const int32_t *row_ptr, const int32_t *col_idx, const int32_t *sources,
+              int32_t k, int threads, double *bc) {
+    if (check_graph_args(n, row_ptr, col_idx) != OR_OK || k < 0 || !bc ||
+        (k > 0 && !sources))
+        return OR_INVALID_ARG;
+    for (int32_t i = 0; i < k; ++i)
+        if (sources[i] < 0 || sources[i] >= n) return OR_INVALID_ARG;
+    for (int32_t v = 0; v < n; ++v) bc[v] = 0.0;
+    if (k == 0 || n == 0) return OR_OK;
+
+    int nt = 1;
+#ifdef _OPENMP
+    nt = threads > 0 ? threads : omp_get_max_threads();
+#else
+    (void)threads;
+#endif
+    if (nt > k) nt = k;
+    double *partial = (double *)calloc((size_t)nt * (size_t)n, sizeof(double));
+    int status = OR_OK;
+#pragma omp parallel num_threads(nt) reduction(max : status)
+    {
+        int t = 0;
+#ifdef _OPENMP
+        t = omp_get_thread_num();
+#endif
+        int32_t lo = (int32_t)((int64_t)k * t / nt), hi = (int32_t)((int64_t)k * (t + 1) / nt);
+        int32_t *dist = (int32_t *)malloc((size_t)n * sizeof(int32_t));
+        int32_t *order = (int32_t *)malloc((size_t)n * sizeof(int32_t));
+        double *sigma = (double *)malloc((size_t)n * sizeof(double));
+        double *delta = (double *)malloc((size_t)n * sizeof(double));
+        double *mine = partial + (size_t)t * (size_t)n;
+        for (int32_t i = lo; i < hi; ++i) {
+            int st = single_source(n, row_ptr, col_idx, sources[i], dist, sigma, delta, mine,
+                                   order);
+            if (st > status) status = st;
+        }
+        free(dist);
+        free(order);
+        free(sigma);
+        free(delta);
+    }
+    for (int t = 0; t < nt; ++t) {
+        const double *p = partial + (size_t)t * (size_t)n;
+        for (int32_t v = 0; v < n; ++v) bc[v] = bc[v] + p[v];
+    }
+    free(partial);
+    return status;
+}
+
+/* Number of threads oracle_bc uses when asked for all of them. */
+int oracle_max_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

@@ -1,0 +1,338 @@
+"""Pins for the CPU oracle: facts fixed independently of it.
+
+Each check is chosen so that a plausible slip in the oracle (a dropped term, a
+wrong sign, a wrong level offset, a transposed ratio, counting the source's own
+dependency, a missing reset between sources) breaks at least one of them;
+tests/test_oracle_mutants.py plants such slips in a copy of the oracle and
+checks that these pins catch them.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+from scipy.sparse.csgraph import shortest_path
+
+import graphgen as gg
+import oracle
+from tests.bruteforce import (adjacency, bc_by_definition, csr_from_adjacency, parse_golden,
+                              walk_dist_sigma)
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "hand_worked.txt")
+
+
+def all_bc(g, sources=None):
+    src = np.arange(g.n, dtype=np.int32) if sources is None else np.asarray(sources, np.int32)
+    bc, st = oracle.bc(g.row_ptr, g.col_idx, src)
+    assert st == oracle.OK
+    return bc
+
+
+def hop_distances(g, s):
+    """Unweighted hop distances by scipy's shortest_path (independent BFS)."""
+    m = sp.csr_matrix((np.ones(g.nnz), g.col_idx, g.row_ptr), shape=(g.n, g.n))
+    d = shortest_path(m, method="D", unweighted=True, indices=[s])[0]
+    return np.where(np.isinf(d), -1, d).astype(np.int64)
+
+
+# ---------------------------------------------------------------------------
+# Hand-worked examples (tests/golden/hand_worked.txt)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("case", parse_golden(GOLDEN), ids=lambda c: c["name"])
+def test_hand_worked(case):
+    e = np.asarray(case["edges"], dtype=np.int32).reshape(-1, 2)
+    g = gg.csr_from_edges(case["n"], e[:, 0], e[:, 1])
+    bc = all_bc(g, case["sources"])
+    np.testing.assert_allclose(bc, case["bc"], rtol=1e-15, atol=1e-15)
+    for s, d in case["dist"].items():
+        dist, sigma, _, st = oracle.single_source(g.row_ptr, g.col_idx, s)
+        assert st == oracle.OK
+        assert dist.tolist() == d
+        assert sigma.tolist() == case["sigma"][s]
+
+
+# ---------------------------------------------------------------------------
+# Brute force: walk counts + the definition
+# ---------------------------------------------------------------------------
+
+def _graphs_from_bits(n, bits_batch):
+    pairs = [(i, j) for i in range(n) for j in range(i + 1, n)]
+    A = np.zeros((len(bits_batch), n, n), dtype=np.int64)
+    for k, (i, j) in enumerate(pairs):
+        on = ((bits_batch >> k) & 1).astype(bool)
+        A[on, i, j] = 1
+        A[on, j, i] = 1
+    return A
+
+
+@pytest.mark.parametrize("n", [4, 5, 6])
+def test_exhaustive_small_graphs(n):
+    """Every labelled simple graph on n <= 6 vertices (2**15 graphs at n=6)."""
+    n_pairs = n * (n - 1) // 2
+    total = 1 << n_pairs
+    chunk = 2048
+    for lo in range(0, total, chunk):
+        bits = np.arange(lo, min(total, lo + chunk), dtype=np.int64)
+        A = _graphs_from_bits(n, bits)
+        want = bc_by_definition(A)
+        for gi in range(A.shape[0]):
+            rp, ci = csr_from_adjacency(A[gi])
+            got, st = oracle.bc(rp, ci, np.arange(n, dtype=np.int32))
+            assert st == oracle.OK
+            np.testing.assert_allclose(got, want[gi], rtol=1e-12, atol=1e-12,
+                                       err_msg=f"graph bits {bits[gi]}")
+
+
+def test_random_graphs_definition_and_subsets():
+    """G(n,p) up to 14 vertices, all sources and random source multisets."""
+    rng = np.random.default_rng(7)
+    for trial in range(120):
+        n = int(rng.integers(2, 15))
+        p = float(rng.uniform(0.1, 0.7))
+        g = gg.gnp(n, p, seed=trial)
+        A = adjacency(g.row_ptr, g.col_idx)
+        np.testing.assert_allclose(all_bc(g), bc_by_definition(A), rtol=1e-12, atol=1e-12)
+        srcs = rng.integers(0, n, size=int(rng.integers(1, 2 * n)))
+        np.testing.assert_allclose(all_bc(g, srcs), bc_by_definition(A, srcs), rtol=1e-12,
+                                   atol=1e-12)
+
+
+def test_multigraph_and_self_loops():
+    """Parallel arcs count as distinct paths; self-loops change nothing."""
+    rng = np.random.default_rng(11)
+    for trial in range(60):
+        n = int(rng.integers(3, 10))
+        m = int(rng.integers(n, 3 * n))
+        u = rng.integers(0, n, size=m)
+        v = rng.integers(0, n, size=m)
+        g = gg.csr_from_edges(n, u, v, dedup=False, drop_loops=False)
+        A = adjacency(g.row_ptr, g.col_idx)
+        np.testing.assert_allclose(all_bc(g), bc_by_definition(A), rtol=1e-12, atol=1e-12)
+        # dropping the loops leaves BC unchanged
+        g2 = gg.csr_from_edges(n, u, v, dedup=False, drop_loops=True)
+        np.testing.assert_allclose(all_bc(g2), all_bc(g), rtol=1e-12, atol=1e-12)
+
+
+def test_dist_sigma_walk_counts():
+    rng = np.random.default_rng(3)
+    for trial in range(60):
+        n = int(rng.integers(2, 16))
+        g = gg.gnp(n, float(rng.uniform(0.1, 0.6)), seed=100 + trial)
+        A = adjacency(g.row_ptr, g.col_idx)
+        D, S = walk_dist_sigma(A)
+        for s in range(n):
+            dist, sigma, _, st = oracle.single_source(g.row_ptr, g.col_idx, s)
+            assert st == oracle.OK
+            assert dist.tolist() == D[s].tolist()
+            assert sigma.tolist() == S[s].astype(np.float64).tolist()
+
+
+# ---------------------------------------------------------------------------
+# Closed forms
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n", [2, 3, 7, 50, 301])
+def test_path_closed_form(n):
+    i = np.arange(n)
+    np.testing.assert_array_equal(all_bc(gg.path(n)), 2.0 * i * (n - 1 - i))
+
+
+@pytest.mark.parametrize("n", [2, 3, 10, 257])
+def test_star_closed_form(n):
+    want = np.zeros(n)
+    want[0] = (n - 1) * (n - 2)
+    np.testing.assert_array_equal(all_bc(gg.star(n)), want)
+
+
+@pytest.mark.parametrize("n", [3, 4, 5, 6, 11, 12, 101, 128])
+def test_cycle_closed_form(n):
+    k = n // 2
+    val = k * (k - 1) if n % 2 else (k - 1) ** 2
+    np.testing.assert_allclose(all_bc(gg.cycle(n)), np.full(n, float(val)), rtol=1e-13)
+
+
+def test_cycle_sigma_antipode():
+    for n in (4, 10, 64):
+        dist, sigma, _, _ = oracle.single_source(gg.cycle(n).row_ptr, gg.cycle(n).col_idx, 0)
+        assert dist[n // 2] == n // 2 and sigma[n // 2] == 2.0
+        assert np.all(sigma[np.arange(n) != n // 2] == 1.0)
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_tree_closed_form(seed):
+    """BC(v) = (n-1)**2 - sum of squared component sizes of T - v; sigma = 1."""
+    n = 40 + 7 * seed
+    g = gg.random_tree(n, seed)
+    want = np.empty(n)
+    for v in range(n):
+        seen = np.zeros(n, bool)
+        seen[v] = True
+        sizes = []
+        for r in g.col_idx[g.row_ptr[v]:g.row_ptr[v + 1]]:
+            stack, size = [r], 0
+            seen[r] = True
+            while stack:
+                x = stack.pop()
+                size += 1
+                for y in g.col_idx[g.row_ptr[x]:g.row_ptr[x + 1]]:
+                    if not seen[y]:
+                        seen[y] = True
+                        stack.append(y)
+            sizes.append(size)
+        want[v] = (n - 1) ** 2 - sum(s * s for s in sizes)
+    np.testing.assert_array_equal(all_bc(g), want)
+    _, sigma, _, _ = oracle.single_source(g.row_ptr, g.col_idx, seed % n)
+    assert np.all(sigma == 1.0)
+
+
+@pytest.mark.parametrize("a,b", [(1, 1), (1, 5), (2, 3), (3, 7), (6, 6)])
+def test_complete_bipartite_closed_form(a, b):
+    g = gg.complete_bipartite(a, b)
+    want = np.concatenate([np.full(a, b * (b - 1) / a), np.full(b, a * (a - 1) / b)])
+    np.testing.assert_allclose(all_bc(g), want, rtol=1e-14)
+    if a > 1:
+        _, sigma, _, _ = oracle.single_source(g.row_ptr, g.col_idx, 0)
+        assert np.all(sigma[1:a] == b)          # same side: one path through each of b
+
+
+@pytest.mark.parametrize("n", [1, 2, 5, 9])
+def test_complete_graph_zero(n):
+    np.testing.assert_array_equal(all_bc(gg.complete(n)), np.zeros(n))
+
+
+@pytest.mark.parametrize("d", [1, 2, 3, 5, 8])
+def test_hypercube_closed_form(d):
+    g = gg.hypercube(d)
+    val = d * 2 ** (d - 1) - 2 ** d + 1
+    np.testing.assert_allclose(all_bc(g), np.full(1 << d, float(val)), rtol=1e-12)
+
+
+def test_hypercube_sigma_factorial():
+    """From vertex 0 of Q_18, sigma(t) = popcount(t)! (all below 2**53: 18! < 2**53)."""
+    d = 18
+    g = gg.hypercube(d)
+    dist, sigma, _, st = oracle.single_source(g.row_ptr, g.col_idx, 0)
+    assert st == oracle.OK
+    pc = np.array([bin(t).count("1") for t in range(1 << d)])
+    assert np.array_equal(dist, pc)
+    fact = np.array([float(math.factorial(k)) for k in range(d + 1)])
+    assert np.array_equal(sigma, fact[pc])
+
+
+def test_lattice_sigma_binomial():
+    """From the corner of a full lattice, sigma(x, y) = C(x+y, x): exact below
+    2**53, within 1e-15 relative above (the 60x60 lattice crosses at x+y=57)."""
+    rows = cols = 60
+    g = gg.grid_full(rows, cols)
+    dist, sigma, _, st = oracle.single_source(g.row_ptr, g.col_idx, 0)
+    assert st == oracle.OK
+    for r in range(rows):
+        for c in range(cols):
+            v = r * cols + c
+            want = math.comb(r + c, r)
+            assert dist[v] == r + c
+            if want < 2 ** 53:
+                assert sigma[v] == float(want)
+            else:
+                assert abs(sigma[v] - want) <= 1e-15 * want * (r + c)
+
+
+def test_lattice_overflow_reports_range():
+    """sigma from a corner of a 600x600 lattice reaches C(1198, 599) > DBL_MAX."""
+    g = gg.grid_full(600, 600)
+    _, sigma, _, st = oracle.single_source(g.row_ptr, g.col_idx, 0, with_delta=False)
+    assert st == oracle.RANGE and np.isinf(sigma).any()
+    _, st2 = oracle.bc(g.row_ptr, g.col_idx, np.array([0], np.int32))
+    assert st2 == oracle.RANGE
+
+
+# ---------------------------------------------------------------------------
+# Invariants on the benchmark-shaped R-MAT scale 12 graph
+# ---------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def rmat12():
+    return gg.rmat(12, 8, seed=1)
+
+
+def test_distances_match_scipy(rmat12):
+    for s in gg.sample_sources(rmat12, 12, seed=5):
+        dist, _, _, _ = oracle.single_source(rmat12.row_ptr, rmat12.col_idx, s, False)
+        assert np.array_equal(dist, hop_distances(rmat12, s))
+
+
+def test_sum_invariant_all_sources(rmat12):
+    """sum_v BC(v) = sum over s, reachable t != s of (d(s,t) - 1), with d from scipy."""
+    g = rmat12
+    bc = all_bc(g)
+    m = sp.csr_matrix((np.ones(g.nnz), g.col_idx, g.row_ptr), shape=(g.n, g.n))
+    D = shortest_path(m, method="D", unweighted=True)
+    fin = np.isfinite(D) & (D > 0)
+    want = float((D[fin] - 1).sum())
+    assert abs(bc.sum() - want) <= 1e-9 * want
+    assert np.all(bc >= 0)
+
+
+def test_per_source_delta_sum(rmat12):
+    """sum over v != s of delta_s(v) = sum over reachable t != s of (d(s,t) - 1)."""
+    for s in gg.sample_sources(rmat12, 16, seed=6):
+        dist, sigma, delta, _ = oracle.single_source(rmat12.row_ptr, rmat12.col_idx, s)
+        d = hop_distances(rmat12, s)
+        want = float((d[d > 0] - 1).sum())
+        got = float(delta.sum() - delta[s])
+        assert abs(got - want) <= 1e-10 * max(1.0, want)
+
+
+def test_additivity_and_duplicates(rmat12):
+    s = gg.sample_sources(rmat12, 40, seed=8)
+    a, b = s[:17], s[17:]
+    np.testing.assert_allclose(all_bc(rmat12, s), all_bc(rmat12, a) + all_bc(rmat12, b),
+                               rtol=1e-12, atol=1e-9)
+    np.testing.assert_allclose(all_bc(rmat12, np.concatenate([a, a])), 2 * all_bc(rmat12, a),
+                               rtol=1e-12, atol=1e-9)
+
+
+def test_thread_count_does_not_change_result(rmat12):
+    s = gg.sample_sources(rmat12, 64, seed=9)
+    b1, _ = oracle.bc(rmat12.row_ptr, rmat12.col_idx, s, threads=1)
+    b4, _ = oracle.bc(rmat12.row_ptr, rmat12.col_idx, s, threads=4)
+    np.testing.assert_allclose(b1, b4, rtol=1e-13, atol=1e-9)
+
+
+# ---------------------------------------------------------------------------
+# NetworkX (independent library)
+# ---------------------------------------------------------------------------
+
+def test_networkx_cross_check():
+    nx = pytest.importorskip("networkx")
+    graphs = [gg.gnp(n, 0.3, seed=n) for n in range(5, 30, 3)] + [gg.rmat(8, 8, seed=2)]
+    for g in graphs:
+        G = nx.Graph()
+        G.add_nodes_from(range(g.n))
+        for u in range(g.n):
+            for v in g.col_idx[g.row_ptr[u]:g.row_ptr[u + 1]]:
+                G.add_edge(u, int(v))
+        ref = nx.betweenness_centrality(G, normalized=False)
+        want = np.array([2.0 * ref[v] for v in range(g.n)])
+        np.testing.assert_allclose(all_bc(g), want, rtol=1e-10, atol=1e-10)
+
+
+# ---------------------------------------------------------------------------
+# Edge cases and argument checks
+# ---------------------------------------------------------------------------
+
+def test_edge_cases():
+    g = gg.path(5)
+    bc, st = oracle.bc(g.row_ptr, g.col_idx, np.zeros(0, np.int32))
+    assert st == oracle.OK and np.all(bc == 0)
+    single = gg.csr_from_edges(1, [], [])
+    bc, st = oracle.bc(single.row_ptr, single.col_idx, np.array([0], np.int32))
+    assert st == oracle.OK and bc.tolist() == [0.0]
+    empty = gg.csr_from_edges(6, [], [])
+    assert np.all(all_bc(empty) == 0)
+    with pytest.raises(oracle.OracleError):
+        oracle.bc(g.row_ptr, g.col_idx, np.array([5], np.int32))
+    with pytest.raises(oracle.OracleError):
+        oracle.single_source(g.row_ptr, g.col_idx, -1)
