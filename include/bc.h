@@ -1,0 +1,165 @@
+/*
+ * bc.h -- C ABI of the MI355X (gfx950) Brandes betweenness-centrality library.
+ *
+ * The operation is the paper's ComputeBC (Section "Background", the BC
+ * specification listing): given an unweighted graph, a set of sources and a
+ * BC array, BC is zeroed (the attachNodeProperty(BC = 0) statement) and then,
+ * for every source, a forward breadth-first pass accumulates shortest-path
+ * counts sigma (iterateInBFS) and a reverse pass over the BFS levels, skipping
+ * the source, accumulates dependencies delta and adds them to BC
+ * (iterateInReverse).  The paper calls this Brandes' algorithm; the result is
+ *
+ *     BC_S(v) = sum over s in S, s != v, of sum over t != s, t != v of
+ *               sigma_st(v) / sigma_st
+ *
+ * over ordered pairs (no factor 1/2, no normalisation).  S is a multiset: a
+ * repeated source counts once per occurrence.  sigma, delta and BC are IEEE
+ * double (the listing declares float; double is used because float loses
+ * integer exactness of sigma at 2^24 and overflows on deep graphs).  Levels are
+ * hop counts, -1 meaning "not reached" (the sentinel of the paper's generated
+ * BFS kernel, Section "Code Generation", BFS traversal).
+ *
+ * Graphs are undirected: a symmetric CSR (every arc u->v has a matching v->u)
+ * with int32 offsets row_ptr[n+1] and int32 neighbours col_idx[row_ptr[n]], the
+ * storage the paper uses on host and device (Section "Code Generation", graph
+ * representation).  Parallel arcs count as distinct paths; self-loops are
+ * accepted and have no effect.
+ *
+ * Conventions for every call:
+ *   - Every call returns a bc_status; no C++ exception crosses this boundary.
+ *   - Pointers marked "host" are ordinary host memory; pointers marked
+ *     "device" are device memory of the current HIP device (e.g. a torch
+ *     tensor's data_ptr()).  Inputs are borrowed for the duration of the call
+ *     (asynchronous calls: until the stream reaches the end of the call's
+ *     work).  The library never frees caller memory.
+ *   - `stream` is a hipStream_t passed as void*; NULL means the default stream.
+ *   - A bc_graph_t is immutable after creation and may be used by several
+ *     threads and streams at once; each run takes a private workspace from a
+ *     pool owned by the graph.  bc_destroy_graph must not race with runs.
+ */
+#ifndef BC_MI355X_BC_H
+#define BC_MI355X_BC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct bc_graph_s *bc_graph_t;
+
+typedef enum {
+    BC_OK = 0,
+    BC_ERR_INVALID_ARG = 1,   /* NULL pointer, k < 0, source out of [0, n), bad option */
+    BC_ERR_INVALID_GRAPH = 2, /* row_ptr[0] != 0, row_ptr decreasing, col_idx out of range,
+                                 or an arc without its reverse (unless trusted symmetric) */
+    BC_ERR_OUT_OF_MEMORY = 3, /* device allocation failed */
+    BC_ERR_RANGE = 4,         /* some sigma became infinite (shortest-path counts beyond
+                                 DBL_MAX); outputs are written but meaningless */
+    BC_ERR_DEVICE = 5,        /* a HIP runtime call failed */
+    BC_ERR_UNSUPPORTED = 6    /* requested feature not available */
+} bc_status;
+
+/* bc_create_graph flags */
+enum {
+    BC_GRAPH_TRUST_SYMMETRIC = 1u << 0, /* skip the host-side symmetry check */
+    BC_GRAPH_INPUT_ON_DEVICE = 1u << 1  /* row_ptr / col_idx are device pointers; the
+                                           structural checks are then skipped */
+};
+
+/* Execution modes (bc_options.mode). */
+enum {
+    BC_MODE_AUTO = 0,    /* library picks */
+    BC_MODE_PLAIN = 1,   /* one source at a time, the paper's source loop */
+    BC_MODE_BATCHED = 2  /* several sources share each level step (bitmask frontiers) */
+};
+
+typedef struct bc_options {
+    int32_t mode;        /* BC_MODE_*                                                   */
+    int32_t batch_width; /* batched mode: sources per batch, 1..64 (0 = 64)              */
+    int32_t level_chunk; /* forward levels launched per host poll, 1..1024 (0 = 8)       */
+    int32_t reserved[5]; /* must be zero                                                 */
+} bc_options;
+
+/*
+ * Copy an undirected CSR graph to the device and prepare it for runs.
+ *   n        vertex count, n >= 0
+ *   row_ptr  [n+1] offsets (host, or device with BC_GRAPH_INPUT_ON_DEVICE);
+ *            row_ptr[0] = 0, non-decreasing, row_ptr[n] = arc count
+ *   col_idx  [row_ptr[n]] neighbour ids in [0, n) (same memory kind as row_ptr)
+ *   flags    BC_GRAPH_* bits
+ *   stream   stream for the copies (the call waits for them before returning)
+ *   out      receives the handle; untouched on error
+ * The caller may free row_ptr / col_idx after the call returns.
+ * Errors: BC_ERR_INVALID_ARG (NULL out, n < 0, NULL arrays with n > 0),
+ * BC_ERR_INVALID_GRAPH, BC_ERR_OUT_OF_MEMORY, BC_ERR_DEVICE.
+ */
+bc_status bc_create_graph(int32_t n, const int32_t *row_ptr, const int32_t *col_idx,
+                          uint32_t flags, void *stream, bc_graph_t *out);
+
+/* Release the graph, its device copy and every pooled workspace.  NULL is accepted. */
+bc_status bc_destroy_graph(bc_graph_t g);
+
+/* n, arc count and device bytes held by the graph (without workspaces).
+ * Any output pointer may be NULL. */
+bc_status bc_graph_info(bc_graph_t g, int32_t *n, int64_t *nnz, size_t *device_bytes);
+
+/*
+ * BC over a source multiset; blocking, host in / host out.
+ *   sources  [k] host, each in [0, n); k >= 0 (k = 0 gives all zeros)
+ *   bc_out   [n] host, overwritten with BC_S
+ * Same as bc_run_async with default options on the default stream followed by
+ * a copy to the host.  Errors: BC_ERR_INVALID_ARG (nothing written),
+ * BC_ERR_RANGE (written, meaningless), BC_ERR_OUT_OF_MEMORY, BC_ERR_DEVICE.
+ */
+bc_status bc_run(bc_graph_t g, const int32_t *sources, int32_t k, double *bc_out);
+
+/*
+ * BC over a source multiset into device memory, ordered on `stream`.
+ *   sources     [k] host (read before the call returns)
+ *   bc_out_dev  [n] device, overwritten with BC_S when the stream reaches the
+ *               end of the call's work
+ *   opt         NULL = defaults
+ * The call may wait on `stream` to poll the BFS depth (the level loop is driven
+ * from the host in chunks of opt->level_chunk levels), so it returns after the
+ * forward passes of all sources have been issued; BC_ERR_RANGE is reported
+ * only after a wait, i.e. always by the time the call returns.
+ */
+bc_status bc_run_async(bc_graph_t g, const int32_t *sources, int32_t k, double *bc_out_dev,
+                       const bc_options *opt, void *stream);
+
+/*
+ * One source, full per-vertex state (host outputs), for parity checks.
+ *   dist   [n] host: hop distance from s, -1 if unreachable
+ *   sigma  [n] host: number of shortest s-v paths (0 if unreachable)
+ *   delta  [n] host or NULL: dependency of s on v (0 for s and unreachable v)
+ * Errors as bc_run.
+ */
+bc_status bc_single_source(bc_graph_t g, int32_t s, int32_t *dist, double *sigma,
+                           double *delta);
+
+/*
+ * Batched-path detail for parity checks: BC as bc_run, plus, when not NULL,
+ * per-source dist [k][n] (int32, host) and sigma [k][n] (double, host), as
+ * produced by the batched kernels (opt->mode must be BC_MODE_BATCHED or
+ * BC_MODE_PLAIN; NULL opt = batched).
+ */
+bc_status bc_run_detail(bc_graph_t g, const int32_t *sources, int32_t k, const bc_options *opt,
+                        double *bc_out, int32_t *dist, double *sigma);
+
+/* Device bytes one run with k sources and the given options would take for its
+ * workspace (for admission control).  opt may be NULL. */
+bc_status bc_workspace_bytes(bc_graph_t g, int32_t k, const bc_options *opt, size_t *bytes);
+
+/* Free pooled workspaces that are idle.  Safe while other runs are in flight. */
+bc_status bc_trim_workspaces(bc_graph_t g);
+
+/* Static description of a status code. */
+const char *bc_status_str(bc_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BC_MI355X_BC_H */

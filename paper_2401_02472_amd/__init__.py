@@ -1,0 +1,209 @@
+"""Brandes betweenness centrality on MI355X (gfx950): Python binding.
+
+Thin wrappers with the names of the C ABI in include/bc.h.  They only marshal
+arguments (numpy arrays for host memory, torch tensors for device memory and
+torch streams for ordering); every step of the computation runs in the HIP
+kernels of libbc_mi355x.so.  The library must be present (or buildable with
+hipcc): there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import _capi
+from ._capi import (BC_ERR_DEVICE, BC_ERR_INVALID_ARG, BC_ERR_INVALID_GRAPH,  # noqa: F401
+                    BC_ERR_OUT_OF_MEMORY, BC_ERR_RANGE, BC_ERR_UNSUPPORTED,
+                    BC_GRAPH_INPUT_ON_DEVICE, BC_GRAPH_TRUST_SYMMETRIC, BC_MODE_AUTO,
+                    BC_MODE_BATCHED, BC_MODE_PLAIN, BC_OK, bc_options)
+
+__all__ = [
+    "BCError", "bc_create_graph", "bc_destroy_graph", "bc_graph_info", "bc_run", "bc_run_async",
+    "bc_single_source", "bc_run_detail", "bc_workspace_bytes", "bc_trim_workspaces",
+    "bc_status_str", "make_options", "Graph", "load_library",
+]
+
+
+class BCError(RuntimeError):
+    """A C-ABI call returned a status other than BC_OK.  `result` holds the
+    outputs when the call still wrote them (BC_ERR_RANGE)."""
+
+    def __init__(self, status: int, where: str, result=None):
+        super().__init__(f"{where}: {bc_status_str(status)} (status {status})")
+        self.status = status
+        self.result = result
+
+
+def load_library():
+    return _capi.load()
+
+
+def bc_status_str(status: int) -> str:
+    return _capi.load().bc_status_str(int(status)).decode()
+
+
+def _i32(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a), dtype=np.int32)
+
+
+def _ptr(a: np.ndarray, ctype):
+    return a.ctypes.data_as(ctypes.POINTER(ctype))
+
+
+def _stream_handle(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def make_options(mode: int = BC_MODE_AUTO, batch_width: int = 0, level_chunk: int = 0):
+    o = bc_options()
+    o.mode, o.batch_width, o.level_chunk = int(mode), int(batch_width), int(level_chunk)
+    return o
+
+
+def _check(st: int, where: str, result=None):
+    if st != BC_OK:
+        raise BCError(st, where, result)
+
+
+def bc_create_graph(n: int, row_ptr, col_idx, flags: int = 0, stream=None) -> int:
+    """Copy a symmetric int32 CSR to the device; returns an opaque handle.
+
+    Host numpy arrays, or device torch tensors together with
+    BC_GRAPH_INPUT_ON_DEVICE in `flags`."""
+    lib = _capi.load()
+    out = ctypes.c_void_p()
+    if flags & BC_GRAPH_INPUT_ON_DEVICE:
+        rp_p, ci_p = ctypes.c_void_p(row_ptr.data_ptr()), ctypes.c_void_p(col_idx.data_ptr())
+        keep = None
+        st_h = _stream_handle(stream)
+    else:
+        rp, ci = _i32(row_ptr), _i32(col_idx)
+        keep = (rp, ci)
+        rp_p, ci_p = ctypes.c_void_p(rp.ctypes.data), ctypes.c_void_p(ci.ctypes.data)
+        st_h = ctypes.c_void_p(0) if stream is None else _stream_handle(stream)
+    st = lib.bc_create_graph(int(n), rp_p, ci_p, int(flags), st_h, ctypes.byref(out))
+    del keep
+    _check(st, "bc_create_graph")
+    return out.value
+
+
+def bc_destroy_graph(g: int) -> None:
+    _check(_capi.load().bc_destroy_graph(ctypes.c_void_p(g)), "bc_destroy_graph")
+
+
+def bc_graph_info(g: int):
+    n, nnz, b = ctypes.c_int32(), ctypes.c_int64(), ctypes.c_size_t()
+    _check(_capi.load().bc_graph_info(ctypes.c_void_p(g), ctypes.byref(n), ctypes.byref(nnz),
+                                      ctypes.byref(b)), "bc_graph_info")
+    return n.value, nnz.value, b.value
+
+
+def bc_run(g: int, sources) -> np.ndarray:
+    """BC over the source multiset (host in, host out)."""
+    n, _, _ = bc_graph_info(g)
+    src = _i32(sources)
+    out = np.empty(max(n, 0), dtype=np.float64)
+    st = _capi.load().bc_run(ctypes.c_void_p(g), _ptr(src, ctypes.c_int32), int(src.size),
+                             _ptr(out, ctypes.c_double))
+    _check(st, "bc_run", out)
+    return out
+
+
+def bc_run_async(g: int, sources, bc_out, options=None, stream=None) -> None:
+    """BC into `bc_out` (a float64 device tensor of n entries), ordered on `stream`
+    (default: torch's current stream)."""
+    src = _i32(sources)
+    opt = ctypes.byref(options) if options is not None else None
+    st = _capi.load().bc_run_async(ctypes.c_void_p(g), _ptr(src, ctypes.c_int32), int(src.size),
+                                   ctypes.c_void_p(bc_out.data_ptr()), opt,
+                                   _stream_handle(stream))
+    _check(st, "bc_run_async", bc_out)
+
+
+def bc_single_source(g: int, s: int):
+    """(dist int32[n], sigma float64[n], delta float64[n]) for one source."""
+    n, _, _ = bc_graph_info(g)
+    dist = np.empty(n, dtype=np.int32)
+    sigma = np.empty(n, dtype=np.float64)
+    delta = np.empty(n, dtype=np.float64)
+    st = _capi.load().bc_single_source(ctypes.c_void_p(g), int(s), _ptr(dist, ctypes.c_int32),
+                                       _ptr(sigma, ctypes.c_double),
+                                       _ptr(delta, ctypes.c_double))
+    _check(st, "bc_single_source", (dist, sigma, delta))
+    return dist, sigma, delta
+
+
+def bc_run_detail(g: int, sources, options=None, want_dist: bool = True,
+                  want_sigma: bool = True):
+    """(bc[n], dist[k][n] or None, sigma[k][n] or None) from the path `options` selects."""
+    n, _, _ = bc_graph_info(g)
+    src = _i32(sources)
+    k = int(src.size)
+    bc = np.empty(n, dtype=np.float64)
+    dist = np.empty((k, n), dtype=np.int32) if want_dist else None
+    sigma = np.empty((k, n), dtype=np.float64) if want_sigma else None
+    opt = ctypes.byref(options) if options is not None else None
+    st = _capi.load().bc_run_detail(ctypes.c_void_p(g), _ptr(src, ctypes.c_int32), k, opt,
+                                    _ptr(bc, ctypes.c_double),
+                                    _ptr(dist, ctypes.c_int32) if want_dist else None,
+                                    _ptr(sigma, ctypes.c_double) if want_sigma else None)
+    _check(st, "bc_run_detail", (bc, dist, sigma))
+    return bc, dist, sigma
+
+
+def bc_workspace_bytes(g: int, k: int, options=None) -> int:
+    out = ctypes.c_size_t()
+    opt = ctypes.byref(options) if options is not None else None
+    _check(_capi.load().bc_workspace_bytes(ctypes.c_void_p(g), int(k), opt, ctypes.byref(out)),
+           "bc_workspace_bytes")
+    return out.value
+
+
+def bc_trim_workspaces(g: int) -> None:
+    _check(_capi.load().bc_trim_workspaces(ctypes.c_void_p(g)), "bc_trim_workspaces")
+
+
+class Graph:
+    """Owning wrapper of a bc_graph_t handle."""
+
+    def __init__(self, n: int, row_ptr, col_idx, flags: int = 0, stream=None):
+        self.handle = bc_create_graph(n, row_ptr, col_idx, flags, stream)
+        self.n, self.nnz, self.device_bytes = bc_graph_info(self.handle)
+
+    def close(self):
+        if self.handle:
+            bc_destroy_graph(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def run(self, sources) -> np.ndarray:
+        return bc_run(self.handle, sources)
+
+    def run_async(self, sources, bc_out, options=None, stream=None) -> None:
+        bc_run_async(self.handle, sources, bc_out, options, stream)
+
+    def single_source(self, s: int):
+        return bc_single_source(self.handle, s)
+
+    def run_detail(self, sources, options=None, want_dist=True, want_sigma=True):
+        return bc_run_detail(self.handle, sources, options, want_dist, want_sigma)
+
+    def workspace_bytes(self, k: int, options=None) -> int:
+        return bc_workspace_bytes(self.handle, k, options)

@@ -1,0 +1,80 @@
+"""ctypes declarations of the C ABI in include/bc.h (argument marshalling only).
+
+The shared library is built in-tree (``libbc_mi355x.so`` next to this file).
+If it is missing it is built once with hipcc; if that fails, loading raises --
+there is no fallback path: every step of the computation runs in the HIP
+kernels behind this ABI.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+from . import build as _build
+
+LIB_PATH = _build.LIB_PATH
+
+BC_OK = 0
+BC_ERR_INVALID_ARG = 1
+BC_ERR_INVALID_GRAPH = 2
+BC_ERR_OUT_OF_MEMORY = 3
+BC_ERR_RANGE = 4
+BC_ERR_DEVICE = 5
+BC_ERR_UNSUPPORTED = 6
+
+BC_GRAPH_TRUST_SYMMETRIC = 1 << 0
+BC_GRAPH_INPUT_ON_DEVICE = 1 << 1
+
+BC_MODE_AUTO = 0
+BC_MODE_PLAIN = 1
+BC_MODE_BATCHED = 2
+
+EXPORTED = ("bc_create_graph", "bc_destroy_graph", "bc_graph_info", "bc_run", "bc_run_async",
+            "bc_single_source", "bc_run_detail", "bc_workspace_bytes", "bc_trim_workspaces",
+            "bc_status_str")
+
+
+class bc_options(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("batch_width", ctypes.c_int32),
+                ("level_chunk", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
+
+
+_lib = None
+_lock = threading.Lock()
+
+
+def load():
+    """Load (building first if absent) the HIP library and declare its signatures."""
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(LIB_PATH):
+            _build.build()
+        lib = ctypes.CDLL(LIB_PATH)
+        i32p = ctypes.POINTER(ctypes.c_int32)
+        i64p = ctypes.POINTER(ctypes.c_int64)
+        f64p = ctypes.POINTER(ctypes.c_double)
+        szp = ctypes.POINTER(ctypes.c_size_t)
+        vp = ctypes.c_void_p
+        optp = ctypes.POINTER(bc_options)
+        sig = {
+            "bc_create_graph": [ctypes.c_int32, vp, vp, ctypes.c_uint32, vp, ctypes.POINTER(vp)],
+            "bc_destroy_graph": [vp],
+            "bc_graph_info": [vp, i32p, i64p, szp],
+            "bc_run": [vp, i32p, ctypes.c_int32, f64p],
+            "bc_run_async": [vp, i32p, ctypes.c_int32, vp, optp, vp],
+            "bc_single_source": [vp, ctypes.c_int32, i32p, f64p, f64p],
+            "bc_run_detail": [vp, i32p, ctypes.c_int32, optp, f64p, i32p, f64p],
+            "bc_workspace_bytes": [vp, ctypes.c_int32, optp, szp],
+            "bc_trim_workspaces": [vp],
+        }
+        for name, args in sig.items():
+            fn = getattr(lib, name)
+            fn.argtypes = args
+            fn.restype = ctypes.c_int
+        lib.bc_status_str.argtypes = [ctypes.c_int]
+        lib.bc_status_str.restype = ctypes.c_char_p
+        _lib = lib
+        return lib

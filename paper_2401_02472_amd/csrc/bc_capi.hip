@@ -1,0 +1,524 @@
+// Host runtime and C ABI (include/bc.h): graph residency, workspace pool, the
+// per-source level loop, and argument checking.
+//
+// The paper's generated host code copies the graph to the device once and
+// returns only the modified property (Section "Backend Optimizations",
+// host-device transfer analysis); here too the CSR stays resident in a
+// bc_graph_t and only BC (plus debug state on request) comes back.
+#include <algorithm>
+#include <atomic>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <vector>
+
+#include "bc.h"
+#include "bc_internal.h"
+
+using namespace bcx;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr int kLevelGrid = 1024;  // workgroups per level kernel (4096 wavefronts)
+
+size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
+
+bc_status from_hip(hipError_t e) {
+    if (e == hipSuccess) return BC_OK;
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) return BC_ERR_OUT_OF_MEMORY;
+    return BC_ERR_DEVICE;
+}
+
+#define BC_TRY_HIP(expr)                          \
+    do {                                          \
+        hipError_t _e = (expr);                   \
+        if (_e != hipSuccess) return from_hip(_e); \
+    } while (0)
+
+struct PlainWS {
+    void *block = nullptr;
+    size_t bytes = 0;
+    PlainDev dev{};
+    int32_t *h_ctrl = nullptr;  // pinned mirror of dev.ctrl
+    hipEvent_t done = nullptr;  // recorded after the last work that used this workspace
+    bool busy = false;
+};
+
+class DeviceGuard {
+  public:
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev_) != hipSuccess) prev_ = -1;
+        if (prev_ != dev) (void)hipSetDevice(dev);
+        dev_ = dev;
+    }
+    ~DeviceGuard() {
+        if (prev_ >= 0 && prev_ != dev_) (void)hipSetDevice(prev_);
+    }
+
+  private:
+    int prev_ = -1, dev_ = -1;
+};
+
+}  // namespace
+
+struct bc_graph_s {
+    int device = 0;
+    int32_t n = 0;
+    int64_t nnz = 0;
+    int32_t *d_row_ptr = nullptr;
+    int32_t *d_col_idx = nullptr;
+    uint64_t total_chunks2 = 0;  // chunk slots needed by bucket-2 vertices of one source
+    size_t device_bytes = 0;
+    std::mutex mu;
+    std::vector<PlainWS *> plain_pool;
+    std::atomic<int32_t> last_depth{8};
+};
+
+namespace {
+
+size_t plain_ws_bytes(const bc_graph_s *g) {
+    const size_t n = (size_t)std::max<int32_t>(g->n, 1);
+    size_t b = 0;
+    b += align_up(((n + 15) / 16) * sizeof(uint32_t));        // lev3
+    b += 2 * align_up(n * sizeof(double));                    // sigma, coef
+    b += 5 * align_up(n * sizeof(int32_t));                   // q0 q1 q2 q2c done2
+    b += align_up(std::max<uint64_t>(g->total_chunks2, 1) * sizeof(double));  // partial
+    b += align_up((n + 2) * sizeof(LevelRec));                // lvl
+    b += align_up(2 * sizeof(int32_t));                       // ctrl
+    return b;
+}
+
+bc_status plain_ws_create(bc_graph_s *g, PlainWS **out) {
+    PlainWS *ws = new (std::nothrow) PlainWS();
+    if (!ws) return BC_ERR_OUT_OF_MEMORY;
+    ws->bytes = plain_ws_bytes(g);
+    hipError_t e = hipMalloc(&ws->block, ws->bytes);
+    if (e != hipSuccess) {
+        delete ws;
+        return from_hip(e);
+    }
+    e = hipHostMalloc((void **)&ws->h_ctrl, 2 * sizeof(int32_t), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ws->done, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        (void)hipFree(ws->block);
+        if (ws->h_ctrl) (void)hipHostFree(ws->h_ctrl);
+        delete ws;
+        return from_hip(e);
+    }
+    const size_t n = (size_t)std::max<int32_t>(g->n, 1);
+    char *p = (char *)ws->block;
+    auto take = [&](size_t bytes) {
+        char *r = p;
+        p += align_up(bytes);
+        return (void *)r;
+    };
+    PlainDev &d = ws->dev;
+    d.n = g->n;
+    d.row_ptr = g->d_row_ptr;
+    d.col_idx = g->d_col_idx;
+    d.lev3 = (uint32_t *)take(((n + 15) / 16) * sizeof(uint32_t));
+    d.sigma = (double *)take(n * sizeof(double));
+    d.coef = (double *)take(n * sizeof(double));
+    d.q0 = (int32_t *)take(n * sizeof(int32_t));
+    d.q1 = (int32_t *)take(n * sizeof(int32_t));
+    d.q2 = (int32_t *)take(n * sizeof(int32_t));
+    d.q2c = (int32_t *)take(n * sizeof(int32_t));
+    d.done2 = (int32_t *)take(n * sizeof(int32_t));
+    d.partial = (double *)take(std::max<uint64_t>(g->total_chunks2, 1) * sizeof(double));
+    d.lvl = (LevelRec *)take((n + 2) * sizeof(LevelRec));
+    d.ctrl = (int32_t *)take(2 * sizeof(int32_t));
+    d.bc = nullptr;
+    *out = ws;
+    return BC_OK;
+}
+
+void plain_ws_destroy(PlainWS *ws) {
+    if (!ws) return;
+    if (ws->done) {
+        (void)hipEventSynchronize(ws->done);
+        (void)hipEventDestroy(ws->done);
+    }
+    if (ws->block) (void)hipFree(ws->block);
+    if (ws->h_ctrl) (void)hipHostFree(ws->h_ctrl);
+    delete ws;
+}
+
+// Take an idle workspace (the caller's stream then waits for its previous
+// user's work), or make a new one.
+bc_status plain_acquire(bc_graph_s *g, hipStream_t stream, PlainWS **out) {
+    {
+        std::lock_guard<std::mutex> lk(g->mu);
+        for (PlainWS *ws : g->plain_pool) {
+            if (!ws->busy) {
+                ws->busy = true;
+                *out = ws;
+                BC_TRY_HIP(hipStreamWaitEvent(stream, ws->done, 0));
+                return BC_OK;
+            }
+        }
+    }
+    PlainWS *ws = nullptr;
+    bc_status st = plain_ws_create(g, &ws);
+    if (st != BC_OK) return st;
+    ws->busy = true;
+    std::lock_guard<std::mutex> lk(g->mu);
+    g->plain_pool.push_back(ws);
+    *out = ws;
+    return BC_OK;
+}
+
+void plain_release(bc_graph_s *g, PlainWS *ws, hipStream_t stream) {
+    (void)hipEventRecord(ws->done, stream);
+    std::lock_guard<std::mutex> lk(g->mu);
+    ws->busy = false;
+}
+
+struct SourceState {
+    int32_t *dist = nullptr;   // device, optional export
+    double *sigma = nullptr;   // device, optional export
+    double *delta = nullptr;   // device, optional export
+};
+
+// Forward pass of one source: levels are launched in chunks and the host polls
+// the deepest discovered level after each chunk.  Returns the deepest level.
+bc_status plain_forward(bc_graph_s *g, PlainWS *ws, int32_t s, int32_t chunk0,
+                        hipStream_t stream, int32_t *deepest_out) {
+    const PlainDev &d = ws->dev;
+    BC_TRY_HIP(plain_init_source(d, s, stream));
+    int32_t L0 = 0;
+    int32_t K = std::max(1, chunk0);
+    for (;;) {
+        const int32_t Lend = (int32_t)std::min<int64_t>((int64_t)L0 + K, g->n);
+        for (int32_t L = L0; L < Lend; ++L) BC_TRY_HIP(plain_forward_level(d, L, kLevelGrid, stream));
+        BC_TRY_HIP(hipMemcpyAsync(ws->h_ctrl, d.ctrl, 2 * sizeof(int32_t), hipMemcpyDeviceToHost,
+                                  stream));
+        BC_TRY_HIP(hipStreamSynchronize(stream));
+        const int32_t deepest = ws->h_ctrl[0];
+        if (deepest < Lend || Lend >= g->n) {
+            *deepest_out = deepest;
+            return BC_OK;
+        }
+        L0 = Lend;
+        K = std::min(K * 2, 1024);
+    }
+}
+
+bc_status plain_run(bc_graph_s *g, const int32_t *sources, int32_t k, double *bc_dev,
+                    const bc_options *opt, hipStream_t stream, const SourceState *exp) {
+    PlainWS *ws = nullptr;
+    bc_status st = plain_acquire(g, stream, &ws);
+    if (st != BC_OK) return st;
+    PlainDev d = ws->dev;
+    d.bc = bc_dev;
+    ws->dev.bc = bc_dev;
+    bc_status result = BC_OK;
+    auto fail = [&](bc_status s2) {
+        plain_release(g, ws, stream);
+        return s2;
+    };
+    hipError_t e = hipMemsetAsync(bc_dev, 0, (size_t)g->n * sizeof(double), stream);
+    if (e != hipSuccess) return fail(from_hip(e));
+    e = plain_reset_run(d, stream);
+    if (e != hipSuccess) return fail(from_hip(e));
+    const int32_t user_chunk = opt ? opt->level_chunk : 0;
+    for (int32_t i = 0; i < k; ++i) {
+        const int32_t chunk = user_chunk > 0 ? user_chunk : g->last_depth.load() + 2;
+        int32_t deepest = 0;
+        st = plain_forward(g, ws, sources[i], chunk, stream, &deepest);
+        if (st != BC_OK) return fail(st);
+        if (user_chunk <= 0) g->last_depth.store(deepest);
+        if (exp) {
+            e = plain_export_fill(g->n, exp[i].dist, exp[i].sigma, exp[i].delta, stream);
+            if (e != hipSuccess) return fail(from_hip(e));
+        }
+        for (int32_t L = deepest; L >= 1; --L) {
+            e = plain_backward_level(d, L, kLevelGrid, exp ? exp[i].delta : nullptr, stream);
+            if (e != hipSuccess) return fail(from_hip(e));
+        }
+        if (exp) {
+            e = plain_export_levels(d, deepest, exp[i].dist, exp[i].sigma, stream);
+            if (e != hipSuccess) return fail(from_hip(e));
+        }
+    }
+    e = hipMemcpyAsync(ws->h_ctrl, d.ctrl, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return fail(from_hip(e));
+    if (ws->h_ctrl[1] != 0) result = BC_ERR_RANGE;
+    plain_release(g, ws, stream);
+    return result;
+}
+
+bc_status check_options(const bc_options *opt) {
+    if (!opt) return BC_OK;
+    if (opt->mode < BC_MODE_AUTO || opt->mode > BC_MODE_BATCHED) return BC_ERR_INVALID_ARG;
+    if (opt->batch_width < 0 || opt->batch_width > 64) return BC_ERR_INVALID_ARG;
+    if (opt->level_chunk < 0 || opt->level_chunk > 1024) return BC_ERR_INVALID_ARG;
+    for (int i = 0; i < 5; ++i)
+        if (opt->reserved[i] != 0) return BC_ERR_INVALID_ARG;
+    return BC_OK;
+}
+
+bc_status check_sources(const bc_graph_s *g, const int32_t *sources, int32_t k) {
+    if (k < 0) return BC_ERR_INVALID_ARG;
+    if (k > 0 && !sources) return BC_ERR_INVALID_ARG;
+    for (int32_t i = 0; i < k; ++i)
+        if (sources[i] < 0 || sources[i] >= g->n) return BC_ERR_INVALID_ARG;
+    return BC_OK;
+}
+
+// Structural checks of a host CSR; with `symmetric`, also that the arc
+// multiset equals its transpose.
+bc_status validate_csr(int32_t n, const int32_t *row_ptr, const int32_t *col_idx,
+                       bool symmetric) {
+    if (row_ptr[0] != 0) return BC_ERR_INVALID_GRAPH;
+    for (int32_t v = 0; v < n; ++v)
+        if (row_ptr[v + 1] < row_ptr[v]) return BC_ERR_INVALID_GRAPH;
+    const int64_t nnz = row_ptr[n];
+    for (int64_t e = 0; e < nnz; ++e)
+        if (col_idx[e] < 0 || col_idx[e] >= n) return BC_ERR_INVALID_GRAPH;
+    if (!symmetric) return BC_OK;
+    // transpose by counting sort; rows of the transpose come out ascending
+    std::vector<int64_t> toff((size_t)n + 1, 0);
+    for (int64_t e = 0; e < nnz; ++e) toff[(size_t)col_idx[e] + 1]++;
+    for (int32_t v = 0; v < n; ++v) toff[(size_t)v + 1] += toff[(size_t)v];
+    for (int32_t v = 0; v < n; ++v)
+        if (toff[(size_t)v + 1] - toff[(size_t)v] != (int64_t)row_ptr[v + 1] - row_ptr[v])
+            return BC_ERR_INVALID_GRAPH;
+    std::vector<int32_t> tcol((size_t)nnz);
+    std::vector<int64_t> cur(toff.begin(), toff.end() - 1);
+    for (int32_t u = 0; u < n; ++u)
+        for (int32_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) tcol[(size_t)cur[col_idx[e]]++] = u;
+    std::vector<int32_t> row;
+    for (int32_t v = 0; v < n; ++v) {
+        row.assign(col_idx + row_ptr[v], col_idx + row_ptr[v + 1]);
+        std::sort(row.begin(), row.end());
+        if (!std::equal(row.begin(), row.end(), tcol.begin() + toff[(size_t)v]))
+            return BC_ERR_INVALID_GRAPH;
+    }
+    return BC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *bc_status_str(bc_status s) {
+    switch (s) {
+        case BC_OK: return "ok";
+        case BC_ERR_INVALID_ARG: return "invalid argument";
+        case BC_ERR_INVALID_GRAPH: return "invalid graph";
+        case BC_ERR_OUT_OF_MEMORY: return "out of device memory";
+        case BC_ERR_RANGE: return "shortest-path count out of double range";
+        case BC_ERR_DEVICE: return "HIP runtime error";
+        case BC_ERR_UNSUPPORTED: return "unsupported";
+    }
+    return "unknown status";
+}
+
+bc_status bc_create_graph(int32_t n, const int32_t *row_ptr, const int32_t *col_idx,
+                          uint32_t flags, void *stream, bc_graph_t *out) {
+    if (!out || n < 0 || !row_ptr) return BC_ERR_INVALID_ARG;
+    if (flags & ~(uint32_t)(BC_GRAPH_TRUST_SYMMETRIC | BC_GRAPH_INPUT_ON_DEVICE))
+        return BC_ERR_INVALID_ARG;
+    const bool on_device = (flags & BC_GRAPH_INPUT_ON_DEVICE) != 0;
+    hipStream_t st = (hipStream_t)stream;
+    std::vector<int32_t> h_rp;
+    const int32_t *rp_host = row_ptr;
+    if (on_device) {
+        h_rp.resize((size_t)n + 1);
+        BC_TRY_HIP(hipMemcpy(h_rp.data(), row_ptr, ((size_t)n + 1) * sizeof(int32_t),
+                             hipMemcpyDeviceToHost));
+        rp_host = h_rp.data();
+        if (rp_host[0] != 0) return BC_ERR_INVALID_GRAPH;
+        for (int32_t v = 0; v < n; ++v)
+            if (rp_host[v + 1] < rp_host[v]) return BC_ERR_INVALID_GRAPH;
+    } else {
+        if (n > 0 && row_ptr[n] > 0 && !col_idx) return BC_ERR_INVALID_ARG;
+        bc_status vs = validate_csr(n, row_ptr, col_idx, !(flags & BC_GRAPH_TRUST_SYMMETRIC));
+        if (vs != BC_OK) return vs;
+    }
+    const int64_t nnz = rp_host[n];
+    if (nnz > 0 && !col_idx) return BC_ERR_INVALID_ARG;
+
+    int device = 0;
+    BC_TRY_HIP(hipGetDevice(&device));
+    bc_graph_s *g = new (std::nothrow) bc_graph_s();
+    if (!g) return BC_ERR_OUT_OF_MEMORY;
+    g->device = device;
+    g->n = n;
+    g->nnz = nnz;
+    uint64_t chunks = 0;
+    for (int32_t v = 0; v < n; ++v) {
+        const int32_t dgr = rp_host[v + 1] - rp_host[v];
+        if (degree_bucket(dgr) == 2) chunks += chunks_of(dgr);
+    }
+    g->total_chunks2 = chunks;
+    const size_t rp_bytes = ((size_t)n + 1) * sizeof(int32_t);
+    const size_t ci_bytes = std::max<size_t>((size_t)nnz, 1) * sizeof(int32_t);
+    hipError_t e = hipMalloc(&g->d_row_ptr, rp_bytes);
+    if (e == hipSuccess) e = hipMalloc(&g->d_col_idx, ci_bytes);
+    const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    if (e == hipSuccess) e = hipMemcpyAsync(g->d_row_ptr, row_ptr, rp_bytes, kind, st);
+    if (e == hipSuccess && nnz > 0)
+        e = hipMemcpyAsync(g->d_col_idx, col_idx, (size_t)nnz * sizeof(int32_t), kind, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        if (g->d_row_ptr) (void)hipFree(g->d_row_ptr);
+        if (g->d_col_idx) (void)hipFree(g->d_col_idx);
+        delete g;
+        return from_hip(e);
+    }
+    g->device_bytes = rp_bytes + ci_bytes;
+    *out = g;
+    return BC_OK;
+}
+
+bc_status bc_destroy_graph(bc_graph_t g) {
+    if (!g) return BC_OK;
+    DeviceGuard dg(g->device);
+    for (PlainWS *ws : g->plain_pool) plain_ws_destroy(ws);
+    g->plain_pool.clear();
+    if (g->d_row_ptr) (void)hipFree(g->d_row_ptr);
+    if (g->d_col_idx) (void)hipFree(g->d_col_idx);
+    delete g;
+    return BC_OK;
+}
+
+bc_status bc_graph_info(bc_graph_t g, int32_t *n, int64_t *nnz, size_t *device_bytes) {
+    if (!g) return BC_ERR_INVALID_ARG;
+    if (n) *n = g->n;
+    if (nnz) *nnz = g->nnz;
+    if (device_bytes) *device_bytes = g->device_bytes;
+    return BC_OK;
+}
+
+bc_status bc_run_async(bc_graph_t g, const int32_t *sources, int32_t k, double *bc_out_dev,
+                       const bc_options *opt, void *stream) {
+    if (!g || (!bc_out_dev && g->n > 0)) return BC_ERR_INVALID_ARG;
+    bc_status st = check_options(opt);
+    if (st != BC_OK) return st;
+    st = check_sources(g, sources, k);
+    if (st != BC_OK) return st;
+    if (g->n == 0) return BC_OK;
+    DeviceGuard dg(g->device);
+    return plain_run(g, sources, k, bc_out_dev, opt, (hipStream_t)stream, nullptr);
+}
+
+bc_status bc_run(bc_graph_t g, const int32_t *sources, int32_t k, double *bc_out) {
+    if (!g || (!bc_out && g->n > 0)) return BC_ERR_INVALID_ARG;
+    bc_status st = check_sources(g, sources, k);
+    if (st != BC_OK) return st;
+    if (g->n == 0) return BC_OK;
+    DeviceGuard dg(g->device);
+    double *d_bc = nullptr;
+    BC_TRY_HIP(hipMalloc(&d_bc, (size_t)g->n * sizeof(double)));
+    st = plain_run(g, sources, k, d_bc, nullptr, nullptr, nullptr);
+    if (st == BC_OK || st == BC_ERR_RANGE) {
+        hipError_t e = hipMemcpy(bc_out, d_bc, (size_t)g->n * sizeof(double),
+                                 hipMemcpyDeviceToHost);
+        if (e != hipSuccess) st = from_hip(e);
+    }
+    (void)hipFree(d_bc);
+    return st;
+}
+
+bc_status bc_run_detail(bc_graph_t g, const int32_t *sources, int32_t k, const bc_options *opt,
+                        double *bc_out, int32_t *dist, double *sigma) {
+    if (!g || (!bc_out && g->n > 0)) return BC_ERR_INVALID_ARG;
+    bc_status st = check_options(opt);
+    if (st != BC_OK) return st;
+    st = check_sources(g, sources, k);
+    if (st != BC_OK) return st;
+    if (g->n == 0) return BC_OK;
+    DeviceGuard dg(g->device);
+    const size_t n = (size_t)g->n;
+    double *d_bc = nullptr;
+    int32_t *d_dist = nullptr;
+    double *d_sigma = nullptr;
+    hipError_t e = hipMalloc(&d_bc, n * sizeof(double));
+    if (e == hipSuccess && dist) e = hipMalloc(&d_dist, std::max<size_t>(1, (size_t)k) * n * sizeof(int32_t));
+    if (e == hipSuccess && sigma) e = hipMalloc(&d_sigma, std::max<size_t>(1, (size_t)k) * n * sizeof(double));
+    if (e != hipSuccess) {
+        (void)hipFree(d_bc);
+        (void)hipFree(d_dist);
+        (void)hipFree(d_sigma);
+        return from_hip(e);
+    }
+    std::vector<SourceState> exp((size_t)std::max(k, 1));
+    for (int32_t i = 0; i < k; ++i) {
+        exp[i].dist = d_dist ? d_dist + (size_t)i * n : nullptr;
+        exp[i].sigma = d_sigma ? d_sigma + (size_t)i * n : nullptr;
+    }
+    st = plain_run(g, sources, k, d_bc, opt, nullptr, (dist || sigma) ? exp.data() : nullptr);
+    if (st == BC_OK || st == BC_ERR_RANGE) {
+        e = hipMemcpy(bc_out, d_bc, n * sizeof(double), hipMemcpyDeviceToHost);
+        if (e == hipSuccess && dist)
+            e = hipMemcpy(dist, d_dist, (size_t)k * n * sizeof(int32_t), hipMemcpyDeviceToHost);
+        if (e == hipSuccess && sigma)
+            e = hipMemcpy(sigma, d_sigma, (size_t)k * n * sizeof(double), hipMemcpyDeviceToHost);
+        if (e != hipSuccess) st = from_hip(e);
+    }
+    (void)hipFree(d_bc);
+    (void)hipFree(d_dist);
+    (void)hipFree(d_sigma);
+    return st;
+}
+
+bc_status bc_single_source(bc_graph_t g, int32_t s, int32_t *dist, double *sigma,
+                           double *delta) {
+    if (!g || ((!dist || !sigma) && g->n > 0)) return BC_ERR_INVALID_ARG;
+    if (s < 0 || s >= g->n) return BC_ERR_INVALID_ARG;
+    DeviceGuard dg(g->device);
+    const size_t n = (size_t)g->n;
+    double *d_bc = nullptr, *d_sigma = nullptr, *d_delta = nullptr;
+    int32_t *d_dist = nullptr;
+    hipError_t e = hipMalloc(&d_bc, n * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(&d_dist, n * sizeof(int32_t));
+    if (e == hipSuccess) e = hipMalloc(&d_sigma, n * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(&d_delta, n * sizeof(double));
+    bc_status st = from_hip(e);
+    if (st == BC_OK) {
+        SourceState exp;
+        exp.dist = d_dist;
+        exp.sigma = d_sigma;
+        exp.delta = d_delta;
+        st = plain_run(g, &s, 1, d_bc, nullptr, nullptr, &exp);
+        if (st == BC_OK || st == BC_ERR_RANGE) {
+            e = hipMemcpy(dist, d_dist, n * sizeof(int32_t), hipMemcpyDeviceToHost);
+            if (e == hipSuccess) e = hipMemcpy(sigma, d_sigma, n * sizeof(double), hipMemcpyDeviceToHost);
+            if (e == hipSuccess && delta)
+                e = hipMemcpy(delta, d_delta, n * sizeof(double), hipMemcpyDeviceToHost);
+            if (e != hipSuccess) st = from_hip(e);
+        }
+    }
+    (void)hipFree(d_bc);
+    (void)hipFree(d_dist);
+    (void)hipFree(d_sigma);
+    (void)hipFree(d_delta);
+    return st;
+}
+
+bc_status bc_workspace_bytes(bc_graph_t g, int32_t k, const bc_options *opt, size_t *bytes) {
+    if (!g || !bytes || k < 0) return BC_ERR_INVALID_ARG;
+    bc_status st = check_options(opt);
+    if (st != BC_OK) return st;
+    *bytes = plain_ws_bytes(g);
+    return BC_OK;
+}
+
+bc_status bc_trim_workspaces(bc_graph_t g) {
+    if (!g) return BC_ERR_INVALID_ARG;
+    DeviceGuard dg(g->device);
+    std::vector<PlainWS *> idle;
+    {
+        std::lock_guard<std::mutex> lk(g->mu);
+        std::vector<PlainWS *> keep;
+        for (PlainWS *ws : g->plain_pool) (ws->busy ? keep : idle).push_back(ws);
+        g->plain_pool.swap(keep);
+    }
+    for (PlainWS *ws : idle) plain_ws_destroy(ws);
+    return BC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,75 @@
+// Internal declarations shared by the library's HIP translation units.
+// Not part of the public ABI (include/bc.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace bcx {
+
+constexpr int kWave = 64;             // CDNA wavefront width
+constexpr int kBlock = 256;           // threads per workgroup for the level kernels
+constexpr int kWavesPerBlock = kBlock / kWave;
+
+// Degree buckets of the frontier queues.  A vertex of degree d is processed by
+//   bucket 0 (d <= kB0MaxDeg):  one lane,
+//   bucket 1 (d <= kB1MaxDeg):  a group of kB1Lanes lanes,
+//   bucket 2 (larger):          one wavefront per chunk of kChunkArcs arcs;
+//                               chunks of one vertex are combined in a fixed order.
+constexpr int kB0MaxDeg = 8;
+constexpr int kB1MaxDeg = 64;
+constexpr int kB1Lanes = 8;
+constexpr int kChunkArcs = 2048;
+
+__host__ __device__ inline int degree_bucket(int32_t d) {
+    return d <= kB0MaxDeg ? 0 : (d <= kB1MaxDeg ? 1 : 2);
+}
+__host__ __device__ inline uint32_t chunks_of(int32_t d) {
+    return (uint32_t)((d + kChunkArcs - 1) / kChunkArcs);
+}
+
+// Per-level bookkeeping of the BFS queues.  Level L of bucket b occupies
+// queue_b[start_b .. start_b + cnt_b).  Counts are appended to atomically while
+// the level is being discovered (during the kernel of level L-1); starts are
+// written by the kernel of level L-1 as well, before anything reads them.
+struct LevelRec {
+    uint32_t start0, start1;
+    uint32_t vstart2, cstart2;  // bucket 2: first vertex slot, first chunk slot
+    uint32_t cnt0, cnt1;
+    unsigned long long cnt2;    // (vertex count << 32) | chunk count
+};
+static_assert(sizeof(LevelRec) == 32, "LevelRec layout");
+
+// Device view of one plain (one source at a time) workspace.
+struct PlainDev {
+    int32_t n;
+    const int32_t *row_ptr;
+    const int32_t *col_idx;
+    uint32_t *lev3;       // 2 bits per vertex (16 per word): level mod 3, or 3 = not reached
+    double *sigma;        // shortest-path counts
+    double *coef;         // (1 + delta[v]) / sigma[v], written by the reverse sweep
+    int32_t *q0, *q1, *q2;  // per-bucket queues (all levels back to back)
+    int32_t *q2c;         // bucket 2: first chunk slot of the vertex
+    int32_t *done2;       // bucket 2: chunks finished (reset by the last one)
+    double *partial;      // bucket 2: per-chunk partial sums
+    LevelRec *lvl;        // [n + 2]
+    int32_t *ctrl;        // [0] deepest non-empty level, [1] range flag
+    double *bc;           // [n] accumulated BC
+};
+
+// Launchers (bc_plain.hip).  All are asynchronous on `stream`.
+hipError_t plain_reset_run(const PlainDev &d, hipStream_t stream);
+hipError_t plain_init_source(const PlainDev &d, int32_t s, hipStream_t stream);
+hipError_t plain_forward_level(const PlainDev &d, int32_t level, int grid, hipStream_t stream);
+hipError_t plain_backward_level(const PlainDev &d, int32_t level, int grid, double *delta_out,
+                                hipStream_t stream);
+// Single-source export: fill dist = -1, sigma = 0, delta = 0 (any may be NULL),
+// then write dist / sigma of every vertex on levels 0..deepest.
+hipError_t plain_export_fill(int32_t n, int32_t *dist, double *sigma, double *delta,
+                             hipStream_t stream);
+hipError_t plain_export_levels(const PlainDev &d, int32_t deepest, int32_t *dist, double *sigma,
+                               hipStream_t stream);
+
+}  // namespace bcx

@@ -1,0 +1,88 @@
+"""Host-side checks of the C-ABI library (no GPU needed).
+
+The library must load and export every function include/bc.h declares; the
+argument and graph checks that run before any device call return the
+documented status codes.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2401_02472_amd as bcm
+from paper_2401_02472_amd import _capi
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include",
+                      "bc.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(bc_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_binding_surface():
+    assert declared_functions() == sorted(_capi.EXPORTED)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _capi.load()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_status_strings():
+    assert bcm.bc_status_str(bcm.BC_OK) == "ok"
+    assert "range" in bcm.bc_status_str(bcm.BC_ERR_RANGE)
+    assert bcm.bc_status_str(99) == "unknown status"
+
+
+def _create(n, rp, ci, flags=0):
+    lib = _capi.load()
+    out = ctypes.c_void_p()
+    rp = np.ascontiguousarray(rp, dtype=np.int32)
+    ci = np.ascontiguousarray(ci, dtype=np.int32)
+    st = lib.bc_create_graph(n, ctypes.c_void_p(rp.ctypes.data), ctypes.c_void_p(ci.ctypes.data),
+                             flags, None, ctypes.byref(out))
+    return st, out
+
+
+@pytest.mark.parametrize("rp,ci", [
+    ([1, 1, 2], [0, 1]),            # row_ptr[0] != 0
+    ([0, 2, 1], [1, 0]),            # decreasing offsets
+    ([0, 1, 2], [1, 2]),            # neighbour out of range
+    ([0, 1, 1], [1]),               # arc 0->1 without 1->0
+    ([0, 2, 3], [1, 1, 0]),         # parallel arcs one way only
+])
+def test_invalid_graphs_rejected(rp, ci):
+    st, _ = _create(2, rp, ci)
+    assert st == bcm.BC_ERR_INVALID_GRAPH
+
+
+def test_invalid_arguments_rejected():
+    lib = _capi.load()
+    rp = np.array([0, 1, 2], dtype=np.int32)
+    ci = np.array([1, 0], dtype=np.int32)
+    assert lib.bc_create_graph(2, ctypes.c_void_p(rp.ctypes.data),
+                               ctypes.c_void_p(ci.ctypes.data), 0, None, None) == \
+        bcm.BC_ERR_INVALID_ARG
+    out = ctypes.c_void_p()
+    assert lib.bc_create_graph(-1, ctypes.c_void_p(rp.ctypes.data),
+                               ctypes.c_void_p(ci.ctypes.data), 0, None, ctypes.byref(out)) == \
+        bcm.BC_ERR_INVALID_ARG
+    assert lib.bc_create_graph(2, ctypes.c_void_p(rp.ctypes.data),
+                               ctypes.c_void_p(ci.ctypes.data), 1 << 7, None,
+                               ctypes.byref(out)) == bcm.BC_ERR_INVALID_ARG
+    assert lib.bc_run(None, None, 0, None) == bcm.BC_ERR_INVALID_ARG
+    assert lib.bc_graph_info(None, None, None, None) == bcm.BC_ERR_INVALID_ARG
+    assert lib.bc_destroy_graph(None) == bcm.BC_OK
+
+
+def test_trusted_flag_skips_symmetry_only():
+    # an asymmetric CSR passes with the trust flag only if the structure is sound;
+    # structural errors are still caught before any device call
+    st, _ = _create(2, [0, 1, 2], [1, 5], flags=bcm.BC_GRAPH_TRUST_SYMMETRIC)
+    assert st == bcm.BC_ERR_INVALID_GRAPH
