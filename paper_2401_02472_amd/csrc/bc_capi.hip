@@ -20,7 +20,7 @@ using namespace bcx;
 namespace {
 
 constexpr size_t kAlign = 256;
-constexpr int kLevelGrid = 1024;  // workgroups per level kernel (4096 wavefronts)
+constexpr int kLevelGrid = 2048;  // workgroups per level kernel (8192 wavefronts)
 
 size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
@@ -81,6 +81,7 @@ size_t plain_ws_bytes(const bc_graph_s *g) {
     const size_t n = (size_t)std::max<int32_t>(g->n, 1);
     size_t b = 0;
     b += align_up(((n + 15) / 16) * sizeof(uint32_t));        // lev3
+    b += align_up(((n + 15) / 16) * 16);                      // nextmap
     b += 2 * align_up(n * sizeof(double));                    // sigma, coef
     b += 5 * align_up(n * sizeof(int32_t));                   // q0 q1 q2 q2c done2
     b += align_up(std::max<uint64_t>(g->total_chunks2, 1) * sizeof(double));  // partial
@@ -118,6 +119,7 @@ bc_status plain_ws_create(bc_graph_s *g, PlainWS **out) {
     d.row_ptr = g->d_row_ptr;
     d.col_idx = g->d_col_idx;
     d.lev3 = (uint32_t *)take(((n + 15) / 16) * sizeof(uint32_t));
+    d.nextmap = (uint8_t *)take(((n + 15) / 16) * 16);
     d.sigma = (double *)take(n * sizeof(double));
     d.coef = (double *)take(n * sizeof(double));
     d.q0 = (int32_t *)take(n * sizeof(int32_t));
@@ -233,7 +235,8 @@ bc_status plain_run(bc_graph_s *g, const int32_t *sources, int32_t k, double *bc
             if (e != hipSuccess) return fail(from_hip(e));
         }
         for (int32_t L = deepest; L >= 1; --L) {
-            e = plain_backward_level(d, L, kLevelGrid, exp ? exp[i].delta : nullptr, stream);
+            e = plain_backward_level(d, L, L == deepest, kLevelGrid,
+                                     exp ? exp[i].delta : nullptr, stream);
             if (e != hipSuccess) return fail(from_hip(e));
         }
         if (exp) {

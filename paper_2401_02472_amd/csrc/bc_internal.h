@@ -48,6 +48,7 @@ struct PlainDev {
     const int32_t *row_ptr;
     const int32_t *col_idx;
     uint32_t *lev3;       // 2 bits per vertex (16 per word): level mod 3, or 3 = not reached
+    uint8_t *nextmap;     // 1 byte per vertex (padded to 16): marked for the next level
     double *sigma;        // shortest-path counts
     double *coef;         // (1 + delta[v]) / sigma[v], written by the reverse sweep
     int32_t *q0, *q1, *q2;  // per-bucket queues (all levels back to back)
@@ -62,9 +63,12 @@ struct PlainDev {
 // Launchers (bc_plain.hip).  All are asynchronous on `stream`.
 hipError_t plain_reset_run(const PlainDev &d, hipStream_t stream);
 hipError_t plain_init_source(const PlainDev &d, int32_t s, hipStream_t stream);
+// Forward step of level L: sigma of the level-L vertices and the marks of
+// level L+1, then the compaction of the marks into the level L+1 queues.
 hipError_t plain_forward_level(const PlainDev &d, int32_t level, int grid, hipStream_t stream);
-hipError_t plain_backward_level(const PlainDev &d, int32_t level, int grid, double *delta_out,
-                                hipStream_t stream);
+// Reverse step of level L (>= 1); `deepest` marks the last level (no children).
+hipError_t plain_backward_level(const PlainDev &d, int32_t level, bool deepest, int grid,
+                                double *delta_out, hipStream_t stream);
 // Single-source export: fill dist = -1, sigma = 0, delta = 0 (any may be NULL),
 // then write dist / sigma of every vertex on levels 0..deepest.
 hipError_t plain_export_fill(int32_t n, int32_t *dist, double *sigma, double *delta,

@@ -11,35 +11,35 @@
 // traversal), which scans all n vertices every level and copies a `finished`
 // flag between host and device after each level:
 //   * Work-efficient queues: each level kernel touches only the vertices of
-//     its level, kept in per-degree-bucket queues that the previous level's
-//     kernel appended to with wavefront-aggregated atomics (one atomic per
-//     wave and bucket, positions from ballot + mbcnt).
+//     its level, kept in per-degree-bucket queues.
 //   * One pass per level does both the sigma sum of a level-L vertex (over its
-//     level L-1 neighbours) and the discovery of its unreached neighbours for
+//     level L-1 neighbours) and the marking of its unreached neighbours for
 //     level L+1, so each adjacency list is read once in the forward direction.
-//   * Level tests read a 2-bit "level mod 3" code per vertex (n/4 bytes, which
-//     stays in each XCD's L2) instead of an int32 level array: neighbours of a
+//     Marking is an idempotent byte store (no atomics per arc); a compaction
+//     kernel then turns the marks into the level L+1 queues, one thread per 16
+//     vertices, with one atomic per wavefront and bucket (positions from
+//     wavefront prefix sums).
+//   * Level tests read a 2-bit "level mod 3" code per vertex (n/4 bytes, small
+//     enough for each XCD's L2) instead of an int32 level array: neighbours of a
 //     reached vertex lie within one level of it, so level mod 3 tells parent,
-//     sibling and child apart.  Discovery turns the code from 3 (not reached)
-//     into (L+1) mod 3 with one atomicAnd, which exactly one caller wins.
+//     sibling and child apart.
 //   * The reverse pass sums c[w] = (1 + delta[w]) / sigma[w] over children w
 //     and sets delta[v] = sigma[v] * sum, which equals the listing's
 //     sum of (sigma[v] / sigma[w]) * (1 + delta[w]) up to rounding.
 //   * Degree buckets pick one lane, an 8-lane group, or one wavefront per
-//     2048-arc chunk per vertex; chunks of one vertex are combined in chunk
-//     order by the last chunk to finish, so every sum has a fixed order and
+//     2048-arc chunk per vertex.  Each lane issues its arcs' loads in batches
+//     of 8 independent loads (neighbour ids, then codes, then sigma or c) so
+//     that memory latency overlaps.  Sums run in a fixed order (chunks of one
+//     vertex are combined in chunk order by the last chunk to finish), so
 //     results are identical from run to run.
 #include "bc_internal.h"
 
 namespace bcx {
 namespace {
 
-__device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
+constexpr int kBatch = 8;  // independent loads in flight per lane and batch
 
-__device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
-    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
-                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
-}
+__device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
 
 __device__ __forceinline__ double wave_sum(double x) {
 #pragma unroll
@@ -47,26 +47,20 @@ __device__ __forceinline__ double wave_sum(double x) {
     return x;
 }
 
-__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
+__device__ __forceinline__ uint32_t wave_excl_scan(uint32_t x, uint32_t &total) {
     const int lane = lane_id();
+    uint32_t incl = x;
 #pragma unroll
     for (int off = 1; off < kWave; off <<= 1) {
-        uint32_t y = __shfl_up(x, off);
-        if (lane >= off) x += y;
+        const uint32_t y = __shfl_up(incl, off);
+        if (lane >= off) incl += y;
     }
-    return x;
+    total = __shfl(incl, kWave - 1);
+    return incl - x;
 }
 
 __device__ __forceinline__ uint32_t lev_code(const uint32_t *lev3, int32_t v) {
     return (lev3[v >> 4] >> ((v & 15) << 1)) & 3u;
-}
-
-// Turn v's code from 3 (not reached) into `code`; true for exactly one caller.
-__device__ __forceinline__ bool lev_claim(uint32_t *lev3, int32_t v, uint32_t code) {
-    const uint32_t sh = (uint32_t)(v & 15) << 1;
-    const uint32_t clear = ((~code) & 3u) << sh;
-    const uint32_t old = atomicAnd(&lev3[v >> 4], ~clear);
-    return ((old >> sh) & 3u) == 3u;
 }
 
 struct LevelCtx {
@@ -74,8 +68,6 @@ struct LevelCtx {
     int32_t L;
     uint32_t code_parent;  // (L-1) mod 3, or 4 (matches nothing) at the source level
     uint32_t code_next;    // (L+1) mod 3
-    // first slots of level L+1 in each queue
-    uint32_t ns0, ns1, nv2, nc2;
     LevelRec cur;
 };
 
@@ -86,73 +78,32 @@ __device__ __forceinline__ LevelCtx make_ctx(const PlainDev &d, int32_t L) {
     c.code_parent = L > 0 ? (uint32_t)((L + 2) % 3) : 4u;
     c.code_next = (uint32_t)((L + 1) % 3);
     c.cur = d.lvl[L];
-    c.ns0 = c.cur.start0 + c.cur.cnt0;
-    c.ns1 = c.cur.start1 + c.cur.cnt1;
-    c.nv2 = c.cur.vstart2 + (uint32_t)(c.cur.cnt2 >> 32);
-    c.nc2 = c.cur.cstart2 + (uint32_t)(c.cur.cnt2 & 0xffffffffu);
     return c;
 }
 
-// Append the vertices this wave discovered (one per lane at most) to the
-// level L+1 queues.  Called by all 64 lanes.
-__device__ void append_discovered(const LevelCtx &c, bool found, int32_t v) {
-    const uint64_t any = __ballot(found);
-    if (any == 0) return;
-    const int lane = lane_id();
-    int32_t deg = 0;
-    if (found) deg = c.d.row_ptr[v + 1] - c.d.row_ptr[v];
-    const int b = found ? degree_bucket(deg) : -1;
-    LevelRec *nx = &c.d.lvl[c.L + 1];
-
-    const uint64_t m0 = __ballot(b == 0);
-    if (m0) {
-        const int leader = __ffsll((unsigned long long)m0) - 1;
-        uint32_t base = 0;
-        if (lane == leader) base = atomicAdd(&nx->cnt0, (uint32_t)__popcll(m0));
-        base = __shfl(base, leader);
-        if (b == 0) c.d.q0[c.ns0 + base + lanes_below(m0)] = v;
-    }
-    const uint64_t m1 = __ballot(b == 1);
-    if (m1) {
-        const int leader = __ffsll((unsigned long long)m1) - 1;
-        uint32_t base = 0;
-        if (lane == leader) base = atomicAdd(&nx->cnt1, (uint32_t)__popcll(m1));
-        base = __shfl(base, leader);
-        if (b == 1) c.d.q1[c.ns1 + base + lanes_below(m1)] = v;
-    }
-    const uint64_t m2 = __ballot(b == 2);
-    if (m2) {
-        const uint32_t nch = (b == 2) ? chunks_of(deg) : 0u;
-        const uint32_t incl = wave_incl_scan(nch);
-        const uint32_t total = __shfl(incl, kWave - 1);
-        const int leader = __ffsll((unsigned long long)m2) - 1;
-        uint32_t vb = 0, cb = 0;
-        if (lane == leader) {
-            const unsigned long long old = atomicAdd(
-                &nx->cnt2, ((unsigned long long)__popcll(m2) << 32) | (unsigned long long)total);
-            vb = (uint32_t)(old >> 32);
-            cb = (uint32_t)(old & 0xffffffffu);
-        }
-        vb = __shfl(vb, leader);
-        cb = __shfl(cb, leader);
-        if (b == 2) {
-            const uint32_t slot = c.nv2 + vb + lanes_below(m2);
-            c.d.q2[slot] = v;
-            c.d.q2c[slot] = (int32_t)(c.nc2 + cb + incl - nch);
-            c.d.done2[slot] = 0;
-        }
-    }
-    if (lane == __ffsll((unsigned long long)any) - 1) atomicMax(&c.d.ctrl[0], c.L + 1);
-}
-
-// Forward visit of arc (w -> v) for a level-L owner w.
-__device__ __forceinline__ void fwd_arc(const LevelCtx &c, int32_t v, double &acc,
-                                        bool &found) {
-    const uint32_t code = lev_code(c.d.lev3, v);
-    if (code == c.code_parent) {
-        acc += c.d.sigma[v];
-    } else if (code == 3u) {
-        found = lev_claim(c.d.lev3, v, c.code_next);
+// Arcs first + stride*j, j < count (count <= kBatch), of one owner vertex.
+// Forward: acc += sigma of parents, unreached neighbours are marked.
+// Reverse: acc += c of children.  Terms are added in j order.
+template <bool FWD>
+__device__ __forceinline__ void arc_batch(const LevelCtx &c, int32_t first, int32_t stride,
+                                          int32_t count, double &acc) {
+    int32_t v[kBatch];
+#pragma unroll
+    for (int j = 0; j < kBatch; ++j) v[j] = (j < count) ? c.d.col_idx[first + stride * j] : -1;
+    uint32_t code[kBatch];
+#pragma unroll
+    for (int j = 0; j < kBatch; ++j) code[j] = (v[j] >= 0) ? lev_code(c.d.lev3, v[j]) : 4u;
+    const uint32_t want = FWD ? c.code_parent : c.code_next;
+    const double *val = FWD ? c.d.sigma : c.d.coef;
+    double x[kBatch];
+#pragma unroll
+    for (int j = 0; j < kBatch; ++j) x[j] = (code[j] == want) ? val[v[j]] : 0.0;
+#pragma unroll
+    for (int j = 0; j < kBatch; ++j) acc += x[j];
+    if (FWD) {
+#pragma unroll
+        for (int j = 0; j < kBatch; ++j)
+            if (code[j] == 3u) c.d.nextmap[v[j]] = 1;
     }
 }
 
@@ -167,72 +118,41 @@ __device__ __forceinline__ void set_delta(const LevelCtx &c, int32_t v, double a
     const double sv = c.d.sigma[v];
     const double delta = sv * acc;
     c.d.coef[v] = (1.0 + delta) / sv;
-    c.d.bc[v] += delta;
+    if (delta != 0.0) c.d.bc[v] += delta;
     if (delta_out) delta_out[v] = delta;
 }
 
-// ---- bucket 0: one lane per vertex -------------------------------------
+// ---- bucket 0: one lane per vertex (degree <= 8) --------------------------
 template <bool FWD>
-__device__ void level_b0(const LevelCtx &c, uint32_t item, double *delta_out) {
-    const int lane = lane_id();
-    const uint32_t idx = item * kWave + (uint32_t)lane;
-    const bool active = idx < c.cur.cnt0;
-    int32_t w = 0, rs = 0, re = 0;
-    if (active) {
-        w = c.d.q0[c.cur.start0 + idx];
-        rs = c.d.row_ptr[w];
-        re = c.d.row_ptr[w + 1];
-    }
+__device__ void level_b0(const LevelCtx &c, uint32_t item, bool leaf, double *delta_out) {
+    const uint32_t idx = item * kWave + (uint32_t)lane_id();
+    if (idx >= c.cur.cnt0) return;
+    const int32_t w = c.d.q0[c.cur.start0 + idx];
     double acc = 0.0;
-    for (int32_t j = 0;; ++j) {
-        const bool has = rs + j < re;
-        if (__ballot(has) == 0) break;
-        bool found = false;
-        int32_t v = 0;
-        if (has) {
-            v = c.d.col_idx[rs + j];
-            if (FWD) {
-                fwd_arc(c, v, acc, found);
-            } else if (lev_code(c.d.lev3, v) == c.code_next) {
-                acc += c.d.coef[v];
-            }
-        }
-        if (FWD) append_discovered(c, found, v);
+    if (!leaf) {
+        const int32_t rs = c.d.row_ptr[w], re = c.d.row_ptr[w + 1];
+        arc_batch<FWD>(c, rs, 1, re - rs, acc);
     }
-    if (active) {
-        if (FWD) set_sigma(c, w, acc);
-        else set_delta(c, w, acc, delta_out);
-    }
+    if (FWD) set_sigma(c, w, acc);
+    else set_delta(c, w, acc, delta_out);
 }
 
-// ---- bucket 1: kB1Lanes lanes per vertex --------------------------------
+// ---- bucket 1: kB1Lanes lanes per vertex (degree <= 64) --------------------
 template <bool FWD>
-__device__ void level_b1(const LevelCtx &c, uint32_t item, double *delta_out) {
+__device__ void level_b1(const LevelCtx &c, uint32_t item, bool leaf, double *delta_out) {
     const int lane = lane_id();
     const int sub = lane & (kB1Lanes - 1);
     const uint32_t idx = item * (kWave / kB1Lanes) + (uint32_t)(lane / kB1Lanes);
     const bool active = idx < c.cur.cnt1;
-    int32_t w = 0, rs = 0, re = 0;
+    int32_t w = 0;
+    double acc = 0.0;
     if (active) {
         w = c.d.q1[c.cur.start1 + idx];
-        rs = c.d.row_ptr[w];
-        re = c.d.row_ptr[w + 1];
-    }
-    double acc = 0.0;
-    for (int32_t e = rs + sub;; e += kB1Lanes) {
-        const bool has = e < re;
-        if (__ballot(has) == 0) break;
-        bool found = false;
-        int32_t v = 0;
-        if (has) {
-            v = c.d.col_idx[e];
-            if (FWD) {
-                fwd_arc(c, v, acc, found);
-            } else if (lev_code(c.d.lev3, v) == c.code_next) {
-                acc += c.d.coef[v];
-            }
+        if (!leaf) {
+            const int32_t rs = c.d.row_ptr[w], re = c.d.row_ptr[w + 1];
+            const int32_t cnt = (re - rs - sub + kB1Lanes - 1) / kB1Lanes;
+            arc_batch<FWD>(c, rs + sub, kB1Lanes, cnt, acc);
         }
-        if (FWD) append_discovered(c, found, v);
     }
 #pragma unroll
     for (int off = kB1Lanes / 2; off >= 1; off >>= 1) acc += __shfl_xor(acc, off);
@@ -244,7 +164,7 @@ __device__ void level_b1(const LevelCtx &c, uint32_t item, double *delta_out) {
 
 // ---- bucket 2: one wavefront per chunk of kChunkArcs arcs ----------------
 template <bool FWD>
-__device__ void level_b2(const LevelCtx &c, uint32_t item, double *delta_out) {
+__device__ void level_b2(const LevelCtx &c, uint32_t item, bool leaf, double *delta_out) {
     const int lane = lane_id();
     const uint32_t nv = (uint32_t)(c.cur.cnt2 >> 32);
     const int32_t slot = (int32_t)(c.cur.cstart2 + item);
@@ -264,20 +184,10 @@ __device__ void level_b2(const LevelCtx &c, uint32_t item, double *delta_out) {
     const int32_t cb = rs + j * kChunkArcs;
     const int32_t ce = min(re, cb + kChunkArcs);
     double acc = 0.0;
-    for (int32_t e = cb + lane;; e += kWave) {
-        const bool has = e < ce;
-        if (__ballot(has) == 0) break;
-        bool found = false;
-        int32_t v = 0;
-        if (has) {
-            v = c.d.col_idx[e];
-            if (FWD) {
-                fwd_arc(c, v, acc, found);
-            } else if (lev_code(c.d.lev3, v) == c.code_next) {
-                acc += c.d.coef[v];
-            }
-        }
-        if (FWD) append_discovered(c, found, v);
+    if (!leaf) {
+        const int32_t mine = (ce - cb - lane + kWave - 1) / kWave;  // arcs of this lane
+        for (int32_t t = 0; t < mine; t += kBatch)
+            arc_batch<FWD>(c, cb + lane + t * kWave, kWave, min(kBatch, mine - t), acc);
     }
     acc = wave_sum(acc);
     if (nch == 1) {
@@ -311,19 +221,9 @@ __device__ void level_b2(const LevelCtx &c, uint32_t item, double *delta_out) {
 }
 
 template <bool FWD>
-__global__ __launch_bounds__(kBlock) void k_level(PlainDev d, int32_t L, double *delta_out) {
+__global__ __launch_bounds__(kBlock) void k_level(PlainDev d, int32_t L, int32_t leaf,
+                                                  double *delta_out) {
     const LevelCtx c = make_ctx(d, L);
-    if (FWD && blockIdx.x == 0 && threadIdx.x == 0) {
-        LevelRec *nx = &d.lvl[L + 1];
-        nx->start0 = c.ns0;
-        nx->start1 = c.ns1;
-        nx->vstart2 = c.nv2;
-        nx->cstart2 = c.nc2;
-        LevelRec *nn = &d.lvl[L + 2];
-        nn->cnt0 = 0;
-        nn->cnt1 = 0;
-        nn->cnt2 = 0ull;
-    }
     const uint32_t nch2 = (uint32_t)(c.cur.cnt2 & 0xffffffffu);
     const uint32_t w1 = (c.cur.cnt1 + (kWave / kB1Lanes) - 1) / (kWave / kB1Lanes);
     const uint32_t w0 = (c.cur.cnt0 + kWave - 1) / kWave;
@@ -331,13 +231,133 @@ __global__ __launch_bounds__(kBlock) void k_level(PlainDev d, int32_t L, double 
     const uint32_t wave = (blockIdx.x * kBlock + threadIdx.x) / kWave;
     const uint32_t nwaves = gridDim.x * kWavesPerBlock;
     for (uint32_t it = wave; it < total; it += nwaves) {
-        if (it < nch2) level_b2<FWD>(c, it, delta_out);
-        else if (it < nch2 + w1) level_b1<FWD>(c, it - nch2, delta_out);
-        else level_b0<FWD>(c, it - nch2 - w1, delta_out);
+        if (it < nch2) level_b2<FWD>(c, it, leaf != 0, delta_out);
+        else if (it < nch2 + w1) level_b1<FWD>(c, it - nch2, leaf != 0, delta_out);
+        else level_b0<FWD>(c, it - nch2 - w1, leaf != 0, delta_out);
+    }
+}
+
+// Compaction after the forward step of level L: every marked vertex gets code
+// (L+1) mod 3 and a slot in the level L+1 queue of its degree bucket; marks
+// are cleared.  Thread t owns vertices 16t .. 16t+15 (one code word, one
+// 16-byte mark group), so codes are written without atomics.
+__global__ __launch_bounds__(kBlock) void k_compact(PlainDev d, int32_t L) {
+    const LevelRec cur = d.lvl[L];
+    const uint32_t ns0 = cur.start0 + cur.cnt0;
+    const uint32_t ns1 = cur.start1 + cur.cnt1;
+    const uint32_t nv2 = cur.vstart2 + (uint32_t)(cur.cnt2 >> 32);
+    const uint32_t nc2 = cur.cstart2 + (uint32_t)(cur.cnt2 & 0xffffffffu);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        LevelRec *nx = &d.lvl[L + 1];
+        nx->start0 = ns0;
+        nx->start1 = ns1;
+        nx->vstart2 = nv2;
+        nx->cstart2 = nc2;
+        LevelRec *nn = &d.lvl[L + 2];
+        nn->cnt0 = 0;
+        nn->cnt1 = 0;
+        nn->cnt2 = 0ull;
+    }
+    const uint32_t code = (uint32_t)((L + 1) % 3);
+    const int32_t words = (d.n + 15) >> 4;
+    LevelRec *nx = &d.lvl[L + 1];
+    const int lane = lane_id();
+    // All lanes of a wave run the same number of iterations (ballots inside).
+    const int32_t stride = gridDim.x * kBlock;
+    const int32_t base0 = blockIdx.x * kBlock + (threadIdx.x & ~(kWave - 1));
+    for (int32_t wb = base0; wb < words; wb += stride) {
+        const int32_t i = wb + lane;
+        uint4 m = make_uint4(0u, 0u, 0u, 0u);
+        if (i < words) m = reinterpret_cast<const uint4 *>(d.nextmap)[i];
+        const bool any = (m.x | m.y | m.z | m.w) != 0u;
+        if (__ballot(any) == 0) continue;
+        uint32_t bits = 0;  // bit j: vertex 16i+j is marked
+        {
+            const uint32_t wv[4] = {m.x, m.y, m.z, m.w};
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int b = 0; b < 4; ++b)
+                    if ((wv[q] >> (8 * b)) & 0xffu) bits |= 1u << (4 * q + b);
+        }
+        int32_t deg[16];
+        uint32_t c0 = 0, c1 = 0, c2 = 0, ch2 = 0;
+        if (bits) {
+            const int32_t v0 = i << 4;
+            int32_t rp[17];
+#pragma unroll
+            for (int j = 0; j <= 16; ++j) rp[j] = (v0 + j <= d.n) ? d.row_ptr[v0 + j] : 0;
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                deg[j] = rp[j + 1] - rp[j];
+                if ((bits >> j) & 1u) {
+                    const int b = degree_bucket(deg[j]);
+                    if (b == 0) ++c0;
+                    else if (b == 1) ++c1;
+                    else {
+                        ++c2;
+                        ch2 += chunks_of(deg[j]);
+                    }
+                }
+            }
+            // codes: fields of marked vertices go from 3 to `code`
+            uint32_t clear = 0;
+#pragma unroll
+            for (int j = 0; j < 16; ++j)
+                if ((bits >> j) & 1u) clear |= ((~code) & 3u) << (2 * j);
+            d.lev3[i] &= ~clear;
+            reinterpret_cast<uint4 *>(d.nextmap)[i] = make_uint4(0u, 0u, 0u, 0u);
+        }
+        uint32_t t0, t1, t2, tc2;
+        uint32_t o0 = wave_excl_scan(c0, t0);
+        uint32_t o1 = wave_excl_scan(c1, t1);
+        uint32_t o2 = wave_excl_scan(c2, t2);
+        uint32_t oc2 = wave_excl_scan(ch2, tc2);
+        uint32_t b0 = 0, b1 = 0, bv2 = 0, bc2 = 0;
+        if (lane == 0) {
+            if (t0) b0 = atomicAdd(&nx->cnt0, t0);
+            if (t1) b1 = atomicAdd(&nx->cnt1, t1);
+            if (t2) {
+                const unsigned long long old = atomicAdd(
+                    &nx->cnt2, ((unsigned long long)t2 << 32) | (unsigned long long)tc2);
+                bv2 = (uint32_t)(old >> 32);
+                bc2 = (uint32_t)(old & 0xffffffffu);
+            }
+            if (t0 | t1 | t2) atomicMax(&d.ctrl[0], L + 1);
+        }
+        b0 = __shfl(b0, 0);
+        b1 = __shfl(b1, 0);
+        bv2 = __shfl(bv2, 0);
+        bc2 = __shfl(bc2, 0);
+        if (bits) {
+            uint32_t p0 = ns0 + b0 + o0, p1 = ns1 + b1 + o1, p2 = nv2 + bv2 + o2;
+            uint32_t pc = nc2 + bc2 + oc2;
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                if (!((bits >> j) & 1u)) continue;
+                const int32_t v = (i << 4) + j;
+                const int b = degree_bucket(deg[j]);
+                if (b == 0) {
+                    d.q0[p0++] = v;
+                } else if (b == 1) {
+                    d.q1[p1++] = v;
+                } else {
+                    d.q2[p2] = v;
+                    d.q2c[p2] = (int32_t)pc;
+                    d.done2[p2] = 0;
+                    ++p2;
+                    pc += chunks_of(deg[j]);
+                }
+            }
+        }
     }
 }
 
 __global__ void k_reset_run(PlainDev d) {
+    const int32_t groups = (d.n + 15) >> 4;
+    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < groups;
+         i += gridDim.x * blockDim.x)
+        reinterpret_cast<uint4 *>(d.nextmap)[i] = make_uint4(0u, 0u, 0u, 0u);
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         d.ctrl[0] = 0;
         d.ctrl[1] = 0;
@@ -403,32 +423,41 @@ __global__ void k_export_levels(PlainDev d, int32_t deepest, int32_t *dist, doub
     }
 }
 
+int grid_for(int64_t items, int cap) {
+    int64_t g = (items + kBlock - 1) / kBlock;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (int)g;
+}
+
 }  // namespace
 
 hipError_t plain_reset_run(const PlainDev &d, hipStream_t stream) {
-    hipLaunchKernelGGL(k_reset_run, dim3(1), dim3(64), 0, stream, d);
+    hipLaunchKernelGGL(k_reset_run, dim3(grid_for((d.n + 15) / 16, 1024)), dim3(kBlock), 0,
+                       stream, d);
     return hipGetLastError();
 }
 
 hipError_t plain_init_source(const PlainDev &d, int32_t s, hipStream_t stream) {
-    const int32_t words = (d.n + 15) >> 4;
-    int grid = (words + kBlock - 1) / kBlock;
-    if (grid < 1) grid = 1;
-    if (grid > 1024) grid = 1024;
-    hipLaunchKernelGGL(k_init_source, dim3(grid), dim3(kBlock), 0, stream, d, s);
+    hipLaunchKernelGGL(k_init_source, dim3(grid_for((d.n + 15) / 16, 1024)), dim3(kBlock), 0,
+                       stream, d, s);
     return hipGetLastError();
 }
 
 hipError_t plain_forward_level(const PlainDev &d, int32_t level, int grid, hipStream_t stream) {
-    hipLaunchKernelGGL(k_level<true>, dim3(grid), dim3(kBlock), 0, stream, d, level,
+    hipLaunchKernelGGL(k_level<true>, dim3(grid), dim3(kBlock), 0, stream, d, level, 0,
                        (double *)nullptr);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_compact, dim3(grid_for((d.n + 15) / 16, 2048)), dim3(kBlock), 0,
+                       stream, d, level);
     return hipGetLastError();
 }
 
-hipError_t plain_backward_level(const PlainDev &d, int32_t level, int grid, double *delta_out,
-                                hipStream_t stream) {
+hipError_t plain_backward_level(const PlainDev &d, int32_t level, bool deepest, int grid,
+                                double *delta_out, hipStream_t stream) {
     hipLaunchKernelGGL(k_level<false>, dim3(grid), dim3(kBlock), 0, stream, d, level,
-                       delta_out);
+                       deepest ? 1 : 0, delta_out);
     return hipGetLastError();
 }
 
@@ -441,11 +470,8 @@ hipError_t plain_export_levels(const PlainDev &d, int32_t deepest, int32_t *dist
 
 hipError_t plain_export_fill(int32_t n, int32_t *dist, double *sigma, double *delta,
                              hipStream_t stream) {
-    int grid = (n + kBlock - 1) / kBlock;
-    if (grid < 1) grid = 1;
-    if (grid > 2048) grid = 2048;
-    hipLaunchKernelGGL(k_export_fill, dim3(grid), dim3(kBlock), 0, stream, n, dist, sigma,
-                       delta);
+    hipLaunchKernelGGL(k_export_fill, dim3(grid_for(n, 2048)), dim3(kBlock), 0, stream, n, dist,
+                       sigma, delta);
     return hipGetLastError();
 }
 
