@@ -66,8 +66,11 @@ struct bc_graph_s {
     int device = 0;
     int32_t n = 0;
     int64_t nnz = 0;
-    int32_t *d_row_ptr = nullptr;
+    int32_t *d_row_ptr = nullptr;   // CSR in the internal (degree-descending) order
     int32_t *d_col_idx = nullptr;
+    int32_t *d_perm = nullptr;      // caller id -> internal id
+    std::vector<int32_t> h_perm;    // same, on the host (source mapping)
+    int32_t b2_end = 0, b1_end = 0; // bucket id ranges
     uint64_t total_chunks2 = 0;  // chunk slots needed by bucket-2 vertices of one source
     size_t device_bytes = 0;
     std::mutex mu;
@@ -87,6 +90,7 @@ size_t plain_ws_bytes(const bc_graph_s *g) {
     b += align_up(std::max<uint64_t>(g->total_chunks2, 1) * sizeof(double));  // partial
     b += align_up((n + 2) * sizeof(LevelRec));                // lvl
     b += align_up(2 * sizeof(int32_t));                       // ctrl
+    b += align_up(n * sizeof(double));                        // bc (internal order)
     return b;
 }
 
@@ -130,7 +134,9 @@ bc_status plain_ws_create(bc_graph_s *g, PlainWS **out) {
     d.partial = (double *)take(std::max<uint64_t>(g->total_chunks2, 1) * sizeof(double));
     d.lvl = (LevelRec *)take((n + 2) * sizeof(LevelRec));
     d.ctrl = (int32_t *)take(2 * sizeof(int32_t));
-    d.bc = nullptr;
+    d.bc = (double *)take(n * sizeof(double));
+    d.b2_end = g->b2_end;
+    d.b1_end = g->b1_end;
     *out = ws;
     return BC_OK;
 }
@@ -206,51 +212,79 @@ bc_status plain_forward(bc_graph_s *g, PlainWS *ws, int32_t s, int32_t chunk0,
     }
 }
 
-bc_status plain_run(bc_graph_s *g, const int32_t *sources, int32_t k, double *bc_dev,
-                    const bc_options *opt, hipStream_t stream, const SourceState *exp) {
+// Export buffers of one source in internal order (device temporaries).
+struct ExportTmp {
+    int32_t *dist = nullptr;
+    double *sigma = nullptr;
+    double *delta = nullptr;
+};
+
+bc_status plain_run(bc_graph_s *g, const int32_t *sources, int32_t k, double *bc_out,
+                    const bc_options *opt, hipStream_t stream, const SourceState *exp,
+                    const ExportTmp *tmp) {
     PlainWS *ws = nullptr;
     bc_status st = plain_acquire(g, stream, &ws);
     if (st != BC_OK) return st;
-    PlainDev d = ws->dev;
-    d.bc = bc_dev;
-    ws->dev.bc = bc_dev;
+    const PlainDev &d = ws->dev;
     bc_status result = BC_OK;
     auto fail = [&](bc_status s2) {
         plain_release(g, ws, stream);
         return s2;
     };
-    hipError_t e = hipMemsetAsync(bc_dev, 0, (size_t)g->n * sizeof(double), stream);
+    hipError_t e = hipMemsetAsync(d.bc, 0, (size_t)g->n * sizeof(double), stream);
     if (e != hipSuccess) return fail(from_hip(e));
     e = plain_reset_run(d, stream);
     if (e != hipSuccess) return fail(from_hip(e));
     const int32_t user_chunk = opt ? opt->level_chunk : 0;
     for (int32_t i = 0; i < k; ++i) {
+        const int32_t s_int = g->h_perm[(size_t)sources[i]];
         const int32_t chunk = user_chunk > 0 ? user_chunk : g->last_depth.load() + 2;
         int32_t deepest = 0;
-        st = plain_forward(g, ws, sources[i], chunk, stream, &deepest);
+        st = plain_forward(g, ws, s_int, chunk, stream, &deepest);
         if (st != BC_OK) return fail(st);
         if (user_chunk <= 0) g->last_depth.store(deepest);
         if (exp) {
-            e = plain_export_fill(g->n, exp[i].dist, exp[i].sigma, exp[i].delta, stream);
+            e = plain_export_fill(g->n, tmp->dist, tmp->sigma, tmp->delta, stream);
             if (e != hipSuccess) return fail(from_hip(e));
         }
         for (int32_t L = deepest; L >= 1; --L) {
             e = plain_backward_level(d, L, L == deepest, kLevelGrid,
-                                     exp ? exp[i].delta : nullptr, stream);
+                                     exp ? tmp->delta : nullptr, stream);
             if (e != hipSuccess) return fail(from_hip(e));
         }
         if (exp) {
-            e = plain_export_levels(d, deepest, exp[i].dist, exp[i].sigma, stream);
+            e = plain_export_levels(d, deepest, tmp->dist, tmp->sigma, stream);
+            if (e == hipSuccess && exp[i].dist) e = gather_i32(g->n, g->d_perm, tmp->dist, exp[i].dist, stream);
+            if (e == hipSuccess && exp[i].sigma) e = gather_f64(g->n, g->d_perm, tmp->sigma, exp[i].sigma, stream);
+            if (e == hipSuccess && exp[i].delta) e = gather_f64(g->n, g->d_perm, tmp->delta, exp[i].delta, stream);
             if (e != hipSuccess) return fail(from_hip(e));
         }
     }
-    e = hipMemcpyAsync(ws->h_ctrl, d.ctrl, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, stream);
+    e = gather_f64(g->n, g->d_perm, d.bc, bc_out, stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(ws->h_ctrl, d.ctrl, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
     if (e != hipSuccess) return fail(from_hip(e));
     if (ws->h_ctrl[1] != 0) result = BC_ERR_RANGE;
     plain_release(g, ws, stream);
     return result;
 }
+
+// Device temporaries for the single-source export (internal order).
+struct ExportAlloc {
+    ExportTmp t;
+    hipError_t alloc(size_t n) {
+        hipError_t e = hipMalloc(&t.dist, n * sizeof(int32_t));
+        if (e == hipSuccess) e = hipMalloc(&t.sigma, n * sizeof(double));
+        if (e == hipSuccess) e = hipMalloc(&t.delta, n * sizeof(double));
+        return e;
+    }
+    ~ExportAlloc() {
+        if (t.dist) (void)hipFree(t.dist);
+        if (t.sigma) (void)hipFree(t.sigma);
+        if (t.delta) (void)hipFree(t.delta);
+    }
+};
 
 bc_status check_options(const bc_options *opt) {
     if (!opt) return BC_OK;
@@ -336,6 +370,15 @@ bc_status bc_create_graph(int32_t n, const int32_t *row_ptr, const int32_t *col_
         if (rp_host[0] != 0) return BC_ERR_INVALID_GRAPH;
         for (int32_t v = 0; v < n; ++v)
             if (rp_host[v + 1] < rp_host[v]) return BC_ERR_INVALID_GRAPH;
+        // the neighbour ids are checked on the host too: the relabelling
+        // kernel indexes with them
+        if (rp_host[n] > 0 && !col_idx) return BC_ERR_INVALID_ARG;
+        std::vector<int32_t> h_ci((size_t)rp_host[n]);
+        if (rp_host[n] > 0)
+            BC_TRY_HIP(hipMemcpy(h_ci.data(), col_idx, (size_t)rp_host[n] * sizeof(int32_t),
+                                 hipMemcpyDeviceToHost));
+        bc_status vs = validate_csr(n, rp_host, h_ci.data(), !(flags & BC_GRAPH_TRUST_SYMMETRIC));
+        if (vs != BC_OK) return vs;
     } else {
         if (n > 0 && row_ptr[n] > 0 && !col_idx) return BC_ERR_INVALID_ARG;
         bc_status vs = validate_csr(n, row_ptr, col_idx, !(flags & BC_GRAPH_TRUST_SYMMETRIC));
@@ -351,28 +394,71 @@ bc_status bc_create_graph(int32_t n, const int32_t *row_ptr, const int32_t *col_
     g->device = device;
     g->n = n;
     g->nnz = nnz;
-    uint64_t chunks = 0;
+
+    // Internal order: degree descending, ties by caller id (counting sort).
+    int32_t maxdeg = 0;
+    for (int32_t v = 0; v < n; ++v) maxdeg = std::max(maxdeg, rp_host[v + 1] - rp_host[v]);
+    std::vector<int64_t> start((size_t)maxdeg + 2, 0);
+    for (int32_t v = 0; v < n; ++v) start[(size_t)(maxdeg - (rp_host[v + 1] - rp_host[v])) + 1]++;
+    for (size_t i = 1; i < start.size(); ++i) start[i] += start[i - 1];
+    std::vector<int32_t> iperm((size_t)std::max(n, 1));
+    g->h_perm.assign((size_t)std::max(n, 1), 0);
     for (int32_t v = 0; v < n; ++v) {
-        const int32_t dgr = rp_host[v + 1] - rp_host[v];
-        if (degree_bucket(dgr) == 2) chunks += chunks_of(dgr);
+        const int32_t slot = (int32_t)start[(size_t)(maxdeg - (rp_host[v + 1] - rp_host[v]))]++;
+        iperm[(size_t)slot] = v;
+        g->h_perm[(size_t)v] = slot;
+    }
+    std::vector<int32_t> new_rp((size_t)n + 1, 0);
+    uint64_t chunks = 0;
+    for (int32_t u = 0; u < n; ++u) {
+        const int32_t o = iperm[(size_t)u];
+        const int32_t dgr = rp_host[o + 1] - rp_host[o];
+        new_rp[(size_t)u + 1] = new_rp[(size_t)u] + dgr;
+        const int b = degree_bucket(dgr);
+        if (b == 2) {
+            g->b2_end = u + 1;
+            chunks += chunks_of(dgr);
+        }
+        if (b >= 1) g->b1_end = u + 1;
     }
     g->total_chunks2 = chunks;
+
     const size_t rp_bytes = ((size_t)n + 1) * sizeof(int32_t);
     const size_t ci_bytes = std::max<size_t>((size_t)nnz, 1) * sizeof(int32_t);
+    const size_t pm_bytes = (size_t)std::max(n, 1) * sizeof(int32_t);
+    int32_t *t_rp = nullptr, *t_ci = nullptr, *t_iperm = nullptr;
     hipError_t e = hipMalloc(&g->d_row_ptr, rp_bytes);
     if (e == hipSuccess) e = hipMalloc(&g->d_col_idx, ci_bytes);
-    const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
-    if (e == hipSuccess) e = hipMemcpyAsync(g->d_row_ptr, row_ptr, rp_bytes, kind, st);
-    if (e == hipSuccess && nnz > 0)
-        e = hipMemcpyAsync(g->d_col_idx, col_idx, (size_t)nnz * sizeof(int32_t), kind, st);
+    if (e == hipSuccess) e = hipMalloc(&g->d_perm, pm_bytes);
+    if (e == hipSuccess) e = hipMalloc(&t_iperm, pm_bytes);
+    if (e == hipSuccess && !on_device) e = hipMalloc(&t_rp, rp_bytes);
+    if (e == hipSuccess && !on_device) e = hipMalloc(&t_ci, ci_bytes);
+    const int32_t *old_rp = on_device ? row_ptr : t_rp;
+    const int32_t *old_ci = on_device ? col_idx : t_ci;
+    if (e == hipSuccess && !on_device)
+        e = hipMemcpyAsync(t_rp, row_ptr, rp_bytes, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && !on_device && nnz > 0)
+        e = hipMemcpyAsync(t_ci, col_idx, (size_t)nnz * sizeof(int32_t), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(g->d_row_ptr, new_rp.data(), rp_bytes, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(g->d_perm, g->h_perm.data(), pm_bytes, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(t_iperm, iperm.data(), pm_bytes, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = relabel_csr(n, nnz, old_rp, old_ci, g->d_row_ptr, g->d_perm, t_iperm, g->d_col_idx, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (t_rp) (void)hipFree(t_rp);
+    if (t_ci) (void)hipFree(t_ci);
+    if (t_iperm) (void)hipFree(t_iperm);
     if (e != hipSuccess) {
         if (g->d_row_ptr) (void)hipFree(g->d_row_ptr);
         if (g->d_col_idx) (void)hipFree(g->d_col_idx);
+        if (g->d_perm) (void)hipFree(g->d_perm);
         delete g;
         return from_hip(e);
     }
-    g->device_bytes = rp_bytes + ci_bytes;
+    g->device_bytes = rp_bytes + ci_bytes + pm_bytes;
     *out = g;
     return BC_OK;
 }
@@ -384,6 +470,7 @@ bc_status bc_destroy_graph(bc_graph_t g) {
     g->plain_pool.clear();
     if (g->d_row_ptr) (void)hipFree(g->d_row_ptr);
     if (g->d_col_idx) (void)hipFree(g->d_col_idx);
+    if (g->d_perm) (void)hipFree(g->d_perm);
     delete g;
     return BC_OK;
 }
@@ -405,7 +492,7 @@ bc_status bc_run_async(bc_graph_t g, const int32_t *sources, int32_t k, double *
     if (st != BC_OK) return st;
     if (g->n == 0) return BC_OK;
     DeviceGuard dg(g->device);
-    return plain_run(g, sources, k, bc_out_dev, opt, (hipStream_t)stream, nullptr);
+    return plain_run(g, sources, k, bc_out_dev, opt, (hipStream_t)stream, nullptr, nullptr);
 }
 
 bc_status bc_run(bc_graph_t g, const int32_t *sources, int32_t k, double *bc_out) {
@@ -416,7 +503,7 @@ bc_status bc_run(bc_graph_t g, const int32_t *sources, int32_t k, double *bc_out
     DeviceGuard dg(g->device);
     double *d_bc = nullptr;
     BC_TRY_HIP(hipMalloc(&d_bc, (size_t)g->n * sizeof(double)));
-    st = plain_run(g, sources, k, d_bc, nullptr, nullptr, nullptr);
+    st = plain_run(g, sources, k, d_bc, nullptr, nullptr, nullptr, nullptr);
     if (st == BC_OK || st == BC_ERR_RANGE) {
         hipError_t e = hipMemcpy(bc_out, d_bc, (size_t)g->n * sizeof(double),
                                  hipMemcpyDeviceToHost);
@@ -453,7 +540,15 @@ bc_status bc_run_detail(bc_graph_t g, const int32_t *sources, int32_t k, const b
         exp[i].dist = d_dist ? d_dist + (size_t)i * n : nullptr;
         exp[i].sigma = d_sigma ? d_sigma + (size_t)i * n : nullptr;
     }
-    st = plain_run(g, sources, k, d_bc, opt, nullptr, (dist || sigma) ? exp.data() : nullptr);
+    ExportAlloc tmp;
+    if ((dist || sigma) && (e = tmp.alloc(n)) != hipSuccess) {
+        (void)hipFree(d_bc);
+        (void)hipFree(d_dist);
+        (void)hipFree(d_sigma);
+        return from_hip(e);
+    }
+    st = plain_run(g, sources, k, d_bc, opt, nullptr, (dist || sigma) ? exp.data() : nullptr,
+                   &tmp.t);
     if (st == BC_OK || st == BC_ERR_RANGE) {
         e = hipMemcpy(bc_out, d_bc, n * sizeof(double), hipMemcpyDeviceToHost);
         if (e == hipSuccess && dist)
@@ -486,7 +581,10 @@ bc_status bc_single_source(bc_graph_t g, int32_t s, int32_t *dist, double *sigma
         exp.dist = d_dist;
         exp.sigma = d_sigma;
         exp.delta = d_delta;
-        st = plain_run(g, &s, 1, d_bc, nullptr, nullptr, &exp);
+        ExportAlloc tmp;
+        e = tmp.alloc(n);
+        st = e != hipSuccess ? from_hip(e)
+                             : plain_run(g, &s, 1, d_bc, nullptr, nullptr, &exp, &tmp.t);
         if (st == BC_OK || st == BC_ERR_RANGE) {
             e = hipMemcpy(dist, d_dist, n * sizeof(int32_t), hipMemcpyDeviceToHost);
             if (e == hipSuccess) e = hipMemcpy(sigma, d_sigma, n * sizeof(double), hipMemcpyDeviceToHost);

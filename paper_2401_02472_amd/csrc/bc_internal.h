@@ -23,6 +23,9 @@ constexpr int kB1MaxDeg = 64;
 constexpr int kB1Lanes = 8;
 constexpr int kChunkArcs = 2048;
 
+// The library relabels vertices by degree, descending, when a graph is
+// created, so the buckets are id ranges: [0, b2_end) bucket 2,
+// [b2_end, b1_end) bucket 1, the rest bucket 0.
 __host__ __device__ inline int degree_bucket(int32_t d) {
     return d <= kB0MaxDeg ? 0 : (d <= kB1MaxDeg ? 1 : 2);
 }
@@ -45,6 +48,7 @@ static_assert(sizeof(LevelRec) == 32, "LevelRec layout");
 // Device view of one plain (one source at a time) workspace.
 struct PlainDev {
     int32_t n;
+    int32_t b2_end, b1_end;  // bucket id ranges (see degree_bucket)
     const int32_t *row_ptr;
     const int32_t *col_idx;
     uint32_t *lev3;       // 2 bits per vertex (16 per word): level mod 3, or 3 = not reached
@@ -61,6 +65,18 @@ struct PlainDev {
 };
 
 // Launchers (bc_plain.hip).  All are asynchronous on `stream`.
+// Graph set-up (bc_graph.hip).
+// new_ci[e] = perm[old_ci[old_rp[iperm[u]] + e - new_rp[u]]] for the internal
+// vertex u owning arc e of the relabelled CSR.
+hipError_t relabel_csr(int32_t n, int64_t nnz, const int32_t *old_rp, const int32_t *old_ci,
+                       const int32_t *new_rp, const int32_t *perm, const int32_t *iperm,
+                       int32_t *new_ci, hipStream_t stream);
+// dst[o] = src[perm[o]] for o < n (internal order -> caller order).
+hipError_t gather_f64(int32_t n, const int32_t *perm, const double *src, double *dst,
+                      hipStream_t stream);
+hipError_t gather_i32(int32_t n, const int32_t *perm, const int32_t *src, int32_t *dst,
+                      hipStream_t stream);
+
 hipError_t plain_reset_run(const PlainDev &d, hipStream_t stream);
 hipError_t plain_init_source(const PlainDev &d, int32_t s, hipStream_t stream);
 // Forward step of level L: sigma of the level-L vertices and the marks of

@@ -89,7 +89,8 @@ __device__ __forceinline__ void arc_batch(const LevelCtx &c, int32_t first, int3
                                           int32_t count, double &acc) {
     int32_t v[kBatch];
 #pragma unroll
-    for (int j = 0; j < kBatch; ++j) v[j] = (j < count) ? c.d.col_idx[first + stride * j] : -1;
+    for (int j = 0; j < kBatch; ++j)
+        v[j] = (j < count) ? __builtin_nontemporal_load(&c.d.col_idx[first + stride * j]) : -1;
     uint32_t code[kBatch];
 #pragma unroll
     for (int j = 0; j < kBatch; ++j) code[j] = (v[j] >= 0) ? lev_code(c.d.lev3, v[j]) : 4u;
@@ -280,23 +281,23 @@ __global__ __launch_bounds__(kBlock) void k_compact(PlainDev d, int32_t L) {
                 for (int b = 0; b < 4; ++b)
                     if ((wv[q] >> (8 * b)) & 0xffu) bits |= 1u << (4 * q + b);
         }
-        int32_t deg[16];
         uint32_t c0 = 0, c1 = 0, c2 = 0, ch2 = 0;
+        uint32_t nch[16];
         if (bits) {
             const int32_t v0 = i << 4;
-            int32_t rp[17];
-#pragma unroll
-            for (int j = 0; j <= 16; ++j) rp[j] = (v0 + j <= d.n) ? d.row_ptr[v0 + j] : 0;
 #pragma unroll
             for (int j = 0; j < 16; ++j) {
-                deg[j] = rp[j + 1] - rp[j];
+                nch[j] = 0;
                 if ((bits >> j) & 1u) {
-                    const int b = degree_bucket(deg[j]);
-                    if (b == 0) ++c0;
-                    else if (b == 1) ++c1;
-                    else {
+                    const int32_t v = v0 + j;
+                    if (v < d.b2_end) {
                         ++c2;
-                        ch2 += chunks_of(deg[j]);
+                        nch[j] = chunks_of(d.row_ptr[v + 1] - d.row_ptr[v]);
+                        ch2 += nch[j];
+                    } else if (v < d.b1_end) {
+                        ++c1;
+                    } else {
+                        ++c0;
                     }
                 }
             }
@@ -336,17 +337,16 @@ __global__ __launch_bounds__(kBlock) void k_compact(PlainDev d, int32_t L) {
             for (int j = 0; j < 16; ++j) {
                 if (!((bits >> j) & 1u)) continue;
                 const int32_t v = (i << 4) + j;
-                const int b = degree_bucket(deg[j]);
-                if (b == 0) {
+                if (v >= d.b1_end) {
                     d.q0[p0++] = v;
-                } else if (b == 1) {
+                } else if (v >= d.b2_end) {
                     d.q1[p1++] = v;
                 } else {
                     d.q2[p2] = v;
                     d.q2c[p2] = (int32_t)pc;
                     d.done2[p2] = 0;
                     ++p2;
-                    pc += chunks_of(deg[j]);
+                    pc += nch[j];
                 }
             }
         }
@@ -375,7 +375,7 @@ __global__ void k_init_source(PlainDev d, int32_t s) {
         d.lev3[i] = (i == sw) ? sval : 0xffffffffu;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         const int32_t deg = d.row_ptr[s + 1] - d.row_ptr[s];
-        const int b = degree_bucket(deg);
+        const int b = s < d.b2_end ? 2 : (s < d.b1_end ? 1 : 0);
         LevelRec r0 = {0u, 0u, 0u, 0u, 0u, 0u, 0ull};
         if (b == 0) {
             r0.cnt0 = 1;
