@@ -86,7 +86,7 @@ size_t plain_ws_bytes(const bc_graph_s *g) {
     b += align_up(((n + 15) / 16) * sizeof(uint32_t));        // lev3
     b += align_up(((n + 15) / 16) * 16);                      // nextmap
     b += 2 * align_up(n * sizeof(double));                    // sigma, coef
-    b += 5 * align_up(n * sizeof(int32_t));                   // q0 q1 q2 q2c done2
+    b += 4 * align_up(n * sizeof(int32_t));                   // q0 q1 q2 q2c
     b += align_up(std::max<uint64_t>(g->total_chunks2, 1) * sizeof(double));  // partial
     b += align_up((n + 2) * sizeof(LevelRec));                // lvl
     b += align_up(2 * sizeof(int32_t));                       // ctrl
@@ -130,7 +130,6 @@ bc_status plain_ws_create(bc_graph_s *g, PlainWS **out) {
     d.q1 = (int32_t *)take(n * sizeof(int32_t));
     d.q2 = (int32_t *)take(n * sizeof(int32_t));
     d.q2c = (int32_t *)take(n * sizeof(int32_t));
-    d.done2 = (int32_t *)take(n * sizeof(int32_t));
     d.partial = (double *)take(std::max<uint64_t>(g->total_chunks2, 1) * sizeof(double));
     d.lvl = (LevelRec *)take((n + 2) * sizeof(LevelRec));
     d.ctrl = (int32_t *)take(2 * sizeof(int32_t));

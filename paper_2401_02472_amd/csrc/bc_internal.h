@@ -57,7 +57,6 @@ struct PlainDev {
     double *coef;         // (1 + delta[v]) / sigma[v], written by the reverse sweep
     int32_t *q0, *q1, *q2;  // per-bucket queues (all levels back to back)
     int32_t *q2c;         // bucket 2: first chunk slot of the vertex
-    int32_t *done2;       // bucket 2: chunks finished (reset by the last one)
     double *partial;      // bucket 2: per-chunk partial sums
     LevelRec *lvl;        // [n + 2]
     int32_t *ctrl;        // [0] deepest non-empty level, [1] range flag

@@ -30,8 +30,9 @@
 //     2048-arc chunk per vertex.  Each lane issues its arcs' loads in batches
 //     of 8 independent loads (neighbour ids, then codes, then sigma or c) so
 //     that memory latency overlaps.  Sums run in a fixed order (chunks of one
-//     vertex are combined in chunk order by the last chunk to finish), so
-//     results are identical from run to run.
+//     vertex are combined in chunk order by the next kernel on the stream, so
+//     no device-scope fences are needed), and results are identical from run
+//     to run.
 #include "bc_internal.h"
 
 namespace bcx {
@@ -191,34 +192,48 @@ __device__ void level_b2(const LevelCtx &c, uint32_t item, bool leaf, double *de
             arc_batch<FWD>(c, cb + lane + t * kWave, kWave, min(kBatch, mine - t), acc);
     }
     acc = wave_sum(acc);
-    if (nch == 1) {
-        if (lane == 0) {
+    if (nch == 1 || leaf) {  // a leaf level has no partials: chunk 0 finishes the vertex
+        if (lane == 0 && j == 0) {
             if (FWD) set_sigma(c, w, acc);
             else set_delta(c, w, acc, delta_out);
         }
         return;
     }
-    // Several chunks: publish this chunk's partial; the last chunk to finish
-    // adds all partials in chunk order.
-    uint32_t prev = 0;
-    if (lane == 0) {
-        __hip_atomic_store(&c.d.partial[first + j], acc, __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
-        prev = __hip_atomic_fetch_add((uint32_t *)&c.d.done2[qi], 1u, __ATOMIC_ACQ_REL,
-                                      __HIP_MEMORY_SCOPE_AGENT);
+    // Several chunks: the partial is combined with the others, in chunk order,
+    // by the next kernel on the stream (the compaction after a forward step,
+    // the finishing kernel after a reverse step).
+    if (lane == 0) c.d.partial[first + j] = acc;
+}
+
+// Sum the chunk partials of the multi-chunk (bucket 2) vertices of level L in
+// chunk order; one wavefront per vertex.  Runs in the kernel after the level
+// kernel, so the partials are visible without fences.
+template <bool FWD>
+__device__ void finish_chunks(const LevelCtx &c, uint32_t wave, uint32_t nwaves,
+                              double *delta_out) {
+    const int lane = lane_id();
+    const uint32_t nv = (uint32_t)(c.cur.cnt2 >> 32);
+    for (uint32_t k = wave; k < nv; k += nwaves) {
+        const uint32_t qi = c.cur.vstart2 + k;
+        const int32_t w = c.d.q2[qi];
+        const uint32_t nch = chunks_of(c.d.row_ptr[w + 1] - c.d.row_ptr[w]);
+        if (nch == 1) continue;
+        const int32_t first = c.d.q2c[qi];
+        double t = 0.0;
+        for (uint32_t j = (uint32_t)lane; j < nch; j += kWave) t += c.d.partial[first + j];
+        t = wave_sum(t);
+        if (lane == 0) {
+            if (FWD) set_sigma(c, w, t);
+            else set_delta(c, w, t, delta_out);
+        }
     }
-    prev = __shfl(prev, 0);
-    if (prev != nch - 1) return;
-    double t = 0.0;
-    for (uint32_t k = (uint32_t)lane; k < nch; k += kWave)
-        t += __hip_atomic_load(&c.d.partial[first + k], __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
-    t = wave_sum(t);
-    if (lane == 0) {
-        if (FWD) set_sigma(c, w, t);
-        else set_delta(c, w, t, delta_out);
-        c.d.done2[qi] = 0;
-    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_finish_reverse(PlainDev d, int32_t L,
+                                                           double *delta_out) {
+    const LevelCtx c = make_ctx(d, L);
+    finish_chunks<false>(c, (blockIdx.x * kBlock + threadIdx.x) / kWave,
+                         gridDim.x * kWavesPerBlock, delta_out);
 }
 
 template <bool FWD>
@@ -243,6 +258,11 @@ __global__ __launch_bounds__(kBlock) void k_level(PlainDev d, int32_t L, int32_t
 // are cleared.  Thread t owns vertices 16t .. 16t+15 (one code word, one
 // 16-byte mark group), so codes are written without atomics.
 __global__ __launch_bounds__(kBlock) void k_compact(PlainDev d, int32_t L) {
+    {
+        const LevelCtx c = make_ctx(d, L);
+        finish_chunks<true>(c, (blockIdx.x * kBlock + threadIdx.x) / kWave,
+                            gridDim.x * kWavesPerBlock, nullptr);
+    }
     const LevelRec cur = d.lvl[L];
     const uint32_t ns0 = cur.start0 + cur.cnt0;
     const uint32_t ns1 = cur.start1 + cur.cnt1;
@@ -344,7 +364,6 @@ __global__ __launch_bounds__(kBlock) void k_compact(PlainDev d, int32_t L) {
                 } else {
                     d.q2[p2] = v;
                     d.q2c[p2] = (int32_t)pc;
-                    d.done2[p2] = 0;
                     ++p2;
                     pc += nch[j];
                 }
@@ -387,7 +406,6 @@ __global__ void k_init_source(PlainDev d, int32_t s) {
             r0.cnt2 = (1ull << 32) | (unsigned long long)chunks_of(deg);
             d.q2[0] = s;
             d.q2c[0] = 0;
-            d.done2[0] = 0;
         }
         d.lvl[0] = r0;
         LevelRec r1 = {0u, 0u, 0u, 0u, 0u, 0u, 0ull};
@@ -458,6 +476,9 @@ hipError_t plain_backward_level(const PlainDev &d, int32_t level, bool deepest, 
                                 double *delta_out, hipStream_t stream) {
     hipLaunchKernelGGL(k_level<false>, dim3(grid), dim3(kBlock), 0, stream, d, level,
                        deepest ? 1 : 0, delta_out);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || deepest) return e;  // leaves have no chunk partials
+    hipLaunchKernelGGL(k_finish_reverse, dim3(64), dim3(kBlock), 0, stream, d, level, delta_out);
     return hipGetLastError();
 }
 
