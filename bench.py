@@ -1,0 +1,215 @@
+#!/usr/bin/env python3
+"""Benchmark: Brandes BC throughput (GTEPS) on one MI355X.
+
+One step = one full BC run (every source of the workload: forward sigma pass,
+reverse dependency pass, BC accumulation) over the resident graph, with the
+graph and the output already in device memory when the timed region starts.
+
+    GTEPS = k * nnz / t / 1e9     (k sources, nnz = CSR arcs = 2m)
+
+Prints one JSON line (see the fields below).  `roofline` reports the dominant
+kernel's algorithmic bytes per launch over its HIP-event-timed average launch
+duration; `cpu_baseline` times the CPU oracle on a bounded sample of the same
+workload on this host's cores.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "BC GTEPS (sources×2m/s) and HBM roofline %; batched vs per-source; p50/p99"
+HBM_PEAK_GBS = 8000.0
+
+# Algorithmic bytes per unit of work (element-granular: each array element a
+# kernel must touch, counted once per use).
+#   forward level kernel, per owner vertex: queue entry 4 + row_ptr pair 8 +
+#     sigma write 8; per arc read: neighbour id 4 + level-code word 4; per
+#     parent arc: parent sigma 8.
+#   reverse level kernel, per owner vertex: queue entry 4 + row_ptr pair 8 +
+#     sigma 8 + c write 8 + BC read-modify-write 16; per arc: 4 + 4; per child
+#     arc: child c 8.
+BYTES = {
+    "forward": {"owners": 20, "arcs": 8, "hits": 8},
+    "reverse": {"owners": 44, "arcs": 8, "hits": 8},
+}
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2401_02472_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode())
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(kernel: str, workload: str, src_hash: str):
+    """HBM bytes per launch from a committed counter summary, if it was taken
+    on the current kernel sources (else None)."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_counters.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m_hash = re.search(r"kernel_source_hash:\s*(\w+)", text)
+    m_val = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    if not m_hash or not m_val or m_hash.group(1) != src_hash:
+        return None
+    return float(m_val.group(1))
+
+
+def cpu_baseline(g, sources, target_s: float):
+    import numpy as np
+
+    import oracle
+
+    threads = min(os.cpu_count() or 1, 16, oracle.max_threads())
+    probe = sources[:1]
+    t = time.perf_counter()
+    oracle.bc(g.row_ptr, g.col_idx, probe, threads=1)
+    t1 = max(time.perf_counter() - t, 1e-6)
+    m = int(max(threads, min(len(sources), round(target_s * threads / t1))))
+    m = min(m, len(sources))
+    sample = np.ascontiguousarray(sources[:m])
+    t = time.perf_counter()
+    oracle.bc(g.row_ptr, g.col_idx, sample, threads=threads)
+    dt = time.perf_counter() - t
+    return {"value": round(m * g.nnz / dt / 1e9, 4), "unit": "GTEPS", "cores": threads,
+            "kind": "oracle",
+            "sample": f"first {m} of the {len(sources)} workload sources, {dt:.2f} s "
+                      f"on {threads} threads"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="rmat-s22-ef16")
+    ap.add_argument("--mode", default="plain", choices=["auto", "plain", "batched"])
+    ap.add_argument("--batch-width", type=int, default=0)
+    ap.add_argument("--sources", type=int, default=0, help="use only the first N sources")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="target oracle CPU time for the cpu_baseline sample (0 = skip)")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="run one device copy of this size first (counter calibration)")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: this build runs on a single MI355X and has no "
+              "multi-GPU path (sources would shard across GPUs with one BC all-reduce; "
+              "see DESIGN.md).", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import graphgen as gg
+    import paper_2401_02472_amd as bcm
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 2
+    torch.cuda.set_device(0)
+    bcm.load_library()
+
+    print(f"# generating {args.workload}", file=sys.stderr, flush=True)
+    g, sources = gg.workload(args.workload)
+    if args.sources:
+        sources = sources[:args.sources]
+    k = int(len(sources))
+    mode = {"auto": bcm.BC_MODE_AUTO, "plain": bcm.BC_MODE_PLAIN,
+            "batched": bcm.BC_MODE_BATCHED}[args.mode]
+    opt = bcm.make_options(mode, args.batch_width)
+
+    G = bcm.Graph(g.n, g.row_ptr, g.col_idx, flags=bcm.BC_GRAPH_TRUST_SYMMETRIC)
+    out = torch.empty(g.n, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    if args.calibrate_copy_mib:
+        nbytes = args.calibrate_copy_mib << 20
+        a = torch.empty(nbytes // 4, dtype=torch.int32, device="cuda").fill_(1)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+        print(f"# calibration copy of {args.calibrate_copy_mib} MiB done", file=sys.stderr,
+              flush=True)
+
+    for _ in range(args.warmup):
+        G.run_async(sources, out, opt)
+    torch.cuda.synchronize()
+    print(f"# warmup done: n={g.n} nnz={g.nnz} k={k}", file=sys.stderr, flush=True)
+
+    G.profile_enable(True)
+    G.profile_read(reset=True)
+    step_ms = []
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        start.record(stream)
+        G.run_async(sources, out, opt)
+        stop.record(stream)
+        stop.synchronize()
+        step_ms.append(start.elapsed_time(stop))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    prof = G.profile_read(reset=True)
+    G.profile_enable(False)
+    ms_per_step = wall * 1e3 / args.steps
+    value = k * g.nnz / (ms_per_step / 1e3) / 1e9
+    print(f"# timed {args.steps} steps: {ms_per_step:.2f} ms/step", file=sys.stderr, flush=True)
+
+    # dominant kernel and its roofline point
+    cls = max(("forward", "reverse"), key=lambda c: prof[c]["ms"])
+    pc = prof[cls]
+    alg_bytes = sum(BYTES[cls][u] * pc[u] for u in ("owners", "arcs", "hits"))
+    launches = max(pc["launches"], 1)
+    avg_ms = pc["ms"] / launches
+    per_launch = alg_bytes / launches
+    achieved = per_launch / (avg_ms / 1e3) / 1e9 if avg_ms > 0 else 0.0
+    kernel_name = {"forward": "k_level_forward", "reverse": "k_level_reverse"}[cls]
+    src_hash = kernel_source_hash()
+    traffic = read_traffic(kernel_name, args.workload, src_hash)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": traffic, "kernel": kernel_name,
+                "alg_bytes_per_launch": round(per_launch), "avg_launch_ms": round(avg_ms, 5),
+                "launches": pc["launches"], "kernel_source_hash": src_hash}
+
+    cpu = None
+    if args.cpu_seconds > 0:
+        print("# timing the CPU oracle sample", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(g, np.asarray(sources, np.int32), args.cpu_seconds)
+
+    q = np.percentile(step_ms, [50, 99]) if step_ms else [0.0, 0.0]
+    kernels = {c: {"launches": prof[c]["launches"], "ms": round(prof[c]["ms"], 3)}
+               for c in ("forward", "compact", "reverse", "finish")}
+    rec = {
+        "metric": METRIC, "value": round(value, 3), "unit": "GTEPS", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n": g.n, "nnz": g.nnz, "sources": k,
+                   "mode": args.mode, "batch_width": args.batch_width,
+                   "graph": g.params},
+        "p50_ms": round(float(q[0]), 3), "p99_ms": round(float(q[1]), 3),
+        "roofline": roofline, "cpu_baseline": cpu, "kernels": kernels,
+    }
+    print(json.dumps(rec), flush=True)
+    G.close()
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

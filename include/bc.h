@@ -64,8 +64,8 @@ typedef enum {
 /* bc_create_graph flags */
 enum {
     BC_GRAPH_TRUST_SYMMETRIC = 1u << 0, /* skip the host-side symmetry check */
-    BC_GRAPH_INPUT_ON_DEVICE = 1u << 1  /* row_ptr / col_idx are device pointers; the
-                                           structural checks are then skipped */
+    BC_GRAPH_INPUT_ON_DEVICE = 1u << 1  /* row_ptr / col_idx are device pointers (they are
+                                           copied to the host for the same checks) */
 };
 
 /* Execution modes (bc_options.mode). */
@@ -154,6 +154,41 @@ bc_status bc_workspace_bytes(bc_graph_t g, int32_t k, const bc_options *opt, siz
 
 /* Free pooled workspaces that are idle.  Safe while other runs are in flight. */
 bc_status bc_trim_workspaces(bc_graph_t g);
+
+/*
+ * Measurement support, for benchmark and profiling tools.  While enabled on a
+ * graph, every run on it brackets each kernel launch with HIP events on the
+ * run's stream and counts the work the kernels did; bc_profile_read returns
+ * the totals accumulated since the last reset.  Classes:
+ *   BC_PROF_FORWARD  forward level kernel (sigma sums and next-level marks)
+ *   BC_PROF_COMPACT  compaction of the marks into the next level's queues
+ *   BC_PROF_REVERSE  reverse level kernel (dependency sums, BC update)
+ *   BC_PROF_FINISH   completion of vertices split into several chunks
+ * owners = vertices processed (for COMPACT: vertices queued), arcs = adjacency
+ * entries read, hits = parent arcs (FORWARD) or child arcs (REVERSE).
+ */
+enum {
+    BC_PROF_FORWARD = 0,
+    BC_PROF_COMPACT = 1,
+    BC_PROF_REVERSE = 2,
+    BC_PROF_FINISH = 3,
+    BC_PROF_CLASSES = 4
+};
+
+typedef struct bc_profile {
+    int64_t launches[BC_PROF_CLASSES];
+    double ms[BC_PROF_CLASSES];
+    int64_t owners[BC_PROF_CLASSES];
+    int64_t arcs[BC_PROF_CLASSES];
+    int64_t hits[BC_PROF_CLASSES];
+    int64_t runs;
+} bc_profile;
+
+/* Switch measurement on (on != 0) or off for runs on g. */
+bc_status bc_profile_enable(bc_graph_t g, int32_t on);
+
+/* Copy the accumulated totals to *out; with reset != 0, clear them. */
+bc_status bc_profile_read(bc_graph_t g, bc_profile *out, int32_t reset);
 
 /* Static description of a status code. */
 const char *bc_status_str(bc_status s);

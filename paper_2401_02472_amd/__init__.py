@@ -21,7 +21,8 @@ from ._capi import (BC_ERR_DEVICE, BC_ERR_INVALID_ARG, BC_ERR_INVALID_GRAPH,  # 
 __all__ = [
     "BCError", "bc_create_graph", "bc_destroy_graph", "bc_graph_info", "bc_run", "bc_run_async",
     "bc_single_source", "bc_run_detail", "bc_workspace_bytes", "bc_trim_workspaces",
-    "bc_status_str", "make_options", "Graph", "load_library",
+    "bc_profile_enable", "bc_profile_read", "bc_status_str", "make_options", "Graph",
+    "load_library",
 ]
 
 
@@ -169,6 +170,22 @@ def bc_trim_workspaces(g: int) -> None:
     _check(_capi.load().bc_trim_workspaces(ctypes.c_void_p(g)), "bc_trim_workspaces")
 
 
+def bc_profile_enable(g: int, on: bool = True) -> None:
+    _check(_capi.load().bc_profile_enable(ctypes.c_void_p(g), int(bool(on))), "bc_profile_enable")
+
+
+def bc_profile_read(g: int, reset: bool = False) -> dict:
+    """Accumulated per-kernel-class timing and work counters of profiled runs."""
+    p = _capi.bc_profile()
+    _check(_capi.load().bc_profile_read(ctypes.c_void_p(g), ctypes.byref(p), int(bool(reset))),
+           "bc_profile_read")
+    out = {"runs": int(p.runs)}
+    for i, name in enumerate(_capi.PROF_CLASS_NAMES):
+        out[name] = {"launches": int(p.launches[i]), "ms": float(p.ms[i]),
+                     "owners": int(p.owners[i]), "arcs": int(p.arcs[i]), "hits": int(p.hits[i])}
+    return out
+
+
 class Graph:
     """Owning wrapper of a bc_graph_t handle."""
 
@@ -207,3 +224,9 @@ class Graph:
 
     def workspace_bytes(self, k: int, options=None) -> int:
         return bc_workspace_bytes(self.handle, k, options)
+
+    def profile_enable(self, on: bool = True) -> None:
+        bc_profile_enable(self.handle, on)
+
+    def profile_read(self, reset: bool = False) -> dict:
+        return bc_profile_read(self.handle, reset)

@@ -32,12 +32,28 @@ BC_MODE_BATCHED = 2
 
 EXPORTED = ("bc_create_graph", "bc_destroy_graph", "bc_graph_info", "bc_run", "bc_run_async",
             "bc_single_source", "bc_run_detail", "bc_workspace_bytes", "bc_trim_workspaces",
-            "bc_status_str")
+            "bc_profile_enable", "bc_profile_read", "bc_status_str")
+
+BC_PROF_FORWARD = 0
+BC_PROF_COMPACT = 1
+BC_PROF_REVERSE = 2
+BC_PROF_FINISH = 3
+BC_PROF_CLASSES = 4
+PROF_CLASS_NAMES = ("forward", "compact", "reverse", "finish")
 
 
 class bc_options(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("batch_width", ctypes.c_int32),
                 ("level_chunk", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
+
+
+class bc_profile(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int64 * BC_PROF_CLASSES),
+                ("ms", ctypes.c_double * BC_PROF_CLASSES),
+                ("owners", ctypes.c_int64 * BC_PROF_CLASSES),
+                ("arcs", ctypes.c_int64 * BC_PROF_CLASSES),
+                ("hits", ctypes.c_int64 * BC_PROF_CLASSES),
+                ("runs", ctypes.c_int64)]
 
 
 _lib = None
@@ -69,6 +85,8 @@ def load():
             "bc_run_detail": [vp, i32p, ctypes.c_int32, optp, f64p, i32p, f64p],
             "bc_workspace_bytes": [vp, ctypes.c_int32, optp, szp],
             "bc_trim_workspaces": [vp],
+            "bc_profile_enable": [vp, ctypes.c_int32],
+            "bc_profile_read": [vp, ctypes.POINTER(bc_profile), ctypes.c_int32],
         }
         for name, args in sig.items():
             fn = getattr(lib, name)

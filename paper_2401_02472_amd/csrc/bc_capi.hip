@@ -21,6 +21,7 @@ namespace {
 
 constexpr size_t kAlign = 256;
 constexpr int kLevelGrid = 2048;  // workgroups per level kernel (8192 wavefronts)
+constexpr int kCtrlInts = 4;      // see PlainDev::ctrl
 
 size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
@@ -36,11 +37,50 @@ bc_status from_hip(hipError_t e) {
         if (_e != hipSuccess) return from_hip(_e); \
     } while (0)
 
+// HIP event pairs bracketing kernel launches of one run (measurement only).
+struct LaunchTimer {
+    std::vector<hipEvent_t> ev;  // 2 per launch
+    std::vector<int> cls;
+    size_t used = 0;
+    bool on = false;
+    hipError_t begin(int c, hipStream_t s) {
+        if (!on) return hipSuccess;
+        if (2 * used + 2 > ev.size()) {
+            for (int i = 0; i < 2; ++i) {
+                hipEvent_t e;
+                // timing only: no system-scope fence (no cache write-back and
+                // invalidation around the timed kernels)
+                hipError_t r = hipEventCreateWithFlags(&e, hipEventDisableSystemFence);
+                if (r != hipSuccess) return r;
+                ev.push_back(e);
+            }
+            cls.push_back(0);
+        }
+        cls[used] = c;
+        return hipEventRecord(ev[2 * used], s);
+    }
+    hipError_t end(hipStream_t s) {
+        if (!on) return hipSuccess;
+        hipError_t r = hipEventRecord(ev[2 * used + 1], s);
+        ++used;
+        return r;
+    }
+    void destroy() {
+        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+        ev.clear();
+        cls.clear();
+    }
+};
+
 struct PlainWS {
+    LaunchTimer timer;
+    unsigned long long *d_stats = nullptr;  // 12 counters (see PlainDev::stats)
     void *block = nullptr;
     size_t bytes = 0;
     PlainDev dev{};
     int32_t *h_ctrl = nullptr;  // pinned mirror of dev.ctrl
+    int32_t *d_trunc = nullptr; // per-source truncation flags of a run
+    size_t trunc_cap = 0;
     hipEvent_t done = nullptr;  // recorded after the last work that used this workspace
     bool busy = false;
 };
@@ -70,12 +110,15 @@ struct bc_graph_s {
     int32_t *d_col_idx = nullptr;
     int32_t *d_perm = nullptr;      // caller id -> internal id
     std::vector<int32_t> h_perm;    // same, on the host (source mapping)
-    int32_t b2_end = 0, b1_end = 0; // bucket id ranges
-    uint64_t total_chunks2 = 0;  // chunk slots needed by bucket-2 vertices of one source
+    int32_t b3_end = 0, b2_end = 0, b1_end = 0;  // bucket id ranges
+    uint64_t total_chunks3 = 0;  // chunk slots needed by bucket-3 vertices of one source
     size_t device_bytes = 0;
     std::mutex mu;
     std::vector<PlainWS *> plain_pool;
-    std::atomic<int32_t> last_depth{8};
+    std::atomic<int32_t> depth_hint{16};  // levels launched per source without polling
+    std::atomic<int32_t> profiling{0};
+    std::mutex prof_mu;
+    bc_profile prof{};
 };
 
 namespace {
@@ -86,11 +129,12 @@ size_t plain_ws_bytes(const bc_graph_s *g) {
     b += align_up(((n + 15) / 16) * sizeof(uint32_t));        // lev3
     b += align_up(((n + 15) / 16) * 16);                      // nextmap
     b += 2 * align_up(n * sizeof(double));                    // sigma, coef
-    b += 4 * align_up(n * sizeof(int32_t));                   // q0 q1 q2 q2c
-    b += align_up(std::max<uint64_t>(g->total_chunks2, 1) * sizeof(double));  // partial
+    b += 5 * align_up(n * sizeof(int32_t));                   // 4 queues + chunk slots
+    b += align_up(std::max<uint64_t>(g->total_chunks3, 1) * sizeof(double));  // partial
     b += align_up((n + 2) * sizeof(LevelRec));                // lvl
-    b += align_up(2 * sizeof(int32_t));                       // ctrl
+    b += align_up(kCtrlInts * sizeof(int32_t));               // ctrl
     b += align_up(n * sizeof(double));                        // bc (internal order)
+    b += align_up(12 * sizeof(unsigned long long));           // work counters
     return b;
 }
 
@@ -103,7 +147,7 @@ bc_status plain_ws_create(bc_graph_s *g, PlainWS **out) {
         delete ws;
         return from_hip(e);
     }
-    e = hipHostMalloc((void **)&ws->h_ctrl, 2 * sizeof(int32_t), hipHostMallocDefault);
+    e = hipHostMalloc((void **)&ws->h_ctrl, kCtrlInts * sizeof(int32_t), hipHostMallocDefault);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&ws->done, hipEventDisableTiming);
     if (e != hipSuccess) {
         (void)hipFree(ws->block);
@@ -126,14 +170,15 @@ bc_status plain_ws_create(bc_graph_s *g, PlainWS **out) {
     d.nextmap = (uint8_t *)take(((n + 15) / 16) * 16);
     d.sigma = (double *)take(n * sizeof(double));
     d.coef = (double *)take(n * sizeof(double));
-    d.q0 = (int32_t *)take(n * sizeof(int32_t));
-    d.q1 = (int32_t *)take(n * sizeof(int32_t));
-    d.q2 = (int32_t *)take(n * sizeof(int32_t));
-    d.q2c = (int32_t *)take(n * sizeof(int32_t));
-    d.partial = (double *)take(std::max<uint64_t>(g->total_chunks2, 1) * sizeof(double));
+    for (int b = 0; b < kBuckets; ++b) d.q[b] = (int32_t *)take(n * sizeof(int32_t));
+    d.q3c = (int32_t *)take(n * sizeof(int32_t));
+    d.partial = (double *)take(std::max<uint64_t>(g->total_chunks3, 1) * sizeof(double));
     d.lvl = (LevelRec *)take((n + 2) * sizeof(LevelRec));
-    d.ctrl = (int32_t *)take(2 * sizeof(int32_t));
+    d.ctrl = (int32_t *)take(kCtrlInts * sizeof(int32_t));
     d.bc = (double *)take(n * sizeof(double));
+    ws->d_stats = (unsigned long long *)take(12 * sizeof(unsigned long long));
+    d.stats = nullptr;
+    d.b3_end = g->b3_end;
     d.b2_end = g->b2_end;
     d.b1_end = g->b1_end;
     *out = ws;
@@ -146,6 +191,8 @@ void plain_ws_destroy(PlainWS *ws) {
         (void)hipEventSynchronize(ws->done);
         (void)hipEventDestroy(ws->done);
     }
+    ws->timer.destroy();
+    if (ws->d_trunc) (void)hipFree(ws->d_trunc);
     if (ws->block) (void)hipFree(ws->block);
     if (ws->h_ctrl) (void)hipHostFree(ws->h_ctrl);
     delete ws;
@@ -187,19 +234,27 @@ struct SourceState {
     double *delta = nullptr;   // device, optional export
 };
 
-// Forward pass of one source: levels are launched in chunks and the host polls
-// the deepest discovered level after each chunk.  Returns the deepest level.
-bc_status plain_forward(bc_graph_s *g, PlainWS *ws, int32_t s, int32_t chunk0,
-                        hipStream_t stream, int32_t *deepest_out) {
+// Forward pass of one source with the host polling the deepest discovered
+// level after each chunk of launched levels (used for state exports and for
+// sources that outgrew the speculative level count).
+bc_status plain_forward_polled(bc_graph_s *g, PlainWS *ws, int32_t s, int32_t chunk0,
+                               hipStream_t stream, int32_t *deepest_out) {
     const PlainDev &d = ws->dev;
     BC_TRY_HIP(plain_init_source(d, s, stream));
     int32_t L0 = 0;
     int32_t K = std::max(1, chunk0);
     for (;;) {
         const int32_t Lend = (int32_t)std::min<int64_t>((int64_t)L0 + K, g->n);
-        for (int32_t L = L0; L < Lend; ++L) BC_TRY_HIP(plain_forward_level(d, L, kLevelGrid, stream));
-        BC_TRY_HIP(hipMemcpyAsync(ws->h_ctrl, d.ctrl, 2 * sizeof(int32_t), hipMemcpyDeviceToHost,
-                                  stream));
+        for (int32_t L = L0; L < Lend; ++L) {
+            BC_TRY_HIP(ws->timer.begin(BC_PROF_FORWARD, stream));
+            BC_TRY_HIP(plain_forward_level(d, L, kLevelGrid, stream));
+            BC_TRY_HIP(ws->timer.end(stream));
+            BC_TRY_HIP(ws->timer.begin(BC_PROF_COMPACT, stream));
+            BC_TRY_HIP(plain_compact(d, L, -1, nullptr, stream));
+            BC_TRY_HIP(ws->timer.end(stream));
+        }
+        BC_TRY_HIP(hipMemcpyAsync(ws->h_ctrl, d.ctrl, kCtrlInts * sizeof(int32_t),
+                                  hipMemcpyDeviceToHost, stream));
         BC_TRY_HIP(hipStreamSynchronize(stream));
         const int32_t deepest = ws->h_ctrl[0];
         if (deepest < Lend || Lend >= g->n) {
@@ -209,6 +264,46 @@ bc_status plain_forward(bc_graph_s *g, PlainWS *ws, int32_t s, int32_t chunk0,
         L0 = Lend;
         K = std::min(K * 2, 1024);
     }
+}
+
+// Reverse pass of one source, levels hi..1 (hi = deepest level when known,
+// else the deepest launched level with `known` false).
+hipError_t plain_reverse(PlainWS *ws, int32_t hi, bool known, double *dout, hipStream_t stream) {
+    const PlainDev &d = ws->dev;
+    for (int32_t L = hi; L >= 1; --L) {
+        const int deepest = known ? (L == hi ? 1 : 0) : -1;
+        hipError_t e = ws->timer.begin(BC_PROF_REVERSE, stream);
+        if (e == hipSuccess) e = plain_backward_level(d, L, deepest, kLevelGrid, dout, stream);
+        if (e == hipSuccess) e = ws->timer.end(stream);
+        if (e == hipSuccess && !(known && L == hi)) {
+            e = ws->timer.begin(BC_PROF_FINISH, stream);
+            if (e == hipSuccess) e = plain_finish_reverse(d, L, dout, stream);
+            if (e == hipSuccess) e = ws->timer.end(stream);
+        }
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// One source without waiting for the device: K forward steps and K-1 reverse
+// steps are enqueued; steps past the deepest level find empty queues and exit.
+// If the source has more than K levels, the compaction of level K-1 marks it
+// truncated, its reverse steps do nothing, and *trunc_flag is set so that the
+// host runs it again.
+hipError_t plain_source_speculative(PlainWS *ws, int32_t s, int32_t K, int32_t *trunc_flag,
+                                    hipStream_t stream) {
+    const PlainDev &d = ws->dev;
+    hipError_t e = plain_init_source(d, s, stream);
+    for (int32_t L = 0; e == hipSuccess && L < K; ++L) {
+        e = ws->timer.begin(BC_PROF_FORWARD, stream);
+        if (e == hipSuccess) e = plain_forward_level(d, L, kLevelGrid, stream);
+        if (e == hipSuccess) e = ws->timer.end(stream);
+        if (e == hipSuccess) e = ws->timer.begin(BC_PROF_COMPACT, stream);
+        if (e == hipSuccess) e = plain_compact(d, L, K - 1, trunc_flag, stream);
+        if (e == hipSuccess) e = ws->timer.end(stream);
+    }
+    if (e == hipSuccess) e = plain_reverse(ws, K - 1, false, nullptr, stream);
+    return e;
 }
 
 // Export buffers of one source in internal order (device temporaries).
@@ -224,33 +319,66 @@ bc_status plain_run(bc_graph_s *g, const int32_t *sources, int32_t k, double *bc
     PlainWS *ws = nullptr;
     bc_status st = plain_acquire(g, stream, &ws);
     if (st != BC_OK) return st;
+    const bool prof = g->profiling.load() != 0;
+    ws->dev.stats = prof ? ws->d_stats : nullptr;
+    ws->timer.on = prof;
+    ws->timer.used = 0;
     const PlainDev &d = ws->dev;
     bc_status result = BC_OK;
     auto fail = [&](bc_status s2) {
         plain_release(g, ws, stream);
         return s2;
     };
-    hipError_t e = hipMemsetAsync(d.bc, 0, (size_t)g->n * sizeof(double), stream);
-    if (e != hipSuccess) return fail(from_hip(e));
-    e = plain_reset_run(d, stream);
-    if (e != hipSuccess) return fail(from_hip(e));
     const int32_t user_chunk = opt ? opt->level_chunk : 0;
-    for (int32_t i = 0; i < k; ++i) {
+    const bool polled = exp != nullptr || user_chunk > 0;
+    if (!polled && (size_t)k > ws->trunc_cap) {
+        if (ws->d_trunc) (void)hipFree(ws->d_trunc);
+        ws->d_trunc = nullptr;
+        ws->trunc_cap = 0;
+        hipError_t ea = hipMalloc(&ws->d_trunc, (size_t)k * sizeof(int32_t));
+        if (ea != hipSuccess) return fail(from_hip(ea));
+        ws->trunc_cap = (size_t)k;
+    }
+    hipError_t e = hipMemsetAsync(d.bc, 0, (size_t)g->n * sizeof(double), stream);
+    if (e == hipSuccess) e = plain_reset_run(d, stream);
+    if (e == hipSuccess && prof)
+        e = hipMemsetAsync(ws->d_stats, 0, 12 * sizeof(unsigned long long), stream);
+    if (e == hipSuccess && !polled && k > 0)
+        e = hipMemsetAsync(ws->d_trunc, 0, (size_t)k * sizeof(int32_t), stream);
+    if (e != hipSuccess) return fail(from_hip(e));
+
+    std::vector<int32_t> redo;  // sources run in polled mode
+    if (polled) {
+        for (int32_t i = 0; i < k; ++i) redo.push_back(i);
+    } else {
+        const int32_t K = (int32_t)std::min<int64_t>(std::max(2, g->depth_hint.load()), g->n);
+        for (int32_t i = 0; i < k && e == hipSuccess; ++i)
+            e = plain_source_speculative(ws, g->h_perm[(size_t)sources[i]], K, ws->d_trunc + i,
+                                         stream);
+        if (e != hipSuccess) return fail(from_hip(e));
+        if (k > 0) {
+            std::vector<int32_t> trunc((size_t)k);
+            e = hipMemcpyAsync(trunc.data(), ws->d_trunc, (size_t)k * sizeof(int32_t),
+                               hipMemcpyDeviceToHost, stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(stream);
+            if (e != hipSuccess) return fail(from_hip(e));
+            for (int32_t i = 0; i < k; ++i)
+                if (trunc[(size_t)i]) redo.push_back(i);
+        }
+    }
+    for (int32_t i : redo) {
         const int32_t s_int = g->h_perm[(size_t)sources[i]];
-        const int32_t chunk = user_chunk > 0 ? user_chunk : g->last_depth.load() + 2;
+        const int32_t chunk = user_chunk > 0 ? user_chunk : std::max(2, g->depth_hint.load());
         int32_t deepest = 0;
-        st = plain_forward(g, ws, s_int, chunk, stream, &deepest);
+        st = plain_forward_polled(g, ws, s_int, chunk, stream, &deepest);
         if (st != BC_OK) return fail(st);
-        if (user_chunk <= 0) g->last_depth.store(deepest);
+        if (deepest + 2 > g->depth_hint.load()) g->depth_hint.store(deepest + 2);
         if (exp) {
             e = plain_export_fill(g->n, tmp->dist, tmp->sigma, tmp->delta, stream);
             if (e != hipSuccess) return fail(from_hip(e));
         }
-        for (int32_t L = deepest; L >= 1; --L) {
-            e = plain_backward_level(d, L, L == deepest, kLevelGrid,
-                                     exp ? tmp->delta : nullptr, stream);
-            if (e != hipSuccess) return fail(from_hip(e));
-        }
+        e = plain_reverse(ws, deepest, true, exp ? tmp->delta : nullptr, stream);
+        if (e != hipSuccess) return fail(from_hip(e));
         if (exp) {
             e = plain_export_levels(d, deepest, tmp->dist, tmp->sigma, stream);
             if (e == hipSuccess && exp[i].dist) e = gather_i32(g->n, g->d_perm, tmp->dist, exp[i].dist, stream);
@@ -261,10 +389,44 @@ bc_status plain_run(bc_graph_s *g, const int32_t *sources, int32_t k, double *bc
     }
     e = gather_f64(g->n, g->d_perm, d.bc, bc_out, stream);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(ws->h_ctrl, d.ctrl, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, stream);
+        e = hipMemcpyAsync(ws->h_ctrl, d.ctrl, kCtrlInts * sizeof(int32_t), hipMemcpyDeviceToHost,
+                           stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
     if (e != hipSuccess) return fail(from_hip(e));
     if (ws->h_ctrl[1] != 0) result = BC_ERR_RANGE;
+    {
+        // next run: launch two levels more than the deepest seen
+        const int32_t seen = ws->h_ctrl[3] + 2;
+        if (!polled && seen != g->depth_hint.load()) g->depth_hint.store(std::max(seen, 2));
+    }
+    if (prof) {
+        bc_profile add{};
+        for (size_t i = 0; i < ws->timer.used; ++i) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, ws->timer.ev[2 * i], ws->timer.ev[2 * i + 1]) == hipSuccess)
+                add.ms[ws->timer.cls[i]] += ms;
+            add.launches[ws->timer.cls[i]] += 1;
+        }
+        unsigned long long cnt[12];
+        if (hipMemcpy(cnt, ws->d_stats, sizeof(cnt), hipMemcpyDeviceToHost) == hipSuccess) {
+            add.owners[BC_PROF_FORWARD] = (int64_t)cnt[0];
+            add.arcs[BC_PROF_FORWARD] = (int64_t)cnt[1];
+            add.hits[BC_PROF_FORWARD] = (int64_t)cnt[2];
+            add.owners[BC_PROF_COMPACT] = (int64_t)cnt[3];
+            add.owners[BC_PROF_REVERSE] = (int64_t)cnt[6];
+            add.arcs[BC_PROF_REVERSE] = (int64_t)cnt[7];
+            add.hits[BC_PROF_REVERSE] = (int64_t)cnt[8];
+        }
+        std::lock_guard<std::mutex> lk(g->prof_mu);
+        for (int c = 0; c < BC_PROF_CLASSES; ++c) {
+            g->prof.launches[c] += add.launches[c];
+            g->prof.ms[c] += add.ms[c];
+            g->prof.owners[c] += add.owners[c];
+            g->prof.arcs[c] += add.arcs[c];
+            g->prof.hits[c] += add.hits[c];
+        }
+        g->prof.runs += 1;
+    }
     plain_release(g, ws, stream);
     return result;
 }
@@ -414,13 +576,14 @@ bc_status bc_create_graph(int32_t n, const int32_t *row_ptr, const int32_t *col_
         const int32_t dgr = rp_host[o + 1] - rp_host[o];
         new_rp[(size_t)u + 1] = new_rp[(size_t)u] + dgr;
         const int b = degree_bucket(dgr);
-        if (b == 2) {
-            g->b2_end = u + 1;
+        if (b == 3) {
+            g->b3_end = u + 1;
             chunks += chunks_of(dgr);
         }
+        if (b >= 2) g->b2_end = u + 1;
         if (b >= 1) g->b1_end = u + 1;
     }
-    g->total_chunks2 = chunks;
+    g->total_chunks3 = chunks;
 
     const size_t rp_bytes = ((size_t)n + 1) * sizeof(int32_t);
     const size_t ci_bytes = std::max<size_t>((size_t)nnz, 1) * sizeof(int32_t);
@@ -604,6 +767,20 @@ bc_status bc_workspace_bytes(bc_graph_t g, int32_t k, const bc_options *opt, siz
     bc_status st = check_options(opt);
     if (st != BC_OK) return st;
     *bytes = plain_ws_bytes(g);
+    return BC_OK;
+}
+
+bc_status bc_profile_enable(bc_graph_t g, int32_t on) {
+    if (!g) return BC_ERR_INVALID_ARG;
+    g->profiling.store(on ? 1 : 0);
+    return BC_OK;
+}
+
+bc_status bc_profile_read(bc_graph_t g, bc_profile *out, int32_t reset) {
+    if (!g || !out) return BC_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(g->prof_mu);
+    *out = g->prof;
+    if (reset) g->prof = bc_profile{};
     return BC_OK;
 }
 

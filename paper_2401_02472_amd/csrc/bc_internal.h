@@ -14,52 +14,66 @@ constexpr int kBlock = 256;           // threads per workgroup for the level ker
 constexpr int kWavesPerBlock = kBlock / kWave;
 
 // Degree buckets of the frontier queues.  A vertex of degree d is processed by
-//   bucket 0 (d <= kB0MaxDeg):  one lane,
-//   bucket 1 (d <= kB1MaxDeg):  a group of kB1Lanes lanes,
-//   bucket 2 (larger):          one wavefront per chunk of kChunkArcs arcs;
-//                               chunks of one vertex are combined in a fixed order.
+//   bucket 0 (d <= kB0MaxDeg):   one lane,
+//   bucket 1 (d <= kB1MaxDeg):   a group of kB1Lanes lanes,
+//   bucket 2 (d <= kChunkArcs):  one wavefront,
+//   bucket 3 (larger):           one wavefront per chunk of kChunkArcs arcs;
+//                                the chunks' partial sums are combined in chunk
+//                                order by the next kernel on the stream.
 constexpr int kB0MaxDeg = 8;
 constexpr int kB1MaxDeg = 64;
 constexpr int kB1Lanes = 8;
 constexpr int kChunkArcs = 2048;
+constexpr int kBuckets = 4;
 
 // The library relabels vertices by degree, descending, when a graph is
-// created, so the buckets are id ranges: [0, b2_end) bucket 2,
-// [b2_end, b1_end) bucket 1, the rest bucket 0.
+// created, so the buckets are id ranges: [0, b3_end) bucket 3,
+// [b3_end, b2_end) bucket 2, [b2_end, b1_end) bucket 1, the rest bucket 0.
 __host__ __device__ inline int degree_bucket(int32_t d) {
-    return d <= kB0MaxDeg ? 0 : (d <= kB1MaxDeg ? 1 : 2);
+    return d <= kB0MaxDeg ? 0 : (d <= kB1MaxDeg ? 1 : (d <= kChunkArcs ? 2 : 3));
 }
 __host__ __device__ inline uint32_t chunks_of(int32_t d) {
     return (uint32_t)((d + kChunkArcs - 1) / kChunkArcs);
 }
 
-// Per-level bookkeeping of the BFS queues.  Level L of bucket b occupies
-// queue_b[start_b .. start_b + cnt_b).  Counts are appended to atomically while
-// the level is being discovered (during the kernel of level L-1); starts are
-// written by the kernel of level L-1 as well, before anything reads them.
+// Per-level bookkeeping of the BFS queues.  Level L of bucket b < 3 occupies
+// queue_b[start[b] .. start[b] + cnt[b]); bucket 3 occupies vertex slots
+// vstart3 .. and chunk slots cstart3 ...  Counts are appended to atomically
+// while the level is being discovered (by the compaction after level L-1),
+// which also writes the starts before anything reads them.
 struct LevelRec {
-    uint32_t start0, start1;
-    uint32_t vstart2, cstart2;  // bucket 2: first vertex slot, first chunk slot
-    uint32_t cnt0, cnt1;
-    unsigned long long cnt2;    // (vertex count << 32) | chunk count
+    uint32_t start[3];
+    uint32_t vstart3, cstart3;
+    uint32_t cnt[3];
+    unsigned long long cnt3;    // (vertex count << 32) | chunk count
 };
-static_assert(sizeof(LevelRec) == 32, "LevelRec layout");
+static_assert(sizeof(LevelRec) == 40, "LevelRec layout");
+
+__host__ __device__ inline bool level_empty(const LevelRec &r) {
+    return (r.cnt[0] | r.cnt[1] | r.cnt[2] | (uint32_t)(r.cnt3 >> 32)) == 0u;
+}
 
 // Device view of one plain (one source at a time) workspace.
 struct PlainDev {
     int32_t n;
-    int32_t b2_end, b1_end;  // bucket id ranges (see degree_bucket)
+    int32_t b3_end, b2_end, b1_end;  // bucket id ranges (see degree_bucket)
     const int32_t *row_ptr;
     const int32_t *col_idx;
     uint32_t *lev3;       // 2 bits per vertex (16 per word): level mod 3, or 3 = not reached
     uint8_t *nextmap;     // 1 byte per vertex (padded to 16): marked for the next level
     double *sigma;        // shortest-path counts
     double *coef;         // (1 + delta[v]) / sigma[v], written by the reverse sweep
-    int32_t *q0, *q1, *q2;  // per-bucket queues (all levels back to back)
-    int32_t *q2c;         // bucket 2: first chunk slot of the vertex
-    double *partial;      // bucket 2: per-chunk partial sums
+    int32_t *q[kBuckets]; // per-bucket queues (all levels back to back)
+    int32_t *q3c;         // bucket 3: first chunk slot of the vertex
+    double *partial;      // bucket 3: per-chunk partial sums
     LevelRec *lvl;        // [n + 2]
-    int32_t *ctrl;        // [0] deepest non-empty level, [1] range flag
+    int32_t *ctrl;        // [0] deepest non-empty level of the current source,
+                          // [1] range flag, [2] current source truncated (more
+                          // levels than launched), [3] deepest level of the run
+    unsigned long long *stats;  // NULL, or work counters when measuring:
+                                // [0..2] forward owners/arcs/parent arcs,
+                                // [3] vertices queued by the compaction,
+                                // [6..8] reverse owners/arcs/child arcs
     double *bc;           // [n] accumulated BC
 };
 
@@ -79,11 +93,20 @@ hipError_t gather_i32(int32_t n, const int32_t *perm, const int32_t *src, int32_
 hipError_t plain_reset_run(const PlainDev &d, hipStream_t stream);
 hipError_t plain_init_source(const PlainDev &d, int32_t s, hipStream_t stream);
 // Forward step of level L: sigma of the level-L vertices and the marks of
-// level L+1, then the compaction of the marks into the level L+1 queues.
+// level L+1.  Then plain_compact turns the marks into the level L+1 queues
+// (and completes the sigma of multi-chunk level-L vertices).
 hipError_t plain_forward_level(const PlainDev &d, int32_t level, int grid, hipStream_t stream);
-// Reverse step of level L (>= 1); `deepest` marks the last level (no children).
-hipError_t plain_backward_level(const PlainDev &d, int32_t level, bool deepest, int grid,
+// `last` is the deepest level launched for this source: finding vertices
+// below it marks the source truncated (ctrl[2], and *trunc_flag if given).
+hipError_t plain_compact(const PlainDev &d, int32_t level, int32_t last, int32_t *trunc_flag,
+                         hipStream_t stream);
+// Reverse step of level L (>= 1); `deepest` = 1 marks the last level (no
+// children), 0 not, -1 lets the kernel decide.  Then plain_finish_reverse
+// completes the multi-chunk vertices.  Both do nothing for a truncated source.
+hipError_t plain_backward_level(const PlainDev &d, int32_t level, int deepest, int grid,
                                 double *delta_out, hipStream_t stream);
+hipError_t plain_finish_reverse(const PlainDev &d, int32_t level, double *delta_out,
+                                hipStream_t stream);
 // Single-source export: fill dist = -1, sigma = 0, delta = 0 (any may be NULL),
 // then write dist / sigma of every vertex on levels 0..deepest.
 hipError_t plain_export_fill(int32_t n, int32_t *dist, double *sigma, double *delta,

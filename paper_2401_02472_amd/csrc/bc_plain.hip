@@ -26,8 +26,8 @@
 //   * The reverse pass sums c[w] = (1 + delta[w]) / sigma[w] over children w
 //     and sets delta[v] = sigma[v] * sum, which equals the listing's
 //     sum of (sigma[v] / sigma[w]) * (1 + delta[w]) up to rounding.
-//   * Degree buckets pick one lane, an 8-lane group, or one wavefront per
-//     2048-arc chunk per vertex.  Each lane issues its arcs' loads in batches
+//   * Degree buckets pick one lane, an 8-lane group, one wavefront, or one
+//     wavefront per 2048-arc chunk per vertex.  Each lane issues its arcs' loads in batches
 //     of 8 independent loads (neighbour ids, then codes, then sigma or c) so
 //     that memory latency overlaps.  Sums run in a fixed order (chunks of one
 //     vertex are combined in chunk order by the next kernel on the stream, so
@@ -85,9 +85,14 @@ __device__ __forceinline__ LevelCtx make_ctx(const PlainDev &d, int32_t L) {
 // Arcs first + stride*j, j < count (count <= kBatch), of one owner vertex.
 // Forward: acc += sigma of parents, unreached neighbours are marked.
 // Reverse: acc += c of children.  Terms are added in j order.
+// Per-lane work counters, reported only when measurement is switched on.
+struct Work {
+    uint32_t owners = 0, arcs = 0, hits = 0;
+};
+
 template <bool FWD>
 __device__ __forceinline__ void arc_batch(const LevelCtx &c, int32_t first, int32_t stride,
-                                          int32_t count, double &acc) {
+                                          int32_t count, double &acc, Work &wk) {
     int32_t v[kBatch];
 #pragma unroll
     for (int j = 0; j < kBatch; ++j)
@@ -100,6 +105,9 @@ __device__ __forceinline__ void arc_batch(const LevelCtx &c, int32_t first, int3
     double x[kBatch];
 #pragma unroll
     for (int j = 0; j < kBatch; ++j) x[j] = (code[j] == want) ? val[v[j]] : 0.0;
+    wk.arcs += (uint32_t)(count > 0 ? count : 0);
+#pragma unroll
+    for (int j = 0; j < kBatch; ++j) wk.hits += (code[j] == want) ? 1u : 0u;
 #pragma unroll
     for (int j = 0; j < kBatch; ++j) acc += x[j];
     if (FWD) {
@@ -126,99 +134,122 @@ __device__ __forceinline__ void set_delta(const LevelCtx &c, int32_t v, double a
 
 // ---- bucket 0: one lane per vertex (degree <= 8) --------------------------
 template <bool FWD>
-__device__ void level_b0(const LevelCtx &c, uint32_t item, bool leaf, double *delta_out) {
+__device__ void level_b0(const LevelCtx &c, uint32_t item, bool leaf, double *delta_out,
+                         Work &wk) {
     const uint32_t idx = item * kWave + (uint32_t)lane_id();
-    if (idx >= c.cur.cnt0) return;
-    const int32_t w = c.d.q0[c.cur.start0 + idx];
+    if (idx >= c.cur.cnt[0]) return;
+    const int32_t w = c.d.q[0][c.cur.start[0] + idx];
     double acc = 0.0;
     if (!leaf) {
         const int32_t rs = c.d.row_ptr[w], re = c.d.row_ptr[w + 1];
-        arc_batch<FWD>(c, rs, 1, re - rs, acc);
+        arc_batch<FWD>(c, rs, 1, re - rs, acc, wk);
     }
+    ++wk.owners;
     if (FWD) set_sigma(c, w, acc);
     else set_delta(c, w, acc, delta_out);
 }
 
 // ---- bucket 1: kB1Lanes lanes per vertex (degree <= 64) --------------------
 template <bool FWD>
-__device__ void level_b1(const LevelCtx &c, uint32_t item, bool leaf, double *delta_out) {
+__device__ void level_b1(const LevelCtx &c, uint32_t item, bool leaf, double *delta_out,
+                         Work &wk) {
     const int lane = lane_id();
     const int sub = lane & (kB1Lanes - 1);
     const uint32_t idx = item * (kWave / kB1Lanes) + (uint32_t)(lane / kB1Lanes);
-    const bool active = idx < c.cur.cnt1;
+    const bool active = idx < c.cur.cnt[1];
     int32_t w = 0;
     double acc = 0.0;
     if (active) {
-        w = c.d.q1[c.cur.start1 + idx];
+        w = c.d.q[1][c.cur.start[1] + idx];
         if (!leaf) {
             const int32_t rs = c.d.row_ptr[w], re = c.d.row_ptr[w + 1];
             const int32_t cnt = (re - rs - sub + kB1Lanes - 1) / kB1Lanes;
-            arc_batch<FWD>(c, rs + sub, kB1Lanes, cnt, acc);
+            arc_batch<FWD>(c, rs + sub, kB1Lanes, cnt, acc, wk);
         }
     }
 #pragma unroll
     for (int off = kB1Lanes / 2; off >= 1; off >>= 1) acc += __shfl_xor(acc, off);
     if (active && sub == 0) {
+        ++wk.owners;
         if (FWD) set_sigma(c, w, acc);
         else set_delta(c, w, acc, delta_out);
     }
 }
 
-// ---- bucket 2: one wavefront per chunk of kChunkArcs arcs ----------------
+// Arcs [cb, ce) of one vertex by one wavefront; returns the wave-wide sum.
 template <bool FWD>
-__device__ void level_b2(const LevelCtx &c, uint32_t item, bool leaf, double *delta_out) {
+__device__ __forceinline__ double wave_arcs(const LevelCtx &c, int32_t cb, int32_t ce,
+                                            Work &wk) {
     const int lane = lane_id();
-    const uint32_t nv = (uint32_t)(c.cur.cnt2 >> 32);
-    const int32_t slot = (int32_t)(c.cur.cstart2 + item);
+    double acc = 0.0;
+    const int32_t mine = (ce - cb - lane + kWave - 1) / kWave;  // arcs of this lane
+    for (int32_t t = 0; t < mine; t += kBatch)
+        arc_batch<FWD>(c, cb + lane + t * kWave, kWave, min(kBatch, mine - t), acc, wk);
+    return wave_sum(acc);
+}
+
+// ---- bucket 2: one wavefront per vertex (degree <= kChunkArcs) ------------
+template <bool FWD>
+__device__ void level_b2(const LevelCtx &c, uint32_t item, bool leaf, double *delta_out,
+                         Work &wk) {
+    const int32_t w = c.d.q[2][c.cur.start[2] + item];
+    double acc = 0.0;
+    if (!leaf) acc = wave_arcs<FWD>(c, c.d.row_ptr[w], c.d.row_ptr[w + 1], wk);
+    if (lane_id() == 0) {
+        ++wk.owners;
+        if (FWD) set_sigma(c, w, acc);
+        else set_delta(c, w, acc, delta_out);
+    }
+}
+
+// ---- bucket 3: one wavefront per chunk of kChunkArcs arcs ----------------
+template <bool FWD>
+__device__ void level_b3(const LevelCtx &c, uint32_t item, bool leaf, double *delta_out,
+                         Work &wk) {
+    const int lane = lane_id();
+    const uint32_t nv = (uint32_t)(c.cur.cnt3 >> 32);
+    const int32_t slot = (int32_t)(c.cur.cstart3 + item);
     // last vertex of the level whose first chunk slot is <= slot
     uint32_t lo = 0, hi = nv - 1;
     while (lo < hi) {
         const uint32_t mid = (lo + hi + 1) >> 1;
-        if (c.d.q2c[c.cur.vstart2 + mid] <= slot) lo = mid;
+        if (c.d.q3c[c.cur.vstart3 + mid] <= slot) lo = mid;
         else hi = mid - 1;
     }
-    const uint32_t qi = c.cur.vstart2 + lo;
-    const int32_t w = c.d.q2[qi];
-    const int32_t first = c.d.q2c[qi];
+    const uint32_t qi = c.cur.vstart3 + lo;
+    const int32_t w = c.d.q[3][qi];
+    const int32_t first = c.d.q3c[qi];
     const int32_t j = slot - first;
     const int32_t rs = c.d.row_ptr[w], re = c.d.row_ptr[w + 1];
-    const uint32_t nch = chunks_of(re - rs);
-    const int32_t cb = rs + j * kChunkArcs;
-    const int32_t ce = min(re, cb + kChunkArcs);
-    double acc = 0.0;
-    if (!leaf) {
-        const int32_t mine = (ce - cb - lane + kWave - 1) / kWave;  // arcs of this lane
-        for (int32_t t = 0; t < mine; t += kBatch)
-            arc_batch<FWD>(c, cb + lane + t * kWave, kWave, min(kBatch, mine - t), acc);
-    }
-    acc = wave_sum(acc);
-    if (nch == 1 || leaf) {  // a leaf level has no partials: chunk 0 finishes the vertex
+    if (leaf) {  // a leaf level has no partials: chunk 0 finishes the vertex
         if (lane == 0 && j == 0) {
-            if (FWD) set_sigma(c, w, acc);
-            else set_delta(c, w, acc, delta_out);
+            ++wk.owners;
+            if (FWD) set_sigma(c, w, 0.0);
+            else set_delta(c, w, 0.0, delta_out);
         }
         return;
     }
-    // Several chunks: the partial is combined with the others, in chunk order,
-    // by the next kernel on the stream (the compaction after a forward step,
-    // the finishing kernel after a reverse step).
-    if (lane == 0) c.d.partial[first + j] = acc;
+    const int32_t cb = rs + j * kChunkArcs;
+    const double acc = wave_arcs<FWD>(c, cb, min(re, cb + kChunkArcs), wk);
+    if (lane == 0) {
+        if (j == 0) ++wk.owners;
+        c.d.partial[first + j] = acc;
+    }
 }
 
-// Sum the chunk partials of the multi-chunk (bucket 2) vertices of level L in
-// chunk order; one wavefront per vertex.  Runs in the kernel after the level
-// kernel, so the partials are visible without fences.
+// Sum the chunk partials of the bucket-3 vertices of level L in chunk order;
+// one wavefront per vertex.  Runs in the kernel after the level kernel, so the
+// partials are visible without fences.
 template <bool FWD>
 __device__ void finish_chunks(const LevelCtx &c, uint32_t wave, uint32_t nwaves,
                               double *delta_out) {
     const int lane = lane_id();
-    const uint32_t nv = (uint32_t)(c.cur.cnt2 >> 32);
+    const uint32_t nv = (uint32_t)(c.cur.cnt3 >> 32);
     for (uint32_t k = wave; k < nv; k += nwaves) {
-        const uint32_t qi = c.cur.vstart2 + k;
-        const int32_t w = c.d.q2[qi];
+        const uint32_t qi = c.cur.vstart3 + k;
+        const int32_t w = c.d.q[3][qi];
         const uint32_t nch = chunks_of(c.d.row_ptr[w + 1] - c.d.row_ptr[w]);
-        if (nch == 1) continue;
-        const int32_t first = c.d.q2c[qi];
+        const int32_t first = c.d.q3c[qi];
         double t = 0.0;
         for (uint32_t j = (uint32_t)lane; j < nch; j += kWave) t += c.d.partial[first + j];
         t = wave_sum(t);
@@ -231,53 +262,87 @@ __device__ void finish_chunks(const LevelCtx &c, uint32_t wave, uint32_t nwaves,
 
 __global__ __launch_bounds__(kBlock) void k_finish_reverse(PlainDev d, int32_t L,
                                                            double *delta_out) {
+    if (d.ctrl[2]) return;
+    if (level_empty(d.lvl[L + 1])) return;  // a leaf level has no partials
     const LevelCtx c = make_ctx(d, L);
     finish_chunks<false>(c, (blockIdx.x * kBlock + threadIdx.x) / kWave,
                          gridDim.x * kWavesPerBlock, delta_out);
 }
 
+__device__ void report_work(unsigned long long *out, const Work &wk) {
+    unsigned long long o = wk.owners, a = wk.arcs, h = wk.hits;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        o += __shfl_xor(o, off);
+        a += __shfl_xor(a, off);
+        h += __shfl_xor(h, off);
+    }
+    if (lane_id() == 0 && (o | a | h)) {
+        atomicAdd(&out[0], o);
+        atomicAdd(&out[1], a);
+        atomicAdd(&out[2], h);
+    }
+}
+
 template <bool FWD>
 __global__ __launch_bounds__(kBlock) void k_level(PlainDev d, int32_t L, int32_t leaf,
                                                   double *delta_out) {
+    if (!FWD && d.ctrl[2]) return;  // truncated source: it is run again with more levels
     const LevelCtx c = make_ctx(d, L);
-    const uint32_t nch2 = (uint32_t)(c.cur.cnt2 & 0xffffffffu);
-    const uint32_t w1 = (c.cur.cnt1 + (kWave / kB1Lanes) - 1) / (kWave / kB1Lanes);
-    const uint32_t w0 = (c.cur.cnt0 + kWave - 1) / kWave;
-    const uint32_t total = nch2 + w1 + w0;
+    if (!FWD && leaf < 0) leaf = level_empty(d.lvl[L + 1]) ? 1 : 0;  // deepest level?
+    const uint32_t n3 = (uint32_t)(c.cur.cnt3 & 0xffffffffu);  // chunks
+    const uint32_t n2 = c.cur.cnt[2];
+    const uint32_t w1 = (c.cur.cnt[1] + (kWave / kB1Lanes) - 1) / (kWave / kB1Lanes);
+    const uint32_t w0 = (c.cur.cnt[0] + kWave - 1) / kWave;
+    const uint32_t total = n3 + n2 + w1 + w0;
     const uint32_t wave = (blockIdx.x * kBlock + threadIdx.x) / kWave;
     const uint32_t nwaves = gridDim.x * kWavesPerBlock;
+    Work wk;
     for (uint32_t it = wave; it < total; it += nwaves) {
-        if (it < nch2) level_b2<FWD>(c, it, leaf != 0, delta_out);
-        else if (it < nch2 + w1) level_b1<FWD>(c, it - nch2, leaf != 0, delta_out);
-        else level_b0<FWD>(c, it - nch2 - w1, leaf != 0, delta_out);
+        if (it < n3) level_b3<FWD>(c, it, leaf != 0, delta_out, wk);
+        else if (it < n3 + n2) level_b2<FWD>(c, it - n3, leaf != 0, delta_out, wk);
+        else if (it < n3 + n2 + w1) level_b1<FWD>(c, it - n3 - n2, leaf != 0, delta_out, wk);
+        else level_b0<FWD>(c, it - n3 - n2 - w1, leaf != 0, delta_out, wk);
     }
+    if (d.stats) report_work(d.stats + (FWD ? 0 : 6), wk);
 }
 
 // Compaction after the forward step of level L: every marked vertex gets code
 // (L+1) mod 3 and a slot in the level L+1 queue of its degree bucket; marks
 // are cleared.  Thread t owns vertices 16t .. 16t+15 (one code word, one
-// 16-byte mark group), so codes are written without atomics.
-__global__ __launch_bounds__(kBlock) void k_compact(PlainDev d, int32_t L) {
+// 16-byte mark group), so codes are written without atomics.  The kernel also
+// completes the sigma of the level-L bucket-3 vertices.
+__global__ __launch_bounds__(kBlock) void k_compact(PlainDev d, int32_t L, int32_t last,
+                                                    int32_t *trunc_flag) {
+    const LevelRec cur = d.lvl[L];
+    if (level_empty(cur)) {
+        // a level past the deepest one: nothing is marked
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            LevelRec *nn = &d.lvl[L + 2];
+            nn->cnt[0] = nn->cnt[1] = nn->cnt[2] = 0u;
+            nn->cnt3 = 0ull;
+        }
+        return;
+    }
     {
         const LevelCtx c = make_ctx(d, L);
         finish_chunks<true>(c, (blockIdx.x * kBlock + threadIdx.x) / kWave,
                             gridDim.x * kWavesPerBlock, nullptr);
     }
-    const LevelRec cur = d.lvl[L];
-    const uint32_t ns0 = cur.start0 + cur.cnt0;
-    const uint32_t ns1 = cur.start1 + cur.cnt1;
-    const uint32_t nv2 = cur.vstart2 + (uint32_t)(cur.cnt2 >> 32);
-    const uint32_t nc2 = cur.cstart2 + (uint32_t)(cur.cnt2 & 0xffffffffu);
+    uint32_t ns[3];
+#pragma unroll
+    for (int b = 0; b < 3; ++b) ns[b] = cur.start[b] + cur.cnt[b];
+    const uint32_t nv3 = cur.vstart3 + (uint32_t)(cur.cnt3 >> 32);
+    const uint32_t nc3 = cur.cstart3 + (uint32_t)(cur.cnt3 & 0xffffffffu);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         LevelRec *nx = &d.lvl[L + 1];
-        nx->start0 = ns0;
-        nx->start1 = ns1;
-        nx->vstart2 = nv2;
-        nx->cstart2 = nc2;
+#pragma unroll
+        for (int b = 0; b < 3; ++b) nx->start[b] = ns[b];
+        nx->vstart3 = nv3;
+        nx->cstart3 = nc3;
         LevelRec *nn = &d.lvl[L + 2];
-        nn->cnt0 = 0;
-        nn->cnt1 = 0;
-        nn->cnt2 = 0ull;
+        nn->cnt[0] = nn->cnt[1] = nn->cnt[2] = 0u;
+        nn->cnt3 = 0ull;
     }
     const uint32_t code = (uint32_t)((L + 1) % 3);
     const int32_t words = (d.n + 15) >> 4;
@@ -301,7 +366,7 @@ __global__ __launch_bounds__(kBlock) void k_compact(PlainDev d, int32_t L) {
                 for (int b = 0; b < 4; ++b)
                     if ((wv[q] >> (8 * b)) & 0xffu) bits |= 1u << (4 * q + b);
         }
-        uint32_t c0 = 0, c1 = 0, c2 = 0, ch2 = 0;
+        uint32_t cb[4] = {0u, 0u, 0u, 0u}, ch3 = 0;
         uint32_t nch[16];
         if (bits) {
             const int32_t v0 = i << 4;
@@ -310,14 +375,16 @@ __global__ __launch_bounds__(kBlock) void k_compact(PlainDev d, int32_t L) {
                 nch[j] = 0;
                 if ((bits >> j) & 1u) {
                     const int32_t v = v0 + j;
-                    if (v < d.b2_end) {
-                        ++c2;
+                    if (v < d.b3_end) {
+                        ++cb[3];
                         nch[j] = chunks_of(d.row_ptr[v + 1] - d.row_ptr[v]);
-                        ch2 += nch[j];
+                        ch3 += nch[j];
+                    } else if (v < d.b2_end) {
+                        ++cb[2];
                     } else if (v < d.b1_end) {
-                        ++c1;
+                        ++cb[1];
                     } else {
-                        ++c0;
+                        ++cb[0];
                     }
                 }
             }
@@ -329,42 +396,53 @@ __global__ __launch_bounds__(kBlock) void k_compact(PlainDev d, int32_t L) {
             d.lev3[i] &= ~clear;
             reinterpret_cast<uint4 *>(d.nextmap)[i] = make_uint4(0u, 0u, 0u, 0u);
         }
-        uint32_t t0, t1, t2, tc2;
-        uint32_t o0 = wave_excl_scan(c0, t0);
-        uint32_t o1 = wave_excl_scan(c1, t1);
-        uint32_t o2 = wave_excl_scan(c2, t2);
-        uint32_t oc2 = wave_excl_scan(ch2, tc2);
-        uint32_t b0 = 0, b1 = 0, bv2 = 0, bc2 = 0;
+        uint32_t off[4], tot[4], offc3, totc3;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) off[b] = wave_excl_scan(cb[b], tot[b]);
+        offc3 = wave_excl_scan(ch3, totc3);
+        uint32_t base[4] = {0u, 0u, 0u, 0u}, basec3 = 0u;
         if (lane == 0) {
-            if (t0) b0 = atomicAdd(&nx->cnt0, t0);
-            if (t1) b1 = atomicAdd(&nx->cnt1, t1);
-            if (t2) {
+#pragma unroll
+            for (int b = 0; b < 3; ++b)
+                if (tot[b]) base[b] = atomicAdd(&nx->cnt[b], tot[b]);
+            if (tot[3]) {
                 const unsigned long long old = atomicAdd(
-                    &nx->cnt2, ((unsigned long long)t2 << 32) | (unsigned long long)tc2);
-                bv2 = (uint32_t)(old >> 32);
-                bc2 = (uint32_t)(old & 0xffffffffu);
+                    &nx->cnt3, ((unsigned long long)tot[3] << 32) | (unsigned long long)totc3);
+                base[3] = (uint32_t)(old >> 32);
+                basec3 = (uint32_t)(old & 0xffffffffu);
             }
-            if (t0 | t1 | t2) atomicMax(&d.ctrl[0], L + 1);
+            const uint32_t found = tot[0] + tot[1] + tot[2] + tot[3];
+            if (found) {
+                atomicMax(&d.ctrl[0], L + 1);
+                atomicMax(&d.ctrl[3], L + 1);
+                if (L == last) {  // more levels than were launched for this source
+                    atomicOr(&d.ctrl[2], 1);
+                    if (trunc_flag) atomicOr(trunc_flag, 1);
+                }
+                if (d.stats) atomicAdd(&d.stats[3], (unsigned long long)found);
+            }
         }
-        b0 = __shfl(b0, 0);
-        b1 = __shfl(b1, 0);
-        bv2 = __shfl(bv2, 0);
-        bc2 = __shfl(bc2, 0);
+#pragma unroll
+        for (int b = 0; b < 4; ++b) base[b] = __shfl(base[b], 0);
+        basec3 = __shfl(basec3, 0);
         if (bits) {
-            uint32_t p0 = ns0 + b0 + o0, p1 = ns1 + b1 + o1, p2 = nv2 + bv2 + o2;
-            uint32_t pc = nc2 + bc2 + oc2;
+            uint32_t p0 = ns[0] + base[0] + off[0], p1 = ns[1] + base[1] + off[1];
+            uint32_t p2 = ns[2] + base[2] + off[2], p3 = nv3 + base[3] + off[3];
+            uint32_t pc = nc3 + basec3 + offc3;
 #pragma unroll
             for (int j = 0; j < 16; ++j) {
                 if (!((bits >> j) & 1u)) continue;
                 const int32_t v = (i << 4) + j;
                 if (v >= d.b1_end) {
-                    d.q0[p0++] = v;
+                    d.q[0][p0++] = v;
                 } else if (v >= d.b2_end) {
-                    d.q1[p1++] = v;
+                    d.q[1][p1++] = v;
+                } else if (v >= d.b3_end) {
+                    d.q[2][p2++] = v;
                 } else {
-                    d.q2[p2] = v;
-                    d.q2c[p2] = (int32_t)pc;
-                    ++p2;
+                    d.q[3][p3] = v;
+                    d.q3c[p3] = (int32_t)pc;
+                    ++p3;
                     pc += nch[j];
                 }
             }
@@ -380,6 +458,8 @@ __global__ void k_reset_run(PlainDev d) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         d.ctrl[0] = 0;
         d.ctrl[1] = 0;
+        d.ctrl[2] = 0;
+        d.ctrl[3] = 0;
     }
 }
 
@@ -393,25 +473,23 @@ __global__ void k_init_source(PlainDev d, int32_t s) {
          i += gridDim.x * blockDim.x)
         d.lev3[i] = (i == sw) ? sval : 0xffffffffu;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-        const int32_t deg = d.row_ptr[s + 1] - d.row_ptr[s];
-        const int b = s < d.b2_end ? 2 : (s < d.b1_end ? 1 : 0);
-        LevelRec r0 = {0u, 0u, 0u, 0u, 0u, 0u, 0ull};
-        if (b == 0) {
-            r0.cnt0 = 1;
-            d.q0[0] = s;
-        } else if (b == 1) {
-            r0.cnt1 = 1;
-            d.q1[0] = s;
+        LevelRec r0 = {};
+        if (s < d.b3_end) {
+            r0.cnt3 = (1ull << 32) |
+                      (unsigned long long)chunks_of(d.row_ptr[s + 1] - d.row_ptr[s]);
+            d.q[3][0] = s;
+            d.q3c[0] = 0;
         } else {
-            r0.cnt2 = (1ull << 32) | (unsigned long long)chunks_of(deg);
-            d.q2[0] = s;
-            d.q2c[0] = 0;
+            const int b = s < d.b2_end ? 2 : (s < d.b1_end ? 1 : 0);
+            r0.cnt[b] = 1;
+            d.q[b][0] = s;
         }
         d.lvl[0] = r0;
-        LevelRec r1 = {0u, 0u, 0u, 0u, 0u, 0u, 0ull};
+        LevelRec r1 = {};
         d.lvl[1] = r1;
         d.sigma[s] = 1.0;
         d.ctrl[0] = 0;
+        d.ctrl[2] = 0;
     }
 }
 
@@ -428,13 +506,20 @@ __global__ void k_export_levels(PlainDev d, int32_t deepest, int32_t *dist, doub
     const int32_t stride = gridDim.x * blockDim.x;
     for (int32_t L = 0; L <= deepest; ++L) {
         const LevelRec r = d.lvl[L];
-        const uint32_t n2 = (uint32_t)(r.cnt2 >> 32);
-        const uint32_t tot = r.cnt0 + r.cnt1 + n2;
+        const uint32_t n3 = (uint32_t)(r.cnt3 >> 32);
+        const uint32_t tot = r.cnt[0] + r.cnt[1] + r.cnt[2] + n3;
         for (uint32_t i = (uint32_t)tid; i < tot; i += (uint32_t)stride) {
             int32_t v;
-            if (i < r.cnt0) v = d.q0[r.start0 + i];
-            else if (i < r.cnt0 + r.cnt1) v = d.q1[r.start1 + i - r.cnt0];
-            else v = d.q2[r.vstart2 + i - r.cnt0 - r.cnt1];
+            uint32_t k = i;
+            if (k < r.cnt[0]) {
+                v = d.q[0][r.start[0] + k];
+            } else if ((k -= r.cnt[0]) < r.cnt[1]) {
+                v = d.q[1][r.start[1] + k];
+            } else if ((k -= r.cnt[1]) < r.cnt[2]) {
+                v = d.q[2][r.start[2] + k];
+            } else {
+                v = d.q[3][r.vstart3 + k - r.cnt[2]];
+            }
             if (dist) dist[v] = L;
             if (sigma) sigma[v] = d.sigma[v];
         }
@@ -465,19 +550,25 @@ hipError_t plain_init_source(const PlainDev &d, int32_t s, hipStream_t stream) {
 hipError_t plain_forward_level(const PlainDev &d, int32_t level, int grid, hipStream_t stream) {
     hipLaunchKernelGGL(k_level<true>, dim3(grid), dim3(kBlock), 0, stream, d, level, 0,
                        (double *)nullptr);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_compact, dim3(grid_for((d.n + 15) / 16, 2048)), dim3(kBlock), 0,
-                       stream, d, level);
     return hipGetLastError();
 }
 
-hipError_t plain_backward_level(const PlainDev &d, int32_t level, bool deepest, int grid,
+hipError_t plain_compact(const PlainDev &d, int32_t level, int32_t last, int32_t *trunc_flag,
+                         hipStream_t stream) {
+    hipLaunchKernelGGL(k_compact, dim3(grid_for((d.n + 15) / 16, 2048)), dim3(kBlock), 0,
+                       stream, d, level, last, trunc_flag);
+    return hipGetLastError();
+}
+
+hipError_t plain_backward_level(const PlainDev &d, int32_t level, int deepest, int grid,
                                 double *delta_out, hipStream_t stream) {
-    hipLaunchKernelGGL(k_level<false>, dim3(grid), dim3(kBlock), 0, stream, d, level,
-                       deepest ? 1 : 0, delta_out);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess || deepest) return e;  // leaves have no chunk partials
+    hipLaunchKernelGGL(k_level<false>, dim3(grid), dim3(kBlock), 0, stream, d, level, deepest,
+                       delta_out);
+    return hipGetLastError();
+}
+
+hipError_t plain_finish_reverse(const PlainDev &d, int32_t level, double *delta_out,
+                                hipStream_t stream) {
     hipLaunchKernelGGL(k_finish_reverse, dim3(64), dim3(kBlock), 0, stream, d, level, delta_out);
     return hipGetLastError();
 }
