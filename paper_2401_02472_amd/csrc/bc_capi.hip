@@ -85,6 +85,21 @@ struct PlainWS {
     bool busy = false;
 };
 
+// Batched workspace: lane-major sigma / c rows for 64 sources, masks, and a
+// level array that grows when a batch runs deeper than it holds.
+struct BatchWS {
+    void *block = nullptr;     // vis, sigma, coef, ctrl, bc
+    size_t bytes = 0;
+    uint64_t *F = nullptr;     // [lcap][n]
+    int32_t lcap = 0;
+    int32_t *d_src = nullptr;  // internal source ids of the run
+    size_t src_cap = 0;
+    int32_t *h_ctrl = nullptr; // pinned mirror of ctrl
+    hipEvent_t done = nullptr;
+    bool busy = false;
+    BatchDev dev{};
+};
+
 class DeviceGuard {
   public:
     explicit DeviceGuard(int dev) {
@@ -111,11 +126,18 @@ struct bc_graph_s {
     int32_t *d_perm = nullptr;      // caller id -> internal id
     std::vector<int32_t> h_perm;    // same, on the host (source mapping)
     int32_t b3_end = 0, b2_end = 0, b1_end = 0;  // bucket id ranges
+    // batched-path work items (vertices of degree > 64 in kChunk-arc chunks)
+    int32_t big_end = 0, multi_end = 0;
+    uint32_t items = 0;
+    int2 *d_item_info = nullptr;
+    uint32_t *d_item_first = nullptr;
     uint64_t total_chunks3 = 0;  // chunk slots needed by bucket-3 vertices of one source
     size_t device_bytes = 0;
     std::mutex mu;
     std::vector<PlainWS *> plain_pool;
+    std::vector<BatchWS *> batch_pool;
     std::atomic<int32_t> depth_hint{16};  // levels launched per source without polling
+    std::atomic<int32_t> batch_depth_hint{16};  // levels of the last batched run
     std::atomic<int32_t> profiling{0};
     std::mutex prof_mu;
     bc_profile prof{};
@@ -447,6 +469,233 @@ struct ExportAlloc {
     }
 };
 
+constexpr int kBatchCtrlInts = 8;
+
+size_t batch_ws_bytes(const bc_graph_s *g) {
+    const size_t n = (size_t)std::max<int32_t>(g->n, 1);
+    size_t b = 0;
+    b += align_up(n * sizeof(uint64_t));                 // vis
+    b += 2 * align_up(n * kWave * sizeof(double));       // sigma, coef rows
+    b += align_up(kBatchCtrlInts * sizeof(int32_t));     // ctrl
+    b += align_up(n * sizeof(double));                   // bc
+    b += align_up((size_t)std::max(g->multi_end, 1) * sizeof(uint64_t));  // reach
+    b += align_up((size_t)std::max<uint32_t>(g->items, 1) * kWave * sizeof(double));  // partial
+    return b;
+}
+
+size_t batch_level_bytes(const bc_graph_s *g, int32_t lcap) {
+    return (size_t)lcap * (size_t)std::max<int32_t>(g->n, 1) * sizeof(uint64_t);
+}
+
+void batch_ws_destroy(BatchWS *ws) {
+    if (!ws) return;
+    if (ws->done) {
+        (void)hipEventSynchronize(ws->done);
+        (void)hipEventDestroy(ws->done);
+    }
+    if (ws->F) (void)hipFree(ws->F);
+    if (ws->d_src) (void)hipFree(ws->d_src);
+    if (ws->block) (void)hipFree(ws->block);
+    if (ws->h_ctrl) (void)hipHostFree(ws->h_ctrl);
+    delete ws;
+}
+
+bc_status batch_ws_create(bc_graph_s *g, BatchWS **out) {
+    BatchWS *ws = new (std::nothrow) BatchWS();
+    if (!ws) return BC_ERR_OUT_OF_MEMORY;
+    ws->bytes = batch_ws_bytes(g);
+    hipError_t e = hipMalloc(&ws->block, ws->bytes);
+    if (e == hipSuccess)
+        e = hipHostMalloc((void **)&ws->h_ctrl, kBatchCtrlInts * sizeof(int32_t),
+                          hipHostMallocDefault);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ws->done, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        batch_ws_destroy(ws);
+        return from_hip(e);
+    }
+    const size_t n = (size_t)std::max<int32_t>(g->n, 1);
+    char *p = (char *)ws->block;
+    auto take = [&](size_t bytes) {
+        char *r = p;
+        p += align_up(bytes);
+        return (void *)r;
+    };
+    BatchDev &d = ws->dev;
+    d.n = g->n;
+    d.row_ptr = g->d_row_ptr;
+    d.col_idx = g->d_col_idx;
+    d.vis = (uint64_t *)take(n * sizeof(uint64_t));
+    d.sigma = (double *)take(n * kWave * sizeof(double));
+    d.coef = (double *)take(n * kWave * sizeof(double));
+    d.ctrl = (int32_t *)take(kBatchCtrlInts * sizeof(int32_t));
+    d.bc = (double *)take(n * sizeof(double));
+    d.reach = (uint64_t *)take((size_t)std::max(g->multi_end, 1) * sizeof(uint64_t));
+    d.partial = (double *)take((size_t)std::max<uint32_t>(g->items, 1) * kWave * sizeof(double));
+    d.big_end = g->big_end;
+    d.multi_end = g->multi_end;
+    d.items = g->items;
+    d.item_info = g->d_item_info;
+    d.item_first = g->d_item_first;
+    d.F = nullptr;
+    d.lcap = 0;
+    *out = ws;
+    return BC_OK;
+}
+
+bc_status batch_grow_levels(bc_graph_s *g, BatchWS *ws, int32_t lcap) {
+    if (lcap <= ws->lcap) return BC_OK;
+    if (ws->F) (void)hipFree(ws->F);
+    ws->F = nullptr;
+    ws->lcap = 0;
+    BC_TRY_HIP(hipMalloc(&ws->F, batch_level_bytes(g, lcap)));
+    ws->lcap = lcap;
+    ws->dev.F = ws->F;
+    ws->dev.lcap = lcap;
+    return BC_OK;
+}
+
+bc_status batch_acquire(bc_graph_s *g, hipStream_t stream, BatchWS **out) {
+    {
+        std::lock_guard<std::mutex> lk(g->mu);
+        for (BatchWS *ws : g->batch_pool) {
+            if (!ws->busy) {
+                ws->busy = true;
+                *out = ws;
+                BC_TRY_HIP(hipStreamWaitEvent(stream, ws->done, 0));
+                return BC_OK;
+            }
+        }
+    }
+    BatchWS *ws = nullptr;
+    bc_status st = batch_ws_create(g, &ws);
+    if (st != BC_OK) return st;
+    ws->busy = true;
+    std::lock_guard<std::mutex> lk(g->mu);
+    g->batch_pool.push_back(ws);
+    *out = ws;
+    return BC_OK;
+}
+
+void batch_release(bc_graph_s *g, BatchWS *ws, hipStream_t stream) {
+    (void)hipEventRecord(ws->done, stream);
+    std::lock_guard<std::mutex> lk(g->mu);
+    ws->busy = false;
+}
+
+// BC over the sources with up to `width` sources per batch.  With dist /
+// sigma (device, caller order, [k][n]), the per-source state is exported too.
+bc_status batched_run(bc_graph_s *g, const int32_t *sources, int32_t k, double *bc_out,
+                      int32_t width, hipStream_t stream, int32_t *dist, double *sigma) {
+    BatchWS *ws = nullptr;
+    bc_status st = batch_acquire(g, stream, &ws);
+    if (st != BC_OK) return st;
+    auto fail = [&](bc_status s2) {
+        batch_release(g, ws, stream);
+        return s2;
+    };
+    const int32_t n = g->n;
+    st = batch_grow_levels(g, ws, std::max(ws->lcap, g->batch_depth_hint.load() + 8));
+    if (st != BC_OK) return fail(st);
+    if ((size_t)k > ws->src_cap) {
+        if (ws->d_src) (void)hipFree(ws->d_src);
+        ws->d_src = nullptr;
+        ws->src_cap = 0;
+        hipError_t ea = hipMalloc(&ws->d_src, (size_t)k * sizeof(int32_t));
+        if (ea != hipSuccess) return fail(from_hip(ea));
+        ws->src_cap = (size_t)k;
+    }
+    std::vector<int32_t> s_int((size_t)std::max(k, 1));
+    for (int32_t i = 0; i < k; ++i) s_int[(size_t)i] = g->h_perm[(size_t)sources[i]];
+    int32_t *x_dist = nullptr;
+    double *x_sigma = nullptr;
+    struct Tmp {
+        int32_t *&a;
+        double *&b;
+        ~Tmp() {
+            if (a) (void)hipFree(a);
+            if (b) (void)hipFree(b);
+        }
+    } tmp_guard{x_dist, x_sigma};
+    hipError_t e = hipSuccess;
+    if (dist) e = hipMalloc(&x_dist, (size_t)kWave * (size_t)n * sizeof(int32_t));
+    if (e == hipSuccess && sigma) e = hipMalloc(&x_sigma, (size_t)kWave * (size_t)n * sizeof(double));
+    if (e == hipSuccess && k > 0)
+        e = hipMemcpyAsync(ws->d_src, s_int.data(), (size_t)k * sizeof(int32_t),
+                           hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipMemsetAsync(ws->dev.bc, 0, (size_t)n * sizeof(double), stream);
+    if (e != hipSuccess) return fail(from_hip(e));
+    int32_t range = 0, run_depth = 0;
+    for (int32_t b0 = 0; b0 < k;) {
+        const int32_t nl = std::min(width, k - b0);
+        const uint64_t full = nl >= 64 ? ~0ull : ((1ull << nl) - 1ull);
+        const BatchDev &d = ws->dev;
+        e = batch_start(d, ws->d_src + b0, nl, stream);
+        if (e != hipSuccess) return fail(from_hip(e));
+        int32_t deepest = 0;
+        bool restart = false;
+        int32_t L0 = 0;
+        for (;;) {
+            const int32_t K = std::max(2, g->batch_depth_hint.load() + 2);
+            const int32_t Lend = std::min(L0 + K, ws->lcap - 1);
+            for (int32_t L = L0; L < Lend && e == hipSuccess; ++L)
+                e = batch_forward(d, L, full, stream);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(ws->h_ctrl, d.ctrl, kBatchCtrlInts * sizeof(int32_t),
+                                   hipMemcpyDeviceToHost, stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(stream);
+            if (e != hipSuccess) return fail(from_hip(e));
+            deepest = ws->h_ctrl[0];
+            if (ws->h_ctrl[2]) {  // level array full: grow it and run the batch again
+                st = batch_grow_levels(g, ws, ws->lcap * 2);
+                if (st != BC_OK) return fail(st);
+                restart = true;
+                break;
+            }
+            if (deepest < Lend || Lend >= n) break;
+            L0 = Lend;
+        }
+        if (restart) continue;
+        for (int32_t L = deepest; L >= 1 && e == hipSuccess; --L)
+            e = batch_reverse(d, L, L == deepest, stream);
+        if (e == hipSuccess && (dist || sigma)) {
+            e = batch_export(d, deepest, nl, x_dist, x_sigma, stream);
+            for (int32_t s = 0; s < nl && e == hipSuccess; ++s) {
+                const size_t row = (size_t)(b0 + s) * (size_t)n;
+                if (dist) e = gather_i32(n, g->d_perm, x_dist + (size_t)s * n, dist + row, stream);
+                if (e == hipSuccess && sigma)
+                    e = gather_f64(n, g->d_perm, x_sigma + (size_t)s * n, sigma + row, stream);
+            }
+        }
+        if (e != hipSuccess) return fail(from_hip(e));
+        range |= ws->h_ctrl[1];
+        run_depth = std::max(run_depth, deepest);
+        b0 += nl;
+    }
+    e = gather_f64(n, g->d_perm, ws->dev.bc, bc_out, stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(ws->h_ctrl, ws->dev.ctrl, kBatchCtrlInts * sizeof(int32_t),
+                           hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return fail(from_hip(e));
+    range |= ws->h_ctrl[1];
+    if (k > 0) g->batch_depth_hint.store(run_depth);
+    batch_release(g, ws, stream);
+    return range ? BC_ERR_RANGE : BC_OK;
+}
+
+// Mode selection: BC_MODE_AUTO picks the batched path when there are enough
+// sources to fill a batch reasonably.
+bool use_batched(const bc_options *opt, int32_t k) {
+    const int32_t mode = opt ? opt->mode : BC_MODE_AUTO;
+    if (mode == BC_MODE_BATCHED) return true;
+    if (mode == BC_MODE_PLAIN) return false;
+    return k >= 16;
+}
+
+int32_t batch_width_of(const bc_options *opt) {
+    return (opt && opt->batch_width > 0) ? opt->batch_width : kWave;
+}
+
 bc_status check_options(const bc_options *opt) {
     if (!opt) return BC_OK;
     if (opt->mode < BC_MODE_AUTO || opt->mode > BC_MODE_BATCHED) return BC_ERR_INVALID_ARG;
@@ -584,6 +833,21 @@ bc_status bc_create_graph(int32_t n, const int32_t *row_ptr, const int32_t *col_
         if (b >= 1) g->b1_end = u + 1;
     }
     g->total_chunks3 = chunks;
+    // batched work items: internal ids are degree-descending, so the vertices
+    // of degree > 64 (> kChunk) are a prefix
+    std::vector<int2> item_info;
+    std::vector<uint32_t> item_first;
+    for (int32_t u = 0; u < n; ++u) {
+        const int32_t o = iperm[(size_t)u];
+        const int32_t dgr = rp_host[o + 1] - rp_host[o];
+        if (dgr <= kB1MaxDeg) break;
+        g->big_end = u + 1;
+        if (dgr > kChunk) g->multi_end = u + 1;
+        item_first.push_back((uint32_t)item_info.size());
+        for (int32_t j = 0; j * kChunk < dgr; ++j) item_info.push_back(make_int2(u, j));
+    }
+    item_first.push_back((uint32_t)item_info.size());
+    g->items = (uint32_t)item_info.size();
 
     const size_t rp_bytes = ((size_t)n + 1) * sizeof(int32_t);
     const size_t ci_bytes = std::max<size_t>((size_t)nnz, 1) * sizeof(int32_t);
@@ -609,6 +873,16 @@ bc_status bc_create_graph(int32_t n, const int32_t *row_ptr, const int32_t *col_
         e = hipMemcpyAsync(t_iperm, iperm.data(), pm_bytes, hipMemcpyHostToDevice, st);
     if (e == hipSuccess)
         e = relabel_csr(n, nnz, old_rp, old_ci, g->d_row_ptr, g->d_perm, t_iperm, g->d_col_idx, st);
+    if (e == hipSuccess)
+        e = hipMalloc(&g->d_item_info, std::max<size_t>(item_info.size(), 1) * sizeof(int2));
+    if (e == hipSuccess)
+        e = hipMalloc(&g->d_item_first, item_first.size() * sizeof(uint32_t));
+    if (e == hipSuccess && !item_info.empty())
+        e = hipMemcpyAsync(g->d_item_info, item_info.data(), item_info.size() * sizeof(int2),
+                           hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(g->d_item_first, item_first.data(),
+                           item_first.size() * sizeof(uint32_t), hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (t_rp) (void)hipFree(t_rp);
     if (t_ci) (void)hipFree(t_ci);
@@ -617,6 +891,8 @@ bc_status bc_create_graph(int32_t n, const int32_t *row_ptr, const int32_t *col_
         if (g->d_row_ptr) (void)hipFree(g->d_row_ptr);
         if (g->d_col_idx) (void)hipFree(g->d_col_idx);
         if (g->d_perm) (void)hipFree(g->d_perm);
+        if (g->d_item_info) (void)hipFree(g->d_item_info);
+        if (g->d_item_first) (void)hipFree(g->d_item_first);
         delete g;
         return from_hip(e);
     }
@@ -630,9 +906,13 @@ bc_status bc_destroy_graph(bc_graph_t g) {
     DeviceGuard dg(g->device);
     for (PlainWS *ws : g->plain_pool) plain_ws_destroy(ws);
     g->plain_pool.clear();
+    for (BatchWS *ws : g->batch_pool) batch_ws_destroy(ws);
+    g->batch_pool.clear();
     if (g->d_row_ptr) (void)hipFree(g->d_row_ptr);
     if (g->d_col_idx) (void)hipFree(g->d_col_idx);
     if (g->d_perm) (void)hipFree(g->d_perm);
+    if (g->d_item_info) (void)hipFree(g->d_item_info);
+    if (g->d_item_first) (void)hipFree(g->d_item_first);
     delete g;
     return BC_OK;
 }
@@ -654,6 +934,9 @@ bc_status bc_run_async(bc_graph_t g, const int32_t *sources, int32_t k, double *
     if (st != BC_OK) return st;
     if (g->n == 0) return BC_OK;
     DeviceGuard dg(g->device);
+    if (use_batched(opt, k))
+        return batched_run(g, sources, k, bc_out_dev, batch_width_of(opt), (hipStream_t)stream,
+                           nullptr, nullptr);
     return plain_run(g, sources, k, bc_out_dev, opt, (hipStream_t)stream, nullptr, nullptr);
 }
 
@@ -665,7 +948,9 @@ bc_status bc_run(bc_graph_t g, const int32_t *sources, int32_t k, double *bc_out
     DeviceGuard dg(g->device);
     double *d_bc = nullptr;
     BC_TRY_HIP(hipMalloc(&d_bc, (size_t)g->n * sizeof(double)));
-    st = plain_run(g, sources, k, d_bc, nullptr, nullptr, nullptr, nullptr);
+    st = use_batched(nullptr, k)
+             ? batched_run(g, sources, k, d_bc, kWave, nullptr, nullptr, nullptr)
+             : plain_run(g, sources, k, d_bc, nullptr, nullptr, nullptr, nullptr);
     if (st == BC_OK || st == BC_ERR_RANGE) {
         hipError_t e = hipMemcpy(bc_out, d_bc, (size_t)g->n * sizeof(double),
                                  hipMemcpyDeviceToHost);
@@ -702,15 +987,19 @@ bc_status bc_run_detail(bc_graph_t g, const int32_t *sources, int32_t k, const b
         exp[i].dist = d_dist ? d_dist + (size_t)i * n : nullptr;
         exp[i].sigma = d_sigma ? d_sigma + (size_t)i * n : nullptr;
     }
+    const bool batched = !opt || opt->mode != BC_MODE_PLAIN;
     ExportAlloc tmp;
-    if ((dist || sigma) && (e = tmp.alloc(n)) != hipSuccess) {
+    if (!batched && (dist || sigma) && (e = tmp.alloc(n)) != hipSuccess) {
         (void)hipFree(d_bc);
         (void)hipFree(d_dist);
         (void)hipFree(d_sigma);
         return from_hip(e);
     }
-    st = plain_run(g, sources, k, d_bc, opt, nullptr, (dist || sigma) ? exp.data() : nullptr,
-                   &tmp.t);
+    if (batched)
+        st = batched_run(g, sources, k, d_bc, batch_width_of(opt), nullptr, d_dist, d_sigma);
+    else
+        st = plain_run(g, sources, k, d_bc, opt, nullptr, (dist || sigma) ? exp.data() : nullptr,
+                       &tmp.t);
     if (st == BC_OK || st == BC_ERR_RANGE) {
         e = hipMemcpy(bc_out, d_bc, n * sizeof(double), hipMemcpyDeviceToHost);
         if (e == hipSuccess && dist)
@@ -766,7 +1055,11 @@ bc_status bc_workspace_bytes(bc_graph_t g, int32_t k, const bc_options *opt, siz
     if (!g || !bytes || k < 0) return BC_ERR_INVALID_ARG;
     bc_status st = check_options(opt);
     if (st != BC_OK) return st;
-    *bytes = plain_ws_bytes(g);
+    if (use_batched(opt, k))
+        *bytes = batch_ws_bytes(g) +
+                 batch_level_bytes(g, std::max(16, g->batch_depth_hint.load() + 8));
+    else
+        *bytes = plain_ws_bytes(g);
     return BC_OK;
 }
 
@@ -788,13 +1081,18 @@ bc_status bc_trim_workspaces(bc_graph_t g) {
     if (!g) return BC_ERR_INVALID_ARG;
     DeviceGuard dg(g->device);
     std::vector<PlainWS *> idle;
+    std::vector<BatchWS *> idle_b;
     {
         std::lock_guard<std::mutex> lk(g->mu);
         std::vector<PlainWS *> keep;
         for (PlainWS *ws : g->plain_pool) (ws->busy ? keep : idle).push_back(ws);
         g->plain_pool.swap(keep);
+        std::vector<BatchWS *> keep_b;
+        for (BatchWS *ws : g->batch_pool) (ws->busy ? keep_b : idle_b).push_back(ws);
+        g->batch_pool.swap(keep_b);
     }
     for (PlainWS *ws : idle) plain_ws_destroy(ws);
+    for (BatchWS *ws : idle_b) batch_ws_destroy(ws);
     return BC_OK;
 }
 

@@ -77,6 +77,44 @@ struct PlainDev {
     double *bc;           // [n] accumulated BC
 };
 
+// Device view of one batched workspace (up to 64 sources, one per lane).
+// Vertices [0, big_end) (degree > 64) are processed as chunk items of kChunk
+// arcs; of those, [0, multi_end) (degree > kChunk) span several items.
+// item_info[i] = (vertex, chunk index); item_first[v] = first item of v.
+constexpr int kChunk = 512;
+
+struct BatchDev {
+    int32_t n;
+    int32_t lcap;          // levels the F array holds
+    int32_t big_end, multi_end;
+    uint32_t items;        // chunk items of the vertices below big_end
+    const int32_t *row_ptr;
+    const int32_t *col_idx;
+    const int2 *item_info;
+    const uint32_t *item_first;  // [big_end + 1]
+    uint64_t *vis;         // [n] sources that reached v
+    uint64_t *F;           // [lcap][n] F[L][v]: sources at distance L from v
+    double *sigma;         // [n][64]
+    double *coef;          // [n][64] (1 + delta) / sigma; child sums while a level runs
+    uint64_t *reach;       // [multi_end] sources reaching a split vertex this iteration
+    double *partial;       // [items][64] reverse child sums per chunk item
+    int32_t *ctrl;         // [0] deepest level, [1] range flag, [2] truncated (level
+                           // array full), [4..5] per-iteration discovery flag (64-bit)
+    double *bc;            // [n] accumulated BC (internal order)
+};
+
+// Launchers (bc_batched.hip).  All are asynchronous on `stream`.
+// Clear the batch state and seed lane s with source src_dev[s], s < nlanes.
+hipError_t batch_start(const BatchDev &d, const int32_t *src_dev, int32_t nlanes,
+                       hipStream_t stream);
+// Forward iteration L -> L+1 (full = mask of the lanes in use).
+hipError_t batch_forward(const BatchDev &d, int32_t level, uint64_t full, hipStream_t stream);
+// Reverse iteration of level L (>= 1); `deepest` marks the last level.
+hipError_t batch_reverse(const BatchDev &d, int32_t level, bool deepest, hipStream_t stream);
+// dist [nlanes][n] (int32) and sigma [nlanes][n] of the batch, internal order.
+hipError_t batch_export(const BatchDev &d, int32_t deepest, int32_t nlanes, int32_t *dist,
+                        double *sigma, hipStream_t stream);
+
 // Launchers (bc_plain.hip).  All are asynchronous on `stream`.
 // Graph set-up (bc_graph.hip).
 // new_ci[e] = perm[old_ci[old_rp[iperm[u]] + e - new_rp[u]]] for the internal

@@ -1,0 +1,155 @@
+"""GPU parity of the batched path (up to 64 sources per level step) against
+the CPU oracle and against the one-source-at-a-time path (compare rules in
+tests/gpu_checks.py)."""
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+import paper_2401_02472_amd as bcm
+from tests.gpu_checks import batched, check_bc, check_sigma, oracle_bc, plain
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need an MI355X"
+    bcm.load_library()
+
+
+FAMILIES = [
+    gg.path(2), gg.path(150), gg.star(5), gg.star(3000), gg.cycle(9), gg.cycle(130),
+    gg.complete(12), gg.complete_bipartite(3, 40), gg.hypercube(7), gg.grid_full(17, 23),
+    gg.torus(8, 12), gg.random_tree(300, 4), gg.gnp(60, 0.08, 2),
+    gg.csr_from_edges(1, [], []), gg.csr_from_edges(7, [], []),
+]
+
+
+@pytest.mark.parametrize("g", FAMILIES, ids=lambda g: g.name)
+def test_families_all_sources(g):
+    with bcm.Graph(g.n, g.row_ptr, g.col_idx) as G:
+        src = np.arange(g.n, dtype=np.int32)
+        check_bc(batched(G, src), oracle_bc(g, src))
+
+
+def test_rmat12_all_sources():
+    """The scale-12 R-MAT workload from all 4096 sources: 64 full batches."""
+    g, src = gg.workload("rmat-s12-ef8")
+    with bcm.Graph(g.n, g.row_ptr, g.col_idx) as G:
+        check_bc(batched(G, src), oracle_bc(g, src))
+
+
+@pytest.mark.parametrize("width", [1, 7, 32, 64])
+def test_batch_widths_and_ragged_last_batch(width):
+    g = gg.rmat(13, 8, seed=11)
+    src = gg.sample_sources(g, 100, seed=12)          # 100 = ragged for every width
+    with bcm.Graph(g.n, g.row_ptr, g.col_idx) as G:
+        check_bc(batched(G, src, batch_width=width), oracle_bc(g, src))
+
+
+@pytest.mark.parametrize("g", [gg.rmat(12, 8, seed=1), gg.rmat(15, 16, seed=5),
+                               gg.grid_road(64, 64, seed=3), gg.star(9000)],
+                         ids=lambda g: g.name)
+def test_per_source_state_bit_exact(g):
+    """dist and sigma of every lane of a batch, from bc_run_detail."""
+    deg = g.degrees()
+    src = list(gg.sample_sources(g, 40, seed=21))
+    src.append(int(np.argmax(deg)))
+    iso = np.nonzero(deg == 0)[0]
+    if iso.size:
+        src.append(int(iso[0]))
+    src = np.asarray(src, np.int32)
+    with bcm.Graph(g.n, g.row_ptr, g.col_idx) as G:
+        bc, dist, sigma = G.run_detail(src, bcm.make_options(bcm.BC_MODE_BATCHED))
+    check_bc(bc, oracle_bc(g, src))
+    for i, s in enumerate(src):
+        od, osg, _, st = oracle.single_source(g.row_ptr, g.col_idx, int(s), with_delta=False)
+        assert st == oracle.OK
+        assert np.array_equal(dist[i], od), f"dist differs for lane {i} (source {s})"
+        check_sigma(sigma[i], osg)
+
+
+def test_duplicates_in_one_batch_and_additivity():
+    g = gg.rmat(11, 8, seed=9)
+    src = gg.sample_sources(g, 24, seed=10)
+    with bcm.Graph(g.n, g.row_ptr, g.col_idx) as G:
+        dup = np.concatenate([src[:5], src[:5], src[:1]])
+        check_bc(batched(G, dup), oracle_bc(g, dup))
+        a = batched(G, src[:10])
+        b = batched(G, src[10:])
+        np.testing.assert_allclose(batched(G, src), a + b, rtol=1e-12, atol=0)
+
+
+def test_batched_equals_plain_and_is_deterministic():
+    g = gg.rmat(14, 16, seed=2)
+    src = gg.sample_sources(g, 96, seed=3)
+    with bcm.Graph(g.n, g.row_ptr, g.col_idx) as G:
+        p = plain(G, src)
+        b1 = batched(G, src)
+        b2 = batched(G, src)
+    assert np.array_equal(b1, b2)
+    check_bc(b1, p)
+
+
+def test_deep_graph_grows_level_array():
+    """A 2000-vertex path from all ends runs deeper than the initial level array."""
+    g = gg.path(2000)
+    src = np.array([0, 1999, 1000, 3, 1500], np.int32)
+    with bcm.Graph(g.n, g.row_ptr, g.col_idx) as G:
+        check_bc(batched(G, src), oracle_bc(g, src))
+        check_bc(batched(G, src), oracle_bc(g, src))
+
+
+def test_road_grid_deep_sigma_beyond_2_53():
+    g = gg.grid_road(256, 256, seed=7)
+    src = gg.sample_sources(g, 70, seed=8)
+    with bcm.Graph(g.n, g.row_ptr, g.col_idx) as G:
+        bc, dist, sigma = G.run_detail(src[:8], bcm.make_options(bcm.BC_MODE_BATCHED))
+        for i, s in enumerate(src[:8]):
+            od, osg, _, _ = oracle.single_source(g.row_ptr, g.col_idx, int(s), with_delta=False)
+            assert np.array_equal(dist[i], od)
+            check_sigma(sigma[i], osg)
+        check_bc(batched(G, src), oracle_bc(g, src))
+
+
+def test_multigraph_and_self_loops():
+    rng = np.random.default_rng(5)
+    u = rng.integers(0, 40, 200)
+    v = rng.integers(0, 40, 200)
+    g = gg.csr_from_edges(40, u, v, dedup=False, drop_loops=False)
+    with bcm.Graph(g.n, g.row_ptr, g.col_idx) as G:
+        src = np.arange(g.n, dtype=np.int32)
+        check_bc(batched(G, src), oracle_bc(g, src))
+
+
+def test_sigma_overflow_reports_range():
+    g = gg.grid_full(600, 600)
+    with bcm.Graph(g.n, g.row_ptr, g.col_idx, flags=bcm.BC_GRAPH_TRUST_SYMMETRIC) as G:
+        with pytest.raises(bcm.BCError) as ei:
+            batched(G, np.array([0, 5], np.int32))
+        assert ei.value.status == bcm.BC_ERR_RANGE
+
+
+def test_auto_mode_matches():
+    g = gg.rmat(12, 8, seed=4)
+    src = gg.sample_sources(g, 40, seed=6)
+    with bcm.Graph(g.n, g.row_ptr, g.col_idx) as G:
+        check_bc(G.run(src), oracle_bc(g, src))
+        check_bc(G.run(src[:3]), oracle_bc(g, src[:3]))
+
+
+def test_rmat22_full_size_one_batch():
+    """Full-size scale-22 R-MAT in the benchmark's launch configuration: one
+    64-source batch; dist / sigma of 3 lanes bit-exact, BC of the batch 1e-9."""
+    g = gg.rmat(22, 16, seed=3)
+    src = gg.sample_sources(g, 256, seed=103)[:64]
+    with bcm.Graph(g.n, g.row_ptr, g.col_idx, flags=bcm.BC_GRAPH_TRUST_SYMMETRIC) as G:
+        got = batched(G, src)
+        _, dist, sigma = G.run_detail(src[:3], bcm.make_options(bcm.BC_MODE_BATCHED))
+    for i, s in enumerate(src[:3]):
+        od, osg, _, _ = oracle.single_source(g.row_ptr, g.col_idx, int(s), with_delta=False)
+        assert np.array_equal(dist[i], od)
+        check_sigma(sigma[i], osg)
+    check_bc(got, oracle_bc(g, src))

@@ -1,21 +1,15 @@
-"""GPU parity of the one-source-at-a-time path against the CPU oracle.
-
-Compare rules (spec tolerances): dist equal everywhere; sigma bitwise
-equal where the oracle's sigma < 2**53, else within 1e-12 relative (sums of
-more than 2**53 are rounded, and the GPU adds parents in a different order);
-BC within 1e-9 relative (every dependency term is >= 0, so there is no
-cancellation), with exact zeros where the oracle has zeros.
-"""
+"""GPU parity of the one-source-at-a-time path against the CPU oracle
+(compare rules in tests/gpu_checks.py)."""
 import numpy as np
 import pytest
 
 import graphgen as gg
 import oracle
 import paper_2401_02472_amd as bcm
+from tests.gpu_checks import check_bc, check_sigma, oracle_bc, plain
 
 pytestmark = pytest.mark.gpu
 
-TWO53 = float(2 ** 53)
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -23,31 +17,6 @@ def _gpu():
     import torch
     assert torch.cuda.is_available(), "GPU tests need an MI355X"
     bcm.load_library()
-
-
-def check_bc(got, want, rtol=1e-9):
-    want = np.asarray(want)
-    assert got.shape == want.shape
-    zero = want == 0
-    assert np.all(got[zero] == 0), "BC must be exactly zero where the oracle's is"
-    err = np.abs(got - want)
-    bad = err > rtol * np.abs(want)
-    assert not bad.any(), f"{bad.sum()} BC values off; worst rel " \
-                          f"{(err[~zero] / np.abs(want[~zero])).max()}"
-
-
-def check_sigma(got, want):
-    exact = want < TWO53
-    assert np.array_equal(got[exact], want[exact])
-    big = ~exact
-    if big.any():
-        assert np.all(np.abs(got[big] - want[big]) <= 1e-12 * want[big])
-
-
-def oracle_bc(g, sources):
-    want, st = oracle.bc(g.row_ptr, g.col_idx, np.asarray(sources, np.int32))
-    assert st == oracle.OK
-    return want
 
 
 FAMILIES = [
@@ -61,14 +30,14 @@ FAMILIES = [
 def test_families_all_sources(g):
     with bcm.Graph(g.n, g.row_ptr, g.col_idx) as G:
         src = np.arange(g.n, dtype=np.int32)
-        check_bc(G.run(src), oracle_bc(g, src))
+        check_bc(plain(G, src), oracle_bc(g, src))
 
 
 def test_rmat12_all_sources():
     """The scale-12 R-MAT workload: exact BC from all 4096 sources."""
     g, src = gg.workload("rmat-s12-ef8")
     with bcm.Graph(g.n, g.row_ptr, g.col_idx) as G:
-        got = G.run(src)
+        got = plain(G, src)
     check_bc(got, oracle_bc(g, src))
 
 
@@ -102,26 +71,26 @@ def test_road_grid_deep_sigma_beyond_2_53():
             od, osg, _, _ = oracle.single_source(g.row_ptr, g.col_idx, int(s))
             assert np.array_equal(dist, od)
             check_sigma(sigma, osg)
-        check_bc(G.run(src), oracle_bc(g, src))
+        check_bc(plain(G, src), oracle_bc(g, src))
 
 
 def test_additivity_duplicates_and_empty():
     g = gg.rmat(11, 8, seed=9)
     src = gg.sample_sources(g, 24, seed=10)
     with bcm.Graph(g.n, g.row_ptr, g.col_idx) as G:
-        assert np.all(G.run(np.zeros(0, np.int32)) == 0)
+        assert np.all(plain(G, np.zeros(0, np.int32)) == 0)
         dup = np.concatenate([src[:5], src[:5]])
-        check_bc(G.run(dup), oracle_bc(g, dup))
-        a = G.run(src[:10])
-        b = G.run(src[10:])
-        np.testing.assert_allclose(G.run(src), a + b, rtol=1e-12, atol=0)
+        check_bc(plain(G, dup), oracle_bc(g, dup))
+        a = plain(G, src[:10])
+        b = plain(G, src[10:])
+        np.testing.assert_allclose(plain(G, src), a + b, rtol=1e-12, atol=0)
 
 
 def test_tiny_graphs():
     for g in [gg.csr_from_edges(1, [], []), gg.csr_from_edges(7, [], []), gg.path(2)]:
         with bcm.Graph(g.n, g.row_ptr, g.col_idx) as G:
             src = np.arange(g.n, dtype=np.int32)
-            check_bc(G.run(src), oracle_bc(g, src))
+            check_bc(plain(G, src), oracle_bc(g, src))
 
 
 def test_multigraph_and_self_loops():
@@ -131,15 +100,15 @@ def test_multigraph_and_self_loops():
     g = gg.csr_from_edges(40, u, v, dedup=False, drop_loops=False)
     with bcm.Graph(g.n, g.row_ptr, g.col_idx) as G:
         src = np.arange(g.n, dtype=np.int32)
-        check_bc(G.run(src), oracle_bc(g, src))
+        check_bc(plain(G, src), oracle_bc(g, src))
 
 
 def test_run_to_run_bit_identical():
     g = gg.rmat(14, 16, seed=2)
     src = gg.sample_sources(g, 8, seed=3)
     with bcm.Graph(g.n, g.row_ptr, g.col_idx) as G:
-        a = G.run(src)
-        b = G.run(src)
+        a = plain(G, src)
+        b = plain(G, src)
     assert np.array_equal(a, b)
 
 
@@ -163,14 +132,14 @@ def test_graph_from_device_tensors():
     ci = torch.from_numpy(g.col_idx).cuda()
     with bcm.Graph(g.n, rp, ci, flags=bcm.BC_GRAPH_INPUT_ON_DEVICE) as G:
         src = np.arange(0, g.n, 7, dtype=np.int32)
-        check_bc(G.run(src), oracle_bc(g, src))
+        check_bc(plain(G, src), oracle_bc(g, src))
 
 
 def test_sigma_overflow_reports_range():
     g = gg.grid_full(600, 600)
     with bcm.Graph(g.n, g.row_ptr, g.col_idx, flags=bcm.BC_GRAPH_TRUST_SYMMETRIC) as G:
         with pytest.raises(bcm.BCError) as ei:
-            G.run(np.array([0], np.int32))
+            plain(G, np.array([0], np.int32))
         assert ei.value.status == bcm.BC_ERR_RANGE
 
 
@@ -193,5 +162,5 @@ def test_rmat22_sampled_full_size():
             od, osg, _, _ = oracle.single_source(g.row_ptr, g.col_idx, int(s), with_delta=False)
             assert np.array_equal(dist, od)
             check_sigma(sigma, osg)
-        got = G.run(src)
+        got = plain(G, src)
     check_bc(got, oracle_bc(g, src))
