@@ -29,16 +29,27 @@ METRIC = "BC GTEPS (sources×2m/s) and HBM roofline %; batched vs per-source; p5
 HBM_PEAK_GBS = 8000.0
 
 # Algorithmic bytes per unit of work (element-granular: each array element a
-# kernel must touch, counted once per use).
-#   forward level kernel, per owner vertex: queue entry 4 + row_ptr pair 8 +
-#     sigma write 8; per arc read: neighbour id 4 + level-code word 4; per
-#     parent arc: parent sigma 8.
-#   reverse level kernel, per owner vertex: queue entry 4 + row_ptr pair 8 +
-#     sigma 8 + c write 8 + BC read-modify-write 16; per arc: 4 + 4; per child
-#     arc: child c 8.
+# kernel must touch, counted once per use), per execution path.
+#   plain forward level kernel, per owner vertex: queue entry 4 + row_ptr
+#     pair 8 + sigma write 8; per arc read: neighbour id 4 + level-code word 4;
+#     per parent arc: parent sigma 8.
+#   plain reverse level kernel, per owner vertex: queue entry 4 + row_ptr pair
+#     8 + sigma 8 + c write 8 + BC read-modify-write 16; per arc: 4 + 4; per
+#     child arc: child c 8.
+#   batched forward kernel (64 sources per probe), per (vertex, source)
+#     discovered: sigma write 8; per arc probed: neighbour id 4 + frontier mask
+#     8; per (arc, source) parent pair: parent sigma 8.
+#   batched reverse kernel, per (vertex, source) at the level: child-sum write
+#     8; per arc probed: 4 + 8; per (arc, source) child pair: child c 8.
 BYTES = {
-    "forward": {"owners": 20, "arcs": 8, "hits": 8},
-    "reverse": {"owners": 44, "arcs": 8, "hits": 8},
+    ("plain", "forward"): {"owners": 20, "arcs": 8, "hits": 8},
+    ("plain", "reverse"): {"owners": 44, "arcs": 8, "hits": 8},
+    ("batched", "forward"): {"owners": 8, "arcs": 12, "hits": 8},
+    ("batched", "reverse"): {"owners": 8, "arcs": 12, "hits": 8},
+}
+KERNELS = {
+    ("plain", "forward"): "k_level_forward", ("plain", "reverse"): "k_level_reverse",
+    ("batched", "forward"): "k_batch_forward", ("batched", "reverse"): "k_batch_reverse",
 }
 
 
@@ -94,11 +105,14 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="rmat-s22-ef16")
-    ap.add_argument("--mode", default="plain", choices=["auto", "plain", "batched"])
+    ap.add_argument("--mode", default="auto", choices=["auto", "plain", "batched"])
     ap.add_argument("--batch-width", type=int, default=0)
     ap.add_argument("--sources", type=int, default=0, help="use only the first N sources")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target oracle CPU time for the cpu_baseline sample (0 = skip)")
+    ap.add_argument("--compare-plain", type=int, default=32,
+                    help="also time this many sources on the one-source-at-a-time path "
+                         "(0 = skip) and report the ratio")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="run one device copy of this size first (counter calibration)")
     args = ap.parse_args()
@@ -150,7 +164,11 @@ def main() -> int:
     torch.cuda.synchronize()
     print(f"# warmup done: n={g.n} nnz={g.nnz} k={k}", file=sys.stderr, flush=True)
 
-    G.profile_enable(True)
+    path = "plain" if mode == bcm.BC_MODE_PLAIN or (mode == bcm.BC_MODE_AUTO and k < 16) \
+        else "batched"
+    # the plain path's event records are sampled (every 16th source) so that
+    # they do not slow the host's launch stream; the batched path records all
+    G.profile_enable(16 if path == "plain" else 1)
     G.profile_read(reset=True)
     step_ms = []
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -173,12 +191,12 @@ def main() -> int:
     # dominant kernel and its roofline point
     cls = max(("forward", "reverse"), key=lambda c: prof[c]["ms"])
     pc = prof[cls]
-    alg_bytes = sum(BYTES[cls][u] * pc[u] for u in ("owners", "arcs", "hits"))
+    alg_bytes = sum(BYTES[(path, cls)][u] * pc[u] for u in ("owners", "arcs", "hits"))
     launches = max(pc["launches"], 1)
     avg_ms = pc["ms"] / launches
     per_launch = alg_bytes / launches
     achieved = per_launch / (avg_ms / 1e3) / 1e9 if avg_ms > 0 else 0.0
-    kernel_name = {"forward": "k_level_forward", "reverse": "k_level_reverse"}[cls]
+    kernel_name = KERNELS[(path, cls)]
     src_hash = kernel_source_hash()
     traffic = read_traffic(kernel_name, args.workload, src_hash)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
@@ -186,6 +204,21 @@ def main() -> int:
                 "traffic": traffic, "kernel": kernel_name,
                 "alg_bytes_per_launch": round(per_launch), "avg_launch_ms": round(avg_ms, 5),
                 "launches": pc["launches"], "kernel_source_hash": src_hash}
+
+    plain_cmp = None
+    if args.compare_plain and path == "batched":
+        sub = np.asarray(sources[:args.compare_plain], np.int32)
+        popt = bcm.make_options(bcm.BC_MODE_PLAIN)
+        G.run_async(sub, out, popt)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        G.run_async(sub, out, popt)
+        torch.cuda.synchronize()
+        pdt = time.perf_counter() - t
+        pg = len(sub) * g.nnz / pdt / 1e9
+        plain_cmp = {"sources": int(len(sub)), "gteps": round(pg, 3),
+                     "ms_per_source": round(pdt * 1e3 / len(sub), 4),
+                     "batched_over_plain": round(value / pg, 3)}
 
     cpu = None
     if args.cpu_seconds > 0:
@@ -201,8 +234,9 @@ def main() -> int:
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": args.workload, "n": g.n, "nnz": g.nnz, "sources": k,
-                   "mode": args.mode, "batch_width": args.batch_width,
-                   "graph": g.params},
+                   "mode": args.mode, "path": path, "batch_width": args.batch_width or
+                   (64 if path == "batched" else 1), "graph": g.params},
+        "plain_comparison": plain_cmp,
         "p50_ms": round(float(q[0]), 3), "p99_ms": round(float(q[1]), 3),
         "roofline": roofline, "cpu_baseline": cpu, "kernels": kernels,
     }

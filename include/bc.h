@@ -184,7 +184,10 @@ typedef struct bc_profile {
     int64_t runs;
 } bc_profile;
 
-/* Switch measurement on (on != 0) or off for runs on g. */
+/* Switch measurement off (on = 0) or on for runs on g.  With on = P > 1, the
+ * one-source-at-a-time path measures only every P-th source of a run, so that
+ * the event records do not slow the host's launch stream; the batched path
+ * measures every launch. */
 bc_status bc_profile_enable(bc_graph_t g, int32_t on);
 
 /* Copy the accumulated totals to *out; with reset != 0, clear them. */

@@ -170,8 +170,9 @@ def bc_trim_workspaces(g: int) -> None:
     _check(_capi.load().bc_trim_workspaces(ctypes.c_void_p(g)), "bc_trim_workspaces")
 
 
-def bc_profile_enable(g: int, on: bool = True) -> None:
-    _check(_capi.load().bc_profile_enable(ctypes.c_void_p(g), int(bool(on))), "bc_profile_enable")
+def bc_profile_enable(g: int, on=True) -> None:
+    """Measurement off (False / 0) or on (True / 1, or a sampling period P > 1)."""
+    _check(_capi.load().bc_profile_enable(ctypes.c_void_p(g), int(on)), "bc_profile_enable")
 
 
 def bc_profile_read(g: int, reset: bool = False) -> dict:
@@ -225,7 +226,7 @@ class Graph:
     def workspace_bytes(self, k: int, options=None) -> int:
         return bc_workspace_bytes(self.handle, k, options)
 
-    def profile_enable(self, on: bool = True) -> None:
+    def profile_enable(self, on=True) -> None:
         bc_profile_enable(self.handle, on)
 
     def profile_read(self, reset: bool = False) -> dict:

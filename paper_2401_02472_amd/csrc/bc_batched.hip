@@ -83,10 +83,32 @@ __device__ __forceinline__ int owner_lane(uint32_t excl, uint32_t a) {
     return o;
 }
 
+// Per-lane work counters, reported only when measurement is switched on:
+// owners = (vertex, source) pairs completed, arcs = arcs probed, hits =
+// (arc, source) pairs whose row value was gathered.
+struct Work {
+    uint32_t owners = 0, arcs = 0, hits = 0;
+};
+
+__device__ void report_work(unsigned long long *out, const Work &wk) {
+    unsigned long long o = wk.owners, a = wk.arcs, h = wk.hits;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        o += __shfl_xor(o, off);
+        a += __shfl_xor(a, off);
+        h += __shfl_xor(h, off);
+    }
+    if (lane_id() == 0 && (o | a | h)) {
+        atomicAdd(&out[0], o);
+        atomicAdd(&out[1], a);
+        atomicAdd(&out[2], h);
+    }
+}
+
 // Walk the lanes set in `hit` (each holding a neighbour id `nb` and a lane
 // mask `m`), kUnroll rows at a time; lane s adds val[nb][s] when s is in m.
 __device__ __forceinline__ void gather_hits(uint64_t hit, int32_t nb, uint64_t m,
-                                            const double *val, double &acc) {
+                                            const double *val, double &acc, Work &wk) {
     const int lane = lane_id();
     while (hit) {
         int32_t vj[kUnroll];
@@ -108,6 +130,8 @@ __device__ __forceinline__ void gather_hits(uint64_t hit, int32_t nb, uint64_t m
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) x[u] = on[u] ? val[(size_t)vj[u] * kWave + lane] : 0.0;
 #pragma unroll
+        for (int u = 0; u < kUnroll; ++u) wk.hits += on[u] ? 1u : 0u;
+#pragma unroll
         for (int u = 0; u < kUnroll; ++u) acc += x[u];
     }
 }
@@ -116,7 +140,7 @@ __device__ __forceinline__ void gather_hits(uint64_t hit, int32_t nb, uint64_t m
 // m = mask[neighbour] & keep, then gather val rows for the hits.
 __device__ __forceinline__ uint64_t probe_chunk(const BatchDev &d, int32_t first, int32_t end,
                                                 const uint64_t *mask, uint64_t keep,
-                                                const double *val, double &acc) {
+                                                const double *val, double &acc, Work &wk) {
     const int lane = lane_id();
     int32_t nb[kProbe];
     uint64_t m[kProbe];
@@ -124,6 +148,7 @@ __device__ __forceinline__ uint64_t probe_chunk(const BatchDev &d, int32_t first
     for (int u = 0; u < kProbe; ++u) {
         const int32_t e = first + u * kWave + lane;
         nb[u] = e < end ? d.col_idx[e] : -1;
+        wk.arcs += e < end ? 1u : 0u;
     }
 #pragma unroll
     for (int u = 0; u < kProbe; ++u) m[u] = nb[u] >= 0 ? (mask[nb[u]] & keep) : 0ull;
@@ -131,7 +156,7 @@ __device__ __forceinline__ uint64_t probe_chunk(const BatchDev &d, int32_t first
 #pragma unroll
     for (int u = 0; u < kProbe; ++u) {
         any |= m[u];
-        gather_hits(__ballot(m[u] != 0ull), nb[u], m[u], val, acc);
+        gather_hits(__ballot(m[u] != 0ull), nb[u], m[u], val, acc, wk);
     }
     return wave_or(any);
 }
@@ -140,7 +165,7 @@ __device__ __forceinline__ uint64_t probe_chunk(const BatchDev &d, int32_t first
 
 // Chunk item of a vertex of degree > 64.
 __device__ void fwd_chunk(const BatchDev &d, int32_t L, uint32_t item, uint64_t full,
-                          uint64_t *found) {
+                          uint64_t *found, Work &wk) {
     const int lane = lane_id();
     const int2 info = d.item_info[item];
     const int32_t w = info.x, j = info.y;
@@ -156,8 +181,9 @@ __device__ void fwd_chunk(const BatchDev &d, int32_t L, uint32_t item, uint64_t 
     const uint64_t *FL = d.F + (size_t)L * (size_t)d.n;
     const int32_t cb = rs + j * kChunk;
     double acc = 0.0;
-    const uint64_t nw = probe_chunk(d, cb, min(re, cb + kChunk), FL, unvis, d.sigma, acc);
+    const uint64_t nw = probe_chunk(d, cb, min(re, cb + kChunk), FL, unvis, d.sigma, acc, wk);
     const bool mine = (nw >> lane) & 1ull;
+    if (mine && (!multi || j == 0)) ++wk.owners;
     if (!multi) {
         if (mine) {
             d.sigma[(size_t)w * kWave + lane] = acc;
@@ -179,7 +205,7 @@ __device__ void fwd_chunk(const BatchDev &d, int32_t L, uint32_t item, uint64_t 
 
 // Group item: vertices base .. base+63 (all of degree <= 64).
 __device__ void fwd_group(const BatchDev &d, int32_t L, int32_t base, uint64_t full,
-                          uint64_t *found) {
+                          uint64_t *found, Work &wk) {
     const int lane = lane_id();
     const uint64_t *FL = d.F + (size_t)L * (size_t)d.n;
     uint64_t *FN = d.F + (size_t)(L + 1) * (size_t)d.n;
@@ -208,6 +234,7 @@ __device__ void fwd_group(const BatchDev &d, int32_t L, int32_t base, uint64_t f
             if ((nw >> lane) & 1ull) {
                 d.sigma[(size_t)w * kWave + lane] = acc;
                 if (!isfinite(acc)) atomicOr(&d.ctrl[1], 1);
+                ++wk.owners;
             }
             if (lane == 0) {
                 FN[w] = nw;
@@ -228,6 +255,7 @@ __device__ void fwd_group(const BatchDev &d, int32_t L, int32_t base, uint64_t f
         if (a < total) {
             nb = d.col_idx[o_rs + (int32_t)(a - o_excl)];
             m = FL[nb] & o_keep;
+            ++wk.arcs;
         }
         uint64_t hit = __ballot(m != 0ull);
         while (hit) {
@@ -243,7 +271,7 @@ __device__ void fwd_group(const BatchDev &d, int32_t L, int32_t base, uint64_t f
             const uint64_t same = __ballot(o == own) & hit;
             hit &= ~same;
             nw |= wave_or(((same >> lane) & 1ull) ? m : 0ull);
-            gather_hits(same, nb, m, d.sigma, acc);
+            gather_hits(same, nb, m, d.sigma, acc, wk);
         }
     }
     flush();
@@ -257,10 +285,12 @@ __global__ __launch_bounds__(kBlock) void k_batch_forward(BatchDev d, int32_t L,
     const uint32_t groups = (uint32_t)((d.n - d.big_end + kWave - 1) / kWave);
     const uint32_t wave = (blockIdx.x * kBlock + threadIdx.x) / kWave;
     const uint32_t nwaves = gridDim.x * kWavesPerBlock;
+    Work wk;
     for (uint32_t it = wave; it < items + groups; it += nwaves) {
-        if (it < items) fwd_chunk(d, L, it, full, found);
-        else fwd_group(d, L, d.big_end + (int32_t)(it - items) * kWave, full, found);
+        if (it < items) fwd_chunk(d, L, it, full, found, wk);
+        else fwd_group(d, L, d.big_end + (int32_t)(it - items) * kWave, full, found, wk);
     }
+    if (d.stats) report_work(d.stats, wk);
 }
 
 // After a forward iteration: completes the split vertices, records the depth
@@ -303,7 +333,7 @@ __global__ void k_batch_level_done(BatchDev d, int32_t L) {
 
 // Chunk item of a vertex of degree > 64: sums of c over children, written to
 // the vertex's c row (one chunk) or to the item's partial row (split vertex).
-__device__ void bwd_chunk(const BatchDev &d, int32_t L, uint32_t item) {
+__device__ void bwd_chunk(const BatchDev &d, int32_t L, uint32_t item, Work &wk) {
     const int lane = lane_id();
     const int2 info = d.item_info[item];
     const int32_t v = info.x, j = info.y;
@@ -313,12 +343,13 @@ __device__ void bwd_chunk(const BatchDev &d, int32_t L, uint32_t item) {
     const int32_t rs = d.row_ptr[v], re = d.row_ptr[v + 1];
     const int32_t cb = rs + j * kChunk;
     double acc = 0.0;
-    (void)probe_chunk(d, cb, min(re, cb + kChunk), FC, mv, d.coef, acc);
+    (void)probe_chunk(d, cb, min(re, cb + kChunk), FC, mv, d.coef, acc, wk);
+    if (((mv >> lane) & 1ull) && j == 0) ++wk.owners;
     if (v < d.multi_end) d.partial[(size_t)item * kWave + lane] = acc;
     else if ((mv >> lane) & 1ull) d.coef[(size_t)v * kWave + lane] = acc;
 }
 
-__device__ void bwd_group(const BatchDev &d, int32_t L, int32_t base) {
+__device__ void bwd_group(const BatchDev &d, int32_t L, int32_t base, Work &wk) {
     const int lane = lane_id();
     const uint64_t *FL = d.F + (size_t)L * (size_t)d.n;
     const uint64_t *FC = d.F + (size_t)(L + 1) * (size_t)d.n;
@@ -334,6 +365,7 @@ __device__ void bwd_group(const BatchDev &d, int32_t L, int32_t base) {
     }
     uint32_t total;
     const uint32_t excl = wave_excl_scan((uint32_t)cnt, total);
+    wk.owners += (uint32_t)__popcll((unsigned long long)mv);
     // owners with lanes at level L but no children keep sum 0: written first
     uint64_t pending = __ballot(mv != 0ull);
     int cur = -1;
@@ -354,6 +386,7 @@ __device__ void bwd_group(const BatchDev &d, int32_t L, int32_t base) {
         if (a < total) {
             nb = d.col_idx[o_rs + (int32_t)(a - o_excl)];
             m = FC[nb] & o_keep;
+            ++wk.arcs;
         }
         uint64_t hit = __ballot(m != 0ull);
         while (hit) {
@@ -367,7 +400,7 @@ __device__ void bwd_group(const BatchDev &d, int32_t L, int32_t base) {
             }
             const uint64_t same = __ballot(o == own) & hit;
             hit &= ~same;
-            gather_hits(same, nb, m, d.coef, acc);
+            gather_hits(same, nb, m, d.coef, acc, wk);
         }
     }
     flush();
@@ -385,10 +418,12 @@ __global__ __launch_bounds__(kBlock) void k_batch_reverse(BatchDev d, int32_t L)
     const uint32_t groups = (uint32_t)((d.n - d.big_end + kWave - 1) / kWave);
     const uint32_t wave = (blockIdx.x * kBlock + threadIdx.x) / kWave;
     const uint32_t nwaves = gridDim.x * kWavesPerBlock;
+    Work wk;
     for (uint32_t it = wave; it < items + groups; it += nwaves) {
-        if (it < items) bwd_chunk(d, L, it);
-        else bwd_group(d, L, d.big_end + (int32_t)(it - items) * kWave);
+        if (it < items) bwd_chunk(d, L, it, wk);
+        else bwd_group(d, L, d.big_end + (int32_t)(it - items) * kWave, wk);
     }
+    if (d.stats) report_work(d.stats + 6, wk);
 }
 
 // Finalise level L: for every v and lane s with s in F_L[v], the child sum is
@@ -522,26 +557,29 @@ hipError_t batch_forward(const BatchDev &d, int32_t level, uint64_t full, hipStr
     const int64_t groups = (d.n - d.big_end + kWave - 1) / kWave;
     hipLaunchKernelGGL(k_batch_forward, dim3(grid_of(d.items + groups)), dim3(kBlock), 0, stream,
                        d, level, full);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    return hipGetLastError();
+}
+
+hipError_t batch_forward_done(const BatchDev &d, int32_t level, uint64_t full,
+                              hipStream_t stream) {
     if (d.multi_end > 0) {
         hipLaunchKernelGGL(k_batch_forward_finish, dim3(grid_of(d.multi_end)), dim3(kBlock), 0,
                            stream, d, level, full);
-        e = hipGetLastError();
+        hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL(k_batch_level_done, dim3(1), dim3(1), 0, stream, d, level);
     return hipGetLastError();
 }
 
-hipError_t batch_reverse(const BatchDev &d, int32_t level, bool deepest, hipStream_t stream) {
-    if (!deepest) {
-        const int64_t groups = (d.n - d.big_end + kWave - 1) / kWave;
-        hipLaunchKernelGGL(k_batch_reverse, dim3(grid_of(d.items + groups)), dim3(kBlock), 0,
-                           stream, d, level);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-    }
+hipError_t batch_reverse(const BatchDev &d, int32_t level, hipStream_t stream) {
+    const int64_t groups = (d.n - d.big_end + kWave - 1) / kWave;
+    hipLaunchKernelGGL(k_batch_reverse, dim3(grid_of(d.items + groups)), dim3(kBlock), 0, stream,
+                       d, level);
+    return hipGetLastError();
+}
+
+hipError_t batch_finalize(const BatchDev &d, int32_t level, bool deepest, hipStream_t stream) {
     hipLaunchKernelGGL(k_batch_finalize, dim3(grid_of((d.n + kWave - 1) / kWave)), dim3(kBlock),
                        0, stream, d, level, deepest ? 1 : 0);
     return hipGetLastError();

@@ -88,6 +88,8 @@ struct PlainWS {
 // Batched workspace: lane-major sigma / c rows for 64 sources, masks, and a
 // level array that grows when a batch runs deeper than it holds.
 struct BatchWS {
+    LaunchTimer timer;
+    unsigned long long *d_stats = nullptr;  // 12 counters (see BatchDev::stats)
     void *block = nullptr;     // vis, sigma, coef, ctrl, bc
     size_t bytes = 0;
     uint64_t *F = nullptr;     // [lcap][n]
@@ -256,6 +258,37 @@ struct SourceState {
     double *delta = nullptr;   // device, optional export
 };
 
+// Add a finished run's event-timed launches and device work counters to the
+// graph's measurement totals (the run's stream has been synchronised).
+void accumulate_profile(bc_graph_s *g, LaunchTimer &timer, const unsigned long long *d_stats) {
+    bc_profile add{};
+    for (size_t i = 0; i < timer.used; ++i) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, timer.ev[2 * i], timer.ev[2 * i + 1]) == hipSuccess)
+            add.ms[timer.cls[i]] += ms;
+        add.launches[timer.cls[i]] += 1;
+    }
+    unsigned long long cnt[12];
+    if (hipMemcpy(cnt, d_stats, sizeof(cnt), hipMemcpyDeviceToHost) == hipSuccess) {
+        add.owners[BC_PROF_FORWARD] = (int64_t)cnt[0];
+        add.arcs[BC_PROF_FORWARD] = (int64_t)cnt[1];
+        add.hits[BC_PROF_FORWARD] = (int64_t)cnt[2];
+        add.owners[BC_PROF_COMPACT] = (int64_t)cnt[3];
+        add.owners[BC_PROF_REVERSE] = (int64_t)cnt[6];
+        add.arcs[BC_PROF_REVERSE] = (int64_t)cnt[7];
+        add.hits[BC_PROF_REVERSE] = (int64_t)cnt[8];
+    }
+    std::lock_guard<std::mutex> lk(g->prof_mu);
+    for (int c = 0; c < BC_PROF_CLASSES; ++c) {
+        g->prof.launches[c] += add.launches[c];
+        g->prof.ms[c] += add.ms[c];
+        g->prof.owners[c] += add.owners[c];
+        g->prof.arcs[c] += add.arcs[c];
+        g->prof.hits[c] += add.hits[c];
+    }
+    g->prof.runs += 1;
+}
+
 // Forward pass of one source with the host polling the deepest discovered
 // level after each chunk of launched levels (used for state exports and for
 // sources that outgrew the speculative level count).
@@ -374,9 +407,17 @@ bc_status plain_run(bc_graph_s *g, const int32_t *sources, int32_t k, double *bc
         for (int32_t i = 0; i < k; ++i) redo.push_back(i);
     } else {
         const int32_t K = (int32_t)std::min<int64_t>(std::max(2, g->depth_hint.load()), g->n);
-        for (int32_t i = 0; i < k && e == hipSuccess; ++i)
+        const int32_t period = std::max(1, g->profiling.load());
+        for (int32_t i = 0; i < k && e == hipSuccess; ++i) {
+            // measurement covers every period-th source only
+            const bool sample = prof && (i % period) == 0;
+            ws->timer.on = sample;
+            ws->dev.stats = sample ? ws->d_stats : nullptr;
             e = plain_source_speculative(ws, g->h_perm[(size_t)sources[i]], K, ws->d_trunc + i,
                                          stream);
+        }
+        ws->timer.on = prof;
+        ws->dev.stats = prof ? ws->d_stats : nullptr;
         if (e != hipSuccess) return fail(from_hip(e));
         if (k > 0) {
             std::vector<int32_t> trunc((size_t)k);
@@ -421,34 +462,7 @@ bc_status plain_run(bc_graph_s *g, const int32_t *sources, int32_t k, double *bc
         const int32_t seen = ws->h_ctrl[3] + 2;
         if (!polled && seen != g->depth_hint.load()) g->depth_hint.store(std::max(seen, 2));
     }
-    if (prof) {
-        bc_profile add{};
-        for (size_t i = 0; i < ws->timer.used; ++i) {
-            float ms = 0.f;
-            if (hipEventElapsedTime(&ms, ws->timer.ev[2 * i], ws->timer.ev[2 * i + 1]) == hipSuccess)
-                add.ms[ws->timer.cls[i]] += ms;
-            add.launches[ws->timer.cls[i]] += 1;
-        }
-        unsigned long long cnt[12];
-        if (hipMemcpy(cnt, ws->d_stats, sizeof(cnt), hipMemcpyDeviceToHost) == hipSuccess) {
-            add.owners[BC_PROF_FORWARD] = (int64_t)cnt[0];
-            add.arcs[BC_PROF_FORWARD] = (int64_t)cnt[1];
-            add.hits[BC_PROF_FORWARD] = (int64_t)cnt[2];
-            add.owners[BC_PROF_COMPACT] = (int64_t)cnt[3];
-            add.owners[BC_PROF_REVERSE] = (int64_t)cnt[6];
-            add.arcs[BC_PROF_REVERSE] = (int64_t)cnt[7];
-            add.hits[BC_PROF_REVERSE] = (int64_t)cnt[8];
-        }
-        std::lock_guard<std::mutex> lk(g->prof_mu);
-        for (int c = 0; c < BC_PROF_CLASSES; ++c) {
-            g->prof.launches[c] += add.launches[c];
-            g->prof.ms[c] += add.ms[c];
-            g->prof.owners[c] += add.owners[c];
-            g->prof.arcs[c] += add.arcs[c];
-            g->prof.hits[c] += add.hits[c];
-        }
-        g->prof.runs += 1;
-    }
+    if (prof) accumulate_profile(g, ws->timer, ws->d_stats);
     plain_release(g, ws, stream);
     return result;
 }
@@ -480,6 +494,7 @@ size_t batch_ws_bytes(const bc_graph_s *g) {
     b += align_up(n * sizeof(double));                   // bc
     b += align_up((size_t)std::max(g->multi_end, 1) * sizeof(uint64_t));  // reach
     b += align_up((size_t)std::max<uint32_t>(g->items, 1) * kWave * sizeof(double));  // partial
+    b += align_up(12 * sizeof(unsigned long long));     // work counters
     return b;
 }
 
@@ -493,6 +508,7 @@ void batch_ws_destroy(BatchWS *ws) {
         (void)hipEventSynchronize(ws->done);
         (void)hipEventDestroy(ws->done);
     }
+    ws->timer.destroy();
     if (ws->F) (void)hipFree(ws->F);
     if (ws->d_src) (void)hipFree(ws->d_src);
     if (ws->block) (void)hipFree(ws->block);
@@ -536,6 +552,8 @@ bc_status batch_ws_create(bc_graph_s *g, BatchWS **out) {
     d.items = g->items;
     d.item_info = g->d_item_info;
     d.item_first = g->d_item_first;
+    ws->d_stats = (unsigned long long *)take(12 * sizeof(unsigned long long));
+    d.stats = nullptr;
     d.F = nullptr;
     d.lcap = 0;
     *out = ws;
@@ -594,6 +612,14 @@ bc_status batched_run(bc_graph_s *g, const int32_t *sources, int32_t k, double *
         return s2;
     };
     const int32_t n = g->n;
+    const bool prof = g->profiling.load() != 0;
+    ws->dev.stats = prof ? ws->d_stats : nullptr;
+    ws->timer.on = prof;
+    ws->timer.used = 0;
+    if (prof) {
+        hipError_t ez = hipMemsetAsync(ws->d_stats, 0, 12 * sizeof(unsigned long long), stream);
+        if (ez != hipSuccess) return fail(from_hip(ez));
+    }
     st = batch_grow_levels(g, ws, std::max(ws->lcap, g->batch_depth_hint.load() + 8));
     if (st != BC_OK) return fail(st);
     if ((size_t)k > ws->src_cap) {
@@ -637,8 +663,14 @@ bc_status batched_run(bc_graph_s *g, const int32_t *sources, int32_t k, double *
         for (;;) {
             const int32_t K = std::max(2, g->batch_depth_hint.load() + 2);
             const int32_t Lend = std::min(L0 + K, ws->lcap - 1);
-            for (int32_t L = L0; L < Lend && e == hipSuccess; ++L)
-                e = batch_forward(d, L, full, stream);
+            for (int32_t L = L0; L < Lend && e == hipSuccess; ++L) {
+                e = ws->timer.begin(BC_PROF_FORWARD, stream);
+                if (e == hipSuccess) e = batch_forward(d, L, full, stream);
+                if (e == hipSuccess) e = ws->timer.end(stream);
+                if (e == hipSuccess) e = ws->timer.begin(BC_PROF_COMPACT, stream);
+                if (e == hipSuccess) e = batch_forward_done(d, L, full, stream);
+                if (e == hipSuccess) e = ws->timer.end(stream);
+            }
             if (e == hipSuccess)
                 e = hipMemcpyAsync(ws->h_ctrl, d.ctrl, kBatchCtrlInts * sizeof(int32_t),
                                    hipMemcpyDeviceToHost, stream);
@@ -655,8 +687,16 @@ bc_status batched_run(bc_graph_s *g, const int32_t *sources, int32_t k, double *
             L0 = Lend;
         }
         if (restart) continue;
-        for (int32_t L = deepest; L >= 1 && e == hipSuccess; --L)
-            e = batch_reverse(d, L, L == deepest, stream);
+        for (int32_t L = deepest; L >= 1 && e == hipSuccess; --L) {
+            if (L != deepest) {
+                e = ws->timer.begin(BC_PROF_REVERSE, stream);
+                if (e == hipSuccess) e = batch_reverse(d, L, stream);
+                if (e == hipSuccess) e = ws->timer.end(stream);
+            }
+            if (e == hipSuccess) e = ws->timer.begin(BC_PROF_FINISH, stream);
+            if (e == hipSuccess) e = batch_finalize(d, L, L == deepest, stream);
+            if (e == hipSuccess) e = ws->timer.end(stream);
+        }
         if (e == hipSuccess && (dist || sigma)) {
             e = batch_export(d, deepest, nl, x_dist, x_sigma, stream);
             for (int32_t s = 0; s < nl && e == hipSuccess; ++s) {
@@ -679,6 +719,7 @@ bc_status batched_run(bc_graph_s *g, const int32_t *sources, int32_t k, double *
     if (e != hipSuccess) return fail(from_hip(e));
     range |= ws->h_ctrl[1];
     if (k > 0) g->batch_depth_hint.store(run_depth);
+    if (prof) accumulate_profile(g, ws->timer, ws->d_stats);
     batch_release(g, ws, stream);
     return range ? BC_ERR_RANGE : BC_OK;
 }
@@ -1064,8 +1105,8 @@ bc_status bc_workspace_bytes(bc_graph_t g, int32_t k, const bc_options *opt, siz
 }
 
 bc_status bc_profile_enable(bc_graph_t g, int32_t on) {
-    if (!g) return BC_ERR_INVALID_ARG;
-    g->profiling.store(on ? 1 : 0);
+    if (!g || on < 0) return BC_ERR_INVALID_ARG;
+    g->profiling.store(on);
     return BC_OK;
 }
 

@@ -100,6 +100,8 @@ struct BatchDev {
     double *partial;       // [items][64] reverse child sums per chunk item
     int32_t *ctrl;         // [0] deepest level, [1] range flag, [2] truncated (level
                            // array full), [4..5] per-iteration discovery flag (64-bit)
+    unsigned long long *stats;  // NULL, or work counters when measuring: [0..2]
+                                // forward, [6..8] reverse (owners, arcs, hits)
     double *bc;            // [n] accumulated BC (internal order)
 };
 
@@ -107,10 +109,15 @@ struct BatchDev {
 // Clear the batch state and seed lane s with source src_dev[s], s < nlanes.
 hipError_t batch_start(const BatchDev &d, const int32_t *src_dev, int32_t nlanes,
                        hipStream_t stream);
-// Forward iteration L -> L+1 (full = mask of the lanes in use).
+// Forward iteration L -> L+1 (full = mask of the lanes in use), then
+// batch_forward_done (completes split vertices, depth bookkeeping).
 hipError_t batch_forward(const BatchDev &d, int32_t level, uint64_t full, hipStream_t stream);
-// Reverse iteration of level L (>= 1); `deepest` marks the last level.
-hipError_t batch_reverse(const BatchDev &d, int32_t level, bool deepest, hipStream_t stream);
+hipError_t batch_forward_done(const BatchDev &d, int32_t level, uint64_t full,
+                              hipStream_t stream);
+// Reverse iteration of level L (>= 1): child sums (not for the deepest
+// level), then batch_finalize (delta, c, BC).
+hipError_t batch_reverse(const BatchDev &d, int32_t level, hipStream_t stream);
+hipError_t batch_finalize(const BatchDev &d, int32_t level, bool deepest, hipStream_t stream);
 // dist [nlanes][n] (int32) and sigma [nlanes][n] of the batch, internal order.
 hipError_t batch_export(const BatchDev &d, int32_t deepest, int32_t nlanes, int32_t *dist,
                         double *sigma, hipStream_t stream);
