@@ -140,6 +140,12 @@ struct bc_graph_s {
     std::vector<BatchWS *> batch_pool;
     std::atomic<int32_t> depth_hint{16};  // levels launched per source without polling
     std::atomic<int32_t> batch_depth_hint{16};  // levels of the last batched run
+    // hop distances (internal order, -1 unreached) from two landmarks: the
+    // highest-degree vertex and the vertex farthest from it; batches are formed
+    // from sources sorted by them
+    std::mutex land_mu;
+    bool land_ready = false;
+    std::vector<int32_t> land1, land2;
     std::atomic<int32_t> profiling{0};
     std::mutex prof_mu;
     bc_profile prof{};
@@ -600,6 +606,50 @@ void batch_release(bc_graph_s *g, BatchWS *ws, hipStream_t stream) {
     ws->busy = false;
 }
 
+// Hop distances from internal vertex s (internal order) with the plain path.
+bc_status bfs_levels(bc_graph_s *g, int32_t s, std::vector<int32_t> &out) {
+    PlainWS *ws = nullptr;
+    bc_status st = plain_acquire(g, nullptr, &ws);
+    if (st != BC_OK) return st;
+    ws->timer.on = false;
+    ws->dev.stats = nullptr;
+    int32_t *d_dist = nullptr;
+    hipError_t e = hipMalloc(&d_dist, (size_t)g->n * sizeof(int32_t));
+    int32_t deepest = 0;
+    if (e == hipSuccess) e = plain_reset_run(ws->dev, nullptr);
+    if (e == hipSuccess) st = plain_forward_polled(g, ws, s, 16, nullptr, &deepest);
+    else st = from_hip(e);
+    if (st == BC_OK) {
+        e = plain_export_fill(g->n, d_dist, nullptr, nullptr, nullptr);
+        if (e == hipSuccess) e = plain_export_levels(ws->dev, deepest, d_dist, nullptr, nullptr);
+        out.resize((size_t)g->n);
+        if (e == hipSuccess)
+            e = hipMemcpy(out.data(), d_dist, (size_t)g->n * sizeof(int32_t), hipMemcpyDeviceToHost);
+        st = from_hip(e);
+    }
+    if (d_dist) (void)hipFree(d_dist);
+    plain_release(g, ws, nullptr);
+    return st;
+}
+
+bc_status ensure_landmarks(bc_graph_s *g) {
+    std::lock_guard<std::mutex> lk(g->land_mu);
+    if (g->land_ready) return BC_OK;
+    if (g->n == 0) {
+        g->land_ready = true;
+        return BC_OK;
+    }
+    bc_status st = bfs_levels(g, 0, g->land1);
+    if (st != BC_OK) return st;
+    int32_t far = 0;
+    for (int32_t v = 0; v < g->n; ++v)
+        if (g->land1[(size_t)v] > g->land1[(size_t)far]) far = v;
+    st = bfs_levels(g, far, g->land2);
+    if (st != BC_OK) return st;
+    g->land_ready = true;
+    return BC_OK;
+}
+
 // BC over the sources with up to `width` sources per batch.  With dist /
 // sigma (device, caller order, [k][n]), the per-source state is exported too.
 bc_status batched_run(bc_graph_s *g, const int32_t *sources, int32_t k, double *bc_out,
@@ -630,8 +680,27 @@ bc_status batched_run(bc_graph_s *g, const int32_t *sources, int32_t k, double *
         if (ea != hipSuccess) return fail(from_hip(ea));
         ws->src_cap = (size_t)k;
     }
+    // Batch composition: sources sorted by their distances to the two
+    // landmarks, so that the 64 sources of a batch lie close together and see
+    // most vertices at the same level (their frontier masks share lanes, the
+    // row gathers are dense).  BC is a sum over sources, so any grouping gives
+    // the same result up to rounding; the order depends only on the inputs.
+    std::vector<int32_t> order((size_t)std::max(k, 1));
+    for (int32_t i = 0; i < k; ++i) order[(size_t)i] = i;
+    if (k > width) {
+        st = ensure_landmarks(g);
+        if (st != BC_OK) return fail(st);
+        const uint32_t far = 0x7fffffff;
+        auto key = [&](int32_t i) {
+            const int32_t v = g->h_perm[(size_t)sources[i]];
+            const int32_t a = g->land1[(size_t)v], b = g->land2[(size_t)v];
+            return std::make_pair(a < 0 ? far : (uint32_t)a, b < 0 ? far : (uint32_t)b);
+        };
+        std::stable_sort(order.begin(), order.begin() + k,
+                         [&](int32_t x, int32_t y) { return key(x) < key(y); });
+    }
     std::vector<int32_t> s_int((size_t)std::max(k, 1));
-    for (int32_t i = 0; i < k; ++i) s_int[(size_t)i] = g->h_perm[(size_t)sources[i]];
+    for (int32_t i = 0; i < k; ++i) s_int[(size_t)i] = g->h_perm[(size_t)sources[order[(size_t)i]]];
     int32_t *x_dist = nullptr;
     double *x_sigma = nullptr;
     struct Tmp {
@@ -700,7 +769,7 @@ bc_status batched_run(bc_graph_s *g, const int32_t *sources, int32_t k, double *
         if (e == hipSuccess && (dist || sigma)) {
             e = batch_export(d, deepest, nl, x_dist, x_sigma, stream);
             for (int32_t s = 0; s < nl && e == hipSuccess; ++s) {
-                const size_t row = (size_t)(b0 + s) * (size_t)n;
+                const size_t row = (size_t)order[(size_t)(b0 + s)] * (size_t)n;
                 if (dist) e = gather_i32(n, g->d_perm, x_dist + (size_t)s * n, dist + row, stream);
                 if (e == hipSuccess && sigma)
                     e = gather_f64(n, g->d_perm, x_sigma + (size_t)s * n, sigma + row, stream);

@@ -153,3 +153,18 @@ def test_rmat22_full_size_one_batch():
         assert np.array_equal(dist[i], od)
         check_sigma(sigma[i], osg)
     check_bc(got, oracle_bc(g, src))
+
+
+def test_detail_rows_follow_caller_order_across_batches():
+    """With more sources than one batch, batches are formed in landmark order;
+    the per-source rows must still come back in the caller's order."""
+    g = gg.rmat(12, 8, seed=13)
+    src = gg.sample_sources(g, 40, seed=14)
+    with bcm.Graph(g.n, g.row_ptr, g.col_idx) as G:
+        bc, dist, sigma = G.run_detail(src, bcm.make_options(bcm.BC_MODE_BATCHED,
+                                                             batch_width=16))
+    check_bc(bc, oracle_bc(g, src))
+    for i, s in enumerate(src):
+        od, osg, _, _ = oracle.single_source(g.row_ptr, g.col_idx, int(s), with_delta=False)
+        assert np.array_equal(dist[i], od), f"row {i} (source {s})"
+        check_sigma(sigma[i], osg)
