@@ -279,7 +279,8 @@ __device__ void fwd_group(const BatchDev &d, int32_t L, int32_t base, uint64_t f
 }
 
 __global__ __launch_bounds__(kBlock) void k_batch_forward(BatchDev d, int32_t L, uint64_t full) {
-    if (L + 1 >= d.lcap) return;
+    // nothing past the deepest level found so far (F_L is empty), or no room
+    if (L > d.ctrl[0] || L + 1 >= d.lcap) return;
     uint64_t *found = (uint64_t *)&d.ctrl[4];
     const uint32_t items = d.items;
     const uint32_t groups = (uint32_t)((d.n - d.big_end + kWave - 1) / kWave);
@@ -297,7 +298,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_forward(BatchDev d, int32_t L,
 // (or the truncation when the level array is full), clears the flag.
 __global__ __launch_bounds__(kBlock) void k_batch_forward_finish(BatchDev d, int32_t L,
                                                                  uint64_t full) {
-    if (L + 1 >= d.lcap) return;
+    if (L > d.ctrl[0] || L + 1 >= d.lcap) return;
     uint64_t *FN = d.F + (size_t)(L + 1) * (size_t)d.n;
     uint64_t *found = (uint64_t *)&d.ctrl[4];
     const int lane = lane_id();
