@@ -99,6 +99,107 @@ def cpu_baseline(g, sources, target_s: float):
                       f"on {threads} threads"}
 
 
+def serving_bench(args) -> int:
+    """Serving mix: Poisson stream of BC requests over 16 resident R-MAT graphs
+    (scales 14-20 with two seeds each, plus 21 and 22; edge factor 16); each
+    request asks for k in {1, 8, 64} random sources of a uniformly chosen graph.
+    Saturation throughput is measured with a burst first; the Poisson stream
+    then runs at 0.8 of it.  Reports GTEPS (sum of k * nnz over the requests /
+    wall time) and p50 / p99 latency from arrival to the result on the host."""
+    import numpy as np
+    import torch
+
+    import graphgen as gg
+    import paper_2401_02472_amd as bcm
+    from paper_2401_02472_amd.serving import BCServer
+
+    torch.cuda.set_device(0)
+    bcm.load_library()
+    specs = [(sc, sd) for sc in range(14, 21) for sd in (1, 2)] + [(21, 1), (22, 1)]
+    graphs, Gs = {}, {}
+    for sc, sd in specs:
+        gid = f"rmat-s{sc}-seed{sd}"
+        print(f"# generating {gid}", file=sys.stderr, flush=True)
+        g = gg.rmat(sc, 16, seed=sd)
+        graphs[gid] = g
+        Gs[gid] = bcm.Graph(g.n, g.row_ptr, g.col_idx, flags=bcm.BC_GRAPH_TRUST_SYMMETRIC)
+    gids = list(graphs)
+    rng = np.random.default_rng(args.serving_seed)
+
+    def make_request(i):
+        gid = gids[int(rng.integers(len(gids)))]
+        k = int(rng.choice([1, 8, 64]))
+        return gid, gg.sample_sources(graphs[gid], k, seed=1000 + i)
+
+    budget = int(args.hbm_budget_gib) << 30
+    srv = BCServer(Gs, budget=budget, slots=args.slots, max_lanes=256)
+    # warm-up: every graph once (landmarks, level hints, workspaces)
+    for gid in gids:
+        srv.submit(gid, gg.sample_sources(graphs[gid], 64, seed=7)).result()
+    # saturation: a burst
+    burst = [make_request(i) for i in range(args.serving_burst)]
+    t = time.perf_counter()
+    futs = [srv.submit(gid, src) for gid, src in burst]
+    for f in futs:
+        f.result()
+    sat_dt = time.perf_counter() - t
+    sat_rate = len(burst) / sat_dt
+    sat_gteps = sum(src.size * graphs[gid].nnz for gid, src in burst) / sat_dt / 1e9
+    print(f"# saturation {sat_rate:.1f} req/s, {sat_gteps:.1f} GTEPS", file=sys.stderr, flush=True)
+    # Poisson stream at 0.8 x saturation
+    lam = args.serving_load * sat_rate
+    stream_reqs = [make_request(10_000 + i) for i in range(args.serving_requests)]
+    srv.completed.clear()
+    t0 = time.perf_counter()
+    arrival = t0
+    futs = []
+    for gid, src in stream_reqs:
+        arrival += float(rng.exponential(1.0 / lam))
+        delay = arrival - time.perf_counter()
+        if delay > 0:
+            time.sleep(delay)
+        futs.append(srv.submit(gid, src))
+    for f in futs:
+        f.result()
+    wall = time.perf_counter() - t0
+    srv.close()
+    lat = srv.latency_stats()
+    work = sum(src.size * graphs[gid].nnz for gid, src in stream_reqs)
+    value = work / wall / 1e9
+    cpu = None
+    if args.cpu_seconds > 0:
+        import oracle
+        threads = min(os.cpu_count() or 1, 16, oracle.max_threads())
+        sample = stream_reqs[:args.serving_cpu_sample]
+        t = time.perf_counter()
+        for gid, src in sample:
+            oracle.bc(graphs[gid].row_ptr, graphs[gid].col_idx, src, threads=threads)
+        dt = time.perf_counter() - t
+        cpu = {"value": round(sum(s.size * graphs[g].nnz for g, s in sample) / dt / 1e9, 4),
+               "unit": "GTEPS", "cores": threads, "kind": "oracle",
+               "sample": f"first {len(sample)} requests of the stream, one after another, "
+                         f"{dt:.2f} s on {threads} threads"}
+    rec = {
+        "metric": METRIC, "value": round(value, 3), "unit": "GTEPS", "n_gpus": 1,
+        "steps": len(stream_reqs), "warmup": len(gids), "ms_per_step": round(wall * 1e3 /
+                                                                            len(stream_reqs), 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "serving-mix", "graphs": len(gids), "edgefactor": 16,
+                   "requests": len(stream_reqs), "k": [1, 8, 64], "arrivals": "poisson",
+                   "load": args.serving_load, "slots": args.slots,
+                   "hbm_budget_gib": args.hbm_budget_gib},
+        "p50_ms": round(lat["p50_ms"], 3), "p99_ms": round(lat["p99_ms"], 3),
+        "mean_latency_ms": round(lat["mean_ms"], 3),
+        "saturation": {"requests_per_s": round(sat_rate, 2), "gteps": round(sat_gteps, 3)},
+        "launches": srv.launches, "roofline": None, "cpu_baseline": cpu,
+    }
+    print(json.dumps(rec), flush=True)
+    for G in Gs.values():
+        G.close()
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -115,6 +216,13 @@ def main() -> int:
                          "(0 = skip) and report the ratio")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="run one device copy of this size first (counter calibration)")
+    ap.add_argument("--slots", type=int, default=4, help="serving: launches in flight")
+    ap.add_argument("--hbm-budget-gib", type=int, default=64, help="serving: HBM budget")
+    ap.add_argument("--serving-requests", type=int, default=400)
+    ap.add_argument("--serving-burst", type=int, default=200)
+    ap.add_argument("--serving-load", type=float, default=0.8)
+    ap.add_argument("--serving-seed", type=int, default=105)
+    ap.add_argument("--serving-cpu-sample", type=int, default=12)
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -132,6 +240,8 @@ def main() -> int:
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         return 2
+    if args.workload == "serving-mix":
+        return serving_bench(args)
     torch.cuda.set_device(0)
     bcm.load_library()
 

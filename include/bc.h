@@ -130,6 +130,25 @@ bc_status bc_run_async(bc_graph_t g, const int32_t *sources, int32_t k, double *
                        const bc_options *opt, void *stream);
 
 /*
+ * Several BC queries on one graph in one call, sharing batches (the serving
+ * path's continuous batching).
+ *   sources    [k] host: the requests' sources back to back, k = req_start[nreq]
+ *   req_start  [nreq+1] host: request r owns sources[req_start[r] .. req_start[r+1])
+ *   nreq       number of requests, >= 0
+ *   bc_outs    [nreq] host array of device pointers, each to n doubles, overwritten
+ *              with that request's BC (caller vertex order) by the end of the
+ *              call's work on `stream`
+ * Sources of different requests share the 64-source batches.  A request of at
+ * most 64 sources never straddles two batches, and a larger one always splits
+ * at the same positions, so each request's result is bit-identical to the one
+ * it gets alone.  Waits on `stream` like bc_run_async.  Errors: as
+ * bc_run_async; BC_ERR_INVALID_ARG also for a decreasing req_start or a NULL
+ * output.
+ */
+bc_status bc_run_multi(bc_graph_t g, const int32_t *sources, const int32_t *req_start,
+                       int32_t nreq, double *const *bc_outs, void *stream);
+
+/*
  * One source, full per-vertex state (host outputs), for parity checks.
  *   dist   [n] host: hop distance from s, -1 if unreachable
  *   sigma  [n] host: number of shortest s-v paths (0 if unreachable)

@@ -20,6 +20,7 @@ from ._capi import (BC_ERR_DEVICE, BC_ERR_INVALID_ARG, BC_ERR_INVALID_GRAPH,  # 
 
 __all__ = [
     "BCError", "bc_create_graph", "bc_destroy_graph", "bc_graph_info", "bc_run", "bc_run_async",
+    "bc_run_multi",
     "bc_single_source", "bc_run_detail", "bc_workspace_bytes", "bc_trim_workspaces",
     "bc_profile_enable", "bc_profile_read", "bc_status_str", "make_options", "Graph",
     "load_library",
@@ -127,6 +128,21 @@ def bc_run_async(g: int, sources, bc_out, options=None, stream=None) -> None:
     _check(st, "bc_run_async", bc_out)
 
 
+def bc_run_multi(g: int, requests, outs, stream=None) -> None:
+    """Several requests (a list of source arrays) in one call; outs[r] is a float64
+    device tensor of n entries that receives request r's BC."""
+    srcs = [_i32(r) for r in requests]
+    start = np.zeros(len(srcs) + 1, dtype=np.int32)
+    start[1:] = np.cumsum([s.size for s in srcs])
+    flat = np.concatenate(srcs) if srcs else np.zeros(0, np.int32)
+    flat = np.ascontiguousarray(flat, dtype=np.int32)
+    ptrs = (ctypes.c_void_p * max(len(srcs), 1))(*[o.data_ptr() for o in outs])
+    st = _capi.load().bc_run_multi(ctypes.c_void_p(g), _ptr(flat, ctypes.c_int32),
+                                   _ptr(start, ctypes.c_int32), len(srcs), ptrs,
+                                   _stream_handle(stream))
+    _check(st, "bc_run_multi", outs)
+
+
 def bc_single_source(g: int, s: int):
     """(dist int32[n], sigma float64[n], delta float64[n]) for one source."""
     n, _, _ = bc_graph_info(g)
@@ -219,6 +235,9 @@ class Graph:
 
     def single_source(self, s: int):
         return bc_single_source(self.handle, s)
+
+    def run_multi(self, requests, outs, stream=None) -> None:
+        bc_run_multi(self.handle, requests, outs, stream)
 
     def run_detail(self, sources, options=None, want_dist=True, want_sigma=True):
         return bc_run_detail(self.handle, sources, options, want_dist, want_sigma)

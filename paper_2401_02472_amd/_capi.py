@@ -31,7 +31,7 @@ BC_MODE_PLAIN = 1
 BC_MODE_BATCHED = 2
 
 EXPORTED = ("bc_create_graph", "bc_destroy_graph", "bc_graph_info", "bc_run", "bc_run_async",
-            "bc_single_source", "bc_run_detail", "bc_workspace_bytes", "bc_trim_workspaces",
+            "bc_run_multi", "bc_single_source", "bc_run_detail", "bc_workspace_bytes", "bc_trim_workspaces",
             "bc_profile_enable", "bc_profile_read", "bc_status_str")
 
 BC_PROF_FORWARD = 0
@@ -81,6 +81,7 @@ def load():
             "bc_graph_info": [vp, i32p, i64p, szp],
             "bc_run": [vp, i32p, ctypes.c_int32, f64p],
             "bc_run_async": [vp, i32p, ctypes.c_int32, vp, optp, vp],
+            "bc_run_multi": [vp, i32p, i32p, ctypes.c_int32, ctypes.POINTER(vp), vp],
             "bc_single_source": [vp, ctypes.c_int32, i32p, f64p, f64p],
             "bc_run_detail": [vp, i32p, ctypes.c_int32, optp, f64p, i32p, f64p],
             "bc_workspace_bytes": [vp, ctypes.c_int32, optp, szp],

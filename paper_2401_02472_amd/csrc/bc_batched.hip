@@ -427,6 +427,22 @@ __global__ __launch_bounds__(kBlock) void k_batch_reverse(BatchDev d, int32_t L)
     if (d.stats) report_work(d.stats + 6, wk);
 }
 
+// Per-request outputs: lanes [seg_start[g], seg_start[g+1]) belong to request
+// g of the batch.  Each segment's deltas are rotated down to lane 0 and summed
+// with the same butterfly whatever the segment's position, so a request's sum
+// does not depend on where in the batch its lanes sit; it is added to the
+// request's output in caller vertex order.
+__device__ void add_segments(const BatchDev &d, int32_t v, double delta) {
+    const int lane = lane_id();
+    for (int32_t g = 0; g < d.nseg; ++g) {
+        const int32_t a = d.seg_start[g], len = d.seg_start[g + 1] - a;
+        double x = __shfl(delta, (lane + a) & (kWave - 1));
+        x = lane < len ? x : 0.0;
+        x = wave_sum(x);
+        if (lane == 0 && x != 0.0) d.seg_out[g][d.iperm[v]] += x;
+    }
+}
+
 // Finalise level L: for every v and lane s with s in F_L[v], the child sum is
 // in c[v][s] (or in the partial rows of a split vertex); delta = sigma * sum,
 // c = (1 + delta) / sigma, BC[v] += sum of the lanes' deltas.  With leaf set
@@ -480,8 +496,12 @@ __global__ __launch_bounds__(kBlock) void k_batch_finalize(BatchDev d, int32_t L
                 const bool on = (mj[u] >> lane) & 1ull;
                 const double delta = on ? sig[u] * sum[u] : 0.0;
                 if (on) d.coef[(size_t)vj[u] * kWave + lane] = (1.0 + delta) / sig[u];
-                const double tot = wave_sum(delta);
-                if (lane == 0 && vj[u] >= 0 && tot != 0.0) d.bc[vj[u]] += tot;
+                if (d.nseg == 0) {
+                    const double tot = wave_sum(delta);
+                    if (lane == 0 && vj[u] >= 0 && tot != 0.0) d.bc[vj[u]] += tot;
+                } else if (vj[u] >= 0) {
+                    add_segments(d, vj[u], delta);
+                }
             }
         }
     }

@@ -126,6 +126,7 @@ struct bc_graph_s {
     int32_t *d_row_ptr = nullptr;   // CSR in the internal (degree-descending) order
     int32_t *d_col_idx = nullptr;
     int32_t *d_perm = nullptr;      // caller id -> internal id
+    int32_t *d_iperm = nullptr;     // internal id -> caller id
     std::vector<int32_t> h_perm;    // same, on the host (source mapping)
     int32_t b3_end = 0, b2_end = 0, b1_end = 0;  // bucket id ranges
     // batched-path work items (vertices of degree > 64 in kChunk-arc chunks)
@@ -650,10 +651,25 @@ bc_status ensure_landmarks(bc_graph_s *g) {
     return BC_OK;
 }
 
-// BC over the sources with up to `width` sources per batch.  With dist /
-// sigma (device, caller order, [k][n]), the per-source state is exported too.
-bc_status batched_run(bc_graph_s *g, const int32_t *sources, int32_t k, double *bc_out,
-                      int32_t width, hipStream_t stream, int32_t *dist, double *sigma) {
+// One batch of a batched run: lanes [first, first + nlanes) of the run's
+// (internal-id) source list; with nseg > 0, its lanes feed nseg request
+// outputs described from seg_first on in the run's segment tables.
+struct BatchPlan {
+    int32_t first, nlanes;
+    int32_t seg_first, nseg;
+};
+
+// Execute a batch plan.  s_int: internal source ids in lane order.  With
+// nseg == 0 everywhere, BC accumulates in the workspace and is gathered into
+// bc_out (caller order); otherwise each segment's output (caller order,
+// zeroed by the caller) receives its lanes' dependencies.  export_row maps a
+// lane of the run to the dist / sigma export row (or NULL: no export).
+bc_status run_batch_plan(bc_graph_s *g, const std::vector<int32_t> &s_int,
+                         const std::vector<BatchPlan> &plan,
+                         const std::vector<int32_t> &seg_start,  // per segment table: nseg+1
+                         const std::vector<double *> &seg_out, double *bc_out,
+                         hipStream_t stream, const int32_t *export_row, int32_t *dist,
+                         double *sigma) {
     BatchWS *ws = nullptr;
     bc_status st = batch_acquire(g, stream, &ws);
     if (st != BC_OK) return st;
@@ -662,6 +678,7 @@ bc_status batched_run(bc_graph_s *g, const int32_t *sources, int32_t k, double *
         return s2;
     };
     const int32_t n = g->n;
+    const int32_t k = (int32_t)s_int.size();
     const bool prof = g->profiling.load() != 0;
     ws->dev.stats = prof ? ws->d_stats : nullptr;
     ws->timer.on = prof;
@@ -672,35 +689,22 @@ bc_status batched_run(bc_graph_s *g, const int32_t *sources, int32_t k, double *
     }
     st = batch_grow_levels(g, ws, std::max(ws->lcap, g->batch_depth_hint.load() + 8));
     if (st != BC_OK) return fail(st);
-    if ((size_t)k > ws->src_cap) {
+    // device copies of the lane sources and the segment tables
+    const size_t seg_ints = seg_start.size(), seg_ptrs = seg_out.size();
+    const size_t need = (size_t)k * sizeof(int32_t) + seg_ints * sizeof(int32_t) +
+                        seg_ptrs * sizeof(double *) + 64;
+    if (need > ws->src_cap) {
         if (ws->d_src) (void)hipFree(ws->d_src);
         ws->d_src = nullptr;
         ws->src_cap = 0;
-        hipError_t ea = hipMalloc(&ws->d_src, (size_t)k * sizeof(int32_t));
+        hipError_t ea = hipMalloc(&ws->d_src, need);
         if (ea != hipSuccess) return fail(from_hip(ea));
-        ws->src_cap = (size_t)k;
+        ws->src_cap = need;
     }
-    // Batch composition: sources sorted by their distances to the two
-    // landmarks, so that the 64 sources of a batch lie close together and see
-    // most vertices at the same level (their frontier masks share lanes, the
-    // row gathers are dense).  BC is a sum over sources, so any grouping gives
-    // the same result up to rounding; the order depends only on the inputs.
-    std::vector<int32_t> order((size_t)std::max(k, 1));
-    for (int32_t i = 0; i < k; ++i) order[(size_t)i] = i;
-    if (k > width) {
-        st = ensure_landmarks(g);
-        if (st != BC_OK) return fail(st);
-        const uint32_t far = 0x7fffffff;
-        auto key = [&](int32_t i) {
-            const int32_t v = g->h_perm[(size_t)sources[i]];
-            const int32_t a = g->land1[(size_t)v], b = g->land2[(size_t)v];
-            return std::make_pair(a < 0 ? far : (uint32_t)a, b < 0 ? far : (uint32_t)b);
-        };
-        std::stable_sort(order.begin(), order.begin() + k,
-                         [&](int32_t x, int32_t y) { return key(x) < key(y); });
-    }
-    std::vector<int32_t> s_int((size_t)std::max(k, 1));
-    for (int32_t i = 0; i < k; ++i) s_int[(size_t)i] = g->h_perm[(size_t)sources[order[(size_t)i]]];
+    int32_t *d_lanes = ws->d_src;
+    int32_t *d_seg_start = d_lanes + k;
+    double **d_seg_out =
+        (double **)(((uintptr_t)(d_seg_start + seg_ints) + 15) & ~(uintptr_t)15);
     int32_t *x_dist = nullptr;
     double *x_sigma = nullptr;
     struct Tmp {
@@ -715,16 +719,28 @@ bc_status batched_run(bc_graph_s *g, const int32_t *sources, int32_t k, double *
     if (dist) e = hipMalloc(&x_dist, (size_t)kWave * (size_t)n * sizeof(int32_t));
     if (e == hipSuccess && sigma) e = hipMalloc(&x_sigma, (size_t)kWave * (size_t)n * sizeof(double));
     if (e == hipSuccess && k > 0)
-        e = hipMemcpyAsync(ws->d_src, s_int.data(), (size_t)k * sizeof(int32_t),
+        e = hipMemcpyAsync(d_lanes, s_int.data(), (size_t)k * sizeof(int32_t),
                            hipMemcpyHostToDevice, stream);
-    if (e == hipSuccess) e = hipMemsetAsync(ws->dev.bc, 0, (size_t)n * sizeof(double), stream);
+    if (e == hipSuccess && seg_ints)
+        e = hipMemcpyAsync(d_seg_start, seg_start.data(), seg_ints * sizeof(int32_t),
+                           hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess && seg_ptrs)
+        e = hipMemcpyAsync(d_seg_out, seg_out.data(), seg_ptrs * sizeof(double *),
+                           hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess && bc_out)
+        e = hipMemsetAsync(ws->dev.bc, 0, (size_t)n * sizeof(double), stream);
     if (e != hipSuccess) return fail(from_hip(e));
     int32_t range = 0, run_depth = 0;
-    for (int32_t b0 = 0; b0 < k;) {
-        const int32_t nl = std::min(width, k - b0);
+    for (size_t bi = 0; bi < plan.size();) {
+        const BatchPlan &bp = plan[bi];
+        const int32_t nl = bp.nlanes;
         const uint64_t full = nl >= 64 ? ~0ull : ((1ull << nl) - 1ull);
-        const BatchDev &d = ws->dev;
-        e = batch_start(d, ws->d_src + b0, nl, stream);
+        BatchDev &d = ws->dev;
+        d.nseg = bp.nseg;
+        d.seg_start = bp.nseg ? d_seg_start + bp.seg_first : nullptr;
+        d.seg_out = bp.nseg ? d_seg_out + (bp.seg_first - (int32_t)bi) : nullptr;
+        d.iperm = g->d_iperm;
+        e = batch_start(d, d_lanes + bp.first, nl, stream);
         if (e != hipSuccess) return fail(from_hip(e));
         int32_t deepest = 0;
         bool restart = false;
@@ -766,21 +782,22 @@ bc_status batched_run(bc_graph_s *g, const int32_t *sources, int32_t k, double *
             if (e == hipSuccess) e = batch_finalize(d, L, L == deepest, stream);
             if (e == hipSuccess) e = ws->timer.end(stream);
         }
-        if (e == hipSuccess && (dist || sigma)) {
+        if (e == hipSuccess && export_row && (dist || sigma)) {
             e = batch_export(d, deepest, nl, x_dist, x_sigma, stream);
-            for (int32_t s = 0; s < nl && e == hipSuccess; ++s) {
-                const size_t row = (size_t)order[(size_t)(b0 + s)] * (size_t)n;
-                if (dist) e = gather_i32(n, g->d_perm, x_dist + (size_t)s * n, dist + row, stream);
+            for (int32_t s2 = 0; s2 < nl && e == hipSuccess; ++s2) {
+                const size_t row = (size_t)export_row[bp.first + s2] * (size_t)n;
+                if (dist) e = gather_i32(n, g->d_perm, x_dist + (size_t)s2 * n, dist + row, stream);
                 if (e == hipSuccess && sigma)
-                    e = gather_f64(n, g->d_perm, x_sigma + (size_t)s * n, sigma + row, stream);
+                    e = gather_f64(n, g->d_perm, x_sigma + (size_t)s2 * n, sigma + row, stream);
             }
         }
         if (e != hipSuccess) return fail(from_hip(e));
         range |= ws->h_ctrl[1];
         run_depth = std::max(run_depth, deepest);
-        b0 += nl;
+        ++bi;
     }
-    e = gather_f64(n, g->d_perm, ws->dev.bc, bc_out, stream);
+    ws->dev.nseg = 0;
+    if (bc_out) e = gather_f64(n, g->d_perm, ws->dev.bc, bc_out, stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(ws->h_ctrl, ws->dev.ctrl, kBatchCtrlInts * sizeof(int32_t),
                            hipMemcpyDeviceToHost, stream);
@@ -791,6 +808,89 @@ bc_status batched_run(bc_graph_s *g, const int32_t *sources, int32_t k, double *
     if (prof) accumulate_profile(g, ws->timer, ws->d_stats);
     batch_release(g, ws, stream);
     return range ? BC_ERR_RANGE : BC_OK;
+}
+
+// BC over the sources with up to `width` sources per batch.  With dist /
+// sigma (device, caller order, [k][n]), the per-source state is exported too.
+bc_status batched_run(bc_graph_s *g, const int32_t *sources, int32_t k, double *bc_out,
+                      int32_t width, hipStream_t stream, int32_t *dist, double *sigma) {
+    // Batch composition: sources sorted by their distances to the two
+    // landmarks, so that the 64 sources of a batch lie close together and see
+    // most vertices at the same level (their frontier masks share lanes, the
+    // row gathers are dense).  BC is a sum over sources, so any grouping gives
+    // the same result up to rounding; the order depends only on the inputs.
+    std::vector<int32_t> order((size_t)k);
+    for (int32_t i = 0; i < k; ++i) order[(size_t)i] = i;
+    if (k > width) {
+        bc_status st = ensure_landmarks(g);
+        if (st != BC_OK) return st;
+        const uint32_t far = 0x7fffffff;
+        auto key = [&](int32_t i) {
+            const int32_t v = g->h_perm[(size_t)sources[i]];
+            const int32_t a = g->land1[(size_t)v], b = g->land2[(size_t)v];
+            return std::make_pair(a < 0 ? far : (uint32_t)a, b < 0 ? far : (uint32_t)b);
+        };
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int32_t x, int32_t y) { return key(x) < key(y); });
+    }
+    std::vector<int32_t> s_int((size_t)k);
+    for (int32_t i = 0; i < k; ++i) s_int[(size_t)i] = g->h_perm[(size_t)sources[order[(size_t)i]]];
+    std::vector<BatchPlan> plan;
+    for (int32_t b0 = 0; b0 < k; b0 += width) plan.push_back({b0, std::min(width, k - b0), 0, 0});
+    return run_batch_plan(g, s_int, plan, {}, {}, bc_out, stream, order.data(), dist, sigma);
+}
+
+// Several requests in one run.  A request of at most 64 sources never
+// straddles two batches; a larger one fills whole batches from a batch start
+// and its remainder starts a batch.  Every request's result is then made of
+// the same lanes in the same order whatever else shares its batches.
+bc_status multi_run(bc_graph_s *g, const int32_t *sources, const int32_t *req_start,
+                    int32_t nreq, double *const *outs, hipStream_t stream) {
+    const int32_t k = req_start[nreq];
+    std::vector<int32_t> s_int((size_t)k);
+    for (int32_t i = 0; i < k; ++i) s_int[(size_t)i] = g->h_perm[(size_t)sources[i]];
+    std::vector<BatchPlan> plan;
+    std::vector<int32_t> seg_start;
+    std::vector<double *> seg_out;
+    // segments of the batch being filled
+    std::vector<std::pair<int32_t, int32_t>> cur;  // (request, lanes)
+    int32_t cur_first = 0, pos = 0;
+    auto close = [&]() {
+        if (pos == 0) return;
+        BatchPlan bp{cur_first, pos, (int32_t)seg_start.size(), (int32_t)cur.size()};
+        // seg_out entries of batch b are stored at seg_first - b (one fewer
+        // entry than seg_start per batch): keep both tables aligned by index
+        int32_t a = 0;
+        for (auto &sg : cur) {
+            seg_start.push_back(a);
+            a += sg.second;
+        }
+        seg_start.push_back(a);
+        for (auto &sg : cur) seg_out.push_back(outs[sg.first]);
+        plan.push_back(bp);
+        cur.clear();
+        cur_first += pos;
+        pos = 0;
+    };
+    for (int32_t r = 0; r < nreq; ++r) {
+        int32_t m = req_start[r + 1] - req_start[r];
+        if (m == 0) continue;
+        if (pos > 0 && (m > kWave || pos + m > kWave)) close();
+        while (m > 0) {
+            const int32_t t = std::min(kWave - pos, m);
+            cur.push_back({r, t});
+            pos += t;
+            m -= t;
+            if (pos == kWave) close();
+        }
+    }
+    close();
+    for (int32_t r = 0; r < nreq; ++r) {
+        hipError_t e = hipMemsetAsync(outs[r], 0, (size_t)g->n * sizeof(double), stream);
+        if (e != hipSuccess) return from_hip(e);
+    }
+    return run_batch_plan(g, s_int, plan, seg_start, seg_out, nullptr, stream, nullptr, nullptr,
+                          nullptr);
 }
 
 // Mode selection: BC_MODE_AUTO picks the batched path when there are enough
@@ -962,11 +1062,11 @@ bc_status bc_create_graph(int32_t n, const int32_t *row_ptr, const int32_t *col_
     const size_t rp_bytes = ((size_t)n + 1) * sizeof(int32_t);
     const size_t ci_bytes = std::max<size_t>((size_t)nnz, 1) * sizeof(int32_t);
     const size_t pm_bytes = (size_t)std::max(n, 1) * sizeof(int32_t);
-    int32_t *t_rp = nullptr, *t_ci = nullptr, *t_iperm = nullptr;
+    int32_t *t_rp = nullptr, *t_ci = nullptr;
     hipError_t e = hipMalloc(&g->d_row_ptr, rp_bytes);
     if (e == hipSuccess) e = hipMalloc(&g->d_col_idx, ci_bytes);
     if (e == hipSuccess) e = hipMalloc(&g->d_perm, pm_bytes);
-    if (e == hipSuccess) e = hipMalloc(&t_iperm, pm_bytes);
+    if (e == hipSuccess) e = hipMalloc(&g->d_iperm, pm_bytes);
     if (e == hipSuccess && !on_device) e = hipMalloc(&t_rp, rp_bytes);
     if (e == hipSuccess && !on_device) e = hipMalloc(&t_ci, ci_bytes);
     const int32_t *old_rp = on_device ? row_ptr : t_rp;
@@ -980,9 +1080,10 @@ bc_status bc_create_graph(int32_t n, const int32_t *row_ptr, const int32_t *col_
     if (e == hipSuccess)
         e = hipMemcpyAsync(g->d_perm, g->h_perm.data(), pm_bytes, hipMemcpyHostToDevice, st);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(t_iperm, iperm.data(), pm_bytes, hipMemcpyHostToDevice, st);
+        e = hipMemcpyAsync(g->d_iperm, iperm.data(), pm_bytes, hipMemcpyHostToDevice, st);
     if (e == hipSuccess)
-        e = relabel_csr(n, nnz, old_rp, old_ci, g->d_row_ptr, g->d_perm, t_iperm, g->d_col_idx, st);
+        e = relabel_csr(n, nnz, old_rp, old_ci, g->d_row_ptr, g->d_perm, g->d_iperm, g->d_col_idx,
+                        st);
     if (e == hipSuccess)
         e = hipMalloc(&g->d_item_info, std::max<size_t>(item_info.size(), 1) * sizeof(int2));
     if (e == hipSuccess)
@@ -996,17 +1097,17 @@ bc_status bc_create_graph(int32_t n, const int32_t *row_ptr, const int32_t *col_
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (t_rp) (void)hipFree(t_rp);
     if (t_ci) (void)hipFree(t_ci);
-    if (t_iperm) (void)hipFree(t_iperm);
     if (e != hipSuccess) {
         if (g->d_row_ptr) (void)hipFree(g->d_row_ptr);
         if (g->d_col_idx) (void)hipFree(g->d_col_idx);
         if (g->d_perm) (void)hipFree(g->d_perm);
+        if (g->d_iperm) (void)hipFree(g->d_iperm);
         if (g->d_item_info) (void)hipFree(g->d_item_info);
         if (g->d_item_first) (void)hipFree(g->d_item_first);
         delete g;
         return from_hip(e);
     }
-    g->device_bytes = rp_bytes + ci_bytes + pm_bytes;
+    g->device_bytes = rp_bytes + ci_bytes + 2 * pm_bytes;
     *out = g;
     return BC_OK;
 }
@@ -1021,6 +1122,7 @@ bc_status bc_destroy_graph(bc_graph_t g) {
     if (g->d_row_ptr) (void)hipFree(g->d_row_ptr);
     if (g->d_col_idx) (void)hipFree(g->d_col_idx);
     if (g->d_perm) (void)hipFree(g->d_perm);
+    if (g->d_iperm) (void)hipFree(g->d_iperm);
     if (g->d_item_info) (void)hipFree(g->d_item_info);
     if (g->d_item_first) (void)hipFree(g->d_item_first);
     delete g;
@@ -1122,6 +1224,22 @@ bc_status bc_run_detail(bc_graph_t g, const int32_t *sources, int32_t k, const b
     (void)hipFree(d_dist);
     (void)hipFree(d_sigma);
     return st;
+}
+
+bc_status bc_run_multi(bc_graph_t g, const int32_t *sources, const int32_t *req_start,
+                       int32_t nreq, double *const *bc_outs, void *stream) {
+    if (!g || nreq < 0 || (nreq > 0 && (!req_start || !bc_outs))) return BC_ERR_INVALID_ARG;
+    if (nreq == 0) return BC_OK;
+    if (req_start[0] != 0) return BC_ERR_INVALID_ARG;
+    for (int32_t r = 0; r < nreq; ++r) {
+        if (req_start[r + 1] < req_start[r]) return BC_ERR_INVALID_ARG;
+        if (!bc_outs[r] && g->n > 0) return BC_ERR_INVALID_ARG;
+    }
+    bc_status st = check_sources(g, sources, req_start[nreq]);
+    if (st != BC_OK) return st;
+    if (g->n == 0) return BC_OK;
+    DeviceGuard dg(g->device);
+    return multi_run(g, sources, req_start, nreq, bc_outs, (hipStream_t)stream);
 }
 
 bc_status bc_single_source(bc_graph_t g, int32_t s, int32_t *dist, double *sigma,

@@ -102,7 +102,13 @@ struct BatchDev {
                            // array full), [4..5] per-iteration discovery flag (64-bit)
     unsigned long long *stats;  // NULL, or work counters when measuring: [0..2]
                                 // forward, [6..8] reverse (owners, arcs, hits)
-    double *bc;            // [n] accumulated BC (internal order)
+    double *bc;            // [n] accumulated BC (internal order), when nseg == 0
+    // Several requests in one batch (nseg > 0): lanes [seg_start[g],
+    // seg_start[g+1]) feed seg_out[g], an [n] array in caller vertex order.
+    int32_t nseg;
+    const int32_t *seg_start;
+    double *const *seg_out;
+    const int32_t *iperm;  // internal id -> caller id
 };
 
 // Launchers (bc_batched.hip).  All are asynchronous on `stream`.
