@@ -77,9 +77,16 @@ enum {
 
 typedef struct bc_options {
     int32_t mode;        /* BC_MODE_*                                                   */
-    int32_t batch_width; /* batched mode: sources per batch, 1..64 (0 = 64)              */
-    int32_t level_chunk; /* forward levels launched per host poll, 1..1024 (0 = 8)       */
-    int32_t reserved[5]; /* must be zero                                                 */
+    int32_t batch_width; /* batched mode: sources per batch, 1..64 (0 = the graph's
+                            setting: bc_autotune's choice, else 64)                      */
+    int32_t level_chunk; /* plain mode: forward levels launched per host poll, 1..1024
+                            (0 = 8)                                                     */
+    int32_t sparse_div;  /* batched mode: a forward level whose frontier has fewer than
+                            nnz / sparse_div arcs expands from the frontier (visits only
+                            the frontier's neighbours) instead of scanning every
+                            unvisited vertex; 1..2^20, -1 = never, 0 = the graph's
+                            setting (bc_autotune's choice, else 64)                      */
+    int32_t reserved[4]; /* must be zero                                                 */
 } bc_options;
 
 /*
@@ -211,6 +218,34 @@ bc_status bc_profile_enable(bc_graph_t g, int32_t on);
 
 /* Copy the accumulated totals to *out; with reset != 0, clear them. */
 bc_status bc_profile_read(bc_graph_t g, bc_profile *out, int32_t reset);
+
+/*
+ * Autotuner (the choices the library makes for BC_MODE_AUTO).  Times, on the
+ * first min(k, 64) of `sources`, the batched path at widths 64 and 32 and at
+ * several sparse_div values, and the one-source-at-a-time path on up to 4 of
+ * them; stores the fastest batched settings in the graph, together with the
+ * source count from which BC_MODE_AUTO takes the batched path (the batch's
+ * time over one plain source's).  Later runs on g with BC_MODE_AUTO (and
+ * batch_width / sparse_div 0) use them; results stay within the usual
+ * rounding of the settings chosen.  Runs on `stream` and waits for it.
+ *   sources  [k] host, k >= 1
+ *   out      NULL or receives the choice and the measured times
+ * Errors: BC_ERR_INVALID_ARG, BC_ERR_OUT_OF_MEMORY, BC_ERR_DEVICE (the graph's
+ * settings are unchanged).  BC_ERR_RANGE from the sample runs is not an error
+ * here.  Not to be called while other runs on g are in flight.
+ */
+typedef struct bc_tuning {
+    int32_t batch_width;        /* chosen sources per batch                          */
+    int32_t sparse_div;         /* chosen sparse_div (-1 = never)                     */
+    int32_t min_batched;        /* BC_MODE_AUTO is batched from this many sources
+                                   (INT32_MAX: never)                                 */
+    int32_t sample;             /* sources timed                                      */
+    double plain_ms_per_source; /* one-source-at-a-time path, per source              */
+    double batch_ms;            /* one batch of the sample with the chosen settings   */
+} bc_tuning;
+
+bc_status bc_autotune(bc_graph_t g, const int32_t *sources, int32_t k, void *stream,
+                      bc_tuning *out);
 
 /* Static description of a status code. */
 const char *bc_status_str(bc_status s);

@@ -62,9 +62,11 @@ def _stream_handle(stream):
     return ctypes.c_void_p(stream.cuda_stream)
 
 
-def make_options(mode: int = BC_MODE_AUTO, batch_width: int = 0, level_chunk: int = 0):
+def make_options(mode: int = BC_MODE_AUTO, batch_width: int = 0, level_chunk: int = 0,
+                 sparse_div: int = 0):
     o = bc_options()
     o.mode, o.batch_width, o.level_chunk = int(mode), int(batch_width), int(level_chunk)
+    o.sparse_div = int(sparse_div)
     return o
 
 
@@ -174,6 +176,18 @@ def bc_run_detail(g: int, sources, options=None, want_dist: bool = True,
     return bc, dist, sigma
 
 
+def bc_autotune(g: int, sources, stream=None) -> dict:
+    """Time the library's execution settings on a sample of `sources` and keep
+    the fastest for BC_MODE_AUTO on this graph; returns the choice."""
+    src = _i32(sources)
+    t = _capi.bc_tuning()
+    _check(_capi.load().bc_autotune(ctypes.c_void_p(g), _ptr(src, ctypes.c_int32), int(src.size),
+                                    _stream_handle(stream), ctypes.byref(t)), "bc_autotune")
+    return {"batch_width": t.batch_width, "sparse_div": t.sparse_div,
+            "min_batched": t.min_batched, "sample": t.sample,
+            "plain_ms_per_source": t.plain_ms_per_source, "batch_ms": t.batch_ms}
+
+
 def bc_workspace_bytes(g: int, k: int, options=None) -> int:
     out = ctypes.c_size_t()
     opt = ctypes.byref(options) if options is not None else None
@@ -241,6 +255,9 @@ class Graph:
 
     def run_detail(self, sources, options=None, want_dist=True, want_sigma=True):
         return bc_run_detail(self.handle, sources, options, want_dist, want_sigma)
+
+    def autotune(self, sources, stream=None) -> dict:
+        return bc_autotune(self.handle, sources, stream)
 
     def workspace_bytes(self, k: int, options=None) -> int:
         return bc_workspace_bytes(self.handle, k, options)

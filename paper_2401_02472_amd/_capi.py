@@ -32,7 +32,7 @@ BC_MODE_BATCHED = 2
 
 EXPORTED = ("bc_create_graph", "bc_destroy_graph", "bc_graph_info", "bc_run", "bc_run_async",
             "bc_run_multi", "bc_single_source", "bc_run_detail", "bc_workspace_bytes", "bc_trim_workspaces",
-            "bc_profile_enable", "bc_profile_read", "bc_status_str")
+            "bc_profile_enable", "bc_profile_read", "bc_autotune", "bc_status_str")
 
 BC_PROF_FORWARD = 0
 BC_PROF_COMPACT = 1
@@ -44,7 +44,14 @@ PROF_CLASS_NAMES = ("forward", "compact", "reverse", "finish")
 
 class bc_options(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("batch_width", ctypes.c_int32),
-                ("level_chunk", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
+                ("level_chunk", ctypes.c_int32), ("sparse_div", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 4)]
+
+
+class bc_tuning(ctypes.Structure):
+    _fields_ = [("batch_width", ctypes.c_int32), ("sparse_div", ctypes.c_int32),
+                ("min_batched", ctypes.c_int32), ("sample", ctypes.c_int32),
+                ("plain_ms_per_source", ctypes.c_double), ("batch_ms", ctypes.c_double)]
 
 
 class bc_profile(ctypes.Structure):
@@ -88,6 +95,7 @@ def load():
             "bc_trim_workspaces": [vp],
             "bc_profile_enable": [vp, ctypes.c_int32],
             "bc_profile_read": [vp, ctypes.POINTER(bc_profile), ctypes.c_int32],
+            "bc_autotune": [vp, i32p, ctypes.c_int32, vp, ctypes.POINTER(bc_tuning)],
         }
         for name, args in sig.items():
             fn = getattr(lib, name)

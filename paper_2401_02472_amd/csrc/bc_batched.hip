@@ -163,9 +163,30 @@ __device__ __forceinline__ uint64_t probe_chunk(const BatchDev &d, int32_t first
 
 // ---- forward ---------------------------------------------------------------
 
+// Size of the next frontier (vertices and arcs), counted per lane and added
+// to the level's counters once per wavefront at the end of a kernel.
+struct Front {
+    uint32_t cnt = 0;
+    unsigned long long arcs = 0;
+};
+
+__device__ void report_front(const BatchDev &d, int32_t L, const Front &fr) {
+    unsigned long long c = fr.cnt, a = fr.arcs;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        c += __shfl_xor(c, off);
+        a += __shfl_xor(a, off);
+    }
+    if (lane_id() == 0 && c) {
+        const int nx = (L + 1) & 1;
+        atomicAdd((uint32_t *)&d.ctrl[kCtlQCount + nx], (uint32_t)c);
+        atomicAdd((unsigned long long *)&d.ctrl[kCtlQArcs + 2 * nx], a);
+    }
+}
+
 // Chunk item of a vertex of degree > 64.
 __device__ void fwd_chunk(const BatchDev &d, int32_t L, uint32_t item, uint64_t full,
-                          uint64_t *found, Work &wk) {
+                          uint64_t *found, Work &wk, Front &fr) {
     const int lane = lane_id();
     const int2 info = d.item_info[item];
     const int32_t w = info.x, j = info.y;
@@ -187,7 +208,7 @@ __device__ void fwd_chunk(const BatchDev &d, int32_t L, uint32_t item, uint64_t 
     if (!multi) {
         if (mine) {
             d.sigma[(size_t)w * kWave + lane] = acc;
-            if (!isfinite(acc)) atomicOr(&d.ctrl[1], 1);
+            if (!isfinite(acc)) atomicOr(&d.ctrl[kCtlRange], 1);
         }
         if (lane == 0) {
             FN[w] = nw;
@@ -196,6 +217,10 @@ __device__ void fwd_chunk(const BatchDev &d, int32_t L, uint32_t item, uint64_t 
                 atomicOr((unsigned long long *)found, 1ull);
             }
         }
+        if (lane == 0 && nw) {
+            ++fr.cnt;
+            fr.arcs += (unsigned long long)(re - rs);
+        }
     } else if (nw) {
         // integer sums: the atomic adds are exact in any order
         if (mine) unsafeAtomicAdd(&d.sigma[(size_t)w * kWave + lane], acc);
@@ -203,18 +228,26 @@ __device__ void fwd_chunk(const BatchDev &d, int32_t L, uint32_t item, uint64_t 
     }
 }
 
-// Group item: vertices base .. base+63 (all of degree <= 64).
-__device__ void fwd_group(const BatchDev &d, int32_t L, int32_t base, uint64_t full,
-                          uint64_t *found, Work &wk) {
+// Group item: 64 vertices, either base .. base+63 (dense step: all of degree
+// <= 64, F_{L+1} written for every one) or list[base .. base+63] (sparse step:
+// candidates of any degree, F_{L+1} cleared beforehand).  The wave flattens
+// the arcs of the vertices that still have unvisited lanes into runs of 64.
+__device__ void fwd_group(const BatchDev &d, int32_t L, int32_t base, const int32_t *list,
+                          int32_t count, uint64_t full, uint64_t *found, Work &wk, Front &fr) {
     const int lane = lane_id();
     const uint64_t *FL = d.F + (size_t)L * (size_t)d.n;
     uint64_t *FN = d.F + (size_t)(L + 1) * (size_t)d.n;
-    const int32_t me = base + lane;
+    int32_t me = -1;
+    if (list) {
+        if (base + lane < count) me = list[base + lane];
+    } else if (base + lane < d.n) {
+        me = base + lane;
+    }
     uint64_t vis = full;
     int32_t rs = 0, cnt = 0;
-    if (me < d.n) {
+    if (me >= 0) {
         vis = d.vis[me];
-        FN[me] = 0ull;
+        if (!list) FN[me] = 0ull;
         if (vis != full) {
             rs = d.row_ptr[me];
             cnt = d.row_ptr[me + 1] - rs;
@@ -229,16 +262,19 @@ __device__ void fwd_group(const BatchDev &d, int32_t L, int32_t base, uint64_t f
     uint64_t any_found = 0;
     auto flush = [&]() {
         if (cur >= 0 && nw) {
-            const int32_t w = base + cur;
-            const uint64_t w_vis = ~shfl64(unvis, cur) & full;  // all lanes active here
+            const int32_t w = __shfl(me, cur);                   // all lanes active here
+            const uint64_t w_vis = ~shfl64(unvis, cur) & full;
+            const int32_t w_deg = __shfl(cnt, cur);
             if ((nw >> lane) & 1ull) {
                 d.sigma[(size_t)w * kWave + lane] = acc;
-                if (!isfinite(acc)) atomicOr(&d.ctrl[1], 1);
+                if (!isfinite(acc)) atomicOr(&d.ctrl[kCtlRange], 1);
                 ++wk.owners;
             }
             if (lane == 0) {
                 FN[w] = nw;
                 d.vis[w] = w_vis | nw;
+                ++fr.cnt;
+                fr.arcs += (unsigned long long)w_deg;
             }
             any_found |= nw;
         }
@@ -279,18 +315,22 @@ __device__ void fwd_group(const BatchDev &d, int32_t L, int32_t base, uint64_t f
 }
 
 __global__ __launch_bounds__(kBlock) void k_batch_forward(BatchDev d, int32_t L, uint64_t full) {
-    // nothing past the deepest level found so far (F_L is empty), or no room
-    if (L > d.ctrl[0] || L + 1 >= d.lcap) return;
-    uint64_t *found = (uint64_t *)&d.ctrl[4];
+    // nothing past the deepest level found so far (F_L is empty), no room, or
+    // this level takes the sparse step
+    if (L > d.ctrl[kCtlDeepest] || L + 1 >= d.lcap || d.ctrl[kCtlMode]) return;
+    uint64_t *found = (uint64_t *)&d.ctrl[kCtlFound];
     const uint32_t items = d.items;
     const uint32_t groups = (uint32_t)((d.n - d.big_end + kWave - 1) / kWave);
     const uint32_t wave = (blockIdx.x * kBlock + threadIdx.x) / kWave;
     const uint32_t nwaves = gridDim.x * kWavesPerBlock;
     Work wk;
+    Front fr;
     for (uint32_t it = wave; it < items + groups; it += nwaves) {
-        if (it < items) fwd_chunk(d, L, it, full, found, wk);
-        else fwd_group(d, L, d.big_end + (int32_t)(it - items) * kWave, full, found, wk);
+        if (it < items) fwd_chunk(d, L, it, full, found, wk, fr);
+        else fwd_group(d, L, d.big_end + (int32_t)(it - items) * kWave, nullptr, 0, full, found,
+                       wk, fr);
     }
+    report_front(d, L, fr);
     if (d.stats) report_work(d.stats, wk);
 }
 
@@ -298,9 +338,10 @@ __global__ __launch_bounds__(kBlock) void k_batch_forward(BatchDev d, int32_t L,
 // (or the truncation when the level array is full), clears the flag.
 __global__ __launch_bounds__(kBlock) void k_batch_forward_finish(BatchDev d, int32_t L,
                                                                  uint64_t full) {
-    if (L > d.ctrl[0] || L + 1 >= d.lcap) return;
+    if (L > d.ctrl[kCtlDeepest] || L + 1 >= d.lcap) return;
     uint64_t *FN = d.F + (size_t)(L + 1) * (size_t)d.n;
-    uint64_t *found = (uint64_t *)&d.ctrl[4];
+    uint64_t *found = (uint64_t *)&d.ctrl[kCtlFound];
+    Front fr;
     const int lane = lane_id();
     const int32_t wave = (blockIdx.x * kBlock + threadIdx.x) / kWave;
     const int32_t nwaves = gridDim.x * kWavesPerBlock;
@@ -309,25 +350,164 @@ __global__ __launch_bounds__(kBlock) void k_batch_forward_finish(BatchDev d, int
         if (lane == 0) FN[w] = nw;
         if (nw == 0ull) continue;
         if ((nw >> lane) & 1ull) {
-            if (!isfinite(d.sigma[(size_t)w * kWave + lane])) atomicOr(&d.ctrl[1], 1);
+            if (!isfinite(d.sigma[(size_t)w * kWave + lane])) atomicOr(&d.ctrl[kCtlRange], 1);
         }
         if (lane == 0) {
             d.vis[w] |= nw;
             d.reach[w] = 0ull;
             atomicOr((unsigned long long *)found, 1ull);
+            ++fr.cnt;
+            fr.arcs += (unsigned long long)(d.row_ptr[w + 1] - d.row_ptr[w]);
         }
     }
+    report_front(d, L, fr);
     (void)full;
 }
 
-// Depth bookkeeping between iterations (one thread).
+// Bookkeeping between iterations (one thread): depth (or truncation when the
+// level array is full), the step the next iteration takes (sparse when the
+// new frontier has few arcs), and the counters of the lists.
 __global__ void k_batch_level_done(BatchDev d, int32_t L) {
-    uint64_t *found = (uint64_t *)&d.ctrl[4];
+    uint64_t *found = (uint64_t *)&d.ctrl[kCtlFound];
     if (*found) {
-        d.ctrl[0] = L + 1;
-        if (L + 2 >= d.lcap) d.ctrl[2] = 1;  // level L+2 would not fit: run again with room
+        d.ctrl[kCtlDeepest] = L + 1;
+        if (L + 2 >= d.lcap) d.ctrl[kCtlTrunc] = 1;  // level L+2 would not fit
     }
     *found = 0ull;
+    const int nx = (L + 1) & 1, cur = L & 1;
+    const unsigned long long arcs = *(unsigned long long *)&d.ctrl[kCtlQArcs + 2 * nx];
+    d.ctrl[kCtlMode] = (int64_t)arcs < d.sparse_arcs ? 1 : 0;
+    // the list of level L is consumed: it receives level L+2
+    d.ctrl[kCtlQCount + cur] = 0;
+    *(unsigned long long *)&d.ctrl[kCtlQArcs + 2 * cur] = 0ull;
+    d.ctrl[kCtlCand] = 0;
+    d.ctrl[kCtlItems] = 0;
+}
+
+// ---- sparse forward step ------------------------------------------------------
+
+// Mark every neighbour of the level-L frontier (the vertices with F_L != 0,
+// found by scanning F_L 64 vertices per wave; their arcs 8 per lane per
+// round).  Marks are idempotent byte stores.
+__global__ __launch_bounds__(kBlock) void k_batch_sparse_mark(BatchDev d, int32_t L) {
+    if (L > d.ctrl[kCtlDeepest] || L + 1 >= d.lcap || !d.ctrl[kCtlMode]) return;
+    const int lane = lane_id();
+    const uint64_t *FL = d.F + (size_t)L * (size_t)d.n;
+    const int32_t groups = (d.n + kWave - 1) / kWave;
+    const int32_t wave = (blockIdx.x * kBlock + threadIdx.x) / kWave;
+    const int32_t nwaves = gridDim.x * kWavesPerBlock;
+    for (int32_t gi = wave; gi < groups; gi += nwaves) {
+        const int32_t me = gi * kWave + lane;
+        const bool on = me < d.n && FL[me] != 0ull;
+        uint64_t todo = __ballot(on);
+        while (todo) {
+            const int t = __ffsll((unsigned long long)todo) - 1;
+            todo &= todo - 1;
+            const int32_t v = gi * kWave + t;
+            const int32_t rs = d.row_ptr[v], re = d.row_ptr[v + 1];
+            for (int32_t cb = rs; cb < re; cb += kProbe * kWave) {
+                int32_t nb[kProbe];
+#pragma unroll
+                for (int u = 0; u < kProbe; ++u) {
+                    const int32_t e = cb + u * kWave + lane;
+                    nb[u] = e < re ? d.col_idx[e] : -1;
+                }
+#pragma unroll
+                for (int u = 0; u < kProbe; ++u)
+                    if (nb[u] >= 0) d.cand[nb[u]] = 1;
+            }
+        }
+    }
+}
+
+// Turn the marks into the candidate lists (one thread per 16 vertices), clear
+// them, and clear F_{L+1} (the sparse pull writes only the candidates').
+__global__ __launch_bounds__(kBlock) void k_batch_sparse_compact(BatchDev d, int32_t L,
+                                                                 uint64_t full) {
+    if (L > d.ctrl[kCtlDeepest] || L + 1 >= d.lcap || !d.ctrl[kCtlMode]) return;
+    const int lane = lane_id();
+    uint64_t *FN = d.F + (size_t)(L + 1) * (size_t)d.n;
+    const int32_t groups = (d.n + 15) >> 4;
+    const int32_t stride = gridDim.x * kBlock;
+    const int32_t base0 = blockIdx.x * kBlock + (threadIdx.x & ~(kWave - 1));
+    for (int32_t wb = base0; wb < groups; wb += stride) {
+        const int32_t i = wb + lane;
+        uint4 m = make_uint4(0u, 0u, 0u, 0u);
+        if (i < groups) {
+            m = reinterpret_cast<const uint4 *>(d.cand)[i];
+#pragma unroll
+            for (int j = 0; j < 16; ++j)
+                if ((i << 4) + j < d.n) FN[(i << 4) + j] = 0ull;
+        }
+        const bool any = (m.x | m.y | m.z | m.w) != 0u;
+        if (__ballot(any) == 0ull) continue;
+        uint32_t bits = 0;
+        {
+            const uint32_t wv[4] = {m.x, m.y, m.z, m.w};
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int b = 0; b < 4; ++b)
+                    if ((wv[q] >> (8 * b)) & 0xffu) bits |= 1u << (4 * q + b);
+        }
+        if (bits) reinterpret_cast<uint4 *>(d.cand)[i] = make_uint4(0u, 0u, 0u, 0u);
+        // vertices visited from every source have nothing to discover
+#pragma unroll
+        for (int j = 0; j < 16; ++j)
+            if (((bits >> j) & 1u) && d.vis[(i << 4) + j] == full) bits &= ~(1u << j);
+        // vertices of degree <= 64 go to the candidate list; larger ones
+        // contribute their chunk items to the item list
+        uint32_t nsmall = 0, nitems = 0;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            if (!((bits >> j) & 1u)) continue;
+            const int32_t v = (i << 4) + j;
+            if (v < d.big_end) nitems += d.item_first[v + 1] - d.item_first[v];
+            else ++nsmall;
+        }
+        uint32_t tot, toti;
+        const uint32_t off = wave_excl_scan(nsmall, tot);
+        const uint32_t offi = wave_excl_scan(nitems, toti);
+        uint32_t base = 0, basei = 0;
+        if (lane == 0) {
+            if (tot) base = atomicAdd((uint32_t *)&d.ctrl[kCtlCand], tot);
+            if (toti) basei = atomicAdd((uint32_t *)&d.ctrl[kCtlItems], toti);
+        }
+        base = __shfl(base, 0);
+        basei = __shfl(basei, 0);
+        uint32_t p = base + off, pi = basei + offi;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            if (!((bits >> j) & 1u)) continue;
+            const int32_t v = (i << 4) + j;
+            if (v < d.big_end) {
+                for (uint32_t it = d.item_first[v]; it < d.item_first[v + 1]; ++it)
+                    d.ilist[pi++] = it;
+            } else {
+                d.clist[p++] = v;
+            }
+        }
+    }
+}
+
+// Pull over the candidates only (groups of 64 list entries).
+__global__ __launch_bounds__(kBlock) void k_batch_sparse_pull(BatchDev d, int32_t L,
+                                                              uint64_t full) {
+    if (L > d.ctrl[kCtlDeepest] || L + 1 >= d.lcap || !d.ctrl[kCtlMode]) return;
+    uint64_t *found = (uint64_t *)&d.ctrl[kCtlFound];
+    const int32_t c = d.ctrl[kCtlCand];
+    const int32_t ni = d.ctrl[kCtlItems];
+    const int32_t groups = (c + kWave - 1) / kWave;
+    const int32_t wave = (blockIdx.x * kBlock + threadIdx.x) / kWave;
+    const int32_t nwaves = gridDim.x * kWavesPerBlock;
+    Work wk;
+    Front fr;
+    for (int32_t it = wave; it < ni + groups; it += nwaves) {
+        if (it < ni) fwd_chunk(d, L, (uint32_t)d.ilist[it], full, found, wk, fr);
+        else fwd_group(d, L, (it - ni) * kWave, d.clist, c, full, found, wk, fr);
+    }
+    report_front(d, L, fr);
+    if (d.stats) report_work(d.stats, wk);
 }
 
 // ---- reverse ---------------------------------------------------------------
@@ -519,19 +699,33 @@ __global__ void k_batch_clear(BatchDev d) {
         d.F[i] = 0ull;
     }
     for (int32_t i = tid; i < d.multi_end; i += stride) d.reach[i] = 0ull;
+    const int32_t groups = (d.n + 15) >> 4;
+    for (int32_t i = tid; i < groups; i += stride)
+        reinterpret_cast<uint4 *>(d.cand)[i] = make_uint4(0u, 0u, 0u, 0u);
     const int64_t rows = (int64_t)d.multi_end * kWave;
     for (int64_t i = tid; i < rows; i += stride) d.sigma[i] = 0.0;
-    if (blockIdx.x == 0 && threadIdx.x < 8) d.ctrl[threadIdx.x] = 0;
+    if (blockIdx.x == 0 && threadIdx.x < kCtlInts) d.ctrl[threadIdx.x] = 0;
 }
 
+// Seed lane s with its source; the first iteration's step is chosen from the
+// distinct sources' arc count.
 __global__ void k_batch_seed(BatchDev d, const int32_t *src, int32_t nlanes) {
     const int lane = threadIdx.x;
+    int32_t s = -1;
+    bool first = false;
     if (lane < nlanes) {
-        const int32_t s = src[lane];
+        s = src[lane];
         atomicOr((unsigned long long *)&d.vis[s], 1ull << lane);
-        atomicOr((unsigned long long *)&d.F[s], 1ull << lane);
+        const unsigned long long old =
+            atomicOr((unsigned long long *)&d.F[s], 1ull << lane);
+        first = old == 0ull;  // exactly one lane per distinct source
         d.sigma[(size_t)s * kWave + lane] = 1.0;
     }
+    const int32_t deg = first ? d.row_ptr[s + 1] - d.row_ptr[s] : 0;
+    unsigned long long arcs = (unsigned long long)deg;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) arcs += __shfl_xor(arcs, off);
+    if (lane == 0) d.ctrl[kCtlMode] = (int64_t)arcs < d.sparse_arcs ? 1 : 0;
 }
 
 // dist[s][v] and sigma[s][v] of lane s (internal vertex order), s < nlanes.
@@ -575,9 +769,21 @@ hipError_t batch_start(const BatchDev &d, const int32_t *src_dev, int32_t nlanes
 }
 
 hipError_t batch_forward(const BatchDev &d, int32_t level, uint64_t full, hipStream_t stream) {
+    // both steps are launched; each returns at once unless the mode chosen on
+    // the device for this level is its own
     const int64_t groups = (d.n - d.big_end + kWave - 1) / kWave;
     hipLaunchKernelGGL(k_batch_forward, dim3(grid_of(d.items + groups)), dim3(kBlock), 0, stream,
                        d, level, full);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_batch_sparse_mark, dim3(2048), dim3(kBlock), 0, stream, d, level);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_batch_sparse_compact, dim3(grid_of(((d.n + 15) / 16 + kWave - 1) / kWave)),
+                       dim3(kBlock), 0, stream, d, level, full);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_batch_sparse_pull, dim3(2048), dim3(kBlock), 0, stream, d, level, full);
     return hipGetLastError();
 }
 

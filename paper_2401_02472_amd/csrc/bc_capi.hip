@@ -6,6 +6,8 @@
 // host-device transfer analysis); here too the CSR stays resident in a
 // bc_graph_t and only BC (plus debug state on request) comes back.
 #include <algorithm>
+#include <climits>
+#include <cmath>
 #include <atomic>
 #include <cstring>
 #include <mutex>
@@ -141,6 +143,11 @@ struct bc_graph_s {
     std::vector<BatchWS *> batch_pool;
     std::atomic<int32_t> depth_hint{16};  // levels launched per source without polling
     std::atomic<int32_t> batch_depth_hint{16};  // levels of the last batched run
+    // settings for BC_MODE_AUTO and zero option fields (bc_autotune stores its
+    // choice here)
+    std::atomic<int32_t> tuned_width{kWave};
+    std::atomic<int32_t> tuned_sparse_div{kDefaultSparseDiv};
+    std::atomic<int32_t> tuned_min_batched{16};
     // hop distances (internal order, -1 unreached) from two landmarks: the
     // highest-degree vertex and the vertex farthest from it; batches are formed
     // from sources sorted by them
@@ -490,7 +497,7 @@ struct ExportAlloc {
     }
 };
 
-constexpr int kBatchCtrlInts = 8;
+constexpr int kBatchCtrlInts = kCtlInts;
 
 size_t batch_ws_bytes(const bc_graph_s *g) {
     const size_t n = (size_t)std::max<int32_t>(g->n, 1);
@@ -502,6 +509,9 @@ size_t batch_ws_bytes(const bc_graph_s *g) {
     b += align_up((size_t)std::max(g->multi_end, 1) * sizeof(uint64_t));  // reach
     b += align_up((size_t)std::max<uint32_t>(g->items, 1) * kWave * sizeof(double));  // partial
     b += align_up(12 * sizeof(unsigned long long));     // work counters
+    b += align_up(n * sizeof(int32_t));                  // candidate list
+    b += align_up((size_t)std::max<uint32_t>(g->items, 1) * sizeof(int32_t));  // item list
+    b += align_up(((n + 15) / 16) * 16);                 // candidate marks
     return b;
 }
 
@@ -561,6 +571,11 @@ bc_status batch_ws_create(bc_graph_s *g, BatchWS **out) {
     d.item_first = g->d_item_first;
     ws->d_stats = (unsigned long long *)take(12 * sizeof(unsigned long long));
     d.stats = nullptr;
+    d.clist = (int32_t *)take(n * sizeof(int32_t));
+    d.ilist = (int32_t *)take((size_t)std::max<uint32_t>(g->items, 1) * sizeof(int32_t));
+    d.cand = (uint8_t *)take(((n + 15) / 16) * 16);
+    d.nnz = g->nnz;
+    d.sparse_arcs = g->nnz / kDefaultSparseDiv;
     d.F = nullptr;
     d.lcap = 0;
     *out = ws;
@@ -669,7 +684,7 @@ bc_status run_batch_plan(bc_graph_s *g, const std::vector<int32_t> &s_int,
                          const std::vector<int32_t> &seg_start,  // per segment table: nseg+1
                          const std::vector<double *> &seg_out, double *bc_out,
                          hipStream_t stream, const int32_t *export_row, int32_t *dist,
-                         double *sigma) {
+                         double *sigma, int32_t sparse_div) {
     BatchWS *ws = nullptr;
     bc_status st = batch_acquire(g, stream, &ws);
     if (st != BC_OK) return st;
@@ -683,6 +698,8 @@ bc_status run_batch_plan(bc_graph_s *g, const std::vector<int32_t> &s_int,
     ws->dev.stats = prof ? ws->d_stats : nullptr;
     ws->timer.on = prof;
     ws->timer.used = 0;
+    // frontier arcs below which a level takes the sparse step (0: never)
+    ws->dev.sparse_arcs = sparse_div < 0 ? 0 : g->nnz / std::max(sparse_div, 1);
     if (prof) {
         hipError_t ez = hipMemsetAsync(ws->d_stats, 0, 12 * sizeof(unsigned long long), stream);
         if (ez != hipSuccess) return fail(from_hip(ez));
@@ -813,7 +830,8 @@ bc_status run_batch_plan(bc_graph_s *g, const std::vector<int32_t> &s_int,
 // BC over the sources with up to `width` sources per batch.  With dist /
 // sigma (device, caller order, [k][n]), the per-source state is exported too.
 bc_status batched_run(bc_graph_s *g, const int32_t *sources, int32_t k, double *bc_out,
-                      int32_t width, hipStream_t stream, int32_t *dist, double *sigma) {
+                      int32_t width, int32_t sparse_div, hipStream_t stream, int32_t *dist,
+                      double *sigma) {
     // Batch composition: sources sorted by their distances to the two
     // landmarks, so that the 64 sources of a batch lie close together and see
     // most vertices at the same level (their frontier masks share lanes, the
@@ -837,7 +855,8 @@ bc_status batched_run(bc_graph_s *g, const int32_t *sources, int32_t k, double *
     for (int32_t i = 0; i < k; ++i) s_int[(size_t)i] = g->h_perm[(size_t)sources[order[(size_t)i]]];
     std::vector<BatchPlan> plan;
     for (int32_t b0 = 0; b0 < k; b0 += width) plan.push_back({b0, std::min(width, k - b0), 0, 0});
-    return run_batch_plan(g, s_int, plan, {}, {}, bc_out, stream, order.data(), dist, sigma);
+    return run_batch_plan(g, s_int, plan, {}, {}, bc_out, stream, order.data(), dist, sigma,
+                          sparse_div);
 }
 
 // Several requests in one run.  A request of at most 64 sources never
@@ -890,20 +909,24 @@ bc_status multi_run(bc_graph_s *g, const int32_t *sources, const int32_t *req_st
         if (e != hipSuccess) return from_hip(e);
     }
     return run_batch_plan(g, s_int, plan, seg_start, seg_out, nullptr, stream, nullptr, nullptr,
-                          nullptr);
+                          nullptr, g->tuned_sparse_div.load());
 }
 
-// Mode selection: BC_MODE_AUTO picks the batched path when there are enough
-// sources to fill a batch reasonably.
-bool use_batched(const bc_options *opt, int32_t k) {
+// Mode selection: BC_MODE_AUTO picks the batched path from the graph's
+// crossover source count on (16 until bc_autotune measures it).
+bool use_batched(const bc_graph_s *g, const bc_options *opt, int32_t k) {
     const int32_t mode = opt ? opt->mode : BC_MODE_AUTO;
     if (mode == BC_MODE_BATCHED) return true;
     if (mode == BC_MODE_PLAIN) return false;
-    return k >= 16;
+    return k >= g->tuned_min_batched.load();
 }
 
-int32_t batch_width_of(const bc_options *opt) {
-    return (opt && opt->batch_width > 0) ? opt->batch_width : kWave;
+int32_t batch_width_of(const bc_graph_s *g, const bc_options *opt) {
+    return (opt && opt->batch_width > 0) ? opt->batch_width : g->tuned_width.load();
+}
+
+int32_t sparse_div_of(const bc_graph_s *g, const bc_options *opt) {
+    return (opt && opt->sparse_div != 0) ? opt->sparse_div : g->tuned_sparse_div.load();
 }
 
 bc_status check_options(const bc_options *opt) {
@@ -911,7 +934,8 @@ bc_status check_options(const bc_options *opt) {
     if (opt->mode < BC_MODE_AUTO || opt->mode > BC_MODE_BATCHED) return BC_ERR_INVALID_ARG;
     if (opt->batch_width < 0 || opt->batch_width > 64) return BC_ERR_INVALID_ARG;
     if (opt->level_chunk < 0 || opt->level_chunk > 1024) return BC_ERR_INVALID_ARG;
-    for (int i = 0; i < 5; ++i)
+    if (opt->sparse_div < -1 || opt->sparse_div > (1 << 20)) return BC_ERR_INVALID_ARG;
+    for (int i = 0; i < 4; ++i)
         if (opt->reserved[i] != 0) return BC_ERR_INVALID_ARG;
     return BC_OK;
 }
@@ -1146,9 +1170,9 @@ bc_status bc_run_async(bc_graph_t g, const int32_t *sources, int32_t k, double *
     if (st != BC_OK) return st;
     if (g->n == 0) return BC_OK;
     DeviceGuard dg(g->device);
-    if (use_batched(opt, k))
-        return batched_run(g, sources, k, bc_out_dev, batch_width_of(opt), (hipStream_t)stream,
-                           nullptr, nullptr);
+    if (use_batched(g, opt, k))
+        return batched_run(g, sources, k, bc_out_dev, batch_width_of(g, opt),
+                           sparse_div_of(g, opt), (hipStream_t)stream, nullptr, nullptr);
     return plain_run(g, sources, k, bc_out_dev, opt, (hipStream_t)stream, nullptr, nullptr);
 }
 
@@ -1160,8 +1184,9 @@ bc_status bc_run(bc_graph_t g, const int32_t *sources, int32_t k, double *bc_out
     DeviceGuard dg(g->device);
     double *d_bc = nullptr;
     BC_TRY_HIP(hipMalloc(&d_bc, (size_t)g->n * sizeof(double)));
-    st = use_batched(nullptr, k)
-             ? batched_run(g, sources, k, d_bc, kWave, nullptr, nullptr, nullptr)
+    st = use_batched(g, nullptr, k)
+             ? batched_run(g, sources, k, d_bc, batch_width_of(g, nullptr),
+                           sparse_div_of(g, nullptr), nullptr, nullptr, nullptr)
              : plain_run(g, sources, k, d_bc, nullptr, nullptr, nullptr, nullptr);
     if (st == BC_OK || st == BC_ERR_RANGE) {
         hipError_t e = hipMemcpy(bc_out, d_bc, (size_t)g->n * sizeof(double),
@@ -1208,7 +1233,8 @@ bc_status bc_run_detail(bc_graph_t g, const int32_t *sources, int32_t k, const b
         return from_hip(e);
     }
     if (batched)
-        st = batched_run(g, sources, k, d_bc, batch_width_of(opt), nullptr, d_dist, d_sigma);
+        st = batched_run(g, sources, k, d_bc, batch_width_of(g, opt), sparse_div_of(g, opt),
+                         nullptr, d_dist, d_sigma);
     else
         st = plain_run(g, sources, k, d_bc, opt, nullptr, (dist || sigma) ? exp.data() : nullptr,
                        &tmp.t);
@@ -1283,7 +1309,7 @@ bc_status bc_workspace_bytes(bc_graph_t g, int32_t k, const bc_options *opt, siz
     if (!g || !bytes || k < 0) return BC_ERR_INVALID_ARG;
     bc_status st = check_options(opt);
     if (st != BC_OK) return st;
-    if (use_batched(opt, k))
+    if (use_batched(g, opt, k))
         *bytes = batch_ws_bytes(g) +
                  batch_level_bytes(g, std::max(16, g->batch_depth_hint.load() + 8));
     else
@@ -1321,6 +1347,106 @@ bc_status bc_trim_workspaces(bc_graph_t g) {
     }
     for (PlainWS *ws : idle) plain_ws_destroy(ws);
     for (BatchWS *ws : idle_b) batch_ws_destroy(ws);
+    return BC_OK;
+}
+
+bc_status bc_autotune(bc_graph_t g, const int32_t *sources, int32_t k, void *stream_,
+                      bc_tuning *out) {
+    if (!g || k < 1) return BC_ERR_INVALID_ARG;
+    bc_status st = check_sources(g, sources, k);
+    if (st != BC_OK) return st;
+    const int32_t m = std::min(k, kWave);
+    bc_tuning t{};
+    t.batch_width = g->tuned_width.load();
+    t.sparse_div = g->tuned_sparse_div.load();
+    t.min_batched = g->tuned_min_batched.load();
+    t.sample = m;
+    if (g->n == 0) {
+        if (out) *out = t;
+        return BC_OK;
+    }
+    DeviceGuard dg(g->device);
+    const hipStream_t stream = (hipStream_t)stream_;
+    double *d_bc = nullptr;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    hipError_t e = hipMalloc(&d_bc, (size_t)g->n * sizeof(double));
+    if (e == hipSuccess) e = hipEventCreate(&ev[0]);
+    if (e == hipSuccess) e = hipEventCreate(&ev[1]);
+    auto cleanup = [&]() {
+        if (d_bc) (void)hipFree(d_bc);
+        if (ev[0]) (void)hipEventDestroy(ev[0]);
+        if (ev[1]) (void)hipEventDestroy(ev[1]);
+    };
+    if (e != hipSuccess) {
+        cleanup();
+        return from_hip(e);
+    }
+    // best of two runs (the first also sets up workspaces, landmarks and the
+    // depth hints)
+    auto timed = [&](auto &&run, double &ms) -> bc_status {
+        ms = 1e30;
+        for (int rep = 0; rep < 2; ++rep) {
+            hipError_t e2 = hipEventRecord(ev[0], stream);
+            if (e2 != hipSuccess) return from_hip(e2);
+            bc_status s2 = run();
+            if (s2 != BC_OK && s2 != BC_ERR_RANGE) return s2;
+            e2 = hipEventRecord(ev[1], stream);
+            if (e2 == hipSuccess) e2 = hipEventSynchronize(ev[1]);
+            float f = 0.f;
+            if (e2 == hipSuccess) e2 = hipEventElapsedTime(&f, ev[0], ev[1]);
+            if (e2 != hipSuccess) return from_hip(e2);
+            ms = std::min(ms, (double)f);
+        }
+        return BC_OK;
+    };
+    auto batched = [&](int32_t width, int32_t div, double &ms) {
+        return timed([&]() { return batched_run(g, sources, m, d_bc, width, div, stream,
+                                                nullptr, nullptr); }, ms);
+    };
+    // sparse-step threshold at width 64, then width 32 with the best threshold
+    const int32_t divs[] = {-1, 16, 64, 256};
+    double best_ms = 1e30;
+    int32_t best_div = kDefaultSparseDiv, best_width = kWave;
+    for (int32_t div : divs) {
+        double ms = 0;
+        st = batched(kWave, div, ms);
+        if (st != BC_OK) break;
+        if (ms < best_ms) {
+            best_ms = ms;
+            best_div = div;
+        }
+    }
+    if (st == BC_OK && m > 32) {
+        double ms = 0;
+        st = batched(32, best_div, ms);
+        if (st == BC_OK && ms < best_ms) {
+            best_ms = ms;
+            best_width = 32;
+        }
+    }
+    // one-source-at-a-time path on up to 4 sources
+    double plain_ms = 0;
+    const int32_t p = std::min(m, 4);
+    if (st == BC_OK)
+        st = timed([&]() { return plain_run(g, sources, p, d_bc, nullptr, stream, nullptr,
+                                            nullptr); }, plain_ms);
+    cleanup();
+    if (st != BC_OK) return st;
+    const double per_source = std::max(plain_ms / p, 1e-6);
+    // the batched path wins for a single batch once k * per_source exceeds
+    // the batch time; beyond 64 sources it wins when it won at 64
+    const double ratio = std::ceil(best_ms / per_source);
+    const int32_t min_batched = ratio > (double)kWave ? INT32_MAX
+                                                      : std::max<int32_t>(2, (int32_t)ratio);
+    g->tuned_width.store(best_width);
+    g->tuned_sparse_div.store(best_div);
+    g->tuned_min_batched.store(min_batched);
+    t.batch_width = best_width;
+    t.sparse_div = best_div;
+    t.min_batched = min_batched;
+    t.plain_ms_per_source = per_source;
+    t.batch_ms = best_ms;
+    if (out) *out = t;
     return BC_OK;
 }
 

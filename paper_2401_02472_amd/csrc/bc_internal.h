@@ -82,6 +82,9 @@ struct PlainDev {
 // arcs; of those, [0, multi_end) (degree > kChunk) span several items.
 // item_info[i] = (vertex, chunk index); item_first[v] = first item of v.
 constexpr int kChunk = 512;
+// Default threshold of the batched forward step: a level whose frontier has
+// fewer than nnz / kDefaultSparseDiv arcs expands from the frontier.
+constexpr int kDefaultSparseDiv = 64;
 
 struct BatchDev {
     int32_t n;
@@ -98,8 +101,15 @@ struct BatchDev {
     double *coef;          // [n][64] (1 + delta) / sigma; child sums while a level runs
     uint64_t *reach;       // [multi_end] sources reaching a split vertex this iteration
     double *partial;       // [items][64] reverse child sums per chunk item
-    int32_t *ctrl;         // [0] deepest level, [1] range flag, [2] truncated (level
-                           // array full), [4..5] per-iteration discovery flag (64-bit)
+    int32_t *ctrl;         // see kCtl* below
+    // sparse forward step: cand marks the neighbours of the frontier (1 byte
+    // per vertex, padded to 16); clist lists the marked vertices of degree
+    // <= 64, ilist the chunk items of the larger ones
+    uint8_t *cand;
+    int32_t *clist;
+    int32_t *ilist;
+    int64_t nnz;
+    int64_t sparse_arcs;   // a level runs sparse when its frontier has fewer arcs
     unsigned long long *stats;  // NULL, or work counters when measuring: [0..2]
                                 // forward, [6..8] reverse (owners, arcs, hits)
     double *bc;            // [n] accumulated BC (internal order), when nseg == 0
@@ -109,6 +119,20 @@ struct BatchDev {
     const int32_t *seg_start;
     double *const *seg_out;
     const int32_t *iperm;  // internal id -> caller id
+};
+
+// BatchDev::ctrl layout (int32 words).
+enum {
+    kCtlDeepest = 0,   // deepest level found
+    kCtlRange = 1,     // some sigma not finite
+    kCtlTrunc = 2,     // level array full: run the batch again with more room
+    kCtlFound = 4,     // [4..5] discovery flag of the running iteration (64-bit)
+    kCtlMode = 6,      // 1: the running iteration takes the sparse forward step
+    kCtlCand = 7,      // candidates listed by the sparse step
+    kCtlQCount = 8,    // [8..9] frontier sizes (vertices), level L & 1
+    kCtlItems = 10,    // chunk items listed by the sparse step
+    kCtlQArcs = 12,    // [12..15] frontier arc counts (64-bit), level L & 1
+    kCtlInts = 16
 };
 
 // Launchers (bc_batched.hip).  All are asynchronous on `stream`.

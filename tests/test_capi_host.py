@@ -78,7 +78,18 @@ def test_invalid_arguments_rejected():
                                ctypes.byref(out)) == bcm.BC_ERR_INVALID_ARG
     assert lib.bc_run(None, None, 0, None) == bcm.BC_ERR_INVALID_ARG
     assert lib.bc_graph_info(None, None, None, None) == bcm.BC_ERR_INVALID_ARG
+    assert lib.bc_autotune(None, None, 1, None, None) == bcm.BC_ERR_INVALID_ARG
     assert lib.bc_destroy_graph(None) == bcm.BC_OK
+
+
+def test_options_layout_matches_header():
+    # eight int32 fields: mode, batch_width, level_chunk, sparse_div, reserved[4]
+    assert ctypes.sizeof(_capi.bc_options) == 32
+    assert [f[0] for f in _capi.bc_options._fields_] == ["mode", "batch_width", "level_chunk",
+                                                        "sparse_div", "reserved"]
+    assert ctypes.sizeof(_capi.bc_tuning) == 32
+    o = bcm.make_options(bcm.BC_MODE_BATCHED, 32, 0, sparse_div=-1)
+    assert (o.mode, o.batch_width, o.sparse_div, list(o.reserved)) == (2, 32, -1, [0] * 4)
 
 
 def test_trusted_flag_skips_symmetry_only():

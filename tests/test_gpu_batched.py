@@ -7,7 +7,7 @@ import pytest
 import graphgen as gg
 import oracle
 import paper_2401_02472_amd as bcm
-from tests.gpu_checks import batched, check_bc, check_sigma, oracle_bc, plain
+from tests.gpu_checks import batched, check_bc, check_sigma, oracle_bc, plain, run_mode
 
 pytestmark = pytest.mark.gpu
 
@@ -168,3 +168,59 @@ def test_detail_rows_follow_caller_order_across_batches():
         od, osg, _, _ = oracle.single_source(g.row_ptr, g.col_idx, int(s), with_delta=False)
         assert np.array_equal(dist[i], od), f"row {i} (source {s})"
         check_sigma(sigma[i], osg)
+
+
+def test_road_grid_without_shortcuts_range():
+    """Road-like grid with no shortcuts (about 1,700 levels, the level array grows
+    several times): BC_ERR_RANGE from the batched path, with every source's
+    distances equal to the oracle's and sigma equal where it stays far from
+    overflow."""
+    g = gg.grid_road(1024, 1024, 0.05, 0.0, seed=2)
+    src = gg.sample_sources(g, 3, seed=102)
+    with bcm.Graph(g.n, g.row_ptr, g.col_idx, flags=bcm.BC_GRAPH_TRUST_SYMMETRIC) as G:
+        with pytest.raises(bcm.BCError) as ei:
+            G.run_detail(src, bcm.make_options(bcm.BC_MODE_BATCHED))
+        assert ei.value.status == bcm.BC_ERR_RANGE
+        _, dist, sigma = ei.value.result
+    for i, s in enumerate(src):
+        od, osg, _, ost = oracle.single_source(g.row_ptr, g.col_idx, int(s), with_delta=False)
+        assert ost == oracle.RANGE
+        assert np.array_equal(dist[i], od)
+        far = osg < 1e300
+        check_sigma(sigma[i][far], osg[far])
+
+
+@pytest.mark.parametrize("div", [-1, 1, 16, 64])
+@pytest.mark.parametrize("g", [gg.rmat(14, 16, seed=11), gg.grid_road(96, 96, seed=12)],
+                         ids=lambda g: g.name)
+def test_sparse_threshold_settings(g, div):
+    """Every setting of the switch between the scan-all step and the
+    frontier-driven step (never, always, and two thresholds) gives the oracle's
+    BC, and the same distances / sigma bit for bit."""
+    src = gg.sample_sources(g, 70, seed=13)
+    opt = bcm.make_options(bcm.BC_MODE_BATCHED, sparse_div=div)
+    with bcm.Graph(g.n, g.row_ptr, g.col_idx) as G:
+        check_bc(batched(G, src, sparse_div=div), oracle_bc(g, src))
+        _, dist, sigma = G.run_detail(src[:3], opt)
+    for i, s in enumerate(src[:3]):
+        od, osg, _, _ = oracle.single_source(g.row_ptr, g.col_idx, int(s), with_delta=False)
+        assert np.array_equal(dist[i], od)
+        check_sigma(sigma[i], osg)
+
+
+def test_autotune_then_auto_mode():
+    """bc_autotune stores a valid choice; BC_MODE_AUTO runs with it match the
+    oracle, on both sides of the chosen crossover."""
+    g = gg.rmat(14, 16, seed=14)
+    src = gg.sample_sources(g, 100, seed=15)
+    with bcm.Graph(g.n, g.row_ptr, g.col_idx) as G:
+        t = G.autotune(src)
+        assert t["batch_width"] in (32, 64)
+        assert t["sparse_div"] in (-1, 16, 64, 256)
+        assert t["min_batched"] >= 2
+        assert t["sample"] == 64
+        assert t["plain_ms_per_source"] > 0 and t["batch_ms"] > 0
+        for k in (3, 100):
+            want = oracle_bc(g, src[:k])
+            check_bc(G.run(src[:k]), want)
+            check_bc(run_mode(G, src[:k], bcm.BC_MODE_AUTO), want)

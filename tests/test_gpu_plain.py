@@ -164,3 +164,25 @@ def test_rmat22_sampled_full_size():
             check_sigma(sigma, osg)
         got = plain(G, src)
     check_bc(got, oracle_bc(g, src))
+
+
+def test_road_grid_without_shortcuts_range():
+    """Road-like grid with no shortcuts (about 1,700 levels): shortest-path counts
+    overflow double on part of the vertices.  The run reports BC_ERR_RANGE, and the
+    distances it still returns match the oracle's everywhere; sigma matches where
+    it stays far from overflow."""
+    g = gg.grid_road(1024, 1024, 0.05, 0.0, seed=2)
+    src = gg.sample_sources(g, 2, seed=102)
+    with bcm.Graph(g.n, g.row_ptr, g.col_idx, flags=bcm.BC_GRAPH_TRUST_SYMMETRIC) as G:
+        for s in src:
+            od, osg, _, ost = oracle.single_source(g.row_ptr, g.col_idx, int(s),
+                                                   with_delta=False)
+            assert ost == oracle.RANGE
+            assert od.max() > 1000
+            with pytest.raises(bcm.BCError) as ei:
+                G.single_source(int(s))
+            assert ei.value.status == bcm.BC_ERR_RANGE
+            dist, sigma, _ = ei.value.result
+            assert np.array_equal(dist, od)
+            far = osg < 1e300
+            check_sigma(sigma[far], osg[far])
