@@ -229,6 +229,8 @@ def main() -> int:
     ap.add_argument("--compare-plain", type=int, default=32,
                     help="also time this many sources on the one-source-at-a-time path "
                          "(0 = skip) and report the ratio")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="auto mode: keep the library's default settings")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="run one device copy of this size first (counter calibration)")
     ap.add_argument("--slots", type=int, default=4, help="serving: launches in flight")
@@ -284,13 +286,20 @@ def main() -> int:
         print(f"# calibration copy of {args.calibrate_copy_mib} MiB done", file=sys.stderr,
               flush=True)
 
+    tuning = None
+    if mode == bcm.BC_MODE_AUTO and not args.no_autotune:
+        # the library's own choice of batch width, sparse-step threshold and
+        # plain / batched crossover, timed on the first 64 sources
+        tuning = G.autotune(sources)
+        print(f"# autotune: {tuning}", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
         G.run_async(sources, out, opt)
     torch.cuda.synchronize()
     print(f"# warmup done: n={g.n} nnz={g.nnz} k={k}", file=sys.stderr, flush=True)
 
-    path = "plain" if mode == bcm.BC_MODE_PLAIN or (mode == bcm.BC_MODE_AUTO and k < 16) \
-        else "batched"
+    min_batched = tuning["min_batched"] if tuning else 16
+    path = "plain" if mode == bcm.BC_MODE_PLAIN or (mode == bcm.BC_MODE_AUTO and
+                                                   k < min_batched) else "batched"
     # the plain path's event records are sampled (every 16th source) so that
     # they do not slow the host's launch stream; the batched path records all
     G.profile_enable(16 if path == "plain" else 1)
@@ -373,7 +382,8 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": args.workload, "n": g.n, "nnz": g.nnz, "sources": k,
                    "mode": args.mode, "path": path, "batch_width": args.batch_width or
-                   (64 if path == "batched" else 1), "graph": g.params},
+                   ((tuning["batch_width"] if tuning else 64) if path == "batched" else 1),
+                   "autotune": tuning, "graph": g.params},
         "plain_comparison": plain_cmp,
         "reached_arc_gteps": round(ra / (ms_per_step / 1e3) / 1e9, 3),
         "end_to_end": end_to_end,

@@ -19,9 +19,11 @@
 //
 // Reverse iteration L: for every vertex v with F_L[v] != 0 and every neighbour
 // w, m = F_{L+1}[w] & F_L[v] are the sources for which w is a child of v; lane
-// s adds c[w][s].  A finalising pass then sets delta = sigma[v][s] * sum,
+// s adds c[w][s].  The wave owning v then sets delta = sigma[v][s] * sum,
 // c[v][s] = (1 + delta) / sigma[v][s], and adds the lanes' deltas to BC[v] in
-// lane order (v != source always holds at levels >= 1).
+// lane order (v != source always holds at levels >= 1).  Vertices split over
+// several work items, and the deepest level, are completed by a finalising
+// pass.
 //
 // Work items: a vertex of degree > 64 is split into chunks of 512 arcs (8 per
 // lane, loaded together), one wavefront per chunk; chunks of one vertex are
@@ -38,6 +40,7 @@ namespace {
 
 constexpr int kProbe = 8;    // arcs per lane probed together in a chunk item
 constexpr int kUnroll = 8;   // neighbour rows gathered concurrently
+constexpr int kRounds = 4;   // runs of 64 flattened arcs probed together in a group item
 
 __device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
 
@@ -136,6 +139,39 @@ __device__ __forceinline__ void gather_hits(uint64_t hit, int32_t nb, uint64_t m
     }
 }
 
+// Take up to kUnroll of the lanes set in `hit` (lowest first; each holds a
+// neighbour id `nb`, a lane mask `m` and an owner lane `o`) and load their
+// rows together: x[u] = val[nb_u][lane] when lane is in m_u, else 0.  The
+// owners and masks come back wave-uniform (oj[u] = -1 past the last hit), so
+// the caller can fold the values into per-owner sums in arc order.
+__device__ __forceinline__ void gather_run(uint64_t &hit, int32_t nb, uint64_t m, int o,
+                                           const double *val, double (&x)[kUnroll],
+                                           uint64_t (&mj)[kUnroll], int (&oj)[kUnroll],
+                                           Work &wk) {
+    const int lane = lane_id();
+    int32_t vj[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+        if (hit) {
+            const int j = __ffsll((unsigned long long)hit) - 1;
+            hit &= hit - 1;
+            vj[u] = __shfl(nb, j);
+            mj[u] = shfl64(m, j);
+            oj[u] = __shfl(o, j);
+        } else {
+            vj[u] = 0;
+            mj[u] = 0ull;
+            oj[u] = -1;
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+        const bool on = (mj[u] >> lane) & 1ull;
+        x[u] = on ? val[(size_t)vj[u] * kWave + lane] : 0.0;
+        wk.hits += on ? 1u : 0u;
+    }
+}
+
 // Probe the arcs first + 64*u + lane (u < kProbe, below `end`) of one vertex:
 // m = mask[neighbour] & keep, then gather val rows for the hits.
 __device__ __forceinline__ uint64_t probe_chunk(const BatchDev &d, int32_t first, int32_t end,
@@ -163,30 +199,33 @@ __device__ __forceinline__ uint64_t probe_chunk(const BatchDev &d, int32_t first
 
 // ---- forward ---------------------------------------------------------------
 
-// Size of the next frontier (vertices and arcs), counted per lane and added
-// to the level's counters once per wavefront at the end of a kernel.
+// Size of the next frontier (vertices and arcs), counted per lane and stored
+// by every wave of a kernel in its own slot of frontier set `set`: no counter
+// is shared between waves (atomics on one address from every wave of the
+// device serialise).
 struct Front {
     uint32_t cnt = 0;
     unsigned long long arcs = 0;
 };
 
-__device__ void report_front(const BatchDev &d, int32_t L, const Front &fr) {
+__device__ void report_front(const BatchDev &d, int set, const Front &fr) {
     unsigned long long c = fr.cnt, a = fr.arcs;
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) {
         c += __shfl_xor(c, off);
         a += __shfl_xor(a, off);
     }
-    if (lane_id() == 0 && c) {
-        const int nx = (L + 1) & 1;
-        atomicAdd((uint32_t *)&d.ctrl[kCtlQCount + nx], (uint32_t)c);
-        atomicAdd((unsigned long long *)&d.ctrl[kCtlQArcs + 2 * nx], a);
+    const int32_t wave = (blockIdx.x * kBlock + threadIdx.x) / kWave;
+    if (lane_id() == 0) {
+        unsigned long long *slot = d.front + ((size_t)set * kFrontWaves + wave) * 2;
+        slot[0] = c;
+        slot[1] = a;
     }
 }
 
 // Chunk item of a vertex of degree > 64.
-__device__ void fwd_chunk(const BatchDev &d, int32_t L, uint32_t item, uint64_t full,
-                          uint64_t *found, Work &wk, Front &fr) {
+__device__ void fwd_chunk(const BatchDev &d, int32_t L, uint32_t item, uint64_t full, Work &wk,
+                          Front &fr) {
     const int lane = lane_id();
     const int2 info = d.item_info[item];
     const int32_t w = info.x, j = info.y;
@@ -214,12 +253,9 @@ __device__ void fwd_chunk(const BatchDev &d, int32_t L, uint32_t item, uint64_t 
             FN[w] = nw;
             if (nw) {
                 d.vis[w] = vis | nw;
-                atomicOr((unsigned long long *)found, 1ull);
+                ++fr.cnt;
+                fr.arcs += (unsigned long long)(re - rs);
             }
-        }
-        if (lane == 0 && nw) {
-            ++fr.cnt;
-            fr.arcs += (unsigned long long)(re - rs);
         }
     } else if (nw) {
         // integer sums: the atomic adds are exact in any order
@@ -233,7 +269,7 @@ __device__ void fwd_chunk(const BatchDev &d, int32_t L, uint32_t item, uint64_t 
 // candidates of any degree, F_{L+1} cleared beforehand).  The wave flattens
 // the arcs of the vertices that still have unvisited lanes into runs of 64.
 __device__ void fwd_group(const BatchDev &d, int32_t L, int32_t base, const int32_t *list,
-                          int32_t count, uint64_t full, uint64_t *found, Work &wk, Front &fr) {
+                          int32_t count, uint64_t full, Work &wk, Front &fr) {
     const int lane = lane_id();
     const uint64_t *FL = d.F + (size_t)L * (size_t)d.n;
     uint64_t *FN = d.F + (size_t)(L + 1) * (size_t)d.n;
@@ -247,11 +283,10 @@ __device__ void fwd_group(const BatchDev &d, int32_t L, int32_t base, const int3
     int32_t rs = 0, cnt = 0;
     if (me >= 0) {
         vis = d.vis[me];
+        rs = d.row_ptr[me];
+        const int32_t re = d.row_ptr[me + 1];
         if (!list) FN[me] = 0ull;
-        if (vis != full) {
-            rs = d.row_ptr[me];
-            cnt = d.row_ptr[me + 1] - rs;
-        }
+        cnt = vis != full ? re - rs : 0;
     }
     uint32_t total;
     const uint32_t excl = wave_excl_scan((uint32_t)cnt, total);
@@ -259,7 +294,6 @@ __device__ void fwd_group(const BatchDev &d, int32_t L, int32_t base, const int3
     int cur = -1;        // owner lane being accumulated
     double acc = 0.0;
     uint64_t nw = 0;
-    uint64_t any_found = 0;
     auto flush = [&]() {
         if (cur >= 0 && nw) {
             const int32_t w = __shfl(me, cur);                   // all lanes active here
@@ -276,49 +310,62 @@ __device__ void fwd_group(const BatchDev &d, int32_t L, int32_t base, const int3
                 ++fr.cnt;
                 fr.arcs += (unsigned long long)w_deg;
             }
-            any_found |= nw;
         }
     };
-    for (uint32_t c0 = 0; c0 < total; c0 += kWave) {
-        const uint32_t a = c0 + (uint32_t)lane;
-        const int o = owner_lane(excl, a);
-        // cross-lane reads first, with every lane active
-        const int32_t o_rs = __shfl(rs, o);
-        const uint32_t o_excl = __shfl(excl, o);
-        const uint64_t o_keep = shfl64(unvis, o);
-        int32_t nb = -1;
-        uint64_t m = 0;
-        if (a < total) {
-            nb = d.col_idx[o_rs + (int32_t)(a - o_excl)];
-            m = FL[nb] & o_keep;
-            ++wk.arcs;
+    for (uint32_t c0 = 0; c0 < total; c0 += kWave * kRounds) {
+        // kRounds runs of 64 arcs: ids, then masks, loaded together
+        int o[kRounds];
+        int32_t nb[kRounds];
+        uint64_t m[kRounds];
+        bool live[kRounds];
+#pragma unroll
+        for (int r = 0; r < kRounds; ++r) {
+            const uint32_t a = c0 + (uint32_t)(r * kWave + lane);
+            o[r] = owner_lane(excl, a);
+            // cross-lane reads first, with every lane active
+            const int32_t o_rs = __shfl(rs, o[r]);
+            const uint32_t o_excl = __shfl(excl, o[r]);
+            live[r] = a < total;
+            nb[r] = live[r] ? d.col_idx[o_rs + (int32_t)(a - o_excl)] : 0;
         }
-        uint64_t hit = __ballot(m != 0ull);
-        while (hit) {
-            // hits of one owner at a time, gathered kUnroll rows at once
-            const int h0 = __ffsll((unsigned long long)hit) - 1;
-            const int own = __shfl(o, h0);
-            if (own != cur) {
-                flush();
-                cur = own;
-                acc = 0.0;
-                nw = 0;
+#pragma unroll
+        for (int r = 0; r < kRounds; ++r) {
+            const uint64_t o_keep = shfl64(unvis, o[r]);
+            m[r] = live[r] ? FL[nb[r]] & o_keep : 0ull;
+            wk.arcs += live[r] ? 1u : 0u;
+        }
+#pragma unroll
+        for (int r = 0; r < kRounds; ++r) {
+            uint64_t hit = __ballot(m[r] != 0ull);
+            while (hit) {
+                // kUnroll parent rows in flight at once, whatever their
+                // owners; then folded into the owners' sums in arc order
+                double x[kUnroll];
+                uint64_t mj[kUnroll];
+                int oj[kUnroll];
+                gather_run(hit, nb[r], m[r], o[r], d.sigma, x, mj, oj, wk);
+#pragma unroll
+                for (int u = 0; u < kUnroll; ++u) {
+                    if (oj[u] < 0) break;
+                    if (oj[u] != cur) {
+                        flush();
+                        cur = oj[u];
+                        acc = 0.0;
+                        nw = 0;
+                    }
+                    acc += x[u];
+                    nw |= mj[u];
+                }
             }
-            const uint64_t same = __ballot(o == own) & hit;
-            hit &= ~same;
-            nw |= wave_or(((same >> lane) & 1ull) ? m : 0ull);
-            gather_hits(same, nb, m, d.sigma, acc, wk);
         }
     }
     flush();
-    if (lane == 0 && any_found) atomicOr((unsigned long long *)found, 1ull);
 }
 
 __global__ __launch_bounds__(kBlock) void k_batch_forward(BatchDev d, int32_t L, uint64_t full) {
     // nothing past the deepest level found so far (F_L is empty), no room, or
     // this level takes the sparse step
     if (L > d.ctrl[kCtlDeepest] || L + 1 >= d.lcap || d.ctrl[kCtlMode]) return;
-    uint64_t *found = (uint64_t *)&d.ctrl[kCtlFound];
     const uint32_t items = d.items;
     const uint32_t groups = (uint32_t)((d.n - d.big_end + kWave - 1) / kWave);
     const uint32_t wave = (blockIdx.x * kBlock + threadIdx.x) / kWave;
@@ -326,11 +373,10 @@ __global__ __launch_bounds__(kBlock) void k_batch_forward(BatchDev d, int32_t L,
     Work wk;
     Front fr;
     for (uint32_t it = wave; it < items + groups; it += nwaves) {
-        if (it < items) fwd_chunk(d, L, it, full, found, wk, fr);
-        else fwd_group(d, L, d.big_end + (int32_t)(it - items) * kWave, nullptr, 0, full, found,
-                       wk, fr);
+        if (it < items) fwd_chunk(d, L, it, full, wk, fr);
+        else fwd_group(d, L, d.big_end + (int32_t)(it - items) * kWave, nullptr, 0, full, wk, fr);
     }
-    report_front(d, L, fr);
+    report_front(d, 0, fr);
     if (d.stats) report_work(d.stats, wk);
 }
 
@@ -340,7 +386,6 @@ __global__ __launch_bounds__(kBlock) void k_batch_forward_finish(BatchDev d, int
                                                                  uint64_t full) {
     if (L > d.ctrl[kCtlDeepest] || L + 1 >= d.lcap) return;
     uint64_t *FN = d.F + (size_t)(L + 1) * (size_t)d.n;
-    uint64_t *found = (uint64_t *)&d.ctrl[kCtlFound];
     Front fr;
     const int lane = lane_id();
     const int32_t wave = (blockIdx.x * kBlock + threadIdx.x) / kWave;
@@ -355,33 +400,55 @@ __global__ __launch_bounds__(kBlock) void k_batch_forward_finish(BatchDev d, int
         if (lane == 0) {
             d.vis[w] |= nw;
             d.reach[w] = 0ull;
-            atomicOr((unsigned long long *)found, 1ull);
             ++fr.cnt;
             fr.arcs += (unsigned long long)(d.row_ptr[w + 1] - d.row_ptr[w]);
         }
     }
-    report_front(d, L, fr);
+    report_front(d, 2, fr);
     (void)full;
 }
 
-// Bookkeeping between iterations (one thread): depth (or truncation when the
-// level array is full), the step the next iteration takes (sparse when the
-// new frontier has few arcs), and the counters of the lists.
-__global__ void k_batch_level_done(BatchDev d, int32_t L) {
-    uint64_t *found = (uint64_t *)&d.ctrl[kCtlFound];
-    if (*found) {
-        d.ctrl[kCtlDeepest] = L + 1;
-        if (L + 2 >= d.lcap) d.ctrl[kCtlTrunc] = 1;  // level L+2 would not fit
+// Bookkeeping between iterations (one block): adds up the frontier slots of
+// the kernels that ran, records the depth (or the truncation when the level
+// array is full), picks the step of the next iteration (sparse when the new
+// frontier has few arcs) and clears the list counters.  waves[s] = the waves
+// of the kernel of frontier set s.
+__global__ __launch_bounds__(kBlock) void k_batch_level_done(BatchDev d, int32_t L, int32_t w0,
+                                                             int32_t w1, int32_t w2) {
+    __shared__ unsigned long long sc[kBlock], sa[kBlock];
+    const int t = threadIdx.x;
+    const bool live = !(L > d.ctrl[kCtlDeepest] || L + 1 >= d.lcap);
+    const int mode = d.ctrl[kCtlMode];
+    unsigned long long c = 0, a = 0;
+    if (live) {
+        const int32_t waves[kFrontSets] = {mode ? 0 : w0, mode ? w1 : 0, w2};
+        for (int set = 0; set < kFrontSets; ++set) {
+            const unsigned long long *slot = d.front + (size_t)set * kFrontWaves * 2;
+            for (int32_t w = t; w < waves[set]; w += kBlock) {
+                c += slot[2 * w];
+                a += slot[2 * w + 1];
+            }
+        }
     }
-    *found = 0ull;
-    const int nx = (L + 1) & 1, cur = L & 1;
-    const unsigned long long arcs = *(unsigned long long *)&d.ctrl[kCtlQArcs + 2 * nx];
-    d.ctrl[kCtlMode] = (int64_t)arcs < d.sparse_arcs ? 1 : 0;
-    // the list of level L is consumed: it receives level L+2
-    d.ctrl[kCtlQCount + cur] = 0;
-    *(unsigned long long *)&d.ctrl[kCtlQArcs + 2 * cur] = 0ull;
-    d.ctrl[kCtlCand] = 0;
-    d.ctrl[kCtlItems] = 0;
+    sc[t] = c;
+    sa[t] = a;
+    __syncthreads();
+    for (int h = kBlock / 2; h >= 1; h >>= 1) {
+        if (t < h) {
+            sc[t] += sc[t + h];
+            sa[t] += sa[t + h];
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        if (live && sc[0] != 0) {
+            d.ctrl[kCtlDeepest] = L + 1;
+            if (L + 2 >= d.lcap) d.ctrl[kCtlTrunc] = 1;  // level L+2 would not fit
+        }
+        if (live) d.ctrl[kCtlMode] = (int64_t)sa[0] < d.sparse_arcs ? 1 : 0;
+        d.ctrl[kCtlCand] = 0;
+        d.ctrl[kCtlItems] = 0;
+    }
 }
 
 // ---- sparse forward step ------------------------------------------------------
@@ -425,22 +492,26 @@ __global__ __launch_bounds__(kBlock) void k_batch_sparse_mark(BatchDev d, int32_
 __global__ __launch_bounds__(kBlock) void k_batch_sparse_compact(BatchDev d, int32_t L,
                                                                  uint64_t full) {
     if (L > d.ctrl[kCtlDeepest] || L + 1 >= d.lcap || !d.ctrl[kCtlMode]) return;
+    // list space is taken once per block (the waves' counts added in LDS):
+    // one atomic per block and list instead of one per wave
+    __shared__ uint32_t s_small[kWavesPerBlock], s_items[kWavesPerBlock], s_base[2];
     const int lane = lane_id();
+    const int wib = threadIdx.x / kWave;
     uint64_t *FN = d.F + (size_t)(L + 1) * (size_t)d.n;
     const int32_t groups = (d.n + 15) >> 4;
     const int32_t stride = gridDim.x * kBlock;
-    const int32_t base0 = blockIdx.x * kBlock + (threadIdx.x & ~(kWave - 1));
-    for (int32_t wb = base0; wb < groups; wb += stride) {
+    // the loop runs the same number of times in every wave of the block
+    for (int32_t bb = blockIdx.x * kBlock; bb < groups; bb += stride) {
+        const int32_t wb = bb + wib * kWave;
         const int32_t i = wb + lane;
         uint4 m = make_uint4(0u, 0u, 0u, 0u);
-        if (i < groups) {
-            m = reinterpret_cast<const uint4 *>(d.cand)[i];
+        if (i < groups) m = reinterpret_cast<const uint4 *>(d.cand)[i];
+        // the wave's 1024 vertices of F_{L+1}, cleared with coalesced stores
 #pragma unroll
-            for (int j = 0; j < 16; ++j)
-                if ((i << 4) + j < d.n) FN[(i << 4) + j] = 0ull;
+        for (int j = 0; j < 16; ++j) {
+            const int32_t v = (wb << 4) + j * kWave + lane;
+            if (v < d.n) FN[v] = 0ull;
         }
-        const bool any = (m.x | m.y | m.z | m.w) != 0u;
-        if (__ballot(any) == 0ull) continue;
         uint32_t bits = 0;
         {
             const uint32_t wv[4] = {m.x, m.y, m.z, m.w};
@@ -468,14 +539,27 @@ __global__ __launch_bounds__(kBlock) void k_batch_sparse_compact(BatchDev d, int
         uint32_t tot, toti;
         const uint32_t off = wave_excl_scan(nsmall, tot);
         const uint32_t offi = wave_excl_scan(nitems, toti);
-        uint32_t base = 0, basei = 0;
         if (lane == 0) {
-            if (tot) base = atomicAdd((uint32_t *)&d.ctrl[kCtlCand], tot);
-            if (toti) basei = atomicAdd((uint32_t *)&d.ctrl[kCtlItems], toti);
+            s_small[wib] = tot;
+            s_items[wib] = toti;
         }
-        base = __shfl(base, 0);
-        basei = __shfl(basei, 0);
-        uint32_t p = base + off, pi = basei + offi;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t a = 0, b = 0;
+            for (int w = 0; w < kWavesPerBlock; ++w) {
+                a += s_small[w];
+                b += s_items[w];
+            }
+            s_base[0] = a ? atomicAdd((uint32_t *)&d.ctrl[kCtlCand], a) : 0u;
+            s_base[1] = b ? atomicAdd((uint32_t *)&d.ctrl[kCtlItems], b) : 0u;
+        }
+        __syncthreads();
+        uint32_t p = s_base[0] + off, pi = s_base[1] + offi;
+        for (int w = 0; w < wib; ++w) {
+            p += s_small[w];
+            pi += s_items[w];
+        }
+        __syncthreads();  // the shared counts are rewritten by the next round
 #pragma unroll
         for (int j = 0; j < 16; ++j) {
             if (!((bits >> j) & 1u)) continue;
@@ -494,7 +578,6 @@ __global__ __launch_bounds__(kBlock) void k_batch_sparse_compact(BatchDev d, int
 __global__ __launch_bounds__(kBlock) void k_batch_sparse_pull(BatchDev d, int32_t L,
                                                               uint64_t full) {
     if (L > d.ctrl[kCtlDeepest] || L + 1 >= d.lcap || !d.ctrl[kCtlMode]) return;
-    uint64_t *found = (uint64_t *)&d.ctrl[kCtlFound];
     const int32_t c = d.ctrl[kCtlCand];
     const int32_t ni = d.ctrl[kCtlItems];
     const int32_t groups = (c + kWave - 1) / kWave;
@@ -503,109 +586,14 @@ __global__ __launch_bounds__(kBlock) void k_batch_sparse_pull(BatchDev d, int32_
     Work wk;
     Front fr;
     for (int32_t it = wave; it < ni + groups; it += nwaves) {
-        if (it < ni) fwd_chunk(d, L, (uint32_t)d.ilist[it], full, found, wk, fr);
-        else fwd_group(d, L, (it - ni) * kWave, d.clist, c, full, found, wk, fr);
+        if (it < ni) fwd_chunk(d, L, (uint32_t)d.ilist[it], full, wk, fr);
+        else fwd_group(d, L, (it - ni) * kWave, d.clist, c, full, wk, fr);
     }
-    report_front(d, L, fr);
+    report_front(d, 1, fr);
     if (d.stats) report_work(d.stats, wk);
 }
 
 // ---- reverse ---------------------------------------------------------------
-
-// Chunk item of a vertex of degree > 64: sums of c over children, written to
-// the vertex's c row (one chunk) or to the item's partial row (split vertex).
-__device__ void bwd_chunk(const BatchDev &d, int32_t L, uint32_t item, Work &wk) {
-    const int lane = lane_id();
-    const int2 info = d.item_info[item];
-    const int32_t v = info.x, j = info.y;
-    const uint64_t mv = d.F[(size_t)L * (size_t)d.n + v];
-    if (mv == 0ull) return;
-    const uint64_t *FC = d.F + (size_t)(L + 1) * (size_t)d.n;
-    const int32_t rs = d.row_ptr[v], re = d.row_ptr[v + 1];
-    const int32_t cb = rs + j * kChunk;
-    double acc = 0.0;
-    (void)probe_chunk(d, cb, min(re, cb + kChunk), FC, mv, d.coef, acc, wk);
-    if (((mv >> lane) & 1ull) && j == 0) ++wk.owners;
-    if (v < d.multi_end) d.partial[(size_t)item * kWave + lane] = acc;
-    else if ((mv >> lane) & 1ull) d.coef[(size_t)v * kWave + lane] = acc;
-}
-
-__device__ void bwd_group(const BatchDev &d, int32_t L, int32_t base, Work &wk) {
-    const int lane = lane_id();
-    const uint64_t *FL = d.F + (size_t)L * (size_t)d.n;
-    const uint64_t *FC = d.F + (size_t)(L + 1) * (size_t)d.n;
-    const int32_t me = base + lane;
-    uint64_t mv = 0;
-    int32_t rs = 0, cnt = 0;
-    if (me < d.n) {
-        mv = FL[me];
-        if (mv) {
-            rs = d.row_ptr[me];
-            cnt = d.row_ptr[me + 1] - rs;
-        }
-    }
-    uint32_t total;
-    const uint32_t excl = wave_excl_scan((uint32_t)cnt, total);
-    wk.owners += (uint32_t)__popcll((unsigned long long)mv);
-    // owners with lanes at level L but no children keep sum 0: written first
-    uint64_t pending = __ballot(mv != 0ull);
-    int cur = -1;
-    double acc = 0.0;
-    auto flush = [&]() {
-        if (cur < 0) return;
-        const uint64_t own_mv = shfl64(mv, cur);  // all lanes active here
-        if ((own_mv >> lane) & 1ull) d.coef[(size_t)(base + cur) * kWave + lane] = acc;
-    };
-    for (uint32_t c0 = 0; c0 < total; c0 += kWave) {
-        const uint32_t a = c0 + (uint32_t)lane;
-        const int o = owner_lane(excl, a);
-        const int32_t o_rs = __shfl(rs, o);
-        const uint32_t o_excl = __shfl(excl, o);
-        const uint64_t o_keep = shfl64(mv, o);
-        int32_t nb = -1;
-        uint64_t m = 0;
-        if (a < total) {
-            nb = d.col_idx[o_rs + (int32_t)(a - o_excl)];
-            m = FC[nb] & o_keep;
-            ++wk.arcs;
-        }
-        uint64_t hit = __ballot(m != 0ull);
-        while (hit) {
-            const int h0 = __ffsll((unsigned long long)hit) - 1;
-            const int own = __shfl(o, h0);
-            if (own != cur) {
-                flush();
-                cur = own;
-                acc = 0.0;
-                pending &= ~(1ull << own);
-            }
-            const uint64_t same = __ballot(o == own) & hit;
-            hit &= ~same;
-            gather_hits(same, nb, m, d.coef, acc, wk);
-        }
-    }
-    flush();
-    // owners without any child: their sums are 0
-    while (pending) {
-        const int t = __ffsll((unsigned long long)pending) - 1;
-        pending &= pending - 1;
-        const uint64_t own_mv = shfl64(mv, t);
-        if ((own_mv >> lane) & 1ull) d.coef[(size_t)(base + t) * kWave + lane] = 0.0;
-    }
-}
-
-__global__ __launch_bounds__(kBlock) void k_batch_reverse(BatchDev d, int32_t L) {
-    const uint32_t items = d.items;
-    const uint32_t groups = (uint32_t)((d.n - d.big_end + kWave - 1) / kWave);
-    const uint32_t wave = (blockIdx.x * kBlock + threadIdx.x) / kWave;
-    const uint32_t nwaves = gridDim.x * kWavesPerBlock;
-    Work wk;
-    for (uint32_t it = wave; it < items + groups; it += nwaves) {
-        if (it < items) bwd_chunk(d, L, it, wk);
-        else bwd_group(d, L, d.big_end + (int32_t)(it - items) * kWave, wk);
-    }
-    if (d.stats) report_work(d.stats + 6, wk);
-}
 
 // Per-request outputs: lanes [seg_start[g], seg_start[g+1]) belong to request
 // g of the batch.  Each segment's deltas are rotated down to lane 0 and summed
@@ -623,25 +611,177 @@ __device__ void add_segments(const BatchDev &d, int32_t v, double delta) {
     }
 }
 
-// Finalise level L: for every v and lane s with s in F_L[v], the child sum is
-// in c[v][s] (or in the partial rows of a split vertex); delta = sigma * sum,
-// c = (1 + delta) / sigma, BC[v] += sum of the lanes' deltas.  With leaf set
-// (the deepest level), every sum is 0.
+// Complete (v, lanes mv) at level L from its children sums acc and its sigma
+// (lane s meaningful for s in mv): delta = sigma * acc, c = (1 + delta) /
+// sigma, and the lanes' deltas added to BC[v] (or to the requests' outputs).
+// Called with every lane active.
+__device__ __forceinline__ void settle(const BatchDev &d, int32_t v, uint64_t mv, double sig,
+                                       double acc) {
+    const int lane = lane_id();
+    const bool on = (mv >> lane) & 1ull;
+    const double delta = on ? sig * acc : 0.0;
+    if (on) d.coef[(size_t)v * kWave + lane] = (1.0 + delta) / sig;
+    if (d.nseg == 0) {
+        const double tot = wave_sum(delta);
+        if (lane == 0 && tot != 0.0) d.bc[v] += tot;
+    } else {
+        add_segments(d, v, delta);
+    }
+}
+
+// Chunk item of a vertex of degree > 64: sums of c over children; a vertex
+// with one chunk is completed here, a split vertex leaves the item's partial
+// row for the finalising pass.
+__device__ void bwd_chunk(const BatchDev &d, int32_t L, uint32_t item, Work &wk) {
+    const int lane = lane_id();
+    const int2 info = d.item_info[item];
+    const int32_t v = info.x, j = info.y;
+    const uint64_t mv = d.F[(size_t)L * (size_t)d.n + v];
+    if (mv == 0ull) return;
+    const uint64_t *FC = d.F + (size_t)(L + 1) * (size_t)d.n;
+    const int32_t rs = d.row_ptr[v], re = d.row_ptr[v + 1];
+    const int32_t cb = rs + j * kChunk;
+    const bool on = (mv >> lane) & 1ull;
+    const double sig = (on && v >= d.multi_end) ? d.sigma[(size_t)v * kWave + lane] : 1.0;
+    double acc = 0.0;
+    (void)probe_chunk(d, cb, min(re, cb + kChunk), FC, mv, d.coef, acc, wk);
+    if (on && j == 0) ++wk.owners;
+    if (v < d.multi_end) d.partial[(size_t)item * kWave + lane] = acc;
+    else settle(d, v, mv, sig, acc);
+}
+
+__device__ void bwd_group(const BatchDev &d, int32_t L, int32_t base, Work &wk) {
+    const int lane = lane_id();
+    const uint64_t *FL = d.F + (size_t)L * (size_t)d.n;
+    const uint64_t *FC = d.F + (size_t)(L + 1) * (size_t)d.n;
+    const int32_t me = base + lane;
+    uint64_t mv = 0;
+    int32_t rs = 0, cnt = 0;
+    if (me < d.n) {
+        mv = FL[me];
+        rs = d.row_ptr[me];
+        const int32_t re = d.row_ptr[me + 1];
+        cnt = mv ? re - rs : 0;
+    }
+    uint32_t total;
+    const uint32_t excl = wave_excl_scan((uint32_t)cnt, total);
+    wk.owners += (uint32_t)__popcll((unsigned long long)mv);
+    // owners with lanes at level L but no children are completed at the end
+    uint64_t pending = __ballot(mv != 0ull);
+    int cur = -1;
+    double acc = 0.0;
+    double cur_sig = 1.0;   // sigma of the owner being accumulated (its lanes)
+    auto flush = [&]() {
+        if (cur < 0) return;
+        settle(d, base + cur, shfl64(mv, cur), cur_sig, acc);  // all lanes active here
+    };
+    for (uint32_t c0 = 0; c0 < total; c0 += kWave * kRounds) {
+        int o[kRounds];
+        int32_t nb[kRounds];
+        uint64_t m[kRounds];
+        bool live[kRounds];
+#pragma unroll
+        for (int r = 0; r < kRounds; ++r) {
+            const uint32_t a = c0 + (uint32_t)(r * kWave + lane);
+            o[r] = owner_lane(excl, a);
+            const int32_t o_rs = __shfl(rs, o[r]);
+            const uint32_t o_excl = __shfl(excl, o[r]);
+            live[r] = a < total;
+            nb[r] = live[r] ? d.col_idx[o_rs + (int32_t)(a - o_excl)] : 0;
+        }
+#pragma unroll
+        for (int r = 0; r < kRounds; ++r) {
+            const uint64_t o_keep = shfl64(mv, o[r]);
+            m[r] = live[r] ? FC[nb[r]] & o_keep : 0ull;
+            wk.arcs += live[r] ? 1u : 0u;
+        }
+#pragma unroll
+        for (int r = 0; r < kRounds; ++r) {
+            uint64_t hit = __ballot(m[r] != 0ull);
+            while (hit) {
+                double x[kUnroll];
+                uint64_t mj[kUnroll];
+                int oj[kUnroll];
+                gather_run(hit, nb[r], m[r], o[r], d.coef, x, mj, oj, wk);
+#pragma unroll
+                for (int u = 0; u < kUnroll; ++u) {
+                    if (oj[u] < 0) break;
+                    if (oj[u] != cur) {
+                        flush();
+                        cur = oj[u];
+                        acc = 0.0;
+                        pending &= ~(1ull << cur);
+                        const bool on = (shfl64(mv, cur) >> lane) & 1ull;
+                        cur_sig = on ? d.sigma[(size_t)(base + cur) * kWave + lane] : 1.0;
+                    }
+                    acc += x[u];
+                }
+            }
+        }
+    }
+    flush();
+    // owners without any child: delta = 0, c = 1 / sigma, nothing for BC
+    while (pending) {
+        int32_t vj[kUnroll];
+        bool on[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            vj[u] = -1;
+            on[u] = false;
+            if (pending) {
+                const int t = __ffsll((unsigned long long)pending) - 1;
+                pending &= pending - 1;
+                vj[u] = base + t;
+                on[u] = (shfl64(mv, t) >> lane) & 1ull;
+            }
+        }
+        double sig[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u)
+            sig[u] = on[u] ? d.sigma[(size_t)vj[u] * kWave + lane] : 1.0;
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u)
+            if (on[u]) d.coef[(size_t)vj[u] * kWave + lane] = 1.0 / sig[u];
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_batch_reverse(BatchDev d, int32_t L) {
+    const uint32_t items = d.items;
+    const uint32_t groups = (uint32_t)((d.n - d.big_end + kWave - 1) / kWave);
+    const uint32_t wave = (blockIdx.x * kBlock + threadIdx.x) / kWave;
+    const uint32_t nwaves = gridDim.x * kWavesPerBlock;
+    Work wk;
+    for (uint32_t it = wave; it < items + groups; it += nwaves) {
+        if (it < items) bwd_chunk(d, L, it, wk);
+        else bwd_group(d, L, d.big_end + (int32_t)(it - items) * kWave, wk);
+    }
+    if (d.stats) report_work(d.stats + 6, wk);
+}
+
+// Finalise level L for the vertices the reverse kernel leaves open: the split
+// vertices (v < multi_end), whose child sums are the partial rows of their
+// chunks added in chunk order, or, with leaf set (the deepest level), every
+// vertex, with sum 0.  delta = sigma * sum, c = (1 + delta) / sigma, BC[v] +=
+// the lanes' deltas.
 __global__ __launch_bounds__(kBlock) void k_batch_finalize(BatchDev d, int32_t L, int32_t leaf) {
     const int lane = lane_id();
     const uint64_t *FL = d.F + (size_t)L * (size_t)d.n;
     const int32_t wave = (blockIdx.x * kBlock + threadIdx.x) / kWave;
     const int32_t nwaves = gridDim.x * kWavesPerBlock;
-    const int32_t groups = (d.n + kWave - 1) / kWave;
+    const int32_t vend = leaf ? d.n : d.multi_end;
+    const int32_t groups = (vend + kWave - 1) / kWave;
     for (int32_t gi = wave; gi < groups; gi += nwaves) {
         const int32_t me = gi * kWave + lane;
-        const uint64_t m_me = me < d.n ? FL[me] : 0ull;
+        const uint64_t m_me = me < vend ? FL[me] : 0ull;
         uint64_t todo = __ballot(m_me != 0ull);
         while (todo) {
-            int32_t vj[4];
-            uint64_t mj[4];
+            // kFinal vertices per round: their rows are loaded together and
+            // their BC updates made by kFinal lanes at once
+            constexpr int kFinal = 8;
+            int32_t vj[kFinal];
+            uint64_t mj[kFinal];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+            for (int u = 0; u < kFinal; ++u) {
                 if (todo) {
                     const int t = __ffsll((unsigned long long)todo) - 1;
                     todo &= todo - 1;
@@ -652,36 +792,54 @@ __global__ __launch_bounds__(kBlock) void k_batch_finalize(BatchDev d, int32_t L
                     mj[u] = 0ull;
                 }
             }
-            double sig[4], sum[4];
+            double sig[kFinal], sum[kFinal];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+            for (int u = 0; u < kFinal; ++u) {
                 const bool on = (mj[u] >> lane) & 1ull;
                 const size_t at = (size_t)(vj[u] < 0 ? 0 : vj[u]) * kWave + lane;
                 sig[u] = on ? d.sigma[at] : 1.0;
                 sum[u] = 0.0;
                 if (on && !leaf) {
-                    if (vj[u] < d.multi_end) {
-                        const int32_t v = vj[u];
-                        const uint32_t i0 = d.item_first[v], i1 = d.item_first[v + 1];
-                        double t = 0.0;
-                        for (uint32_t i = i0; i < i1; ++i) t += d.partial[(size_t)i * kWave + lane];
-                        sum[u] = t;
-                    } else {
-                        sum[u] = d.coef[at];
+                    // the chunks' partial rows in chunk order, 8 loads in flight
+                    const int32_t v = vj[u];
+                    const uint32_t i0 = d.item_first[v], i1 = d.item_first[v + 1];
+                    double t = 0.0;
+                    uint32_t i = i0;
+                    for (; i + 8 <= i1; i += 8) {
+                        double x[8];
+#pragma unroll
+                        for (int q = 0; q < 8; ++q) x[q] = d.partial[(size_t)(i + q) * kWave + lane];
+#pragma unroll
+                        for (int q = 0; q < 8; ++q) t += x[q];
                     }
+                    for (; i < i1; ++i) t += d.partial[(size_t)i * kWave + lane];
+                    sum[u] = t;
                 }
             }
+            double delta[kFinal];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+            for (int u = 0; u < kFinal; ++u) {
                 const bool on = (mj[u] >> lane) & 1ull;
-                const double delta = on ? sig[u] * sum[u] : 0.0;
-                if (on) d.coef[(size_t)vj[u] * kWave + lane] = (1.0 + delta) / sig[u];
-                if (d.nseg == 0) {
-                    const double tot = wave_sum(delta);
-                    if (lane == 0 && vj[u] >= 0 && tot != 0.0) d.bc[vj[u]] += tot;
-                } else if (vj[u] >= 0) {
-                    add_segments(d, vj[u], delta);
+                delta[u] = on ? sig[u] * sum[u] : 0.0;
+                if (on) d.coef[(size_t)vj[u] * kWave + lane] = (1.0 + delta[u]) / sig[u];
+            }
+            if (d.nseg == 0) {
+                // lane u receives vertex u's sum over the lanes
+                double my_tot = 0.0;
+                int32_t my_v = -1;
+#pragma unroll
+                for (int u = 0; u < kFinal; ++u) {
+                    const double tot = wave_sum(delta[u]);
+                    if (lane == u) {
+                        my_tot = tot;
+                        my_v = vj[u];
+                    }
                 }
+                if (my_v >= 0 && my_tot != 0.0) d.bc[my_v] += my_tot;
+            } else {
+#pragma unroll
+                for (int u = 0; u < kFinal; ++u)
+                    if (vj[u] >= 0) add_segments(d, vj[u], delta[u]);
             }
         }
     }
@@ -752,8 +910,10 @@ __global__ void k_batch_export(BatchDev d, int32_t deepest, int32_t nlanes, int3
 
 int grid_of(int64_t waves) {
     int64_t g = (waves + kWavesPerBlock - 1) / kWavesPerBlock;
-    return (int)(g < 1 ? 1 : (g > 2048 ? 2048 : g));
+    return (int)(g < 1 ? 1 : (g > kMaxGridBlocks ? kMaxGridBlocks : g));
 }
+
+constexpr int kSparseGrid = kMaxGridBlocks;  // blocks of the sparse mark / pull kernels
 
 }  // namespace
 
@@ -776,14 +936,15 @@ hipError_t batch_forward(const BatchDev &d, int32_t level, uint64_t full, hipStr
                        d, level, full);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_batch_sparse_mark, dim3(2048), dim3(kBlock), 0, stream, d, level);
+    hipLaunchKernelGGL(k_batch_sparse_mark, dim3(kSparseGrid), dim3(kBlock), 0, stream, d, level);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_batch_sparse_compact, dim3(grid_of(((d.n + 15) / 16 + kWave - 1) / kWave)),
                        dim3(kBlock), 0, stream, d, level, full);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_batch_sparse_pull, dim3(2048), dim3(kBlock), 0, stream, d, level, full);
+    hipLaunchKernelGGL(k_batch_sparse_pull, dim3(kSparseGrid), dim3(kBlock), 0, stream, d, level,
+                       full);
     return hipGetLastError();
 }
 
@@ -795,7 +956,11 @@ hipError_t batch_forward_done(const BatchDev &d, int32_t level, uint64_t full,
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k_batch_level_done, dim3(1), dim3(1), 0, stream, d, level);
+    const int64_t groups = (d.n - d.big_end + kWave - 1) / kWave;
+    const int32_t w0 = grid_of(d.items + groups) * kWavesPerBlock;
+    const int32_t w1 = kSparseGrid * kWavesPerBlock;
+    const int32_t w2 = d.multi_end > 0 ? grid_of(d.multi_end) * kWavesPerBlock : 0;
+    hipLaunchKernelGGL(k_batch_level_done, dim3(1), dim3(kBlock), 0, stream, d, level, w0, w1, w2);
     return hipGetLastError();
 }
 
@@ -807,7 +972,9 @@ hipError_t batch_reverse(const BatchDev &d, int32_t level, hipStream_t stream) {
 }
 
 hipError_t batch_finalize(const BatchDev &d, int32_t level, bool deepest, hipStream_t stream) {
-    hipLaunchKernelGGL(k_batch_finalize, dim3(grid_of((d.n + kWave - 1) / kWave)), dim3(kBlock),
+    const int32_t vend = deepest ? d.n : d.multi_end;
+    if (vend == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_batch_finalize, dim3(grid_of((vend + kWave - 1) / kWave)), dim3(kBlock),
                        0, stream, d, level, deepest ? 1 : 0);
     return hipGetLastError();
 }

@@ -511,6 +511,7 @@ size_t batch_ws_bytes(const bc_graph_s *g) {
     b += align_up(12 * sizeof(unsigned long long));     // work counters
     b += align_up(n * sizeof(int32_t));                  // candidate list
     b += align_up((size_t)std::max<uint32_t>(g->items, 1) * sizeof(int32_t));  // item list
+    b += align_up((size_t)kFrontSets * kFrontWaves * 2 * sizeof(unsigned long long));
     b += align_up(((n + 15) / 16) * 16);                 // candidate marks
     return b;
 }
@@ -574,6 +575,8 @@ bc_status batch_ws_create(bc_graph_s *g, BatchWS **out) {
     d.clist = (int32_t *)take(n * sizeof(int32_t));
     d.ilist = (int32_t *)take((size_t)std::max<uint32_t>(g->items, 1) * sizeof(int32_t));
     d.cand = (uint8_t *)take(((n + 15) / 16) * 16);
+    d.front = (unsigned long long *)take((size_t)kFrontSets * kFrontWaves * 2 *
+                                         sizeof(unsigned long long));
     d.nnz = g->nnz;
     d.sparse_arcs = g->nnz / kDefaultSparseDiv;
     d.F = nullptr;

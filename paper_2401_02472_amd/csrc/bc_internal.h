@@ -108,6 +108,7 @@ struct BatchDev {
     uint8_t *cand;
     int32_t *clist;
     int32_t *ilist;
+    unsigned long long *front;  // [kFrontSets][kFrontWaves][2]
     int64_t nnz;
     int64_t sparse_arcs;   // a level runs sparse when its frontier has fewer arcs
     unsigned long long *stats;  // NULL, or work counters when measuring: [0..2]
@@ -126,14 +127,19 @@ enum {
     kCtlDeepest = 0,   // deepest level found
     kCtlRange = 1,     // some sigma not finite
     kCtlTrunc = 2,     // level array full: run the batch again with more room
-    kCtlFound = 4,     // [4..5] discovery flag of the running iteration (64-bit)
-    kCtlMode = 6,      // 1: the running iteration takes the sparse forward step
-    kCtlCand = 7,      // candidates listed by the sparse step
-    kCtlQCount = 8,    // [8..9] frontier sizes (vertices), level L & 1
-    kCtlItems = 10,    // chunk items listed by the sparse step
-    kCtlQArcs = 12,    // [12..15] frontier arc counts (64-bit), level L & 1
-    kCtlInts = 16
+    kCtlMode = 3,      // 1: the running iteration takes the sparse forward step
+    kCtlCand = 4,      // candidates listed by the sparse step
+    kCtlItems = 5,     // chunk items listed by the sparse step
+    kCtlInts = 8
 };
+
+// Per-wave frontier counts of one forward iteration: set 0 the scan-all step,
+// set 1 the sparse step, set 2 the completion of split vertices; each wave of
+// those kernels stores (vertices, arcs) of the new frontier it found in its
+// own slot, and the bookkeeping kernel adds them up (no shared counter).
+constexpr int kMaxGridBlocks = 2048;
+constexpr int kFrontWaves = kMaxGridBlocks * kWavesPerBlock;
+constexpr int kFrontSets = 3;
 
 // Launchers (bc_batched.hip).  All are asynchronous on `stream`.
 // Clear the batch state and seed lane s with source src_dev[s], s < nlanes.
