@@ -110,8 +110,9 @@ __device__ void report_work(unsigned long long *out, const Work &wk) {
 
 // Walk the lanes set in `hit` (each holding a neighbour id `nb` and a lane
 // mask `m`), kUnroll rows at a time; lane s adds val[nb][s] when s is in m.
+template <typename V>
 __device__ __forceinline__ void gather_hits(uint64_t hit, int32_t nb, uint64_t m,
-                                            const double *val, double &acc, Work &wk) {
+                                            const V *val, double &acc, Work &wk) {
     const int lane = lane_id();
     while (hit) {
         int32_t vj[kUnroll];
@@ -129,9 +130,16 @@ __device__ __forceinline__ void gather_hits(uint64_t hit, int32_t nb, uint64_t m
                 on[u] = false;
             }
         }
+        // raw loads first (all in flight), conversions after
+        V raw[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            raw[u] = 0;
+            if (on[u]) raw[u] = val[(size_t)vj[u] * kWave + lane];
+        }
         double x[kUnroll];
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) x[u] = on[u] ? val[(size_t)vj[u] * kWave + lane] : 0.0;
+        for (int u = 0; u < kUnroll; ++u) x[u] = (double)raw[u];
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) wk.hits += on[u] ? 1u : 0u;
 #pragma unroll
@@ -144,8 +152,9 @@ __device__ __forceinline__ void gather_hits(uint64_t hit, int32_t nb, uint64_t m
 // rows together: x[u] = val[nb_u][lane] when lane is in m_u, else 0.  The
 // owners and masks come back wave-uniform (oj[u] = -1 past the last hit), so
 // the caller can fold the values into per-owner sums in arc order.
+template <typename V>
 __device__ __forceinline__ void gather_run(uint64_t &hit, int32_t nb, uint64_t m, int o,
-                                           const double *val, double (&x)[kUnroll],
+                                           const V *val, double (&x)[kUnroll],
                                            uint64_t (&mj)[kUnroll], int (&oj)[kUnroll],
                                            Work &wk) {
     const int lane = lane_id();
@@ -164,19 +173,25 @@ __device__ __forceinline__ void gather_run(uint64_t &hit, int32_t nb, uint64_t m
             oj[u] = -1;
         }
     }
+    // raw loads first (all in flight), conversions after
+    V raw[kUnroll];
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
         const bool on = (mj[u] >> lane) & 1ull;
-        x[u] = on ? val[(size_t)vj[u] * kWave + lane] : 0.0;
+        raw[u] = 0;
+        if (on) raw[u] = val[(size_t)vj[u] * kWave + lane];
         wk.hits += on ? 1u : 0u;
     }
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) x[u] = (double)raw[u];
 }
 
 // Probe the arcs first + 64*u + lane (u < kProbe, below `end`) of one vertex:
 // m = mask[neighbour] & keep, then gather val rows for the hits.
+template <typename V>
 __device__ __forceinline__ uint64_t probe_chunk(const BatchDev &d, int32_t first, int32_t end,
                                                 const uint64_t *mask, uint64_t keep,
-                                                const double *val, double &acc, Work &wk) {
+                                                const V *val, double &acc, Work &wk) {
     const int lane = lane_id();
     int32_t nb[kProbe];
     uint64_t m[kProbe];
@@ -195,6 +210,41 @@ __device__ __forceinline__ uint64_t probe_chunk(const BatchDev &d, int32_t first
         gather_hits(__ballot(m[u] != 0ull), nb[u], m[u], val, acc, wk);
     }
     return wave_or(any);
+}
+
+// ---- sigma rows ------------------------------------------------------------
+
+// Shortest-path counts are integers.  They are kept as exact uint32 rows
+// (narrow: half the bytes per gathered row) while every count fits; a count
+// that does not fit raises kCtlNarrow and the batch is run again with double
+// rows (wide), where a count beyond double's range raises kCtlRange.  A split
+// vertex's chunks add their partial sums into a double row of its own (exact
+// integer adds in any order, no returned values), which the completion kernel
+// stores into the vertex's sigma row.
+template <bool N> struct SigRows;
+
+template <> struct SigRows<true> {
+    using T = uint32_t;
+    __device__ static T *rows(const BatchDev &d) { return d.sigma32; }
+    // a complete sum (exact in double)
+    __device__ static void store(const BatchDev &d, size_t at, double acc) {
+        if (acc >= 4294967296.0) atomicOr(&d.ctrl[kCtlNarrow], 1);
+        d.sigma32[at] = (uint32_t)fmin(acc, 4294967295.0);
+    }
+};
+
+template <> struct SigRows<false> {
+    using T = double;
+    __device__ static T *rows(const BatchDev &d) { return d.sigma; }
+    __device__ static void store(const BatchDev &d, size_t at, double acc) {
+        d.sigma[at] = acc;
+        if (!isfinite(acc)) atomicOr(&d.ctrl[kCtlRange], 1);
+    }
+};
+
+template <bool N>
+__device__ __forceinline__ double sig_at(const BatchDev &d, size_t at) {
+    return (double)SigRows<N>::rows(d)[at];
 }
 
 // ---- forward ---------------------------------------------------------------
@@ -224,6 +274,7 @@ __device__ void report_front(const BatchDev &d, int set, const Front &fr) {
 }
 
 // Chunk item of a vertex of degree > 64.
+template <bool N>
 __device__ void fwd_chunk(const BatchDev &d, int32_t L, uint32_t item, uint64_t full, Work &wk,
                           Front &fr) {
     const int lane = lane_id();
@@ -241,14 +292,12 @@ __device__ void fwd_chunk(const BatchDev &d, int32_t L, uint32_t item, uint64_t 
     const uint64_t *FL = d.F + (size_t)L * (size_t)d.n;
     const int32_t cb = rs + j * kChunk;
     double acc = 0.0;
-    const uint64_t nw = probe_chunk(d, cb, min(re, cb + kChunk), FL, unvis, d.sigma, acc, wk);
+    const uint64_t nw =
+        probe_chunk(d, cb, min(re, cb + kChunk), FL, unvis, SigRows<N>::rows(d), acc, wk);
     const bool mine = (nw >> lane) & 1ull;
     if (mine && (!multi || j == 0)) ++wk.owners;
     if (!multi) {
-        if (mine) {
-            d.sigma[(size_t)w * kWave + lane] = acc;
-            if (!isfinite(acc)) atomicOr(&d.ctrl[kCtlRange], 1);
-        }
+        if (mine) SigRows<N>::store(d, (size_t)w * kWave + lane, acc);
         if (lane == 0) {
             FN[w] = nw;
             if (nw) {
@@ -258,8 +307,7 @@ __device__ void fwd_chunk(const BatchDev &d, int32_t L, uint32_t item, uint64_t 
             }
         }
     } else if (nw) {
-        // integer sums: the atomic adds are exact in any order
-        if (mine) unsafeAtomicAdd(&d.sigma[(size_t)w * kWave + lane], acc);
+        if (mine) unsafeAtomicAdd(&d.hubsig[(size_t)w * kWave + lane], acc);
         if (lane == 0) atomicOr((unsigned long long *)&d.reach[w], (unsigned long long)nw);
     }
 }
@@ -268,6 +316,7 @@ __device__ void fwd_chunk(const BatchDev &d, int32_t L, uint32_t item, uint64_t 
 // <= 64, F_{L+1} written for every one) or list[base .. base+63] (sparse step:
 // candidates of any degree, F_{L+1} cleared beforehand).  The wave flattens
 // the arcs of the vertices that still have unvisited lanes into runs of 64.
+template <bool N>
 __device__ void fwd_group(const BatchDev &d, int32_t L, int32_t base, const int32_t *list,
                           int32_t count, uint64_t full, Work &wk, Front &fr) {
     const int lane = lane_id();
@@ -300,8 +349,7 @@ __device__ void fwd_group(const BatchDev &d, int32_t L, int32_t base, const int3
             const uint64_t w_vis = ~shfl64(unvis, cur) & full;
             const int32_t w_deg = __shfl(cnt, cur);
             if ((nw >> lane) & 1ull) {
-                d.sigma[(size_t)w * kWave + lane] = acc;
-                if (!isfinite(acc)) atomicOr(&d.ctrl[kCtlRange], 1);
+                SigRows<N>::store(d, (size_t)w * kWave + lane, acc);
                 ++wk.owners;
             }
             if (lane == 0) {
@@ -343,7 +391,7 @@ __device__ void fwd_group(const BatchDev &d, int32_t L, int32_t base, const int3
                 double x[kUnroll];
                 uint64_t mj[kUnroll];
                 int oj[kUnroll];
-                gather_run(hit, nb[r], m[r], o[r], d.sigma, x, mj, oj, wk);
+                gather_run(hit, nb[r], m[r], o[r], SigRows<N>::rows(d), x, mj, oj, wk);
 #pragma unroll
                 for (int u = 0; u < kUnroll; ++u) {
                     if (oj[u] < 0) break;
@@ -362,6 +410,7 @@ __device__ void fwd_group(const BatchDev &d, int32_t L, int32_t base, const int3
     flush();
 }
 
+template <bool N>
 __global__ __launch_bounds__(kBlock) void k_batch_forward(BatchDev d, int32_t L, uint64_t full) {
     // nothing past the deepest level found so far (F_L is empty), no room, or
     // this level takes the sparse step
@@ -373,8 +422,9 @@ __global__ __launch_bounds__(kBlock) void k_batch_forward(BatchDev d, int32_t L,
     Work wk;
     Front fr;
     for (uint32_t it = wave; it < items + groups; it += nwaves) {
-        if (it < items) fwd_chunk(d, L, it, full, wk, fr);
-        else fwd_group(d, L, d.big_end + (int32_t)(it - items) * kWave, nullptr, 0, full, wk, fr);
+        if (it < items) fwd_chunk<N>(d, L, it, full, wk, fr);
+        else fwd_group<N>(d, L, d.big_end + (int32_t)(it - items) * kWave, nullptr, 0, full, wk,
+                          fr);
     }
     report_front(d, 0, fr);
     if (d.stats) report_work(d.stats, wk);
@@ -382,6 +432,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_forward(BatchDev d, int32_t L,
 
 // After a forward iteration: completes the split vertices, records the depth
 // (or the truncation when the level array is full), clears the flag.
+template <bool N>
 __global__ __launch_bounds__(kBlock) void k_batch_forward_finish(BatchDev d, int32_t L,
                                                                  uint64_t full) {
     if (L > d.ctrl[kCtlDeepest] || L + 1 >= d.lcap) return;
@@ -395,7 +446,8 @@ __global__ __launch_bounds__(kBlock) void k_batch_forward_finish(BatchDev d, int
         if (lane == 0) FN[w] = nw;
         if (nw == 0ull) continue;
         if ((nw >> lane) & 1ull) {
-            if (!isfinite(d.sigma[(size_t)w * kWave + lane])) atomicOr(&d.ctrl[kCtlRange], 1);
+            const size_t at = (size_t)w * kWave + lane;
+            SigRows<N>::store(d, at, d.hubsig[at]);
         }
         if (lane == 0) {
             d.vis[w] |= nw;
@@ -575,6 +627,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_sparse_compact(BatchDev d, int
 }
 
 // Pull over the candidates only (groups of 64 list entries).
+template <bool N>
 __global__ __launch_bounds__(kBlock) void k_batch_sparse_pull(BatchDev d, int32_t L,
                                                               uint64_t full) {
     if (L > d.ctrl[kCtlDeepest] || L + 1 >= d.lcap || !d.ctrl[kCtlMode]) return;
@@ -586,8 +639,8 @@ __global__ __launch_bounds__(kBlock) void k_batch_sparse_pull(BatchDev d, int32_
     Work wk;
     Front fr;
     for (int32_t it = wave; it < ni + groups; it += nwaves) {
-        if (it < ni) fwd_chunk(d, L, (uint32_t)d.ilist[it], full, wk, fr);
-        else fwd_group(d, L, (it - ni) * kWave, d.clist, c, full, wk, fr);
+        if (it < ni) fwd_chunk<N>(d, L, (uint32_t)d.ilist[it], full, wk, fr);
+        else fwd_group<N>(d, L, (it - ni) * kWave, d.clist, c, full, wk, fr);
     }
     report_front(d, 1, fr);
     if (d.stats) report_work(d.stats, wk);
@@ -632,6 +685,7 @@ __device__ __forceinline__ void settle(const BatchDev &d, int32_t v, uint64_t mv
 // Chunk item of a vertex of degree > 64: sums of c over children; a vertex
 // with one chunk is completed here, a split vertex leaves the item's partial
 // row for the finalising pass.
+template <bool N>
 __device__ void bwd_chunk(const BatchDev &d, int32_t L, uint32_t item, Work &wk) {
     const int lane = lane_id();
     const int2 info = d.item_info[item];
@@ -642,7 +696,7 @@ __device__ void bwd_chunk(const BatchDev &d, int32_t L, uint32_t item, Work &wk)
     const int32_t rs = d.row_ptr[v], re = d.row_ptr[v + 1];
     const int32_t cb = rs + j * kChunk;
     const bool on = (mv >> lane) & 1ull;
-    const double sig = (on && v >= d.multi_end) ? d.sigma[(size_t)v * kWave + lane] : 1.0;
+    const double sig = (on && v >= d.multi_end) ? sig_at<N>(d, (size_t)v * kWave + lane) : 1.0;
     double acc = 0.0;
     (void)probe_chunk(d, cb, min(re, cb + kChunk), FC, mv, d.coef, acc, wk);
     if (on && j == 0) ++wk.owners;
@@ -650,6 +704,7 @@ __device__ void bwd_chunk(const BatchDev &d, int32_t L, uint32_t item, Work &wk)
     else settle(d, v, mv, sig, acc);
 }
 
+template <bool N>
 __device__ void bwd_group(const BatchDev &d, int32_t L, int32_t base, Work &wk) {
     const int lane = lane_id();
     const uint64_t *FL = d.F + (size_t)L * (size_t)d.n;
@@ -712,7 +767,7 @@ __device__ void bwd_group(const BatchDev &d, int32_t L, int32_t base, Work &wk) 
                         acc = 0.0;
                         pending &= ~(1ull << cur);
                         const bool on = (shfl64(mv, cur) >> lane) & 1ull;
-                        cur_sig = on ? d.sigma[(size_t)(base + cur) * kWave + lane] : 1.0;
+                        cur_sig = on ? sig_at<N>(d, (size_t)(base + cur) * kWave + lane) : 1.0;
                     }
                     acc += x[u];
                 }
@@ -738,13 +793,14 @@ __device__ void bwd_group(const BatchDev &d, int32_t L, int32_t base, Work &wk) 
         double sig[kUnroll];
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u)
-            sig[u] = on[u] ? d.sigma[(size_t)vj[u] * kWave + lane] : 1.0;
+            sig[u] = on[u] ? sig_at<N>(d, (size_t)vj[u] * kWave + lane) : 1.0;
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u)
             if (on[u]) d.coef[(size_t)vj[u] * kWave + lane] = 1.0 / sig[u];
     }
 }
 
+template <bool N>
 __global__ __launch_bounds__(kBlock) void k_batch_reverse(BatchDev d, int32_t L) {
     const uint32_t items = d.items;
     const uint32_t groups = (uint32_t)((d.n - d.big_end + kWave - 1) / kWave);
@@ -752,8 +808,8 @@ __global__ __launch_bounds__(kBlock) void k_batch_reverse(BatchDev d, int32_t L)
     const uint32_t nwaves = gridDim.x * kWavesPerBlock;
     Work wk;
     for (uint32_t it = wave; it < items + groups; it += nwaves) {
-        if (it < items) bwd_chunk(d, L, it, wk);
-        else bwd_group(d, L, d.big_end + (int32_t)(it - items) * kWave, wk);
+        if (it < items) bwd_chunk<N>(d, L, it, wk);
+        else bwd_group<N>(d, L, d.big_end + (int32_t)(it - items) * kWave, wk);
     }
     if (d.stats) report_work(d.stats + 6, wk);
 }
@@ -763,6 +819,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_reverse(BatchDev d, int32_t L)
 // chunks added in chunk order, or, with leaf set (the deepest level), every
 // vertex, with sum 0.  delta = sigma * sum, c = (1 + delta) / sigma, BC[v] +=
 // the lanes' deltas.
+template <bool N>
 __global__ __launch_bounds__(kBlock) void k_batch_finalize(BatchDev d, int32_t L, int32_t leaf) {
     const int lane = lane_id();
     const uint64_t *FL = d.F + (size_t)L * (size_t)d.n;
@@ -797,7 +854,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_finalize(BatchDev d, int32_t L
             for (int u = 0; u < kFinal; ++u) {
                 const bool on = (mj[u] >> lane) & 1ull;
                 const size_t at = (size_t)(vj[u] < 0 ? 0 : vj[u]) * kWave + lane;
-                sig[u] = on ? d.sigma[at] : 1.0;
+                sig[u] = on ? sig_at<N>(d, at) : 1.0;
                 sum[u] = 0.0;
                 if (on && !leaf) {
                     // the chunks' partial rows in chunk order, 8 loads in flight
@@ -849,6 +906,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_finalize(BatchDev d, int32_t L
 
 // vis = 0 and F_0 = 0 everywhere; the split vertices' sigma rows and reach
 // masks are cleared for the atomic combine.
+template <bool N>
 __global__ void k_batch_clear(BatchDev d) {
     const int32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
     const int32_t stride = gridDim.x * blockDim.x;
@@ -861,12 +919,13 @@ __global__ void k_batch_clear(BatchDev d) {
     for (int32_t i = tid; i < groups; i += stride)
         reinterpret_cast<uint4 *>(d.cand)[i] = make_uint4(0u, 0u, 0u, 0u);
     const int64_t rows = (int64_t)d.multi_end * kWave;
-    for (int64_t i = tid; i < rows; i += stride) d.sigma[i] = 0.0;
+    for (int64_t i = tid; i < rows; i += stride) d.hubsig[i] = 0.0;
     if (blockIdx.x == 0 && threadIdx.x < kCtlInts) d.ctrl[threadIdx.x] = 0;
 }
 
 // Seed lane s with its source; the first iteration's step is chosen from the
 // distinct sources' arc count.
+template <bool N>
 __global__ void k_batch_seed(BatchDev d, const int32_t *src, int32_t nlanes) {
     const int lane = threadIdx.x;
     int32_t s = -1;
@@ -877,7 +936,7 @@ __global__ void k_batch_seed(BatchDev d, const int32_t *src, int32_t nlanes) {
         const unsigned long long old =
             atomicOr((unsigned long long *)&d.F[s], 1ull << lane);
         first = old == 0ull;  // exactly one lane per distinct source
-        d.sigma[(size_t)s * kWave + lane] = 1.0;
+        SigRows<N>::rows(d)[(size_t)s * kWave + lane] = 1;
     }
     const int32_t deg = first ? d.row_ptr[s + 1] - d.row_ptr[s] : 0;
     unsigned long long arcs = (unsigned long long)deg;
@@ -887,6 +946,7 @@ __global__ void k_batch_seed(BatchDev d, const int32_t *src, int32_t nlanes) {
 }
 
 // dist[s][v] and sigma[s][v] of lane s (internal vertex order), s < nlanes.
+template <bool N>
 __global__ void k_batch_export(BatchDev d, int32_t deepest, int32_t nlanes, int32_t *dist,
                                double *sigma) {
     for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < d.n;
@@ -903,7 +963,7 @@ __global__ void k_batch_export(BatchDev d, int32_t deepest, int32_t nlanes, int3
             }
             if (dist) dist[(size_t)s * d.n + v] = lev;
             if (sigma)
-                sigma[(size_t)s * d.n + v] = lev >= 0 ? d.sigma[(size_t)v * kWave + s] : 0.0;
+                sigma[(size_t)s * d.n + v] = lev >= 0 ? sig_at<N>(d, (size_t)v * kWave + s) : 0.0;
         }
     }
 }
@@ -921,10 +981,10 @@ hipError_t batch_start(const BatchDev &d, const int32_t *src_dev, int32_t nlanes
                        hipStream_t stream) {
     int grid = (d.n + kBlock - 1) / kBlock;
     grid = grid < 1 ? 1 : (grid > 4096 ? 4096 : grid);
-    hipLaunchKernelGGL(k_batch_clear, dim3(grid), dim3(kBlock), 0, stream, d);
+    hipLaunchKernelGGL(d.narrow ? k_batch_clear<true> : k_batch_clear<false>, dim3(grid), dim3(kBlock), 0, stream, d);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_batch_seed, dim3(1), dim3(kWave), 0, stream, d, src_dev, nlanes);
+    hipLaunchKernelGGL(d.narrow ? k_batch_seed<true> : k_batch_seed<false>, dim3(1), dim3(kWave), 0, stream, d, src_dev, nlanes);
     return hipGetLastError();
 }
 
@@ -932,7 +992,7 @@ hipError_t batch_forward(const BatchDev &d, int32_t level, uint64_t full, hipStr
     // both steps are launched; each returns at once unless the mode chosen on
     // the device for this level is its own
     const int64_t groups = (d.n - d.big_end + kWave - 1) / kWave;
-    hipLaunchKernelGGL(k_batch_forward, dim3(grid_of(d.items + groups)), dim3(kBlock), 0, stream,
+    hipLaunchKernelGGL(d.narrow ? k_batch_forward<true> : k_batch_forward<false>, dim3(grid_of(d.items + groups)), dim3(kBlock), 0, stream,
                        d, level, full);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -943,7 +1003,7 @@ hipError_t batch_forward(const BatchDev &d, int32_t level, uint64_t full, hipStr
                        dim3(kBlock), 0, stream, d, level, full);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_batch_sparse_pull, dim3(kSparseGrid), dim3(kBlock), 0, stream, d, level,
+    hipLaunchKernelGGL(d.narrow ? k_batch_sparse_pull<true> : k_batch_sparse_pull<false>, dim3(kSparseGrid), dim3(kBlock), 0, stream, d, level,
                        full);
     return hipGetLastError();
 }
@@ -951,7 +1011,7 @@ hipError_t batch_forward(const BatchDev &d, int32_t level, uint64_t full, hipStr
 hipError_t batch_forward_done(const BatchDev &d, int32_t level, uint64_t full,
                               hipStream_t stream) {
     if (d.multi_end > 0) {
-        hipLaunchKernelGGL(k_batch_forward_finish, dim3(grid_of(d.multi_end)), dim3(kBlock), 0,
+        hipLaunchKernelGGL(d.narrow ? k_batch_forward_finish<true> : k_batch_forward_finish<false>, dim3(grid_of(d.multi_end)), dim3(kBlock), 0,
                            stream, d, level, full);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
@@ -966,7 +1026,7 @@ hipError_t batch_forward_done(const BatchDev &d, int32_t level, uint64_t full,
 
 hipError_t batch_reverse(const BatchDev &d, int32_t level, hipStream_t stream) {
     const int64_t groups = (d.n - d.big_end + kWave - 1) / kWave;
-    hipLaunchKernelGGL(k_batch_reverse, dim3(grid_of(d.items + groups)), dim3(kBlock), 0, stream,
+    hipLaunchKernelGGL(d.narrow ? k_batch_reverse<true> : k_batch_reverse<false>, dim3(grid_of(d.items + groups)), dim3(kBlock), 0, stream,
                        d, level);
     return hipGetLastError();
 }
@@ -974,7 +1034,7 @@ hipError_t batch_reverse(const BatchDev &d, int32_t level, hipStream_t stream) {
 hipError_t batch_finalize(const BatchDev &d, int32_t level, bool deepest, hipStream_t stream) {
     const int32_t vend = deepest ? d.n : d.multi_end;
     if (vend == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_batch_finalize, dim3(grid_of((vend + kWave - 1) / kWave)), dim3(kBlock),
+    hipLaunchKernelGGL(d.narrow ? k_batch_finalize<true> : k_batch_finalize<false>, dim3(grid_of((vend + kWave - 1) / kWave)), dim3(kBlock),
                        0, stream, d, level, deepest ? 1 : 0);
     return hipGetLastError();
 }
@@ -983,7 +1043,7 @@ hipError_t batch_export(const BatchDev &d, int32_t deepest, int32_t nlanes, int3
                         double *sigma, hipStream_t stream) {
     int grid = (d.n + kBlock - 1) / kBlock;
     grid = grid < 1 ? 1 : (grid > 4096 ? 4096 : grid);
-    hipLaunchKernelGGL(k_batch_export, dim3(grid), dim3(kBlock), 0, stream, d, deepest, nlanes,
+    hipLaunchKernelGGL(d.narrow ? k_batch_export<true> : k_batch_export<false>, dim3(grid), dim3(kBlock), 0, stream, d, deepest, nlanes,
                        dist, sigma);
     return hipGetLastError();
 }

@@ -148,6 +148,9 @@ struct bc_graph_s {
     std::atomic<int32_t> tuned_width{kWave};
     std::atomic<int32_t> tuned_sparse_div{kDefaultSparseDiv};
     std::atomic<int32_t> tuned_min_batched{16};
+    // set once a path count did not fit the batched path's uint32 sigma rows:
+    // later batches start with double rows
+    std::atomic<bool> sigma_wide{false};
     // hop distances (internal order, -1 unreached) from two landmarks: the
     // highest-degree vertex and the vertex farthest from it; batches are formed
     // from sources sorted by them
@@ -507,6 +510,7 @@ size_t batch_ws_bytes(const bc_graph_s *g) {
     b += align_up(kBatchCtrlInts * sizeof(int32_t));     // ctrl
     b += align_up(n * sizeof(double));                   // bc
     b += align_up((size_t)std::max(g->multi_end, 1) * sizeof(uint64_t));  // reach
+    b += align_up((size_t)std::max(g->multi_end, 1) * kWave * sizeof(double));  // hub sums
     b += align_up((size_t)std::max<uint32_t>(g->items, 1) * kWave * sizeof(double));  // partial
     b += align_up(12 * sizeof(unsigned long long));     // work counters
     b += align_up(n * sizeof(int32_t));                  // candidate list
@@ -560,10 +564,13 @@ bc_status batch_ws_create(bc_graph_s *g, BatchWS **out) {
     d.col_idx = g->d_col_idx;
     d.vis = (uint64_t *)take(n * sizeof(uint64_t));
     d.sigma = (double *)take(n * kWave * sizeof(double));
+    d.sigma32 = reinterpret_cast<uint32_t *>(d.sigma);
+    d.narrow = 1;
     d.coef = (double *)take(n * kWave * sizeof(double));
     d.ctrl = (int32_t *)take(kBatchCtrlInts * sizeof(int32_t));
     d.bc = (double *)take(n * sizeof(double));
     d.reach = (uint64_t *)take((size_t)std::max(g->multi_end, 1) * sizeof(uint64_t));
+    d.hubsig = (double *)take((size_t)std::max(g->multi_end, 1) * kWave * sizeof(double));
     d.partial = (double *)take((size_t)std::max<uint32_t>(g->items, 1) * kWave * sizeof(double));
     d.big_end = g->big_end;
     d.multi_end = g->multi_end;
@@ -760,6 +767,7 @@ bc_status run_batch_plan(bc_graph_s *g, const std::vector<int32_t> &s_int,
         d.seg_start = bp.nseg ? d_seg_start + bp.seg_first : nullptr;
         d.seg_out = bp.nseg ? d_seg_out + (bp.seg_first - (int32_t)bi) : nullptr;
         d.iperm = g->d_iperm;
+        d.narrow = g->sigma_wide.load() ? 0 : 1;
         e = batch_start(d, d_lanes + bp.first, nl, stream);
         if (e != hipSuccess) return fail(from_hip(e));
         int32_t deepest = 0;
@@ -782,6 +790,11 @@ bc_status run_batch_plan(bc_graph_s *g, const std::vector<int32_t> &s_int,
             if (e == hipSuccess) e = hipStreamSynchronize(stream);
             if (e != hipSuccess) return fail(from_hip(e));
             deepest = ws->h_ctrl[0];
+            if (ws->h_ctrl[kCtlNarrow]) {  // a path count needs double rows: run again
+                g->sigma_wide.store(true);
+                restart = true;
+                break;
+            }
             if (ws->h_ctrl[2]) {  // level array full: grow it and run the batch again
                 st = batch_grow_levels(g, ws, ws->lcap * 2);
                 if (st != BC_OK) return fail(st);

@@ -97,8 +97,11 @@ struct BatchDev {
     const uint32_t *item_first;  // [big_end + 1]
     uint64_t *vis;         // [n] sources that reached v
     uint64_t *F;           // [lcap][n] F[L][v]: sources at distance L from v
-    double *sigma;         // [n][64]
-    double *coef;          // [n][64] (1 + delta) / sigma; child sums while a level runs
+    double *sigma;         // [n][64] path counts as doubles (wide rows)
+    uint32_t *sigma32;     // [n][64] the same memory as exact uint32 counts (narrow rows)
+    double *hubsig;        // [multi_end][64] split vertices' sums, added by their chunks
+    int32_t narrow;        // 1: sigma32 rows are in use
+    double *coef;          // [n][64] (1 + delta) / sigma
     uint64_t *reach;       // [multi_end] sources reaching a split vertex this iteration
     double *partial;       // [items][64] reverse child sums per chunk item
     int32_t *ctrl;         // see kCtl* below
@@ -130,6 +133,7 @@ enum {
     kCtlMode = 3,      // 1: the running iteration takes the sparse forward step
     kCtlCand = 4,      // candidates listed by the sparse step
     kCtlItems = 5,     // chunk items listed by the sparse step
+    kCtlNarrow = 6,    // a path count does not fit the uint32 sigma rows
     kCtlInts = 8
 };
 

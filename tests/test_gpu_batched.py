@@ -224,3 +224,49 @@ def test_autotune_then_auto_mode():
             want = oracle_bc(g, src[:k])
             check_bc(G.run(src[:k]), want)
             check_bc(run_mode(G, src[:k], bcm.BC_MODE_AUTO), want)
+
+
+def _diamond_chain(k, fan=0):
+    """k diamonds in series (0 -> {1, 2} -> 3 -> {4, 5} -> 6 ...): sigma doubles at
+    each diamond end, 2**k at the last.  With fan > 0 the last vertex fans out to
+    `fan` vertices that all meet in one hub, whose sigma is fan * 2**k."""
+    u, v = [], []
+    for i in range(k):
+        a = 3 * i
+        for b in (a + 1, a + 2):
+            u += [a, b]
+            v += [b, a + 3]
+    end = 3 * k
+    n = end + 1
+    if fan:
+        hub = n + fan
+        for j in range(fan):
+            u += [end, n + j]
+            v += [n + j, hub]
+        n = hub + 1
+    return gg.csr_from_edges(n, np.array(u), np.array(v))
+
+
+@pytest.mark.parametrize("k,fan", [(31, 0), (32, 0), (33, 0), (22, 1023), (22, 1024)],
+                         ids=["2^31", "2^32", "2^33", "hub-below-2^32", "hub-at-2^32"])
+def test_path_counts_around_the_uint32_rows(k, fan):
+    """Path counts kept as exact uint32 rows while they fit: a count of 2**32 or
+    more (also when a split hub's chunks add up to it) reruns the batch with
+    double rows; sigma stays bit-exact and BC matches the oracle either way, and
+    later runs on the same graph agree."""
+    g = _diamond_chain(k, fan)
+    src = np.array([0, 1, 3 * k, 5], np.int32)
+    with bcm.Graph(g.n, g.row_ptr, g.col_idx) as G:
+        opt = bcm.make_options(bcm.BC_MODE_BATCHED)
+        got, dist, sigma = G.run_detail(src, opt)
+        again, _, _ = G.run_detail(src, opt)
+    check_bc(got, oracle_bc(g, src))
+    assert np.array_equal(got, again)
+    for i, s in enumerate(src):
+        od, osg, _, _ = oracle.single_source(g.row_ptr, g.col_idx, int(s), with_delta=False)
+        assert np.array_equal(dist[i], od)
+        assert np.array_equal(sigma[i], osg)
+    if fan:
+        assert sigma[0].max() == fan * 2.0 ** k
+    else:
+        assert sigma[0].max() == 2.0 ** k
