@@ -86,7 +86,11 @@ typedef struct bc_options {
                             the frontier's neighbours) instead of scanning every
                             unvisited vertex; 1..2^20, -1 = never, 0 = the graph's
                             setting (bc_autotune's choice, else 64)                      */
-    int32_t reserved[4]; /* must be zero                                                 */
+    int32_t concurrency; /* batched mode: batches run at once, each with its own
+                            workspace and stream, 1..8 (0 = by workspace size: 4 up to
+                            1 GB, 2 up to 8 GB, else 1); BC is the sum of the parts in
+                            a fixed order, identical from run to run for one setting   */
+    int32_t reserved[3]; /* must be zero                                                 */
 } bc_options;
 
 /*

@@ -63,10 +63,10 @@ def _stream_handle(stream):
 
 
 def make_options(mode: int = BC_MODE_AUTO, batch_width: int = 0, level_chunk: int = 0,
-                 sparse_div: int = 0):
+                 sparse_div: int = 0, concurrency: int = 0):
     o = bc_options()
     o.mode, o.batch_width, o.level_chunk = int(mode), int(batch_width), int(level_chunk)
-    o.sparse_div = int(sparse_div)
+    o.sparse_div, o.concurrency = int(sparse_div), int(concurrency)
     return o
 
 

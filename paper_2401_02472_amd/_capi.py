@@ -45,7 +45,7 @@ PROF_CLASS_NAMES = ("forward", "compact", "reverse", "finish")
 class bc_options(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("batch_width", ctypes.c_int32),
                 ("level_chunk", ctypes.c_int32), ("sparse_div", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 4)]
+                ("concurrency", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
 
 
 class bc_tuning(ctypes.Structure):

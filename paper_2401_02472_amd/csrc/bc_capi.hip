@@ -11,6 +11,7 @@
 #include <atomic>
 #include <cstring>
 #include <mutex>
+#include <thread>
 #include <new>
 #include <vector>
 
@@ -151,6 +152,9 @@ struct bc_graph_s {
     // set once a path count did not fit the batched path's uint32 sigma rows:
     // later batches start with double rows
     std::atomic<bool> sigma_wide{false};
+    // internal streams for batches run at once (created on first use)
+    std::mutex stream_mu;
+    std::vector<hipStream_t> streams;
     // hop distances (internal order, -1 unreached) from two landmarks: the
     // highest-degree vertex and the vertex farthest from it; batches are formed
     // from sources sorted by them
@@ -845,9 +849,34 @@ bc_status run_batch_plan(bc_graph_s *g, const std::vector<int32_t> &s_int,
 
 // BC over the sources with up to `width` sources per batch.  With dist /
 // sigma (device, caller order, [k][n]), the per-source state is exported too.
+// Batches run at once for `concurrency` (0: by workspace size; the choice
+// depends only on the graph and the batch count, so results are identical
+// from run to run).  Parts overlap one another's small kernels and host
+// polls; beyond the process's 4 hardware queues they gain nothing, and the
+// large graphs' level kernels already fill the device.
+int32_t parts_of(const bc_graph_s *g, int32_t concurrency, int32_t nbatches) {
+    int32_t p = concurrency;
+    if (p <= 0) {
+        const size_t ws = batch_ws_bytes(g) + batch_level_bytes(g, 16);
+        p = ws <= ((size_t)1 << 30) ? 4 : (ws <= ((size_t)8 << 30) ? 2 : 1);
+    }
+    return std::max(1, std::min(p, nbatches));
+}
+
+bc_status get_streams(bc_graph_s *g, int32_t p, std::vector<hipStream_t> &out) {
+    std::lock_guard<std::mutex> lk(g->stream_mu);
+    while ((int32_t)g->streams.size() < p) {
+        hipStream_t st = nullptr;
+        BC_TRY_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+        g->streams.push_back(st);
+    }
+    out.assign(g->streams.begin(), g->streams.begin() + p);
+    return BC_OK;
+}
+
 bc_status batched_run(bc_graph_s *g, const int32_t *sources, int32_t k, double *bc_out,
-                      int32_t width, int32_t sparse_div, hipStream_t stream, int32_t *dist,
-                      double *sigma) {
+                      int32_t width, int32_t sparse_div, int32_t concurrency,
+                      hipStream_t stream, int32_t *dist, double *sigma) {
     // Batch composition: sources sorted by their distances to the two
     // landmarks, so that the 64 sources of a batch lie close together and see
     // most vertices at the same level (their frontier masks share lanes, the
@@ -871,8 +900,68 @@ bc_status batched_run(bc_graph_s *g, const int32_t *sources, int32_t k, double *
     for (int32_t i = 0; i < k; ++i) s_int[(size_t)i] = g->h_perm[(size_t)sources[order[(size_t)i]]];
     std::vector<BatchPlan> plan;
     for (int32_t b0 = 0; b0 < k; b0 += width) plan.push_back({b0, std::min(width, k - b0), 0, 0});
-    return run_batch_plan(g, s_int, plan, {}, {}, bc_out, stream, order.data(), dist, sigma,
-                          sparse_div);
+    const int32_t P = parts_of(g, concurrency, (int32_t)plan.size());
+    if (P <= 1)
+        return run_batch_plan(g, s_int, plan, {}, {}, bc_out, stream, order.data(), dist, sigma,
+                              sparse_div);
+    // P parts of consecutive batches, each on its own stream and workspace,
+    // ordered after the caller's earlier work; BC = the parts' sum in part
+    // order, on the caller's stream
+    std::vector<hipStream_t> streams;
+    bc_status st = get_streams(g, P, streams);
+    if (st != BC_OK) return st;
+    const size_t n = (size_t)g->n;
+    double *parts = nullptr;
+    hipEvent_t ev_start = nullptr;
+    std::vector<hipEvent_t> ev_done((size_t)P, nullptr);
+    auto cleanup = [&]() {
+        if (parts) (void)hipFree(parts);
+        if (ev_start) (void)hipEventDestroy(ev_start);
+        for (hipEvent_t ev : ev_done)
+            if (ev) (void)hipEventDestroy(ev);
+    };
+    hipError_t e = hipMalloc(&parts, (size_t)P * n * sizeof(double));
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ev_start, hipEventDisableTiming);
+    for (int32_t i = 0; i < P && e == hipSuccess; ++i)
+        e = hipEventCreateWithFlags(&ev_done[(size_t)i], hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventRecord(ev_start, stream);
+    for (int32_t i = 0; i < P && e == hipSuccess; ++i) e = hipStreamWaitEvent(streams[i], ev_start, 0);
+    if (e != hipSuccess) {
+        cleanup();
+        return from_hip(e);
+    }
+    const int32_t nb = (int32_t)plan.size();
+    std::vector<bc_status> status((size_t)P, BC_OK);
+    std::vector<std::thread> workers;
+    for (int32_t i = 0; i < P; ++i) {
+        workers.emplace_back([&, i]() {
+            DeviceGuard dg(g->device);
+            const int32_t b0 = (int32_t)((int64_t)nb * i / P), b1 = (int32_t)((int64_t)nb * (i + 1) / P);
+            std::vector<BatchPlan> sub(plan.begin() + b0, plan.begin() + b1);
+            status[(size_t)i] = run_batch_plan(g, s_int, sub, {}, {}, parts + (size_t)i * n,
+                                               streams[(size_t)i], order.data(), dist, sigma,
+                                               sparse_div);
+            if (hipEventRecord(ev_done[(size_t)i], streams[(size_t)i]) != hipSuccess &&
+                status[(size_t)i] == BC_OK)
+                status[(size_t)i] = BC_ERR_DEVICE;
+        });
+    }
+    for (std::thread &t : workers) t.join();
+    bc_status result = BC_OK;
+    for (bc_status s2 : status) {
+        if (s2 != BC_OK && s2 != BC_ERR_RANGE) {
+            result = s2;
+            break;
+        }
+        if (s2 == BC_ERR_RANGE) result = BC_ERR_RANGE;
+    }
+    for (int32_t i = 0; i < P && e == hipSuccess; ++i) e = hipStreamWaitEvent(stream, ev_done[i], 0);
+    if (e == hipSuccess && (result == BC_OK || result == BC_ERR_RANGE))
+        e = sum_parts(g->n, parts, P, bc_out, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    cleanup();
+    if (e != hipSuccess) return from_hip(e);
+    return result;
 }
 
 // Several requests in one run.  A request of at most 64 sources never
@@ -951,7 +1040,8 @@ bc_status check_options(const bc_options *opt) {
     if (opt->batch_width < 0 || opt->batch_width > 64) return BC_ERR_INVALID_ARG;
     if (opt->level_chunk < 0 || opt->level_chunk > 1024) return BC_ERR_INVALID_ARG;
     if (opt->sparse_div < -1 || opt->sparse_div > (1 << 20)) return BC_ERR_INVALID_ARG;
-    for (int i = 0; i < 4; ++i)
+    if (opt->concurrency < 0 || opt->concurrency > kMaxParts) return BC_ERR_INVALID_ARG;
+    for (int i = 0; i < 3; ++i)
         if (opt->reserved[i] != 0) return BC_ERR_INVALID_ARG;
     return BC_OK;
 }
@@ -1157,6 +1247,8 @@ bc_status bc_destroy_graph(bc_graph_t g) {
     DeviceGuard dg(g->device);
     for (PlainWS *ws : g->plain_pool) plain_ws_destroy(ws);
     g->plain_pool.clear();
+    for (hipStream_t st : g->streams) (void)hipStreamDestroy(st);
+    g->streams.clear();
     for (BatchWS *ws : g->batch_pool) batch_ws_destroy(ws);
     g->batch_pool.clear();
     if (g->d_row_ptr) (void)hipFree(g->d_row_ptr);
@@ -1188,7 +1280,8 @@ bc_status bc_run_async(bc_graph_t g, const int32_t *sources, int32_t k, double *
     DeviceGuard dg(g->device);
     if (use_batched(g, opt, k))
         return batched_run(g, sources, k, bc_out_dev, batch_width_of(g, opt),
-                           sparse_div_of(g, opt), (hipStream_t)stream, nullptr, nullptr);
+                           sparse_div_of(g, opt), opt ? opt->concurrency : 0,
+                           (hipStream_t)stream, nullptr, nullptr);
     return plain_run(g, sources, k, bc_out_dev, opt, (hipStream_t)stream, nullptr, nullptr);
 }
 
@@ -1202,7 +1295,7 @@ bc_status bc_run(bc_graph_t g, const int32_t *sources, int32_t k, double *bc_out
     BC_TRY_HIP(hipMalloc(&d_bc, (size_t)g->n * sizeof(double)));
     st = use_batched(g, nullptr, k)
              ? batched_run(g, sources, k, d_bc, batch_width_of(g, nullptr),
-                           sparse_div_of(g, nullptr), nullptr, nullptr, nullptr)
+                           sparse_div_of(g, nullptr), 0, nullptr, nullptr, nullptr)
              : plain_run(g, sources, k, d_bc, nullptr, nullptr, nullptr, nullptr);
     if (st == BC_OK || st == BC_ERR_RANGE) {
         hipError_t e = hipMemcpy(bc_out, d_bc, (size_t)g->n * sizeof(double),
@@ -1250,7 +1343,7 @@ bc_status bc_run_detail(bc_graph_t g, const int32_t *sources, int32_t k, const b
     }
     if (batched)
         st = batched_run(g, sources, k, d_bc, batch_width_of(g, opt), sparse_div_of(g, opt),
-                         nullptr, d_dist, d_sigma);
+                         opt ? opt->concurrency : 0, nullptr, d_dist, d_sigma);
     else
         st = plain_run(g, sources, k, d_bc, opt, nullptr, (dist || sigma) ? exp.data() : nullptr,
                        &tmp.t);
@@ -1416,7 +1509,7 @@ bc_status bc_autotune(bc_graph_t g, const int32_t *sources, int32_t k, void *str
         return BC_OK;
     };
     auto batched = [&](int32_t width, int32_t div, double &ms) {
-        return timed([&]() { return batched_run(g, sources, m, d_bc, width, div, stream,
+        return timed([&]() { return batched_run(g, sources, m, d_bc, width, div, 1, stream,
                                                 nullptr, nullptr); }, ms);
     };
     // sparse-step threshold at width 64, then width 32 with the best threshold

@@ -85,6 +85,8 @@ constexpr int kChunk = 512;
 // Default threshold of the batched forward step: a level whose frontier has
 // fewer than nnz / kDefaultSparseDiv arcs expands from the frontier.
 constexpr int kDefaultSparseDiv = 64;
+// Most batches one call runs at once (each with its own workspace and stream).
+constexpr int kMaxParts = 8;
 
 struct BatchDev {
     int32_t n;
@@ -172,6 +174,8 @@ hipError_t relabel_csr(int32_t n, int64_t nnz, const int32_t *old_rp, const int3
 // dst[o] = src[perm[o]] for o < n (internal order -> caller order).
 hipError_t gather_f64(int32_t n, const int32_t *perm, const double *src, double *dst,
                       hipStream_t stream);
+hipError_t sum_parts(int32_t n, const double *parts, int32_t nparts, double *out,
+                     hipStream_t stream);
 hipError_t gather_i32(int32_t n, const int32_t *perm, const int32_t *src, int32_t *dst,
                       hipStream_t stream);
 

@@ -270,3 +270,23 @@ def test_path_counts_around_the_uint32_rows(k, fan):
         assert sigma[0].max() == fan * 2.0 ** k
     else:
         assert sigma[0].max() == 2.0 ** k
+
+
+@pytest.mark.parametrize("conc", [1, 2, 3, 8])
+def test_batches_run_at_once(conc):
+    """Batches split over `conc` concurrent parts (own workspace and stream each):
+    BC matches the oracle, repeats bit for bit, and the per-source rows of every
+    part land in the caller's order."""
+    g = gg.rmat(13, 8, seed=16)
+    src = gg.sample_sources(g, 300, seed=17)
+    opt = bcm.make_options(bcm.BC_MODE_BATCHED, concurrency=conc)
+    with bcm.Graph(g.n, g.row_ptr, g.col_idx) as G:
+        a = batched(G, src, concurrency=conc)
+        b = batched(G, src, concurrency=conc)
+        _, dist, sigma = G.run_detail(src[:130], opt)
+    check_bc(a, oracle_bc(g, src))
+    assert np.array_equal(a, b)
+    for i in (0, 64, 129):
+        od, osg, _, _ = oracle.single_source(g.row_ptr, g.col_idx, int(src[i]), with_delta=False)
+        assert np.array_equal(dist[i], od)
+        assert np.array_equal(sigma[i], osg)
