@@ -90,8 +90,21 @@ typedef struct bc_options {
                             workspace and stream, 1..8 (0 = by workspace size: 4 up to
                             1 GB, 2 up to 8 GB, else 1); BC is the sum of the parts in
                             a fixed order, identical from run to run for one setting   */
-    int32_t reserved[3]; /* must be zero                                                 */
+    int32_t level_loop;  /* batched mode: BC_LOOP_* (who drives the level loop)           */
+    int32_t reserved[2]; /* must be zero                                                 */
 } bc_options;
+
+/* bc_options.level_loop.  HOST: the host launches every level step as
+ * grid-wide kernels and polls the depth.  DEVICE: one workgroup runs a whole
+ * batch (every level, with workgroup barriers) and all batches of the call go
+ * in one launch: for small graphs, where launch and polling costs dominate,
+ * or many batches.  AUTO picks DEVICE for graphs of at most 2^20 arcs, or at
+ * most 2^24 arcs with 32 or more batches. */
+enum {
+    BC_LOOP_AUTO = 0,
+    BC_LOOP_HOST = 1,
+    BC_LOOP_DEVICE = 2
+};
 
 /*
  * Copy an undirected CSR graph to the device and prepare it for runs.

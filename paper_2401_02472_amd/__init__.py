@@ -16,7 +16,8 @@ from . import _capi
 from ._capi import (BC_ERR_DEVICE, BC_ERR_INVALID_ARG, BC_ERR_INVALID_GRAPH,  # noqa: F401
                     BC_ERR_OUT_OF_MEMORY, BC_ERR_RANGE, BC_ERR_UNSUPPORTED,
                     BC_GRAPH_INPUT_ON_DEVICE, BC_GRAPH_TRUST_SYMMETRIC, BC_MODE_AUTO,
-                    BC_MODE_BATCHED, BC_MODE_PLAIN, BC_OK, bc_options)
+                    BC_MODE_BATCHED, BC_MODE_PLAIN, BC_OK, bc_options,
+                    BC_LOOP_AUTO, BC_LOOP_HOST, BC_LOOP_DEVICE)
 
 __all__ = [
     "BCError", "bc_create_graph", "bc_destroy_graph", "bc_graph_info", "bc_run", "bc_run_async",
@@ -63,10 +64,10 @@ def _stream_handle(stream):
 
 
 def make_options(mode: int = BC_MODE_AUTO, batch_width: int = 0, level_chunk: int = 0,
-                 sparse_div: int = 0, concurrency: int = 0):
+                 sparse_div: int = 0, concurrency: int = 0, level_loop: int = 0):
     o = bc_options()
     o.mode, o.batch_width, o.level_chunk = int(mode), int(batch_width), int(level_chunk)
-    o.sparse_div, o.concurrency = int(sparse_div), int(concurrency)
+    o.sparse_div, o.concurrency, o.level_loop = int(sparse_div), int(concurrency), int(level_loop)
     return o
 
 

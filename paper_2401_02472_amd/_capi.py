@@ -34,6 +34,10 @@ EXPORTED = ("bc_create_graph", "bc_destroy_graph", "bc_graph_info", "bc_run", "b
             "bc_run_multi", "bc_single_source", "bc_run_detail", "bc_workspace_bytes", "bc_trim_workspaces",
             "bc_profile_enable", "bc_profile_read", "bc_autotune", "bc_status_str")
 
+BC_LOOP_AUTO = 0
+BC_LOOP_HOST = 1
+BC_LOOP_DEVICE = 2
+
 BC_PROF_FORWARD = 0
 BC_PROF_COMPACT = 1
 BC_PROF_REVERSE = 2
@@ -45,7 +49,8 @@ PROF_CLASS_NAMES = ("forward", "compact", "reverse", "finish")
 class bc_options(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("batch_width", ctypes.c_int32),
                 ("level_chunk", ctypes.c_int32), ("sparse_div", ctypes.c_int32),
-                ("concurrency", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+                ("concurrency", ctypes.c_int32), ("level_loop", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
 
 
 class bc_tuning(ctypes.Structure):

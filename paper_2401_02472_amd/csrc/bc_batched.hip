@@ -430,17 +430,13 @@ __global__ __launch_bounds__(kBlock) void k_batch_forward(BatchDev d, int32_t L,
     if (d.stats) report_work(d.stats, wk);
 }
 
-// After a forward iteration: completes the split vertices, records the depth
-// (or the truncation when the level array is full), clears the flag.
+// After a forward iteration: completes the split vertices (their summed
+// counts, F_{L+1}, vis) and counts them into the new frontier.
 template <bool N>
-__global__ __launch_bounds__(kBlock) void k_batch_forward_finish(BatchDev d, int32_t L,
-                                                                 uint64_t full) {
-    if (L > d.ctrl[kCtlDeepest] || L + 1 >= d.lcap) return;
+__device__ void finish_split(const BatchDev &d, int32_t L, int32_t wave, int32_t nwaves,
+                             Front &fr) {
     uint64_t *FN = d.F + (size_t)(L + 1) * (size_t)d.n;
-    Front fr;
     const int lane = lane_id();
-    const int32_t wave = (blockIdx.x * kBlock + threadIdx.x) / kWave;
-    const int32_t nwaves = gridDim.x * kWavesPerBlock;
     for (int32_t w = wave; w < d.multi_end; w += nwaves) {
         const uint64_t nw = d.reach[w];
         if (lane == 0) FN[w] = nw;
@@ -456,6 +452,15 @@ __global__ __launch_bounds__(kBlock) void k_batch_forward_finish(BatchDev d, int
             fr.arcs += (unsigned long long)(d.row_ptr[w + 1] - d.row_ptr[w]);
         }
     }
+}
+
+template <bool N>
+__global__ __launch_bounds__(kBlock) void k_batch_forward_finish(BatchDev d, int32_t L,
+                                                                 uint64_t full) {
+    if (L > d.ctrl[kCtlDeepest] || L + 1 >= d.lcap) return;
+    Front fr;
+    finish_split<N>(d, L, (blockIdx.x * kBlock + threadIdx.x) / kWave,
+                    gridDim.x * kWavesPerBlock, fr);
     report_front(d, 2, fr);
     (void)full;
 }
@@ -820,11 +825,10 @@ __global__ __launch_bounds__(kBlock) void k_batch_reverse(BatchDev d, int32_t L)
 // vertex, with sum 0.  delta = sigma * sum, c = (1 + delta) / sigma, BC[v] +=
 // the lanes' deltas.
 template <bool N>
-__global__ __launch_bounds__(kBlock) void k_batch_finalize(BatchDev d, int32_t L, int32_t leaf) {
+__device__ void finalize_level(const BatchDev &d, int32_t L, int32_t leaf, int32_t wave,
+                               int32_t nwaves) {
     const int lane = lane_id();
     const uint64_t *FL = d.F + (size_t)L * (size_t)d.n;
-    const int32_t wave = (blockIdx.x * kBlock + threadIdx.x) / kWave;
-    const int32_t nwaves = gridDim.x * kWavesPerBlock;
     const int32_t vend = leaf ? d.n : d.multi_end;
     const int32_t groups = (vend + kWave - 1) / kWave;
     for (int32_t gi = wave; gi < groups; gi += nwaves) {
@@ -899,6 +903,104 @@ __global__ __launch_bounds__(kBlock) void k_batch_finalize(BatchDev d, int32_t L
                     if (vj[u] >= 0) add_segments(d, vj[u], delta[u]);
             }
         }
+    }
+}
+
+template <bool N>
+__global__ __launch_bounds__(kBlock) void k_batch_finalize(BatchDev d, int32_t L, int32_t leaf) {
+    finalize_level<N>(d, L, leaf, (blockIdx.x * kBlock + threadIdx.x) / kWave,
+                      gridDim.x * kWavesPerBlock);
+}
+
+// ---- device-resident level loop (small graphs) -----------------------------
+
+// One workgroup runs one whole batch: clear, seed, every forward level, every
+// reverse level and the completion, with a workgroup barrier between steps
+// (the waves of a workgroup share one compute unit and its L1, so the barrier
+// orders their global-memory accesses).  A call's batches run as the
+// workgroups of one launch.  The per-wave step code is the one the grid-wide
+// kernels run.  ctrl of the batch receives the depth and the flags
+// (truncation: the host runs the call again with a longer level array).
+constexpr int kFusedBlock = 1024;
+constexpr int kFusedWaves = kFusedBlock / kWave;
+
+template <bool N>
+__global__ __launch_bounds__(kFusedBlock) void k_batch_fused(const BatchDev *devs,
+                                                             const int32_t *lanes,
+                                                             const int2 *batches) {
+    const BatchDev &d = devs[blockIdx.x];
+    const int2 bt = batches[blockIdx.x];  // (first lane in `lanes`, lane count)
+    const int t = threadIdx.x;
+    const int lane = lane_id();
+    const int32_t wave = t / kWave;
+    __shared__ uint32_t s_found;
+    // clear
+    for (int32_t i = t; i < d.n; i += kFusedBlock) {
+        d.vis[i] = 0ull;
+        d.F[i] = 0ull;
+        if (d.nseg == 0) d.bc[i] = 0.0;
+    }
+    for (int32_t i = t; i < d.multi_end; i += kFusedBlock) d.reach[i] = 0ull;
+    for (int64_t i = t; i < (int64_t)d.multi_end * kWave; i += kFusedBlock) d.hubsig[i] = 0.0;
+    if (t < kCtlInts) d.ctrl[t] = 0;
+    __syncthreads();
+    // seed
+    const int32_t nl = bt.y;
+    if (wave == 0 && lane < nl) {
+        const int32_t s = lanes[bt.x + lane];
+        atomicOr((unsigned long long *)&d.vis[s], 1ull << lane);
+        atomicOr((unsigned long long *)&d.F[s], 1ull << lane);
+        SigRows<N>::rows(d)[(size_t)s * kWave + lane] = 1;
+    }
+    __syncthreads();
+    const uint64_t full = nl >= 64 ? ~0ull : ((1ull << nl) - 1ull);
+    const uint32_t items = d.items;
+    const uint32_t groups = (uint32_t)((d.n - d.big_end + kWave - 1) / kWave);
+    // forward
+    int32_t deepest = 0;
+    bool trunc = false;
+    for (int32_t L = 0;; ++L) {
+        if (L + 1 >= d.lcap) {  // level L+1 does not fit
+            trunc = true;
+            break;
+        }
+        if (t == 0) s_found = 0;
+        Front fr;
+        Work wk;
+        for (uint32_t it = wave; it < items + groups; it += kFusedWaves) {
+            if (it < items) fwd_chunk<N>(d, L, it, full, wk, fr);
+            else fwd_group<N>(d, L, d.big_end + (int32_t)(it - items) * kWave, nullptr, 0, full,
+                              wk, fr);
+        }
+        __syncthreads();
+        finish_split<N>(d, L, wave, kFusedWaves, fr);
+        uint32_t c = fr.cnt;
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) c += __shfl_xor(c, off);
+        if (lane == 0 && c) atomicAdd(&s_found, c);
+        __syncthreads();
+        const uint32_t found = s_found;
+        __syncthreads();  // s_found is reset by the next iteration
+        if (found == 0) break;
+        deepest = L + 1;
+    }
+    if (t == 0) {
+        d.ctrl[kCtlDeepest] = deepest;
+        if (trunc) d.ctrl[kCtlTrunc] = 1;
+    }
+    if (trunc) return;
+    // reverse
+    for (int32_t L = deepest; L >= 1; --L) {
+        if (L != deepest) {
+            Work wk;
+            for (uint32_t it = wave; it < items + groups; it += kFusedWaves) {
+                if (it < items) bwd_chunk<N>(d, L, it, wk);
+                else bwd_group<N>(d, L, d.big_end + (int32_t)(it - items) * kWave, wk);
+            }
+            __syncthreads();
+        }
+        finalize_level<N>(d, L, L == deepest ? 1 : 0, wave, kFusedWaves);
+        __syncthreads();
     }
 }
 
@@ -1036,6 +1138,14 @@ hipError_t batch_finalize(const BatchDev &d, int32_t level, bool deepest, hipStr
     if (vend == 0) return hipSuccess;
     hipLaunchKernelGGL(d.narrow ? k_batch_finalize<true> : k_batch_finalize<false>, dim3(grid_of((vend + kWave - 1) / kWave)), dim3(kBlock),
                        0, stream, d, level, deepest ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t batch_fused(const BatchDev *devs_dev, int32_t nbatches, bool narrow,
+                       const int32_t *lanes_dev, const int2 *batches_dev, hipStream_t stream) {
+    if (nbatches <= 0) return hipSuccess;
+    hipLaunchKernelGGL(narrow ? k_batch_fused<true> : k_batch_fused<false>, dim3(nbatches),
+                       dim3(kFusedBlock), 0, stream, devs_dev, lanes_dev, batches_dev);
     return hipGetLastError();
 }
 

@@ -155,6 +155,22 @@ struct bc_graph_s {
     // internal streams for batches run at once (created on first use)
     std::mutex stream_mu;
     std::vector<hipStream_t> streams;
+    // workspaces of the device-resident level loop (one per batch of a launch)
+    std::mutex fused_mu;
+    struct Fused {
+        void *block = nullptr;
+        size_t bytes = 0;
+        int32_t cap = 0, lcap = 0;
+        BatchDev *d_devs = nullptr;
+        int32_t *h_ctrl = nullptr;  // pinned [cap][kCtlInts]
+        int32_t *d_ctrl = nullptr;  // [cap][kCtlInts]
+        double *d_bc = nullptr;     // [cap][n] per-batch BC (internal order)
+        double *d_total = nullptr;  // [n] running BC total of a run (not in the pool)
+        int32_t *d_lanes = nullptr;
+        size_t lanes_cap = 0;
+        int2 *d_batches = nullptr;
+        std::vector<BatchDev> h_devs;
+    } fused;
     // hop distances (internal order, -1 unreached) from two landmarks: the
     // highest-degree vertex and the vertex farthest from it; batches are formed
     // from sources sorted by them
@@ -167,6 +183,8 @@ struct bc_graph_s {
 };
 
 namespace {
+
+void fused_release(bc_graph_s *g);
 
 size_t plain_ws_bytes(const bc_graph_s *g) {
     const size_t n = (size_t)std::max<int32_t>(g->n, 1);
@@ -849,6 +867,274 @@ bc_status run_batch_plan(bc_graph_s *g, const std::vector<int32_t> &s_int,
 
 // BC over the sources with up to `width` sources per batch.  With dist /
 // sigma (device, caller order, [k][n]), the per-source state is exported too.
+// ---- device-resident level loop ----------------------------------------------
+
+// Bytes of one batch's workspace in the fused pool (vis, sigma / coef rows,
+// split-vertex rows, partial rows, the level array).
+size_t fused_batch_bytes(const bc_graph_s *g, int32_t lcap) {
+    const size_t n = (size_t)std::max<int32_t>(g->n, 1);
+    const size_t multi = (size_t)std::max(g->multi_end, 1);
+    const size_t items = (size_t)std::max<uint32_t>(g->items, 1);
+    return align_up(n * sizeof(uint64_t)) + 2 * align_up(n * kWave * sizeof(double)) +
+           align_up(multi * sizeof(uint64_t)) + align_up(multi * kWave * sizeof(double)) +
+           align_up(items * kWave * sizeof(double)) +
+           align_up((size_t)lcap * n * sizeof(uint64_t));
+}
+
+// The batch workspaces of the pool (not the run's lane and segment tables).
+void fused_release_pool(bc_graph_s *g) {
+    auto &f = g->fused;
+    if (f.block) (void)hipFree(f.block);
+    if (f.d_devs) (void)hipFree(f.d_devs);
+    if (f.h_ctrl) (void)hipHostFree(f.h_ctrl);
+    if (f.d_batches) (void)hipFree(f.d_batches);
+    f.block = nullptr;
+    f.d_devs = nullptr;
+    f.h_ctrl = nullptr;
+    f.d_batches = nullptr;
+    f.d_ctrl = nullptr;
+    f.d_bc = nullptr;
+    f.bytes = 0;
+    f.cap = f.lcap = 0;
+    f.h_devs.clear();
+}
+
+void fused_release(bc_graph_s *g) {
+    fused_release_pool(g);
+    auto &f = g->fused;
+    if (f.d_lanes) (void)hipFree(f.d_lanes);
+    if (f.d_total) (void)hipFree(f.d_total);
+    f.d_lanes = nullptr;
+    f.d_total = nullptr;
+    f.lanes_cap = 0;
+}
+
+// Batches per launch that fit the pool budget with `lcap` levels each.
+constexpr size_t kFusedBudget = (size_t)4 << 30;
+int32_t fused_cap(const bc_graph_s *g, int32_t nbatches, int32_t lcap) {
+    const size_t per = fused_batch_bytes(g, lcap);
+    return (int32_t)std::max<size_t>(1, std::min<size_t>((size_t)std::max(nbatches, 1),
+                                                         kFusedBudget / per));
+}
+
+// Pool for `cap` batches with `lcap` levels each (caller holds fused_mu); an
+// existing pool at least that large is kept.
+bc_status fused_reserve(bc_graph_s *g, int32_t cap, int32_t lcap) {
+    auto &f = g->fused;
+    if (f.block && f.cap >= cap && f.lcap >= lcap) return BC_OK;
+    fused_release_pool(g);
+    const size_t n = (size_t)std::max<int32_t>(g->n, 1);
+    const size_t per = fused_batch_bytes(g, lcap);
+    const size_t head = align_up((size_t)cap * kCtlInts * sizeof(int32_t)) +
+                        align_up((size_t)cap * n * sizeof(double));
+    f.bytes = head + (size_t)cap * per;
+    hipError_t e = hipMalloc(&f.block, f.bytes);
+    if (e == hipSuccess) e = hipMalloc(&f.d_devs, (size_t)cap * sizeof(BatchDev));
+    if (e == hipSuccess) e = hipMalloc(&f.d_batches, (size_t)cap * sizeof(int2));
+    if (e == hipSuccess)
+        e = hipHostMalloc((void **)&f.h_ctrl, (size_t)cap * kCtlInts * sizeof(int32_t),
+                          hipHostMallocDefault);
+    if (e != hipSuccess) {
+        fused_release(g);
+        return from_hip(e);
+    }
+    f.cap = cap;
+    f.lcap = lcap;
+    char *p = (char *)f.block;
+    auto take = [&](size_t bytes) {
+        char *r = p;
+        p += align_up(bytes);
+        return (void *)r;
+    };
+    f.d_ctrl = (int32_t *)take((size_t)cap * kCtlInts * sizeof(int32_t));
+    f.d_bc = (double *)take((size_t)cap * n * sizeof(double));
+    f.h_devs.assign((size_t)cap, BatchDev{});
+    for (int32_t b = 0; b < cap; ++b) {
+        BatchDev &d = f.h_devs[(size_t)b];
+        d.n = g->n;
+        d.row_ptr = g->d_row_ptr;
+        d.col_idx = g->d_col_idx;
+        d.big_end = g->big_end;
+        d.multi_end = g->multi_end;
+        d.items = g->items;
+        d.item_info = g->d_item_info;
+        d.item_first = g->d_item_first;
+        d.iperm = g->d_iperm;
+        d.nnz = g->nnz;
+        d.lcap = lcap;
+        d.ctrl = f.d_ctrl + (size_t)b * kCtlInts;
+        d.bc = f.d_bc + (size_t)b * n;
+        d.vis = (uint64_t *)take(n * sizeof(uint64_t));
+        d.sigma = (double *)take(n * kWave * sizeof(double));
+        d.sigma32 = reinterpret_cast<uint32_t *>(d.sigma);
+        d.coef = (double *)take(n * kWave * sizeof(double));
+        d.reach = (uint64_t *)take((size_t)std::max(g->multi_end, 1) * sizeof(uint64_t));
+        d.hubsig = (double *)take((size_t)std::max(g->multi_end, 1) * kWave * sizeof(double));
+        d.partial = (double *)take((size_t)std::max<uint32_t>(g->items, 1) * kWave * sizeof(double));
+        d.F = (uint64_t *)take((size_t)lcap * n * sizeof(uint64_t));
+    }
+    return BC_OK;
+}
+
+// The whole batch plan with the device-resident level loop: up to `cap`
+// batches per launch (one workgroup each).  Without segments, BC (caller
+// order) = the batches' BC added in batch order; with segments, each batch
+// adds its lanes' dependencies to its requests' outputs (requests of at most
+// 64 sources only, so no two batches of a launch share an output).
+bc_status fused_run(bc_graph_s *g, const std::vector<int32_t> &s_int,
+                    const std::vector<BatchPlan> &plan, const std::vector<int32_t> &seg_start,
+                    const std::vector<double *> &seg_out, double *bc_out, hipStream_t stream,
+                    const int32_t *export_row, int32_t *dist, double *sigma) {
+    std::lock_guard<std::mutex> lk(g->fused_mu);
+    const int32_t nb = (int32_t)plan.size();
+    const size_t n = (size_t)g->n;
+    auto &f = g->fused;
+    const bool prof = g->profiling.load() != 0;
+    const int32_t lcap = std::max(16, g->batch_depth_hint.load() + 8);
+    bc_status st = fused_reserve(g, fused_cap(g, nb, lcap), lcap);
+    if (st != BC_OK) return st;
+    // the running BC total outlives pool regrowth
+    if (bc_out && !f.d_total) BC_TRY_HIP(hipMalloc(&f.d_total, std::max<size_t>(n, 1) * sizeof(double)));
+    // lanes and segment tables on the device
+    const size_t k = s_int.size();
+    const size_t seg_ints = seg_start.size(), seg_ptrs = seg_out.size();
+    const size_t need = k * sizeof(int32_t) + seg_ints * sizeof(int32_t) +
+                        seg_ptrs * sizeof(double *) + 64;
+    if (need > f.lanes_cap) {
+        if (f.d_lanes) (void)hipFree(f.d_lanes);
+        f.d_lanes = nullptr;
+        f.lanes_cap = 0;
+        BC_TRY_HIP(hipMalloc(&f.d_lanes, need));
+        f.lanes_cap = need;
+    }
+    int32_t *d_seg_start = f.d_lanes + k;
+    double **d_seg_out = (double **)(((uintptr_t)(d_seg_start + seg_ints) + 15) & ~(uintptr_t)15);
+    hipError_t e = hipSuccess;
+    if (k) e = hipMemcpyAsync(f.d_lanes, s_int.data(), k * sizeof(int32_t), hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess && seg_ints)
+        e = hipMemcpyAsync(d_seg_start, seg_start.data(), seg_ints * sizeof(int32_t),
+                           hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess && seg_ptrs)
+        e = hipMemcpyAsync(d_seg_out, seg_out.data(), seg_ptrs * sizeof(double *),
+                           hipMemcpyHostToDevice, stream);
+    if (e != hipSuccess) return from_hip(e);
+    int32_t *x_dist = nullptr;
+    double *x_sigma = nullptr;
+    struct Tmp {
+        int32_t *&a;
+        double *&b;
+        ~Tmp() {
+            if (a) (void)hipFree(a);
+            if (b) (void)hipFree(b);
+        }
+    } tmp_guard{x_dist, x_sigma};
+    if (dist) BC_TRY_HIP(hipMalloc(&x_dist, (size_t)kWave * n * sizeof(int32_t)));
+    if (sigma) BC_TRY_HIP(hipMalloc(&x_sigma, (size_t)kWave * n * sizeof(double)));
+    LaunchTimer timer;
+    timer.on = prof;
+    bool range = false;
+    int32_t run_depth = 0;
+    std::vector<int2> bt;
+    for (int32_t b0 = 0; b0 < nb;) {
+        const int32_t m = std::min(f.cap, nb - b0);
+        bt.resize((size_t)std::max(m, 1));
+        const bool narrow = !g->sigma_wide.load();
+        for (int32_t i = 0; i < m; ++i) {
+            const BatchPlan &bp = plan[(size_t)(b0 + i)];
+            BatchDev &d = f.h_devs[(size_t)i];
+            d.narrow = narrow ? 1 : 0;
+            d.nseg = bp.nseg;
+            d.seg_start = bp.nseg ? d_seg_start + bp.seg_first : nullptr;
+            d.seg_out = bp.nseg ? d_seg_out + (bp.seg_first - (b0 + i)) : nullptr;
+            bt[(size_t)i] = make_int2(bp.first, bp.nlanes);
+        }
+        e = hipMemcpyAsync(f.d_devs, f.h_devs.data(), (size_t)m * sizeof(BatchDev),
+                           hipMemcpyHostToDevice, stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(f.d_batches, bt.data(), (size_t)m * sizeof(int2),
+                               hipMemcpyHostToDevice, stream);
+        if (e == hipSuccess) e = timer.begin(BC_PROF_FORWARD, stream);
+        if (e == hipSuccess) e = batch_fused(f.d_devs, m, narrow, f.d_lanes, f.d_batches, stream);
+        if (e == hipSuccess) e = timer.end(stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(f.h_ctrl, f.d_ctrl, (size_t)m * kCtlInts * sizeof(int32_t),
+                               hipMemcpyDeviceToHost, stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) break;
+        bool trunc = false, wide = false;
+        for (int32_t i = 0; i < m; ++i) {
+            const int32_t *c = f.h_ctrl + (size_t)i * kCtlInts;
+            trunc |= c[kCtlTrunc] != 0;
+            wide |= c[kCtlNarrow] != 0;
+        }
+        if (wide) {  // a path count needs double rows: run these batches again
+            g->sigma_wide.store(true);
+            continue;
+        }
+        if (trunc) {  // a batch ran deeper than the level array: grow it, run again
+            const int32_t l2 = f.lcap * 2;
+            fused_release_pool(g);  // the longer arrays may hold fewer batches
+            st = fused_reserve(g, fused_cap(g, nb - b0, l2), l2);
+            if (st != BC_OK) return st;
+            continue;
+        }
+        for (int32_t i = 0; i < m; ++i) {
+            const int32_t *c = f.h_ctrl + (size_t)i * kCtlInts;
+            range |= c[kCtlRange] != 0;
+            run_depth = std::max(run_depth, c[kCtlDeepest]);
+        }
+        if (export_row && (dist || sigma)) {
+            for (int32_t i = 0; i < m && e == hipSuccess; ++i) {
+                const BatchPlan &bp = plan[(size_t)(b0 + i)];
+                const BatchDev &d = f.h_devs[(size_t)i];
+                e = batch_export(d, f.h_ctrl[(size_t)i * kCtlInts + kCtlDeepest], bp.nlanes, x_dist,
+                                 x_sigma, stream);
+                for (int32_t s2 = 0; s2 < bp.nlanes && e == hipSuccess; ++s2) {
+                    const size_t row = (size_t)export_row[bp.first + s2] * n;
+                    if (dist) e = gather_i32(g->n, g->d_perm, x_dist + (size_t)s2 * n, dist + row, stream);
+                    if (e == hipSuccess && sigma)
+                        e = gather_f64(g->n, g->d_perm, x_sigma + (size_t)s2 * n, sigma + row, stream);
+                }
+            }
+        }
+        if (e == hipSuccess && bc_out) e = sum_parts(g->n, f.d_bc, m, f.d_total, stream, b0 > 0);
+        if (e != hipSuccess) break;
+        b0 += m;
+    }
+    if (e == hipSuccess && bc_out) {
+        if (nb == 0) e = hipMemsetAsync(bc_out, 0, n * sizeof(double), stream);
+        else e = gather_f64(g->n, g->d_perm, f.d_total, bc_out, stream);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) {
+        timer.destroy();
+        return from_hip(e);
+    }
+    if (nb > 0) g->batch_depth_hint.store(run_depth);
+    if (prof) {
+        // whole batches per launch: counted as forward launches, no work counters
+        std::lock_guard<std::mutex> plk(g->prof_mu);
+        for (size_t i = 0; i < timer.used; ++i) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, timer.ev[2 * i], timer.ev[2 * i + 1]) == hipSuccess)
+                g->prof.ms[timer.cls[i]] += ms;
+            g->prof.launches[timer.cls[i]] += 1;
+        }
+        g->prof.runs += 1;
+    }
+    timer.destroy();
+    return range ? BC_ERR_RANGE : BC_OK;
+}
+
+// The device-resident loop runs a batch on one compute unit: it pays off
+// when the graph is small (launch and polling costs dominate the host-driven
+// loop) or when there are enough batches to occupy many compute units.
+bool use_fused(const bc_graph_s *g, int32_t level_loop, int32_t nbatches) {
+    if (level_loop == BC_LOOP_DEVICE) return true;
+    if (level_loop == BC_LOOP_HOST) return false;
+    return g->nnz <= ((int64_t)1 << 20) || (nbatches >= 32 && g->nnz <= ((int64_t)1 << 24));
+}
+
 // Batches run at once for `concurrency` (0: by workspace size; the choice
 // depends only on the graph and the batch count, so results are identical
 // from run to run).  Parts overlap one another's small kernels and host
@@ -876,7 +1162,7 @@ bc_status get_streams(bc_graph_s *g, int32_t p, std::vector<hipStream_t> &out) {
 
 bc_status batched_run(bc_graph_s *g, const int32_t *sources, int32_t k, double *bc_out,
                       int32_t width, int32_t sparse_div, int32_t concurrency,
-                      hipStream_t stream, int32_t *dist, double *sigma) {
+                      int32_t level_loop, hipStream_t stream, int32_t *dist, double *sigma) {
     // Batch composition: sources sorted by their distances to the two
     // landmarks, so that the 64 sources of a batch lie close together and see
     // most vertices at the same level (their frontier masks share lanes, the
@@ -900,6 +1186,8 @@ bc_status batched_run(bc_graph_s *g, const int32_t *sources, int32_t k, double *
     for (int32_t i = 0; i < k; ++i) s_int[(size_t)i] = g->h_perm[(size_t)sources[order[(size_t)i]]];
     std::vector<BatchPlan> plan;
     for (int32_t b0 = 0; b0 < k; b0 += width) plan.push_back({b0, std::min(width, k - b0), 0, 0});
+    if (use_fused(g, level_loop, (int32_t)plan.size()))
+        return fused_run(g, s_int, plan, {}, {}, bc_out, stream, order.data(), dist, sigma);
     const int32_t P = parts_of(g, concurrency, (int32_t)plan.size());
     if (P <= 1)
         return run_batch_plan(g, s_int, plan, {}, {}, bc_out, stream, order.data(), dist, sigma,
@@ -1013,6 +1301,13 @@ bc_status multi_run(bc_graph_s *g, const int32_t *sources, const int32_t *req_st
         hipError_t e = hipMemsetAsync(outs[r], 0, (size_t)g->n * sizeof(double), stream);
         if (e != hipSuccess) return from_hip(e);
     }
+    // the device-resident loop runs a launch's batches at once: only when no
+    // request spans two batches (no two workgroups add to one output)
+    bool spans = false;
+    for (int32_t r = 0; r < nreq; ++r) spans |= req_start[r + 1] - req_start[r] > kWave;
+    if (!spans && use_fused(g, BC_LOOP_AUTO, (int32_t)plan.size()))
+        return fused_run(g, s_int, plan, seg_start, seg_out, nullptr, stream, nullptr, nullptr,
+                         nullptr);
     return run_batch_plan(g, s_int, plan, seg_start, seg_out, nullptr, stream, nullptr, nullptr,
                           nullptr, g->tuned_sparse_div.load());
 }
@@ -1041,7 +1336,9 @@ bc_status check_options(const bc_options *opt) {
     if (opt->level_chunk < 0 || opt->level_chunk > 1024) return BC_ERR_INVALID_ARG;
     if (opt->sparse_div < -1 || opt->sparse_div > (1 << 20)) return BC_ERR_INVALID_ARG;
     if (opt->concurrency < 0 || opt->concurrency > kMaxParts) return BC_ERR_INVALID_ARG;
-    for (int i = 0; i < 3; ++i)
+    if (opt->level_loop < BC_LOOP_AUTO || opt->level_loop > BC_LOOP_DEVICE)
+        return BC_ERR_INVALID_ARG;
+    for (int i = 0; i < 2; ++i)
         if (opt->reserved[i] != 0) return BC_ERR_INVALID_ARG;
     return BC_OK;
 }
@@ -1249,6 +1546,7 @@ bc_status bc_destroy_graph(bc_graph_t g) {
     g->plain_pool.clear();
     for (hipStream_t st : g->streams) (void)hipStreamDestroy(st);
     g->streams.clear();
+    fused_release(g);
     for (BatchWS *ws : g->batch_pool) batch_ws_destroy(ws);
     g->batch_pool.clear();
     if (g->d_row_ptr) (void)hipFree(g->d_row_ptr);
@@ -1281,7 +1579,7 @@ bc_status bc_run_async(bc_graph_t g, const int32_t *sources, int32_t k, double *
     if (use_batched(g, opt, k))
         return batched_run(g, sources, k, bc_out_dev, batch_width_of(g, opt),
                            sparse_div_of(g, opt), opt ? opt->concurrency : 0,
-                           (hipStream_t)stream, nullptr, nullptr);
+                           opt ? opt->level_loop : 0, (hipStream_t)stream, nullptr, nullptr);
     return plain_run(g, sources, k, bc_out_dev, opt, (hipStream_t)stream, nullptr, nullptr);
 }
 
@@ -1295,7 +1593,7 @@ bc_status bc_run(bc_graph_t g, const int32_t *sources, int32_t k, double *bc_out
     BC_TRY_HIP(hipMalloc(&d_bc, (size_t)g->n * sizeof(double)));
     st = use_batched(g, nullptr, k)
              ? batched_run(g, sources, k, d_bc, batch_width_of(g, nullptr),
-                           sparse_div_of(g, nullptr), 0, nullptr, nullptr, nullptr)
+                           sparse_div_of(g, nullptr), 0, 0, nullptr, nullptr, nullptr)
              : plain_run(g, sources, k, d_bc, nullptr, nullptr, nullptr, nullptr);
     if (st == BC_OK || st == BC_ERR_RANGE) {
         hipError_t e = hipMemcpy(bc_out, d_bc, (size_t)g->n * sizeof(double),
@@ -1343,7 +1641,8 @@ bc_status bc_run_detail(bc_graph_t g, const int32_t *sources, int32_t k, const b
     }
     if (batched)
         st = batched_run(g, sources, k, d_bc, batch_width_of(g, opt), sparse_div_of(g, opt),
-                         opt ? opt->concurrency : 0, nullptr, d_dist, d_sigma);
+                         opt ? opt->concurrency : 0, opt ? opt->level_loop : 0, nullptr, d_dist,
+                         d_sigma);
     else
         st = plain_run(g, sources, k, d_bc, opt, nullptr, (dist || sigma) ? exp.data() : nullptr,
                        &tmp.t);
@@ -1509,8 +1808,8 @@ bc_status bc_autotune(bc_graph_t g, const int32_t *sources, int32_t k, void *str
         return BC_OK;
     };
     auto batched = [&](int32_t width, int32_t div, double &ms) {
-        return timed([&]() { return batched_run(g, sources, m, d_bc, width, div, 1, stream,
-                                                nullptr, nullptr); }, ms);
+        return timed([&]() { return batched_run(g, sources, m, d_bc, width, div, 1, BC_LOOP_HOST,
+                                                stream, nullptr, nullptr); }, ms);
     };
     // sparse-step threshold at width 64, then width 32 with the best threshold
     const int32_t divs[] = {-1, 16, 64, 256};

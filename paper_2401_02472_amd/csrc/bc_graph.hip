@@ -56,20 +56,22 @@ hipError_t gather_f64(int32_t n, const int32_t *perm, const double *src, double 
     return hipGetLastError();
 }
 
-// out[v] = parts[0][v] + parts[1][v] + ... (in part order), parts stored [nparts][n].
-__global__ void k_sum_parts(int32_t n, const double *parts, int32_t nparts, double *out) {
+// out[v] = (accumulate ? out[v] : 0) + parts[0][v] + parts[1][v] + ... (in
+// part order), parts stored [nparts][n].
+__global__ void k_sum_parts(int32_t n, const double *parts, int32_t nparts, double *out,
+                            int32_t accumulate) {
     for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
-        double t = parts[v];
-        for (int32_t i = 1; i < nparts; ++i) t += parts[(size_t)i * n + v];
+        double t = accumulate ? out[v] : 0.0;
+        for (int32_t i = 0; i < nparts; ++i) t += parts[(size_t)i * n + v];
         out[v] = t;
     }
 }
 
 hipError_t sum_parts(int32_t n, const double *parts, int32_t nparts, double *out,
-                     hipStream_t stream) {
+                     hipStream_t stream, bool accumulate) {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_sum_parts, dim3(grid_for(n)), dim3(kBlock), 0, stream, n, parts, nparts,
-                       out);
+                       out, accumulate ? 1 : 0);
     return hipGetLastError();
 }
 

@@ -161,6 +161,11 @@ hipError_t batch_forward_done(const BatchDev &d, int32_t level, uint64_t full,
 hipError_t batch_reverse(const BatchDev &d, int32_t level, hipStream_t stream);
 hipError_t batch_finalize(const BatchDev &d, int32_t level, bool deepest, hipStream_t stream);
 // dist [nlanes][n] (int32) and sigma [nlanes][n] of the batch, internal order.
+// Every batch of a call in one launch, one workgroup per batch (graphs small
+// enough for one compute unit per batch); devs_dev[b] is batch b's workspace,
+// batches_dev[b] = (first lane in lanes_dev, lane count).
+hipError_t batch_fused(const BatchDev *devs_dev, int32_t nbatches, bool narrow,
+                       const int32_t *lanes_dev, const int2 *batches_dev, hipStream_t stream);
 hipError_t batch_export(const BatchDev &d, int32_t deepest, int32_t nlanes, int32_t *dist,
                         double *sigma, hipStream_t stream);
 
@@ -175,7 +180,7 @@ hipError_t relabel_csr(int32_t n, int64_t nnz, const int32_t *old_rp, const int3
 hipError_t gather_f64(int32_t n, const int32_t *perm, const double *src, double *dst,
                       hipStream_t stream);
 hipError_t sum_parts(int32_t n, const double *parts, int32_t nparts, double *out,
-                     hipStream_t stream);
+                     hipStream_t stream, bool accumulate = false);
 hipError_t gather_i32(int32_t n, const int32_t *perm, const int32_t *src, int32_t *dst,
                       hipStream_t stream);
 

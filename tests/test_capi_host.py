@@ -84,14 +84,16 @@ def test_invalid_arguments_rejected():
 
 def test_options_layout_matches_header():
     # eight int32 fields: mode, batch_width, level_chunk, sparse_div, concurrency,
-    # reserved[3]
+    # level_loop, reserved[2]
     assert ctypes.sizeof(_capi.bc_options) == 32
     assert [f[0] for f in _capi.bc_options._fields_] == ["mode", "batch_width", "level_chunk",
-                                                        "sparse_div", "concurrency", "reserved"]
+                                                        "sparse_div", "concurrency", "level_loop",
+                                                        "reserved"]
     assert ctypes.sizeof(_capi.bc_tuning) == 32
-    o = bcm.make_options(bcm.BC_MODE_BATCHED, 32, 0, sparse_div=-1, concurrency=3)
-    assert (o.mode, o.batch_width, o.sparse_div, o.concurrency, list(o.reserved)) == \
-        (2, 32, -1, 3, [0] * 3)
+    o = bcm.make_options(bcm.BC_MODE_BATCHED, 32, 0, sparse_div=-1, concurrency=3,
+                         level_loop=bcm.BC_LOOP_DEVICE)
+    assert (o.mode, o.batch_width, o.sparse_div, o.concurrency, o.level_loop,
+            list(o.reserved)) == (2, 32, -1, 3, 2, [0] * 2)
 
 
 def test_trusted_flag_skips_symmetry_only():

@@ -198,9 +198,10 @@ def test_sparse_threshold_settings(g, div):
     frontier-driven step (never, always, and two thresholds) gives the oracle's
     BC, and the same distances / sigma bit for bit."""
     src = gg.sample_sources(g, 70, seed=13)
-    opt = bcm.make_options(bcm.BC_MODE_BATCHED, sparse_div=div)
+    opt = bcm.make_options(bcm.BC_MODE_BATCHED, sparse_div=div, level_loop=bcm.BC_LOOP_HOST)
     with bcm.Graph(g.n, g.row_ptr, g.col_idx) as G:
-        check_bc(batched(G, src, sparse_div=div), oracle_bc(g, src))
+        check_bc(batched(G, src, sparse_div=div, level_loop=bcm.BC_LOOP_HOST),
+                 oracle_bc(g, src))
         _, dist, sigma = G.run_detail(src[:3], opt)
     for i, s in enumerate(src[:3]):
         od, osg, _, _ = oracle.single_source(g.row_ptr, g.col_idx, int(s), with_delta=False)
@@ -279,10 +280,11 @@ def test_batches_run_at_once(conc):
     part land in the caller's order."""
     g = gg.rmat(13, 8, seed=16)
     src = gg.sample_sources(g, 300, seed=17)
-    opt = bcm.make_options(bcm.BC_MODE_BATCHED, concurrency=conc)
+    kw = dict(concurrency=conc, level_loop=bcm.BC_LOOP_HOST)
+    opt = bcm.make_options(bcm.BC_MODE_BATCHED, **kw)
     with bcm.Graph(g.n, g.row_ptr, g.col_idx) as G:
-        a = batched(G, src, concurrency=conc)
-        b = batched(G, src, concurrency=conc)
+        a = batched(G, src, **kw)
+        b = batched(G, src, **kw)
         _, dist, sigma = G.run_detail(src[:130], opt)
     check_bc(a, oracle_bc(g, src))
     assert np.array_equal(a, b)
@@ -290,3 +292,28 @@ def test_batches_run_at_once(conc):
         od, osg, _, _ = oracle.single_source(g.row_ptr, g.col_idx, int(src[i]), with_delta=False)
         assert np.array_equal(dist[i], od)
         assert np.array_equal(sigma[i], osg)
+
+
+LOOP_GRAPHS = [gg.rmat(12, 8, seed=1), gg.grid_road(64, 64, seed=18), gg.path(300),
+               gg.star(3000), gg.complete(40), gg.hypercube(9)]
+
+
+@pytest.mark.parametrize("g", LOOP_GRAPHS, ids=lambda g: g.name)
+@pytest.mark.parametrize("loop", [bcm.BC_LOOP_HOST, bcm.BC_LOOP_DEVICE], ids=["host", "device"])
+def test_level_loop_modes(g, loop):
+    """The host-driven level loop and the device-resident one (a workgroup per
+    batch, all batches in one launch) both give the oracle's BC and the same
+    distances / sigma; deep graphs outgrow the device loop's level array and
+    run again with a longer one."""
+    src = gg.sample_sources(g, min(g.n, 150), seed=19)
+    opt = bcm.make_options(bcm.BC_MODE_BATCHED, level_loop=loop)
+    with bcm.Graph(g.n, g.row_ptr, g.col_idx) as G:
+        got = batched(G, src, level_loop=loop)
+        again = batched(G, src, level_loop=loop)
+        _, dist, sigma = G.run_detail(src[:66], opt)
+    check_bc(got, oracle_bc(g, src))
+    assert np.array_equal(got, again)
+    for i in (0, min(65, len(src) - 1)):
+        od, osg, _, _ = oracle.single_source(g.row_ptr, g.col_idx, int(src[i]), with_delta=False)
+        assert np.array_equal(dist[i], od)
+        check_sigma(sigma[i], osg)
