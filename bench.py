@@ -233,6 +233,8 @@ def main() -> int:
     ap.add_argument("--compare-plain", type=int, default=32,
                     help="also time this many sources on the one-source-at-a-time path "
                          "(0 = skip) and report the ratio")
+    ap.add_argument("--concurrency", type=int, default=0,
+                    help="batches run at once (0 = the library's choice)")
     ap.add_argument("--no-end-to-end", action="store_true",
                     help="skip the run with host transfers")
     ap.add_argument("--no-autotune", action="store_true",
@@ -275,7 +277,8 @@ def main() -> int:
     k = int(len(sources))
     mode = {"auto": bcm.BC_MODE_AUTO, "plain": bcm.BC_MODE_PLAIN,
             "batched": bcm.BC_MODE_BATCHED}[args.mode]
-    opt = bcm.make_options(mode, args.batch_width, sparse_div=args.sparse_div)
+    opt = bcm.make_options(mode, args.batch_width, sparse_div=args.sparse_div,
+                           concurrency=args.concurrency)
 
     G = bcm.Graph(g.n, g.row_ptr, g.col_idx, flags=bcm.BC_GRAPH_TRUST_SYMMETRIC)
     out = torch.empty(g.n, dtype=torch.float64, device="cuda")
@@ -343,25 +346,53 @@ def main() -> int:
     value = k * g.nnz / (ms_per_step / 1e3) / 1e9
     print(f"# timed {args.steps} steps: {ms_per_step:.2f} ms/step", file=sys.stderr, flush=True)
 
-    # dominant kernel and its roofline point
-    cls = max(("forward", "reverse"), key=lambda c: prof[c]["ms"])
-    pc = prof[cls]
-    alg_bytes = sum(BYTES[(path, cls)][u] * pc[u] for u in ("owners", "arcs", "hits"))
-    launches = max(pc["launches"], 1)
-    avg_ms = pc["ms"] / launches
-    per_launch = alg_bytes / launches
-    achieved = per_launch / (avg_ms / 1e3) / 1e9 if avg_ms > 0 else 0.0
-    kernel_name = KERNELS[(path, cls)]
     src_hash = kernel_source_hash()
-    traffic = read_traffic(kernel_name, args.workload, src_hash)
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+
+    def roofline_of(prof, path):
+        """Dominant kernel of a profile and its roofline point."""
+        if prof["fused"]["launches"]:
+            # device-resident level loop: one launch runs whole batches, forward
+            # and reverse; its bytes are both passes' work counters
+            pc = prof["fused"]
+            alg_bytes = sum(BYTES[("batched", c)][u] * prof[c][u]
+                            for c in ("forward", "reverse") for u in ("owners", "arcs", "hits"))
+            kernel_name = "k_batch_fused"
+        else:
+            cls = max(("forward", "reverse"), key=lambda c: prof[c]["ms"])
+            pc = prof[cls]
+            alg_bytes = sum(BYTES[(path, cls)][u] * pc[u] for u in ("owners", "arcs", "hits"))
+            kernel_name = KERNELS[(path, cls)]
+        launches = max(pc["launches"], 1)
+        avg_ms = pc["ms"] / launches
+        per_launch = alg_bytes / launches
+        achieved = per_launch / (avg_ms / 1e3) / 1e9 if avg_ms > 0 else 0.0
+        return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": traffic, "kernel": kernel_name,
-                "alg_bytes_per_launch": round(per_launch), "avg_launch_ms": round(avg_ms, 5),
-                "launches": pc["launches"], "kernel_source_hash": src_hash}
+                "traffic": read_traffic(kernel_name, args.workload, src_hash),
+                "kernel": kernel_name, "alg_bytes_per_launch": round(per_launch),
+                "avg_launch_ms": round(avg_ms, 5), "launches": pc["launches"],
+                "kernel_source_hash": src_hash}
+
+    if prof["fused"]["launches"]:
+        path = "batched-device-loop"
+    roofline = roofline_of(prof, path)
+    # With concurrent parts (two batches on two streams), a launch's event
+    # duration includes the other part's overlapping kernels: the fraction
+    # above is then a lower bound.  The same point from two extra steps run as
+    # one part (not timed for `value`):
+    roofline_one_part = None
+    if path == "batched" and args.concurrency != 1:
+        opt1 = bcm.make_options(mode, args.batch_width, sparse_div=args.sparse_div, concurrency=1)
+        G.profile_enable(1)
+        G.profile_read(reset=True)
+        for _ in range(2):
+            G.run_async(sources, out, opt1)
+        torch.cuda.synchronize()
+        roofline_one_part = roofline_of(G.profile_read(reset=True), path)
+        G.profile_enable(False)
 
     plain_cmp = None
-    if args.compare_plain and path == "batched":
+    if args.compare_plain and path.startswith("batched"):
         sub = np.asarray(sources[:args.compare_plain], np.int32)
         popt = bcm.make_options(bcm.BC_MODE_PLAIN)
         G.run_async(sub, out, popt)
@@ -384,7 +415,7 @@ def main() -> int:
 
     q = np.percentile(step_ms, [50, 99]) if step_ms else [0.0, 0.0]
     kernels = {c: {"launches": prof[c]["launches"], "ms": round(prof[c]["ms"], 3)}
-               for c in ("forward", "compact", "reverse", "finish")}
+               for c in ("forward", "compact", "reverse", "finish", "fused")}
     rec = {
         "metric": METRIC, "value": round(value, 3), "unit": "GTEPS", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
@@ -392,14 +423,16 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": args.workload, "n": g.n, "nnz": g.nnz, "sources": k,
                    "mode": args.mode, "path": path, "batch_width": args.batch_width or
-                   ((tuning["batch_width"] if tuning else 64) if path == "batched" else 1),
+                   ((tuning["batch_width"] if tuning else 64) if path.startswith("batched") else 1),
                    "sparse_div": args.sparse_div or (tuning["sparse_div"] if tuning else 64),
+                   "concurrency": args.concurrency,
                    "autotune": tuning, "graph": g.params},
         "plain_comparison": plain_cmp,
         "reached_arc_gteps": round(ra / (ms_per_step / 1e3) / 1e9, 3),
         "end_to_end": end_to_end,
         "p50_ms": round(float(q[0]), 3), "p99_ms": round(float(q[1]), 3),
-        "roofline": roofline, "cpu_baseline": cpu, "kernels": kernels,
+        "roofline": roofline, "roofline_one_part": roofline_one_part,
+        "cpu_baseline": cpu, "kernels": kernels,
     }
     print(json.dumps(rec), flush=True)
     G.close()

@@ -98,8 +98,10 @@ typedef struct bc_options {
  * grid-wide kernels and polls the depth.  DEVICE: one workgroup runs a whole
  * batch (every level, with workgroup barriers) and all batches of the call go
  * in one launch: for small graphs, where launch and polling costs dominate,
- * or many batches.  AUTO picks DEVICE for graphs of at most 2^20 arcs, or at
- * most 2^24 arcs with 32 or more batches. */
+ * or many batches.  AUTO picks the loop with the lower estimated time for the
+ * call's batch count (a batch on one compute unit against a batch across the
+ * device; e.g. DEVICE from about 6 batches at 53K arcs, 27 at 425K, 87 at
+ * 1.8M). */
 enum {
     BC_LOOP_AUTO = 0,
     BC_LOOP_HOST = 1,
@@ -207,6 +209,9 @@ bc_status bc_trim_workspaces(bc_graph_t g);
  *   BC_PROF_COMPACT  compaction of the marks into the next level's queues
  *   BC_PROF_REVERSE  reverse level kernel (dependency sums, BC update)
  *   BC_PROF_FINISH   completion of vertices split into several chunks
+ *   BC_PROF_FUSED    device-resident level loop: one launch runs whole
+ *                    batches (its forward and reverse work counters are
+ *                    added to FORWARD and REVERSE, which then show no launches)
  * owners = vertices processed (for COMPACT: vertices queued), arcs = adjacency
  * entries read, hits = parent arcs (FORWARD) or child arcs (REVERSE).
  */
@@ -215,7 +220,8 @@ enum {
     BC_PROF_COMPACT = 1,
     BC_PROF_REVERSE = 2,
     BC_PROF_FINISH = 3,
-    BC_PROF_CLASSES = 4
+    BC_PROF_FUSED = 4,
+    BC_PROF_CLASSES = 5
 };
 
 typedef struct bc_profile {

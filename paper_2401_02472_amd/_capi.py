@@ -42,8 +42,9 @@ BC_PROF_FORWARD = 0
 BC_PROF_COMPACT = 1
 BC_PROF_REVERSE = 2
 BC_PROF_FINISH = 3
-BC_PROF_CLASSES = 4
-PROF_CLASS_NAMES = ("forward", "compact", "reverse", "finish")
+BC_PROF_FUSED = 4
+BC_PROF_CLASSES = 5
+PROF_CLASS_NAMES = ("forward", "compact", "reverse", "finish", "fused")
 
 
 class bc_options(ctypes.Structure):

@@ -959,6 +959,7 @@ __global__ __launch_bounds__(kFusedBlock) void k_batch_fused(const BatchDev *dev
     // forward
     int32_t deepest = 0;
     bool trunc = false;
+    Work wkf, wkr;
     for (int32_t L = 0;; ++L) {
         if (L + 1 >= d.lcap) {  // level L+1 does not fit
             trunc = true;
@@ -966,11 +967,10 @@ __global__ __launch_bounds__(kFusedBlock) void k_batch_fused(const BatchDev *dev
         }
         if (t == 0) s_found = 0;
         Front fr;
-        Work wk;
         for (uint32_t it = wave; it < items + groups; it += kFusedWaves) {
-            if (it < items) fwd_chunk<N>(d, L, it, full, wk, fr);
+            if (it < items) fwd_chunk<N>(d, L, it, full, wkf, fr);
             else fwd_group<N>(d, L, d.big_end + (int32_t)(it - items) * kWave, nullptr, 0, full,
-                              wk, fr);
+                              wkf, fr);
         }
         __syncthreads();
         finish_split<N>(d, L, wave, kFusedWaves, fr);
@@ -992,15 +992,18 @@ __global__ __launch_bounds__(kFusedBlock) void k_batch_fused(const BatchDev *dev
     // reverse
     for (int32_t L = deepest; L >= 1; --L) {
         if (L != deepest) {
-            Work wk;
             for (uint32_t it = wave; it < items + groups; it += kFusedWaves) {
-                if (it < items) bwd_chunk<N>(d, L, it, wk);
-                else bwd_group<N>(d, L, d.big_end + (int32_t)(it - items) * kWave, wk);
+                if (it < items) bwd_chunk<N>(d, L, it, wkr);
+                else bwd_group<N>(d, L, d.big_end + (int32_t)(it - items) * kWave, wkr);
             }
             __syncthreads();
         }
         finalize_level<N>(d, L, L == deepest ? 1 : 0, wave, kFusedWaves);
         __syncthreads();
+    }
+    if (d.stats) {
+        report_work(d.stats, wkf);
+        report_work(d.stats + 6, wkr);
     }
 }
 

@@ -169,6 +169,7 @@ struct bc_graph_s {
         int32_t *d_lanes = nullptr;
         size_t lanes_cap = 0;
         int2 *d_batches = nullptr;
+        unsigned long long *d_stats = nullptr;  // 12 work counters (as BatchDev::stats)
         std::vector<BatchDev> h_devs;
     } fused;
     // hop distances (internal order, -1 unreached) from two landmarks: the
@@ -904,8 +905,10 @@ void fused_release(bc_graph_s *g) {
     auto &f = g->fused;
     if (f.d_lanes) (void)hipFree(f.d_lanes);
     if (f.d_total) (void)hipFree(f.d_total);
+    if (f.d_stats) (void)hipFree(f.d_stats);
     f.d_lanes = nullptr;
     f.d_total = nullptr;
+    f.d_stats = nullptr;
     f.lanes_cap = 0;
 }
 
@@ -1032,6 +1035,10 @@ bc_status fused_run(bc_graph_s *g, const std::vector<int32_t> &s_int,
     if (sigma) BC_TRY_HIP(hipMalloc(&x_sigma, (size_t)kWave * n * sizeof(double)));
     LaunchTimer timer;
     timer.on = prof;
+    if (prof) {
+        if (!f.d_stats) BC_TRY_HIP(hipMalloc(&f.d_stats, 12 * sizeof(unsigned long long)));
+        BC_TRY_HIP(hipMemsetAsync(f.d_stats, 0, 12 * sizeof(unsigned long long), stream));
+    }
     bool range = false;
     int32_t run_depth = 0;
     std::vector<int2> bt;
@@ -1043,6 +1050,7 @@ bc_status fused_run(bc_graph_s *g, const std::vector<int32_t> &s_int,
             const BatchPlan &bp = plan[(size_t)(b0 + i)];
             BatchDev &d = f.h_devs[(size_t)i];
             d.narrow = narrow ? 1 : 0;
+            d.stats = prof ? f.d_stats : nullptr;
             d.nseg = bp.nseg;
             d.seg_start = bp.nseg ? d_seg_start + bp.seg_first : nullptr;
             d.seg_out = bp.nseg ? d_seg_out + (bp.seg_first - (b0 + i)) : nullptr;
@@ -1053,7 +1061,7 @@ bc_status fused_run(bc_graph_s *g, const std::vector<int32_t> &s_int,
         if (e == hipSuccess)
             e = hipMemcpyAsync(f.d_batches, bt.data(), (size_t)m * sizeof(int2),
                                hipMemcpyHostToDevice, stream);
-        if (e == hipSuccess) e = timer.begin(BC_PROF_FORWARD, stream);
+        if (e == hipSuccess) e = timer.begin(BC_PROF_FUSED, stream);
         if (e == hipSuccess) e = batch_fused(f.d_devs, m, narrow, f.d_lanes, f.d_batches, stream);
         if (e == hipSuccess) e = timer.end(stream);
         if (e == hipSuccess)
@@ -1111,28 +1119,25 @@ bc_status fused_run(bc_graph_s *g, const std::vector<int32_t> &s_int,
         return from_hip(e);
     }
     if (nb > 0) g->batch_depth_hint.store(run_depth);
-    if (prof) {
-        // whole batches per launch: counted as forward launches, no work counters
-        std::lock_guard<std::mutex> plk(g->prof_mu);
-        for (size_t i = 0; i < timer.used; ++i) {
-            float ms = 0.f;
-            if (hipEventElapsedTime(&ms, timer.ev[2 * i], timer.ev[2 * i + 1]) == hipSuccess)
-                g->prof.ms[timer.cls[i]] += ms;
-            g->prof.launches[timer.cls[i]] += 1;
-        }
-        g->prof.runs += 1;
-    }
+    if (prof) accumulate_profile(g, timer, f.d_stats);
     timer.destroy();
     return range ? BC_ERR_RANGE : BC_OK;
 }
 
-// The device-resident loop runs a batch on one compute unit: it pays off
-// when the graph is small (launch and polling costs dominate the host-driven
-// loop) or when there are enough batches to occupy many compute units.
+// The device-resident loop runs a batch on one compute unit (up to 256
+// batches at once); the host-driven loop runs a batch across the device.
+// Measured on MI355X (R-MAT graphs of 53K to 7.6M arcs): one batch takes about
+// 2 ms + 50 ns per arc on the device loop and, amortised over the host loop's
+// concurrent parts, 0.8 ms + 0.15 ns per arc on the host loop.  AUTO picks
+// the loop with the lower estimate for the call's batch count.
 bool use_fused(const bc_graph_s *g, int32_t level_loop, int32_t nbatches) {
     if (level_loop == BC_LOOP_DEVICE) return true;
     if (level_loop == BC_LOOP_HOST) return false;
-    return g->nnz <= ((int64_t)1 << 20) || (nbatches >= 32 && g->nnz <= ((int64_t)1 << 24));
+    const double arcs = (double)g->nnz;
+    const double device = 2e-3 + 50e-9 * arcs;
+    const double host = 0.8e-3 + 0.15e-9 * arcs;
+    const double rounds = std::ceil((double)nbatches / 256.0);
+    return (double)nbatches * host > rounds * device;
 }
 
 // Batches run at once for `concurrency` (0: by workspace size; the choice
@@ -1808,7 +1813,7 @@ bc_status bc_autotune(bc_graph_t g, const int32_t *sources, int32_t k, void *str
         return BC_OK;
     };
     auto batched = [&](int32_t width, int32_t div, double &ms) {
-        return timed([&]() { return batched_run(g, sources, m, d_bc, width, div, 1, BC_LOOP_HOST,
+        return timed([&]() { return batched_run(g, sources, m, d_bc, width, div, 1, BC_LOOP_AUTO,
                                                 stream, nullptr, nullptr); }, ms);
     };
     // sparse-step threshold at width 64, then width 32 with the best threshold
