@@ -470,9 +470,12 @@ __global__ __launch_bounds__(kBlock) void k_batch_forward_finish(BatchDev d, int
 // array is full), picks the step of the next iteration (sparse when the new
 // frontier has few arcs) and clears the list counters.  waves[s] = the waves
 // of the kernel of frontier set s.
-__global__ __launch_bounds__(kBlock) void k_batch_level_done(BatchDev d, int32_t L, int32_t w0,
-                                                             int32_t w1, int32_t w2) {
-    __shared__ unsigned long long sc[kBlock], sa[kBlock];
+constexpr int kDoneBlock = 1024;
+
+__global__ __launch_bounds__(kDoneBlock) void k_batch_level_done(BatchDev d, int32_t L,
+                                                                 int32_t w0, int32_t w1,
+                                                                 int32_t w2) {
+    __shared__ unsigned long long sc[kDoneBlock], sa[kDoneBlock];
     const int t = threadIdx.x;
     const bool live = !(L > d.ctrl[kCtlDeepest] || L + 1 >= d.lcap);
     const int mode = d.ctrl[kCtlMode];
@@ -481,7 +484,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_level_done(BatchDev d, int32_t
         const int32_t waves[kFrontSets] = {mode ? 0 : w0, mode ? w1 : 0, w2};
         for (int set = 0; set < kFrontSets; ++set) {
             const unsigned long long *slot = d.front + (size_t)set * kFrontWaves * 2;
-            for (int32_t w = t; w < waves[set]; w += kBlock) {
+            for (int32_t w = t; w < waves[set]; w += kDoneBlock) {
                 c += slot[2 * w];
                 a += slot[2 * w + 1];
             }
@@ -490,7 +493,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_level_done(BatchDev d, int32_t
     sc[t] = c;
     sa[t] = a;
     __syncthreads();
-    for (int h = kBlock / 2; h >= 1; h >>= 1) {
+    for (int h = kDoneBlock / 2; h >= 1; h >>= 1) {
         if (t < h) {
             sc[t] += sc[t + h];
             sa[t] += sa[t + h];
@@ -617,15 +620,29 @@ __global__ __launch_bounds__(kBlock) void k_batch_sparse_compact(BatchDev d, int
             pi += s_items[w];
         }
         __syncthreads();  // the shared counts are rewritten by the next round
+        uint32_t big = 0;  // bit j: vertex 16i+j is a listed candidate of degree > 64
 #pragma unroll
         for (int j = 0; j < 16; ++j) {
             if (!((bits >> j) & 1u)) continue;
             const int32_t v = (i << 4) + j;
-            if (v < d.big_end) {
-                for (uint32_t it = d.item_first[v]; it < d.item_first[v + 1]; ++it)
-                    d.ilist[pi++] = it;
-            } else {
-                d.clist[p++] = v;
+            if (v < d.big_end) big |= 1u << j;
+            else d.clist[p++] = v;
+        }
+        // chunk items of the large candidates, written by the whole wave (a
+        // hub has hundreds of items)
+        uint64_t owners = __ballot(big != 0u);
+        while (owners) {
+            const int src = __ffsll((unsigned long long)owners) - 1;
+            owners &= owners - 1;
+            uint32_t sbig = __shfl(big, src);
+            uint32_t spi = __shfl(pi, src);
+            const int32_t sv0 = __shfl(i, src) << 4;
+            while (sbig) {
+                const int j = __ffs(sbig) - 1;
+                sbig &= sbig - 1;
+                const uint32_t f0 = d.item_first[sv0 + j], cnt = d.item_first[sv0 + j + 1] - f0;
+                for (uint32_t q = (uint32_t)lane; q < cnt; q += kWave) d.ilist[spi + q] = f0 + q;
+                spi += cnt;
             }
         }
     }
@@ -820,16 +837,39 @@ __global__ __launch_bounds__(kBlock) void k_batch_reverse(BatchDev d, int32_t L)
 }
 
 // Finalise level L for the vertices the reverse kernel leaves open: the split
-// vertices (v < multi_end), whose child sums are the partial rows of their
-// chunks added in chunk order, or, with leaf set (the deepest level), every
-// vertex, with sum 0.  delta = sigma * sum, c = (1 + delta) / sigma, BC[v] +=
-// the lanes' deltas.
+// vertices (v < multi_end, one wave each), whose child sums are the partial
+// rows of their chunks added in chunk order, or, with leaf set (the deepest
+// level), every vertex, with sum 0.  delta = sigma * sum, c = (1 + delta) /
+// sigma, BC[v] += the lanes' deltas.
 template <bool N>
 __device__ void finalize_level(const BatchDev &d, int32_t L, int32_t leaf, int32_t wave,
                                int32_t nwaves) {
     const int lane = lane_id();
     const uint64_t *FL = d.F + (size_t)L * (size_t)d.n;
-    const int32_t vend = leaf ? d.n : d.multi_end;
+    if (!leaf) {
+        // split vertices, one wave each: the chunks' partial rows added in
+        // chunk order (8 rows in flight), then delta, c and BC
+        for (int32_t v = wave; v < d.multi_end; v += nwaves) {
+            const uint64_t mv = FL[v];
+            if (mv == 0ull) continue;
+            const bool on = (mv >> lane) & 1ull;
+            const double sig = on ? sig_at<N>(d, (size_t)v * kWave + lane) : 1.0;
+            const uint32_t i0 = d.item_first[v], i1 = d.item_first[v + 1];
+            double t = 0.0;
+            uint32_t i = i0;
+            for (; i + 8 <= i1; i += 8) {
+                double x[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) x[q] = d.partial[(size_t)(i + q) * kWave + lane];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) t += x[q];
+            }
+            for (; i < i1; ++i) t += d.partial[(size_t)i * kWave + lane];
+            settle(d, v, mv, sig, t);
+        }
+        return;
+    }
+    const int32_t vend = d.n;
     const int32_t groups = (vend + kWave - 1) / kWave;
     for (int32_t gi = wave; gi < groups; gi += nwaves) {
         const int32_t me = gi * kWave + lane;
@@ -859,23 +899,7 @@ __device__ void finalize_level(const BatchDev &d, int32_t L, int32_t leaf, int32
                 const bool on = (mj[u] >> lane) & 1ull;
                 const size_t at = (size_t)(vj[u] < 0 ? 0 : vj[u]) * kWave + lane;
                 sig[u] = on ? sig_at<N>(d, at) : 1.0;
-                sum[u] = 0.0;
-                if (on && !leaf) {
-                    // the chunks' partial rows in chunk order, 8 loads in flight
-                    const int32_t v = vj[u];
-                    const uint32_t i0 = d.item_first[v], i1 = d.item_first[v + 1];
-                    double t = 0.0;
-                    uint32_t i = i0;
-                    for (; i + 8 <= i1; i += 8) {
-                        double x[8];
-#pragma unroll
-                        for (int q = 0; q < 8; ++q) x[q] = d.partial[(size_t)(i + q) * kWave + lane];
-#pragma unroll
-                        for (int q = 0; q < 8; ++q) t += x[q];
-                    }
-                    for (; i < i1; ++i) t += d.partial[(size_t)i * kWave + lane];
-                    sum[u] = t;
-                }
+                sum[u] = 0.0;  // the deepest level has no children
             }
             double delta[kFinal];
 #pragma unroll
@@ -1125,7 +1149,8 @@ hipError_t batch_forward_done(const BatchDev &d, int32_t level, uint64_t full,
     const int32_t w0 = grid_of(d.items + groups) * kWavesPerBlock;
     const int32_t w1 = kSparseGrid * kWavesPerBlock;
     const int32_t w2 = d.multi_end > 0 ? grid_of(d.multi_end) * kWavesPerBlock : 0;
-    hipLaunchKernelGGL(k_batch_level_done, dim3(1), dim3(kBlock), 0, stream, d, level, w0, w1, w2);
+    hipLaunchKernelGGL(k_batch_level_done, dim3(1), dim3(kDoneBlock), 0, stream, d, level, w0, w1,
+                       w2);
     return hipGetLastError();
 }
 
@@ -1137,10 +1162,11 @@ hipError_t batch_reverse(const BatchDev &d, int32_t level, hipStream_t stream) {
 }
 
 hipError_t batch_finalize(const BatchDev &d, int32_t level, bool deepest, hipStream_t stream) {
-    const int32_t vend = deepest ? d.n : d.multi_end;
-    if (vend == 0) return hipSuccess;
-    hipLaunchKernelGGL(d.narrow ? k_batch_finalize<true> : k_batch_finalize<false>, dim3(grid_of((vend + kWave - 1) / kWave)), dim3(kBlock),
-                       0, stream, d, level, deepest ? 1 : 0);
+    // deepest level: every vertex, 64 per wave; otherwise one wave per split vertex
+    const int64_t waves = deepest ? (d.n + kWave - 1) / kWave : d.multi_end;
+    if (waves == 0) return hipSuccess;
+    hipLaunchKernelGGL(d.narrow ? k_batch_finalize<true> : k_batch_finalize<false>,
+                       dim3(grid_of(waves)), dim3(kBlock), 0, stream, d, level, deepest ? 1 : 0);
     return hipGetLastError();
 }
 
