@@ -119,9 +119,11 @@ def serving_bench(args) -> int:
     """Serving mix: Poisson stream of BC requests over 16 resident R-MAT graphs
     (scales 14-20 with two seeds each, plus 21 and 22; edge factor 16); each
     request asks for k in {1, 8, 64} random sources of a uniformly chosen graph.
-    Saturation throughput is measured with a burst first; the Poisson stream
-    then runs at 0.8 of it.  Reports GTEPS (sum of k * nnz over the requests /
-    wall time) and p50 / p99 latency from arrival to the result on the host."""
+    Saturation throughput is measured with a burst first; Poisson streams then
+    run at 0.5, 0.8 and 0.95 of it (the headline line is --serving-load), and
+    once more under a small workspace budget that makes admission queue.
+    Reports GTEPS (sum of k * nnz over the requests / wall time) and p50 / p99
+    latency from arrival to the result on the host."""
     import numpy as np
     import torch
 
@@ -147,11 +149,31 @@ def serving_bench(args) -> int:
         k = int(rng.choice([1, 8, 64]))
         return gid, gg.sample_sources(graphs[gid], k, seed=1000 + i)
 
+    def poisson_run(srv, lam, reqs):
+        """Submit `reqs` as a Poisson stream of rate lam; (wall s, latency stats)."""
+        srv.completed.clear()
+        t0 = time.perf_counter()
+        arrival = t0
+        futs = []
+        for gid, src in reqs:
+            arrival += float(rng.exponential(1.0 / lam))
+            delay = arrival - time.perf_counter()
+            if delay > 0:
+                time.sleep(delay)
+            futs.append(srv.submit(gid, src))
+        for f in futs:
+            f.result()
+        return time.perf_counter() - t0, srv.latency_stats()
+
     budget = int(args.hbm_budget_gib) << 30
     srv = BCServer(Gs, budget=budget, slots=args.slots, max_lanes=256)
-    # warm-up: every graph once (landmarks, level hints, workspaces)
+    # warm-up: every graph once (landmarks, level hints, workspaces), then
+    # `serving_warmup` requests of the mix
     for gid in gids:
         srv.submit(gid, gg.sample_sources(graphs[gid], 64, seed=7)).result()
+    for f in [srv.submit(gid, src) for gid, src in
+              (make_request(50_000 + i) for i in range(args.serving_warmup))]:
+        f.result()
     # saturation: a burst
     burst = [make_request(i) for i in range(args.serving_burst)]
     t = time.perf_counter()
@@ -162,24 +184,37 @@ def serving_bench(args) -> int:
     sat_rate = len(burst) / sat_dt
     sat_gteps = sum(src.size * graphs[gid].nnz for gid, src in burst) / sat_dt / 1e9
     print(f"# saturation {sat_rate:.1f} req/s, {sat_gteps:.1f} GTEPS", file=sys.stderr, flush=True)
-    # Poisson stream at 0.8 x saturation
-    lam = args.serving_load * sat_rate
-    stream_reqs = [make_request(10_000 + i) for i in range(args.serving_requests)]
-    srv.completed.clear()
-    t0 = time.perf_counter()
-    arrival = t0
-    futs = []
-    for gid, src in stream_reqs:
-        arrival += float(rng.exponential(1.0 / lam))
-        delay = arrival - time.perf_counter()
-        if delay > 0:
-            time.sleep(delay)
-        futs.append(srv.submit(gid, src))
-    for f in futs:
-        f.result()
-    wall = time.perf_counter() - t0
+    # Poisson streams at several fractions of saturation; the headline is
+    # args.serving_load
+    loads = sorted(set([0.5, 0.8, 0.95, args.serving_load]))
+    per_load = {}
+    stream_reqs = None
+    for li, load in enumerate(loads):
+        reqs = [make_request(100_000 * (li + 1) + i) for i in range(args.serving_requests)]
+        wall_l, lat_l = poisson_run(srv, load * sat_rate, reqs)
+        work_l = sum(src.size * graphs[gid].nnz for gid, src in reqs)
+        per_load[str(load)] = {"gteps": round(work_l / wall_l / 1e9, 3),
+                               "p50_ms": round(lat_l["p50_ms"], 3),
+                               "p99_ms": round(lat_l["p99_ms"], 3),
+                               "mean_ms": round(lat_l["mean_ms"], 3)}
+        print(f"# load {load}: {per_load[str(load)]}", file=sys.stderr, flush=True)
+        if load == args.serving_load:
+            stream_reqs, wall, lat = reqs, wall_l, lat_l
+    launches = srv.launches
     srv.close()
-    lat = srv.latency_stats()
+    # the same mix under a small workspace budget: admission queues launches
+    stress = None
+    if args.serving_stress_gib > 0:
+        srv2 = BCServer(Gs, budget=int(args.serving_stress_gib) << 30, slots=args.slots,
+                        max_lanes=256)
+        reqs = [make_request(900_000 + i) for i in range(args.serving_requests)]
+        wall_s, lat_s = poisson_run(srv2, args.serving_load * sat_rate, reqs)
+        work_s = sum(src.size * graphs[gid].nnz for gid, src in reqs)
+        stress = {"hbm_budget_gib": args.serving_stress_gib,
+                  "gteps": round(work_s / wall_s / 1e9, 3), "p50_ms": round(lat_s["p50_ms"], 3),
+                  "p99_ms": round(lat_s["p99_ms"], 3), "max_reserved_gib":
+                  round(srv2.max_reserved / 2**30, 2), "launches": srv2.launches}
+        srv2.close()
     work = sum(src.size * graphs[gid].nnz for gid, src in stream_reqs)
     value = work / wall / 1e9
     cpu = None
@@ -197,8 +232,8 @@ def serving_bench(args) -> int:
                          f"{dt:.2f} s on {threads} threads"}
     rec = {
         "metric": METRIC, "value": round(value, 3), "unit": "GTEPS", "n_gpus": 1,
-        "steps": len(stream_reqs), "warmup": len(gids), "ms_per_step": round(wall * 1e3 /
-                                                                            len(stream_reqs), 3),
+        "steps": len(stream_reqs), "warmup": len(gids) + args.serving_warmup,
+        "ms_per_step": round(wall * 1e3 / len(stream_reqs), 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "serving-mix", "graphs": len(gids), "edgefactor": 16,
@@ -208,7 +243,8 @@ def serving_bench(args) -> int:
         "p50_ms": round(lat["p50_ms"], 3), "p99_ms": round(lat["p99_ms"], 3),
         "mean_latency_ms": round(lat["mean_ms"], 3),
         "saturation": {"requests_per_s": round(sat_rate, 2), "gteps": round(sat_gteps, 3)},
-        "launches": srv.launches, "roofline": None, "cpu_baseline": cpu,
+        "loads": per_load, "stress": stress,
+        "launches": launches, "roofline": None, "cpu_baseline": cpu,
     }
     print(json.dumps(rec), flush=True)
     for G in Gs.values():
@@ -219,8 +255,8 @@ def serving_bench(args) -> int:
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="rmat-s22-ef16")
     ap.add_argument("--mode", default="auto", choices=["auto", "plain", "batched"])
     ap.add_argument("--batch-width", type=int, default=0)
@@ -243,7 +279,10 @@ def main() -> int:
                     help="run one device copy of this size first (counter calibration)")
     ap.add_argument("--slots", type=int, default=4, help="serving: launches in flight")
     ap.add_argument("--hbm-budget-gib", type=int, default=64, help="serving: HBM budget")
-    ap.add_argument("--serving-requests", type=int, default=400)
+    ap.add_argument("--serving-requests", type=int, default=2000)
+    ap.add_argument("--serving-warmup", type=int, default=100)
+    ap.add_argument("--serving-stress-gib", type=int, default=8,
+                    help="serving: second run under this workspace budget (0 = skip)")
     ap.add_argument("--serving-burst", type=int, default=200)
     ap.add_argument("--serving-load", type=float, default=0.8)
     ap.add_argument("--serving-seed", type=int, default=105)

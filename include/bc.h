@@ -194,7 +194,9 @@ bc_status bc_run_detail(bc_graph_t g, const int32_t *sources, int32_t k, const b
                         double *bc_out, int32_t *dist, double *sigma);
 
 /* Device bytes one run with k sources and the given options would take for its
- * workspace (for admission control).  opt may be NULL. */
+ * workspaces (for admission control): one per concurrent part, or the
+ * device-resident loop's per-batch pool, at the graph's current level-array
+ * estimate (a deeper graph grows it).  opt may be NULL. */
 bc_status bc_workspace_bytes(bc_graph_t g, int32_t k, const bc_options *opt, size_t *bytes);
 
 /* Free pooled workspaces that are idle.  Safe while other runs are in flight. */

@@ -1722,11 +1722,24 @@ bc_status bc_workspace_bytes(bc_graph_t g, int32_t k, const bc_options *opt, siz
     if (!g || !bytes || k < 0) return BC_ERR_INVALID_ARG;
     bc_status st = check_options(opt);
     if (st != BC_OK) return st;
-    if (use_batched(g, opt, k))
-        *bytes = batch_ws_bytes(g) +
-                 batch_level_bytes(g, std::max(16, g->batch_depth_hint.load() + 8));
-    else
+    if (!use_batched(g, opt, k)) {
         *bytes = plain_ws_bytes(g);
+        return BC_OK;
+    }
+    const int32_t width = batch_width_of(g, opt);
+    const int32_t nb = (k + width - 1) / width;
+    const int32_t lcap = std::max(16, g->batch_depth_hint.load() + 8);
+    if (use_fused(g, opt ? opt->level_loop : 0, nb)) {
+        // the device-loop pool: per-batch workspaces, BC arrays and control words
+        const int32_t cap = fused_cap(g, nb, lcap);
+        const size_t n = (size_t)std::max<int32_t>(g->n, 1);
+        *bytes = (size_t)cap * (fused_batch_bytes(g, lcap) + n * sizeof(double) +
+                                kCtlInts * sizeof(int32_t)) + n * sizeof(double);
+    } else {
+        // one workspace per concurrent part
+        const int32_t parts = parts_of(g, opt ? opt->concurrency : 0, nb);
+        *bytes = (size_t)parts * (batch_ws_bytes(g) + batch_level_bytes(g, lcap));
+    }
     return BC_OK;
 }
 

@@ -60,7 +60,8 @@ class GpuExecutor:
     def bytes_needed(self, graph_id, k: int, nreq: int) -> int:
         from . import BC_MODE_BATCHED, make_options
         G = self.graphs[graph_id]
-        ws = G.workspace_bytes(max(k, 1), make_options(BC_MODE_BATCHED))
+        # bc_run_multi runs its batches as one part (or in the device loop)
+        ws = G.workspace_bytes(max(k, 1), make_options(BC_MODE_BATCHED, concurrency=1))
         return int(ws) + nreq * 8 * G.n
 
     def run(self, slot: int, graph_id, requests):
