@@ -690,18 +690,23 @@ __device__ void add_segments(const BatchDev &d, int32_t v, double delta) {
 // (lane s meaningful for s in mv): delta = sigma * acc, c = (1 + delta) /
 // sigma, and the lanes' deltas added to BC[v] (or to the requests' outputs).
 // Called with every lane active.
-__device__ __forceinline__ void settle(const BatchDev &d, int32_t v, uint64_t mv, double sig,
-                                       double acc) {
+// As settle, but BC[v]'s share is returned (the lanes' delta sum, the same
+// in every lane) for the caller to add later; segments are added at once.
+__device__ __forceinline__ double settle_deferred(const BatchDev &d, int32_t v, uint64_t mv,
+                                                  double sig, double acc) {
     const int lane = lane_id();
     const bool on = (mv >> lane) & 1ull;
     const double delta = on ? sig * acc : 0.0;
     if (on) d.coef[(size_t)v * kWave + lane] = (1.0 + delta) / sig;
-    if (d.nseg == 0) {
-        const double tot = wave_sum(delta);
-        if (lane == 0 && tot != 0.0) d.bc[v] += tot;
-    } else {
-        add_segments(d, v, delta);
-    }
+    if (d.nseg == 0) return wave_sum(delta);
+    add_segments(d, v, delta);
+    return 0.0;
+}
+
+__device__ __forceinline__ void settle(const BatchDev &d, int32_t v, uint64_t mv, double sig,
+                                       double acc) {
+    const double tot = settle_deferred(d, v, mv, sig, acc);
+    if (lane_id() == 0 && tot != 0.0) d.bc[v] += tot;
 }
 
 // Chunk item of a vertex of degree > 64: sums of c over children; a vertex
@@ -748,9 +753,14 @@ __device__ void bwd_group(const BatchDev &d, int32_t L, int32_t base, Work &wk) 
     int cur = -1;
     double acc = 0.0;
     double cur_sig = 1.0;   // sigma of the owner being accumulated (its lanes)
+    // BC shares of the group's owners, held by the owner's lane and added in
+    // one parallel read-modify-write at the end (a load per owner otherwise
+    // stalls the wave)
+    double my_bc = 0.0;
     auto flush = [&]() {
         if (cur < 0) return;
-        settle(d, base + cur, shfl64(mv, cur), cur_sig, acc);  // all lanes active here
+        const double tot = settle_deferred(d, base + cur, shfl64(mv, cur), cur_sig, acc);
+        if (lane == cur) my_bc = tot;  // all lanes active here
     };
     for (uint32_t c0 = 0; c0 < total; c0 += kWave * kRounds) {
         int o[kRounds];
@@ -820,6 +830,7 @@ __device__ void bwd_group(const BatchDev &d, int32_t L, int32_t base, Work &wk) 
         for (int u = 0; u < kUnroll; ++u)
             if (on[u]) d.coef[(size_t)vj[u] * kWave + lane] = 1.0 / sig[u];
     }
+    if (my_bc != 0.0) d.bc[base + lane] += my_bc;
 }
 
 template <bool N>
