@@ -40,7 +40,7 @@ namespace {
 
 constexpr int kProbe = 8;    // arcs per lane probed together in a chunk item
 constexpr int kUnroll = 8;   // neighbour rows gathered concurrently
-constexpr int kRounds = 4;   // runs of 64 flattened arcs probed together in a group item
+constexpr int kRounds = 2;   // runs of 64 flattened arcs probed together in a group item
 
 __device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
 
@@ -93,7 +93,7 @@ struct Work {
     uint32_t owners = 0, arcs = 0, hits = 0;
 };
 
-__device__ void report_work(unsigned long long *out, const Work &wk) {
+__device__ __forceinline__ void report_work(unsigned long long *out, const Work &wk) {
     unsigned long long o = wk.owners, a = wk.arcs, h = wk.hits;
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) {
@@ -258,7 +258,7 @@ struct Front {
     unsigned long long arcs = 0;
 };
 
-__device__ void report_front(const BatchDev &d, int set, const Front &fr) {
+__device__ __forceinline__ void report_front(const BatchDev &d, int set, const Front &fr) {
     unsigned long long c = fr.cnt, a = fr.arcs;
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) {
@@ -275,8 +275,8 @@ __device__ void report_front(const BatchDev &d, int set, const Front &fr) {
 
 // Chunk item of a vertex of degree > 64.
 template <bool N>
-__device__ void fwd_chunk(const BatchDev &d, int32_t L, uint32_t item, uint64_t full, Work &wk,
-                          Front &fr) {
+__device__ __forceinline__ void
+fwd_chunk(const BatchDev &d, int32_t L, uint32_t item, uint64_t full, Work &wk, Front &fr) {
     const int lane = lane_id();
     const int2 info = d.item_info[item];
     const int32_t w = info.x, j = info.y;
@@ -317,8 +317,9 @@ __device__ void fwd_chunk(const BatchDev &d, int32_t L, uint32_t item, uint64_t 
 // candidates of any degree, F_{L+1} cleared beforehand).  The wave flattens
 // the arcs of the vertices that still have unvisited lanes into runs of 64.
 template <bool N>
-__device__ void fwd_group(const BatchDev &d, int32_t L, int32_t base, const int32_t *list,
-                          int32_t count, uint64_t full, Work &wk, Front &fr) {
+__device__ __forceinline__ void
+fwd_group(const BatchDev &d, int32_t L, int32_t base, const int32_t *list, int32_t count,
+          uint64_t full, Work &wk, Front &fr) {
     const int lane = lane_id();
     const uint64_t *FL = d.F + (size_t)L * (size_t)d.n;
     uint64_t *FN = d.F + (size_t)(L + 1) * (size_t)d.n;
@@ -433,8 +434,8 @@ __global__ __launch_bounds__(kBlock) void k_batch_forward(BatchDev d, int32_t L,
 // After a forward iteration: completes the split vertices (their summed
 // counts, F_{L+1}, vis) and counts them into the new frontier.
 template <bool N>
-__device__ void finish_split(const BatchDev &d, int32_t L, int32_t wave, int32_t nwaves,
-                             Front &fr) {
+__device__ __forceinline__ void
+finish_split(const BatchDev &d, int32_t L, int32_t wave, int32_t nwaves, Front &fr) {
     uint64_t *FN = d.F + (size_t)(L + 1) * (size_t)d.n;
     const int lane = lane_id();
     for (int32_t w = wave; w < d.multi_end; w += nwaves) {
@@ -675,7 +676,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_sparse_pull(BatchDev d, int32_
 // with the same butterfly whatever the segment's position, so a request's sum
 // does not depend on where in the batch its lanes sit; it is added to the
 // request's output in caller vertex order.
-__device__ void add_segments(const BatchDev &d, int32_t v, double delta) {
+__device__ __forceinline__ void add_segments(const BatchDev &d, int32_t v, double delta) {
     const int lane = lane_id();
     for (int32_t g = 0; g < d.nseg; ++g) {
         const int32_t a = d.seg_start[g], len = d.seg_start[g + 1] - a;
@@ -713,7 +714,7 @@ __device__ __forceinline__ void settle(const BatchDev &d, int32_t v, uint64_t mv
 // with one chunk is completed here, a split vertex leaves the item's partial
 // row for the finalising pass.
 template <bool N>
-__device__ void bwd_chunk(const BatchDev &d, int32_t L, uint32_t item, Work &wk) {
+__device__ __forceinline__ void bwd_chunk(const BatchDev &d, int32_t L, uint32_t item, Work &wk) {
     const int lane = lane_id();
     const int2 info = d.item_info[item];
     const int32_t v = info.x, j = info.y;
@@ -732,7 +733,7 @@ __device__ void bwd_chunk(const BatchDev &d, int32_t L, uint32_t item, Work &wk)
 }
 
 template <bool N>
-__device__ void bwd_group(const BatchDev &d, int32_t L, int32_t base, Work &wk) {
+__device__ __forceinline__ void bwd_group(const BatchDev &d, int32_t L, int32_t base, Work &wk) {
     const int lane = lane_id();
     const uint64_t *FL = d.F + (size_t)L * (size_t)d.n;
     const uint64_t *FC = d.F + (size_t)(L + 1) * (size_t)d.n;
@@ -853,8 +854,8 @@ __global__ __launch_bounds__(kBlock) void k_batch_reverse(BatchDev d, int32_t L)
 // level), every vertex, with sum 0.  delta = sigma * sum, c = (1 + delta) /
 // sigma, BC[v] += the lanes' deltas.
 template <bool N>
-__device__ void finalize_level(const BatchDev &d, int32_t L, int32_t leaf, int32_t wave,
-                               int32_t nwaves) {
+__device__ __forceinline__ void
+finalize_level(const BatchDev &d, int32_t L, int32_t leaf, int32_t wave, int32_t nwaves) {
     const int lane = lane_id();
     const uint64_t *FL = d.F + (size_t)L * (size_t)d.n;
     if (!leaf) {
@@ -954,7 +955,10 @@ __global__ __launch_bounds__(kBlock) void k_batch_finalize(BatchDev d, int32_t L
 // (the waves of a workgroup share one compute unit and its L1, so the barrier
 // orders their global-memory accesses).  A call's batches run as the
 // workgroups of one launch.  The per-wave step code is the one the grid-wide
-// kernels run.  ctrl of the batch receives the depth and the flags
+// kernels run, inlined here as there: no kernel of this library makes calls
+// (with the steps as out-of-line calls, this kernel's dependency sums came
+// out wrong on gfx950, varying from run to run, while the level masks and
+// path counts stayed exact).  ctrl of the batch receives the depth and the flags
 // (truncation: the host runs the call again with a longer level array).
 constexpr int kFusedBlock = 1024;
 constexpr int kFusedWaves = kFusedBlock / kWave;

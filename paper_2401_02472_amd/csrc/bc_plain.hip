@@ -134,8 +134,8 @@ __device__ __forceinline__ void set_delta(const LevelCtx &c, int32_t v, double a
 
 // ---- bucket 0: one lane per vertex (degree <= 8) --------------------------
 template <bool FWD>
-__device__ void level_b0(const LevelCtx &c, uint32_t item, bool leaf, double *delta_out,
-                         Work &wk) {
+__device__ __forceinline__ void
+level_b0(const LevelCtx &c, uint32_t item, bool leaf, double *delta_out, Work &wk) {
     const uint32_t idx = item * kWave + (uint32_t)lane_id();
     if (idx >= c.cur.cnt[0]) return;
     const int32_t w = c.d.q[0][c.cur.start[0] + idx];
@@ -151,8 +151,8 @@ __device__ void level_b0(const LevelCtx &c, uint32_t item, bool leaf, double *de
 
 // ---- bucket 1: kB1Lanes lanes per vertex (degree <= 64) --------------------
 template <bool FWD>
-__device__ void level_b1(const LevelCtx &c, uint32_t item, bool leaf, double *delta_out,
-                         Work &wk) {
+__device__ __forceinline__ void
+level_b1(const LevelCtx &c, uint32_t item, bool leaf, double *delta_out, Work &wk) {
     const int lane = lane_id();
     const int sub = lane & (kB1Lanes - 1);
     const uint32_t idx = item * (kWave / kB1Lanes) + (uint32_t)(lane / kB1Lanes);
@@ -190,8 +190,8 @@ __device__ __forceinline__ double wave_arcs(const LevelCtx &c, int32_t cb, int32
 
 // ---- bucket 2: one wavefront per vertex (degree <= kChunkArcs) ------------
 template <bool FWD>
-__device__ void level_b2(const LevelCtx &c, uint32_t item, bool leaf, double *delta_out,
-                         Work &wk) {
+__device__ __forceinline__ void
+level_b2(const LevelCtx &c, uint32_t item, bool leaf, double *delta_out, Work &wk) {
     const int32_t w = c.d.q[2][c.cur.start[2] + item];
     double acc = 0.0;
     if (!leaf) acc = wave_arcs<FWD>(c, c.d.row_ptr[w], c.d.row_ptr[w + 1], wk);
@@ -204,8 +204,8 @@ __device__ void level_b2(const LevelCtx &c, uint32_t item, bool leaf, double *de
 
 // ---- bucket 3: one wavefront per chunk of kChunkArcs arcs ----------------
 template <bool FWD>
-__device__ void level_b3(const LevelCtx &c, uint32_t item, bool leaf, double *delta_out,
-                         Work &wk) {
+__device__ __forceinline__ void
+level_b3(const LevelCtx &c, uint32_t item, bool leaf, double *delta_out, Work &wk) {
     const int lane = lane_id();
     const uint32_t nv = (uint32_t)(c.cur.cnt3 >> 32);
     const int32_t slot = (int32_t)(c.cur.cstart3 + item);
@@ -241,7 +241,7 @@ __device__ void level_b3(const LevelCtx &c, uint32_t item, bool leaf, double *de
 // one wavefront per vertex.  Runs in the kernel after the level kernel, so the
 // partials are visible without fences.
 template <bool FWD>
-__device__ void finish_chunks(const LevelCtx &c, uint32_t wave, uint32_t nwaves,
+__device__ __forceinline__ void finish_chunks(const LevelCtx &c, uint32_t wave, uint32_t nwaves,
                               double *delta_out) {
     const int lane = lane_id();
     const uint32_t nv = (uint32_t)(c.cur.cnt3 >> 32);
@@ -269,7 +269,7 @@ __global__ __launch_bounds__(kBlock) void k_finish_reverse(PlainDev d, int32_t L
                          gridDim.x * kWavesPerBlock, delta_out);
 }
 
-__device__ void report_work(unsigned long long *out, const Work &wk) {
+__device__ __forceinline__ void report_work(unsigned long long *out, const Work &wk) {
     unsigned long long o = wk.owners, a = wk.arcs, h = wk.hits;
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) {

@@ -101,3 +101,36 @@ def test_trusted_flag_skips_symmetry_only():
     # structural errors are still caught before any device call
     st, _ = _create(2, [0, 1, 2], [1, 5], flags=bcm.BC_GRAPH_TRUST_SYMMETRIC)
     assert st == bcm.BC_ERR_INVALID_GRAPH
+
+
+LLVM_BIN = "/opt/rocm/llvm/bin"
+
+
+@pytest.mark.skipif(not os.path.exists(os.path.join(LLVM_BIN, "clang-offload-bundler")),
+                    reason="ROCm LLVM tools not installed")
+def test_device_code_makes_no_calls(tmp_path):
+    """Every device step is inlined into its kernels: the gfx950 code objects
+    of the library hold kernels only, no call or return instructions."""
+    import subprocess
+    _capi.load()
+    fat = tmp_path / "fat.bin"
+    subprocess.run([os.path.join(LLVM_BIN, "llvm-objcopy"), "--dump-section=.hip_fatbin=" + str(fat),
+                    _capi.LIB_PATH, str(tmp_path / "lib.copy")], check=True)
+    data = fat.read_bytes()
+    magic = b"__CLANG_OFFLOAD_BUNDLE__"
+    starts = [m.start() for m in re.finditer(re.escape(magic), data)]
+    assert starts, "no offload bundle in the library"
+    kernels = 0
+    for i, a in enumerate(starts):
+        b = starts[i + 1] if i + 1 < len(starts) else len(data)
+        part = tmp_path / f"b{i}.bin"
+        part.write_bytes(data[a:b])
+        co = tmp_path / f"co{i}.o"
+        subprocess.run([os.path.join(LLVM_BIN, "clang-offload-bundler"), "--unbundle", "--type=o",
+                        "--input=" + str(part), "--targets=hipv4-amdgcn-amd-amdhsa--gfx950",
+                        "--output=" + str(co)], check=True)
+        asm = subprocess.run([os.path.join(LLVM_BIN, "llvm-objdump"), "-d", str(co)],
+                             capture_output=True, text=True, check=True).stdout
+        assert "s_swappc" not in asm and "s_setpc" not in asm
+        kernels += asm.count("s_endpgm")
+    assert kernels > 0
