@@ -229,6 +229,22 @@ def grid_full(rows: int, cols: int) -> CSR:
                        rows=rows, cols=cols)
 
 
+def diamond_chain(k: int, width: int = 2) -> CSR:
+    """k diamonds in series: hub 0, `width` middle vertices joined to hub 0 and
+    to hub 1, then the next diamond from hub 1, and so on.  Hub i
+    has id i * (width + 1); the middles of diamond i (between hubs i-1 and
+    i) are the ids just below hub i's."""
+    step = width + 1
+    pairs = []
+    for i in range(k):
+        a = i * step
+        for j in range(1, width + 1):
+            pairs.append((a, a + j))
+            pairs.append((a + j, a + step))
+    return _from_pairs(k * step + 1, pairs, f"diamonds-{k}x{width}", kind="diamond_chain",
+                       k=k, width=width)
+
+
 def torus(rows: int, cols: int) -> CSR:
     pairs = []
     for r in range(rows):

@@ -12,7 +12,10 @@ stated at the top of that file.
 Pins (tests/test_oracle_pins.py) tie it to facts fixed independently of it:
 brute-force path counting on tiny graphs, closed forms for path, star, cycle,
 tree, complete bipartite, complete and hypercube graphs, the distance-sum
-invariant, additivity over sources, and NetworkX's betweenness.
+invariant, additivity over sources, and NetworkX's betweenness.  The
+extended-range functions (``*_ext``, long double) are pinned to closed forms on
+chains of diamonds whose path counts pass double's range, to exact big-integer
+counts on deep grids, and to the double oracle wherever counts fit double.
 """
 from __future__ import annotations
 
@@ -67,6 +70,14 @@ def _load():
                               f64p]
     lib.oracle_max_threads.restype = ctypes.c_int
     lib.oracle_max_threads.argtypes = []
+    lib.oracle_ld_digits.restype = ctypes.c_int
+    lib.oracle_ld_digits.argtypes = []
+    lib.oracle_single_source_ext.restype = ctypes.c_int
+    lib.oracle_single_source_ext.argtypes = [ctypes.c_int32, i32p, i32p, ctypes.c_int32, i32p,
+                                             f64p, i32p, f64p]
+    lib.oracle_bc_ext.restype = ctypes.c_int
+    lib.oracle_bc_ext.argtypes = [ctypes.c_int32, i32p, i32p, i32p, ctypes.c_int32, ctypes.c_int,
+                                  f64p]
     _lib = lib
     return lib
 
@@ -107,6 +118,47 @@ def bc(row_ptr, col_idx, sources, threads: int = 0):
     out = np.empty(n, dtype=np.float64)
     st = lib.oracle_bc(n, rpp, cip, srcp if src.size else None, int(src.size), int(threads),
                        out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    if st == INVALID_ARG:
+        raise OracleError("invalid argument")
+    return out, st
+
+
+def long_double_digits() -> int:
+    """Significand bits of the C long double the extended oracle computes in."""
+    return int(_load().oracle_ld_digits())
+
+
+def single_source_ext(row_ptr, col_idx, s: int, with_delta: bool = True):
+    """Extended range: (dist int32[n], sig_m float64[n], sig_e int32[n], delta float64[n] or
+    None, status), sigma = sig_m * 2**sig_e, computed in long double."""
+    lib = _load()
+    rp, rpp = _i32(row_ptr)
+    ci, cip = _i32(col_idx)
+    n = rp.shape[0] - 1
+    dist = np.empty(n, dtype=np.int32)
+    sig_m = np.empty(n, dtype=np.float64)
+    sig_e = np.empty(n, dtype=np.int32)
+    delta = np.empty(n, dtype=np.float64) if with_delta else None
+    i32 = ctypes.POINTER(ctypes.c_int32)
+    f64 = ctypes.POINTER(ctypes.c_double)
+    st = lib.oracle_single_source_ext(n, rpp, cip, int(s), dist.ctypes.data_as(i32),
+                                      sig_m.ctypes.data_as(f64), sig_e.ctypes.data_as(i32),
+                                      delta.ctypes.data_as(f64) if with_delta else None)
+    if st == INVALID_ARG:
+        raise OracleError("invalid argument")
+    return dist, sig_m, sig_e, delta, st
+
+
+def bc_ext(row_ptr, col_idx, sources, threads: int = 0):
+    """Extended range: (BC float64[n], status), the Brandes sum computed in long double."""
+    lib = _load()
+    rp, rpp = _i32(row_ptr)
+    ci, cip = _i32(col_idx)
+    src, srcp = _i32(sources)
+    n = rp.shape[0] - 1
+    out = np.empty(n, dtype=np.float64)
+    st = lib.oracle_bc_ext(n, rpp, cip, srcp if src.size else None, int(src.size), int(threads),
+                           out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
     if st == INVALID_ARG:
         raise OracleError("invalid argument")
     return out, st

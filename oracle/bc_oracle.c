@@ -34,10 +34,12 @@
  *     shortest path and have no effect.
  *
  * Status codes: 0 = ok, 1 = invalid argument, 4 = some sigma is not finite
- * (BC is then written but meaningless).
+ * (BC is then written but meaningless).  The *_ext entry points at the end
+ * run the same steps in long double for path counts beyond double's range.
  *
  * Built with gcc -O2, no fast-math.
  */
+#include <float.h>
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
@@ -180,6 +182,125 @@ int oracle_bc(int32_t n, const int32_t *row_ptr, const int32_t *col_idx, const i
     for (int t = 0; t < nt; ++t) {
         const double *p = partial + (size_t)t * (size_t)n;
         for (int32_t v = 0; v < n; ++v) bc[v] = bc[v] + p[v];
+    }
+    free(partial);
+    return status;
+}
+
+/* ---- extended range --------------------------------------------------------
+ *
+ * The same steps with sigma and delta held in long double (the x86 80-bit
+ * extended format: 64-bit significand, exponents to about +-16382), for graphs
+ * whose path counts pass double's range -- deep grids without shortcuts,
+ * chains of diamonds.  Extended-range counts are a reading beyond the paper,
+ * whose listing declares float: only the number format changes, not the
+ * algorithm.  sigma leaves as (m, e) with sigma = m * 2^e, 0.5 <= m < 1
+ * (m = 0, e = 0 where sigma = 0); delta and BC fit double. */
+
+static int single_source_ld(int32_t n, const int32_t *row_ptr, const int32_t *col_idx,
+                            int32_t s, int32_t *dist, long double *sigma, long double *delta,
+                            long double *bc, int32_t *order) {
+    int32_t reached = bfs_order(n, row_ptr, col_idx, s, dist, order);
+    for (int32_t v = 0; v < n; ++v) sigma[v] = 0.0L;
+    sigma[s] = 1.0L;
+    int status = OR_OK;
+    for (int32_t i = 1; i < reached; ++i) {
+        int32_t v = order[i];
+        long double acc = 0.0L;
+        for (int32_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {
+            int32_t w = col_idx[e];
+            if (dist[w] == dist[v] - 1) acc = acc + sigma[w];
+        }
+        sigma[v] = acc;
+        if (!isfinite(acc)) status = OR_RANGE;
+    }
+    if (delta == NULL) return status;
+    for (int32_t v = 0; v < n; ++v) delta[v] = 0.0L;
+    for (int32_t i = reached - 1; i >= 1; --i) {
+        int32_t v = order[i];
+        long double acc = 0.0L;
+        for (int32_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {
+            int32_t w = col_idx[e];
+            if (dist[w] == dist[v] + 1) acc = acc + (sigma[v] / sigma[w]) * (1.0L + delta[w]);
+        }
+        delta[v] = acc;
+        if (bc) bc[v] = bc[v] + delta[v];
+    }
+    return status;
+}
+
+/* Significand bits of long double (64 for the x86 extended format). */
+int oracle_ld_digits(void) { return LDBL_MANT_DIG; }
+
+/* dist[n], sigma as (sig_m[n], sig_e[n]), delta[n] (may be NULL) for one source. */
+int oracle_single_source_ext(int32_t n, const int32_t *row_ptr, const int32_t *col_idx,
+                             int32_t s, int32_t *dist, double *sig_m, int32_t *sig_e,
+                             double *delta) {
+    if (check_graph_args(n, row_ptr, col_idx) != OR_OK || s < 0 || s >= n || !dist || !sig_m ||
+        !sig_e)
+        return OR_INVALID_ARG;
+    int32_t *order = (int32_t *)malloc((size_t)n * sizeof(int32_t));
+    long double *sigma = (long double *)malloc((size_t)n * sizeof(long double));
+    long double *dl = delta ? (long double *)malloc((size_t)n * sizeof(long double)) : NULL;
+    int st = single_source_ld(n, row_ptr, col_idx, s, dist, sigma, dl, NULL, order);
+    for (int32_t v = 0; v < n; ++v) {
+        int e = 0;
+        sig_m[v] = (double)frexpl(sigma[v], &e);
+        sig_e[v] = e;
+        if (delta) delta[v] = (double)dl[v];
+    }
+    free(order);
+    free(sigma);
+    free(dl);
+    return st;
+}
+
+/* As oracle_bc, with the counts in long double (partials added in thread
+ * order in long double, then rounded to double). */
+int oracle_bc_ext(int32_t n, const int32_t *row_ptr, const int32_t *col_idx,
+                  const int32_t *sources, int32_t k, int threads, double *bc) {
+    if (check_graph_args(n, row_ptr, col_idx) != OR_OK || k < 0 || !bc ||
+        (k > 0 && !sources))
+        return OR_INVALID_ARG;
+    for (int32_t i = 0; i < k; ++i)
+        if (sources[i] < 0 || sources[i] >= n) return OR_INVALID_ARG;
+    for (int32_t v = 0; v < n; ++v) bc[v] = 0.0;
+    if (k == 0 || n == 0) return OR_OK;
+    int nt = 1;
+#ifdef _OPENMP
+    nt = threads > 0 ? threads : omp_get_max_threads();
+#else
+    (void)threads;
+#endif
+    if (nt > k) nt = k;
+    long double *partial = (long double *)calloc((size_t)nt * (size_t)n, sizeof(long double));
+    int status = OR_OK;
+#pragma omp parallel num_threads(nt) reduction(max : status)
+    {
+        int t = 0;
+#ifdef _OPENMP
+        t = omp_get_thread_num();
+#endif
+        int32_t lo = (int32_t)((int64_t)k * t / nt), hi = (int32_t)((int64_t)k * (t + 1) / nt);
+        int32_t *dist = (int32_t *)malloc((size_t)n * sizeof(int32_t));
+        int32_t *order = (int32_t *)malloc((size_t)n * sizeof(int32_t));
+        long double *sigma = (long double *)malloc((size_t)n * sizeof(long double));
+        long double *delta = (long double *)malloc((size_t)n * sizeof(long double));
+        long double *mine = partial + (size_t)t * (size_t)n;
+        for (int32_t i = lo; i < hi; ++i) {
+            int st = single_source_ld(n, row_ptr, col_idx, sources[i], dist, sigma, delta, mine,
+                                      order);
+            if (st > status) status = st;
+        }
+        free(dist);
+        free(order);
+        free(sigma);
+        free(delta);
+    }
+    for (int32_t v = 0; v < n; ++v) {
+        long double acc = 0.0L;
+        for (int t = 0; t < nt; ++t) acc = acc + partial[(size_t)t * (size_t)n + v];
+        bc[v] = (double)acc;
     }
     free(partial);
     return status;

@@ -73,11 +73,60 @@ def test_unmutated_copy_passes(swap_oracle):
     _pin_suite()
 
 
+# The extended-range (long double) copy of the algorithm sits after this
+# marker; the double oracle's mutants edit the text before it, the extended
+# ones the text after it.
+EXT_MARK = "/* ---- extended range"
+
+EXT_MUTANTS = {
+    "drop-one-plus": ("(1.0L + delta[w])", "(delta[w])"),
+    "transposed-ratio": ("(sigma[v] / sigma[w])", "(sigma[w] / sigma[v])"),
+    "forward-siblings": ("if (dist[w] == dist[v] - 1) acc = acc + sigma[w];",
+                         "if (dist[w] == dist[v]) acc = acc + sigma[w];"),
+    "backward-siblings-too": ("if (dist[w] == dist[v] + 1) acc",
+                              "if (dist[w] >= dist[v] && w != v) acc"),
+    "source-counts-itself": ("for (int32_t i = reached - 1; i >= 1; --i)",
+                             "for (int32_t i = reached - 1; i >= 0; --i)"),
+    "sigma-src-two": ("sigma[s] = 1.0L;", "sigma[s] = 2.0L;"),
+    "bc-overwrite": ("if (bc) bc[v] = bc[v] + delta[v];", "if (bc) bc[v] = delta[v];"),
+    "double-precision": ("long double acc = 0.0L;\n        for (int32_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {\n            int32_t w = col_idx[e];\n            if (dist[w] == dist[v] - 1)",
+                         "double acc = 0.0;\n        for (int32_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {\n            int32_t w = col_idx[e];\n            if (dist[w] == dist[v] - 1)"),
+}
+
+
+def _ext_pin_suite():
+    """The extended-range pins (quick ones) against the loaded library."""
+    pins.test_ext_diamond_chain_closed_form(1100, 2)
+    pins.test_ext_diamond_chain_closed_form(700, 3)
+    pins.test_ext_lattice_sigma_binomial()
+    pins.test_ext_matches_double_oracle_when_counts_fit()
+
+
+def _mutate(text, before, after, ext):
+    head, mark, tail = text.partition(EXT_MARK)
+    assert mark, "extended-range section not found"
+    part = tail if ext else head
+    assert part.count(before) == 1, f"mutation site {before!r} not unique"
+    part = part.replace(before, after)
+    return head + mark + part if ext else part + mark + tail
+
+
 @pytest.mark.parametrize("name", sorted(MUTANTS))
 def test_mutant_is_caught(name, swap_oracle):
     before, after = MUTANTS[name]
-    text = open(SRC).read()
-    assert text.count(before) == 1, f"mutation site for {name} not unique"
-    swap_oracle(text.replace(before, after))
+    swap_oracle(_mutate(open(SRC).read(), before, after, ext=False))
     with pytest.raises(AssertionError):
         _pin_suite()
+
+
+def test_unmutated_copy_passes_extended_pins(swap_oracle):
+    swap_oracle(open(SRC).read())
+    _ext_pin_suite()
+
+
+@pytest.mark.parametrize("name", sorted(EXT_MUTANTS))
+def test_extended_mutant_is_caught(name, swap_oracle):
+    before, after = EXT_MUTANTS[name]
+    swap_oracle(_mutate(open(SRC).read(), before, after, ext=True))
+    with pytest.raises(AssertionError):
+        _ext_pin_suite()

@@ -336,3 +336,107 @@ def test_edge_cases():
         oracle.bc(g.row_ptr, g.col_idx, np.array([5], np.int32))
     with pytest.raises(oracle.OracleError):
         oracle.single_source(g.row_ptr, g.col_idx, -1)
+
+
+# ---------------------------------------------------------------------------
+# Extended range (long double): counts beyond double's range
+# ---------------------------------------------------------------------------
+
+def as_fraction(m, e):
+    """Exact value m * 2**e of the extended oracle's (mantissa, exponent) pair.
+    The mantissa comes back rounded to double (53 bits) from the oracle's
+    64-bit long double, so comparisons allow 2**-53 for that rounding."""
+    from fractions import Fraction
+    return Fraction(float(m)) * (Fraction(2) ** int(e))
+
+
+def test_ext_oracle_computes_in_extended_precision():
+    assert oracle.long_double_digits() >= 64
+
+
+@pytest.mark.parametrize("k,width", [(1100, 2), (700, 3)])
+def test_ext_diamond_chain_closed_form(k, width):
+    """Chain of k diamonds of `width` middles, from hub 0: hub i has
+    sigma = width**i (past 2**1024 here) and dependency (width+1)*(k-i); a
+    middle vertex of diamond i carries 1/width of every path to hub i and
+    beyond, so delta = (1 + (width+1)*(k-i)) / width.  The double oracle
+    overflows on the same graph."""
+    from fractions import Fraction
+    g = gg.diamond_chain(k, width)
+    step = width + 1
+    dist, sm, se, delta, st = oracle.single_source_ext(g.row_ptr, g.col_idx, 0)
+    assert st == oracle.OK
+    _, _, _, st64 = oracle.single_source(g.row_ptr, g.col_idx, 0)
+    assert st64 == oracle.RANGE
+    for i in range(1, k + 1):
+        hub = i * step
+        assert dist[hub] == 2 * i
+        want = Fraction(width) ** i
+        got = as_fraction(sm[hub], se[hub])
+        assert abs(got - want) <= want * (Fraction(1, 2 ** 53) + Fraction(i, 2 ** 62))
+        assert delta[hub] == pytest.approx((width + 1) * (k - i), rel=1e-15, abs=0)
+        for j in range(1, width + 1):
+            mid = hub - step + j
+            assert dist[mid] == 2 * i - 1
+            want_m = Fraction(width) ** (i - 1)
+            assert (abs(as_fraction(sm[mid], se[mid]) - want_m)
+                    <= want_m * (Fraction(1, 2 ** 53) + Fraction(i, 2 ** 62)))
+            assert delta[mid] == pytest.approx((1 + (width + 1) * (k - i)) / width, rel=1e-15)
+    bc, st2 = oracle.bc_ext(g.row_ptr, g.col_idx, np.array([0], np.int32))
+    assert st2 == oracle.OK
+    want_bc = delta.copy()
+    want_bc[0] = 0.0
+    assert np.array_equal(bc, want_bc)
+
+
+def test_ext_lattice_sigma_binomial():
+    """From the corner of a 600x600 lattice sigma(r, c) = C(r+c, r), up to
+    C(1198, 599) ~ 2**1194: the extended oracle's counts against exact big
+    integers on a sample of vertices."""
+    from fractions import Fraction
+    rows = cols = 600
+    g = gg.grid_full(rows, cols)
+    dist, sm, se, _, st = oracle.single_source_ext(g.row_ptr, g.col_idx, 0, with_delta=False)
+    assert st == oracle.OK
+    rng = np.random.default_rng(3)
+    for v in list(rng.integers(0, g.n, 300)) + [g.n - 1, cols - 1, (rows - 1) * cols]:
+        r, c = divmod(int(v), cols)
+        assert dist[v] == r + c
+        want = Fraction(math.comb(r + c, r))
+        assert (abs(as_fraction(sm[v], se[v]) - want)
+                <= want * (Fraction(1, 2 ** 53) + Fraction(r + c + 1, 2 ** 62)))
+
+
+def test_ext_matches_double_oracle_when_counts_fit():
+    """Where every count fits double, the extended oracle gives the double
+    oracle's results (to rounding)."""
+    for g in (gg.rmat(11, 8, seed=21), gg.grid_road(40, 40, seed=22), gg.hypercube(8)):
+        src = gg.sample_sources(g, 50, seed=23)
+        a, st = oracle.bc(g.row_ptr, g.col_idx, src)
+        b, st2 = oracle.bc_ext(g.row_ptr, g.col_idx, src)
+        assert st == st2 == oracle.OK
+        nz = a != 0
+        assert np.array_equal(nz, b != 0)
+        assert np.max(np.abs(a[nz] - b[nz]) / a[nz]) < 1e-12
+        for s in src[:3]:
+            d0, s0, dl0, _ = oracle.single_source(g.row_ptr, g.col_idx, int(s))
+            d1, sm, se, dl1, _ = oracle.single_source_ext(g.row_ptr, g.col_idx, int(s))
+            assert np.array_equal(d0, d1)
+            assert np.array_equal(np.ldexp(sm, se), s0)  # integers below 2**53: exact
+            assert np.allclose(dl1, dl0, rtol=1e-13, atol=0)
+
+
+def test_ext_sum_invariant_deep_road_grid():
+    """Road-like 1024x1024 grid without shortcuts (~1,700 levels, counts past
+    double's range): sum_v BC(v) = sum over sources of sum_t (d(s,t) - 1)."""
+    g = gg.grid_road(1024, 1024, 0.05, 0.0, seed=2)
+    src = gg.sample_sources(g, 2, seed=102)
+    bc, st = oracle.bc_ext(g.row_ptr, g.col_idx, src)
+    assert st == oracle.OK
+    want = 0
+    for s in src:
+        d = hop_distances(g, int(s))
+        r = d[d > 0]
+        assert r.max() > 1000
+        want += int((r - 1).sum())
+    assert abs(bc.sum() - want) <= 1e-12 * want
