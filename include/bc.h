@@ -19,6 +19,16 @@
  * hop counts, -1 meaning "not reached" (the sentinel of the paper's generated
  * BFS kernel, Section "Code Generation", BFS traversal).
  *
+ * Extended range.  Path counts can pass double's range on deep graphs (a
+ * 600x600 lattice reaches C(1198, 599) ~ 2^1194).  When a run finds a count
+ * beyond DBL_MAX it runs again with level-scaled counts: each level's counts
+ * per source are kept times a power of two chosen from the level's largest
+ * count, which the reverse pass undoes exactly; the graph then stays in this
+ * mode (batched kernels, host-driven level loop) for every later call,
+ * whatever the options ask.  Scaling by powers of two is exact, so results
+ * keep double's rounding.  BC_ERR_RANGE remains for graphs whose counts span
+ * more than about 2^1000 within one level.
+ *
  * Graphs are undirected: a symmetric CSR (every arc u->v has a matching v->u)
  * with int32 offsets row_ptr[n+1] and int32 neighbours col_idx[row_ptr[n]], the
  * storage the paper uses on host and device (Section "Code Generation", graph
@@ -55,8 +65,8 @@ typedef enum {
     BC_ERR_INVALID_GRAPH = 2, /* row_ptr[0] != 0, row_ptr decreasing, col_idx out of range,
                                  or an arc without its reverse (unless trusted symmetric) */
     BC_ERR_OUT_OF_MEMORY = 3, /* device allocation failed */
-    BC_ERR_RANGE = 4,         /* some sigma became infinite (shortest-path counts beyond
-                                 DBL_MAX); outputs are written but meaningless */
+    BC_ERR_RANGE = 4,         /* shortest-path counts beyond even the extended range (see
+                                 above); outputs are written but meaningless */
     BC_ERR_DEVICE = 5,        /* a HIP runtime call failed */
     BC_ERR_UNSUPPORTED = 6    /* requested feature not available */
 } bc_status;
@@ -101,7 +111,7 @@ typedef struct bc_options {
  * or many batches.  AUTO picks the loop with the lower estimated time for the
  * call's batch count (a batch on one compute unit against a batch across the
  * device; e.g. DEVICE from about 6 batches at 53K arcs, 27 at 425K, 87 at
- * 1.8M). */
+ * 1.8M).  A graph in extended range always takes HOST. */
 enum {
     BC_LOOP_AUTO = 0,
     BC_LOOP_HOST = 1,
@@ -175,7 +185,9 @@ bc_status bc_run_multi(bc_graph_t g, const int32_t *sources, const int32_t *req_
                        int32_t nreq, double *const *bc_outs, void *stream);
 
 /*
- * One source, full per-vertex state (host outputs), for parity checks.
+ * One source, full per-vertex state (host outputs), for parity checks, from
+ * the one-source-at-a-time path in double (no extended range: counts beyond
+ * DBL_MAX give BC_ERR_RANGE, with dist still exact).
  *   dist   [n] host: hop distance from s, -1 if unreachable
  *   sigma  [n] host: number of shortest s-v paths (0 if unreachable)
  *   delta  [n] host or NULL: dependency of s on v (0 for s and unreachable v)
@@ -188,7 +200,8 @@ bc_status bc_single_source(bc_graph_t g, int32_t s, int32_t *dist, double *sigma
  * Batched-path detail for parity checks: BC as bc_run, plus, when not NULL,
  * per-source dist [k][n] (int32, host) and sigma [k][n] (double, host), as
  * produced by the batched kernels (opt->mode must be BC_MODE_BATCHED or
- * BC_MODE_PLAIN; NULL opt = batched).
+ * BC_MODE_PLAIN; NULL opt = batched).  In extended range sigma is the count
+ * rounded to double: +infinity where it passes DBL_MAX.
  */
 bc_status bc_run_detail(bc_graph_t g, const int32_t *sources, int32_t k, const bc_options *opt,
                         double *bc_out, int32_t *dist, double *sigma);

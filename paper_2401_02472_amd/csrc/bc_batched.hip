@@ -236,15 +236,26 @@ template <> struct SigRows<true> {
 template <> struct SigRows<false> {
     using T = double;
     __device__ static T *rows(const BatchDev &d) { return d.sigma; }
+    // a complete sum: at least 1 unscaled, at least 2^-1000 scaled (below
+    // that the extended range would lose precision), finite
     __device__ static void store(const BatchDev &d, size_t at, double acc) {
         d.sigma[at] = acc;
-        if (!isfinite(acc)) atomicOr(&d.ctrl[kCtlRange], 1);
+        if (!(acc >= 0x1p-1000 && acc <= 0x1.fffffffffffffp+1023))
+            atomicOr(&d.ctrl[kCtlRange], 1);
     }
 };
 
 template <bool N>
 __device__ __forceinline__ double sig_at(const BatchDev &d, size_t at) {
     return (double)SigRows<N>::rows(d)[at];
+}
+
+// Scale of level L for this lane: 1 unless the extended range is on.  Sums of
+// level-L rows are multiplied by it when stored (forward) or completed
+// (reverse); a power of two, so the product is exact.
+template <bool N>
+__device__ __forceinline__ double level_scale(const BatchDev &d, int32_t L) {
+    return (!N && d.xs) ? d.xs[(size_t)L * kWave + lane_id()] : 1.0;
 }
 
 // ---- forward ---------------------------------------------------------------
@@ -256,9 +267,17 @@ __device__ __forceinline__ double sig_at(const BatchDev &d, size_t at) {
 struct Front {
     uint32_t cnt = 0;
     unsigned long long arcs = 0;
+    double smax = 0.0;  // the lane's largest stored count (wide rows)
 };
 
-__device__ __forceinline__ void report_front(const BatchDev &d, int set, const Front &fr) {
+// Also records, in extended range, each lane's largest count stored for
+// level L+1 (one atomic max per lane and wave that stored any).
+template <bool N>
+__device__ __forceinline__ void report_front(const BatchDev &d, int set, int32_t L,
+                                             const Front &fr) {
+    if (!N && d.xmax && fr.smax > 0.0)
+        atomicMax(&d.xmax[(size_t)(L + 1) * kWave + lane_id()],
+                  (unsigned long long)__double_as_longlong(fr.smax));
     unsigned long long c = fr.cnt, a = fr.arcs;
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) {
@@ -273,10 +292,18 @@ __device__ __forceinline__ void report_front(const BatchDev &d, int set, const F
     }
 }
 
-// Chunk item of a vertex of degree > 64.
+// A complete count of level L+1 (already scaled): stored, and kept for the
+// lane's largest value.
 template <bool N>
-__device__ __forceinline__ void
-fwd_chunk(const BatchDev &d, int32_t L, uint32_t item, uint64_t full, Work &wk, Front &fr) {
+__device__ __forceinline__ void store_sigma(const BatchDev &d, size_t at, double acc, Front &fr) {
+    SigRows<N>::store(d, at, acc);
+    if (!N) fr.smax = fmax(fr.smax, acc);
+}
+
+// Chunk item of a vertex of degree > 64 (xsc: the lane's scale of level L).
+template <bool N>
+__device__ __forceinline__ void fwd_chunk(const BatchDev &d, int32_t L, uint32_t item,
+                                          uint64_t full, double xsc, Work &wk, Front &fr) {
     const int lane = lane_id();
     const int2 info = d.item_info[item];
     const int32_t w = info.x, j = info.y;
@@ -297,7 +324,7 @@ fwd_chunk(const BatchDev &d, int32_t L, uint32_t item, uint64_t full, Work &wk, 
     const bool mine = (nw >> lane) & 1ull;
     if (mine && (!multi || j == 0)) ++wk.owners;
     if (!multi) {
-        if (mine) SigRows<N>::store(d, (size_t)w * kWave + lane, acc);
+        if (mine) store_sigma<N>(d, (size_t)w * kWave + lane, acc * xsc, fr);
         if (lane == 0) {
             FN[w] = nw;
             if (nw) {
@@ -319,7 +346,7 @@ fwd_chunk(const BatchDev &d, int32_t L, uint32_t item, uint64_t full, Work &wk, 
 template <bool N>
 __device__ __forceinline__ void
 fwd_group(const BatchDev &d, int32_t L, int32_t base, const int32_t *list, int32_t count,
-          uint64_t full, Work &wk, Front &fr) {
+          uint64_t full, double xsc, Work &wk, Front &fr) {
     const int lane = lane_id();
     const uint64_t *FL = d.F + (size_t)L * (size_t)d.n;
     uint64_t *FN = d.F + (size_t)(L + 1) * (size_t)d.n;
@@ -350,7 +377,7 @@ fwd_group(const BatchDev &d, int32_t L, int32_t base, const int32_t *list, int32
             const uint64_t w_vis = ~shfl64(unvis, cur) & full;
             const int32_t w_deg = __shfl(cnt, cur);
             if ((nw >> lane) & 1ull) {
-                SigRows<N>::store(d, (size_t)w * kWave + lane, acc);
+                store_sigma<N>(d, (size_t)w * kWave + lane, acc * xsc, fr);
                 ++wk.owners;
             }
             if (lane == 0) {
@@ -420,22 +447,23 @@ __global__ __launch_bounds__(kBlock) void k_batch_forward(BatchDev d, int32_t L,
     const uint32_t groups = (uint32_t)((d.n - d.big_end + kWave - 1) / kWave);
     const uint32_t wave = (blockIdx.x * kBlock + threadIdx.x) / kWave;
     const uint32_t nwaves = gridDim.x * kWavesPerBlock;
+    const double xsc = level_scale<N>(d, L);
     Work wk;
     Front fr;
     for (uint32_t it = wave; it < items + groups; it += nwaves) {
-        if (it < items) fwd_chunk<N>(d, L, it, full, wk, fr);
-        else fwd_group<N>(d, L, d.big_end + (int32_t)(it - items) * kWave, nullptr, 0, full, wk,
-                          fr);
+        if (it < items) fwd_chunk<N>(d, L, it, full, xsc, wk, fr);
+        else fwd_group<N>(d, L, d.big_end + (int32_t)(it - items) * kWave, nullptr, 0, full, xsc,
+                          wk, fr);
     }
-    report_front(d, 0, fr);
+    report_front<N>(d, 0, L, fr);
     if (d.stats) report_work(d.stats, wk);
 }
 
 // After a forward iteration: completes the split vertices (their summed
 // counts, F_{L+1}, vis) and counts them into the new frontier.
 template <bool N>
-__device__ __forceinline__ void
-finish_split(const BatchDev &d, int32_t L, int32_t wave, int32_t nwaves, Front &fr) {
+__device__ __forceinline__ void finish_split(const BatchDev &d, int32_t L, int32_t wave,
+                                             int32_t nwaves, double xsc, Front &fr) {
     uint64_t *FN = d.F + (size_t)(L + 1) * (size_t)d.n;
     const int lane = lane_id();
     for (int32_t w = wave; w < d.multi_end; w += nwaves) {
@@ -444,7 +472,7 @@ finish_split(const BatchDev &d, int32_t L, int32_t wave, int32_t nwaves, Front &
         if (nw == 0ull) continue;
         if ((nw >> lane) & 1ull) {
             const size_t at = (size_t)w * kWave + lane;
-            SigRows<N>::store(d, at, d.hubsig[at]);
+            store_sigma<N>(d, at, d.hubsig[at] * xsc, fr);
         }
         if (lane == 0) {
             d.vis[w] |= nw;
@@ -461,8 +489,8 @@ __global__ __launch_bounds__(kBlock) void k_batch_forward_finish(BatchDev d, int
     if (L > d.ctrl[kCtlDeepest] || L + 1 >= d.lcap) return;
     Front fr;
     finish_split<N>(d, L, (blockIdx.x * kBlock + threadIdx.x) / kWave,
-                    gridDim.x * kWavesPerBlock, fr);
-    report_front(d, 2, fr);
+                    gridDim.x * kWavesPerBlock, level_scale<N>(d, L), fr);
+    report_front<N>(d, 2, L, fr);
     (void)full;
 }
 
@@ -500,6 +528,15 @@ __global__ __launch_bounds__(kDoneBlock) void k_batch_level_done(BatchDev d, int
             sa[t] += sa[t + h];
         }
         __syncthreads();
+    }
+    // extended range: level L+1's scale from its largest stored counts (k = 0
+    // below 2^512, so ordinary counts are never rescaled), and its exponent
+    if (live && d.xs && t < kWave) {
+        const size_t at = (size_t)(L + 1) * kWave + t;
+        const double m = __longlong_as_double((long long)d.xmax[at]);
+        const int k = m >= 0x1p512 ? ilogb(m) : 0;
+        d.xs[at] = ldexp(1.0, -k);
+        d.xe[at] = d.xe[at - kWave] - ilogb(d.xs[at - kWave]);
     }
     if (t == 0) {
         if (live && sc[0] != 0) {
@@ -659,13 +696,14 @@ __global__ __launch_bounds__(kBlock) void k_batch_sparse_pull(BatchDev d, int32_
     const int32_t groups = (c + kWave - 1) / kWave;
     const int32_t wave = (blockIdx.x * kBlock + threadIdx.x) / kWave;
     const int32_t nwaves = gridDim.x * kWavesPerBlock;
+    const double xsc = level_scale<N>(d, L);
     Work wk;
     Front fr;
     for (int32_t it = wave; it < ni + groups; it += nwaves) {
-        if (it < ni) fwd_chunk<N>(d, L, (uint32_t)d.ilist[it], full, wk, fr);
-        else fwd_group<N>(d, L, (it - ni) * kWave, d.clist, c, full, wk, fr);
+        if (it < ni) fwd_chunk<N>(d, L, (uint32_t)d.ilist[it], full, xsc, wk, fr);
+        else fwd_group<N>(d, L, (it - ni) * kWave, d.clist, c, full, xsc, wk, fr);
     }
-    report_front(d, 1, fr);
+    report_front<N>(d, 1, L, fr);
     if (d.stats) report_work(d.stats, wk);
 }
 
@@ -687,26 +725,34 @@ __device__ __forceinline__ void add_segments(const BatchDev &d, int32_t v, doubl
     }
 }
 
-// Complete (v, lanes mv) at level L from its children sums acc and its sigma
-// (lane s meaningful for s in mv): delta = sigma * acc, c = (1 + delta) /
-// sigma, and the lanes' deltas added to BC[v] (or to the requests' outputs).
-// Called with every lane active.
-// As settle, but BC[v]'s share is returned (the lanes' delta sum, the same
-// in every lane) for the caller to add later; segments are added at once.
+// Complete (v, lanes mv) at level L from its children sums acc (already
+// times the level's scale) and its sigma (lane s meaningful for s in mv):
+// delta = sigma * acc, c = (1 + delta) / sigma, and the lanes' deltas added
+// to BC[v] (or to the requests' outputs).  Called with every lane active.
+// This form returns BC[v]'s share (the lanes' delta sum, the same in every
+// lane) for the caller to add later; segments are added at once.  With wide
+// rows a c beyond double's range (possible only with scaled counts) raises
+// the range flag.
+template <bool N>
 __device__ __forceinline__ double settle_deferred(const BatchDev &d, int32_t v, uint64_t mv,
                                                   double sig, double acc) {
     const int lane = lane_id();
     const bool on = (mv >> lane) & 1ull;
     const double delta = on ? sig * acc : 0.0;
-    if (on) d.coef[(size_t)v * kWave + lane] = (1.0 + delta) / sig;
+    if (on) {
+        const double c = (1.0 + delta) / sig;
+        d.coef[(size_t)v * kWave + lane] = c;
+        if (!N && !(c <= 0x1.fffffffffffffp+1023)) atomicOr(&d.ctrl[kCtlRange], 1);
+    }
     if (d.nseg == 0) return wave_sum(delta);
     add_segments(d, v, delta);
     return 0.0;
 }
 
+template <bool N>
 __device__ __forceinline__ void settle(const BatchDev &d, int32_t v, uint64_t mv, double sig,
                                        double acc) {
-    const double tot = settle_deferred(d, v, mv, sig, acc);
+    const double tot = settle_deferred<N>(d, v, mv, sig, acc);
     if (lane_id() == 0 && tot != 0.0) d.bc[v] += tot;
 }
 
@@ -714,7 +760,8 @@ __device__ __forceinline__ void settle(const BatchDev &d, int32_t v, uint64_t mv
 // with one chunk is completed here, a split vertex leaves the item's partial
 // row for the finalising pass.
 template <bool N>
-__device__ __forceinline__ void bwd_chunk(const BatchDev &d, int32_t L, uint32_t item, Work &wk) {
+__device__ __forceinline__ void bwd_chunk(const BatchDev &d, int32_t L, uint32_t item,
+                                          double xsc, Work &wk) {
     const int lane = lane_id();
     const int2 info = d.item_info[item];
     const int32_t v = info.x, j = info.y;
@@ -729,11 +776,12 @@ __device__ __forceinline__ void bwd_chunk(const BatchDev &d, int32_t L, uint32_t
     (void)probe_chunk(d, cb, min(re, cb + kChunk), FC, mv, d.coef, acc, wk);
     if (on && j == 0) ++wk.owners;
     if (v < d.multi_end) d.partial[(size_t)item * kWave + lane] = acc;
-    else settle(d, v, mv, sig, acc);
+    else settle<N>(d, v, mv, sig, acc * xsc);
 }
 
 template <bool N>
-__device__ __forceinline__ void bwd_group(const BatchDev &d, int32_t L, int32_t base, Work &wk) {
+__device__ __forceinline__ void bwd_group(const BatchDev &d, int32_t L, int32_t base, double xsc,
+                                          Work &wk) {
     const int lane = lane_id();
     const uint64_t *FL = d.F + (size_t)L * (size_t)d.n;
     const uint64_t *FC = d.F + (size_t)(L + 1) * (size_t)d.n;
@@ -760,7 +808,7 @@ __device__ __forceinline__ void bwd_group(const BatchDev &d, int32_t L, int32_t 
     double my_bc = 0.0;
     auto flush = [&]() {
         if (cur < 0) return;
-        const double tot = settle_deferred(d, base + cur, shfl64(mv, cur), cur_sig, acc);
+        const double tot = settle_deferred<N>(d, base + cur, shfl64(mv, cur), cur_sig, acc * xsc);
         if (lane == cur) my_bc = tot;  // all lanes active here
     };
     for (uint32_t c0 = 0; c0 < total; c0 += kWave * kRounds) {
@@ -840,10 +888,11 @@ __global__ __launch_bounds__(kBlock) void k_batch_reverse(BatchDev d, int32_t L)
     const uint32_t groups = (uint32_t)((d.n - d.big_end + kWave - 1) / kWave);
     const uint32_t wave = (blockIdx.x * kBlock + threadIdx.x) / kWave;
     const uint32_t nwaves = gridDim.x * kWavesPerBlock;
+    const double xsc = level_scale<N>(d, L);
     Work wk;
     for (uint32_t it = wave; it < items + groups; it += nwaves) {
-        if (it < items) bwd_chunk<N>(d, L, it, wk);
-        else bwd_group<N>(d, L, d.big_end + (int32_t)(it - items) * kWave, wk);
+        if (it < items) bwd_chunk<N>(d, L, it, xsc, wk);
+        else bwd_group<N>(d, L, d.big_end + (int32_t)(it - items) * kWave, xsc, wk);
     }
     if (d.stats) report_work(d.stats + 6, wk);
 }
@@ -877,7 +926,7 @@ finalize_level(const BatchDev &d, int32_t L, int32_t leaf, int32_t wave, int32_t
                 for (int q = 0; q < 8; ++q) t += x[q];
             }
             for (; i < i1; ++i) t += d.partial[(size_t)i * kWave + lane];
-            settle(d, v, mv, sig, t);
+            settle<N>(d, v, mv, sig, t * level_scale<N>(d, L));
         }
         return;
     }
@@ -959,7 +1008,8 @@ __global__ __launch_bounds__(kBlock) void k_batch_finalize(BatchDev d, int32_t L
 // (with the steps as out-of-line calls, this kernel's dependency sums came
 // out wrong on gfx950, varying from run to run, while the level masks and
 // path counts stayed exact).  ctrl of the batch receives the depth and the flags
-// (truncation: the host runs the call again with a longer level array).
+// (truncation: the host runs the call again with a longer level array).  No
+// extended range here: the host runs graphs that need it on its own loop.
 constexpr int kFusedBlock = 1024;
 constexpr int kFusedWaves = kFusedBlock / kWave;
 
@@ -1007,12 +1057,12 @@ __global__ __launch_bounds__(kFusedBlock) void k_batch_fused(const BatchDev *dev
         if (t == 0) s_found = 0;
         Front fr;
         for (uint32_t it = wave; it < items + groups; it += kFusedWaves) {
-            if (it < items) fwd_chunk<N>(d, L, it, full, wkf, fr);
+            if (it < items) fwd_chunk<N>(d, L, it, full, 1.0, wkf, fr);
             else fwd_group<N>(d, L, d.big_end + (int32_t)(it - items) * kWave, nullptr, 0, full,
-                              wkf, fr);
+                              1.0, wkf, fr);
         }
         __syncthreads();
-        finish_split<N>(d, L, wave, kFusedWaves, fr);
+        finish_split<N>(d, L, wave, kFusedWaves, 1.0, fr);
         uint32_t c = fr.cnt;
 #pragma unroll
         for (int off = 32; off >= 1; off >>= 1) c += __shfl_xor(c, off);
@@ -1032,8 +1082,8 @@ __global__ __launch_bounds__(kFusedBlock) void k_batch_fused(const BatchDev *dev
     for (int32_t L = deepest; L >= 1; --L) {
         if (L != deepest) {
             for (uint32_t it = wave; it < items + groups; it += kFusedWaves) {
-                if (it < items) bwd_chunk<N>(d, L, it, wkr);
-                else bwd_group<N>(d, L, d.big_end + (int32_t)(it - items) * kWave, wkr);
+                if (it < items) bwd_chunk<N>(d, L, it, 1.0, wkr);
+                else bwd_group<N>(d, L, d.big_end + (int32_t)(it - items) * kWave, 1.0, wkr);
             }
             __syncthreads();
         }
@@ -1064,7 +1114,16 @@ __global__ void k_batch_clear(BatchDev d) {
         reinterpret_cast<uint4 *>(d.cand)[i] = make_uint4(0u, 0u, 0u, 0u);
     const int64_t rows = (int64_t)d.multi_end * kWave;
     for (int64_t i = tid; i < rows; i += stride) d.hubsig[i] = 0.0;
-    if (blockIdx.x == 0 && threadIdx.x < kCtlInts) d.ctrl[threadIdx.x] = 0;
+    // the range flag stays set over the run's batches (the host clears it)
+    if (blockIdx.x == 0 && threadIdx.x < kCtlInts && threadIdx.x != kCtlRange)
+        d.ctrl[threadIdx.x] = 0;
+    if (d.xmax) {  // extended range: no maxima yet, level 0 (the sources) unscaled
+        for (int64_t i = tid; i < (int64_t)d.lcap * kWave; i += stride) d.xmax[i] = 0ull;
+        if (tid < kWave) {
+            d.xs[tid] = 1.0;
+            d.xe[tid] = 0;
+        }
+    }
 }
 
 // Seed lane s with its source; the first iteration's step is chosen from the
@@ -1106,8 +1165,13 @@ __global__ void k_batch_export(BatchDev d, int32_t deepest, int32_t nlanes, int3
                     }
             }
             if (dist) dist[(size_t)s * d.n + v] = lev;
-            if (sigma)
-                sigma[(size_t)s * d.n + v] = lev >= 0 ? sig_at<N>(d, (size_t)v * kWave + s) : 0.0;
+            if (sigma) {
+                // extended range: the stored value times 2^xe (infinite past
+                // double's range)
+                double x = lev >= 0 ? sig_at<N>(d, (size_t)v * kWave + s) : 0.0;
+                if (lev >= 0 && d.xe) x = ldexp(x, d.xe[(size_t)lev * kWave + s]);
+                sigma[(size_t)s * d.n + v] = x;
+            }
         }
     }
 }

@@ -95,7 +95,10 @@ struct BatchWS {
     unsigned long long *d_stats = nullptr;  // 12 counters (see BatchDev::stats)
     void *block = nullptr;     // vis, sigma, coef, ctrl, bc
     size_t bytes = 0;
-    uint64_t *F = nullptr;     // [lcap][n]
+    uint64_t *F = nullptr;     // [lcap][n], then the extended-range tables
+    double *xs = nullptr;
+    unsigned long long *xmax = nullptr;
+    int32_t *xe = nullptr;
     int32_t lcap = 0;
     int32_t *d_src = nullptr;  // internal source ids of the run
     size_t src_cap = 0;
@@ -152,6 +155,9 @@ struct bc_graph_s {
     // set once a path count did not fit the batched path's uint32 sigma rows:
     // later batches start with double rows
     std::atomic<bool> sigma_wide{false};
+    // set once a path count overflowed double: later batches keep level-scaled
+    // counts (extended range, host-driven loop only)
+    std::atomic<bool> sigma_ext{false};
     // internal streams for batches run at once (created on first use)
     std::mutex stream_mu;
     std::vector<hipStream_t> streams;
@@ -543,8 +549,10 @@ size_t batch_ws_bytes(const bc_graph_s *g) {
     return b;
 }
 
+// F[lcap][n] and the extended-range tables xs, xmax, xe ([lcap][64] each).
 size_t batch_level_bytes(const bc_graph_s *g, int32_t lcap) {
-    return (size_t)lcap * (size_t)std::max<int32_t>(g->n, 1) * sizeof(uint64_t);
+    return (size_t)lcap * ((size_t)std::max<int32_t>(g->n, 1) * sizeof(uint64_t) +
+                           kWave * (sizeof(double) + sizeof(unsigned long long) + sizeof(int32_t)));
 }
 
 void batch_ws_destroy(BatchWS *ws) {
@@ -624,6 +632,9 @@ bc_status batch_grow_levels(bc_graph_s *g, BatchWS *ws, int32_t lcap) {
     ws->lcap = lcap;
     ws->dev.F = ws->F;
     ws->dev.lcap = lcap;
+    ws->xs = (double *)(ws->F + (size_t)lcap * (size_t)std::max<int32_t>(g->n, 1));
+    ws->xmax = (unsigned long long *)(ws->xs + (size_t)lcap * kWave);
+    ws->xe = (int32_t *)(ws->xmax + (size_t)lcap * kWave);
     return BC_OK;
 }
 
@@ -779,6 +790,8 @@ bc_status run_batch_plan(bc_graph_s *g, const std::vector<int32_t> &s_int,
                            hipMemcpyHostToDevice, stream);
     if (e == hipSuccess && bc_out)
         e = hipMemsetAsync(ws->dev.bc, 0, (size_t)n * sizeof(double), stream);
+    if (e == hipSuccess)  // the batches' kernels only ever set the range flag
+        e = hipMemsetAsync(ws->dev.ctrl + kCtlRange, 0, sizeof(int32_t), stream);
     if (e != hipSuccess) return fail(from_hip(e));
     int32_t range = 0, run_depth = 0;
     for (size_t bi = 0; bi < plan.size();) {
@@ -790,7 +803,11 @@ bc_status run_batch_plan(bc_graph_s *g, const std::vector<int32_t> &s_int,
         d.seg_start = bp.nseg ? d_seg_start + bp.seg_first : nullptr;
         d.seg_out = bp.nseg ? d_seg_out + (bp.seg_first - (int32_t)bi) : nullptr;
         d.iperm = g->d_iperm;
-        d.narrow = g->sigma_wide.load() ? 0 : 1;
+        const bool ext = g->sigma_ext.load();
+        d.narrow = (ext || g->sigma_wide.load()) ? 0 : 1;
+        d.xs = ext ? ws->xs : nullptr;
+        d.xmax = ext ? ws->xmax : nullptr;
+        d.xe = ext ? ws->xe : nullptr;
         e = batch_start(d, d_lanes + bp.first, nl, stream);
         if (e != hipSuccess) return fail(from_hip(e));
         int32_t deepest = 0;
@@ -815,6 +832,14 @@ bc_status run_batch_plan(bc_graph_s *g, const std::vector<int32_t> &s_int,
             deepest = ws->h_ctrl[0];
             if (ws->h_ctrl[kCtlNarrow]) {  // a path count needs double rows: run again
                 g->sigma_wide.store(true);
+                restart = true;
+                break;
+            }
+            if (ws->h_ctrl[kCtlRange] && !ext) {  // beyond double: run again level-scaled
+                g->sigma_wide.store(true);
+                g->sigma_ext.store(true);
+                e = hipMemsetAsync(d.ctrl + kCtlRange, 0, sizeof(int32_t), stream);
+                if (e != hipSuccess) return fail(from_hip(e));
                 restart = true;
                 break;
             }
@@ -1069,15 +1094,21 @@ bc_status fused_run(bc_graph_s *g, const std::vector<int32_t> &s_int,
                                hipMemcpyDeviceToHost, stream);
         if (e == hipSuccess) e = hipStreamSynchronize(stream);
         if (e != hipSuccess) break;
-        bool trunc = false, wide = false;
+        bool trunc = false, wide = false, over = false;
         for (int32_t i = 0; i < m; ++i) {
             const int32_t *c = f.h_ctrl + (size_t)i * kCtlInts;
             trunc |= c[kCtlTrunc] != 0;
             wide |= c[kCtlNarrow] != 0;
+            over |= c[kCtlRange] != 0;
         }
         if (wide) {  // a path count needs double rows: run these batches again
             g->sigma_wide.store(true);
             continue;
+        }
+        if (over) {  // beyond double: the caller runs the call again level-scaled
+            g->sigma_ext.store(true);
+            timer.destroy();
+            return BC_ERR_RANGE;
         }
         if (trunc) {  // a batch ran deeper than the level array: grow it, run again
             const int32_t l2 = f.lcap * 2;
@@ -1131,6 +1162,7 @@ bc_status fused_run(bc_graph_s *g, const std::vector<int32_t> &s_int,
 // concurrent parts, 0.8 ms + 0.15 ns per arc on the host loop.  AUTO picks
 // the loop with the lower estimate for the call's batch count.
 bool use_fused(const bc_graph_s *g, int32_t level_loop, int32_t nbatches) {
+    if (g->sigma_ext.load()) return false;  // extended range: host loop only
     if (level_loop == BC_LOOP_DEVICE) return true;
     if (level_loop == BC_LOOP_HOST) return false;
     const double arcs = (double)g->nnz;
@@ -1191,8 +1223,12 @@ bc_status batched_run(bc_graph_s *g, const int32_t *sources, int32_t k, double *
     for (int32_t i = 0; i < k; ++i) s_int[(size_t)i] = g->h_perm[(size_t)sources[order[(size_t)i]]];
     std::vector<BatchPlan> plan;
     for (int32_t b0 = 0; b0 < k; b0 += width) plan.push_back({b0, std::min(width, k - b0), 0, 0});
-    if (use_fused(g, level_loop, (int32_t)plan.size()))
-        return fused_run(g, s_int, plan, {}, {}, bc_out, stream, order.data(), dist, sigma);
+    if (use_fused(g, level_loop, (int32_t)plan.size())) {
+        // a count beyond double's range sends the call to the host loop
+        const bc_status st =
+            fused_run(g, s_int, plan, {}, {}, bc_out, stream, order.data(), dist, sigma);
+        if (st != BC_ERR_RANGE || !g->sigma_ext.load()) return st;
+    }
     const int32_t P = parts_of(g, concurrency, (int32_t)plan.size());
     if (P <= 1)
         return run_batch_plan(g, s_int, plan, {}, {}, bc_out, stream, order.data(), dist, sigma,
@@ -1310,16 +1346,31 @@ bc_status multi_run(bc_graph_s *g, const int32_t *sources, const int32_t *req_st
     // request spans two batches (no two workgroups add to one output)
     bool spans = false;
     for (int32_t r = 0; r < nreq; ++r) spans |= req_start[r + 1] - req_start[r] > kWave;
-    if (!spans && use_fused(g, BC_LOOP_AUTO, (int32_t)plan.size()))
-        return fused_run(g, s_int, plan, seg_start, seg_out, nullptr, stream, nullptr, nullptr,
-                         nullptr);
+    if (!spans && use_fused(g, BC_LOOP_AUTO, (int32_t)plan.size())) {
+        const bc_status st = fused_run(g, s_int, plan, seg_start, seg_out, nullptr, stream,
+                                       nullptr, nullptr, nullptr);
+        if (st != BC_ERR_RANGE || !g->sigma_ext.load()) return st;
+        // beyond double's range: outputs cleared and the call run again level-scaled
+        for (int32_t r = 0; r < nreq; ++r) {
+            hipError_t e = hipMemsetAsync(outs[r], 0, (size_t)g->n * sizeof(double), stream);
+            if (e != hipSuccess) return from_hip(e);
+        }
+    }
     return run_batch_plan(g, s_int, plan, seg_start, seg_out, nullptr, stream, nullptr, nullptr,
                           nullptr, g->tuned_sparse_div.load());
 }
 
 // Mode selection: BC_MODE_AUTO picks the batched path from the graph's
 // crossover source count on (16 until bc_autotune measures it).
+// A plain run whose counts overflowed double: the graph switches to the
+// batched path's extended range for this and every later call.
+void plain_overflowed(bc_graph_s *g) {
+    g->sigma_wide.store(true);
+    g->sigma_ext.store(true);
+}
+
 bool use_batched(const bc_graph_s *g, const bc_options *opt, int32_t k) {
+    if (g->sigma_ext.load()) return true;  // only the batched path has the extended range
     const int32_t mode = opt ? opt->mode : BC_MODE_AUTO;
     if (mode == BC_MODE_BATCHED) return true;
     if (mode == BC_MODE_PLAIN) return false;
@@ -1398,7 +1449,7 @@ const char *bc_status_str(bc_status s) {
         case BC_ERR_INVALID_ARG: return "invalid argument";
         case BC_ERR_INVALID_GRAPH: return "invalid graph";
         case BC_ERR_OUT_OF_MEMORY: return "out of device memory";
-        case BC_ERR_RANGE: return "shortest-path count out of double range";
+        case BC_ERR_RANGE: return "shortest-path counts out of the representable range";
         case BC_ERR_DEVICE: return "HIP runtime error";
         case BC_ERR_UNSUPPORTED: return "unsupported";
     }
@@ -1581,11 +1632,14 @@ bc_status bc_run_async(bc_graph_t g, const int32_t *sources, int32_t k, double *
     if (st != BC_OK) return st;
     if (g->n == 0) return BC_OK;
     DeviceGuard dg(g->device);
-    if (use_batched(g, opt, k))
-        return batched_run(g, sources, k, bc_out_dev, batch_width_of(g, opt),
-                           sparse_div_of(g, opt), opt ? opt->concurrency : 0,
-                           opt ? opt->level_loop : 0, (hipStream_t)stream, nullptr, nullptr);
-    return plain_run(g, sources, k, bc_out_dev, opt, (hipStream_t)stream, nullptr, nullptr);
+    if (!use_batched(g, opt, k)) {
+        st = plain_run(g, sources, k, bc_out_dev, opt, (hipStream_t)stream, nullptr, nullptr);
+        if (st != BC_ERR_RANGE) return st;
+        plain_overflowed(g);
+    }
+    return batched_run(g, sources, k, bc_out_dev, batch_width_of(g, opt), sparse_div_of(g, opt),
+                       opt ? opt->concurrency : 0, opt ? opt->level_loop : 0,
+                       (hipStream_t)stream, nullptr, nullptr);
 }
 
 bc_status bc_run(bc_graph_t g, const int32_t *sources, int32_t k, double *bc_out) {
@@ -1596,10 +1650,14 @@ bc_status bc_run(bc_graph_t g, const int32_t *sources, int32_t k, double *bc_out
     DeviceGuard dg(g->device);
     double *d_bc = nullptr;
     BC_TRY_HIP(hipMalloc(&d_bc, (size_t)g->n * sizeof(double)));
-    st = use_batched(g, nullptr, k)
-             ? batched_run(g, sources, k, d_bc, batch_width_of(g, nullptr),
-                           sparse_div_of(g, nullptr), 0, 0, nullptr, nullptr, nullptr)
-             : plain_run(g, sources, k, d_bc, nullptr, nullptr, nullptr, nullptr);
+    st = BC_ERR_RANGE;
+    if (!use_batched(g, nullptr, k)) {
+        st = plain_run(g, sources, k, d_bc, nullptr, nullptr, nullptr, nullptr);
+        if (st == BC_ERR_RANGE) plain_overflowed(g);
+    }
+    if (st == BC_ERR_RANGE)
+        st = batched_run(g, sources, k, d_bc, batch_width_of(g, nullptr), sparse_div_of(g, nullptr),
+                         0, 0, nullptr, nullptr, nullptr);
     if (st == BC_OK || st == BC_ERR_RANGE) {
         hipError_t e = hipMemcpy(bc_out, d_bc, (size_t)g->n * sizeof(double),
                                  hipMemcpyDeviceToHost);
@@ -1636,7 +1694,7 @@ bc_status bc_run_detail(bc_graph_t g, const int32_t *sources, int32_t k, const b
         exp[i].dist = d_dist ? d_dist + (size_t)i * n : nullptr;
         exp[i].sigma = d_sigma ? d_sigma + (size_t)i * n : nullptr;
     }
-    const bool batched = !opt || opt->mode != BC_MODE_PLAIN;
+    const bool batched = !opt || opt->mode != BC_MODE_PLAIN || g->sigma_ext.load();
     ExportAlloc tmp;
     if (!batched && (dist || sigma) && (e = tmp.alloc(n)) != hipSuccess) {
         (void)hipFree(d_bc);
@@ -1644,13 +1702,16 @@ bc_status bc_run_detail(bc_graph_t g, const int32_t *sources, int32_t k, const b
         (void)hipFree(d_sigma);
         return from_hip(e);
     }
-    if (batched)
+    st = BC_ERR_RANGE;
+    if (!batched) {
+        st = plain_run(g, sources, k, d_bc, opt, nullptr, (dist || sigma) ? exp.data() : nullptr,
+                       &tmp.t);
+        if (st == BC_ERR_RANGE) plain_overflowed(g);
+    }
+    if (st == BC_ERR_RANGE)
         st = batched_run(g, sources, k, d_bc, batch_width_of(g, opt), sparse_div_of(g, opt),
                          opt ? opt->concurrency : 0, opt ? opt->level_loop : 0, nullptr, d_dist,
                          d_sigma);
-    else
-        st = plain_run(g, sources, k, d_bc, opt, nullptr, (dist || sigma) ? exp.data() : nullptr,
-                       &tmp.t);
     if (st == BC_OK || st == BC_ERR_RANGE) {
         e = hipMemcpy(bc_out, d_bc, n * sizeof(double), hipMemcpyDeviceToHost);
         if (e == hipSuccess && dist)

@@ -125,12 +125,20 @@ struct BatchDev {
     const int32_t *seg_start;
     double *const *seg_out;
     const int32_t *iperm;  // internal id -> caller id
+    // Extended range (wide rows only; all three NULL otherwise).  Level L's
+    // rows hold sigma * 2^-xe[L][s] for lane s; level L+1's counts are summed
+    // from them and stored times xs[L][s] = 2^-k, k chosen from the largest
+    // stored value of level L (xmax[L][s], the bits of a positive double) so
+    // that counts of any size stay inside double's range.
+    double *xs;                 // [lcap][64]
+    int32_t *xe;                // [lcap][64]
+    unsigned long long *xmax;   // [lcap][64]
 };
 
 // BatchDev::ctrl layout (int32 words).
 enum {
     kCtlDeepest = 0,   // deepest level found
-    kCtlRange = 1,     // some sigma not finite
+    kCtlRange = 1,     // some sigma (or scaled coefficient) out of range
     kCtlTrunc = 2,     // level array full: run the batch again with more room
     kCtlMode = 3,      // 1: the running iteration takes the sparse forward step
     kCtlCand = 4,      // candidates listed by the sparse step

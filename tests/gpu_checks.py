@@ -1,6 +1,6 @@
 """Compare helpers shared by the GPU parity tests.
 
-Compare rules (spec tolerances): dist equal everywhere; sigma bitwise
+Compare rules (the target tolerances): dist equal everywhere; sigma bitwise
 equal where the oracle's sigma < 2**53, else within 1e-12 relative (sums of
 more than 2**53 are rounded, and the GPU adds parents in another order); BC
 within 1e-9 relative (every dependency term is >= 0, so there is no
@@ -54,3 +54,21 @@ def oracle_bc(g, sources):
     want, st = oracle.bc(g.row_ptr, g.col_idx, np.asarray(sources, np.int32))
     assert st == oracle.OK
     return want
+
+
+def oracle_bc_ext(g, sources):
+    """The extended-range (long double) oracle's BC."""
+    want, st = oracle.bc_ext(g.row_ptr, g.col_idx, np.asarray(sources, np.int32))
+    assert st == oracle.OK
+    return want
+
+
+def check_sigma_ext(got, sig_m, sig_e):
+    """Exported sigma (double: infinite past double's range) against the
+    extended oracle's sig_m * 2**sig_e: equal below 2**53, 1e-12 relative up to
+    double's largest value, infinite beyond it."""
+    with np.errstate(over="ignore"):
+        want = np.ldexp(sig_m, sig_e)
+    fits = np.isfinite(want)
+    assert np.all(np.isposinf(got[~fits]))
+    check_sigma(got[fits], want[fits])

@@ -7,7 +7,8 @@ import pytest
 import graphgen as gg
 import oracle
 import paper_2401_02472_amd as bcm
-from tests.gpu_checks import batched, check_bc, check_sigma, oracle_bc, plain, run_mode
+from tests.gpu_checks import (batched, check_bc, check_sigma, check_sigma_ext, oracle_bc,
+                              oracle_bc_ext, plain, run_mode)
 
 pytestmark = pytest.mark.gpu
 
@@ -124,12 +125,59 @@ def test_multigraph_and_self_loops():
         check_bc(batched(G, src), oracle_bc(g, src))
 
 
-def test_sigma_overflow_reports_range():
+def test_sigma_overflow_extended_range():
+    """Counts past double's range (600x600 lattice: up to C(1198, 599) ~ 2**1194
+    from a corner): the batched path switches to level-scaled counts.  BC within
+    1e-9 of the extended oracle, distances equal, exported sigma as in
+    check_sigma_ext; the graph stays in extended range for the next call."""
     g = gg.grid_full(600, 600)
+    src = np.array([0, 5, 1234, g.n - 1], np.int32)
+    want = oracle_bc_ext(g, src)
     with bcm.Graph(g.n, g.row_ptr, g.col_idx, flags=bcm.BC_GRAPH_TRUST_SYMMETRIC) as G:
-        with pytest.raises(bcm.BCError) as ei:
-            batched(G, np.array([0, 5], np.int32))
-        assert ei.value.status == bcm.BC_ERR_RANGE
+        bc, dist, sigma = G.run_detail(src, bcm.make_options(bcm.BC_MODE_BATCHED))
+        again = batched(G, src[:2])
+    check_bc(bc, want)
+    check_bc(again, oracle_bc_ext(g, src[:2]))
+    for i, s in enumerate(src):
+        od, sm, se, _, st = oracle.single_source_ext(g.row_ptr, g.col_idx, int(s),
+                                                     with_delta=False)
+        assert st == oracle.OK
+        assert np.array_equal(dist[i], od)
+        check_sigma_ext(sigma[i], sm, se)
+
+
+@pytest.mark.parametrize("k,width", [(1100, 2), (700, 3)])
+def test_diamond_chain_extended_closed_form(k, width):
+    """Chain of k diamonds from hub 0 (counts width**i past 2**1024): hub i's BC
+    is (width+1)(k-i), a middle vertex of diamond i has (1 + (width+1)(k-i)) /
+    width, the source 0."""
+    g = gg.diamond_chain(k, width)
+    step = width + 1
+    want = np.zeros(g.n)
+    for i in range(1, k + 1):
+        want[i * step] = (width + 1) * (k - i)
+        want[i * step - step + 1:i * step] = (1 + (width + 1) * (k - i)) / width
+    with bcm.Graph(g.n, g.row_ptr, g.col_idx) as G:
+        check_bc(batched(G, np.array([0], np.int32)), want)
+
+
+def test_extended_range_device_loop_falls_back():
+    """All 3301 sources of a diamond chain: 52 batches, which take the
+    device-resident loop by default; its counts overflow double, and the call
+    runs again on the host loop with level-scaled counts.  bc_run_multi on the
+    same kind of graph clears its outputs and does the same."""
+    g = gg.diamond_chain(1100, 2)
+    src = np.arange(g.n, dtype=np.int32)
+    with bcm.Graph(g.n, g.row_ptr, g.col_idx) as G:
+        check_bc(G.run(src), oracle_bc_ext(g, src))
+    reqs = [src[:10], src[100:164], src[3000:3001], src[5:6]]
+    import torch
+    with bcm.Graph(g.n, g.row_ptr, g.col_idx) as G:
+        outs = [torch.full((g.n,), 7.0, dtype=torch.float64, device="cuda") for _ in reqs]
+        G.run_multi(reqs, outs)
+        torch.cuda.synchronize()
+        for r, o in zip(reqs, outs):
+            check_bc(o.cpu().numpy(), oracle_bc_ext(g, r))
 
 
 def test_auto_mode_matches():
@@ -170,24 +218,22 @@ def test_detail_rows_follow_caller_order_across_batches():
         check_sigma(sigma[i], osg)
 
 
-def test_road_grid_without_shortcuts_range():
+def test_road_grid_without_shortcuts_extended():
     """Road-like grid with no shortcuts (about 1,700 levels, the level array grows
-    several times): BC_ERR_RANGE from the batched path, with every source's
-    distances equal to the oracle's and sigma equal where it stays far from
-    overflow."""
+    several times; counts overflow double): BC within 1e-9 of the extended
+    oracle, distances equal, exported sigma as in check_sigma_ext."""
     g = gg.grid_road(1024, 1024, 0.05, 0.0, seed=2)
     src = gg.sample_sources(g, 3, seed=102)
     with bcm.Graph(g.n, g.row_ptr, g.col_idx, flags=bcm.BC_GRAPH_TRUST_SYMMETRIC) as G:
-        with pytest.raises(bcm.BCError) as ei:
-            G.run_detail(src, bcm.make_options(bcm.BC_MODE_BATCHED))
-        assert ei.value.status == bcm.BC_ERR_RANGE
-        _, dist, sigma = ei.value.result
+        bc, dist, sigma = G.run_detail(src, bcm.make_options(bcm.BC_MODE_BATCHED))
+    check_bc(bc, oracle_bc_ext(g, src))
     for i, s in enumerate(src):
-        od, osg, _, ost = oracle.single_source(g.row_ptr, g.col_idx, int(s), with_delta=False)
-        assert ost == oracle.RANGE
+        od, sm, se, _, ost = oracle.single_source_ext(g.row_ptr, g.col_idx, int(s),
+                                                      with_delta=False)
+        assert ost == oracle.OK
+        assert od.max() > 1000
         assert np.array_equal(dist[i], od)
-        far = osg < 1e300
-        check_sigma(sigma[i][far], osg[far])
+        check_sigma_ext(sigma[i], sm, se)
 
 
 @pytest.mark.parametrize("div", [-1, 1, 16, 64])

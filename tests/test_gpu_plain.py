@@ -6,7 +6,7 @@ import pytest
 import graphgen as gg
 import oracle
 import paper_2401_02472_amd as bcm
-from tests.gpu_checks import check_bc, check_sigma, oracle_bc, plain
+from tests.gpu_checks import check_bc, check_sigma, oracle_bc, oracle_bc_ext, plain
 
 pytestmark = pytest.mark.gpu
 
@@ -135,11 +135,16 @@ def test_graph_from_device_tensors():
         check_bc(plain(G, src), oracle_bc(g, src))
 
 
-def test_sigma_overflow_reports_range():
+def test_sigma_overflow_switches_to_extended_range():
+    """A plain-mode call whose counts pass double's range is completed by the
+    batched path's level-scaled counts (and the graph stays there); the
+    per-source state of bc_single_source, in double, still reports the range."""
     g = gg.grid_full(600, 600)
     with bcm.Graph(g.n, g.row_ptr, g.col_idx, flags=bcm.BC_GRAPH_TRUST_SYMMETRIC) as G:
+        check_bc(plain(G, np.array([0], np.int32)), oracle_bc_ext(g, [0]))
+        check_bc(plain(G, np.array([7, 9], np.int32)), oracle_bc_ext(g, [7, 9]))
         with pytest.raises(bcm.BCError) as ei:
-            plain(G, np.array([0], np.int32))
+            G.single_source(0)
         assert ei.value.status == bcm.BC_ERR_RANGE
 
 
