@@ -85,21 +85,39 @@ def cpu_baseline(g, sources, target_s: float):
 
     threads = min(os.cpu_count() or 1, 16, oracle.max_threads())
     probe = sources[:1]
+    run, kind = oracle.bc, "oracle"
     t = time.perf_counter()
-    oracle.bc(g.row_ptr, g.col_idx, probe, threads=1)
+    _, st = run(g.row_ptr, g.col_idx, probe, threads=1)
+    if st == oracle.RANGE:  # counts beyond double: the long-double oracle
+        run, kind = oracle.bc_ext, "oracle (extended range, long double)"
+        t = time.perf_counter()
+        run(g.row_ptr, g.col_idx, probe, threads=1)
     t1 = max(time.perf_counter() - t, 1e-6)
     m = int(max(threads, min(len(sources), round(target_s * threads / t1))))
     m = min(m, len(sources))
     sample = np.ascontiguousarray(sources[:m])
     t = time.perf_counter()
-    oracle.bc(g.row_ptr, g.col_idx, sample, threads=threads)
+    run(g.row_ptr, g.col_idx, sample, threads=threads)
     dt = time.perf_counter() - t
     return {"value": round(m * g.nnz / dt / 1e9, 4), "unit": "GTEPS", "cores": threads,
-            "kind": "oracle",
+            "kind": kind,
             "sample": f"first {m} of the {len(sources)} workload sources, {dt:.2f} s "
                       f"on {threads} threads",
             "one_thread_value": round(g.nnz / t1 / 1e9, 4),
             "one_thread_sample": f"first source on 1 thread, {t1:.2f} s"}
+
+
+def profile_stride(g, s: int) -> int:
+    """Level stride of the batched path's measurement: 1 up to 16 levels, else
+    about 8 measured levels per pass (BFS depth from s by scipy)."""
+    import numpy as np
+    import scipy.sparse as sp
+    from scipy.sparse.csgraph import shortest_path
+
+    a = sp.csr_matrix((np.ones(g.nnz, dtype=np.int8), g.col_idx, g.row_ptr), shape=(g.n, g.n))
+    dist = shortest_path(a, method="D", unweighted=True, indices=[s])[0]
+    d = int(dist[np.isfinite(dist)].max())
+    return 1 if d <= 16 else max(1, d // 8)
 
 
 def reached_arcs(g, sources) -> int:
@@ -363,9 +381,11 @@ def main() -> int:
     min_batched = tuning["min_batched"] if tuning else 16
     path = "plain" if mode == bcm.BC_MODE_PLAIN or (mode == bcm.BC_MODE_AUTO and
                                                    k < min_batched) else "batched"
-    # the plain path's event records are sampled (every 16th source) so that
-    # they do not slow the host's launch stream; the batched path records all
-    G.profile_enable(16 if path == "plain" else 1)
+    # event records are sampled so that they do not slow short launches: the
+    # plain path measures every 16th source, the batched host loop every
+    # stride-th level (all levels up to 16 deep; about 8 per pass beyond)
+    stride = 16 if path == "plain" else profile_stride(g, int(sources[0]))
+    G.profile_enable(stride)
     G.profile_read(reset=True)
     step_ms = []
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -422,7 +442,7 @@ def main() -> int:
     roofline_one_part = None
     if path == "batched" and args.concurrency != 1:
         opt1 = bcm.make_options(mode, args.batch_width, sparse_div=args.sparse_div, concurrency=1)
-        G.profile_enable(1)
+        G.profile_enable(stride)
         G.profile_read(reset=True)
         for _ in range(2):
             G.run_async(sources, out, opt1)
@@ -432,6 +452,14 @@ def main() -> int:
 
     plain_cmp = None
     if args.compare_plain and path.startswith("batched"):
+        try:  # the one-source path computes in double only
+            G.single_source(int(sources[0]))
+        except bcm.BCError as exc:
+            if exc.status != bcm.BC_ERR_RANGE:
+                raise
+            plain_cmp = {"skipped": "path counts beyond double's range: the one-source-at-"
+                                    "a-time path has no extended range"}
+    if args.compare_plain and path.startswith("batched") and plain_cmp is None:
         sub = np.asarray(sources[:args.compare_plain], np.int32)
         popt = bcm.make_options(bcm.BC_MODE_PLAIN)
         G.run_async(sub, out, popt)
@@ -467,6 +495,7 @@ def main() -> int:
                    "concurrency": args.concurrency,
                    "autotune": tuning, "graph": g.params},
         "plain_comparison": plain_cmp,
+        "profile_level_stride": stride,
         "reached_arc_gteps": round(ra / (ms_per_step / 1e3) / 1e9, 3),
         "end_to_end": end_to_end,
         "p50_ms": round(float(q[0]), 3), "p99_ms": round(float(q[1]), 3),

@@ -299,6 +299,9 @@ WORKLOADS = {
     "grid-1024x1024": (lambda: grid_road(1024, 1024, 0.05, 0.001, seed=2), 64, 102),
     "rmat-s22-ef16": (lambda: rmat(22, 16, seed=3), 256, 103),
     "er-n8388608-d16": (lambda: erdos_renyi(1 << 23, 16, seed=4), 128, 104),
+    # the road-like grid at full diameter (no shortcuts): ~1,700 levels, path
+    # counts beyond double's range
+    "grid-1024x1024-noshortcut": (lambda: grid_road(1024, 1024, 0.05, 0.0, seed=2), 64, 102),
 }
 
 

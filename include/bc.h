@@ -249,9 +249,10 @@ typedef struct bc_profile {
 } bc_profile;
 
 /* Switch measurement off (on = 0) or on for runs on g.  With on = P > 1, the
- * one-source-at-a-time path measures only every P-th source of a run, so that
- * the event records do not slow the host's launch stream; the batched path
- * measures every launch. */
+ * one-source-at-a-time path measures only every P-th source of a run, and the
+ * batched path's host-driven loop only the launches of every P-th level (the
+ * work counters cover the same launches), so that the event records do not
+ * slow short launches; with P = 1 every launch is measured. */
 bc_status bc_profile_enable(bc_graph_t g, int32_t on);
 
 /* Copy the accumulated totals to *out; with reset != 0, clear them. */

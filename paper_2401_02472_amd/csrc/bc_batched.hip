@@ -1189,10 +1189,12 @@ hipError_t batch_start(const BatchDev &d, const int32_t *src_dev, int32_t nlanes
                        hipStream_t stream) {
     int grid = (d.n + kBlock - 1) / kBlock;
     grid = grid < 1 ? 1 : (grid > 4096 ? 4096 : grid);
-    hipLaunchKernelGGL(d.narrow ? k_batch_clear<true> : k_batch_clear<false>, dim3(grid), dim3(kBlock), 0, stream, d);
+    hipLaunchKernelGGL(d.narrow ? k_batch_clear<true> : k_batch_clear<false>,
+                       dim3(grid), dim3(kBlock), 0, stream, d);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(d.narrow ? k_batch_seed<true> : k_batch_seed<false>, dim3(1), dim3(kWave), 0, stream, d, src_dev, nlanes);
+    hipLaunchKernelGGL(d.narrow ? k_batch_seed<true> : k_batch_seed<false>,
+                       dim3(1), dim3(kWave), 0, stream, d, src_dev, nlanes);
     return hipGetLastError();
 }
 
@@ -1200,10 +1202,12 @@ hipError_t batch_forward(const BatchDev &d, int32_t level, uint64_t full, hipStr
     // both steps are launched; each returns at once unless the mode chosen on
     // the device for this level is its own
     const int64_t groups = (d.n - d.big_end + kWave - 1) / kWave;
-    hipLaunchKernelGGL(d.narrow ? k_batch_forward<true> : k_batch_forward<false>, dim3(grid_of(d.items + groups)), dim3(kBlock), 0, stream,
+    hipLaunchKernelGGL(d.narrow ? k_batch_forward<true> : k_batch_forward<false>,
+                       dim3(grid_of(d.items + groups)), dim3(kBlock), 0, stream,
                        d, level, full);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    if (d.sparse_arcs == 0) return hipSuccess;  // the sparse step is switched off
     hipLaunchKernelGGL(k_batch_sparse_mark, dim3(kSparseGrid), dim3(kBlock), 0, stream, d, level);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -1211,7 +1215,8 @@ hipError_t batch_forward(const BatchDev &d, int32_t level, uint64_t full, hipStr
                        dim3(kBlock), 0, stream, d, level, full);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(d.narrow ? k_batch_sparse_pull<true> : k_batch_sparse_pull<false>, dim3(kSparseGrid), dim3(kBlock), 0, stream, d, level,
+    hipLaunchKernelGGL(d.narrow ? k_batch_sparse_pull<true> : k_batch_sparse_pull<false>,
+                       dim3(kSparseGrid), dim3(kBlock), 0, stream, d, level,
                        full);
     return hipGetLastError();
 }
@@ -1219,7 +1224,8 @@ hipError_t batch_forward(const BatchDev &d, int32_t level, uint64_t full, hipStr
 hipError_t batch_forward_done(const BatchDev &d, int32_t level, uint64_t full,
                               hipStream_t stream) {
     if (d.multi_end > 0) {
-        hipLaunchKernelGGL(d.narrow ? k_batch_forward_finish<true> : k_batch_forward_finish<false>, dim3(grid_of(d.multi_end)), dim3(kBlock), 0,
+        hipLaunchKernelGGL(d.narrow ? k_batch_forward_finish<true> : k_batch_forward_finish<false>,
+                           dim3(grid_of(d.multi_end)), dim3(kBlock), 0,
                            stream, d, level, full);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
@@ -1235,7 +1241,8 @@ hipError_t batch_forward_done(const BatchDev &d, int32_t level, uint64_t full,
 
 hipError_t batch_reverse(const BatchDev &d, int32_t level, hipStream_t stream) {
     const int64_t groups = (d.n - d.big_end + kWave - 1) / kWave;
-    hipLaunchKernelGGL(d.narrow ? k_batch_reverse<true> : k_batch_reverse<false>, dim3(grid_of(d.items + groups)), dim3(kBlock), 0, stream,
+    hipLaunchKernelGGL(d.narrow ? k_batch_reverse<true> : k_batch_reverse<false>,
+                       dim3(grid_of(d.items + groups)), dim3(kBlock), 0, stream,
                        d, level);
     return hipGetLastError();
 }
@@ -1261,7 +1268,8 @@ hipError_t batch_export(const BatchDev &d, int32_t deepest, int32_t nlanes, int3
                         double *sigma, hipStream_t stream) {
     int grid = (d.n + kBlock - 1) / kBlock;
     grid = grid < 1 ? 1 : (grid > 4096 ? 4096 : grid);
-    hipLaunchKernelGGL(d.narrow ? k_batch_export<true> : k_batch_export<false>, dim3(grid), dim3(kBlock), 0, stream, d, deepest, nlanes,
+    hipLaunchKernelGGL(d.narrow ? k_batch_export<true> : k_batch_export<false>,
+                       dim3(grid), dim3(kBlock), 0, stream, d, deepest, nlanes,
                        dist, sigma);
     return hipGetLastError();
 }

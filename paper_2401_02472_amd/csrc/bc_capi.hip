@@ -794,6 +794,15 @@ bc_status run_batch_plan(bc_graph_s *g, const std::vector<int32_t> &s_int,
         e = hipMemsetAsync(ws->dev.ctrl + kCtlRange, 0, sizeof(int32_t), stream);
     if (e != hipSuccess) return fail(from_hip(e));
     int32_t range = 0, run_depth = 0;
+    // measurement covers the launches of every stride-th level only (all of
+    // them with stride 1): events around every launch slow deep graphs' short
+    // level steps
+    const int32_t stride = std::max(1, g->profiling.load());
+    auto measure = [&](int32_t L) {
+        const bool m = prof && L % stride == 0;
+        ws->timer.on = m;
+        ws->dev.stats = m ? ws->d_stats : nullptr;
+    };
     for (size_t bi = 0; bi < plan.size();) {
         const BatchPlan &bp = plan[bi];
         const int32_t nl = bp.nlanes;
@@ -817,6 +826,7 @@ bc_status run_batch_plan(bc_graph_s *g, const std::vector<int32_t> &s_int,
             const int32_t K = std::max(2, g->batch_depth_hint.load() + 2);
             const int32_t Lend = std::min(L0 + K, ws->lcap - 1);
             for (int32_t L = L0; L < Lend && e == hipSuccess; ++L) {
+                measure(L);
                 e = ws->timer.begin(BC_PROF_FORWARD, stream);
                 if (e == hipSuccess) e = batch_forward(d, L, full, stream);
                 if (e == hipSuccess) e = ws->timer.end(stream);
@@ -854,6 +864,7 @@ bc_status run_batch_plan(bc_graph_s *g, const std::vector<int32_t> &s_int,
         }
         if (restart) continue;
         for (int32_t L = deepest; L >= 1 && e == hipSuccess; --L) {
+            measure(L);
             if (L != deepest) {
                 e = ws->timer.begin(BC_PROF_REVERSE, stream);
                 if (e == hipSuccess) e = batch_reverse(d, L, stream);
