@@ -114,9 +114,10 @@ def draw(seed: int, stream: int, i: int) -> int:
 
 
 def rmat(scale: int, edgefactor: int, a: float = 0.57, b: float = 0.19, c: float = 0.19,
-         seed: int = 1, relabel: bool = True) -> CSR:
-    """Undirected R-MAT graph with 2**scale vertices and edgefactor*2**scale sampled edges;
-    self-loops and duplicates removed, vertex ids randomly relabelled."""
+         seed: int = 1, relabel: bool = True, directed: bool = False) -> CSR:
+    """R-MAT graph with 2**scale vertices and edgefactor*2**scale sampled edges;
+    self-loops and duplicates removed, vertex ids randomly relabelled.  Undirected
+    (symmetrised) unless `directed`, which keeps each sampled edge as one arc."""
     lib = _load()
     n = 1 << scale
     m = edgefactor * n
@@ -127,9 +128,10 @@ def rmat(scale: int, edgefactor: int, a: float = 0.57, b: float = 0.19, c: float
         perm = np.empty(n, dtype=np.int32)
         lib.gg_permutation(n, seed, _p32(perm))
         lib.gg_relabel(m, _p32(perm), _p32(src), _p32(dst))
-    g = csr_from_edges(n, src, dst, name=f"rmat-s{scale}-ef{edgefactor}",
+    g = csr_from_edges(n, src, dst, symmetrize=not directed,
+                       name=f"rmat-s{scale}-ef{edgefactor}" + ("-dir" if directed else ""),
                        params=dict(kind="rmat", scale=scale, edgefactor=edgefactor, a=a, b=b, c=c,
-                                   seed=seed, relabel=relabel))
+                                   seed=seed, relabel=relabel, directed=directed))
     return g
 
 
@@ -273,6 +275,30 @@ def gnp(n: int, p: float, seed: int) -> CSR:
             idx += 1
     return _from_pairs(n, pairs if pairs else np.zeros((0, 2)), f"gnp-{n}-{p}", kind="gnp",
                        n=n, p=p, seed=seed)
+
+
+def gnp_directed(n: int, p: float, seed: int) -> CSR:
+    """Directed G(n, p) for small n: each ordered pair (i, j), i != j, kept as arc
+    i -> j when its draw (stream 13) < p."""
+    u, v = [], []
+    idx = 0
+    for i in range(n):
+        for j in range(n):
+            if i != j:
+                if (draw(seed, 13, idx) >> 11) * 2.0 ** -53 < p:
+                    u.append(i)
+                    v.append(j)
+                idx += 1
+    return csr_from_edges(n, np.array(u, np.int64), np.array(v, np.int64), symmetrize=False,
+                          name=f"dgnp-{n}-{p}", params=dict(kind="gnp_directed", n=n, p=p,
+                                                             seed=seed))
+
+
+def directed(n: int, pairs, name: str) -> CSR:
+    """Directed graph from (u, v) arc pairs (duplicates and self-loops removed)."""
+    pairs = np.asarray(pairs, dtype=np.int64).reshape(-1, 2)
+    return csr_from_edges(n, pairs[:, 0], pairs[:, 1], symmetrize=False, name=name,
+                          params=dict(kind="directed", n=n))
 
 
 def from_adjacency_bits(n: int, bits: int) -> CSR:

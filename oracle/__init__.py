@@ -16,6 +16,9 @@ invariant, additivity over sources, and NetworkX's betweenness.  The
 extended-range functions (``*_ext``, long double) are pinned to closed forms on
 chains of diamonds whose path counts pass double's range, to exact big-integer
 counts on deep grids, and to the double oracle wherever counts fit double.
+The directed entry points (``directed=True``) are pinned to closed forms on
+directed paths, cycles and stars, brute force on random digraphs, NetworkX's
+directed betweenness and the undirected oracle on symmetric graphs.
 """
 from __future__ import annotations
 
@@ -70,6 +73,10 @@ def _load():
                               f64p]
     lib.oracle_max_threads.restype = ctypes.c_int
     lib.oracle_max_threads.argtypes = []
+    lib.oracle_single_source_directed.restype = ctypes.c_int
+    lib.oracle_single_source_directed.argtypes = lib.oracle_single_source.argtypes
+    lib.oracle_bc_directed.restype = ctypes.c_int
+    lib.oracle_bc_directed.argtypes = lib.oracle_bc.argtypes
     lib.oracle_ld_digits.restype = ctypes.c_int
     lib.oracle_ld_digits.argtypes = []
     lib.oracle_single_source_ext.restype = ctypes.c_int
@@ -91,8 +98,9 @@ def max_threads() -> int:
     return int(_load().oracle_max_threads())
 
 
-def single_source(row_ptr, col_idx, s: int, with_delta: bool = True):
-    """(dist int32[n], sigma float64[n], delta float64[n] or None, status) from source s."""
+def single_source(row_ptr, col_idx, s: int, with_delta: bool = True, directed: bool = False):
+    """(dist int32[n], sigma float64[n], delta float64[n] or None, status) from source s
+    (directed: the CSR lists out-arcs)."""
     lib = _load()
     rp, rpp = _i32(row_ptr)
     ci, cip = _i32(col_idx)
@@ -100,7 +108,8 @@ def single_source(row_ptr, col_idx, s: int, with_delta: bool = True):
     dist = np.empty(n, dtype=np.int32)
     sigma = np.empty(n, dtype=np.float64)
     delta = np.empty(n, dtype=np.float64) if with_delta else None
-    st = lib.oracle_single_source(n, rpp, cip, int(s), dist.ctypes.data_as(ctypes.POINTER(
+    fn = lib.oracle_single_source_directed if directed else lib.oracle_single_source
+    st = fn(n, rpp, cip, int(s), dist.ctypes.data_as(ctypes.POINTER(
         ctypes.c_int32)), sigma.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
         delta.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if with_delta else None)
     if st == INVALID_ARG:
@@ -108,16 +117,18 @@ def single_source(row_ptr, col_idx, s: int, with_delta: bool = True):
     return dist, sigma, delta, st
 
 
-def bc(row_ptr, col_idx, sources, threads: int = 0):
-    """(BC float64[n], status): raw Brandes sum over `sources` (ordered pairs, no scaling)."""
+def bc(row_ptr, col_idx, sources, threads: int = 0, directed: bool = False):
+    """(BC float64[n], status): raw Brandes sum over `sources` (ordered pairs, no scaling;
+    directed: the CSR lists out-arcs)."""
     lib = _load()
     rp, rpp = _i32(row_ptr)
     ci, cip = _i32(col_idx)
     src, srcp = _i32(sources)
     n = rp.shape[0] - 1
     out = np.empty(n, dtype=np.float64)
-    st = lib.oracle_bc(n, rpp, cip, srcp if src.size else None, int(src.size), int(threads),
-                       out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    fn = lib.oracle_bc_directed if directed else lib.oracle_bc
+    st = fn(n, rpp, cip, srcp if src.size else None, int(src.size), int(threads),
+            out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
     if st == INVALID_ARG:
         raise OracleError("invalid argument")
     return out, st

@@ -32,6 +32,11 @@
  *   - A source does not add its own dependency to its BC (v != src).
  *   - Parallel arcs count as distinct paths; self-loops never lie on a
  *     shortest path and have no effect.
+ *   - Directed graphs (the *_directed entry points; the CSR lists out-arcs):
+ *     the BFS follows arcs forward, sigma sums over parents (arcs into v from
+ *     the previous level) and dependencies over children (arcs out of v to the
+ *     next level) -- Brandes' algorithm for directed graphs, over the ordered
+ *     pairs (s, t) with t reachable from s.
  *
  * Status codes: 0 = ok, 1 = invalid argument, 4 = some sigma is not finite
  * (BC is then written but meaningless).  The *_ext entry points at the end
@@ -76,9 +81,16 @@ static int32_t bfs_order(int32_t n, const int32_t *row_ptr, const int32_t *col_i
 /* One source: dist, sigma and delta for every vertex.  delta may be NULL
  * (then only the forward pass runs).  bc, when not NULL, receives
  * bc[v] += delta[v] for every reached v != s.  order is scratch of n int32.
- * Returns OR_OK or OR_RANGE. */
+ * Returns OR_OK or OR_RANGE.
+ *
+ * directed = 0: the CSR is symmetric and a vertex's parents are among its
+ * neighbours, so sigma is pulled over them.  directed = 1: the CSR lists out-
+ * arcs; the BFS follows them, and since a vertex's parents are found through
+ * their own out-arcs, each vertex, once its sigma is final (BFS order), adds
+ * it to its children (Brandes' formulation).  The reverse pass is the same in
+ * both cases: children are reached through out-arcs. */
 static int single_source(int32_t n, const int32_t *row_ptr, const int32_t *col_idx, int32_t s,
-                         int32_t *dist, double *sigma, double *delta, double *bc,
+                         int directed, int32_t *dist, double *sigma, double *delta, double *bc,
                          int32_t *order) {
     int32_t reached = bfs_order(n, row_ptr, col_idx, s, dist, order);
 
@@ -86,17 +98,31 @@ static int single_source(int32_t n, const int32_t *row_ptr, const int32_t *col_i
     for (int32_t v = 0; v < n; ++v) sigma[v] = 0.0;
     sigma[s] = 1.0;
 
-    /* Forward pass, BFS order: sigma[v] = sum of sigma over parents. */
     int status = OR_OK;
-    for (int32_t i = 1; i < reached; ++i) {
-        int32_t v = order[i];
-        double acc = 0.0;
-        for (int32_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {
-            int32_t w = col_idx[e];
-            if (dist[w] == dist[v] - 1) acc = acc + sigma[w];
+    if (directed) {
+        /* Forward pass, BFS order: sigma[v] is final when v is reached in the
+         * order; it is added to every child of v. */
+        for (int32_t i = 0; i < reached; ++i) {
+            int32_t v = order[i];
+            for (int32_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {
+                int32_t w = col_idx[e];
+                if (dist[w] == dist[v] + 1) sigma[w] = sigma[w] + sigma[v];
+            }
         }
-        sigma[v] = acc;
-        if (!isfinite(acc)) status = OR_RANGE;
+        for (int32_t i = 1; i < reached; ++i)
+            if (!isfinite(sigma[order[i]])) status = OR_RANGE;
+    } else {
+        /* Forward pass, BFS order: sigma[v] = sum of sigma over parents. */
+        for (int32_t i = 1; i < reached; ++i) {
+            int32_t v = order[i];
+            double acc = 0.0;
+            for (int32_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {
+                int32_t w = col_idx[e];
+                if (dist[w] == dist[v] - 1) acc = acc + sigma[w];
+            }
+            sigma[v] = acc;
+            if (!isfinite(acc)) status = OR_RANGE;
+        }
     }
     if (delta == NULL) return status;
 
@@ -128,7 +154,18 @@ int oracle_single_source(int32_t n, const int32_t *row_ptr, const int32_t *col_i
     if (check_graph_args(n, row_ptr, col_idx) != OR_OK || s < 0 || s >= n || !dist || !sigma)
         return OR_INVALID_ARG;
     int32_t *order = (int32_t *)malloc((size_t)n * sizeof(int32_t));
-    int st = single_source(n, row_ptr, col_idx, s, dist, sigma, delta, NULL, order);
+    int st = single_source(n, row_ptr, col_idx, s, 0, dist, sigma, delta, NULL, order);
+    free(order);
+    return st;
+}
+
+/* As oracle_single_source for a directed graph (row_ptr / col_idx list out-arcs). */
+int oracle_single_source_directed(int32_t n, const int32_t *row_ptr, const int32_t *col_idx,
+                                  int32_t s, int32_t *dist, double *sigma, double *delta) {
+    if (check_graph_args(n, row_ptr, col_idx) != OR_OK || s < 0 || s >= n || !dist || !sigma)
+        return OR_INVALID_ARG;
+    int32_t *order = (int32_t *)malloc((size_t)n * sizeof(int32_t));
+    int st = single_source(n, row_ptr, col_idx, s, 1, dist, sigma, delta, NULL, order);
     free(order);
     return st;
 }
@@ -138,8 +175,8 @@ int oracle_single_source(int32_t n, const int32_t *row_ptr, const int32_t *col_i
  * own partial BC, and the partials are added in thread order, so the result
  * does not depend on scheduling.  With one thread the sources are processed in
  * the given order. */
-int oracle_bc(int32_t n, const int32_t *row_ptr, const int32_t *col_idx, const int32_t *sources,
-              int32_t k, int threads, double *bc) {
+static int run_bc(int32_t n, const int32_t *row_ptr, const int32_t *col_idx,
+                  const int32_t *sources, int32_t k, int threads, int directed, double *bc) {
     if (check_graph_args(n, row_ptr, col_idx) != OR_OK || k < 0 || !bc ||
         (k > 0 && !sources))
         return OR_INVALID_ARG;
@@ -170,8 +207,8 @@ int oracle_bc(int32_t n, const int32_t *row_ptr, const int32_t *col_idx, const i
         double *delta = (double *)malloc((size_t)n * sizeof(double));
         double *mine = partial + (size_t)t * (size_t)n;
         for (int32_t i = lo; i < hi; ++i) {
-            int st = single_source(n, row_ptr, col_idx, sources[i], dist, sigma, delta, mine,
-                                   order);
+            int st = single_source(n, row_ptr, col_idx, sources[i], directed, dist, sigma, delta,
+                                   mine, order);
             if (st > status) status = st;
         }
         free(dist);
@@ -185,6 +222,18 @@ int oracle_bc(int32_t n, const int32_t *row_ptr, const int32_t *col_idx, const i
     }
     free(partial);
     return status;
+}
+
+int oracle_bc(int32_t n, const int32_t *row_ptr, const int32_t *col_idx, const int32_t *sources,
+              int32_t k, int threads, double *bc) {
+    return run_bc(n, row_ptr, col_idx, sources, k, threads, 0, bc);
+}
+
+/* As oracle_bc for a directed graph (row_ptr / col_idx list out-arcs): ordered
+ * pairs (s, t) with t reachable from s along arcs. */
+int oracle_bc_directed(int32_t n, const int32_t *row_ptr, const int32_t *col_idx,
+                       const int32_t *sources, int32_t k, int threads, double *bc) {
+    return run_bc(n, row_ptr, col_idx, sources, k, threads, 1, bc);
 }
 
 /* ---- extended range --------------------------------------------------------

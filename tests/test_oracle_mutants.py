@@ -94,6 +94,40 @@ EXT_MUTANTS = {
 }
 
 
+# Slips in the directed forward pass (the reverse pass is shared with the
+# undirected case and covered above).
+DIR_MUTANTS = {
+    "directed-pulls-like-undirected": ("    if (directed) {", "    if (0) {"),
+    "push-without-level-test": ("if (dist[w] == dist[v] + 1) sigma[w] = sigma[w] + sigma[v];",
+                                "if (dist[w] >= dist[v] && w != v) sigma[w] = sigma[w] + sigma[v];"),
+    "push-skips-source": ("        for (int32_t i = 0; i < reached; ++i) {\n            int32_t v = order[i];\n            for (int32_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {\n                int32_t w = col_idx[e];\n                if (dist[w] == dist[v] + 1) sigma[w]",
+                          "        for (int32_t i = 1; i < reached; ++i) {\n            int32_t v = order[i];\n            for (int32_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {\n                int32_t w = col_idx[e];\n                if (dist[w] == dist[v] + 1) sigma[w]"),
+    "push-overwrites": ("if (dist[w] == dist[v] + 1) sigma[w] = sigma[w] + sigma[v];",
+                        "if (dist[w] == dist[v] + 1) sigma[w] = sigma[v];"),
+}
+
+
+def _directed_pin_suite():
+    for n in (7, 50):
+        pins.test_directed_path_closed_form(n)
+    pins.test_directed_cycle_closed_form(9)
+    pins.test_directed_stars_and_diamond()
+    pins.test_directed_random_definition()
+
+
+def test_unmutated_copy_passes_directed_pins(swap_oracle):
+    swap_oracle(open(SRC).read())
+    _directed_pin_suite()
+
+
+@pytest.mark.parametrize("name", sorted(DIR_MUTANTS))
+def test_directed_mutant_is_caught(name, swap_oracle):
+    before, after = DIR_MUTANTS[name]
+    swap_oracle(_mutate(open(SRC).read(), before, after, ext=False))
+    with pytest.raises(AssertionError):
+        _directed_pin_suite()
+
+
 def _ext_pin_suite():
     """The extended-range pins (quick ones) against the loaded library."""
     pins.test_ext_diamond_chain_closed_form(1100, 2)

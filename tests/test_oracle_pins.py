@@ -440,3 +440,104 @@ def test_ext_sum_invariant_deep_road_grid():
         assert r.max() > 1000
         want += int((r - 1).sum())
     assert abs(bc.sum() - want) <= 1e-12 * want
+
+
+# ---------------------------------------------------------------------------
+# Directed graphs (the CSR lists out-arcs)
+# ---------------------------------------------------------------------------
+
+def dir_bc(g, sources=None):
+    src = np.arange(g.n, dtype=np.int32) if sources is None else np.asarray(sources, np.int32)
+    bc, st = oracle.bc(g.row_ptr, g.col_idx, src, directed=True)
+    assert st == oracle.OK
+    return bc
+
+
+@pytest.mark.parametrize("n", [2, 7, 50])
+def test_directed_path_closed_form(n):
+    """0 -> 1 -> ... -> n-1: vertex i lies on the paths from the i vertices before
+    it to the n-1-i after it."""
+    g = gg.directed(n, [(i, i + 1) for i in range(n - 1)], f"dpath-{n}")
+    want = np.array([i * (n - 1 - i) for i in range(n)], dtype=np.float64)
+    assert np.array_equal(dir_bc(g), want)
+
+
+@pytest.mark.parametrize("n", [3, 9, 12])
+def test_directed_cycle_closed_form(n):
+    """Directed n-cycle: the unique path of length d has d-1 interior vertices, n
+    paths of each length 1..n-1, spread evenly: BC = (n-1)(n-2)/2 everywhere."""
+    g = gg.directed(n, [(i, (i + 1) % n) for i in range(n)], f"dcycle-{n}")
+    assert np.array_equal(dir_bc(g), np.full(n, (n - 1) * (n - 2) / 2))
+
+
+def test_directed_stars_and_diamond():
+    """Out-star and in-star: no path has an interior vertex.  Diamond DAG
+    0 -> {1, 2} -> 3: 1 and 2 each carry half of the one pair (0, 3)."""
+    n = 9
+    out_star = gg.directed(n, [(0, i) for i in range(1, n)], "out-star")
+    in_star = gg.directed(n, [(i, 0) for i in range(1, n)], "in-star")
+    assert not dir_bc(out_star).any() and not dir_bc(in_star).any()
+    both = gg.directed(n, [(0, i) for i in range(1, n)] + [(i, 0) for i in range(1, n)], "star")
+    want = np.zeros(n)
+    want[0] = (n - 1) * (n - 2)
+    assert np.array_equal(dir_bc(both), want)
+    dia = gg.directed(4, [(0, 1), (0, 2), (1, 3), (2, 3)], "diamond-dag")
+    assert np.array_equal(dir_bc(dia), [0.0, 0.5, 0.5, 0.0])
+    d, sg, dl, st = oracle.single_source(dia.row_ptr, dia.col_idx, 0, directed=True)
+    assert list(d) == [0, 1, 1, 2] and list(sg) == [1, 1, 1, 2] and list(dl) == [0, 0.5, 0.5, 0]
+    d, sg, _, _ = oracle.single_source(dia.row_ptr, dia.col_idx, 3, directed=True)
+    assert list(d) == [-1, -1, -1, 0] and list(sg) == [0, 0, 0, 1]
+
+
+def test_directed_random_definition():
+    """Random digraphs up to 12 vertices: BC from the definition (walk counting
+    on the directed adjacency), all sources and random multisets; dist and sigma
+    of single sources against the walk counts."""
+    rng = np.random.default_rng(17)
+    for trial in range(80):
+        n = int(rng.integers(2, 13))
+        g = gg.gnp_directed(n, float(rng.uniform(0.05, 0.5)), seed=trial)
+        A = adjacency(g.row_ptr, g.col_idx)
+        np.testing.assert_allclose(dir_bc(g), bc_by_definition(A), rtol=1e-12, atol=1e-12)
+        srcs = rng.integers(0, n, size=int(rng.integers(1, 2 * n)))
+        np.testing.assert_allclose(dir_bc(g, srcs), bc_by_definition(A, srcs), rtol=1e-12,
+                                   atol=1e-12)
+        dist, sigma = walk_dist_sigma(A)
+        for s in range(min(n, 3)):
+            d, sg, _, st = oracle.single_source(g.row_ptr, g.col_idx, s, directed=True)
+            assert st == oracle.OK
+            assert np.array_equal(d, dist[s]) and np.array_equal(sg, sigma[s])
+
+
+def test_directed_networkx_cross_check():
+    nx = pytest.importorskip("networkx")
+    graphs = [gg.gnp_directed(n, 0.2, seed=n) for n in range(5, 26, 5)]
+    graphs.append(gg.rmat(8, 8, seed=2, directed=True))
+    for g in graphs:
+        G = nx.DiGraph()
+        G.add_nodes_from(range(g.n))
+        for u in range(g.n):
+            for v in g.col_idx[g.row_ptr[u]:g.row_ptr[u + 1]]:
+                G.add_edge(u, int(v))
+        ref = nx.betweenness_centrality(G, normalized=False)  # ordered pairs for digraphs
+        want = np.array([ref[v] for v in range(g.n)])
+        np.testing.assert_allclose(dir_bc(g), want, rtol=1e-10, atol=1e-10)
+
+
+def test_directed_on_symmetric_graph_equals_undirected(rmat12):
+    src = gg.sample_sources(rmat12, 60, seed=5)
+    a = all_bc(rmat12, src)
+    b = dir_bc(rmat12, src)
+    assert np.max(np.abs(a - b) / np.maximum(a, 1)) < 1e-12
+
+
+def test_directed_sum_invariant():
+    """Directed R-MAT scale 12: sum_v BC(v) = sum_s sum_{t reachable} (d(s,t) - 1),
+    with directed distances from scipy."""
+    g = gg.rmat(12, 8, seed=9, directed=True)
+    src = gg.sample_sources(g, 40, seed=10)
+    m = sp.csr_matrix((np.ones(g.nnz), g.col_idx, g.row_ptr), shape=(g.n, g.n))
+    d = shortest_path(m, method="D", directed=True, unweighted=True, indices=src)
+    want = float(np.where(np.isfinite(d) & (d > 0), d - 1, 0).sum())
+    got = dir_bc(g, src).sum()
+    assert abs(got - want) <= 1e-10 * want
