@@ -15,6 +15,7 @@ workload on this host's cores.
 from __future__ import annotations
 
 import argparse
+import functools
 import hashlib
 import json
 import os
@@ -85,7 +86,10 @@ def cpu_baseline(g, sources, target_s: float):
 
     threads = min(os.cpu_count() or 1, 16, oracle.max_threads())
     probe = sources[:1]
-    run, kind = oracle.bc, "oracle"
+    directed = bool(g.params.get("directed"))
+    run, kind = functools.partial(oracle.bc, directed=directed), "oracle"
+    if directed:
+        kind = "oracle (directed)"
     t = time.perf_counter()
     _, st = run(g.row_ptr, g.col_idx, probe, threads=1)
     if st == oracle.RANGE:  # counts beyond double: the long-double oracle
@@ -115,14 +119,18 @@ def profile_stride(g, s: int) -> int:
     from scipy.sparse.csgraph import shortest_path
 
     a = sp.csr_matrix((np.ones(g.nnz, dtype=np.int8), g.col_idx, g.row_ptr), shape=(g.n, g.n))
-    dist = shortest_path(a, method="D", unweighted=True, indices=[s])[0]
+    dist = shortest_path(a, method="D", directed=bool(g.params.get("directed")), unweighted=True,
+                         indices=[s])[0]
     d = int(dist[np.isfinite(dist)].max())
     return 1 if d <= 16 else max(1, d // 8)
 
 
-def reached_arcs(g, sources) -> int:
+def reached_arcs(g, sources):
     """Sum over the sources of the arcs leaving the vertices each one reaches
-    (the degree sum of its connected component)."""
+    (the degree sum of its connected component); None for a directed graph
+    (reachability differs per source)."""
+    if g.params.get("directed"):
+        return None
     import numpy as np
     import scipy.sparse as sp
     from scipy.sparse.csgraph import connected_components
@@ -337,7 +345,9 @@ def main() -> int:
     opt = bcm.make_options(mode, args.batch_width, sparse_div=args.sparse_div,
                            concurrency=args.concurrency)
 
-    G = bcm.Graph(g.n, g.row_ptr, g.col_idx, flags=bcm.BC_GRAPH_TRUST_SYMMETRIC)
+    gflags = (bcm.BC_GRAPH_DIRECTED if g.params.get("directed")
+              else bcm.BC_GRAPH_TRUST_SYMMETRIC)
+    G = bcm.Graph(g.n, g.row_ptr, g.col_idx, flags=gflags)
     out = torch.empty(g.n, dtype=torch.float64, device="cuda")
     stream = torch.cuda.current_stream()
 
@@ -365,7 +375,7 @@ def main() -> int:
         # host sources in, host BC out (one H2D of the sources, one D2H of BC),
         # and the one-time graph upload
         t = time.perf_counter()
-        G2 = bcm.Graph(g.n, g.row_ptr, g.col_idx, flags=bcm.BC_GRAPH_TRUST_SYMMETRIC)
+        G2 = bcm.Graph(g.n, g.row_ptr, g.col_idx, flags=gflags)
         create_ms = (time.perf_counter() - t) * 1e3
         G2.close()
         t = time.perf_counter()
@@ -452,13 +462,17 @@ def main() -> int:
 
     plain_cmp = None
     if args.compare_plain and path.startswith("batched"):
-        try:  # the one-source path computes in double only
+        try:  # the one-source path computes in double, on undirected graphs
             G.single_source(int(sources[0]))
         except bcm.BCError as exc:
-            if exc.status != bcm.BC_ERR_RANGE:
+            if exc.status == bcm.BC_ERR_RANGE:
+                plain_cmp = {"skipped": "path counts beyond double's range: the one-source-at-"
+                                        "a-time path has no extended range"}
+            elif exc.status == bcm.BC_ERR_UNSUPPORTED:
+                plain_cmp = {"skipped": "directed graph: the one-source-at-a-time path is "
+                                        "undirected only"}
+            else:
                 raise
-            plain_cmp = {"skipped": "path counts beyond double's range: the one-source-at-"
-                                    "a-time path has no extended range"}
     if args.compare_plain and path.startswith("batched") and plain_cmp is None:
         sub = np.asarray(sources[:args.compare_plain], np.int32)
         popt = bcm.make_options(bcm.BC_MODE_PLAIN)
@@ -496,7 +510,7 @@ def main() -> int:
                    "autotune": tuning, "graph": g.params},
         "plain_comparison": plain_cmp,
         "profile_level_stride": stride,
-        "reached_arc_gteps": round(ra / (ms_per_step / 1e3) / 1e9, 3),
+        "reached_arc_gteps": None if ra is None else round(ra / (ms_per_step / 1e3) / 1e9, 3),
         "end_to_end": end_to_end,
         "p50_ms": round(float(q[0]), 3), "p99_ms": round(float(q[1]), 3),
         "roofline": roofline, "roofline_one_part": roofline_one_part,

@@ -328,6 +328,9 @@ WORKLOADS = {
     # the road-like grid at full diameter (no shortcuts): ~1,700 levels, path
     # counts beyond double's range
     "grid-1024x1024-noshortcut": (lambda: grid_road(1024, 1024, 0.05, 0.0, seed=2), 64, 102),
+    # directed R-MAT: each sampled edge kept as one arc (about half the arcs of
+    # the undirected graph of the same size)
+    "rmat-s22-ef16-dir": (lambda: rmat(22, 16, seed=3, directed=True), 256, 103),
 }
 
 

@@ -29,11 +29,17 @@
  * keep double's rounding.  BC_ERR_RANGE remains for graphs whose counts span
  * more than about 2^1000 within one level.
  *
- * Graphs are undirected: a symmetric CSR (every arc u->v has a matching v->u)
- * with int32 offsets row_ptr[n+1] and int32 neighbours col_idx[row_ptr[n]], the
- * storage the paper uses on host and device (Section "Code Generation", graph
- * representation).  Parallel arcs count as distinct paths; self-loops are
- * accepted and have no effect.
+ * Graphs are undirected by default: a symmetric CSR (every arc u->v has a
+ * matching v->u) with int32 offsets row_ptr[n+1] and int32 neighbours
+ * col_idx[row_ptr[n]], the storage the paper uses on host and device (Section
+ * "Code Generation", graph representation).  Parallel arcs count as distinct
+ * paths; self-loops are accepted and have no effect.  With BC_GRAPH_DIRECTED
+ * the CSR lists out-arcs and need not be symmetric: the BFS follows arcs
+ * forward, sigma sums over the arcs into v from the previous level (the
+ * library keeps the reversed CSR for this, the paper's reverse CSR of Section
+ * "Code Generation") and dependencies over the arcs out of v to the next
+ * level; BC is then over the ordered pairs (s, t) with t reachable from s.
+ * Directed graphs run on the batched path whatever the options ask.
  *
  * Conventions for every call:
  *   - Every call returns a bc_status; no C++ exception crosses this boundary.
@@ -74,8 +80,9 @@ typedef enum {
 /* bc_create_graph flags */
 enum {
     BC_GRAPH_TRUST_SYMMETRIC = 1u << 0, /* skip the host-side symmetry check */
-    BC_GRAPH_INPUT_ON_DEVICE = 1u << 1  /* row_ptr / col_idx are device pointers (they are
+    BC_GRAPH_INPUT_ON_DEVICE = 1u << 1, /* row_ptr / col_idx are device pointers (they are
                                            copied to the host for the same checks) */
+    BC_GRAPH_DIRECTED = 1u << 2         /* out-arc CSR of a directed graph (no symmetry) */
 };
 
 /* Execution modes (bc_options.mode). */
@@ -187,7 +194,8 @@ bc_status bc_run_multi(bc_graph_t g, const int32_t *sources, const int32_t *req_
 /*
  * One source, full per-vertex state (host outputs), for parity checks, from
  * the one-source-at-a-time path in double (no extended range: counts beyond
- * DBL_MAX give BC_ERR_RANGE, with dist still exact).
+ * DBL_MAX give BC_ERR_RANGE, with dist still exact).  Undirected graphs only:
+ * BC_ERR_UNSUPPORTED for a graph created with BC_GRAPH_DIRECTED.
  *   dist   [n] host: hop distance from s, -1 if unreachable
  *   sigma  [n] host: number of shortest s-v paths (0 if unreachable)
  *   delta  [n] host or NULL: dependency of s on v (0 for s and unreachable v)

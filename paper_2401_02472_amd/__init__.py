@@ -15,7 +15,8 @@ import numpy as np
 from . import _capi
 from ._capi import (BC_ERR_DEVICE, BC_ERR_INVALID_ARG, BC_ERR_INVALID_GRAPH,  # noqa: F401
                     BC_ERR_OUT_OF_MEMORY, BC_ERR_RANGE, BC_ERR_UNSUPPORTED,
-                    BC_GRAPH_INPUT_ON_DEVICE, BC_GRAPH_TRUST_SYMMETRIC, BC_MODE_AUTO,
+                    BC_GRAPH_DIRECTED, BC_GRAPH_INPUT_ON_DEVICE, BC_GRAPH_TRUST_SYMMETRIC,
+                    BC_MODE_AUTO,
                     BC_MODE_BATCHED, BC_MODE_PLAIN, BC_OK, bc_options,
                     BC_LOOP_AUTO, BC_LOOP_HOST, BC_LOOP_DEVICE)
 

@@ -25,6 +25,7 @@ BC_ERR_UNSUPPORTED = 6
 
 BC_GRAPH_TRUST_SYMMETRIC = 1 << 0
 BC_GRAPH_INPUT_ON_DEVICE = 1 << 1
+BC_GRAPH_DIRECTED = 1 << 2
 
 BC_MODE_AUTO = 0
 BC_MODE_PLAIN = 1

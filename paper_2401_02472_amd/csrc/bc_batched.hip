@@ -189,7 +189,7 @@ __device__ __forceinline__ void gather_run(uint64_t &hit, int32_t nb, uint64_t m
 // Probe the arcs first + 64*u + lane (u < kProbe, below `end`) of one vertex:
 // m = mask[neighbour] & keep, then gather val rows for the hits.
 template <typename V>
-__device__ __forceinline__ uint64_t probe_chunk(const BatchDev &d, int32_t first, int32_t end,
+__device__ __forceinline__ uint64_t probe_chunk(const int32_t *col, int32_t first, int32_t end,
                                                 const uint64_t *mask, uint64_t keep,
                                                 const V *val, double &acc, Work &wk) {
     const int lane = lane_id();
@@ -198,7 +198,7 @@ __device__ __forceinline__ uint64_t probe_chunk(const BatchDev &d, int32_t first
 #pragma unroll
     for (int u = 0; u < kProbe; ++u) {
         const int32_t e = first + u * kWave + lane;
-        nb[u] = e < end ? d.col_idx[e] : -1;
+        nb[u] = e < end ? col[e] : -1;
         wk.arcs += e < end ? 1u : 0u;
     }
 #pragma unroll
@@ -305,9 +305,9 @@ template <bool N>
 __device__ __forceinline__ void fwd_chunk(const BatchDev &d, int32_t L, uint32_t item,
                                           uint64_t full, double xsc, Work &wk, Front &fr) {
     const int lane = lane_id();
-    const int2 info = d.item_info[item];
+    const int2 info = d.item_info_in[item];
     const int32_t w = info.x, j = info.y;
-    const int32_t rs = d.row_ptr[w], re = d.row_ptr[w + 1];
+    const int32_t rs = d.row_ptr_in[w], re = d.row_ptr_in[w + 1];
     const bool multi = w < d.multi_end;
     uint64_t *FN = d.F + (size_t)(L + 1) * (size_t)d.n;
     const uint64_t vis = d.vis[w];
@@ -319,8 +319,8 @@ __device__ __forceinline__ void fwd_chunk(const BatchDev &d, int32_t L, uint32_t
     const uint64_t *FL = d.F + (size_t)L * (size_t)d.n;
     const int32_t cb = rs + j * kChunk;
     double acc = 0.0;
-    const uint64_t nw =
-        probe_chunk(d, cb, min(re, cb + kChunk), FL, unvis, SigRows<N>::rows(d), acc, wk);
+    const uint64_t nw = probe_chunk(d.col_idx_in, cb, min(re, cb + kChunk), FL, unvis,
+                                    SigRows<N>::rows(d), acc, wk);
     const bool mine = (nw >> lane) & 1ull;
     if (mine && (!multi || j == 0)) ++wk.owners;
     if (!multi) {
@@ -360,8 +360,8 @@ fwd_group(const BatchDev &d, int32_t L, int32_t base, const int32_t *list, int32
     int32_t rs = 0, cnt = 0;
     if (me >= 0) {
         vis = d.vis[me];
-        rs = d.row_ptr[me];
-        const int32_t re = d.row_ptr[me + 1];
+        rs = d.row_ptr_in[me];
+        const int32_t re = d.row_ptr_in[me + 1];
         if (!list) FN[me] = 0ull;
         cnt = vis != full ? re - rs : 0;
     }
@@ -402,7 +402,7 @@ fwd_group(const BatchDev &d, int32_t L, int32_t base, const int32_t *list, int32
             const int32_t o_rs = __shfl(rs, o[r]);
             const uint32_t o_excl = __shfl(excl, o[r]);
             live[r] = a < total;
-            nb[r] = live[r] ? d.col_idx[o_rs + (int32_t)(a - o_excl)] : 0;
+            nb[r] = live[r] ? d.col_idx_in[o_rs + (int32_t)(a - o_excl)] : 0;
         }
 #pragma unroll
         for (int r = 0; r < kRounds; ++r) {
@@ -443,7 +443,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_forward(BatchDev d, int32_t L,
     // nothing past the deepest level found so far (F_L is empty), no room, or
     // this level takes the sparse step
     if (L > d.ctrl[kCtlDeepest] || L + 1 >= d.lcap || d.ctrl[kCtlMode]) return;
-    const uint32_t items = d.items;
+    const uint32_t items = d.items_in;
     const uint32_t groups = (uint32_t)((d.n - d.big_end + kWave - 1) / kWave);
     const uint32_t wave = (blockIdx.x * kBlock + threadIdx.x) / kWave;
     const uint32_t nwaves = gridDim.x * kWavesPerBlock;
@@ -631,7 +631,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_sparse_compact(BatchDev d, int
         for (int j = 0; j < 16; ++j) {
             if (!((bits >> j) & 1u)) continue;
             const int32_t v = (i << 4) + j;
-            if (v < d.big_end) nitems += d.item_first[v + 1] - d.item_first[v];
+            if (v < d.big_end) nitems += d.item_first_in[v + 1] - d.item_first_in[v];
             else ++nsmall;
         }
         uint32_t tot, toti;
@@ -678,7 +678,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_sparse_compact(BatchDev d, int
             while (sbig) {
                 const int j = __ffs(sbig) - 1;
                 sbig &= sbig - 1;
-                const uint32_t f0 = d.item_first[sv0 + j], cnt = d.item_first[sv0 + j + 1] - f0;
+                const uint32_t f0 = d.item_first_in[sv0 + j], cnt = d.item_first_in[sv0 + j + 1] - f0;
                 for (uint32_t q = (uint32_t)lane; q < cnt; q += kWave) d.ilist[spi + q] = f0 + q;
                 spi += cnt;
             }
@@ -773,7 +773,7 @@ __device__ __forceinline__ void bwd_chunk(const BatchDev &d, int32_t L, uint32_t
     const bool on = (mv >> lane) & 1ull;
     const double sig = (on && v >= d.multi_end) ? sig_at<N>(d, (size_t)v * kWave + lane) : 1.0;
     double acc = 0.0;
-    (void)probe_chunk(d, cb, min(re, cb + kChunk), FC, mv, d.coef, acc, wk);
+    (void)probe_chunk(d.col_idx, cb, min(re, cb + kChunk), FC, mv, d.coef, acc, wk);
     if (on && j == 0) ++wk.owners;
     if (v < d.multi_end) d.partial[(size_t)item * kWave + lane] = acc;
     else settle<N>(d, v, mv, sig, acc * xsc);
@@ -1043,7 +1043,8 @@ __global__ __launch_bounds__(kFusedBlock) void k_batch_fused(const BatchDev *dev
     }
     __syncthreads();
     const uint64_t full = nl >= 64 ? ~0ull : ((1ull << nl) - 1ull);
-    const uint32_t items = d.items;
+    const uint32_t items = d.items;         // reverse (arcs out of a vertex)
+    const uint32_t items_in = d.items_in;   // forward (arcs into a vertex)
     const uint32_t groups = (uint32_t)((d.n - d.big_end + kWave - 1) / kWave);
     // forward
     int32_t deepest = 0;
@@ -1056,10 +1057,10 @@ __global__ __launch_bounds__(kFusedBlock) void k_batch_fused(const BatchDev *dev
         }
         if (t == 0) s_found = 0;
         Front fr;
-        for (uint32_t it = wave; it < items + groups; it += kFusedWaves) {
-            if (it < items) fwd_chunk<N>(d, L, it, full, 1.0, wkf, fr);
-            else fwd_group<N>(d, L, d.big_end + (int32_t)(it - items) * kWave, nullptr, 0, full,
-                              1.0, wkf, fr);
+        for (uint32_t it = wave; it < items_in + groups; it += kFusedWaves) {
+            if (it < items_in) fwd_chunk<N>(d, L, it, full, 1.0, wkf, fr);
+            else fwd_group<N>(d, L, d.big_end + (int32_t)(it - items_in) * kWave, nullptr, 0,
+                              full, 1.0, wkf, fr);
         }
         __syncthreads();
         finish_split<N>(d, L, wave, kFusedWaves, 1.0, fr);
@@ -1203,7 +1204,7 @@ hipError_t batch_forward(const BatchDev &d, int32_t level, uint64_t full, hipStr
     // the device for this level is its own
     const int64_t groups = (d.n - d.big_end + kWave - 1) / kWave;
     hipLaunchKernelGGL(d.narrow ? k_batch_forward<true> : k_batch_forward<false>,
-                       dim3(grid_of(d.items + groups)), dim3(kBlock), 0, stream,
+                       dim3(grid_of(d.items_in + groups)), dim3(kBlock), 0, stream,
                        d, level, full);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -1231,7 +1232,7 @@ hipError_t batch_forward_done(const BatchDev &d, int32_t level, uint64_t full,
         if (e != hipSuccess) return e;
     }
     const int64_t groups = (d.n - d.big_end + kWave - 1) / kWave;
-    const int32_t w0 = grid_of(d.items + groups) * kWavesPerBlock;
+    const int32_t w0 = grid_of(d.items_in + groups) * kWavesPerBlock;
     const int32_t w1 = kSparseGrid * kWavesPerBlock;
     const int32_t w2 = d.multi_end > 0 ? grid_of(d.multi_end) * kWavesPerBlock : 0;
     hipLaunchKernelGGL(k_batch_level_done, dim3(1), dim3(kDoneBlock), 0, stream, d, level, w0, w1,

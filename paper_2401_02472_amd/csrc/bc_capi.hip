@@ -140,6 +140,15 @@ struct bc_graph_s {
     uint32_t items = 0;
     int2 *d_item_info = nullptr;
     uint32_t *d_item_first = nullptr;
+    // directed graphs: the reversed CSR (arcs into each vertex, internal order)
+    // and its chunk items, for the forward pass; for undirected graphs these
+    // point at the arrays above
+    bool directed = false;
+    uint32_t items_in = 0;
+    int32_t *d_row_ptr_in = nullptr;
+    int32_t *d_col_idx_in = nullptr;
+    int2 *d_item_info_in = nullptr;
+    uint32_t *d_item_first_in = nullptr;
     uint64_t total_chunks3 = 0;  // chunk slots needed by bucket-3 vertices of one source
     size_t device_bytes = 0;
     std::mutex mu;
@@ -543,7 +552,8 @@ size_t batch_ws_bytes(const bc_graph_s *g) {
     b += align_up((size_t)std::max<uint32_t>(g->items, 1) * kWave * sizeof(double));  // partial
     b += align_up(12 * sizeof(unsigned long long));     // work counters
     b += align_up(n * sizeof(int32_t));                  // candidate list
-    b += align_up((size_t)std::max<uint32_t>(g->items, 1) * sizeof(int32_t));  // item list
+    // item list of the sparse step (the forward pass's items)
+    b += align_up((size_t)std::max<uint32_t>(g->items_in, 1) * sizeof(int32_t));
     b += align_up((size_t)kFrontSets * kFrontWaves * 2 * sizeof(unsigned long long));
     b += align_up(((n + 15) / 16) * 16);                 // candidate marks
     return b;
@@ -608,10 +618,15 @@ bc_status batch_ws_create(bc_graph_s *g, BatchWS **out) {
     d.items = g->items;
     d.item_info = g->d_item_info;
     d.item_first = g->d_item_first;
+    d.items_in = g->items_in;
+    d.row_ptr_in = g->d_row_ptr_in;
+    d.col_idx_in = g->d_col_idx_in;
+    d.item_info_in = g->d_item_info_in;
+    d.item_first_in = g->d_item_first_in;
     ws->d_stats = (unsigned long long *)take(12 * sizeof(unsigned long long));
     d.stats = nullptr;
     d.clist = (int32_t *)take(n * sizeof(int32_t));
-    d.ilist = (int32_t *)take((size_t)std::max<uint32_t>(g->items, 1) * sizeof(int32_t));
+    d.ilist = (int32_t *)take((size_t)std::max<uint32_t>(g->items_in, 1) * sizeof(int32_t));
     d.cand = (uint8_t *)take(((n + 15) / 16) * 16);
     d.front = (unsigned long long *)take((size_t)kFrontSets * kFrontWaves * 2 *
                                          sizeof(unsigned long long));
@@ -998,6 +1013,11 @@ bc_status fused_reserve(bc_graph_s *g, int32_t cap, int32_t lcap) {
         d.items = g->items;
         d.item_info = g->d_item_info;
         d.item_first = g->d_item_first;
+        d.items_in = g->items_in;
+        d.row_ptr_in = g->d_row_ptr_in;
+        d.col_idx_in = g->d_col_idx_in;
+        d.item_info_in = g->d_item_info_in;
+        d.item_first_in = g->d_item_first_in;
         d.iperm = g->d_iperm;
         d.nnz = g->nnz;
         d.lcap = lcap;
@@ -1218,7 +1238,7 @@ bc_status batched_run(bc_graph_s *g, const int32_t *sources, int32_t k, double *
     // the same result up to rounding; the order depends only on the inputs.
     std::vector<int32_t> order((size_t)k);
     for (int32_t i = 0; i < k; ++i) order[(size_t)i] = i;
-    if (k > width) {
+    if (k > width && !g->directed) {  // the landmarks' BFS runs undirected
         bc_status st = ensure_landmarks(g);
         if (st != BC_OK) return st;
         const uint32_t far = 0x7fffffff;
@@ -1381,7 +1401,8 @@ void plain_overflowed(bc_graph_s *g) {
 }
 
 bool use_batched(const bc_graph_s *g, const bc_options *opt, int32_t k) {
-    if (g->sigma_ext.load()) return true;  // only the batched path has the extended range
+    // only the batched path has the extended range and directed graphs
+    if (g->sigma_ext.load() || g->directed) return true;
     const int32_t mode = opt ? opt->mode : BC_MODE_AUTO;
     if (mode == BC_MODE_BATCHED) return true;
     if (mode == BC_MODE_PLAIN) return false;
@@ -1450,6 +1471,29 @@ bc_status validate_csr(int32_t n, const int32_t *row_ptr, const int32_t *col_idx
     return BC_OK;
 }
 
+// The graph's device arrays (the reversed CSR and its items only when they
+// are arrays of their own, i.e. for a directed graph).
+void free_graph_arrays(bc_graph_s *g) {
+    if (g->directed) {
+        if (g->d_row_ptr_in) (void)hipFree(g->d_row_ptr_in);
+        if (g->d_col_idx_in) (void)hipFree(g->d_col_idx_in);
+        if (g->d_item_info_in) (void)hipFree(g->d_item_info_in);
+        if (g->d_item_first_in) (void)hipFree(g->d_item_first_in);
+    }
+    g->d_row_ptr_in = g->d_col_idx_in = nullptr;
+    g->d_item_info_in = nullptr;
+    g->d_item_first_in = nullptr;
+    if (g->d_row_ptr) (void)hipFree(g->d_row_ptr);
+    if (g->d_col_idx) (void)hipFree(g->d_col_idx);
+    if (g->d_perm) (void)hipFree(g->d_perm);
+    if (g->d_iperm) (void)hipFree(g->d_iperm);
+    if (g->d_item_info) (void)hipFree(g->d_item_info);
+    if (g->d_item_first) (void)hipFree(g->d_item_first);
+    g->d_row_ptr = g->d_col_idx = g->d_perm = g->d_iperm = nullptr;
+    g->d_item_info = nullptr;
+    g->d_item_first = nullptr;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1470,12 +1514,16 @@ const char *bc_status_str(bc_status s) {
 bc_status bc_create_graph(int32_t n, const int32_t *row_ptr, const int32_t *col_idx,
                           uint32_t flags, void *stream, bc_graph_t *out) {
     if (!out || n < 0 || !row_ptr) return BC_ERR_INVALID_ARG;
-    if (flags & ~(uint32_t)(BC_GRAPH_TRUST_SYMMETRIC | BC_GRAPH_INPUT_ON_DEVICE))
+    if (flags & ~(uint32_t)(BC_GRAPH_TRUST_SYMMETRIC | BC_GRAPH_INPUT_ON_DEVICE |
+                            BC_GRAPH_DIRECTED))
         return BC_ERR_INVALID_ARG;
     const bool on_device = (flags & BC_GRAPH_INPUT_ON_DEVICE) != 0;
+    const bool directed = (flags & BC_GRAPH_DIRECTED) != 0;
+    const bool check_sym = !(flags & (BC_GRAPH_TRUST_SYMMETRIC | BC_GRAPH_DIRECTED));
     hipStream_t st = (hipStream_t)stream;
-    std::vector<int32_t> h_rp;
+    std::vector<int32_t> h_rp, h_ci;
     const int32_t *rp_host = row_ptr;
+    const int32_t *ci_host = col_idx;
     if (on_device) {
         h_rp.resize((size_t)n + 1);
         BC_TRY_HIP(hipMemcpy(h_rp.data(), row_ptr, ((size_t)n + 1) * sizeof(int32_t),
@@ -1487,19 +1535,38 @@ bc_status bc_create_graph(int32_t n, const int32_t *row_ptr, const int32_t *col_
         // the neighbour ids are checked on the host too: the relabelling
         // kernel indexes with them
         if (rp_host[n] > 0 && !col_idx) return BC_ERR_INVALID_ARG;
-        std::vector<int32_t> h_ci((size_t)rp_host[n]);
+        h_ci.resize((size_t)rp_host[n]);
         if (rp_host[n] > 0)
             BC_TRY_HIP(hipMemcpy(h_ci.data(), col_idx, (size_t)rp_host[n] * sizeof(int32_t),
                                  hipMemcpyDeviceToHost));
-        bc_status vs = validate_csr(n, rp_host, h_ci.data(), !(flags & BC_GRAPH_TRUST_SYMMETRIC));
+        ci_host = h_ci.data();
+        bc_status vs = validate_csr(n, rp_host, ci_host, check_sym);
         if (vs != BC_OK) return vs;
     } else {
         if (n > 0 && row_ptr[n] > 0 && !col_idx) return BC_ERR_INVALID_ARG;
-        bc_status vs = validate_csr(n, row_ptr, col_idx, !(flags & BC_GRAPH_TRUST_SYMMETRIC));
+        bc_status vs = validate_csr(n, row_ptr, col_idx, check_sym);
         if (vs != BC_OK) return vs;
     }
     const int64_t nnz = rp_host[n];
     if (nnz > 0 && !col_idx) return BC_ERR_INVALID_ARG;
+
+    // directed: the arcs into each vertex (caller ids), by counting sort
+    std::vector<int32_t> in_rp, in_ci;
+    if (directed) {
+        in_rp.assign((size_t)n + 1, 0);
+        for (int64_t e = 0; e < nnz; ++e) in_rp[(size_t)ci_host[e] + 1]++;
+        for (int32_t v = 0; v < n; ++v) in_rp[(size_t)v + 1] += in_rp[(size_t)v];
+        in_ci.resize((size_t)std::max<int64_t>(nnz, 1));
+        std::vector<int32_t> cur(in_rp.begin(), in_rp.end() - 1);
+        for (int32_t u = 0; u < n; ++u)
+            for (int32_t e = rp_host[u]; e < rp_host[u + 1]; ++e)
+                in_ci[(size_t)cur[(size_t)ci_host[e]]++] = u;
+    }
+    auto out_deg = [&](int32_t o) { return rp_host[o + 1] - rp_host[o]; };
+    auto in_deg = [&](int32_t o) { return directed ? in_rp[(size_t)o + 1] - in_rp[(size_t)o]
+                                                   : out_deg(o); };
+    // the order key: the degree, or for a directed graph the larger of the two
+    auto key_deg = [&](int32_t o) { return std::max(out_deg(o), in_deg(o)); };
 
     int device = 0;
     BC_TRY_HIP(hipGetDevice(&device));
@@ -1508,61 +1575,78 @@ bc_status bc_create_graph(int32_t n, const int32_t *row_ptr, const int32_t *col_
     g->device = device;
     g->n = n;
     g->nnz = nnz;
+    g->directed = directed;
 
-    // Internal order: degree descending, ties by caller id (counting sort).
+    // Internal order: key degree descending, ties by caller id (counting sort).
     int32_t maxdeg = 0;
-    for (int32_t v = 0; v < n; ++v) maxdeg = std::max(maxdeg, rp_host[v + 1] - rp_host[v]);
+    for (int32_t v = 0; v < n; ++v) maxdeg = std::max(maxdeg, key_deg(v));
     std::vector<int64_t> start((size_t)maxdeg + 2, 0);
-    for (int32_t v = 0; v < n; ++v) start[(size_t)(maxdeg - (rp_host[v + 1] - rp_host[v])) + 1]++;
+    for (int32_t v = 0; v < n; ++v) start[(size_t)(maxdeg - key_deg(v)) + 1]++;
     for (size_t i = 1; i < start.size(); ++i) start[i] += start[i - 1];
     std::vector<int32_t> iperm((size_t)std::max(n, 1));
     g->h_perm.assign((size_t)std::max(n, 1), 0);
     for (int32_t v = 0; v < n; ++v) {
-        const int32_t slot = (int32_t)start[(size_t)(maxdeg - (rp_host[v + 1] - rp_host[v]))]++;
+        const int32_t slot = (int32_t)start[(size_t)(maxdeg - key_deg(v))]++;
         iperm[(size_t)slot] = v;
         g->h_perm[(size_t)v] = slot;
     }
-    std::vector<int32_t> new_rp((size_t)n + 1, 0);
-    uint64_t chunks = 0;
+    std::vector<int32_t> new_rp((size_t)n + 1, 0), new_rp_in;
+    if (directed) new_rp_in.assign((size_t)n + 1, 0);
     for (int32_t u = 0; u < n; ++u) {
         const int32_t o = iperm[(size_t)u];
-        const int32_t dgr = rp_host[o + 1] - rp_host[o];
+        const int32_t dgr = out_deg(o);
         new_rp[(size_t)u + 1] = new_rp[(size_t)u] + dgr;
+        if (directed) new_rp_in[(size_t)u + 1] = new_rp_in[(size_t)u] + in_deg(o);
+        // one-source path buckets (id ranges; undirected graphs only run there,
+        // where the order makes them exact)
         const int b = degree_bucket(dgr);
-        if (b == 3) {
-            g->b3_end = u + 1;
-            chunks += chunks_of(dgr);
-        }
+        if (b == 3) g->b3_end = u + 1;
         if (b >= 2) g->b2_end = u + 1;
         if (b >= 1) g->b1_end = u + 1;
     }
+    uint64_t chunks = 0;
+    for (int32_t u = 0; u < g->b3_end; ++u) chunks += chunks_of(out_deg(iperm[(size_t)u]));
     g->total_chunks3 = chunks;
-    // batched work items: internal ids are degree-descending, so the vertices
-    // of degree > 64 (> kChunk) are a prefix
-    std::vector<int2> item_info;
-    std::vector<uint32_t> item_first;
+    // batched work items: internal ids are key-degree-descending, so the
+    // vertices of key degree > 64 (> kChunk) are a prefix; each of them has at
+    // least one item per direction
+    std::vector<int2> item_info, item_info_in;
+    std::vector<uint32_t> item_first, item_first_in;
     for (int32_t u = 0; u < n; ++u) {
         const int32_t o = iperm[(size_t)u];
-        const int32_t dgr = rp_host[o + 1] - rp_host[o];
-        if (dgr <= kB1MaxDeg) break;
+        if (key_deg(o) <= kB1MaxDeg) break;
         g->big_end = u + 1;
-        if (dgr > kChunk) g->multi_end = u + 1;
+        if (key_deg(o) > kChunk) g->multi_end = u + 1;
         item_first.push_back((uint32_t)item_info.size());
-        for (int32_t j = 0; j * kChunk < dgr; ++j) item_info.push_back(make_int2(u, j));
+        for (int32_t j = 0; j == 0 || j * kChunk < out_deg(o); ++j)
+            item_info.push_back(make_int2(u, j));
+        if (directed) {
+            item_first_in.push_back((uint32_t)item_info_in.size());
+            for (int32_t j = 0; j == 0 || j * kChunk < in_deg(o); ++j)
+                item_info_in.push_back(make_int2(u, j));
+        }
     }
     item_first.push_back((uint32_t)item_info.size());
+    if (directed) item_first_in.push_back((uint32_t)item_info_in.size());
     g->items = (uint32_t)item_info.size();
+    g->items_in = directed ? (uint32_t)item_info_in.size() : g->items;
 
     const size_t rp_bytes = ((size_t)n + 1) * sizeof(int32_t);
     const size_t ci_bytes = std::max<size_t>((size_t)nnz, 1) * sizeof(int32_t);
     const size_t pm_bytes = (size_t)std::max(n, 1) * sizeof(int32_t);
-    int32_t *t_rp = nullptr, *t_ci = nullptr;
+    int32_t *t_rp = nullptr, *t_ci = nullptr, *t_rp_in = nullptr, *t_ci_in = nullptr;
     hipError_t e = hipMalloc(&g->d_row_ptr, rp_bytes);
     if (e == hipSuccess) e = hipMalloc(&g->d_col_idx, ci_bytes);
     if (e == hipSuccess) e = hipMalloc(&g->d_perm, pm_bytes);
     if (e == hipSuccess) e = hipMalloc(&g->d_iperm, pm_bytes);
     if (e == hipSuccess && !on_device) e = hipMalloc(&t_rp, rp_bytes);
     if (e == hipSuccess && !on_device) e = hipMalloc(&t_ci, ci_bytes);
+    if (directed) {
+        if (e == hipSuccess) e = hipMalloc(&g->d_row_ptr_in, rp_bytes);
+        if (e == hipSuccess) e = hipMalloc(&g->d_col_idx_in, ci_bytes);
+        if (e == hipSuccess) e = hipMalloc(&t_rp_in, rp_bytes);
+        if (e == hipSuccess) e = hipMalloc(&t_ci_in, ci_bytes);
+    }
     const int32_t *old_rp = on_device ? row_ptr : t_rp;
     const int32_t *old_ci = on_device ? col_idx : t_ci;
     if (e == hipSuccess && !on_device)
@@ -1578,30 +1662,50 @@ bc_status bc_create_graph(int32_t n, const int32_t *row_ptr, const int32_t *col_
     if (e == hipSuccess)
         e = relabel_csr(n, nnz, old_rp, old_ci, g->d_row_ptr, g->d_perm, g->d_iperm, g->d_col_idx,
                         st);
-    if (e == hipSuccess)
-        e = hipMalloc(&g->d_item_info, std::max<size_t>(item_info.size(), 1) * sizeof(int2));
-    if (e == hipSuccess)
-        e = hipMalloc(&g->d_item_first, item_first.size() * sizeof(uint32_t));
-    if (e == hipSuccess && !item_info.empty())
-        e = hipMemcpyAsync(g->d_item_info, item_info.data(), item_info.size() * sizeof(int2),
-                           hipMemcpyHostToDevice, st);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(g->d_item_first, item_first.data(),
-                           item_first.size() * sizeof(uint32_t), hipMemcpyHostToDevice, st);
+    if (directed) {
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(t_rp_in, in_rp.data(), rp_bytes, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess && nnz > 0)
+            e = hipMemcpyAsync(t_ci_in, in_ci.data(), (size_t)nnz * sizeof(int32_t),
+                               hipMemcpyHostToDevice, st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(g->d_row_ptr_in, new_rp_in.data(), rp_bytes, hipMemcpyHostToDevice,
+                               st);
+        if (e == hipSuccess)
+            e = relabel_csr(n, nnz, t_rp_in, t_ci_in, g->d_row_ptr_in, g->d_perm, g->d_iperm,
+                            g->d_col_idx_in, st);
+    }
+    auto upload_items = [&](const std::vector<int2> &info, const std::vector<uint32_t> &first,
+                            int2 **d_info, uint32_t **d_first) {
+        if (e == hipSuccess)
+            e = hipMalloc(d_info, std::max<size_t>(info.size(), 1) * sizeof(int2));
+        if (e == hipSuccess) e = hipMalloc(d_first, first.size() * sizeof(uint32_t));
+        if (e == hipSuccess && !info.empty())
+            e = hipMemcpyAsync(*d_info, info.data(), info.size() * sizeof(int2),
+                               hipMemcpyHostToDevice, st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(*d_first, first.data(), first.size() * sizeof(uint32_t),
+                               hipMemcpyHostToDevice, st);
+    };
+    upload_items(item_info, item_first, &g->d_item_info, &g->d_item_first);
+    if (directed) upload_items(item_info_in, item_first_in, &g->d_item_info_in, &g->d_item_first_in);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (t_rp) (void)hipFree(t_rp);
     if (t_ci) (void)hipFree(t_ci);
+    if (t_rp_in) (void)hipFree(t_rp_in);
+    if (t_ci_in) (void)hipFree(t_ci_in);
+    if (!directed) {  // the forward pass reads the same arrays
+        g->d_row_ptr_in = g->d_row_ptr;
+        g->d_col_idx_in = g->d_col_idx;
+        g->d_item_info_in = g->d_item_info;
+        g->d_item_first_in = g->d_item_first;
+    }
     if (e != hipSuccess) {
-        if (g->d_row_ptr) (void)hipFree(g->d_row_ptr);
-        if (g->d_col_idx) (void)hipFree(g->d_col_idx);
-        if (g->d_perm) (void)hipFree(g->d_perm);
-        if (g->d_iperm) (void)hipFree(g->d_iperm);
-        if (g->d_item_info) (void)hipFree(g->d_item_info);
-        if (g->d_item_first) (void)hipFree(g->d_item_first);
+        free_graph_arrays(g);
         delete g;
         return from_hip(e);
     }
-    g->device_bytes = rp_bytes + ci_bytes + 2 * pm_bytes;
+    g->device_bytes = (directed ? 2 : 1) * (rp_bytes + ci_bytes) + 2 * pm_bytes;
     *out = g;
     return BC_OK;
 }
@@ -1616,12 +1720,7 @@ bc_status bc_destroy_graph(bc_graph_t g) {
     fused_release(g);
     for (BatchWS *ws : g->batch_pool) batch_ws_destroy(ws);
     g->batch_pool.clear();
-    if (g->d_row_ptr) (void)hipFree(g->d_row_ptr);
-    if (g->d_col_idx) (void)hipFree(g->d_col_idx);
-    if (g->d_perm) (void)hipFree(g->d_perm);
-    if (g->d_iperm) (void)hipFree(g->d_iperm);
-    if (g->d_item_info) (void)hipFree(g->d_item_info);
-    if (g->d_item_first) (void)hipFree(g->d_item_first);
+    free_graph_arrays(g);
     delete g;
     return BC_OK;
 }
@@ -1705,7 +1804,7 @@ bc_status bc_run_detail(bc_graph_t g, const int32_t *sources, int32_t k, const b
         exp[i].dist = d_dist ? d_dist + (size_t)i * n : nullptr;
         exp[i].sigma = d_sigma ? d_sigma + (size_t)i * n : nullptr;
     }
-    const bool batched = !opt || opt->mode != BC_MODE_PLAIN || g->sigma_ext.load();
+    const bool batched = !opt || opt->mode != BC_MODE_PLAIN || g->sigma_ext.load() || g->directed;
     ExportAlloc tmp;
     if (!batched && (dist || sigma) && (e = tmp.alloc(n)) != hipSuccess) {
         (void)hipFree(d_bc);
@@ -1757,6 +1856,7 @@ bc_status bc_single_source(bc_graph_t g, int32_t s, int32_t *dist, double *sigma
                            double *delta) {
     if (!g || ((!dist || !sigma) && g->n > 0)) return BC_ERR_INVALID_ARG;
     if (s < 0 || s >= g->n) return BC_ERR_INVALID_ARG;
+    if (g->directed) return BC_ERR_UNSUPPORTED;  // the one-source path is undirected
     DeviceGuard dg(g->device);
     const size_t n = (size_t)g->n;
     double *d_bc = nullptr, *d_sigma = nullptr, *d_delta = nullptr;
@@ -1923,9 +2023,10 @@ bc_status bc_autotune(bc_graph_t g, const int32_t *sources, int32_t k, void *str
         }
     }
     // one-source-at-a-time path on up to 4 sources
-    double plain_ms = 0;
+    // (none for a directed graph, which always takes the batched path)
+    double plain_ms = 1e30;
     const int32_t p = std::min(m, 4);
-    if (st == BC_OK)
+    if (st == BC_OK && !g->directed)
         st = timed([&]() { return plain_run(g, sources, p, d_bc, nullptr, stream, nullptr,
                                             nullptr); }, plain_ms);
     cleanup();

@@ -80,7 +80,9 @@ struct PlainDev {
 // Device view of one batched workspace (up to 64 sources, one per lane).
 // Vertices [0, big_end) (degree > 64) are processed as chunk items of kChunk
 // arcs; of those, [0, multi_end) (degree > kChunk) span several items.
-// item_info[i] = (vertex, chunk index); item_first[v] = first item of v.
+// item_info[i] = (vertex, chunk index); item_first[v] = first item of v.  For
+// a directed graph the degree is the larger of the in- and out-degree, and a
+// vertex below big_end has at least one item in either direction.
 constexpr int kChunk = 512;
 // Default threshold of the batched forward step: a level whose frontier has
 // fewer than nnz / kDefaultSparseDiv arcs expands from the frontier.
@@ -97,6 +99,14 @@ struct BatchDev {
     const int32_t *col_idx;
     const int2 *item_info;
     const uint32_t *item_first;  // [big_end + 1]
+    // The forward pass pulls over the arcs into each vertex: for a directed
+    // graph the reversed CSR and its own chunk items, for an undirected one
+    // the same arrays as above.
+    uint32_t items_in;
+    const int32_t *row_ptr_in;
+    const int32_t *col_idx_in;
+    const int2 *item_info_in;
+    const uint32_t *item_first_in;
     uint64_t *vis;         // [n] sources that reached v
     uint64_t *F;           // [lcap][n] F[L][v]: sources at distance L from v
     double *sigma;         // [n][64] path counts as doubles (wide rows)

@@ -134,3 +134,12 @@ def test_device_code_makes_no_calls(tmp_path):
         assert "s_swappc" not in asm and "s_setpc" not in asm
         kernels += asm.count("s_endpgm")
     assert kernels > 0
+
+
+def test_directed_flag_keeps_structure_checks():
+    # a directed CSR need not be symmetric, but its structure is still checked
+    # before any device call
+    st, _ = _create(2, [0, 1, 2], [1, 5], flags=bcm.BC_GRAPH_DIRECTED)
+    assert st == bcm.BC_ERR_INVALID_GRAPH
+    st, _ = _create(2, [0, 2, 1], [1, 0], flags=bcm.BC_GRAPH_DIRECTED)
+    assert st == bcm.BC_ERR_INVALID_GRAPH
