@@ -59,6 +59,9 @@ def _load():
     lib.gg_csr_from_edges.restype = ctypes.c_int64
     lib.gg_csr_from_edges.argtypes = [ctypes.c_int32, ctypes.c_int64, i32p, i32p, ctypes.c_int,
                                       ctypes.c_int, ctypes.c_int, i32p, i32p]
+    lib.gg_edge_weights.restype = None
+    lib.gg_edge_weights.argtypes = [ctypes.c_int32, i32p, i32p, ctypes.c_uint64, ctypes.c_int32,
+                                    ctypes.c_int32, ctypes.c_int, i32p]
     lib.gg_sample_without_replacement.restype = None
     lib.gg_sample_without_replacement.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_uint64,
                                                   i64p]
@@ -164,6 +167,17 @@ def grid_road(rows: int, cols: int, remove_frac: float = 0.05, shortcut_frac: fl
                           name=f"grid-{rows}x{cols}",
                           params=dict(kind="grid", rows=rows, cols=cols, remove_frac=remove_frac,
                                       shortcut_frac=shortcut_frac, shortcuts=n_short, seed=seed))
+
+
+def edge_weights(g: CSR, seed: int, lo: int = 1, hi: int = 100) -> np.ndarray:
+    """int32 weights in [lo, hi] for g's arcs (CSR order), uniform per edge: the two
+    arcs of an undirected edge get the same weight; a directed graph's arcs are
+    drawn independently."""
+    lib = _load()
+    w = np.empty(max(g.nnz, 1), dtype=np.int32)
+    lib.gg_edge_weights(g.n, _p32(g.row_ptr), _p32(g.col_idx), seed, lo, hi,
+                        0 if g.params.get("directed") else 1, _p32(w))
+    return w[:g.nnz]
 
 
 def sample_sources(g: CSR, k: int, seed: int, min_degree: int = 1) -> np.ndarray:

@@ -211,3 +211,24 @@ void gg_sample_without_replacement(int64_t count, int64_t k, uint64_t seed, int6
     }
     free(idx);
 }
+
+/* Arc weights in [lo, hi] (stream 14), for the CSR's arcs in order.  With
+ * symmetric != 0 the weight of arc u->v is drawn from the unordered pair
+ * {u, v} (index min*n + max), so both arcs of an undirected edge agree;
+ * otherwise from the arc (u*n + v). */
+void gg_edge_weights(int32_t n, const int32_t *row_ptr, const int32_t *col_idx, uint64_t seed,
+                     int32_t lo, int32_t hi, int symmetric, int32_t *w) {
+    const uint64_t key = stream_key(seed, 14);
+    const uint64_t span = (uint64_t)(hi - lo + 1);
+    for (int32_t u = 0; u < n; ++u) {
+        for (int32_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) {
+            const int32_t v = col_idx[e];
+            uint64_t a = (uint64_t)u, b = (uint64_t)v;
+            if (symmetric && b < a) {
+                a = (uint64_t)v;
+                b = (uint64_t)u;
+            }
+            w[e] = lo + (int32_t)(ctr_draw(key, a * (uint64_t)n + b) % span);
+        }
+    }
+}

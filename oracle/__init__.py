@@ -18,7 +18,9 @@ chains of diamonds whose path counts pass double's range, to exact big-integer
 counts on deep grids, and to the double oracle wherever counts fit double.
 The directed entry points (``directed=True``) are pinned to closed forms on
 directed paths, cycles and stars, brute force on random digraphs, NetworkX's
-directed betweenness and the undirected oracle on symmetric graphs.
+directed betweenness and the undirected oracle on symmetric graphs.  ``sssp``
+(the paper's weighted single-source shortest paths) is pinned to scipy's
+Dijkstra, to hop distances with unit weights and to prefix sums on paths.
 """
 from __future__ import annotations
 
@@ -77,6 +79,9 @@ def _load():
     lib.oracle_single_source_directed.argtypes = lib.oracle_single_source.argtypes
     lib.oracle_bc_directed.restype = ctypes.c_int
     lib.oracle_bc_directed.argtypes = lib.oracle_bc.argtypes
+    lib.oracle_sssp.restype = ctypes.c_int64
+    lib.oracle_sssp.argtypes = [ctypes.c_int32, i32p, i32p, i32p, ctypes.c_int32,
+                                ctypes.POINTER(ctypes.c_int64)]
     lib.oracle_ld_digits.restype = ctypes.c_int
     lib.oracle_ld_digits.argtypes = []
     lib.oracle_single_source_ext.restype = ctypes.c_int
@@ -173,3 +178,19 @@ def bc_ext(row_ptr, col_idx, sources, threads: int = 0):
     if st == INVALID_ARG:
         raise OracleError("invalid argument")
     return out, st
+
+
+def sssp(row_ptr, col_idx, weight, s: int):
+    """(dist int64[n] with -1 where unreachable, passes): the paper's fixed-point
+    SSSP from s over weighted out-arcs (weight[e] for arc e, non-negative)."""
+    lib = _load()
+    rp, rpp = _i32(row_ptr)
+    ci, cip = _i32(col_idx)
+    w, wp = _i32(weight)
+    n = rp.shape[0] - 1
+    dist = np.empty(n, dtype=np.int64)
+    passes = lib.oracle_sssp(n, rpp, cip, wp if w.size else None, int(s),
+                             dist.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
+    if passes < 0:
+        raise OracleError("invalid argument")
+    return dist, int(passes)

@@ -40,7 +40,8 @@
  *
  * Status codes: 0 = ok, 1 = invalid argument, 4 = some sigma is not finite
  * (BC is then written but meaningless).  The *_ext entry points at the end
- * run the same steps in long double for path counts beyond double's range.
+ * run the same steps in long double for path counts beyond double's range;
+ * oracle_sssp is the paper's weighted single-source shortest paths.
  *
  * Built with gcc -O2, no fast-math.
  */
@@ -234,6 +235,60 @@ int oracle_bc(int32_t n, const int32_t *row_ptr, const int32_t *col_idx, const i
 int oracle_bc_directed(int32_t n, const int32_t *row_ptr, const int32_t *col_idx,
                        const int32_t *sources, int32_t k, int threads, double *bc) {
     return run_bc(n, row_ptr, col_idx, sources, k, threads, 1, bc);
+}
+
+/* ---- single-source shortest paths ---------------------------------------------
+ *
+ * The paper's SSSP (Sections "fixedPoint Construct" and "Min/Max
+ * Constructs"): dist = infinity everywhere but dist[src] = 0, modified[src] =
+ * true; a fixed-point loop runs while some vertex is modified.  Each pass visits
+ * the modified vertices v (in id order) and, for each out-arc (v, nbr) of weight
+ * w, applies <nbr.dist, nbr.modified_next> = <Min(nbr.dist, v.dist + w), true>
+ * (both only when the new distance is smaller); then modified = modified_next
+ * and modified_next is cleared.  Distances are updated in place, as in the
+ * generated code.  Weights are non-negative integers; distances are 64-bit.
+ * dist[v] = -1 where v is unreachable.  Returns the number of passes (>= 1),
+ * or -1 for invalid arguments (a negative weight included). */
+int64_t oracle_sssp(int32_t n, const int32_t *row_ptr, const int32_t *col_idx,
+                    const int32_t *weight, int32_t s, int64_t *dist) {
+    if (check_graph_args(n, row_ptr, col_idx) != OR_OK || s < 0 || s >= n || !dist ||
+        (row_ptr[n] > 0 && !weight))
+        return -1;
+    for (int64_t e = 0; e < row_ptr[n]; ++e)
+        if (weight[e] < 0) return -1;
+    const int64_t inf = INT64_MAX;
+    char *modified = (char *)calloc((size_t)n, 1);
+    char *modified_next = (char *)calloc((size_t)n, 1);
+    for (int32_t v = 0; v < n; ++v) dist[v] = inf;
+    dist[s] = 0;
+    modified[s] = 1;
+    int64_t passes = 0;
+    int finished = 0;
+    while (!finished) {
+        finished = 1;
+        ++passes;
+        for (int32_t v = 0; v < n; ++v) {
+            if (!modified[v]) continue;
+            for (int32_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {
+                int32_t nbr = col_idx[e];
+                int64_t dist_new = dist[v] + weight[e];
+                if (dist[nbr] > dist_new) {
+                    dist[nbr] = dist_new;
+                    modified_next[nbr] = 1;
+                    finished = 0;
+                }
+            }
+        }
+        char *t = modified;
+        modified = modified_next;
+        modified_next = t;
+        memset(modified_next, 0, (size_t)n);
+    }
+    for (int32_t v = 0; v < n; ++v)
+        if (dist[v] == inf) dist[v] = -1;
+    free(modified);
+    free(modified_next);
+    return passes;
 }
 
 /* ---- extended range --------------------------------------------------------

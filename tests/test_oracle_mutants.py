@@ -11,6 +11,7 @@ import subprocess
 import numpy as np
 import pytest
 
+import graphgen as gg
 import oracle
 from tests import test_oracle_pins as pins
 
@@ -126,6 +127,33 @@ def test_directed_mutant_is_caught(name, swap_oracle):
     swap_oracle(_mutate(open(SRC).read(), before, after, ext=False))
     with pytest.raises(AssertionError):
         _directed_pin_suite()
+
+
+SSSP_MUTANTS = {
+    "sssp-unit-weights": ("int64_t dist_new = dist[v] + weight[e];",
+                          "int64_t dist_new = dist[v] + 1;"),
+    "sssp-single-pass": ("                    finished = 0;\n", ""),
+    "sssp-forgets-next": ("                    modified_next[nbr] = 1;\n", ""),
+}
+
+
+def _sssp_pin_suite():
+    for g in (gg.rmat(12, 8, seed=1), gg.grid_road(64, 64, seed=2)):
+        pins.test_sssp_matches_dijkstra(g)
+    pins.test_sssp_path_prefix_sums_and_zero_weights()
+
+
+def test_unmutated_copy_passes_sssp_pins(swap_oracle):
+    swap_oracle(open(SRC).read())
+    _sssp_pin_suite()
+
+
+@pytest.mark.parametrize("name", sorted(SSSP_MUTANTS))
+def test_sssp_mutant_is_caught(name, swap_oracle):
+    before, after = SSSP_MUTANTS[name]
+    swap_oracle(_mutate(open(SRC).read(), before, after, ext=False))
+    with pytest.raises(AssertionError):
+        _sssp_pin_suite()
 
 
 def _ext_pin_suite():

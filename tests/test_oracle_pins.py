@@ -541,3 +541,65 @@ def test_directed_sum_invariant():
     want = float(np.where(np.isfinite(d) & (d > 0), d - 1, 0).sum())
     got = dir_bc(g, src).sum()
     assert abs(got - want) <= 1e-10 * want
+
+
+# ---------------------------------------------------------------------------
+# Single-source shortest paths (weighted)
+# ---------------------------------------------------------------------------
+
+def dijkstra(g, w, s):
+    """scipy's Dijkstra on the weighted CSR (an independent method); -1 unreachable."""
+    from scipy.sparse.csgraph import dijkstra as sp_dijkstra
+    # csr_matrix would add parallel arcs' weights: keep the lightest arc of each pair
+    u = np.repeat(np.arange(g.n), np.diff(g.row_ptr))
+    order = np.lexsort((w, g.col_idx, u))
+    u, v, ww = u[order], g.col_idx[order], w[order]
+    first = np.ones(len(u), bool)
+    first[1:] = (u[1:] != u[:-1]) | (v[1:] != v[:-1])
+    m = sp.csr_matrix((ww[first].astype(np.float64), (u[first], v[first])), shape=(g.n, g.n))
+    d = sp_dijkstra(m, directed=True, indices=[s])[0]
+    return np.where(np.isinf(d), -1, d).astype(np.int64)
+
+
+@pytest.mark.parametrize("g", [gg.rmat(12, 8, seed=1), gg.grid_road(64, 64, seed=2),
+                               gg.rmat(11, 8, seed=4, directed=True),
+                               gg.gnp_directed(80, 0.03, seed=5)], ids=lambda g: g.name)
+def test_sssp_matches_dijkstra(g):
+    w = gg.edge_weights(g, seed=7)
+    for s in gg.sample_sources(g, 6, seed=8):
+        d, passes = oracle.sssp(g.row_ptr, g.col_idx, w, int(s))
+        assert np.array_equal(d, dijkstra(g, w, int(s)))
+        assert passes >= 1
+
+
+def test_sssp_unit_weights_are_hop_distances():
+    g = gg.rmat(12, 8, seed=2)
+    w = np.ones(g.nnz, dtype=np.int32)
+    for s in gg.sample_sources(g, 4, seed=3):
+        d, _ = oracle.sssp(g.row_ptr, g.col_idx, w, int(s))
+        assert np.array_equal(d, hop_distances(g, int(s)))
+
+
+def test_sssp_path_prefix_sums_and_zero_weights():
+    """Weighted path: dist(i) = sum of the first i weights; zero weights allowed;
+    an unreachable vertex gives -1; a directed path is one-way."""
+    n = 40
+    rng = np.random.default_rng(1)
+    wts = rng.integers(0, 100, n - 1).astype(np.int32)
+    g = gg.path(n)
+    w = np.empty(g.nnz, np.int32)
+    for u in range(n):
+        for e in range(g.row_ptr[u], g.row_ptr[u + 1]):
+            w[e] = wts[min(u, g.col_idx[e])]
+    d, _ = oracle.sssp(g.row_ptr, g.col_idx, w, 0)
+    assert np.array_equal(d, np.concatenate([[0], np.cumsum(wts)]))
+    dp = gg.directed(n + 1, [(i, i + 1) for i in range(n - 1)], "dpath")
+    d, _ = oracle.sssp(dp.row_ptr, dp.col_idx, wts, 5)
+    assert np.all(d[:5] == -1) and d[n] == -1
+    assert np.array_equal(d[5:n], np.concatenate([[0], np.cumsum(wts[5:n - 1])]))
+
+
+def test_sssp_rejects_negative_weights():
+    g = gg.path(3)
+    with pytest.raises(oracle.OracleError):
+        oracle.sssp(g.row_ptr, g.col_idx, np.array([1, -1, 1, 1], np.int32), 0)
