@@ -49,6 +49,11 @@ BYTES = {
     ("batched", "forward"): {"owners": 8, "arcs": 12, "hits": 8},
     ("batched", "reverse"): {"owners": 16, "arcs": 12, "hits": 8},
 }
+# sssp pass kernel: per pass, the stamp of every vertex 4; per vertex whose
+# arcs are relaxed: row_ptr pair 8 + its distance 4; per arc relaxed:
+# neighbour id 4 + weight 4 + neighbour distance 4; per improvement: atomic
+# min 4 + stamp write 4.
+SSSP_BYTES = {"vertex": 4, "owners": 12, "arcs": 12, "hits": 8}
 KERNELS = {
     ("plain", "forward"): "k_level_forward", ("plain", "reverse"): "k_level_reverse",
     ("batched", "forward"): "k_batch_forward", ("batched", "reverse"): "k_batch_reverse",
@@ -278,6 +283,92 @@ def serving_bench(args) -> int:
     return 0
 
 
+def sssp_bench(args) -> int:
+    """SSSP workload: the scale-22 R-MAT with weights in [1, 100] (seed 3); a step
+    is one shortest-path run from each of --sssp-sources sampled sources.
+    GTEPS = sources x arcs / time (the BC metric's convention)."""
+    import numpy as np
+    import torch
+
+    import graphgen as gg
+    import oracle
+    import paper_2401_02472_amd as bcm
+
+    torch.cuda.set_device(0)
+    bcm.load_library()
+    g, _ = gg.workload("rmat-s22-ef16")
+    w = gg.edge_weights(g, seed=3)
+    sources = gg.sample_sources(g, args.sssp_sources, seed=103)
+    G = bcm.Graph(g.n, g.row_ptr, g.col_idx, flags=bcm.BC_GRAPH_TRUST_SYMMETRIC)
+    G.set_weights(w)
+    out = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        for s in sources:
+            G.sssp(int(s), out)
+    torch.cuda.synchronize()
+    G.profile_enable(1)
+    G.profile_read(reset=True)
+    step_ms = []
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        start.record(stream)
+        for s in sources:
+            G.sssp(int(s), out)
+        stop.record(stream)
+        stop.synchronize()
+        step_ms.append(start.elapsed_time(stop))
+    wall = time.perf_counter() - t0
+    prof = G.profile_read(reset=True)
+    G.profile_enable(False)
+    ms_per_step = wall * 1e3 / args.steps
+    value = len(sources) * g.nnz / (ms_per_step / 1e3) / 1e9
+    pc = prof["sssp"]
+    launches = max(pc["launches"], 1)
+    alg = (SSSP_BYTES["vertex"] * g.n * pc["launches"] + SSSP_BYTES["owners"] * pc["owners"] +
+           SSSP_BYTES["arcs"] * pc["arcs"] + SSSP_BYTES["hits"] * pc["hits"]) / launches
+    avg_ms = pc["ms"] / launches
+    achieved = alg / (avg_ms / 1e3) / 1e9 if avg_ms > 0 else 0.0
+    src_hash = kernel_source_hash()
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": read_traffic("k_sssp_pass", "sssp-rmat-s22-ef16", src_hash),
+            "kernel": "k_sssp_pass", "alg_bytes_per_launch": int(alg),
+            "avg_launch_ms": round(avg_ms, 5), "launches": pc["launches"],
+            "passes_per_source": round(pc["launches"] / (args.steps * len(sources)), 2),
+            "kernel_source_hash": src_hash}
+    # the oracle (one thread: the fixed-point passes are sequential) on a prefix
+    cpu = None
+    if args.cpu_seconds > 0:
+        t = time.perf_counter()
+        m = 0
+        for s in sources:
+            oracle.sssp(g.row_ptr, g.col_idx, w, int(s))
+            m += 1
+            if time.perf_counter() - t > args.cpu_seconds:
+                break
+        dt = time.perf_counter() - t
+        cpu = {"value": round(m * g.nnz / dt / 1e9, 4), "unit": "GTEPS", "cores": 1,
+               "kind": "oracle", "sample": f"first {m} of the {len(sources)} sources, "
+                                           f"{dt:.2f} s on one thread"}
+    q = np.percentile(step_ms, [50, 99])
+    rec = {
+        "metric": "SSSP GTEPS (sources x arcs / s); HBM roofline", "value": round(value, 3),
+        "unit": "GTEPS", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+        "config": {"workload": "sssp-rmat-s22-ef16", "n": g.n, "nnz": g.nnz,
+                   "sources": len(sources), "weights": "uniform [1, 100] per edge, seed 3",
+                   "graph": g.params},
+        "p50_ms": round(float(q[0]), 3), "p99_ms": round(float(q[1]), 3),
+        "roofline": roof, "cpu_baseline": cpu,
+    }
+    print(json.dumps(rec), flush=True)
+    G.close()
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -313,6 +404,8 @@ def main() -> int:
     ap.add_argument("--serving-load", type=float, default=0.8)
     ap.add_argument("--serving-seed", type=int, default=105)
     ap.add_argument("--serving-cpu-sample", type=int, default=12)
+    ap.add_argument("--sssp-sources", type=int, default=16,
+                    help="sssp-rmat-s22-ef16: sources per step")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -332,6 +425,8 @@ def main() -> int:
         return 2
     if args.workload == "serving-mix":
         return serving_bench(args)
+    if args.workload == "sssp-rmat-s22-ef16":
+        return sssp_bench(args)
     torch.cuda.set_device(0)
     bcm.load_library()
 

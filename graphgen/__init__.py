@@ -305,14 +305,14 @@ def gnp_directed(n: int, p: float, seed: int) -> CSR:
                 idx += 1
     return csr_from_edges(n, np.array(u, np.int64), np.array(v, np.int64), symmetrize=False,
                           name=f"dgnp-{n}-{p}", params=dict(kind="gnp_directed", n=n, p=p,
-                                                             seed=seed))
+                                                             seed=seed, directed=True))
 
 
 def directed(n: int, pairs, name: str) -> CSR:
     """Directed graph from (u, v) arc pairs (duplicates and self-loops removed)."""
     pairs = np.asarray(pairs, dtype=np.int64).reshape(-1, 2)
     return csr_from_edges(n, pairs[:, 0], pairs[:, 1], symmetrize=False, name=name,
-                          params=dict(kind="directed", n=n))
+                          params=dict(kind="directed", n=n, directed=True))
 
 
 def from_adjacency_bits(n: int, bits: int) -> CSR:

@@ -232,6 +232,8 @@ bc_status bc_trim_workspaces(bc_graph_t g);
  *   BC_PROF_COMPACT  compaction of the marks into the next level's queues
  *   BC_PROF_REVERSE  reverse level kernel (dependency sums, BC update)
  *   BC_PROF_FINISH   completion of vertices split into several chunks
+ *   BC_PROF_SSSP     one pass of bc_sssp (owners = vertices whose arcs were
+ *                    relaxed, arcs = arcs relaxed, hits = improved distances)
  *   BC_PROF_FUSED    device-resident level loop: one launch runs whole
  *                    batches (its forward and reverse work counters are
  *                    added to FORWARD and REVERSE, which then show no launches)
@@ -244,7 +246,8 @@ enum {
     BC_PROF_REVERSE = 2,
     BC_PROF_FINISH = 3,
     BC_PROF_FUSED = 4,
-    BC_PROF_CLASSES = 5
+    BC_PROF_SSSP = 5,
+    BC_PROF_CLASSES = 6
 };
 
 typedef struct bc_profile {
@@ -293,6 +296,30 @@ typedef struct bc_tuning {
 
 bc_status bc_autotune(bc_graph_t g, const int32_t *sources, int32_t k, void *stream,
                       bc_tuning *out);
+
+/*
+ * Single-source shortest paths over weighted arcs, the paper's second
+ * propagation algorithm (Sections "fixedPoint Construct" and "Min/Max
+ * Constructs": passes over the vertices modified by the previous pass relax
+ * their out-arcs with Min(nbr.dist, v.dist + w) until a pass modifies
+ * nothing).  Uses the graph's out-arcs (for an undirected graph, both arcs of
+ * an edge; give them the same weight).
+ *
+ * bc_set_weights attaches arc weights: weight [row_ptr[n]] host, non-negative
+ * int32, in the order of the caller's col_idx (copied; the caller may free it).
+ * Until it is called every arc weighs 1 (hop distances).  Errors:
+ * BC_ERR_INVALID_ARG (NULL, a negative weight), BC_ERR_RANGE (the largest
+ * weight times n-1 does not fit int32: distances are int32),
+ * BC_ERR_OUT_OF_MEMORY, BC_ERR_DEVICE.
+ *
+ * bc_sssp writes dist_dev [n] (device, int32, caller vertex order): the
+ * distance from `source`, -1 where unreachable, complete when the call
+ * returns (it waits on `stream` once per 8 queued passes).  Calls on one graph
+ * are serialised (one workspace per graph).  Errors: BC_ERR_INVALID_ARG,
+ * BC_ERR_OUT_OF_MEMORY, BC_ERR_DEVICE.
+ */
+bc_status bc_set_weights(bc_graph_t g, const int32_t *weight);
+bc_status bc_sssp(bc_graph_t g, int32_t source, int32_t *dist_dev, void *stream);
 
 /* Static description of a status code. */
 const char *bc_status_str(bc_status s);

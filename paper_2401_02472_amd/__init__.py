@@ -24,7 +24,8 @@ __all__ = [
     "BCError", "bc_create_graph", "bc_destroy_graph", "bc_graph_info", "bc_run", "bc_run_async",
     "bc_run_multi",
     "bc_single_source", "bc_run_detail", "bc_workspace_bytes", "bc_trim_workspaces",
-    "bc_profile_enable", "bc_profile_read", "bc_status_str", "make_options", "Graph",
+    "bc_profile_enable", "bc_profile_read", "bc_set_weights", "bc_sssp", "bc_status_str",
+    "make_options", "Graph",
     "load_library",
 ]
 
@@ -145,6 +146,21 @@ def bc_run_multi(g: int, requests, outs, stream=None) -> None:
                                    _ptr(start, ctypes.c_int32), len(srcs), ptrs,
                                    _stream_handle(stream))
     _check(st, "bc_run_multi", outs)
+
+
+def bc_set_weights(g: int, weight) -> None:
+    """Arc weights for SSSP (int32 >= 0, in the order of the graph's col_idx)."""
+    w = _i32(weight)
+    _check(_capi.load().bc_set_weights(ctypes.c_void_p(g), _ptr(w, ctypes.c_int32)),
+           "bc_set_weights")
+
+
+def bc_sssp(g: int, source: int, dist_out, stream=None) -> None:
+    """Shortest-path distances from `source` into dist_out (int32 device tensor of
+    n entries; -1 where unreachable)."""
+    st = _capi.load().bc_sssp(ctypes.c_void_p(g), int(source),
+                              ctypes.c_void_p(dist_out.data_ptr()), _stream_handle(stream))
+    _check(st, "bc_sssp", dist_out)
 
 
 def bc_single_source(g: int, s: int):
@@ -269,3 +285,14 @@ class Graph:
 
     def profile_read(self, reset: bool = False) -> dict:
         return bc_profile_read(self.handle, reset)
+
+    def set_weights(self, weight) -> None:
+        bc_set_weights(self.handle, weight)
+
+    def sssp(self, source: int, dist_out=None, stream=None):
+        """Distances from `source` (int32 device tensor; allocated when not given)."""
+        if dist_out is None:
+            import torch
+            dist_out = torch.empty(self.n, dtype=torch.int32, device="cuda")
+        bc_sssp(self.handle, source, dist_out, stream)
+        return dist_out

@@ -33,7 +33,8 @@ BC_MODE_BATCHED = 2
 
 EXPORTED = ("bc_create_graph", "bc_destroy_graph", "bc_graph_info", "bc_run", "bc_run_async",
             "bc_run_multi", "bc_single_source", "bc_run_detail", "bc_workspace_bytes", "bc_trim_workspaces",
-            "bc_profile_enable", "bc_profile_read", "bc_autotune", "bc_status_str")
+            "bc_profile_enable", "bc_profile_read", "bc_autotune", "bc_set_weights", "bc_sssp",
+            "bc_status_str")
 
 BC_LOOP_AUTO = 0
 BC_LOOP_HOST = 1
@@ -44,8 +45,9 @@ BC_PROF_COMPACT = 1
 BC_PROF_REVERSE = 2
 BC_PROF_FINISH = 3
 BC_PROF_FUSED = 4
-BC_PROF_CLASSES = 5
-PROF_CLASS_NAMES = ("forward", "compact", "reverse", "finish", "fused")
+BC_PROF_SSSP = 5
+BC_PROF_CLASSES = 6
+PROF_CLASS_NAMES = ("forward", "compact", "reverse", "finish", "fused", "sssp")
 
 
 class bc_options(ctypes.Structure):
@@ -103,6 +105,8 @@ def load():
             "bc_profile_enable": [vp, ctypes.c_int32],
             "bc_profile_read": [vp, ctypes.POINTER(bc_profile), ctypes.c_int32],
             "bc_autotune": [vp, i32p, ctypes.c_int32, vp, ctypes.POINTER(bc_tuning)],
+            "bc_set_weights": [vp, i32p],
+            "bc_sssp": [vp, ctypes.c_int32, vp, vp],
         }
         for name, args in sig.items():
             fn = getattr(lib, name)

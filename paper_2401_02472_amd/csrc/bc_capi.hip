@@ -149,7 +149,16 @@ struct bc_graph_s {
     int32_t *d_col_idx_in = nullptr;
     int2 *d_item_info_in = nullptr;
     uint32_t *d_item_first_in = nullptr;
-    uint64_t total_chunks3 = 0;  // chunk slots needed by bucket-3 vertices of one source
+    uint64_t total_chunks3 = 0;
+    // single-source shortest paths: arc weights (internal arc order; NULL =
+    // every arc weighs 1) and a workspace used by one call at a time
+    int32_t *d_weight = nullptr;
+    std::mutex sssp_mu;
+    struct Sssp {
+        int32_t *dist = nullptr, *stamp = nullptr, *flags = nullptr;
+        int32_t *h_flags = nullptr;               // pinned mirror of one flag block
+        unsigned long long *d_stats = nullptr;    // 12 counters ([9..11] used)
+    } sssp;  // chunk slots needed by bucket-3 vertices of one source
     size_t device_bytes = 0;
     std::mutex mu;
     std::vector<PlainWS *> plain_pool;
@@ -332,6 +341,9 @@ void accumulate_profile(bc_graph_s *g, LaunchTimer &timer, const unsigned long l
         add.owners[BC_PROF_REVERSE] = (int64_t)cnt[6];
         add.arcs[BC_PROF_REVERSE] = (int64_t)cnt[7];
         add.hits[BC_PROF_REVERSE] = (int64_t)cnt[8];
+        add.owners[BC_PROF_SSSP] = (int64_t)cnt[9];
+        add.arcs[BC_PROF_SSSP] = (int64_t)cnt[10];
+        add.hits[BC_PROF_SSSP] = (int64_t)cnt[11];
     }
     std::lock_guard<std::mutex> lk(g->prof_mu);
     for (int c = 0; c < BC_PROF_CLASSES; ++c) {
@@ -1489,6 +1501,15 @@ void free_graph_arrays(bc_graph_s *g) {
     if (g->d_iperm) (void)hipFree(g->d_iperm);
     if (g->d_item_info) (void)hipFree(g->d_item_info);
     if (g->d_item_first) (void)hipFree(g->d_item_first);
+    if (g->d_weight) (void)hipFree(g->d_weight);
+    auto &w = g->sssp;
+    if (w.dist) (void)hipFree(w.dist);
+    if (w.stamp) (void)hipFree(w.stamp);
+    if (w.flags) (void)hipFree(w.flags);
+    if (w.h_flags) (void)hipHostFree(w.h_flags);
+    if (w.d_stats) (void)hipFree(w.d_stats);
+    w = bc_graph_s::Sssp{};
+    g->d_weight = nullptr;
     g->d_row_ptr = g->d_col_idx = g->d_perm = g->d_iperm = nullptr;
     g->d_item_info = nullptr;
     g->d_item_first = nullptr;
@@ -1888,6 +1909,119 @@ bc_status bc_single_source(bc_graph_t g, int32_t s, int32_t *dist, double *sigma
     (void)hipFree(d_sigma);
     (void)hipFree(d_delta);
     return st;
+}
+
+bc_status bc_set_weights(bc_graph_t g, const int32_t *weight) {
+    if (!g || (!weight && g->nnz > 0)) return BC_ERR_INVALID_ARG;
+    int32_t maxw = 0;
+    for (int64_t e = 0; e < g->nnz; ++e) {
+        if (weight[e] < 0) return BC_ERR_INVALID_ARG;
+        maxw = std::max(maxw, weight[e]);
+    }
+    // every distance must fit int32 (and stay below the "unreached" value)
+    if ((int64_t)maxw * std::max<int64_t>(g->n - 1, 0) >= (int64_t)INT32_MAX) return BC_ERR_RANGE;
+    if (g->n == 0 || g->nnz == 0) return BC_OK;
+    DeviceGuard dg(g->device);
+    std::lock_guard<std::mutex> lk(g->sssp_mu);
+    // the caller's row offsets, from the internal ones and the permutation
+    const size_t n = (size_t)g->n;
+    std::vector<int32_t> new_rp(n + 1), old_rp(n + 1, 0);
+    BC_TRY_HIP(hipMemcpy(new_rp.data(), g->d_row_ptr, (n + 1) * sizeof(int32_t),
+                         hipMemcpyDeviceToHost));
+    for (size_t o = 0; o < n; ++o) {
+        const int32_t u = g->h_perm[o];
+        old_rp[o + 1] = old_rp[o] + (new_rp[(size_t)u + 1] - new_rp[(size_t)u]);
+    }
+    int32_t *t_rp = nullptr, *t_w = nullptr, *w_new = nullptr;
+    hipError_t e = hipMalloc(&t_rp, (n + 1) * sizeof(int32_t));
+    if (e == hipSuccess) e = hipMalloc(&t_w, (size_t)g->nnz * sizeof(int32_t));
+    if (e == hipSuccess) e = hipMalloc(&w_new, (size_t)g->nnz * sizeof(int32_t));
+    if (e == hipSuccess)
+        e = hipMemcpy(t_rp, old_rp.data(), (n + 1) * sizeof(int32_t), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(t_w, weight, (size_t)g->nnz * sizeof(int32_t), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = permute_arc_values(g->n, g->nnz, t_rp, t_w, g->d_row_ptr, g->d_iperm, w_new, nullptr);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (t_rp) (void)hipFree(t_rp);
+    if (t_w) (void)hipFree(t_w);
+    if (e != hipSuccess) {
+        if (w_new) (void)hipFree(w_new);
+        return from_hip(e);
+    }
+    if (g->d_weight) (void)hipFree(g->d_weight);
+    g->d_weight = w_new;
+    return BC_OK;
+}
+
+bc_status bc_sssp(bc_graph_t g, int32_t source, int32_t *dist_dev, void *stream_) {
+    if (!g || source < 0 || source >= g->n || !dist_dev) return BC_ERR_INVALID_ARG;
+    DeviceGuard dg(g->device);
+    std::lock_guard<std::mutex> lk(g->sssp_mu);
+    const hipStream_t stream = (hipStream_t)stream_;
+    auto &w = g->sssp;
+    constexpr int32_t K = 8;  // passes queued per host poll
+    if (!w.dist) {
+        hipError_t e = hipMalloc(&w.dist, (size_t)g->n * sizeof(int32_t));
+        if (e == hipSuccess) e = hipMalloc(&w.stamp, (size_t)g->n * sizeof(int32_t));
+        if (e == hipSuccess) e = hipMalloc(&w.flags, 2 * K * sizeof(int32_t));
+        if (e == hipSuccess) e = hipMalloc(&w.d_stats, 12 * sizeof(unsigned long long));
+        if (e == hipSuccess)
+            e = hipHostMalloc((void **)&w.h_flags, K * sizeof(int32_t), hipHostMallocDefault);
+        if (e != hipSuccess) {
+            if (w.dist) (void)hipFree(w.dist);
+            if (w.stamp) (void)hipFree(w.stamp);
+            if (w.flags) (void)hipFree(w.flags);
+            if (w.d_stats) (void)hipFree(w.d_stats);
+            w = bc_graph_s::Sssp{};
+            return from_hip(e);
+        }
+    }
+    const int32_t stride = std::max(1, g->profiling.load());
+    const bool prof = g->profiling.load() != 0;
+    LaunchTimer timer;
+    SsspDev d{};
+    d.n = g->n;
+    d.big_end = g->big_end;
+    d.items = g->items;
+    d.row_ptr = g->d_row_ptr;
+    d.col_idx = g->d_col_idx;
+    d.weight = g->d_weight;
+    d.item_info = g->d_item_info;
+    d.dist = w.dist;
+    d.stamp = w.stamp;
+    hipError_t e = hipSuccess;
+    if (prof) e = hipMemsetAsync(w.d_stats, 0, 12 * sizeof(unsigned long long), stream);
+    if (e == hipSuccess) e = sssp_init(g->n, w.dist, w.stamp, g->h_perm[(size_t)source], stream);
+    // flag of pass p (1, 2, ...) in block ((p-1)/K) & 1; a block is cleared
+    // before its chunk of passes is queued
+    auto slot = [&](int32_t p) { return w.flags + (((p - 1) / K) & 1) * K + (p - 1) % K; };
+    bool done = false;
+    for (int32_t p0 = 1; e == hipSuccess && !done; p0 += K) {
+        if (p0 > g->n + K) {  // more passes than a shortest path has arcs: cannot happen
+            e = hipErrorUnknown;
+            break;
+        }
+        e = hipMemsetAsync(slot(p0), 0, K * sizeof(int32_t), stream);
+        for (int32_t p = p0; p < p0 + K && e == hipSuccess; ++p) {
+            const bool m = prof && (p - 1) % stride == 0;
+            timer.on = m;
+            d.stats = m ? w.d_stats + 9 : nullptr;
+            e = timer.begin(BC_PROF_SSSP, stream);
+            if (e == hipSuccess) e = sssp_pass(d, p, p == 1 ? nullptr : slot(p - 1), slot(p), stream);
+            if (e == hipSuccess) e = timer.end(stream);
+        }
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(w.h_flags, slot(p0), K * sizeof(int32_t), hipMemcpyDeviceToHost,
+                               stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
+        for (int32_t q = 0; q < K && e == hipSuccess; ++q) done |= w.h_flags[q] == 0;
+    }
+    if (e == hipSuccess) e = sssp_export(g->n, g->d_perm, w.dist, dist_dev, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e == hipSuccess && prof) accumulate_profile(g, timer, w.d_stats);
+    timer.destroy();
+    return from_hip(e);
 }
 
 bc_status bc_workspace_bytes(bc_graph_t g, int32_t k, const bc_options *opt, size_t *bytes) {

@@ -187,6 +187,31 @@ hipError_t batch_fused(const BatchDev *devs_dev, int32_t nbatches, bool narrow,
 hipError_t batch_export(const BatchDev &d, int32_t deepest, int32_t nlanes, int32_t *dist,
                         double *sigma, hipStream_t stream);
 
+// Device view of a single-source shortest-path run (bc_sssp.hip): the graph's
+// out-arcs with their weights (NULL: every arc weighs 1), the same chunk items
+// as the batched BC path, a distance and a pass stamp per vertex.
+struct SsspDev {
+    int32_t n;
+    int32_t big_end;
+    uint32_t items;
+    const int32_t *row_ptr;
+    const int32_t *col_idx;
+    const int32_t *weight;
+    const int2 *item_info;
+    int32_t *dist;
+    int32_t *stamp;               // pass that must relax the vertex's arcs
+    unsigned long long *stats;    // NULL, or [0..2]: vertices relaxed, arcs, improvements
+};
+
+hipError_t sssp_init(int32_t n, int32_t *dist, int32_t *stamp, int32_t src, hipStream_t stream);
+hipError_t sssp_pass(const SsspDev &d, int32_t pass, const int32_t *prev, int32_t *cur,
+                     hipStream_t stream);
+hipError_t sssp_export(int32_t n, const int32_t *perm, const int32_t *dist, int32_t *out,
+                       hipStream_t stream);
+hipError_t permute_arc_values(int32_t n, int64_t nnz, const int32_t *old_rp,
+                              const int32_t *old_vals, const int32_t *new_rp,
+                              const int32_t *iperm, int32_t *new_vals, hipStream_t stream);
+
 // Launchers (bc_plain.hip).  All are asynchronous on `stream`.
 // Graph set-up (bc_graph.hip).
 // new_ci[e] = perm[old_ci[old_rp[iperm[u]] + e - new_rp[u]]] for the internal

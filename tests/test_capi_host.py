@@ -79,6 +79,8 @@ def test_invalid_arguments_rejected():
     assert lib.bc_run(None, None, 0, None) == bcm.BC_ERR_INVALID_ARG
     assert lib.bc_graph_info(None, None, None, None) == bcm.BC_ERR_INVALID_ARG
     assert lib.bc_autotune(None, None, 1, None, None) == bcm.BC_ERR_INVALID_ARG
+    assert lib.bc_set_weights(None, None) == bcm.BC_ERR_INVALID_ARG
+    assert lib.bc_sssp(None, 0, None, None) == bcm.BC_ERR_INVALID_ARG
     assert lib.bc_destroy_graph(None) == bcm.BC_OK
 
 
