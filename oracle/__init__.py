@@ -21,6 +21,9 @@ directed paths, cycles and stars, brute force on random digraphs, NetworkX's
 directed betweenness and the undirected oracle on symmetric graphs.  ``sssp``
 (the paper's weighted single-source shortest paths) is pinned to scipy's
 Dijkstra, to hop distances with unit weights and to prefix sums on paths.
+``pagerank`` is pinned to the fixed point of its linear system (scipy's direct
+solve), to uniform ranks on regular graphs, to a one-iteration closed form on
+stars and to NetworkX's PageRank on graphs without dangling vertices.
 """
 from __future__ import annotations
 
@@ -82,6 +85,9 @@ def _load():
     lib.oracle_sssp.restype = ctypes.c_int64
     lib.oracle_sssp.argtypes = [ctypes.c_int32, i32p, i32p, i32p, ctypes.c_int32,
                                 ctypes.POINTER(ctypes.c_int64)]
+    lib.oracle_pagerank.restype = ctypes.c_int64
+    lib.oracle_pagerank.argtypes = [ctypes.c_int32, i32p, i32p, ctypes.c_double, ctypes.c_double,
+                                    ctypes.c_int32, f64p, f64p]
     lib.oracle_ld_digits.restype = ctypes.c_int
     lib.oracle_ld_digits.argtypes = []
     lib.oracle_single_source_ext.restype = ctypes.c_int
@@ -194,3 +200,19 @@ def sssp(row_ptr, col_idx, weight, s: int):
     if passes < 0:
         raise OracleError("invalid argument")
     return dist, int(passes)
+
+
+def pagerank(row_ptr, col_idx, damping: float = 0.85, tol: float = 1e-10, max_iter: int = 100):
+    """(pr float64[n], iterations, last L1 change): the paper's PageRank (pull over
+    in-arcs, start 1/n, stop when the L1 change <= tol or after max_iter)."""
+    lib = _load()
+    rp, rpp = _i32(row_ptr)
+    ci, cip = _i32(col_idx)
+    n = rp.shape[0] - 1
+    pr = np.empty(n, dtype=np.float64)
+    last = ctypes.c_double(0.0)
+    it = lib.oracle_pagerank(n, rpp, cip, float(damping), float(tol), int(max_iter),
+                             pr.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(last))
+    if it < 0:
+        raise OracleError("invalid argument")
+    return pr, int(it), float(last.value)

@@ -41,7 +41,8 @@
  * Status codes: 0 = ok, 1 = invalid argument, 4 = some sigma is not finite
  * (BC is then written but meaningless).  The *_ext entry points at the end
  * run the same steps in long double for path counts beyond double's range;
- * oracle_sssp is the paper's weighted single-source shortest paths.
+ * oracle_sssp is the paper's weighted single-source shortest paths and
+ * oracle_pagerank its PageRank.
  *
  * Built with gcc -O2, no fast-math.
  */
@@ -289,6 +290,63 @@ int64_t oracle_sssp(int32_t n, const int32_t *row_ptr, const int32_t *col_idx,
     free(modified);
     free(modified_next);
     return passes;
+}
+
+/* ---- PageRank -------------------------------------------------------------------
+ *
+ * The paper's PageRank (the generated loop of Section "Backend Optimizations",
+ * OpenACC reduction): every vertex starts at 1/n; an iteration computes, for
+ * each v, sum = sum over the arcs u->v of pr[u] / outdeg(u) (pulled over the
+ * reversed CSR, in-neighbours in ascending id order), val = (1 - damping)/n +
+ * damping * sum, diff += |val - pr[v]|, pr_next[v] = val; then pr = pr_next.
+ * Iterations stop once diff <= tol or after max_iter of them.  The listing
+ * accumulates the signed difference val - pr[v], which sums to zero whenever no
+ * rank leaks (it would stop after one iteration); the L1 norm is taken instead.
+ * The CSR lists out-arcs (for an undirected graph, both arcs of an edge).
+ * pr[n] receives the result; returns the iterations run (>= 1), or -1 for
+ * invalid arguments. */
+int64_t oracle_pagerank(int32_t n, const int32_t *row_ptr, const int32_t *col_idx,
+                        double damping, double tol, int32_t max_iter, double *pr,
+                        double *last_diff) {
+    if (check_graph_args(n, row_ptr, col_idx) != OR_OK || !pr || max_iter < 1 ||
+        !(damping >= 0.0 && damping <= 1.0) || !(tol >= 0.0))
+        return -1;
+    if (n == 0) return 1;
+    const int64_t nnz = row_ptr[n];
+    /* reversed CSR by counting sort: in-neighbours in ascending id order */
+    int32_t *in_rp = (int32_t *)calloc((size_t)n + 1, sizeof(int32_t));
+    int32_t *in_ci = (int32_t *)malloc((size_t)(nnz > 0 ? nnz : 1) * sizeof(int32_t));
+    for (int64_t e = 0; e < nnz; ++e) in_rp[col_idx[e] + 1]++;
+    for (int32_t v = 0; v < n; ++v) in_rp[v + 1] += in_rp[v];
+    int32_t *fill = (int32_t *)malloc((size_t)n * sizeof(int32_t));
+    for (int32_t v = 0; v < n; ++v) fill[v] = in_rp[v];
+    for (int32_t u = 0; u < n; ++u)
+        for (int32_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) in_ci[fill[col_idx[e]]++] = u;
+    double *next = (double *)malloc((size_t)n * sizeof(double));
+    for (int32_t v = 0; v < n; ++v) pr[v] = 1.0 / (double)n;
+    int64_t iter = 0;
+    double diff = 0.0;
+    do {
+        diff = 0.0;
+        for (int32_t v = 0; v < n; ++v) {
+            double sum = 0.0;
+            for (int32_t e = in_rp[v]; e < in_rp[v + 1]; ++e) {
+                int32_t u = in_ci[e];
+                sum = sum + pr[u] / (double)(row_ptr[u + 1] - row_ptr[u]);
+            }
+            double val = (1.0 - damping) / (double)n + damping * sum;
+            diff = diff + fabs(val - pr[v]);
+            next[v] = val;
+        }
+        for (int32_t v = 0; v < n; ++v) pr[v] = next[v];
+        ++iter;
+    } while (diff > tol && iter < max_iter);
+    if (last_diff) *last_diff = diff;
+    free(in_rp);
+    free(in_ci);
+    free(fill);
+    free(next);
+    return iter;
 }
 
 /* ---- extended range --------------------------------------------------------

@@ -156,6 +156,34 @@ def test_sssp_mutant_is_caught(name, swap_oracle):
         _sssp_pin_suite()
 
 
+PR_MUTANTS = {
+    "pr-signed-diff": ("diff = diff + fabs(val - pr[v]);", "diff = diff + (val - pr[v]);"),
+    "pr-no-teleport": ("double val = (1.0 - damping) / (double)n + damping * sum;",
+                       "double val = damping * sum;"),
+    "pr-own-outdeg": ("sum = sum + pr[u] / (double)(row_ptr[u + 1] - row_ptr[u]);",
+                      "sum = sum + pr[u] / (double)(row_ptr[v + 1] - row_ptr[v] + 1);"),
+}
+
+
+def _pr_pin_suite():
+    for g in (gg.rmat(10, 8, seed=1), gg.rmat(10, 8, seed=2, directed=True)):
+        pins.test_pagerank_converges_to_fixed_point(g)
+    pins.test_pagerank_star_one_iteration()
+
+
+def test_unmutated_copy_passes_pagerank_pins(swap_oracle):
+    swap_oracle(open(SRC).read())
+    _pr_pin_suite()
+
+
+@pytest.mark.parametrize("name", sorted(PR_MUTANTS))
+def test_pagerank_mutant_is_caught(name, swap_oracle):
+    before, after = PR_MUTANTS[name]
+    swap_oracle(_mutate(open(SRC).read(), before, after, ext=False))
+    with pytest.raises(AssertionError):
+        _pr_pin_suite()
+
+
 def _ext_pin_suite():
     """The extended-range pins (quick ones) against the loaded library."""
     pins.test_ext_diamond_chain_closed_form(1100, 2)

@@ -603,3 +603,77 @@ def test_sssp_rejects_negative_weights():
     g = gg.path(3)
     with pytest.raises(oracle.OracleError):
         oracle.sssp(g.row_ptr, g.col_idx, np.array([1, -1, 1, 1], np.int32), 0)
+
+
+# ---------------------------------------------------------------------------
+# PageRank
+# ---------------------------------------------------------------------------
+
+def pr_fixed_point(g, damping):
+    """Solution of x = (1 - d)/n + d * P x with P[v, u] = 1/outdeg(u) per arc u->v,
+    by scipy's sparse direct solver (an independent method)."""
+    import scipy.sparse.linalg as sla
+    n = g.n
+    deg = np.diff(g.row_ptr).astype(np.float64)
+    u = np.repeat(np.arange(n), np.diff(g.row_ptr))
+    P = sp.csr_matrix((1.0 / deg[u], (g.col_idx, u)), shape=(n, n))
+    A = (sp.identity(n, format="csr") - damping * P).tocsc()
+    return sla.spsolve(A, np.full(n, (1.0 - damping) / n))
+
+
+@pytest.mark.parametrize("g", [gg.cycle(12), gg.complete(9), gg.hypercube(6),
+                               gg.torus(6, 7)], ids=lambda g: g.name)
+def test_pagerank_regular_graphs_uniform(g):
+    pr, it, _ = oracle.pagerank(g.row_ptr, g.col_idx, 0.85, 1e-14, 50)
+    np.testing.assert_allclose(pr, np.full(g.n, 1.0 / g.n), rtol=1e-14)
+
+
+@pytest.mark.parametrize("g", [gg.rmat(10, 8, seed=1), gg.rmat(10, 8, seed=2, directed=True),
+                               gg.gnp_directed(60, 0.08, seed=3), gg.grid_road(30, 30, seed=4)],
+                         ids=lambda g: g.name)
+def test_pagerank_converges_to_fixed_point(g):
+    """Iterated to a tight tolerance, the ranks are the linear system's solution
+    (dangling vertices leak their rank, as in the paper's formula)."""
+    for d in (0.85, 0.5):
+        pr, it, last = oracle.pagerank(g.row_ptr, g.col_idx, d, 1e-13, 2000)
+        assert last <= 1e-13 and it < 2000
+        np.testing.assert_allclose(pr, pr_fixed_point(g, d), rtol=1e-9, atol=1e-15)
+
+
+def test_pagerank_star_one_iteration():
+    """Leaves -> centre (n = 9): after one iteration from 1/n the centre has
+    (1-d)/n + d (n-1)/n, the leaves (1-d)/n; the next L1 change follows."""
+    n, d = 9, 0.85
+    g = gg.directed(n, [(i, 0) for i in range(1, n)], "in-star")
+    pr, it, last = oracle.pagerank(g.row_ptr, g.col_idx, d, 0.0, 1)
+    assert it == 1
+    want = np.full(n, (1 - d) / n)
+    want[0] += d * (n - 1) / n
+    np.testing.assert_allclose(pr, want, rtol=1e-15)
+    np.testing.assert_allclose(last, abs(want[0] - 1 / n) + (n - 1) * abs(want[1] - 1 / n),
+                               rtol=1e-14)
+
+
+def test_pagerank_stopping_rule():
+    g = gg.rmat(9, 8, seed=5)
+    _, it_cap, _ = oracle.pagerank(g.row_ptr, g.col_idx, 0.85, 0.0, 7)
+    assert it_cap == 7
+    pr, it, last = oracle.pagerank(g.row_ptr, g.col_idx, 0.85, 1e-6, 1000)
+    assert last <= 1e-6
+    _, _, prev = oracle.pagerank(g.row_ptr, g.col_idx, 0.85, 0.0, it - 1)
+    assert prev > 1e-6
+
+
+def test_pagerank_networkx_cross_check():
+    nx = pytest.importorskip("networkx")
+    for g in (gg.rmat(9, 8, seed=6), gg.cycle(40), gg.gnp(50, 0.2, seed=7)):
+        if (np.diff(g.row_ptr) == 0).any():
+            continue   # NetworkX spreads dangling rank; the paper's formula does not
+        G = nx.DiGraph()
+        G.add_nodes_from(range(g.n))
+        for u in range(g.n):
+            for v in g.col_idx[g.row_ptr[u]:g.row_ptr[u + 1]]:
+                G.add_edge(u, int(v))
+        ref = nx.pagerank(G, alpha=0.85, tol=1e-14, max_iter=10000)
+        pr, _, _ = oracle.pagerank(g.row_ptr, g.col_idx, 0.85, 1e-15, 10000)
+        np.testing.assert_allclose(pr, [ref[v] for v in range(g.n)], rtol=1e-8)
