@@ -54,6 +54,10 @@ BYTES = {
 # neighbour id 4 + weight 4 + neighbour distance 4; per improvement: atomic
 # min 4 + stamp write 4.
 SSSP_BYTES = {"vertex": 4, "owners": 12, "arcs": 12, "hits": 8}
+# pagerank sum kernel, per iteration: per vertex row_ptr_in pair 8 + out-
+# offsets pair 8 (out-degree) + rank read 8 + rank write 8 + share write 8;
+# per arc: in-neighbour id 4 + its share 8.
+PR_BYTES = {"vertex": 40, "arc": 12}
 KERNELS = {
     ("plain", "forward"): "k_level_forward", ("plain", "reverse"): "k_level_reverse",
     ("batched", "forward"): "k_batch_forward", ("batched", "reverse"): "k_batch_reverse",
@@ -369,6 +373,78 @@ def sssp_bench(args) -> int:
     return 0
 
 
+def pagerank_bench(args) -> int:
+    """PageRank workload: the scale-22 R-MAT; a step is one run of --pr-iterations
+    iterations (damping 0.85, tol 0).  GTEPS = arcs x iterations / time."""
+    import numpy as np
+    import torch
+
+    import graphgen as gg
+    import oracle
+    import paper_2401_02472_amd as bcm
+
+    torch.cuda.set_device(0)
+    bcm.load_library()
+    g, _ = gg.workload("rmat-s22-ef16")
+    iters = args.pr_iterations
+    G = bcm.Graph(g.n, g.row_ptr, g.col_idx, flags=bcm.BC_GRAPH_TRUST_SYMMETRIC)
+    out = torch.empty(g.n, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        G.pagerank(0.85, 0.0, iters, out)
+    torch.cuda.synchronize()
+    G.profile_enable(1)
+    G.profile_read(reset=True)
+    step_ms = []
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        start.record(stream)
+        G.pagerank(0.85, 0.0, iters, out)
+        stop.record(stream)
+        stop.synchronize()
+        step_ms.append(start.elapsed_time(stop))
+    wall = time.perf_counter() - t0
+    prof = G.profile_read(reset=True)
+    G.profile_enable(False)
+    ms_per_step = wall * 1e3 / args.steps
+    value = iters * g.nnz / (ms_per_step / 1e3) / 1e9
+    pc = prof["pagerank"]
+    launches = max(pc["launches"], 1)
+    alg = PR_BYTES["vertex"] * g.n + PR_BYTES["arc"] * g.nnz
+    avg_ms = pc["ms"] / launches
+    achieved = alg / (avg_ms / 1e3) / 1e9 if avg_ms > 0 else 0.0
+    src_hash = kernel_source_hash()
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": read_traffic("k_pr_pull", "pagerank-rmat-s22-ef16", src_hash),
+            "kernel": "k_pr_pull", "alg_bytes_per_launch": int(alg),
+            "avg_launch_ms": round(avg_ms, 5), "launches": pc["launches"],
+            "kernel_source_hash": src_hash}
+    cpu = None
+    if args.cpu_seconds > 0:
+        m = 3
+        t = time.perf_counter()
+        oracle.pagerank(g.row_ptr, g.col_idx, 0.85, 0.0, m)
+        dt = time.perf_counter() - t
+        cpu = {"value": round(m * g.nnz / dt / 1e9, 4), "unit": "GTEPS", "cores": 1,
+               "kind": "oracle", "sample": f"{m} iterations on one thread, {dt:.2f} s"}
+    q = np.percentile(step_ms, [50, 99])
+    rec = {
+        "metric": "PageRank GTEPS (arcs x iterations / s); HBM roofline", "value": round(value, 3),
+        "unit": "GTEPS", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "pagerank-rmat-s22-ef16", "n": g.n, "nnz": g.nnz,
+                   "iterations": iters, "damping": 0.85, "graph": g.params},
+        "p50_ms": round(float(q[0]), 3), "p99_ms": round(float(q[1]), 3),
+        "roofline": roof, "cpu_baseline": cpu,
+    }
+    print(json.dumps(rec), flush=True)
+    G.close()
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -406,6 +482,8 @@ def main() -> int:
     ap.add_argument("--serving-cpu-sample", type=int, default=12)
     ap.add_argument("--sssp-sources", type=int, default=16,
                     help="sssp-rmat-s22-ef16: sources per step")
+    ap.add_argument("--pr-iterations", type=int, default=20,
+                    help="pagerank-rmat-s22-ef16: iterations per step")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -427,6 +505,8 @@ def main() -> int:
         return serving_bench(args)
     if args.workload == "sssp-rmat-s22-ef16":
         return sssp_bench(args)
+    if args.workload == "pagerank-rmat-s22-ef16":
+        return pagerank_bench(args)
     torch.cuda.set_device(0)
     bcm.load_library()
 

@@ -234,6 +234,8 @@ bc_status bc_trim_workspaces(bc_graph_t g);
  *   BC_PROF_FINISH   completion of vertices split into several chunks
  *   BC_PROF_SSSP     one pass of bc_sssp (owners = vertices whose arcs were
  *                    relaxed, arcs = arcs relaxed, hits = improved distances)
+ *   BC_PROF_PAGERANK the sum step of one bc_pagerank iteration (timing only;
+ *                    its bytes follow from the graph's size)
  *   BC_PROF_FUSED    device-resident level loop: one launch runs whole
  *                    batches (its forward and reverse work counters are
  *                    added to FORWARD and REVERSE, which then show no launches)
@@ -247,7 +249,8 @@ enum {
     BC_PROF_FINISH = 3,
     BC_PROF_FUSED = 4,
     BC_PROF_SSSP = 5,
-    BC_PROF_CLASSES = 6
+    BC_PROF_PAGERANK = 6,
+    BC_PROF_CLASSES = 7
 };
 
 typedef struct bc_profile {
@@ -320,6 +323,28 @@ bc_status bc_autotune(bc_graph_t g, const int32_t *sources, int32_t k, void *str
  */
 bc_status bc_set_weights(bc_graph_t g, const int32_t *weight);
 bc_status bc_sssp(bc_graph_t g, int32_t source, int32_t *dist_dev, void *stream);
+
+/*
+ * PageRank, the paper's pull iteration (Section "Backend Optimizations", the
+ * generated reduction loop): every vertex starts at 1/n; an iteration computes
+ * for each v the sum over the arcs u->v of pr[u] / outdeg(u), the new rank
+ * (1 - damping)/n + damping * sum, and the L1 change sum |new - old| (the
+ * listing adds the signed change, which sums to zero whenever no rank leaks;
+ * the L1 norm is the test used here); iterations stop when the change is at
+ * most tol or after max_iter.  Vertices without out-arcs keep no share of their
+ * rank (the formula's leak).  Arcs are the graph's out-arcs (an undirected
+ * graph's edges count both ways); a directed graph's sums use its reversed CSR.
+ *   damping     in [0, 1] (0.85 typically)
+ *   tol         >= 0; 0 runs max_iter iterations unless a change is exactly 0
+ *   max_iter    >= 1
+ *   pr_dev      [n] device double, caller vertex order, written by the time the
+ *               call returns (it waits on `stream` once per 8 queued iterations)
+ *   iterations  host, may be NULL: iterations run
+ * Calls on one graph are serialised.  Errors: BC_ERR_INVALID_ARG,
+ * BC_ERR_OUT_OF_MEMORY, BC_ERR_DEVICE.
+ */
+bc_status bc_pagerank(bc_graph_t g, double damping, double tol, int32_t max_iter, double *pr_dev,
+                      int32_t *iterations, void *stream);
 
 /* Static description of a status code. */
 const char *bc_status_str(bc_status s);

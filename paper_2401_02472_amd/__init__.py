@@ -24,7 +24,8 @@ __all__ = [
     "BCError", "bc_create_graph", "bc_destroy_graph", "bc_graph_info", "bc_run", "bc_run_async",
     "bc_run_multi",
     "bc_single_source", "bc_run_detail", "bc_workspace_bytes", "bc_trim_workspaces",
-    "bc_profile_enable", "bc_profile_read", "bc_set_weights", "bc_sssp", "bc_status_str",
+    "bc_profile_enable", "bc_profile_read", "bc_set_weights", "bc_sssp", "bc_pagerank",
+    "bc_status_str",
     "make_options", "Graph",
     "load_library",
 ]
@@ -163,6 +164,18 @@ def bc_sssp(g: int, source: int, dist_out, stream=None) -> None:
     _check(st, "bc_sssp", dist_out)
 
 
+def bc_pagerank(g: int, pr_out, damping: float = 0.85, tol: float = 1e-10, max_iter: int = 100,
+                stream=None) -> int:
+    """PageRank into pr_out (float64 device tensor of n entries); returns the
+    iterations run."""
+    it = ctypes.c_int32(0)
+    st = _capi.load().bc_pagerank(ctypes.c_void_p(g), float(damping), float(tol), int(max_iter),
+                                  ctypes.c_void_p(pr_out.data_ptr()), ctypes.byref(it),
+                                  _stream_handle(stream))
+    _check(st, "bc_pagerank", pr_out)
+    return int(it.value)
+
+
 def bc_single_source(g: int, s: int):
     """(dist int32[n], sigma float64[n], delta float64[n]) for one source."""
     n, _, _ = bc_graph_info(g)
@@ -285,6 +298,15 @@ class Graph:
 
     def profile_read(self, reset: bool = False) -> dict:
         return bc_profile_read(self.handle, reset)
+
+    def pagerank(self, damping: float = 0.85, tol: float = 1e-10, max_iter: int = 100,
+                 pr_out=None, stream=None):
+        """(ranks as a float64 device tensor, iterations run)."""
+        if pr_out is None:
+            import torch
+            pr_out = torch.empty(self.n, dtype=torch.float64, device="cuda")
+        it = bc_pagerank(self.handle, pr_out, damping, tol, max_iter, stream)
+        return pr_out, it
 
     def set_weights(self, weight) -> None:
         bc_set_weights(self.handle, weight)

@@ -34,7 +34,7 @@ BC_MODE_BATCHED = 2
 EXPORTED = ("bc_create_graph", "bc_destroy_graph", "bc_graph_info", "bc_run", "bc_run_async",
             "bc_run_multi", "bc_single_source", "bc_run_detail", "bc_workspace_bytes", "bc_trim_workspaces",
             "bc_profile_enable", "bc_profile_read", "bc_autotune", "bc_set_weights", "bc_sssp",
-            "bc_status_str")
+            "bc_pagerank", "bc_status_str")
 
 BC_LOOP_AUTO = 0
 BC_LOOP_HOST = 1
@@ -46,8 +46,9 @@ BC_PROF_REVERSE = 2
 BC_PROF_FINISH = 3
 BC_PROF_FUSED = 4
 BC_PROF_SSSP = 5
-BC_PROF_CLASSES = 6
-PROF_CLASS_NAMES = ("forward", "compact", "reverse", "finish", "fused", "sssp")
+BC_PROF_PAGERANK = 6
+BC_PROF_CLASSES = 7
+PROF_CLASS_NAMES = ("forward", "compact", "reverse", "finish", "fused", "sssp", "pagerank")
 
 
 class bc_options(ctypes.Structure):
@@ -107,6 +108,7 @@ def load():
             "bc_autotune": [vp, i32p, ctypes.c_int32, vp, ctypes.POINTER(bc_tuning)],
             "bc_set_weights": [vp, i32p],
             "bc_sssp": [vp, ctypes.c_int32, vp, vp],
+            "bc_pagerank": [vp, ctypes.c_double, ctypes.c_double, ctypes.c_int32, vp, i32p, vp],
         }
         for name, args in sig.items():
             fn = getattr(lib, name)

@@ -8,7 +8,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB_PATH = os.path.join(HERE, "libbc_mi355x.so")
-SOURCES = ["bc_graph.hip", "bc_plain.hip", "bc_batched.hip", "bc_sssp.hip", "bc_capi.hip"]
+SOURCES = ["bc_graph.hip", "bc_plain.hip", "bc_batched.hip", "bc_sssp.hip", "bc_pagerank.hip",
+           "bc_capi.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

@@ -158,7 +158,15 @@ struct bc_graph_s {
         int32_t *dist = nullptr, *stamp = nullptr, *flags = nullptr;
         int32_t *h_flags = nullptr;               // pinned mirror of one flag block
         unsigned long long *d_stats = nullptr;    // 12 counters ([9..11] used)
-    } sssp;  // chunk slots needed by bucket-3 vertices of one source
+    } sssp;
+    // PageRank workspace (one call at a time)
+    std::mutex pr_mu;
+    struct Pr {
+        void *block = nullptr;        // ranks, shares, partials, slots
+        double *diff = nullptr;       // [cap]
+        int32_t cap = 0;
+        double *h_diff = nullptr;     // pinned, 8 entries
+    } prw;  // chunk slots needed by bucket-3 vertices of one source
     size_t device_bytes = 0;
     std::mutex mu;
     std::vector<PlainWS *> plain_pool;
@@ -1509,6 +1517,11 @@ void free_graph_arrays(bc_graph_s *g) {
     if (w.h_flags) (void)hipHostFree(w.h_flags);
     if (w.d_stats) (void)hipFree(w.d_stats);
     w = bc_graph_s::Sssp{};
+    auto &pw = g->prw;
+    if (pw.block) (void)hipFree(pw.block);
+    if (pw.diff) (void)hipFree(pw.diff);
+    if (pw.h_diff) (void)hipHostFree(pw.h_diff);
+    pw = bc_graph_s::Pr{};
     g->d_weight = nullptr;
     g->d_row_ptr = g->d_col_idx = g->d_perm = g->d_iperm = nullptr;
     g->d_item_info = nullptr;
@@ -2022,6 +2035,117 @@ bc_status bc_sssp(bc_graph_t g, int32_t source, int32_t *dist_dev, void *stream_
     if (e == hipSuccess && prof) accumulate_profile(g, timer, w.d_stats);
     timer.destroy();
     return from_hip(e);
+}
+
+bc_status bc_pagerank(bc_graph_t g, double damping, double tol, int32_t max_iter, double *pr_dev,
+                      int32_t *iterations, void *stream_) {
+    if (!g || !pr_dev || max_iter < 1 || !(damping >= 0.0 && damping <= 1.0) || !(tol >= 0.0))
+        return BC_ERR_INVALID_ARG;
+    if (iterations) *iterations = 0;
+    if (g->n == 0) {
+        if (iterations) *iterations = 1;
+        return BC_OK;
+    }
+    DeviceGuard dg(g->device);
+    std::lock_guard<std::mutex> lk(g->pr_mu);
+    const hipStream_t stream = (hipStream_t)stream_;
+    auto &w = g->prw;
+    const size_t n = (size_t)g->n;
+    const size_t items = std::max<uint32_t>(g->items_in, 1);
+    constexpr int32_t K = 8;  // iterations queued per host poll
+    if (!w.block) {
+        const size_t bytes = 4 * align_up(n * sizeof(double)) + align_up(items * sizeof(double)) +
+                             align_up(2 * (size_t)kFrontWaves * sizeof(double));
+        hipError_t e = hipMalloc(&w.block, bytes);
+        if (e == hipSuccess)
+            e = hipHostMalloc((void **)&w.h_diff, K * sizeof(double), hipHostMallocDefault);
+        if (e != hipSuccess) {
+            if (w.block) (void)hipFree(w.block);
+            w = bc_graph_s::Pr{};
+            return from_hip(e);
+        }
+    }
+    if (w.cap < max_iter) {
+        if (w.diff) (void)hipFree(w.diff);
+        w.diff = nullptr;
+        w.cap = 0;
+        BC_TRY_HIP(hipMalloc(&w.diff, (size_t)max_iter * sizeof(double)));
+        w.cap = max_iter;
+    }
+    PrDev d{};
+    d.n = g->n;
+    d.big_end = g->big_end;
+    d.multi_end = g->multi_end;
+    d.items_in = g->items_in;
+    d.row_ptr = g->d_row_ptr;
+    d.row_ptr_in = g->d_row_ptr_in;
+    d.col_idx_in = g->d_col_idx_in;
+    d.item_info_in = g->d_item_info_in;
+    d.item_first_in = g->d_item_first_in;
+    char *p = (char *)w.block;
+    auto take = [&](size_t b) {
+        char *r = p;
+        p += align_up(b);
+        return (double *)r;
+    };
+    d.pr[0] = take(n * sizeof(double));
+    d.pr[1] = take(n * sizeof(double));
+    d.contrib[0] = take(n * sizeof(double));
+    d.contrib[1] = take(n * sizeof(double));
+    d.partial = take(items * sizeof(double));
+    d.slots = take(2 * (size_t)kFrontWaves * sizeof(double));
+    d.diff = w.diff;
+    d.damping = damping;
+    d.base = (1.0 - damping) / (double)g->n;
+    d.tol = tol;
+    const bool prof = g->profiling.load() != 0;
+    const int32_t stride = std::max(1, g->profiling.load());
+    LaunchTimer timer;
+    hipError_t e = pagerank_init(d, max_iter, stream);
+    int32_t done = max_iter;  // iterations run
+    for (int32_t i0 = 0; e == hipSuccess && i0 < max_iter; i0 += K) {
+        const int32_t i1 = std::min(max_iter, i0 + K);
+        for (int32_t i = i0; i < i1 && e == hipSuccess; ++i) {
+            timer.on = prof && i % stride == 0;
+            e = timer.begin(BC_PROF_PAGERANK, stream);
+            if (e == hipSuccess) e = pagerank_pull(d, i, stream);
+            if (e == hipSuccess) e = timer.end(stream);
+            if (e == hipSuccess) e = pagerank_finish(d, i, stream);
+        }
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(w.h_diff, w.diff + i0, (size_t)(i1 - i0) * sizeof(double),
+                               hipMemcpyDeviceToHost, stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
+        bool stop = false;
+        for (int32_t i = i0; i < i1 && e == hipSuccess && !stop; ++i) {
+            const double x = w.h_diff[i - i0];
+            if (x >= 0.0 && x <= tol) {
+                done = i + 1;
+                stop = true;
+            }
+        }
+        if (stop) break;
+    }
+    if (e == hipSuccess) e = gather_f64(g->n, g->d_perm, d.pr[done & 1], pr_dev, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e == hipSuccess && prof) {
+        // timing only: no work counters for PageRank (its bytes follow from the graph)
+        bc_profile add{};
+        for (size_t i = 0; i < timer.used; ++i) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, timer.ev[2 * i], timer.ev[2 * i + 1]) == hipSuccess)
+                add.ms[timer.cls[i]] += ms;
+            add.launches[timer.cls[i]] += 1;
+        }
+        std::lock_guard<std::mutex> lk2(g->prof_mu);
+        g->prof.launches[BC_PROF_PAGERANK] += add.launches[BC_PROF_PAGERANK];
+        g->prof.ms[BC_PROF_PAGERANK] += add.ms[BC_PROF_PAGERANK];
+        g->prof.runs += 1;
+    }
+    timer.destroy();
+    if (e != hipSuccess) return from_hip(e);
+    if (iterations) *iterations = done;
+    return BC_OK;
 }
 
 bc_status bc_workspace_bytes(bc_graph_t g, int32_t k, const bc_options *opt, size_t *bytes) {

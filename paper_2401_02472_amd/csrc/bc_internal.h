@@ -203,6 +203,34 @@ struct SsspDev {
     unsigned long long *stats;    // NULL, or [0..2]: vertices relaxed, arcs, improvements
 };
 
+// Device view of a PageRank run (bc_pagerank.hip): the reversed CSR and its
+// chunk items (for the pull), the out-offsets (out-degrees), two rank and
+// two share buffers (iteration i reads [i & 1], writes [(i + 1) & 1]), chunk
+// partials of the split vertices, per-wave change slots (2 sets) and the
+// change of every iteration (-1 = not run).
+struct PrDev {
+    int32_t n;
+    int32_t big_end, multi_end;
+    uint32_t items_in;
+    const int32_t *row_ptr;
+    const int32_t *row_ptr_in;
+    const int32_t *col_idx_in;
+    const int2 *item_info_in;
+    const uint32_t *item_first_in;
+    double *pr[2];
+    double *contrib[2];
+    double *partial;
+    double *slots;   // [2][kFrontWaves]
+    double *diff;    // [max_iter]
+    double damping, base, tol;  // base = (1 - damping) / n
+};
+
+hipError_t pagerank_init(const PrDev &d, int32_t max_iter, hipStream_t stream);
+// One iteration = pagerank_pull (the sums, most of the work), then
+// pagerank_finish (split vertices and the iteration's change).
+hipError_t pagerank_pull(const PrDev &d, int32_t iter, hipStream_t stream);
+hipError_t pagerank_finish(const PrDev &d, int32_t iter, hipStream_t stream);
+
 hipError_t sssp_init(int32_t n, int32_t *dist, int32_t *stamp, int32_t src, hipStream_t stream);
 hipError_t sssp_pass(const SsspDev &d, int32_t pass, const int32_t *prev, int32_t *cur,
                      hipStream_t stream);

@@ -81,6 +81,7 @@ def test_invalid_arguments_rejected():
     assert lib.bc_autotune(None, None, 1, None, None) == bcm.BC_ERR_INVALID_ARG
     assert lib.bc_set_weights(None, None) == bcm.BC_ERR_INVALID_ARG
     assert lib.bc_sssp(None, 0, None, None) == bcm.BC_ERR_INVALID_ARG
+    assert lib.bc_pagerank(None, 0.85, 0.0, 10, None, None, None) == bcm.BC_ERR_INVALID_ARG
     assert lib.bc_destroy_graph(None) == bcm.BC_OK
 
 
