@@ -18,6 +18,9 @@
 namespace bcx {
 namespace {
 
+constexpr int kPerLane = kChunk / kWave;  // arcs per lane in a chunk item
+static_assert(kPerLane * kWave == kChunk, "a chunk item is kPerLane arcs per lane");
+
 constexpr int kDiffBlock = 1024;
 
 __device__ __forceinline__ bool converged(const PrDev &d, int32_t iter) {
@@ -60,15 +63,15 @@ __global__ __launch_bounds__(kBlock) void k_pr_pull(PrDev d, int32_t iter) {
             const int32_t v = info.x, j = info.y;
             const int32_t rs = d.row_ptr_in[v], re = d.row_ptr_in[v + 1];
             const int32_t cb = rs + j * kChunk, ce = min(re, cb + kChunk);
-            double x[8];
+            double x[kPerLane];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
+            for (int u = 0; u < kPerLane; ++u) {
                 const int32_t e = cb + u * kWave + lane;
                 x[u] = e < ce ? contrib[d.col_idx_in[e]] : 0.0;
             }
             double s = 0.0;
 #pragma unroll
-            for (int u = 0; u < 8; ++u) s += x[u];
+            for (int u = 0; u < kPerLane; ++u) s += x[u];
             s = wave_sum(s);
             if (v < d.multi_end) {
                 if (lane == 0) d.partial[it] = s;

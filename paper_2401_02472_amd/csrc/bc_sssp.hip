@@ -17,6 +17,9 @@
 namespace bcx {
 namespace {
 
+constexpr int kPerLane = kChunk / kWave;  // arcs per lane in a chunk item
+static_assert(kPerLane * kWave == kChunk, "a chunk item is kPerLane arcs per lane");
+
 constexpr int32_t kInf = 0x7fffffff;
 
 struct Relax {
@@ -42,7 +45,7 @@ __device__ __forceinline__ int32_t weight_of(const SsspDev &d, int64_t e) {
     return d.weight ? d.weight[e] : 1;
 }
 
-// Chunk item (vertex of degree > 64): 8 arcs per lane, loads issued together.
+// Chunk item (vertex of degree > 64): kPerLane arcs per lane, loads issued together.
 __device__ __forceinline__ void sssp_chunk(const SsspDev &d, int32_t pass, uint32_t item,
                                            Relax &r) {
     const int lane = lane_id();
@@ -53,16 +56,16 @@ __device__ __forceinline__ void sssp_chunk(const SsspDev &d, int32_t pass, uint3
     const int32_t rs = d.row_ptr[v], re = d.row_ptr[v + 1];
     const int32_t cb = rs + j * kChunk, ce = min(re, cb + kChunk);
     if (lane == 0 && j == 0) ++r.active;
-    int32_t nb[8], nd[8];
+    int32_t nb[kPerLane], nd[kPerLane];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
+    for (int u = 0; u < kPerLane; ++u) {
         const int32_t e = cb + u * kWave + lane;
         nb[u] = e < ce ? d.col_idx[e] : -1;
         nd[u] = e < ce ? dv + weight_of(d, e) : 0;
         r.arcs += e < ce ? 1u : 0u;
     }
 #pragma unroll
-    for (int u = 0; u < 8; ++u)
+    for (int u = 0; u < kPerLane; ++u)
         if (nb[u] >= 0) relax(d, nb[u], nd[u], pass, r);
 }
 

@@ -363,3 +363,18 @@ def test_level_loop_modes(g, loop):
         od, osg, _, _ = oracle.single_source(g.row_ptr, g.col_idx, int(src[i]), with_delta=False)
         assert np.array_equal(dist[i], od)
         check_sigma(sigma[i], osg)
+
+
+@pytest.mark.parametrize("g", [gg.grid_full(17, 23), gg.rmat(12, 8, seed=1), gg.complete(40)],
+                         ids=lambda g: g.name)
+def test_device_loop_repeats_bit_for_bit(g):
+    """The device-resident loop, run eight times on all sources: every run gives
+    the oracle's BC and the same bits (its waves hand data to one another only
+    across workgroup barriers; a race would show as run-to-run differences)."""
+    src = np.arange(g.n, dtype=np.int32)
+    want = oracle_bc(g, src)
+    with bcm.Graph(g.n, g.row_ptr, g.col_idx) as G:
+        runs = [batched(G, src, level_loop=bcm.BC_LOOP_DEVICE) for _ in range(8)]
+    check_bc(runs[0], want)
+    for r in runs[1:]:
+        assert np.array_equal(r, runs[0])
