@@ -105,7 +105,7 @@ typedef struct bc_options {
                             setting (bc_autotune's choice, else 64)                      */
     int32_t concurrency; /* batched mode: batches run at once, each with its own
                             workspace and stream, 1..8 (0 = by workspace size: 4 up to
-                            1 GB, 2 up to 8 GB, else 1); BC is the sum of the parts in
+                            1 GB, 2 up to 16 GB, else 1); BC is the sum of the parts in
                             a fixed order, identical from run to run for one setting   */
     int32_t level_loop;  /* batched mode: BC_LOOP_* (who drives the level loop)           */
     int32_t reserved[2]; /* must be zero                                                 */

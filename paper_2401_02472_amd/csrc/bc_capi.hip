@@ -1232,7 +1232,7 @@ int32_t parts_of(const bc_graph_s *g, int32_t concurrency, int32_t nbatches) {
     int32_t p = concurrency;
     if (p <= 0) {
         const size_t ws = batch_ws_bytes(g) + batch_level_bytes(g, 16);
-        p = ws <= ((size_t)1 << 30) ? 4 : (ws <= ((size_t)8 << 30) ? 2 : 1);
+        p = ws <= ((size_t)1 << 30) ? 4 : (ws <= ((size_t)16 << 30) ? 2 : 1);
     }
     return std::max(1, std::min(p, nbatches));
 }

@@ -6,8 +6,9 @@
 //
 // pr[u] / outdeg(u) is kept per vertex (contrib, written with the rank), so
 // an arc costs one 8-byte gather.  Sums run over the reversed CSR in the
-// work layout of the batched BC kernels: vertices of degree <= 64 one lane
-// each (arcs in CSR order), vertices up to 512 arcs one wave each (tree sum),
+// work layout of the batched BC kernels: vertices of degree <= 64 64 at a
+// time with their arcs flattened into runs of 64 (a segmented scan per run),
+// vertices up to 512 arcs one wave each (tree sum),
 // larger ones one wave per 512-arc chunk with the chunks' partial sums added
 // in chunk order by a second kernel.  The change is summed per wave into
 // slots that a third kernel adds in slot order, so every result repeats bit
@@ -79,13 +80,37 @@ __global__ __launch_bounds__(kBlock) void k_pr_pull(PrDev d, int32_t iter) {
                 change += settle_rank(d, v, s, pr, pr_next, contrib_next);
             }
         } else {
+            // 64 vertices of degree <= 64: their arcs flattened into runs of 64
+            // (coalesced index reads, 64 gathers per load), each run summed per
+            // vertex by a segmented scan and added to the vertex's lane
             const int32_t v = d.big_end + (int32_t)(it - d.items_in) * kWave + lane;
+            int32_t rs = 0, cnt = 0;
             if (v < d.n) {
-                double s = 0.0;
-                for (int32_t e = d.row_ptr_in[v]; e < d.row_ptr_in[v + 1]; ++e)
-                    s += contrib[d.col_idx_in[e]];
-                change += settle_rank(d, v, s, pr, pr_next, contrib_next);
+                rs = d.row_ptr_in[v];
+                cnt = d.row_ptr_in[v + 1] - rs;
             }
+            uint32_t total;
+            const uint32_t excl = wave_excl_scan((uint32_t)cnt, total);
+            double s = 0.0;
+            for (uint32_t c0 = 0; c0 < total; c0 += kWave) {
+                const uint32_t a = c0 + (uint32_t)lane;
+                const int o = owner_lane(excl, a);
+                const int32_t o_rs = __shfl(rs, o);
+                const uint32_t o_excl = __shfl(excl, o);
+                double x = a < total ? contrib[d.col_idx_in[o_rs + (int32_t)(a - o_excl)]] : 0.0;
+#pragma unroll
+                for (int off = 1; off < kWave; off <<= 1) {
+                    const double y = __shfl_up(x, off);
+                    const int oy = __shfl_up(o, off);
+                    if (lane >= off && oy == o) x += y;
+                }
+                // the vertex's arcs in this run end at lane hi - 1 - c0
+                const uint32_t lo = excl > c0 ? excl : c0;
+                const uint32_t hi = min(excl + (uint32_t)cnt, c0 + (uint32_t)kWave);
+                const double part = __shfl(x, hi > lo ? (int)(hi - 1 - c0) : 0);
+                if (hi > lo) s += part;
+            }
+            if (v < d.n) change += settle_rank(d, v, s, pr, pr_next, contrib_next);
         }
     }
     report_diff(d, 0, change);
