@@ -29,8 +29,13 @@
 // lane, loaded together), one wavefront per chunk; chunks of one vertex are
 // combined by exact FP64 atomic adds of integer sigma (forward) or by partial
 // rows summed in chunk order (reverse).  Vertices of degree <= 64 are taken 64
-// at a time: the wavefront flattens their arcs into runs of 64 and walks the
-// hits in vertex order.  Every sum has a fixed order except the forward
+// at a time: the wavefront flattens their arcs into runs of 64 (one arc per
+// lane), transposes each run's 64 x 64 arc-by-source hit matrix with lane
+// shuffles, and each lane then walks the arcs that count for its own source
+// in arc order, one running sum per vertex.  A load thus serves 64 sources on
+// 64 different arcs, so it stays full where few sources share an arc (deep,
+// sparse levels) instead of serving one arc's few sources.  Every sum has a
+// fixed order except the forward
 // combine of split vertices, which adds integers exactly; results are
 // identical from run to run.
 #include "bc_internal.h"
@@ -104,43 +109,45 @@ __device__ __forceinline__ void gather_hits(uint64_t hit, int32_t nb, uint64_t m
     }
 }
 
-// Take up to kUnroll of the lanes set in `hit` (lowest first; each holds a
-// neighbour id `nb`, a lane mask `m` and an owner lane `o`) and load their
-// rows together: x[u] = val[nb_u][lane] when lane is in m_u, else 0.  The
-// owners and masks come back wave-uniform (oj[u] = -1 past the last hit), so
-// the caller can fold the values into per-owner sums in arc order.
-template <typename V>
-__device__ __forceinline__ void gather_run(uint64_t &hit, int32_t nb, uint64_t m, int o,
-                                           const V *val, double (&x)[kUnroll],
-                                           uint64_t (&mj)[kUnroll], int (&oj)[kUnroll],
-                                           Work &wk) {
+// Visit, in arc order, the arcs of one run of 64 flattened arcs that are this
+// lane's: bit j of `col` set when arc j (neighbour id `nb` and owner lane `o`
+// held by lane j) counts for this lane's source.  Up to kUnroll values
+// val[nb_j][lane] are loaded at once, one neighbour per lane, then passed to
+// take(owner, value) in arc order.  `col` comes from the transpose of the
+// run's per-arc source masks, so a load serves 64 sources on different arcs
+// instead of the sources of one arc.
+template <typename V, typename Take>
+__device__ __forceinline__ void walk_own(uint64_t col, int32_t nb, int o, const V *val, Work &wk,
+                                         Take &&take) {
     const int lane = lane_id();
-    int32_t vj[kUnroll];
+    while (__ballot(col != 0ull)) {
+        int j[kUnroll];
+        bool on[kUnroll];
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
-        if (hit) {
-            const int j = __ffsll((unsigned long long)hit) - 1;
-            hit &= hit - 1;
-            vj[u] = __shfl(nb, j);
-            mj[u] = shfl64(m, j);
-            oj[u] = __shfl(o, j);
-        } else {
-            vj[u] = 0;
-            mj[u] = 0ull;
-            oj[u] = -1;
+        for (int u = 0; u < kUnroll; ++u) {
+            on[u] = col != 0ull;
+            j[u] = on[u] ? __ffsll((unsigned long long)col) - 1 : 0;
+            col &= col - 1;
+        }
+        int32_t vj[kUnroll];
+        int oj[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            vj[u] = __shfl(nb, j[u]);  // every lane active here
+            oj[u] = __shfl(o, j[u]);
+        }
+        V raw[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            raw[u] = 0;
+            if (on[u]) raw[u] = val[(size_t)vj[u] * kWave + lane];
+        }
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            if (on[u]) take(oj[u], (double)raw[u]);
+            wk.hits += on[u] ? 1u : 0u;
         }
     }
-    // raw loads first (all in flight), conversions after
-    V raw[kUnroll];
-#pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
-        const bool on = (mj[u] >> lane) & 1ull;
-        raw[u] = 0;
-        if (on) raw[u] = val[(size_t)vj[u] * kWave + lane];
-        wk.hits += on ? 1u : 0u;
-    }
-#pragma unroll
-    for (int u = 0; u < kUnroll; ++u) x[u] = (double)raw[u];
 }
 
 // Probe the arcs first + 64*u + lane (u < kProbe, below `end`) of one vertex:
@@ -319,31 +326,31 @@ fwd_group(const BatchDev &d, int32_t L, int32_t base, const int32_t *list, int32
         vis = d.vis[me];
         rs = d.row_ptr_in[me];
         const int32_t re = d.row_ptr_in[me + 1];
-        if (!list) FN[me] = 0ull;
         cnt = vis != full ? re - rs : 0;
     }
     uint32_t total;
     const uint32_t excl = wave_excl_scan((uint32_t)cnt, total);
     const uint64_t unvis = ~vis & full;
-    int cur = -1;        // owner lane being accumulated
+    // Each lane (source) keeps its own running sum and owner, walking its
+    // parent arcs in arc order (owners ascending); see walk_own.
+    int cur = -1;             // owner lane being summed by this lane
     double acc = 0.0;
-    uint64_t nw = 0;
+    uint64_t owners = 0;      // owner lanes this lane found parents for
     auto flush = [&]() {
-        if (cur >= 0 && nw) {
-            const int32_t w = __shfl(me, cur);                   // all lanes active here
-            const uint64_t w_vis = ~shfl64(unvis, cur) & full;
-            const int32_t w_deg = __shfl(cnt, cur);
-            if ((nw >> lane) & 1ull) {
-                store_sigma<N>(d, (size_t)w * kWave + lane, acc * xsc, fr);
-                ++wk.owners;
-            }
-            if (lane == 0) {
-                FN[w] = nw;
-                d.vis[w] = w_vis | nw;
-                ++fr.cnt;
-                fr.arcs += (unsigned long long)w_deg;
-            }
+        if (cur >= 0) {
+            const int32_t w = list ? list[base + cur] : base + cur;
+            store_sigma<N>(d, (size_t)w * kWave + lane, acc * xsc, fr);
+            ++wk.owners;
         }
+    };
+    auto take = [&](int ow, double x) {
+        if (ow != cur) {
+            flush();
+            cur = ow;
+            acc = 0.0;
+            owners |= 1ull << cur;
+        }
+        acc += x;
     };
     for (uint32_t c0 = 0; c0 < total; c0 += kWave * kRounds) {
         // kRounds runs of 64 arcs: ids, then masks, loaded together
@@ -368,31 +375,21 @@ fwd_group(const BatchDev &d, int32_t L, int32_t base, const int32_t *list, int32
             wk.arcs += live[r] ? 1u : 0u;
         }
 #pragma unroll
-        for (int r = 0; r < kRounds; ++r) {
-            uint64_t hit = __ballot(m[r] != 0ull);
-            while (hit) {
-                // kUnroll parent rows in flight at once, whatever their
-                // owners; then folded into the owners' sums in arc order
-                double x[kUnroll];
-                uint64_t mj[kUnroll];
-                int oj[kUnroll];
-                gather_run(hit, nb[r], m[r], o[r], SigRows<N>::rows(d), x, mj, oj, wk);
-#pragma unroll
-                for (int u = 0; u < kUnroll; ++u) {
-                    if (oj[u] < 0) break;
-                    if (oj[u] != cur) {
-                        flush();
-                        cur = oj[u];
-                        acc = 0.0;
-                        nw = 0;
-                    }
-                    acc += x[u];
-                    nw |= mj[u];
-                }
-            }
-        }
+        for (int r = 0; r < kRounds; ++r)
+            if (__ballot(m[r] != 0ull))
+                walk_own(transpose64(m[r]), nb[r], o[r], SigRows<N>::rows(d), wk, take);
     }
     flush();
+    // lane i: the sources that reached its vertex at L+1
+    const uint64_t nw = transpose64(owners);
+    if (me >= 0) {
+        FN[me] = nw;
+        if (nw) {
+            d.vis[me] = vis | nw;
+            ++fr.cnt;
+            fr.arcs += (unsigned long long)cnt;
+        }
+    }
 }
 
 template <bool N>
@@ -754,19 +751,26 @@ __device__ __forceinline__ void bwd_group(const BatchDev &d, int32_t L, int32_t 
     uint32_t total;
     const uint32_t excl = wave_excl_scan((uint32_t)cnt, total);
     wk.owners += (uint32_t)__popcll((unsigned long long)mv);
-    // owners with lanes at level L but no children are completed at the end
-    uint64_t pending = __ballot(mv != 0ull);
+    // Each lane (source) sums c over its own children arcs in arc order
+    // (see walk_own); a finished sum (times the level's scale) is parked in
+    // the owner's coef entry, which no wave reads during this level (it is
+    // read only where the owner sits at level L + 1, and written only where
+    // it sits at L).  The owners are completed afterwards, one wave-wide
+    // settle each, from those sums and their sigma rows.
     int cur = -1;
     double acc = 0.0;
-    double cur_sig = 1.0;   // sigma of the owner being accumulated (its lanes)
-    // BC shares of the group's owners, held by the owner's lane and added in
-    // one parallel read-modify-write at the end (a load per owner otherwise
-    // stalls the wave)
-    double my_bc = 0.0;
+    uint64_t owners = 0;      // owner lanes this lane found children for
     auto flush = [&]() {
-        if (cur < 0) return;
-        const double tot = settle_deferred<N>(d, base + cur, shfl64(mv, cur), cur_sig, acc * xsc);
-        if (lane == cur) my_bc = tot;  // all lanes active here
+        if (cur >= 0) d.coef[(size_t)(base + cur) * kWave + lane] = acc * xsc;
+    };
+    auto take = [&](int ow, double x) {
+        if (ow != cur) {
+            flush();
+            cur = ow;
+            acc = 0.0;
+            owners |= 1ull << cur;
+        }
+        acc += x;
     };
     for (uint32_t c0 = 0; c0 < total; c0 += kWave * kRounds) {
         int o[kRounds];
@@ -789,30 +793,48 @@ __device__ __forceinline__ void bwd_group(const BatchDev &d, int32_t L, int32_t 
             wk.arcs += live[r] ? 1u : 0u;
         }
 #pragma unroll
-        for (int r = 0; r < kRounds; ++r) {
-            uint64_t hit = __ballot(m[r] != 0ull);
-            while (hit) {
-                double x[kUnroll];
-                uint64_t mj[kUnroll];
-                int oj[kUnroll];
-                gather_run(hit, nb[r], m[r], o[r], d.coef, x, mj, oj, wk);
-#pragma unroll
-                for (int u = 0; u < kUnroll; ++u) {
-                    if (oj[u] < 0) break;
-                    if (oj[u] != cur) {
-                        flush();
-                        cur = oj[u];
-                        acc = 0.0;
-                        pending &= ~(1ull << cur);
-                        const bool on = (shfl64(mv, cur) >> lane) & 1ull;
-                        cur_sig = on ? sig_at<N>(d, (size_t)(base + cur) * kWave + lane) : 1.0;
-                    }
-                    acc += x[u];
-                }
-            }
-        }
+        for (int r = 0; r < kRounds; ++r)
+            if (__ballot(m[r] != 0ull))
+                walk_own(transpose64(m[r]), nb[r], o[r], d.coef, wk, take);
     }
     flush();
+    // lane t: the sources for which owner t has children
+    const uint64_t touched = transpose64(owners);
+    // BC shares of the group's owners, held by the owner's lane and added in
+    // one parallel read-modify-write at the end (a load per owner otherwise
+    // stalls the wave)
+    double my_bc = 0.0;
+    uint64_t busy = __ballot(touched != 0ull);
+    while (busy) {
+        int t[kUnroll];
+        uint64_t mt[kUnroll];
+        double x[kUnroll], sg[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            t[u] = -1;
+            if (busy) {
+                t[u] = __ffsll((unsigned long long)busy) - 1;
+                busy &= busy - 1;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            const int tt = t[u] < 0 ? 0 : t[u];
+            mt[u] = t[u] < 0 ? 0ull : shfl64(mv, tt);
+            const uint64_t tu = shfl64(touched, tt);
+            const bool on = (mt[u] >> lane) & 1ull;
+            const size_t at = (size_t)(base + tt) * kWave + lane;
+            x[u] = (on && ((tu >> lane) & 1ull)) ? d.coef[at] : 0.0;
+            sg[u] = on ? sig_at<N>(d, at) : 1.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            if (t[u] < 0) break;  // wave-uniform
+            const double tot = settle_deferred<N>(d, base + t[u], mt[u], sg[u], x[u]);
+            if (lane == t[u]) my_bc = tot;
+        }
+    }
+    uint64_t pending = __ballot(mv != 0ull && touched == 0ull);
     // owners without any child: delta = 0, c = 1 / sigma, nothing for BC
     while (pending) {
         int32_t vj[kUnroll];

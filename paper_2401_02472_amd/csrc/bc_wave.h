@@ -53,4 +53,22 @@ __device__ __forceinline__ int owner_lane(uint32_t excl, uint32_t a) {
     return o;
 }
 
+// Transpose of a 64x64 bit matrix held one row per lane (bit j of lane i's
+// value = entry (i, j)): lane i receives column i.  Six butterfly stages, each
+// swapping the off-diagonal k x k blocks of every 2k x 2k block.
+__device__ __forceinline__ uint64_t transpose64(uint64_t row) {
+    const int lane = lane_id();
+    const uint64_t keep[6] = {0x00000000FFFFFFFFull, 0x0000FFFF0000FFFFull, 0x00FF00FF00FF00FFull,
+                              0x0F0F0F0F0F0F0F0Full, 0x3333333333333333ull, 0x5555555555555555ull};
+#pragma unroll
+    for (int st = 0, k = 32; st < 6; ++st, k >>= 1) {
+        const uint32_t lo = __shfl_xor((uint32_t)row, k);
+        const uint32_t hi = __shfl_xor((uint32_t)(row >> 32), k);
+        const uint64_t p = ((uint64_t)hi << 32) | lo;
+        if (lane & k) row = (row & ~keep[st]) | ((p >> k) & keep[st]);
+        else row = (row & keep[st]) | ((p & keep[st]) << k);
+    }
+    return row;
+}
+
 }  // namespace bcx
