@@ -2259,15 +2259,19 @@ bc_status bc_autotune(bc_graph_t g, const int32_t *sources, int32_t k, void *str
         return timed([&]() { return batched_run(g, sources, m, d_bc, width, div, 1, BC_LOOP_AUTO,
                                                 stream, nullptr, nullptr); }, ms);
     };
-    // sparse-step threshold at width 64, then width 32 with the best threshold
-    const int32_t divs[] = {-1, 16, 64, 256};
+    // sparse-step threshold at width 64 (the default first), then width 32
+    // with the best threshold; a setting replaces the current choice only when
+    // it is more than 2 % faster (on one sample batch, near-equal settings
+    // swap places from run to run)
+    constexpr double kTuneMargin = 0.98;
+    const int32_t divs[] = {kDefaultSparseDiv, -1, 16, 256};
     double best_ms = 1e30;
     int32_t best_div = kDefaultSparseDiv, best_width = kWave;
     for (int32_t div : divs) {
         double ms = 0;
         st = batched(kWave, div, ms);
         if (st != BC_OK) break;
-        if (ms < best_ms) {
+        if (div == kDefaultSparseDiv || ms < best_ms * kTuneMargin) {
             best_ms = ms;
             best_div = div;
         }
@@ -2275,7 +2279,7 @@ bc_status bc_autotune(bc_graph_t g, const int32_t *sources, int32_t k, void *str
     if (st == BC_OK && m > 32) {
         double ms = 0;
         st = batched(32, best_div, ms);
-        if (st == BC_OK && ms < best_ms) {
+        if (st == BC_OK && ms < best_ms * kTuneMargin) {
             best_ms = ms;
             best_width = 32;
         }
