@@ -47,6 +47,10 @@ namespace {
 constexpr int kProbe = 8;    // arcs per lane probed together in a chunk item
 constexpr int kUnroll = 8;   // neighbour rows gathered concurrently
 constexpr int kRounds = 2;   // runs of 64 flattened arcs probed together in a group item
+// a reverse group whose owners carry at least this many sources on average
+// reads its children's c rows arc by arc (bwd_runs_rows), else source by
+// source (bwd_runs_lanes)
+constexpr int kDenseOwner = 8;
 
 // Per-lane work counters, reported only when measurement is switched on:
 // owners = (vertex, source) pairs completed, arcs = arcs probed, hits =
@@ -107,6 +111,45 @@ __device__ __forceinline__ void gather_hits(uint64_t hit, int32_t nb, uint64_t m
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) acc += x[u];
     }
+}
+
+// Take up to kUnroll of the lanes set in `hit` (lowest first; each holds a
+// neighbour id `nb`, a lane mask `m` and an owner lane `o`) and load their
+// rows together: x[u] = val[nb_u][lane] when lane is in m_u, else 0.  The
+// owners and masks come back wave-uniform (oj[u] = -1 past the last hit), so
+// the caller can fold the values into per-owner sums in arc order.
+template <typename V>
+__device__ __forceinline__ void gather_run(uint64_t &hit, int32_t nb, uint64_t m, int o,
+                                           const V *val, double (&x)[kUnroll],
+                                           uint64_t (&mj)[kUnroll], int (&oj)[kUnroll],
+                                           Work &wk) {
+    const int lane = lane_id();
+    int32_t vj[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+        if (hit) {
+            const int j = __ffsll((unsigned long long)hit) - 1;
+            hit &= hit - 1;
+            vj[u] = __shfl(nb, j);
+            mj[u] = shfl64(m, j);
+            oj[u] = __shfl(o, j);
+        } else {
+            vj[u] = 0;
+            mj[u] = 0ull;
+            oj[u] = -1;
+        }
+    }
+    // raw loads first (all in flight), conversions after
+    V raw[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+        const bool on = (mj[u] >> lane) & 1ull;
+        raw[u] = 0;
+        if (on) raw[u] = val[(size_t)vj[u] * kWave + lane];
+        wk.hits += on ? 1u : 0u;
+    }
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) x[u] = (double)raw[u];
 }
 
 // Visit, in arc order, the arcs of one run of 64 flattened arcs that are this
@@ -733,30 +776,84 @@ __device__ __forceinline__ void bwd_chunk(const BatchDev &d, int32_t L, uint32_t
     else settle<N>(d, v, mv, sig, acc * xsc);
 }
 
+// The runs of a reverse group, arc by arc: up to kUnroll hit arcs' c rows
+// loaded for all 64 sources at once, folded into one owner's sum at a time
+// (the wave switches owner in arc order) and each owner completed when the
+// next one starts.  For groups whose owners carry many sources each.
 template <bool N>
-__device__ __forceinline__ void bwd_group(const BatchDev &d, int32_t L, int32_t base, double xsc,
-                                          Work &wk) {
+__device__ __forceinline__ void bwd_runs_rows(const BatchDev &d, const uint64_t *FC, int32_t base,
+                                              uint64_t mv, int32_t rs, uint32_t excl,
+                                              uint32_t total, double xsc, Work &wk,
+                                              uint64_t &pending, double &my_bc) {
     const int lane = lane_id();
-    const uint64_t *FL = d.F + (size_t)L * (size_t)d.n;
-    const uint64_t *FC = d.F + (size_t)(L + 1) * (size_t)d.n;
-    const int32_t me = base + lane;
-    uint64_t mv = 0;
-    int32_t rs = 0, cnt = 0;
-    if (me < d.n) {
-        mv = FL[me];
-        rs = d.row_ptr[me];
-        const int32_t re = d.row_ptr[me + 1];
-        cnt = mv ? re - rs : 0;
+    int cur = -1;
+    double acc = 0.0;
+    double cur_sig = 1.0;   // sigma of the owner being accumulated (its lanes)
+    auto flush = [&]() {
+        if (cur < 0) return;
+        const double tot = settle_deferred<N>(d, base + cur, shfl64(mv, cur), cur_sig, acc * xsc);
+        if (lane == cur) my_bc = tot;  // all lanes active here
+    };
+    for (uint32_t c0 = 0; c0 < total; c0 += kWave * kRounds) {
+        int o[kRounds];
+        int32_t nb[kRounds];
+        uint64_t m[kRounds];
+        bool live[kRounds];
+#pragma unroll
+        for (int r = 0; r < kRounds; ++r) {
+            const uint32_t a = c0 + (uint32_t)(r * kWave + lane);
+            o[r] = owner_lane(excl, a);
+            const int32_t o_rs = __shfl(rs, o[r]);
+            const uint32_t o_excl = __shfl(excl, o[r]);
+            live[r] = a < total;
+            nb[r] = live[r] ? d.col_idx[o_rs + (int32_t)(a - o_excl)] : 0;
+        }
+#pragma unroll
+        for (int r = 0; r < kRounds; ++r) {
+            const uint64_t o_keep = shfl64(mv, o[r]);
+            m[r] = live[r] ? FC[nb[r]] & o_keep : 0ull;
+            wk.arcs += live[r] ? 1u : 0u;
+        }
+#pragma unroll
+        for (int r = 0; r < kRounds; ++r) {
+            uint64_t hit = __ballot(m[r] != 0ull);
+            while (hit) {
+                double x[kUnroll];
+                uint64_t mj[kUnroll];
+                int oj[kUnroll];
+                gather_run(hit, nb[r], m[r], o[r], d.coef, x, mj, oj, wk);
+#pragma unroll
+                for (int u = 0; u < kUnroll; ++u) {
+                    if (oj[u] < 0) break;
+                    if (oj[u] != cur) {
+                        flush();
+                        cur = oj[u];
+                        acc = 0.0;
+                        pending &= ~(1ull << cur);
+                        const bool on = (shfl64(mv, cur) >> lane) & 1ull;
+                        cur_sig = on ? sig_at<N>(d, (size_t)(base + cur) * kWave + lane) : 1.0;
+                    }
+                    acc += x[u];
+                }
+            }
+        }
     }
-    uint32_t total;
-    const uint32_t excl = wave_excl_scan((uint32_t)cnt, total);
-    wk.owners += (uint32_t)__popcll((unsigned long long)mv);
-    // Each lane (source) sums c over its own children arcs in arc order
-    // (see walk_own); a finished sum (times the level's scale) is parked in
-    // the owner's coef entry, which no wave reads during this level (it is
-    // read only where the owner sits at level L + 1, and written only where
-    // it sits at L).  The owners are completed afterwards, one wave-wide
-    // settle each, from those sums and their sigma rows.
+    flush();
+}
+
+// The runs of a reverse group, source by source: each lane sums c over its
+// own children arcs in arc order (see walk_own); a finished sum (times the
+// level's scale) is parked in the owner's c entry, which no wave reads during
+// this level (it is read only where the owner sits at level L + 1, and
+// written only where it sits at L).  The owners are completed afterwards, one
+// wave-wide settle each, from those sums and their sigma rows.  For groups
+// whose owners carry few sources each (deep, sparse levels).
+template <bool N>
+__device__ __forceinline__ void bwd_runs_lanes(const BatchDev &d, const uint64_t *FC, int32_t base,
+                                               uint64_t mv, int32_t rs, uint32_t excl,
+                                               uint32_t total, double xsc, Work &wk,
+                                               uint64_t &pending, double &my_bc) {
+    const int lane = lane_id();
     int cur = -1;
     double acc = 0.0;
     uint64_t owners = 0;      // owner lanes this lane found children for
@@ -800,11 +897,8 @@ __device__ __forceinline__ void bwd_group(const BatchDev &d, int32_t L, int32_t 
     flush();
     // lane t: the sources for which owner t has children
     const uint64_t touched = transpose64(owners);
-    // BC shares of the group's owners, held by the owner's lane and added in
-    // one parallel read-modify-write at the end (a load per owner otherwise
-    // stalls the wave)
-    double my_bc = 0.0;
     uint64_t busy = __ballot(touched != 0ull);
+    pending &= ~busy;
     while (busy) {
         int t[kUnroll];
         uint64_t mt[kUnroll];
@@ -834,7 +928,37 @@ __device__ __forceinline__ void bwd_group(const BatchDev &d, int32_t L, int32_t 
             if (lane == t[u]) my_bc = tot;
         }
     }
-    uint64_t pending = __ballot(mv != 0ull && touched == 0ull);
+}
+
+template <bool N>
+__device__ __forceinline__ void bwd_group(const BatchDev &d, int32_t L, int32_t base, double xsc,
+                                          Work &wk) {
+    const int lane = lane_id();
+    const uint64_t *FL = d.F + (size_t)L * (size_t)d.n;
+    const uint64_t *FC = d.F + (size_t)(L + 1) * (size_t)d.n;
+    const int32_t me = base + lane;
+    uint64_t mv = 0;
+    int32_t rs = 0, cnt = 0;
+    if (me < d.n) {
+        mv = FL[me];
+        rs = d.row_ptr[me];
+        const int32_t re = d.row_ptr[me + 1];
+        cnt = mv ? re - rs : 0;
+    }
+    uint32_t total;
+    const uint32_t excl = wave_excl_scan((uint32_t)cnt, total);
+    const int pairs = wave_sum_int(__popcll((unsigned long long)mv));
+    wk.owners += (uint32_t)__popcll((unsigned long long)mv);
+    // owners with lanes at level L but no children are completed at the end
+    uint64_t pending = __ballot(mv != 0ull);
+    // BC shares of the group's owners, held by the owner's lane and added in
+    // one parallel read-modify-write at the end (a load per owner otherwise
+    // stalls the wave)
+    double my_bc = 0.0;
+    if (pairs >= kDenseOwner * __popcll(pending))
+        bwd_runs_rows<N>(d, FC, base, mv, rs, excl, total, xsc, wk, pending, my_bc);
+    else
+        bwd_runs_lanes<N>(d, FC, base, mv, rs, excl, total, xsc, wk, pending, my_bc);
     // owners without any child: delta = 0, c = 1 / sigma, nothing for BC
     while (pending) {
         int32_t vj[kUnroll];

@@ -53,6 +53,12 @@ __device__ __forceinline__ int owner_lane(uint32_t excl, uint32_t a) {
     return o;
 }
 
+__device__ __forceinline__ int wave_sum_int(int x) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off);
+    return x;
+}
+
 // Transpose of a 64x64 bit matrix held one row per lane (bit j of lane i's
 // value = entry (i, j)): lane i receives column i.  Six butterfly stages, each
 // swapping the off-diagonal k x k blocks of every 2k x 2k block.
