@@ -30,12 +30,12 @@
 // combined by exact FP64 atomic adds of integer sigma (forward) or by partial
 // rows summed in chunk order (reverse).  Vertices of degree <= 64 are taken 64
 // at a time: the wavefront flattens their arcs into runs of 64 (one arc per
-// lane), transposes each run's 64 x 64 arc-by-source hit matrix with lane
-// shuffles, and each lane then walks the arcs that count for its own source
-// in arc order, one running sum per vertex.  A load thus serves 64 sources on
-// 64 different arcs, so it stays full where few sources share an arc (deep,
-// sparse levels) instead of serving one arc's few sources.  Every sum has a
-// fixed order except the forward
+// lane) and walks the hits either arc by arc (one row for all sources per
+// load) or, where arcs carry few sources each (deep, sparse levels), source by
+// source: each run's 64 x 64 arc-by-source hit matrix is transposed with lane
+// shuffles and each lane walks the arcs that count for its own source, so a
+// load serves 64 sources on 64 different arcs.  Either way a lane adds its
+// values in arc order.  Every sum has a fixed order except the forward
 // combine of split vertices, which adds integers exactly; results are
 // identical from run to run.
 #include "bc_internal.h"
@@ -51,6 +51,10 @@ constexpr int kRounds = 2;   // runs of 64 flattened arcs probed together in a g
 // reads its children's c rows arc by arc (bwd_runs_rows), else source by
 // source (bwd_runs_lanes)
 constexpr int kDenseOwner = 8;
+// a forward group whose first run's hit arcs carry at least this many
+// sources on average reads parent rows arc by arc (fwd_runs_rows), else
+// source by source (fwd_runs_lanes)
+constexpr int kDenseArc = 4;
 
 // Per-lane work counters, reported only when measurement is switched on:
 // owners = (vertex, source) pairs completed, arcs = arcs probed, hits =
@@ -346,36 +350,98 @@ __device__ __forceinline__ void fwd_chunk(const BatchDev &d, int32_t L, uint32_t
     }
 }
 
-// Group item: 64 vertices, either base .. base+63 (dense step: all of degree
-// <= 64, F_{L+1} written for every one) or list[base .. base+63] (sparse step:
-// candidates of any degree, F_{L+1} cleared beforehand).  The wave flattens
-// the arcs of the vertices that still have unvisited lanes into runs of 64.
+// Forward runs of a group item, arc by arc: up to kUnroll hit arcs' sigma
+// rows loaded for all 64 sources at once and folded into one owner's sum at a
+// time (the wave switches owner in arc order); an owner's counts, F_{L+1} and
+// vis entries are stored when the next owner starts.  For groups whose arcs
+// carry many sources each.
 template <bool N>
-__device__ __forceinline__ void
-fwd_group(const BatchDev &d, int32_t L, int32_t base, const int32_t *list, int32_t count,
-          uint64_t full, double xsc, Work &wk, Front &fr) {
+__device__ __forceinline__ void fwd_runs_rows(const BatchDev &d, const uint64_t *FL, uint64_t *FN,
+                                              int32_t me, int32_t rs, int32_t cnt, uint32_t excl,
+                                              uint32_t total, uint64_t unvis, uint64_t full,
+                                              double xsc, Work &wk, Front &fr) {
     const int lane = lane_id();
-    const uint64_t *FL = d.F + (size_t)L * (size_t)d.n;
-    uint64_t *FN = d.F + (size_t)(L + 1) * (size_t)d.n;
-    int32_t me = -1;
-    if (list) {
-        if (base + lane < count) me = list[base + lane];
-    } else if (base + lane < d.n) {
-        me = base + lane;
+    int cur = -1;        // owner lane being accumulated
+    double acc = 0.0;
+    uint64_t nw = 0;
+    auto flush = [&]() {
+        if (cur >= 0 && nw) {
+            const int32_t w = __shfl(me, cur);                   // all lanes active here
+            const uint64_t w_vis = ~shfl64(unvis, cur) & full;
+            const int32_t w_deg = __shfl(cnt, cur);
+            if ((nw >> lane) & 1ull) {
+                store_sigma<N>(d, (size_t)w * kWave + lane, acc * xsc, fr);
+                ++wk.owners;
+            }
+            if (lane == 0) {
+                FN[w] = nw;
+                d.vis[w] = w_vis | nw;
+                ++fr.cnt;
+                fr.arcs += (unsigned long long)w_deg;
+            }
+        }
+    };
+    for (uint32_t c0 = 0; c0 < total; c0 += kWave * kRounds) {
+        // kRounds runs of 64 arcs: ids, then masks, loaded together
+        int o[kRounds];
+        int32_t nb[kRounds];
+        uint64_t m[kRounds];
+        bool live[kRounds];
+#pragma unroll
+        for (int r = 0; r < kRounds; ++r) {
+            const uint32_t a = c0 + (uint32_t)(r * kWave + lane);
+            o[r] = owner_lane(excl, a);
+            // cross-lane reads first, with every lane active
+            const int32_t o_rs = __shfl(rs, o[r]);
+            const uint32_t o_excl = __shfl(excl, o[r]);
+            live[r] = a < total;
+            nb[r] = live[r] ? d.col_idx_in[o_rs + (int32_t)(a - o_excl)] : 0;
+        }
+#pragma unroll
+        for (int r = 0; r < kRounds; ++r) {
+            const uint64_t o_keep = shfl64(unvis, o[r]);
+            m[r] = live[r] ? FL[nb[r]] & o_keep : 0ull;
+            wk.arcs += live[r] ? 1u : 0u;
+        }
+#pragma unroll
+        for (int r = 0; r < kRounds; ++r) {
+            uint64_t hit = __ballot(m[r] != 0ull);
+            while (hit) {
+                // kUnroll parent rows in flight at once, whatever their
+                // owners; then folded into the owners' sums in arc order
+                double x[kUnroll];
+                uint64_t mj[kUnroll];
+                int oj[kUnroll];
+                gather_run(hit, nb[r], m[r], o[r], SigRows<N>::rows(d), x, mj, oj, wk);
+#pragma unroll
+                for (int u = 0; u < kUnroll; ++u) {
+                    if (oj[u] < 0) break;
+                    if (oj[u] != cur) {
+                        flush();
+                        cur = oj[u];
+                        acc = 0.0;
+                        nw = 0;
+                    }
+                    acc += x[u];
+                    nw |= mj[u];
+                }
+            }
+        }
     }
-    uint64_t vis = full;
-    int32_t rs = 0, cnt = 0;
-    if (me >= 0) {
-        vis = d.vis[me];
-        rs = d.row_ptr_in[me];
-        const int32_t re = d.row_ptr_in[me + 1];
-        cnt = vis != full ? re - rs : 0;
-    }
-    uint32_t total;
-    const uint32_t excl = wave_excl_scan((uint32_t)cnt, total);
-    const uint64_t unvis = ~vis & full;
-    // Each lane (source) keeps its own running sum and owner, walking its
-    // parent arcs in arc order (owners ascending); see walk_own.
+    flush();
+}
+
+// Forward runs of a group item, source by source: each lane keeps its own
+// running sum and owner and walks its parent arcs in arc order (owners
+// ascending; see walk_own); F_{L+1} and vis are written per vertex at the end.
+// For groups whose arcs carry few sources each (deep, sparse levels).
+template <bool N>
+__device__ __forceinline__ void fwd_runs_lanes(const BatchDev &d, const uint64_t *FL, uint64_t *FN,
+                                               int32_t base, const int32_t *list, int32_t me,
+                                               uint64_t vis, int32_t rs, int32_t cnt,
+                                               uint32_t excl, uint32_t total, uint64_t unvis,
+                                               double xsc, Work &wk, Front &fr) {
+    const int lane = lane_id();
     int cur = -1;             // owner lane being summed by this lane
     double acc = 0.0;
     uint64_t owners = 0;      // owner lanes this lane found parents for
@@ -432,6 +498,57 @@ fwd_group(const BatchDev &d, int32_t L, int32_t base, const int32_t *list, int32
             ++fr.cnt;
             fr.arcs += (unsigned long long)cnt;
         }
+    }
+}
+
+// Group item: 64 vertices, either base .. base+63 (dense step: all of degree
+// <= 64, F_{L+1} written for every one) or list[base .. base+63] (sparse step:
+// candidates of any degree, F_{L+1} cleared beforehand).  The wave flattens
+// the arcs of the vertices that still have unvisited lanes into runs of 64;
+// the first run's masks choose the walk: by rows when its hit arcs carry at
+// least kDenseArc sources on average, else by lanes.
+template <bool N>
+__device__ __forceinline__ void
+fwd_group(const BatchDev &d, int32_t L, int32_t base, const int32_t *list, int32_t count,
+          uint64_t full, double xsc, Work &wk, Front &fr) {
+    const int lane = lane_id();
+    const uint64_t *FL = d.F + (size_t)L * (size_t)d.n;
+    uint64_t *FN = d.F + (size_t)(L + 1) * (size_t)d.n;
+    int32_t me = -1;
+    if (list) {
+        if (base + lane < count) me = list[base + lane];
+    } else if (base + lane < d.n) {
+        me = base + lane;
+    }
+    uint64_t vis = full;
+    int32_t rs = 0, cnt = 0;
+    if (me >= 0) {
+        vis = d.vis[me];
+        rs = d.row_ptr_in[me];
+        const int32_t re = d.row_ptr_in[me + 1];
+        cnt = vis != full ? re - rs : 0;
+    }
+    uint32_t total;
+    const uint32_t excl = wave_excl_scan((uint32_t)cnt, total);
+    const uint64_t unvis = ~vis & full;
+    bool rows = true;
+    if (total > 0) {
+        const uint32_t a = (uint32_t)lane;
+        const int o = owner_lane(excl, a);
+        const int32_t o_rs = __shfl(rs, o);
+        const uint32_t o_excl = __shfl(excl, o);
+        const uint64_t o_keep = shfl64(unvis, o);
+        uint64_t m = 0ull;
+        if (a < total) m = FL[d.col_idx_in[o_rs + (int32_t)(a - o_excl)]] & o_keep;
+        const int hits = __popcll((unsigned long long)__ballot(m != 0ull));
+        rows = wave_sum_int(__popcll((unsigned long long)m)) >= kDenseArc * hits;
+    }
+    if (rows) {
+        if (!list && me >= 0) FN[me] = 0ull;
+        fwd_runs_rows<N>(d, FL, FN, me, rs, cnt, excl, total, unvis, full, xsc, wk, fr);
+    } else {
+        fwd_runs_lanes<N>(d, FL, FN, base, list, me, vis, rs, cnt, excl, total, unvis, xsc, wk,
+                          fr);
     }
 }
 
