@@ -378,3 +378,54 @@ def test_device_loop_repeats_bit_for_bit(g):
     check_bc(runs[0], want)
     for r in runs[1:]:
         assert np.array_equal(r, runs[0])
+
+
+def _clique_and_grid(k=48, side=48):
+    """A k-clique (vertices 0..k-1) joined by six edges to a side x side grid:
+    the clique's arcs carry most sources of a batch at once, the grid's deep
+    levels one or two each."""
+    src, dst = [], []
+    for a in range(k):
+        for b in range(a + 1, k):
+            src.append(a)
+            dst.append(b)
+    for r in range(side):
+        for c in range(side):
+            v = k + r * side + c
+            if c + 1 < side:
+                src.append(v)
+                dst.append(v + 1)
+            if r + 1 < side:
+                src.append(v)
+                dst.append(v + side)
+    for i in range(6):
+        src.append(i)
+        dst.append(k + i * (side * side // 6))
+    return gg.csr_from_edges(k + side * side, src, dst, name=f"clique{k}+grid{side}")
+
+
+@pytest.mark.parametrize("loop,div", [(bcm.BC_LOOP_HOST, -1), (bcm.BC_LOOP_HOST, 64),
+                                      (bcm.BC_LOOP_DEVICE, 64)],
+                         ids=["host-scan", "host-sparse", "device"])
+def test_dense_and_sparse_groups_in_one_run(loop, div):
+    """Batches whose level steps mix 64-vertex groups with dense hit masks (the
+    clique: parent and child rows read arc by arc) and sparse ones (the grid's
+    deep levels: the transposed, source-by-source walk): BC, dist and sigma
+    equal the oracle's whichever walk a group takes, and repeat bit for bit."""
+    g = _clique_and_grid()
+    rng = np.random.default_rng(40)
+    src = np.concatenate([rng.choice(48, 30, replace=False),
+                          48 + rng.choice(g.n - 48, 70, replace=False)]).astype(np.int32)
+    rng.shuffle(src)
+    opt = bcm.make_options(bcm.BC_MODE_BATCHED, level_loop=loop, sparse_div=div)
+    with bcm.Graph(g.n, g.row_ptr, g.col_idx) as G:
+        got = batched(G, src, level_loop=loop, sparse_div=div)
+        again = batched(G, src, level_loop=loop, sparse_div=div)
+        _, dist, sigma = G.run_detail(src, opt)
+    check_bc(got, oracle_bc(g, src))
+    assert np.array_equal(got, again)
+    for i in (0, 17, 63, 64, 99):
+        od, osg, _, st = oracle.single_source(g.row_ptr, g.col_idx, int(src[i]), with_delta=False)
+        assert st == oracle.OK
+        assert np.array_equal(dist[i], od), f"dist differs for lane {i} (source {src[i]})"
+        check_sigma(sigma[i], osg)
