@@ -9,11 +9,13 @@
 //
 //   F_L[v]   64-bit mask, bit s set when v is at distance L from source s
 //   vis[v]   64-bit mask of the sources that have reached v
-//   sigma[v][s], c[v][s]   lane-major rows of 64 doubles (512 bytes)
+//   sigma[v][s]   lane-major rows of 64 counts: uint32 (256 bytes) while
+//                 every count fits 32 bits, else doubles
+//   c[v][s]       lane-major rows of 64 doubles (512 bytes)
 //
 // Forward iteration L (pull): for every vertex w with lanes still unvisited
 // and every neighbour v, m = F_L[v] & ~vis[w] are the sources for which v is a
-// parent of w; lane s adds sigma[v][s] for s in m (a coalesced row read), and
+// parent of w; lane s adds sigma[v][s] for s in m (see the walks below), and
 // the union of the m is the set of sources reaching w at level L+1.  The
 // neighbour ids and masks are probed once per arc for all 64 sources.
 //
@@ -503,7 +505,8 @@ __device__ __forceinline__ void fwd_runs_lanes(const BatchDev &d, const uint64_t
 
 // Group item: 64 vertices, either base .. base+63 (dense step: all of degree
 // <= 64, F_{L+1} written for every one) or list[base .. base+63] (sparse step:
-// candidates of any degree, F_{L+1} cleared beforehand).  The wave flattens
+// the step's candidates of degree <= 64, F_{L+1} cleared beforehand; larger
+// candidates come as chunk items).  The wave flattens
 // the arcs of the vertices that still have unvisited lanes into runs of 64;
 // the first run's masks choose the walk: by rows when its hit arcs carry at
 // least kDenseArc sources on average, else by lanes.
