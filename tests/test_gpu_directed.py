@@ -138,3 +138,48 @@ def test_directed_rmat22_full_size_one_batch():
         assert np.array_equal(dist[i], od)
         check_sigma(sigma[i], osg)
     check_bc(got, oracle_dir(g, src))
+
+
+def _dclique_and_grid(k=48, side=40, seed=41):
+    """A k-clique with arcs both ways, joined both ways to a side x side grid
+    whose edges are one-way (random direction) or two-way: dense hit masks in
+    the clique, sparse ones on the grid's deep levels, in both directions of
+    the walk (forward over in-arcs, reverse over out-arcs)."""
+    rng = np.random.default_rng(seed)
+    pairs = [(a, b) for a in range(k) for b in range(k) if a != b]
+    for r in range(side):
+        for c in range(side):
+            v = k + r * side + c
+            for w in ([v + 1] if c + 1 < side else []) + ([v + side] if r + 1 < side else []):
+                x = rng.integers(3)
+                if x != 1:
+                    pairs.append((v, w))
+                if x != 0:
+                    pairs.append((w, v))
+    for i in range(6):
+        t = k + i * (side * side // 6)
+        pairs += [(i, t), (t, i)]
+    return gg.directed(k + side * side, pairs, f"dclique{k}+grid{side}")
+
+
+@pytest.mark.parametrize("loop", [bcm.BC_LOOP_HOST, bcm.BC_LOOP_DEVICE], ids=["host", "device"])
+def test_directed_dense_and_sparse_groups(loop):
+    """Directed batches whose groups take both walks in one run: BC, dist and
+    sigma equal the directed oracle's, and the run repeats bit for bit."""
+    g = _dclique_and_grid()
+    rng = np.random.default_rng(42)
+    src = np.concatenate([rng.choice(48, 30, replace=False),
+                          48 + rng.choice(g.n - 48, 70, replace=False)]).astype(np.int32)
+    rng.shuffle(src)
+    with dgraph(g) as G:
+        got = run_mode(G, src, bcm.BC_MODE_BATCHED, level_loop=loop)
+        again = run_mode(G, src, bcm.BC_MODE_BATCHED, level_loop=loop)
+        _, dist, sigma = G.run_detail(src, bcm.make_options(bcm.BC_MODE_BATCHED, level_loop=loop))
+    check_bc(got, oracle_dir(g, src))
+    assert np.array_equal(got, again)
+    for i in (0, 17, 63, 64, 99):
+        od, osg, _, st = oracle.single_source(g.row_ptr, g.col_idx, int(src[i]), with_delta=False,
+                                              directed=True)
+        assert st == oracle.OK
+        assert np.array_equal(dist[i], od), f"dist differs for lane {i} (source {src[i]})"
+        check_sigma(sigma[i], osg)
