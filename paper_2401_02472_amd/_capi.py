@@ -14,6 +14,8 @@ import threading
 from . import build as _build
 
 LIB_PATH = _build.LIB_PATH
+# BC_MI355X_CHECK_EXEC=1 loads the check build instead (see build.py)
+CHECK_EXEC = os.environ.get("BC_MI355X_CHECK_EXEC", "") == "1"
 
 BC_OK = 0
 BC_ERR_INVALID_ARG = 1
@@ -83,9 +85,10 @@ def load():
     with _lock:
         if _lib is not None:
             return _lib
-        if not os.path.exists(LIB_PATH):
-            _build.build()
-        lib = ctypes.CDLL(LIB_PATH)
+        path = _build.CHECK_LIB_PATH if CHECK_EXEC else LIB_PATH
+        if not os.path.exists(path):
+            _build.build(check_exec=CHECK_EXEC)
+        lib = ctypes.CDLL(path)
         i32p = ctypes.POINTER(ctypes.c_int32)
         i64p = ctypes.POINTER(ctypes.c_int64)
         f64p = ctypes.POINTER(ctypes.c_double)
@@ -114,6 +117,9 @@ def load():
             fn = getattr(lib, name)
             fn.argtypes = args
             fn.restype = ctypes.c_int
+        if CHECK_EXEC:
+            lib.bc_debug_exec_partial.argtypes = []
+            lib.bc_debug_exec_partial.restype = ctypes.c_uint
         lib.bc_status_str.argtypes = [ctypes.c_int]
         lib.bc_status_str.restype = ctypes.c_char_p
         _lib = lib

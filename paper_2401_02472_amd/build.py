@@ -8,7 +8,10 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB_PATH = os.path.join(HERE, "libbc_mi355x.so")
+# the same library with the cross-lane exec checks compiled in (BC_CHECK_EXEC)
+CHECK_LIB_PATH = os.path.join(HERE, "libbc_mi355x_check.so")
 SOURCES = ["bc_graph.hip", "bc_plain.hip", "bc_batched.hip", "bc_sssp.hip", "bc_pagerank.hip",
+           "bc_rt_graph.hip", "bc_rt_plain.hip", "bc_rt_batched.hip", "bc_rt_algos.hip", "bc_tune.hip",
            "bc_capi.hip"]
 
 HIPCC_FLAGS = [
@@ -24,17 +27,22 @@ HIPCC_FLAGS = [
 ]
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, check_exec: bool = False) -> str:
+    """Compile the library; with check_exec, the check build (every cross-lane
+    helper counts calls made with part of a wave inactive)."""
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    tmp = LIB_PATH + ".tmp"
-    cmd = [hipcc, *HIPCC_FLAGS, "-I", os.path.join(ROOT, "include"), "-I", CSRC,
+    out = CHECK_LIB_PATH if check_exec else LIB_PATH
+    tmp = out + ".tmp"
+    cmd = [hipcc, *HIPCC_FLAGS, *(["-DBC_CHECK_EXEC"] if check_exec else []),
+           "-I", os.path.join(ROOT, "include"), "-I", CSRC,
            *[os.path.join(CSRC, s) for s in SOURCES], "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB_PATH)
-    return LIB_PATH
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":
-    print(build(verbose=True))
+    import sys
+    print(build(verbose=True, check_exec="--check-exec" in sys.argv))

@@ -28,18 +28,18 @@
 // pass.
 //
 // Work items: a vertex of degree > 64 is split into chunks of 512 arcs (8 per
-// lane, loaded together), one wavefront per chunk; chunks of one vertex are
-// combined by exact FP64 atomic adds of integer sigma (forward) or by partial
-// rows summed in chunk order (reverse).  Vertices of degree <= 64 are taken 64
+// lane, loaded together), one wavefront per chunk; each chunk of a vertex with
+// several chunks leaves a partial row of per-source sums (forward: parent
+// counts, reverse: child coefficients), which the next kernel adds in chunk
+// order.  Vertices of degree <= 64 are taken 64
 // at a time: the wavefront flattens their arcs into runs of 64 (one arc per
 // lane) and walks the hits either arc by arc (one row for all sources per
 // load) or, where arcs carry few sources each (deep, sparse levels), source by
 // source: each run's 64 x 64 arc-by-source hit matrix is transposed with lane
 // shuffles and each lane walks the arcs that count for its own source, so a
 // load serves 64 sources on 64 different arcs.  Either way a lane adds its
-// values in arc order.  Every sum has a fixed order except the forward
-// combine of split vertices, which adds integers exactly; results are
-// identical from run to run.
+// values in arc order.  Every sum has a fixed order, so results are identical
+// from run to run, also where counts pass 2^53 and additions round.
 #include "bc_internal.h"
 #include "bc_wave.h"
 
@@ -66,6 +66,7 @@ struct Work {
 };
 
 __device__ __forceinline__ void report_work(unsigned long long *out, const Work &wk) {
+    BC_FULL_EXEC();
     unsigned long long o = wk.owners, a = wk.arcs, h = wk.hits;
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) {
@@ -87,6 +88,7 @@ __device__ __forceinline__ void gather_hits(uint64_t hit, int32_t nb, uint64_t m
                                             const V *val, double &acc, Work &wk) {
     const int lane = lane_id();
     while (hit) {
+        BC_FULL_EXEC();
         int32_t vj[kUnroll];
         bool on[kUnroll];
 #pragma unroll
@@ -129,6 +131,7 @@ __device__ __forceinline__ void gather_run(uint64_t &hit, int32_t nb, uint64_t m
                                            const V *val, double (&x)[kUnroll],
                                            uint64_t (&mj)[kUnroll], int (&oj)[kUnroll],
                                            Work &wk) {
+    BC_FULL_EXEC();
     const int lane = lane_id();
     int32_t vj[kUnroll];
 #pragma unroll
@@ -180,6 +183,7 @@ __device__ __forceinline__ void walk_own(uint64_t col, int32_t nb, int o, const 
         }
         int32_t vj[kUnroll];
         int oj[kUnroll];
+        BC_FULL_EXEC();
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
             vj[u] = __shfl(nb, j[u]);  // every lane active here
@@ -231,9 +235,8 @@ __device__ __forceinline__ uint64_t probe_chunk(const int32_t *col, int32_t firs
 // (narrow: half the bytes per gathered row) while every count fits; a count
 // that does not fit raises kCtlNarrow and the batch is run again with double
 // rows (wide), where a count beyond double's range raises kCtlRange.  A split
-// vertex's chunks add their partial sums into a double row of its own (exact
-// integer adds in any order, no returned values), which the completion kernel
-// stores into the vertex's sigma row.
+// vertex's chunks leave double partial rows, which the completion kernel adds
+// in chunk order and stores into the vertex's sigma row.
 template <bool N> struct SigRows;
 
 template <> struct SigRows<true> {
@@ -288,6 +291,7 @@ struct Front {
 template <bool N>
 __device__ __forceinline__ void report_front(const BatchDev &d, int set, int32_t L,
                                              const Front &fr) {
+    BC_FULL_EXEC();
     if (!N && d.xmax && fr.smax > 0.0)
         atomicMax(&d.xmax[(size_t)(L + 1) * kWave + lane_id()],
                   (unsigned long long)__double_as_longlong(fr.smax));
@@ -325,6 +329,9 @@ __device__ __forceinline__ void fwd_chunk(const BatchDev &d, int32_t L, uint32_t
     uint64_t *FN = d.F + (size_t)(L + 1) * (size_t)d.n;
     const uint64_t vis = d.vis[w];
     const uint64_t unvis = ~vis & full;
+    // (vis of a split vertex changes only in the completion kernel, so all of
+    // its chunks agree here; with nothing to discover none writes a row and
+    // the completion skips the vertex)
     if (unvis == 0ull) {
         if (!multi && lane == 0) FN[w] = 0ull;
         return;
@@ -346,9 +353,11 @@ __device__ __forceinline__ void fwd_chunk(const BatchDev &d, int32_t L, uint32_t
                 fr.arcs += (unsigned long long)(re - rs);
             }
         }
-    } else if (nw) {
-        if (mine) unsafeAtomicAdd(&d.hubsig[(size_t)w * kWave + lane], acc);
-        if (lane == 0) atomicOr((unsigned long long *)&d.reach[w], (unsigned long long)nw);
+    } else {
+        // every lane's sum (0 without parents in this chunk), for the
+        // completion kernel to add in chunk order
+        d.partial[(size_t)item * kWave + lane] = acc;
+        if (nw && lane == 0) atomicOr((unsigned long long *)&d.reach[w], (unsigned long long)nw);
     }
 }
 
@@ -368,6 +377,7 @@ __device__ __forceinline__ void fwd_runs_rows(const BatchDev &d, const uint64_t 
     uint64_t nw = 0;
     auto flush = [&]() {
         if (cur >= 0 && nw) {
+            BC_FULL_EXEC();
             const int32_t w = __shfl(me, cur);                   // all lanes active here
             const uint64_t w_vis = ~shfl64(unvis, cur) & full;
             const int32_t w_deg = __shfl(cnt, cur);
@@ -576,8 +586,9 @@ __global__ __launch_bounds__(kBlock) void k_batch_forward(BatchDev d, int32_t L,
     if (d.stats) report_work(d.stats, wk);
 }
 
-// After a forward iteration: completes the split vertices (their summed
-// counts, F_{L+1}, vis) and counts them into the new frontier.
+// After a forward iteration: completes the split vertices (their counts = the
+// chunks' partial rows added in chunk order, F_{L+1}, vis) and counts them
+// into the new frontier.
 template <bool N>
 __device__ __forceinline__ void finish_split(const BatchDev &d, int32_t L, int32_t wave,
                                              int32_t nwaves, double xsc, Front &fr) {
@@ -587,10 +598,18 @@ __device__ __forceinline__ void finish_split(const BatchDev &d, int32_t L, int32
         const uint64_t nw = d.reach[w];
         if (lane == 0) FN[w] = nw;
         if (nw == 0ull) continue;
-        if ((nw >> lane) & 1ull) {
-            const size_t at = (size_t)w * kWave + lane;
-            store_sigma<N>(d, at, d.hubsig[at] * xsc, fr);
+        const uint32_t i0 = d.item_first_in[w], i1 = d.item_first_in[w + 1];
+        double t = 0.0;
+        uint32_t i = i0;
+        for (; i + 8 <= i1; i += 8) {  // 8 rows in flight
+            double x[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) x[q] = d.partial[(size_t)(i + q) * kWave + lane];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) t += x[q];
         }
+        for (; i < i1; ++i) t += d.partial[(size_t)i * kWave + lane];
+        if ((nw >> lane) & 1ull) store_sigma<N>(d, (size_t)w * kWave + lane, t * xsc, fr);
         if (lane == 0) {
             d.vis[w] |= nw;
             d.reach[w] = 0ull;
@@ -832,6 +851,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_sparse_pull(BatchDev d, int32_
 // does not depend on where in the batch its lanes sit; it is added to the
 // request's output in caller vertex order.
 __device__ __forceinline__ void add_segments(const BatchDev &d, int32_t v, double delta) {
+    BC_FULL_EXEC();
     const int lane = lane_id();
     for (int32_t g = 0; g < d.nseg; ++g) {
         const int32_t a = d.seg_start[g], len = d.seg_start[g + 1] - a;
@@ -853,6 +873,7 @@ __device__ __forceinline__ void add_segments(const BatchDev &d, int32_t v, doubl
 template <bool N>
 __device__ __forceinline__ double settle_deferred(const BatchDev &d, int32_t v, uint64_t mv,
                                                   double sig, double acc) {
+    BC_FULL_EXEC();
     const int lane = lane_id();
     const bool on = (mv >> lane) & 1ull;
     const double delta = on ? sig * acc : 0.0;
@@ -1253,7 +1274,6 @@ __global__ __launch_bounds__(kFusedBlock) void k_batch_fused(const BatchDev *dev
         if (d.nseg == 0) d.bc[i] = 0.0;
     }
     for (int32_t i = t; i < d.multi_end; i += kFusedBlock) d.reach[i] = 0ull;
-    for (int64_t i = t; i < (int64_t)d.multi_end * kWave; i += kFusedBlock) d.hubsig[i] = 0.0;
     if (t < kCtlInts) d.ctrl[t] = 0;
     __syncthreads();
     // seed
@@ -1322,8 +1342,7 @@ __global__ __launch_bounds__(kFusedBlock) void k_batch_fused(const BatchDev *dev
 
 // ---- batch set-up and export ------------------------------------------------
 
-// vis = 0 and F_0 = 0 everywhere; the split vertices' sigma rows and reach
-// masks are cleared for the atomic combine.
+// vis = 0 and F_0 = 0 everywhere; the split vertices' reach masks cleared.
 template <bool N>
 __global__ void k_batch_clear(BatchDev d) {
     const int32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1336,8 +1355,6 @@ __global__ void k_batch_clear(BatchDev d) {
     const int32_t groups = (d.n + 15) >> 4;
     for (int32_t i = tid; i < groups; i += stride)
         reinterpret_cast<uint4 *>(d.cand)[i] = make_uint4(0u, 0u, 0u, 0u);
-    const int64_t rows = (int64_t)d.multi_end * kWave;
-    for (int64_t i = tid; i < rows; i += stride) d.hubsig[i] = 0.0;
     // the range flag stays set over the run's batches (the host clears it)
     if (blockIdx.x == 0 && threadIdx.x < kCtlInts && threadIdx.x != kCtlRange)
         d.ctrl[threadIdx.x] = 0;
@@ -1408,6 +1425,10 @@ int grid_of(int64_t waves) {
 constexpr int kSparseGrid = kMaxGridBlocks;  // blocks of the sparse mark / pull kernels
 
 }  // namespace
+
+#ifdef BC_CHECK_EXEC
+unsigned int exec_partial_batched() { return exec_partial_take(); }
+#endif
 
 hipError_t batch_start(const BatchDev &d, const int32_t *src_dev, int32_t nlanes,
                        hipStream_t stream) {

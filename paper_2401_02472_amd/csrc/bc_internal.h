@@ -111,11 +111,12 @@ struct BatchDev {
     uint64_t *F;           // [lcap][n] F[L][v]: sources at distance L from v
     double *sigma;         // [n][64] path counts as doubles (wide rows)
     uint32_t *sigma32;     // [n][64] the same memory as exact uint32 counts (narrow rows)
-    double *hubsig;        // [multi_end][64] split vertices' sums, added by their chunks
     int32_t narrow;        // 1: sigma32 rows are in use
     double *coef;          // [n][64] (1 + delta) / sigma
     uint64_t *reach;       // [multi_end] sources reaching a split vertex this iteration
-    double *partial;       // [items][64] reverse child sums per chunk item
+    double *partial;       // [max(items, items_in)][64] per-chunk-item sums: the
+                           // forward pass's parent counts of split vertices
+                           // (items_in), the reverse pass's child sums (items)
     int32_t *ctrl;         // see kCtl* below
     // sparse forward step: cand marks the neighbours of the frontier (1 byte
     // per vertex, padded to 16); clist lists the marked vertices of degree
@@ -164,6 +165,15 @@ enum {
 constexpr int kMaxGridBlocks = 2048;
 constexpr int kFrontWaves = kMaxGridBlocks * kWavesPerBlock;
 constexpr int kFrontSets = 3;
+
+#ifdef BC_CHECK_EXEC
+// Check builds: each kernel file's count of cross-lane helper calls made with
+// part of a wave inactive since the last read (see BC_FULL_EXEC in bc_wave.h).
+unsigned int exec_partial_batched();
+unsigned int exec_partial_plain();
+unsigned int exec_partial_sssp();
+unsigned int exec_partial_pagerank();
+#endif
 
 // Launchers (bc_batched.hip).  All are asynchronous on `stream`.
 // Clear the batch state and seed lane s with source src_dev[s], s < nlanes.

@@ -172,6 +172,10 @@ int waves_blocks(int64_t waves) {
 
 }  // namespace
 
+#ifdef BC_CHECK_EXEC
+unsigned int exec_partial_pagerank() { return exec_partial_take(); }
+#endif
+
 hipError_t pagerank_init(const PrDev &d, int32_t max_iter, hipStream_t stream) {
     const int64_t m = d.n > max_iter ? d.n : max_iter;
     int64_t b = (m + kBlock - 1) / kBlock;

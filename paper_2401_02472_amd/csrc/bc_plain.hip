@@ -34,31 +34,12 @@
 //     no device-scope fences are needed), and results are identical from run
 //     to run.
 #include "bc_internal.h"
+#include "bc_wave.h"
 
 namespace bcx {
 namespace {
 
 constexpr int kBatch = 8;  // independent loads in flight per lane and batch
-
-__device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
-
-__device__ __forceinline__ double wave_sum(double x) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off);
-    return x;
-}
-
-__device__ __forceinline__ uint32_t wave_excl_scan(uint32_t x, uint32_t &total) {
-    const int lane = lane_id();
-    uint32_t incl = x;
-#pragma unroll
-    for (int off = 1; off < kWave; off <<= 1) {
-        const uint32_t y = __shfl_up(incl, off);
-        if (lane >= off) incl += y;
-    }
-    total = __shfl(incl, kWave - 1);
-    return incl - x;
-}
 
 __device__ __forceinline__ uint32_t lev_code(const uint32_t *lev3, int32_t v) {
     return (lev3[v >> 4] >> ((v & 15) << 1)) & 3u;
@@ -534,6 +515,10 @@ int grid_for(int64_t items, int cap) {
 }
 
 }  // namespace
+
+#ifdef BC_CHECK_EXEC
+unsigned int exec_partial_plain() { return exec_partial_take(); }
+#endif
 
 hipError_t plain_reset_run(const PlainDev &d, hipStream_t stream) {
     hipLaunchKernelGGL(k_reset_run, dim3(grid_for((d.n + 15) / 16, 1024)), dim3(kBlock), 0,

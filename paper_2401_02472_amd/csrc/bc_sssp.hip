@@ -170,6 +170,10 @@ int blocks_for(int64_t n) {
 
 }  // namespace
 
+#ifdef BC_CHECK_EXEC
+unsigned int exec_partial_sssp() { return exec_partial_take(); }
+#endif
+
 hipError_t sssp_init(int32_t n, int32_t *dist, int32_t *stamp, int32_t src, hipStream_t stream) {
     hipLaunchKernelGGL(k_sssp_init, dim3(blocks_for(n)), dim3(kBlock), 0, stream, n, dist, stamp,
                        src);

@@ -429,3 +429,84 @@ def test_dense_and_sparse_groups_in_one_run(loop, div):
         assert st == oracle.OK
         assert np.array_equal(dist[i], od), f"dist differs for lane {i} (source {src[i]})"
         check_sigma(sigma[i], osg)
+
+
+def _hub_past_2_53(m=1100):
+    """Source 0 reaches vertex A through 60 diamonds in series (sigma 2^60, level
+    120) and vertices u_b, b < 11, through a path then b + 8 diamonds (sigma
+    2^(b+8), level 120).  Parent p_j (j = 1..m) is joined to A and to u_b for
+    every bit b of j, so sigma(p_j) = 2^60 + 256 j: distinct, exact in double
+    and beyond 2^53.  Hub H is joined to every p_j: degree m > 1024, so it is
+    split into chunks of 512 arcs (A too), and sigma(H), a sum of m values near
+    2^60, rounds.  Returns (graph, A, H, [u_b])."""
+    src, dst = [], []
+    nxt = [1]
+
+    def new():
+        v = nxt[0]
+        nxt[0] += 1
+        return v
+
+    def diamonds(start, count):
+        v = start
+        for _ in range(count):
+            a, b, e = new(), new(), new()
+            src.extend([v, v, a, b])
+            dst.extend([a, b, e, e])
+            v = e
+        return v
+
+    A = diamonds(0, 60)
+    us = []
+    for b in range(11):
+        v = 0
+        for _ in range(120 - 2 * (b + 8)):
+            w = new()
+            src.append(v)
+            dst.append(w)
+            v = w
+        us.append(diamonds(v, b + 8))
+    parents = [new() for _ in range(m)]
+    H = new()
+    for j, p in enumerate(parents, start=1):
+        src.extend([p, p])
+        dst.extend([A, H])
+        for b in range(11):
+            if (j >> b) & 1:
+                src.append(p)
+                dst.append(us[b])
+    g = gg.csr_from_edges(nxt[0], np.array(src), np.array(dst), name=f"hub-past-2^53-{m}")
+    return g, A, H, us
+
+
+@pytest.mark.parametrize("loop", [bcm.BC_LOOP_HOST, bcm.BC_LOOP_DEVICE], ids=["host", "device"])
+def test_split_hub_sums_past_2_53_repeat_bit_for_bit(loop):
+    """Split vertices add their chunks' parent counts in chunk order, so a hub
+    whose parents carry distinct counts beyond 2^53 (sums that round) gets the
+    same bits on every run and whatever else shares its batch; sigma within
+    1e-12 and BC within 1e-9 of the oracle."""
+    import torch
+    g, A, H, us = _hub_past_2_53()
+    srcs = np.array([0, A, H, us[3], 5, 77], np.int32)
+    od, osg, _, _ = oracle.single_source(g.row_ptr, g.col_idx, 0, with_delta=False)
+    assert od[H] == 122 and osg[H] > 2.0 ** 63
+    want = oracle_bc(g, srcs)
+    opt = bcm.make_options(bcm.BC_MODE_BATCHED, level_loop=loop)
+    with bcm.Graph(g.n, g.row_ptr, g.col_idx) as G:
+        runs = [batched(G, srcs, level_loop=loop) for _ in range(6)]
+        _, dist, sigma = G.run_detail(srcs, opt)
+        other = gg.sample_sources(g, 40, seed=3)
+        outs = [torch.empty(g.n, dtype=torch.float64, device="cuda") for _ in range(3)]
+        G.run_multi([other[:20], srcs, other[20:]], outs)
+        alone = torch.empty(g.n, dtype=torch.float64, device="cuda")
+        G.run_multi([srcs], [alone])
+        torch.cuda.synchronize()
+    check_bc(runs[0], want)
+    for r in runs[1:]:
+        assert np.array_equal(r, runs[0])
+    assert np.array_equal(outs[1].cpu().numpy(), alone.cpu().numpy())
+    check_bc(alone.cpu().numpy(), want)
+    for i, s in enumerate(srcs):
+        od, osg, _, _ = oracle.single_source(g.row_ptr, g.col_idx, int(s), with_delta=False)
+        assert np.array_equal(dist[i], od)
+        check_sigma(sigma[i], osg)
