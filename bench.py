@@ -30,24 +30,29 @@ METRIC = "BC GTEPS (sources×2m/s) and HBM roofline %; batched vs per-source; p5
 HBM_PEAK_GBS = 8000.0
 
 # Algorithmic bytes per unit of work (element-granular: each array element a
-# kernel must touch, counted once per use), per execution path.
+# kernel must touch, counted once per use), per execution path.  Units are the
+# kernels' own work counters: owners, arcs, hits, and (batched path) vertices
+# examined.
 #   plain forward level kernel, per owner vertex: queue entry 4 + row_ptr
 #     pair 8 + sigma write 8; per arc read: neighbour id 4 + level-code word 4;
 #     per parent arc: parent sigma 8.
 #   plain reverse level kernel, per owner vertex: queue entry 4 + row_ptr pair
 #     8 + sigma 8 + c write 8 + BC read-modify-write 16; per arc: 4 + 4; per
 #     child arc: child c 8.
-#   batched forward kernel (64 sources per probe), per (vertex, source)
-#     discovered: sigma write 8; per arc probed: neighbour id 4 + frontier mask
-#     8; per (arc, source) parent pair: parent sigma 8.
-#   batched reverse kernel, per (vertex, source) at the level: sigma read 8 +
-#     c write 8 (delta, c and BC are completed in the kernel); per arc
-#     probed: 4 + 8; per (arc, source) child pair: child c 8.
+#   batched forward kernel (64 sources per probe), per vertex examined:
+#     visited mask 8 + row_ptr pair 8 + next-level mask write 8; per (vertex,
+#     source) discovered: sigma write 8; per arc probed: neighbour id 4 +
+#     frontier mask 8; per (arc, source) parent pair: parent sigma 8.
+#   batched reverse kernel, per vertex examined: level mask 8 (the scan of F_L
+#     that finds the level's vertices) + row_ptr pair 8; per (vertex, source)
+#     at the level: sigma read 8 + c write 8 (delta, c and BC are completed in
+#     the kernel); per arc probed: 4 + 8; per (arc, source) child pair: child
+#     c 8.
 BYTES = {
     ("plain", "forward"): {"owners": 20, "arcs": 8, "hits": 8},
     ("plain", "reverse"): {"owners": 44, "arcs": 8, "hits": 8},
-    ("batched", "forward"): {"owners": 8, "arcs": 12, "hits": 8},
-    ("batched", "reverse"): {"owners": 16, "arcs": 12, "hits": 8},
+    ("batched", "forward"): {"owners": 8, "arcs": 12, "hits": 8, "vertices": 24},
+    ("batched", "reverse"): {"owners": 16, "arcs": 12, "hits": 8, "vertices": 16},
 }
 # sssp pass kernel: per pass, the stamp of every vertex 4; per vertex whose
 # arcs are relaxed: row_ptr pair 8 + its distance 4; per arc relaxed:
@@ -566,12 +571,9 @@ def main() -> int:
     min_batched = tuning["min_batched"] if tuning else 16
     path = "plain" if mode == bcm.BC_MODE_PLAIN or (mode == bcm.BC_MODE_AUTO and
                                                    k < min_batched) else "batched"
-    # event records are sampled so that they do not slow short launches: the
-    # plain path measures every 16th source, the batched host loop every
-    # stride-th level (all levels up to 16 deep; about 8 per pass beyond)
-    stride = 16 if path == "plain" else profile_stride(g, int(sources[0]))
-    G.profile_enable(stride)
-    G.profile_read(reset=True)
+    # timed steps: the library's measurement hooks (events around launches,
+    # work counters) are off
+    G.profile_enable(False)
     step_ms = []
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -584,56 +586,80 @@ def main() -> int:
         step_ms.append(start.elapsed_time(stop))
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    prof = G.profile_read(reset=True)
-    G.profile_enable(False)
     ms_per_step = wall * 1e3 / args.steps
     value = k * g.nnz / (ms_per_step / 1e3) / 1e9
     print(f"# timed {args.steps} steps: {ms_per_step:.2f} ms/step", file=sys.stderr, flush=True)
 
+    # measured steps (not part of `value`): events around the launches and the
+    # kernels' work counters.  Event records are sampled so that they do not
+    # slow short launches: the plain path measures every 16th source, the
+    # batched host loop every stride-th level (all levels up to 16 deep; about
+    # 8 per pass beyond).
+    stride = 16 if path == "plain" else profile_stride(g, int(sources[0]))
+
+    def measured(options, steps=2):
+        G.profile_enable(stride)
+        G.profile_read(reset=True)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(steps):
+            G.run_async(sources, out, options)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t) * 1e3 / steps
+        p = G.profile_read(reset=True)
+        G.profile_enable(False)
+        return p, dt, steps
+
+    prof, meas_ms, meas_steps = measured(opt)
+    levels_per_step = prof["levels"] / meas_steps
+
     src_hash = kernel_source_hash()
 
-    def roofline_of(prof, path):
+    def roofline_of(prof, path, ms_step, steps):
         """Dominant kernel of a profile and its roofline point."""
         if prof["fused"]["launches"]:
             # device-resident level loop: one launch runs whole batches, forward
             # and reverse; its bytes are both passes' work counters
             pc = prof["fused"]
             alg_bytes = sum(BYTES[("batched", c)][u] * prof[c][u]
-                            for c in ("forward", "reverse") for u in ("owners", "arcs", "hits"))
+                            for c in ("forward", "reverse") for u in BYTES[("batched", c)])
             kernel_name = "k_batch_fused"
         else:
             cls = max(("forward", "reverse"), key=lambda c: prof[c]["ms"])
             pc = prof[cls]
-            alg_bytes = sum(BYTES[(path, cls)][u] * pc[u] for u in ("owners", "arcs", "hits"))
+            alg_bytes = sum(BYTES[(path, cls)][u] * pc[u] for u in BYTES[(path, cls)])
             kernel_name = KERNELS[(path, cls)]
         launches = max(pc["launches"], 1)
         avg_ms = pc["ms"] / launches
         per_launch = alg_bytes / launches
         achieved = per_launch / (avg_ms / 1e3) / 1e9 if avg_ms > 0 else 0.0
+        # a kernel that runs alone takes at most the step's time: with the
+        # launches of concurrent parts overlapping, it would not
+        kernel_ms_step = pc["ms"] / steps
+        assert kernel_ms_step <= ms_step * 1.001, (
+            f"{kernel_name}: {kernel_ms_step:.3f} ms of launches per {ms_step:.3f} ms step")
         return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": read_traffic(kernel_name, args.workload, src_hash),
                 "kernel": kernel_name, "alg_bytes_per_launch": round(per_launch),
                 "avg_launch_ms": round(avg_ms, 5), "launches": pc["launches"],
+                "kernel_ms_per_step": round(kernel_ms_step, 3),
+                "step_ms": round(ms_step, 3), "steps": steps,
                 "kernel_source_hash": src_hash}
 
     if prof["fused"]["launches"]:
         path = "batched-device-loop"
-    roofline = roofline_of(prof, path)
-    # With concurrent parts (two batches on two streams), a launch's event
-    # duration includes the other part's overlapping kernels: the fraction
-    # above is then a lower bound.  The same point from two extra steps run as
-    # one part (not timed for `value`):
-    roofline_one_part = None
-    if path == "batched" and args.concurrency != 1:
+    # The roofline point comes from steps run as one part: with concurrent
+    # parts (batches on several streams) a launch's event duration also counts
+    # the other parts' kernels running beside it, so it is not the kernel's own.
+    one_part = path == "batched" and args.concurrency != 1
+    if one_part:
         opt1 = bcm.make_options(mode, args.batch_width, sparse_div=args.sparse_div, concurrency=1)
-        G.profile_enable(stride)
-        G.profile_read(reset=True)
-        for _ in range(2):
-            G.run_async(sources, out, opt1)
-        torch.cuda.synchronize()
-        roofline_one_part = roofline_of(G.profile_read(reset=True), path)
-        G.profile_enable(False)
+        roof_prof, roof_ms, roof_steps = measured(opt1)
+    else:
+        roof_prof, roof_ms, roof_steps = prof, meas_ms, meas_steps
+    roofline = roofline_of(roof_prof, path, roof_ms, roof_steps)
+    roofline["measured_as"] = "one part" if one_part else "the benchmarked configuration"
 
     plain_cmp = None
     if args.compare_plain and path.startswith("batched"):
@@ -670,8 +696,11 @@ def main() -> int:
         cpu = cpu_baseline(g, np.asarray(sources, np.int32), args.cpu_seconds)
 
     q = np.percentile(step_ms, [50, 99]) if step_ms else [0.0, 0.0]
-    kernels = {c: {"launches": prof[c]["launches"], "ms": round(prof[c]["ms"], 3)}
+    # per step, from the measured steps of the benchmarked configuration
+    kernels = {c: {"launches": round(prof[c]["launches"] / meas_steps, 1),
+                   "ms": round(prof[c]["ms"] / meas_steps, 3)}
                for c in ("forward", "compact", "reverse", "finish", "fused")}
+    kernels["measured_step_ms"] = round(meas_ms, 3)
     rec = {
         "metric": METRIC, "value": round(value, 3), "unit": "GTEPS", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
@@ -685,10 +714,12 @@ def main() -> int:
                    "autotune": tuning, "graph": g.params},
         "plain_comparison": plain_cmp,
         "profile_level_stride": stride,
+        "level_steps_per_step": round(levels_per_step, 1),
+        "per_level_us": round(ms_per_step * 1e3 / levels_per_step, 2) if levels_per_step else None,
         "reached_arc_gteps": None if ra is None else round(ra / (ms_per_step / 1e3) / 1e9, 3),
         "end_to_end": end_to_end,
         "p50_ms": round(float(q[0]), 3), "p99_ms": round(float(q[1]), 3),
-        "roofline": roofline, "roofline_one_part": roofline_one_part,
+        "roofline": roofline,
         "cpu_baseline": cpu, "kernels": kernels,
     }
     print(json.dumps(rec), flush=True)

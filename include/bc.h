@@ -260,6 +260,12 @@ typedef struct bc_profile {
     int64_t arcs[BC_PROF_CLASSES];
     int64_t hits[BC_PROF_CLASSES];
     int64_t runs;
+    int64_t vertices[BC_PROF_CLASSES]; /* FORWARD / REVERSE of the batched path:
+                                          vertices examined (mask and offsets
+                                          read) */
+    int64_t levels;  /* level steps taken: for every source (one-source path) or
+                        batch (batched path), depth + 1 forward and depth reverse
+                        steps; with P > 1 below, every run still counts all */
 } bc_profile;
 
 /* Switch measurement off (on = 0) or on for runs on g.  With on = P > 1, the

@@ -241,10 +241,11 @@ def bc_profile_read(g: int, reset: bool = False) -> dict:
     p = _capi.bc_profile()
     _check(_capi.load().bc_profile_read(ctypes.c_void_p(g), ctypes.byref(p), int(bool(reset))),
            "bc_profile_read")
-    out = {"runs": int(p.runs)}
+    out = {"runs": int(p.runs), "levels": int(p.levels)}
     for i, name in enumerate(_capi.PROF_CLASS_NAMES):
         out[name] = {"launches": int(p.launches[i]), "ms": float(p.ms[i]),
-                     "owners": int(p.owners[i]), "arcs": int(p.arcs[i]), "hits": int(p.hits[i])}
+                     "owners": int(p.owners[i]), "arcs": int(p.arcs[i]), "hits": int(p.hits[i]),
+                     "vertices": int(p.vertices[i])}
     return out
 
 

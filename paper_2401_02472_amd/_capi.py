@@ -72,7 +72,9 @@ class bc_profile(ctypes.Structure):
                 ("owners", ctypes.c_int64 * BC_PROF_CLASSES),
                 ("arcs", ctypes.c_int64 * BC_PROF_CLASSES),
                 ("hits", ctypes.c_int64 * BC_PROF_CLASSES),
-                ("runs", ctypes.c_int64)]
+                ("runs", ctypes.c_int64),
+                ("vertices", ctypes.c_int64 * BC_PROF_CLASSES),
+                ("levels", ctypes.c_int64)]
 
 
 _lib = None

@@ -60,24 +60,30 @@ constexpr int kDenseArc = 4;
 
 // Per-lane work counters, reported only when measurement is switched on:
 // owners = (vertex, source) pairs completed, arcs = arcs probed, hits =
-// (arc, source) pairs whose row value was gathered.
+// (arc, source) pairs whose row value was gathered, verts = vertices
+// examined (their mask and offsets read: every vertex of a group item, the
+// first chunk of a chunked vertex).
 struct Work {
-    uint32_t owners = 0, arcs = 0, hits = 0;
+    uint32_t owners = 0, arcs = 0, hits = 0, verts = 0;
 };
 
-__device__ __forceinline__ void report_work(unsigned long long *out, const Work &wk) {
+// Adds a wave's counters to stats[base .. base + 2] and stats[vslot].
+__device__ __forceinline__ void report_work(unsigned long long *stats, int base, int vslot,
+                                            const Work &wk) {
     BC_FULL_EXEC();
-    unsigned long long o = wk.owners, a = wk.arcs, h = wk.hits;
+    unsigned long long o = wk.owners, a = wk.arcs, h = wk.hits, v = wk.verts;
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) {
         o += __shfl_xor(o, off);
         a += __shfl_xor(a, off);
         h += __shfl_xor(h, off);
+        v += __shfl_xor(v, off);
     }
-    if (lane_id() == 0 && (o | a | h)) {
-        atomicAdd(&out[0], o);
-        atomicAdd(&out[1], a);
-        atomicAdd(&out[2], h);
+    if (lane_id() == 0 && (o | a | h | v)) {
+        atomicAdd(&stats[base], o);
+        atomicAdd(&stats[base + 1], a);
+        atomicAdd(&stats[base + 2], h);
+        atomicAdd(&stats[vslot], v);
     }
 }
 
@@ -329,6 +335,7 @@ __device__ __forceinline__ void fwd_chunk(const BatchDev &d, int32_t L, uint32_t
     uint64_t *FN = d.F + (size_t)(L + 1) * (size_t)d.n;
     const uint64_t vis = d.vis[w];
     const uint64_t unvis = ~vis & full;
+    if (lane == 0 && j == 0) ++wk.verts;
     // (vis of a split vertex changes only in the completion kernel, so all of
     // its chunks agree here; with nothing to discover none writes a row and
     // the completion skips the vertex)
@@ -541,6 +548,7 @@ fwd_group(const BatchDev &d, int32_t L, int32_t base, const int32_t *list, int32
         const int32_t re = d.row_ptr_in[me + 1];
         cnt = vis != full ? re - rs : 0;
     }
+    wk.verts += me >= 0 ? 1u : 0u;
     uint32_t total;
     const uint32_t excl = wave_excl_scan((uint32_t)cnt, total);
     const uint64_t unvis = ~vis & full;
@@ -583,7 +591,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_forward(BatchDev d, int32_t L,
                           wk, fr);
     }
     report_front<N>(d, 0, L, fr);
-    if (d.stats) report_work(d.stats, wk);
+    if (d.stats) report_work(d.stats, 0, 12, wk);
 }
 
 // After a forward iteration: completes the split vertices (their counts = the
@@ -840,7 +848,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_sparse_pull(BatchDev d, int32_
         else fwd_group<N>(d, L, (it - ni) * kWave, d.clist, c, full, xsc, wk, fr);
     }
     report_front<N>(d, 1, L, fr);
-    if (d.stats) report_work(d.stats, wk);
+    if (d.stats) report_work(d.stats, 0, 12, wk);
 }
 
 // ---- reverse ---------------------------------------------------------------
@@ -904,6 +912,7 @@ __device__ __forceinline__ void bwd_chunk(const BatchDev &d, int32_t L, uint32_t
     const int2 info = d.item_info[item];
     const int32_t v = info.x, j = info.y;
     const uint64_t mv = d.F[(size_t)L * (size_t)d.n + v];
+    if (lane == 0 && j == 0) ++wk.verts;
     if (mv == 0ull) return;
     const uint64_t *FC = d.F + (size_t)(L + 1) * (size_t)d.n;
     const int32_t rs = d.row_ptr[v], re = d.row_ptr[v + 1];
@@ -1090,6 +1099,7 @@ __device__ __forceinline__ void bwd_group(const BatchDev &d, int32_t L, int32_t 
     const uint32_t excl = wave_excl_scan((uint32_t)cnt, total);
     const int pairs = wave_sum_int(__popcll((unsigned long long)mv));
     wk.owners += (uint32_t)__popcll((unsigned long long)mv);
+    wk.verts += me < d.n ? 1u : 0u;
     // owners with lanes at level L but no children are completed at the end
     uint64_t pending = __ballot(mv != 0ull);
     // BC shares of the group's owners, held by the owner's lane and added in
@@ -1138,7 +1148,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_reverse(BatchDev d, int32_t L)
         if (it < items) bwd_chunk<N>(d, L, it, xsc, wk);
         else bwd_group<N>(d, L, d.big_end + (int32_t)(it - items) * kWave, xsc, wk);
     }
-    if (d.stats) report_work(d.stats + 6, wk);
+    if (d.stats) report_work(d.stats, 6, 13, wk);
 }
 
 // Finalise level L for the vertices the reverse kernel leaves open: the split
@@ -1335,8 +1345,8 @@ __global__ __launch_bounds__(kFusedBlock) void k_batch_fused(const BatchDev *dev
         __syncthreads();
     }
     if (d.stats) {
-        report_work(d.stats, wkf);
-        report_work(d.stats + 6, wkr);
+        report_work(d.stats, 0, 12, wkf);
+        report_work(d.stats, 6, 13, wkr);
     }
 }
 

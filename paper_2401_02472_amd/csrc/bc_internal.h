@@ -26,6 +26,12 @@ constexpr int kB1Lanes = 8;
 constexpr int kChunkArcs = 2048;
 constexpr int kBuckets = 4;
 
+// Work counters of measured runs (device, 64-bit each): [0..2] forward
+// owners / arcs / hits, [3] vertices queued by the plain compaction, [6..8]
+// reverse owners / arcs / hits, [9..11] SSSP, [12] / [13] vertices whose
+// arcs the batched forward / reverse kernels walked.
+constexpr int kStatWords = 16;
+
 // The library relabels vertices by degree, descending, when a graph is
 // created, so the buckets are id ranges: [0, b3_end) bucket 3,
 // [b3_end, b2_end) bucket 2, [b2_end, b1_end) bucket 1, the rest bucket 0.
@@ -69,7 +75,8 @@ struct PlainDev {
     LevelRec *lvl;        // [n + 2]
     int32_t *ctrl;        // [0] deepest non-empty level of the current source,
                           // [1] range flag, [2] current source truncated (more
-                          // levels than launched), [3] deepest level of the run
+                          // levels than launched), [3] deepest level of the run,
+                          // [4] sum of the depths of the run's earlier sources
     unsigned long long *stats;  // NULL, or work counters when measuring:
                                 // [0..2] forward owners/arcs/parent arcs,
                                 // [3] vertices queued by the compaction,
@@ -127,8 +134,8 @@ struct BatchDev {
     unsigned long long *front;  // [kFrontSets][kFrontWaves][2]
     int64_t nnz;
     int64_t sparse_arcs;   // a level runs sparse when its frontier has fewer arcs
-    unsigned long long *stats;  // NULL, or work counters when measuring: [0..2]
-                                // forward, [6..8] reverse (owners, arcs, hits)
+    unsigned long long *stats;  // NULL, or work counters when measuring (see
+                                // kStatWords)
     double *bc;            // [n] accumulated BC (internal order), when nseg == 0
     // Several requests in one batch (nseg > 0): lanes [seg_start[g],
     // seg_start[g+1]) feed seg_out[g], an [n] array in caller vertex order.

@@ -441,6 +441,7 @@ __global__ void k_reset_run(PlainDev d) {
         d.ctrl[1] = 0;
         d.ctrl[2] = 0;
         d.ctrl[3] = 0;
+        d.ctrl[4] = 0;
     }
 }
 
@@ -469,6 +470,7 @@ __global__ void k_init_source(PlainDev d, int32_t s) {
         LevelRec r1 = {};
         d.lvl[1] = r1;
         d.sigma[s] = 1.0;
+        d.ctrl[4] += d.ctrl[0];  // the previous source's depth
         d.ctrl[0] = 0;
         d.ctrl[2] = 0;
     }

@@ -61,7 +61,7 @@ bc_status bc_sssp(bc_graph_t g, int32_t source, int32_t *dist_dev, void *stream_
         hipError_t e = hipMalloc(&w.dist, (size_t)g->n * sizeof(int32_t));
         if (e == hipSuccess) e = hipMalloc(&w.stamp, (size_t)g->n * sizeof(int32_t));
         if (e == hipSuccess) e = hipMalloc(&w.flags, 2 * K * sizeof(int32_t));
-        if (e == hipSuccess) e = hipMalloc(&w.d_stats, 12 * sizeof(unsigned long long));
+        if (e == hipSuccess) e = hipMalloc(&w.d_stats, kStatWords * sizeof(unsigned long long));
         if (e == hipSuccess)
             e = hipHostMalloc((void **)&w.h_flags, K * sizeof(int32_t), hipHostMallocDefault);
         if (e != hipSuccess) {
@@ -87,7 +87,7 @@ bc_status bc_sssp(bc_graph_t g, int32_t source, int32_t *dist_dev, void *stream_
     d.dist = w.dist;
     d.stamp = w.stamp;
     hipError_t e = hipSuccess;
-    if (prof) e = hipMemsetAsync(w.d_stats, 0, 12 * sizeof(unsigned long long), stream);
+    if (prof) e = hipMemsetAsync(w.d_stats, 0, kStatWords * sizeof(unsigned long long), stream);
     if (e == hipSuccess) e = sssp_init(g->n, w.dist, w.stamp, g->h_perm[(size_t)source], stream);
     // flag of pass p (1, 2, ...) in block ((p-1)/K) & 1; a block is cleared
     // before its chunk of passes is queued

@@ -20,7 +20,7 @@ size_t batch_ws_bytes(const bc_graph_s *g) {
     b += align_up(n * sizeof(double));                   // bc
     b += align_up((size_t)std::max(g->multi_end, 1) * sizeof(uint64_t));  // reach
     b += align_up(partial_rows(g) * kWave * sizeof(double));  // chunk partial rows
-    b += align_up(12 * sizeof(unsigned long long));     // work counters
+    b += align_up(kStatWords * sizeof(unsigned long long));     // work counters
     b += align_up(n * sizeof(int32_t));                  // candidate list
     // item list of the sparse step (the forward pass's items)
     b += align_up((size_t)std::max<uint32_t>(g->items_in, 1) * sizeof(int32_t));
@@ -92,7 +92,7 @@ bc_status batch_ws_create(bc_graph_s *g, BatchWS **out) {
     d.col_idx_in = g->d_col_idx_in;
     d.item_info_in = g->d_item_info_in;
     d.item_first_in = g->d_item_first_in;
-    ws->d_stats = (unsigned long long *)take(12 * sizeof(unsigned long long));
+    ws->d_stats = (unsigned long long *)take(kStatWords * sizeof(unsigned long long));
     d.stats = nullptr;
     d.clist = (int32_t *)take(n * sizeof(int32_t));
     d.ilist = (int32_t *)take((size_t)std::max<uint32_t>(g->items_in, 1) * sizeof(int32_t));
@@ -168,6 +168,82 @@ bc_status ensure_landmarks(bc_graph_s *g) {
     return BC_OK;
 }
 
+// One batch: clear and seed, the forward levels in chunks with one host poll
+// per chunk, then the reverse levels.  A path count that needs double rows
+// (or the extended range) switches the graph to them and asks for a rerun; a
+// level array too short for the batch asks for a longer one.
+hipError_t drive_batch(bc_graph_s *g, BatchDev &d, const ExtTables &ext, const int32_t *lanes_dev,
+                       int32_t nl, int32_t *h_ctrl, hipStream_t stream, LaunchTimer &timer,
+                       unsigned long long *d_stats, int32_t stride, BatchOutcome &how,
+                       int32_t &deepest) {
+    const int32_t n = g->n;
+    const uint64_t full = nl >= 64 ? ~0ull : ((1ull << nl) - 1ull);
+    const bool prof = d_stats != nullptr;
+    auto measure = [&](int32_t L) {
+        const bool m = prof && L % stride == 0;
+        timer.on = m;
+        d.stats = m ? d_stats : nullptr;
+    };
+    const bool use_ext = g->sigma_ext.load();
+    d.narrow = (use_ext || g->sigma_wide.load()) ? 0 : 1;
+    d.xs = use_ext ? ext.xs : nullptr;
+    d.xmax = use_ext ? ext.xmax : nullptr;
+    d.xe = use_ext ? ext.xe : nullptr;
+    how = BatchOutcome::Done;
+    deepest = 0;
+    hipError_t e = batch_start(d, lanes_dev, nl, stream);
+    if (e != hipSuccess) return e;
+    int32_t L0 = 0;
+    for (;;) {
+        const int32_t K = std::max(2, g->batch_depth_hint.load() + 2);
+        const int32_t Lend = std::min(L0 + K, d.lcap - 1);
+        for (int32_t L = L0; L < Lend && e == hipSuccess; ++L) {
+            measure(L);
+            e = timer.begin(BC_PROF_FORWARD, stream);
+            if (e == hipSuccess) e = batch_forward(d, L, full, stream);
+            if (e == hipSuccess) e = timer.end(stream);
+            if (e == hipSuccess) e = timer.begin(BC_PROF_COMPACT, stream);
+            if (e == hipSuccess) e = batch_forward_done(d, L, full, stream);
+            if (e == hipSuccess) e = timer.end(stream);
+        }
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(h_ctrl, d.ctrl, kBatchCtrlInts * sizeof(int32_t),
+                               hipMemcpyDeviceToHost, stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) return e;
+        deepest = h_ctrl[kCtlDeepest];
+        if (h_ctrl[kCtlNarrow]) {  // a path count needs double rows: run again
+            g->sigma_wide.store(true);
+            how = BatchOutcome::Rerun;
+            return hipSuccess;
+        }
+        if (h_ctrl[kCtlRange] && !use_ext) {  // beyond double: run again level-scaled
+            g->sigma_wide.store(true);
+            g->sigma_ext.store(true);
+            how = BatchOutcome::Rerun;
+            return hipMemsetAsync(d.ctrl + kCtlRange, 0, sizeof(int32_t), stream);
+        }
+        if (h_ctrl[kCtlTrunc]) {
+            how = BatchOutcome::Grow;
+            return hipSuccess;
+        }
+        if (deepest < Lend || Lend >= n) break;
+        L0 = Lend;
+    }
+    for (int32_t L = deepest; L >= 1 && e == hipSuccess; --L) {
+        measure(L);
+        if (L != deepest) {
+            e = timer.begin(BC_PROF_REVERSE, stream);
+            if (e == hipSuccess) e = batch_reverse(d, L, stream);
+            if (e == hipSuccess) e = timer.end(stream);
+        }
+        if (e == hipSuccess) e = timer.begin(BC_PROF_FINISH, stream);
+        if (e == hipSuccess) e = batch_finalize(d, L, L == deepest, stream);
+        if (e == hipSuccess) e = timer.end(stream);
+    }
+    return e;
+}
+
 // One batch of a batched run: lanes [first, first + nlanes) of the run's
 // (internal-id) source list; with nseg > 0, its lanes feed nseg request
 // outputs described from seg_first on in the run's segment tables.
@@ -203,7 +279,7 @@ bc_status run_batch_plan(bc_graph_s *g, const std::vector<int32_t> &s_int,
     // frontier arcs below which a level takes the sparse step (0: never)
     ws->dev.sparse_arcs = sparse_div < 0 ? 0 : g->nnz / std::max(sparse_div, 1);
     if (prof) {
-        hipError_t ez = hipMemsetAsync(ws->d_stats, 0, 12 * sizeof(unsigned long long), stream);
+        hipError_t ez = hipMemsetAsync(ws->d_stats, 0, kStatWords * sizeof(unsigned long long), stream);
         if (ez != hipSuccess) return fail(from_hip(ez));
     }
     st = batch_grow_levels(g, ws, std::max(ws->lcap, g->batch_depth_hint.load() + 8));
@@ -252,85 +328,30 @@ bc_status run_batch_plan(bc_graph_s *g, const std::vector<int32_t> &s_int,
         e = hipMemsetAsync(ws->dev.ctrl + kCtlRange, 0, sizeof(int32_t), stream);
     if (e != hipSuccess) return fail(from_hip(e));
     int32_t range = 0, run_depth = 0;
+    int64_t level_steps = 0;  // forward and reverse, over the batches
     // measurement covers the launches of every stride-th level only (all of
     // them with stride 1): events around every launch slow deep graphs' short
     // level steps
     const int32_t stride = std::max(1, g->profiling.load());
-    auto measure = [&](int32_t L) {
-        const bool m = prof && L % stride == 0;
-        ws->timer.on = m;
-        ws->dev.stats = m ? ws->d_stats : nullptr;
-    };
     for (size_t bi = 0; bi < plan.size();) {
         const BatchPlan &bp = plan[bi];
         const int32_t nl = bp.nlanes;
-        const uint64_t full = nl >= 64 ? ~0ull : ((1ull << nl) - 1ull);
         BatchDev &d = ws->dev;
         d.nseg = bp.nseg;
         d.seg_start = bp.nseg ? d_seg_start + bp.seg_first : nullptr;
         d.seg_out = bp.nseg ? d_seg_out + (bp.seg_first - (int32_t)bi) : nullptr;
         d.iperm = g->d_iperm;
-        const bool ext = g->sigma_ext.load();
-        d.narrow = (ext || g->sigma_wide.load()) ? 0 : 1;
-        d.xs = ext ? ws->xs : nullptr;
-        d.xmax = ext ? ws->xmax : nullptr;
-        d.xe = ext ? ws->xe : nullptr;
-        e = batch_start(d, d_lanes + bp.first, nl, stream);
-        if (e != hipSuccess) return fail(from_hip(e));
+        BatchOutcome how = BatchOutcome::Done;
         int32_t deepest = 0;
-        bool restart = false;
-        int32_t L0 = 0;
-        for (;;) {
-            const int32_t K = std::max(2, g->batch_depth_hint.load() + 2);
-            const int32_t Lend = std::min(L0 + K, ws->lcap - 1);
-            for (int32_t L = L0; L < Lend && e == hipSuccess; ++L) {
-                measure(L);
-                e = ws->timer.begin(BC_PROF_FORWARD, stream);
-                if (e == hipSuccess) e = batch_forward(d, L, full, stream);
-                if (e == hipSuccess) e = ws->timer.end(stream);
-                if (e == hipSuccess) e = ws->timer.begin(BC_PROF_COMPACT, stream);
-                if (e == hipSuccess) e = batch_forward_done(d, L, full, stream);
-                if (e == hipSuccess) e = ws->timer.end(stream);
-            }
-            if (e == hipSuccess)
-                e = hipMemcpyAsync(ws->h_ctrl, d.ctrl, kBatchCtrlInts * sizeof(int32_t),
-                                   hipMemcpyDeviceToHost, stream);
-            if (e == hipSuccess) e = hipStreamSynchronize(stream);
-            if (e != hipSuccess) return fail(from_hip(e));
-            deepest = ws->h_ctrl[0];
-            if (ws->h_ctrl[kCtlNarrow]) {  // a path count needs double rows: run again
-                g->sigma_wide.store(true);
-                restart = true;
-                break;
-            }
-            if (ws->h_ctrl[kCtlRange] && !ext) {  // beyond double: run again level-scaled
-                g->sigma_wide.store(true);
-                g->sigma_ext.store(true);
-                e = hipMemsetAsync(d.ctrl + kCtlRange, 0, sizeof(int32_t), stream);
-                if (e != hipSuccess) return fail(from_hip(e));
-                restart = true;
-                break;
-            }
-            if (ws->h_ctrl[2]) {  // level array full: grow it and run the batch again
-                st = batch_grow_levels(g, ws, ws->lcap * 2);
-                if (st != BC_OK) return fail(st);
-                restart = true;
-                break;
-            }
-            if (deepest < Lend || Lend >= n) break;
-            L0 = Lend;
-        }
-        if (restart) continue;
-        for (int32_t L = deepest; L >= 1 && e == hipSuccess; --L) {
-            measure(L);
-            if (L != deepest) {
-                e = ws->timer.begin(BC_PROF_REVERSE, stream);
-                if (e == hipSuccess) e = batch_reverse(d, L, stream);
-                if (e == hipSuccess) e = ws->timer.end(stream);
-            }
-            if (e == hipSuccess) e = ws->timer.begin(BC_PROF_FINISH, stream);
-            if (e == hipSuccess) e = batch_finalize(d, L, L == deepest, stream);
-            if (e == hipSuccess) e = ws->timer.end(stream);
+        const ExtTables ext{ws->xs, ws->xmax, ws->xe};
+        e = drive_batch(g, d, ext, d_lanes + bp.first, nl, ws->h_ctrl, stream, ws->timer,
+                        prof ? ws->d_stats : nullptr, stride, how, deepest);
+        if (e != hipSuccess) return fail(from_hip(e));
+        if (how == BatchOutcome::Rerun) continue;
+        if (how == BatchOutcome::Grow) {  // level array full: grow it, run the batch again
+            st = batch_grow_levels(g, ws, ws->lcap * 2);
+            if (st != BC_OK) return fail(st);
+            continue;
         }
         if (e == hipSuccess && export_row && (dist || sigma)) {
             e = batch_export(d, deepest, nl, x_dist, x_sigma, stream);
@@ -344,6 +365,7 @@ bc_status run_batch_plan(bc_graph_s *g, const std::vector<int32_t> &s_int,
         if (e != hipSuccess) return fail(from_hip(e));
         range |= ws->h_ctrl[1];
         run_depth = std::max(run_depth, deepest);
+        level_steps += 2 * (int64_t)deepest + 1;
         ++bi;
     }
     ws->dev.nseg = 0;
@@ -355,7 +377,7 @@ bc_status run_batch_plan(bc_graph_s *g, const std::vector<int32_t> &s_int,
     if (e != hipSuccess) return fail(from_hip(e));
     range |= ws->h_ctrl[1];
     if (k > 0) g->batch_depth_hint.store(run_depth);
-    if (prof) accumulate_profile(g, ws->timer, ws->d_stats);
+    if (prof) accumulate_profile(g, ws->timer, ws->d_stats, level_steps);
     batch_release(g, ws, stream);
     return range ? BC_ERR_RANGE : BC_OK;
 }
@@ -530,11 +552,12 @@ bc_status fused_run(bc_graph_s *g, const std::vector<int32_t> &s_int,
     LaunchTimer timer;
     timer.on = prof;
     if (prof) {
-        if (!f.d_stats) BC_TRY_HIP(hipMalloc(&f.d_stats, 12 * sizeof(unsigned long long)));
-        BC_TRY_HIP(hipMemsetAsync(f.d_stats, 0, 12 * sizeof(unsigned long long), stream));
+        if (!f.d_stats) BC_TRY_HIP(hipMalloc(&f.d_stats, kStatWords * sizeof(unsigned long long)));
+        BC_TRY_HIP(hipMemsetAsync(f.d_stats, 0, kStatWords * sizeof(unsigned long long), stream));
     }
     bool range = false;
     int32_t run_depth = 0;
+    int64_t level_steps = 0;  // forward and reverse, over the batches
     std::vector<int2> bt;
     for (int32_t b0 = 0; b0 < nb;) {
         const int32_t m = std::min(f.cap, nb - b0);
@@ -590,6 +613,7 @@ bc_status fused_run(bc_graph_s *g, const std::vector<int32_t> &s_int,
             const int32_t *c = f.h_ctrl + (size_t)i * kCtlInts;
             range |= c[kCtlRange] != 0;
             run_depth = std::max(run_depth, c[kCtlDeepest]);
+            level_steps += 2 * (int64_t)c[kCtlDeepest] + 1;
         }
         if (export_row && (dist || sigma)) {
             for (int32_t i = 0; i < m && e == hipSuccess; ++i) {
@@ -619,7 +643,7 @@ bc_status fused_run(bc_graph_s *g, const std::vector<int32_t> &s_int,
         return from_hip(e);
     }
     if (nb > 0) g->batch_depth_hint.store(run_depth);
-    if (prof) accumulate_profile(g, timer, f.d_stats);
+    if (prof) accumulate_profile(g, timer, f.d_stats, level_steps);
     timer.destroy();
     return range ? BC_ERR_RANGE : BC_OK;
 }

@@ -16,7 +16,7 @@ size_t plain_ws_bytes(const bc_graph_s *g) {
     b += align_up((n + 2) * sizeof(LevelRec));                // lvl
     b += align_up(kCtrlInts * sizeof(int32_t));               // ctrl
     b += align_up(n * sizeof(double));                        // bc (internal order)
-    b += align_up(12 * sizeof(unsigned long long));           // work counters
+    b += align_up(kStatWords * sizeof(unsigned long long));           // work counters
     return b;
 }
 
@@ -58,7 +58,7 @@ bc_status plain_ws_create(bc_graph_s *g, PlainWS **out) {
     d.lvl = (LevelRec *)take((n + 2) * sizeof(LevelRec));
     d.ctrl = (int32_t *)take(kCtrlInts * sizeof(int32_t));
     d.bc = (double *)take(n * sizeof(double));
-    ws->d_stats = (unsigned long long *)take(12 * sizeof(unsigned long long));
+    ws->d_stats = (unsigned long long *)take(kStatWords * sizeof(unsigned long long));
     d.stats = nullptr;
     d.b3_end = g->b3_end;
     d.b2_end = g->b2_end;
@@ -112,7 +112,8 @@ void plain_release(bc_graph_s *g, PlainWS *ws, hipStream_t stream) {
 
 // Add a finished run's event-timed launches and device work counters to the
 // graph's measurement totals (the run's stream has been synchronised).
-void accumulate_profile(bc_graph_s *g, LaunchTimer &timer, const unsigned long long *d_stats) {
+void accumulate_profile(bc_graph_s *g, LaunchTimer &timer, const unsigned long long *d_stats,
+                        int64_t levels) {
     bc_profile add{};
     for (size_t i = 0; i < timer.used; ++i) {
         float ms = 0.f;
@@ -120,7 +121,7 @@ void accumulate_profile(bc_graph_s *g, LaunchTimer &timer, const unsigned long l
             add.ms[timer.cls[i]] += ms;
         add.launches[timer.cls[i]] += 1;
     }
-    unsigned long long cnt[12];
+    unsigned long long cnt[kStatWords];
     if (hipMemcpy(cnt, d_stats, sizeof(cnt), hipMemcpyDeviceToHost) == hipSuccess) {
         add.owners[BC_PROF_FORWARD] = (int64_t)cnt[0];
         add.arcs[BC_PROF_FORWARD] = (int64_t)cnt[1];
@@ -132,6 +133,8 @@ void accumulate_profile(bc_graph_s *g, LaunchTimer &timer, const unsigned long l
         add.owners[BC_PROF_SSSP] = (int64_t)cnt[9];
         add.arcs[BC_PROF_SSSP] = (int64_t)cnt[10];
         add.hits[BC_PROF_SSSP] = (int64_t)cnt[11];
+        add.vertices[BC_PROF_FORWARD] = (int64_t)cnt[12];
+        add.vertices[BC_PROF_REVERSE] = (int64_t)cnt[13];
     }
     std::lock_guard<std::mutex> lk(g->prof_mu);
     for (int c = 0; c < BC_PROF_CLASSES; ++c) {
@@ -140,7 +143,9 @@ void accumulate_profile(bc_graph_s *g, LaunchTimer &timer, const unsigned long l
         g->prof.owners[c] += add.owners[c];
         g->prof.arcs[c] += add.arcs[c];
         g->prof.hits[c] += add.hits[c];
+        g->prof.vertices[c] += add.vertices[c];
     }
+    g->prof.levels += levels;
     g->prof.runs += 1;
 }
 
@@ -246,7 +251,7 @@ bc_status plain_run(bc_graph_s *g, const int32_t *sources, int32_t k, double *bc
     hipError_t e = hipMemsetAsync(d.bc, 0, (size_t)g->n * sizeof(double), stream);
     if (e == hipSuccess) e = plain_reset_run(d, stream);
     if (e == hipSuccess && prof)
-        e = hipMemsetAsync(ws->d_stats, 0, 12 * sizeof(unsigned long long), stream);
+        e = hipMemsetAsync(ws->d_stats, 0, kStatWords * sizeof(unsigned long long), stream);
     if (e == hipSuccess && !polled && k > 0)
         e = hipMemsetAsync(ws->d_trunc, 0, (size_t)k * sizeof(int32_t), stream);
     if (e != hipSuccess) return fail(from_hip(e));
@@ -311,7 +316,13 @@ bc_status plain_run(bc_graph_s *g, const int32_t *sources, int32_t k, double *bc
         const int32_t seen = ws->h_ctrl[3] + 2;
         if (!polled && seen != g->depth_hint.load()) g->depth_hint.store(std::max(seen, 2));
     }
-    if (prof) accumulate_profile(g, ws->timer, ws->d_stats);
+    if (prof) {
+        // level steps: every source run (truncated ones again when re-run)
+        // takes depth + 1 forward and depth reverse steps
+        const int64_t runs = (polled ? 0 : k) + (int64_t)redo.size();
+        const int64_t depths = (int64_t)ws->h_ctrl[4] + ws->h_ctrl[0];
+        accumulate_profile(g, ws->timer, ws->d_stats, 2 * depths + runs);
+    }
     plain_release(g, ws, stream);
     return result;
 }

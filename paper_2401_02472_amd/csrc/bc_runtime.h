@@ -20,7 +20,7 @@ namespace bcx {
 
 constexpr size_t kAlign = 256;
 constexpr int kLevelGrid = 2048;  // workgroups per level kernel (8192 wavefronts)
-constexpr int kCtrlInts = 4;      // see PlainDev::ctrl
+constexpr int kCtrlInts = 5;      // see PlainDev::ctrl
 
 inline size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
@@ -73,7 +73,7 @@ struct LaunchTimer {
 
 struct PlainWS {
     LaunchTimer timer;
-    unsigned long long *d_stats = nullptr;  // 12 counters (see PlainDev::stats)
+    unsigned long long *d_stats = nullptr;  // kStatWords counters
     void *block = nullptr;
     size_t bytes = 0;
     PlainDev dev{};
@@ -88,7 +88,7 @@ struct PlainWS {
 // level array that grows when a batch runs deeper than it holds.
 struct BatchWS {
     LaunchTimer timer;
-    unsigned long long *d_stats = nullptr;  // 12 counters (see BatchDev::stats)
+    unsigned long long *d_stats = nullptr;  // kStatWords counters
     void *block = nullptr;     // vis, sigma, coef, ctrl, bc
     size_t bytes = 0;
     uint64_t *F = nullptr;     // [lcap][n], then the extended-range tables
@@ -189,7 +189,7 @@ struct bc_graph_s {
     struct Sssp {
         int32_t *dist = nullptr, *stamp = nullptr, *flags = nullptr;
         int32_t *h_flags = nullptr;               // pinned mirror of one flag block
-        unsigned long long *d_stats = nullptr;    // 12 counters ([9..11] used)
+        unsigned long long *d_stats = nullptr;    // kStatWords counters ([9..11] used)
     } sssp;
     // PageRank workspace (one call at a time)
     std::mutex pr_mu;
@@ -233,7 +233,7 @@ struct bc_graph_s {
         int32_t *d_lanes = nullptr;
         size_t lanes_cap = 0;
         int2 *d_batches = nullptr;
-        unsigned long long *d_stats = nullptr;  // 12 work counters (as BatchDev::stats)
+        unsigned long long *d_stats = nullptr;  // kStatWords work counters
         std::vector<BatchDev> h_devs;
     } fused;
     // hop distances (internal order, -1 unreached) from two landmarks: the
@@ -254,13 +254,17 @@ size_t plain_ws_bytes(const bc_graph_s *g);
 void plain_ws_destroy(PlainWS *ws);
 bc_status plain_acquire(bc_graph_s *g, hipStream_t stream, PlainWS **out);
 void plain_release(bc_graph_s *g, PlainWS *ws, hipStream_t stream);
-void accumulate_profile(bc_graph_s *g, LaunchTimer &timer, const unsigned long long *d_stats);
+// `levels`: level steps the run took (forward and reverse, over its sources
+// or batches).
+void accumulate_profile(bc_graph_s *g, LaunchTimer &timer, const unsigned long long *d_stats,
+                        int64_t levels = 0);
 bc_status plain_run(bc_graph_s *g, const int32_t *sources, int32_t k, double *bc_out,
                     const bc_options *opt, hipStream_t stream, const SourceState *exp,
                     const ExportTmp *tmp);
 bc_status bfs_levels(bc_graph_s *g, int32_t s, std::vector<int32_t> &out);
 
 // ---- batched runtime (bc_rt_batched.hip) ----
+size_t partial_rows(const bc_graph_s *g);
 size_t batch_ws_bytes(const bc_graph_s *g);
 size_t batch_level_bytes(const bc_graph_s *g, int32_t lcap);
 void batch_ws_destroy(BatchWS *ws);
@@ -274,6 +278,17 @@ bc_status batched_run(bc_graph_s *g, const int32_t *sources, int32_t k, double *
                       int32_t level_loop, hipStream_t stream, int32_t *dist, double *sigma);
 bc_status multi_run(bc_graph_s *g, const int32_t *sources, const int32_t *req_start,
                     int32_t nreq, double *const *outs, hipStream_t stream);
+// Extended-range tables of a batch workspace ([lcap][64] each).
+struct ExtTables {
+    double *xs;
+    unsigned long long *xmax;
+    int32_t *xe;
+};
+enum class BatchOutcome { Done, Rerun, Grow };
+hipError_t drive_batch(bc_graph_s *g, BatchDev &d, const ExtTables &ext, const int32_t *lanes_dev,
+                       int32_t nl, int32_t *h_ctrl, hipStream_t stream, LaunchTimer &timer,
+                       unsigned long long *d_stats, int32_t stride, BatchOutcome &how,
+                       int32_t &deepest);
 
 // ---- graph residency (bc_rt_graph.hip) ----
 void free_graph_arrays(bc_graph_s *g);

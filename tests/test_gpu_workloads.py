@@ -55,7 +55,11 @@ def _check_lanes(g, src, dist, sigma, lanes, directed=False):
         return i
 
     with ThreadPoolExecutor(WORKERS) as ex:
-        done = list(ex.map(one, lanes))
+        done = []
+        for i in ex.map(one, lanes):
+            done.append(i)
+            if len(done) % 32 == 0:
+                _say(f"{len(done)} lanes checked")
     assert done == list(lanes)
 
 
@@ -68,23 +72,31 @@ def _distance_sum(dist):
     return total
 
 
+def _say(msg):
+    print(f"# {msg}", flush=True)
+
+
 def _benchmarked(name, flags, directed=False):
     g, src = gg.workload(name)
+    _say(f"{name}: n={g.n} nnz={g.nnz} k={len(src)}")
     with bcm.Graph(g.n, g.row_ptr, g.col_idx, flags=flags) as G:
         tuning = G.autotune(src)
         got = run_mode(G, src, bcm.BC_MODE_AUTO)
         again = run_mode(G, src, bcm.BC_MODE_AUTO)
         bc2, dist, sigma = G.run_detail(src, bcm.make_options(bcm.BC_MODE_AUTO))
+    _say(f"{name}: GPU runs done, tuning {tuning}")
     assert tuning["batch_width"] in (32, 64, 128)
     # same batches, parts and sums whether or not the state is exported
     assert np.array_equal(got, again)
     assert np.array_equal(got, bc2)
     check_bc(got, _oracle_bc(g, src, directed))
+    _say(f"{name}: BC matches the oracle")
     if not directed:
         tot = float(np.sum(got))
         want = float(_distance_sum(dist))
         assert abs(tot - want) <= 1e-9 * want
     _check_lanes(g, src, dist, sigma, range(len(src)), directed)
+    _say(f"{name}: dist / sigma of all {len(src)} lanes match")
     return g, src
 
 
