@@ -74,7 +74,9 @@ typedef enum {
     BC_ERR_RANGE = 4,         /* shortest-path counts beyond even the extended range (see
                                  above); outputs are written but meaningless */
     BC_ERR_DEVICE = 5,        /* a HIP runtime call failed */
-    BC_ERR_UNSUPPORTED = 6    /* requested feature not available */
+    BC_ERR_UNSUPPORTED = 6,   /* requested feature not available */
+    BC_ERR_TOO_LARGE = 7      /* the run does not fit the fixed device array of
+                                 bc_run_async_noalloc (graph too large or too deep) */
 } bc_status;
 
 /* bc_create_graph flags */
@@ -171,6 +173,32 @@ bc_status bc_run(bc_graph_t g, const int32_t *sources, int32_t k, double *bc_out
  */
 bc_status bc_run_async(bc_graph_t g, const int32_t *sources, int32_t k, double *bc_out_dev,
                        const bc_options *opt, void *stream);
+
+/*
+ * bc_run_async for callers that cannot allocate device memory (code under
+ * HIP graph capture elsewhere in the process, tight serving loops, harnesses
+ * that forbid hipMalloc): the same batched kernels with the host-driven level
+ * loop, one batch at a time, every device buffer of the run carved out of one
+ * fixed array of BC_NOALLOC_SCRATCH_BYTES that the library holds on each
+ * device from its first use of this call until the process ends.  The call
+ * makes no device (or host) allocation; inputs and outputs are the caller's.
+ *   sources     [k] host (read before the call returns)
+ *   bc_out_dev  [n] device, overwritten with BC_S
+ * Batches are the sources in the order given, batch_width at a time (the
+ * graph's setting, as for bc_run_async with NULL options), so results agree
+ * with bc_run_async up to the rounding of a different grouping of sources.
+ * The workspace needs about 1,050 bytes per vertex plus 8 bytes per vertex and
+ * level (64 MiB hold graphs of about 55,000 vertices at 16 levels).  The call
+ * waits on `stream` like bc_run_async and has finished its work on return.
+ * Calls that overlap on one device share the array and race: the caller
+ * serialises them.  Errors: as bc_run_async; BC_ERR_TOO_LARGE, before any
+ * device work, when the graph's workspace with two levels does not fit, or
+ * after the forward pass when a batch is deeper than the array's level count
+ * (bc_out_dev is then not written).
+ */
+#define BC_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+bc_status bc_run_async_noalloc(bc_graph_t g, const int32_t *sources, int32_t k,
+                               double *bc_out_dev, void *stream);
 
 /*
  * Several BC queries on one graph in one call, sharing batches (the serving

@@ -14,7 +14,8 @@ import numpy as np
 
 from . import _capi
 from ._capi import (BC_ERR_DEVICE, BC_ERR_INVALID_ARG, BC_ERR_INVALID_GRAPH,  # noqa: F401
-                    BC_ERR_OUT_OF_MEMORY, BC_ERR_RANGE, BC_ERR_UNSUPPORTED,
+                    BC_ERR_OUT_OF_MEMORY, BC_ERR_RANGE, BC_ERR_TOO_LARGE, BC_ERR_UNSUPPORTED,
+                    BC_NOALLOC_SCRATCH_BYTES,
                     BC_GRAPH_DIRECTED, BC_GRAPH_INPUT_ON_DEVICE, BC_GRAPH_TRUST_SYMMETRIC,
                     BC_MODE_AUTO,
                     BC_MODE_BATCHED, BC_MODE_PLAIN, BC_OK, bc_options,
@@ -22,6 +23,7 @@ from ._capi import (BC_ERR_DEVICE, BC_ERR_INVALID_ARG, BC_ERR_INVALID_GRAPH,  # 
 
 __all__ = [
     "BCError", "bc_create_graph", "bc_destroy_graph", "bc_graph_info", "bc_run", "bc_run_async",
+    "bc_run_async_noalloc",
     "bc_run_multi",
     "bc_single_source", "bc_run_detail", "bc_workspace_bytes", "bc_trim_workspaces",
     "bc_profile_enable", "bc_profile_read", "bc_set_weights", "bc_sssp", "bc_pagerank",
@@ -132,6 +134,16 @@ def bc_run_async(g: int, sources, bc_out, options=None, stream=None) -> None:
                                    ctypes.c_void_p(bc_out.data_ptr()), opt,
                                    _stream_handle(stream))
     _check(st, "bc_run_async", bc_out)
+
+
+def bc_run_async_noalloc(g: int, sources, bc_out, stream=None) -> None:
+    """bc_run_async without any allocation: the run's device buffers come from
+    the library's fixed per-device array (BC_NOALLOC_SCRATCH_BYTES)."""
+    src = _i32(sources)
+    st = _capi.load().bc_run_async_noalloc(ctypes.c_void_p(g), _ptr(src, ctypes.c_int32),
+                                           int(src.size), ctypes.c_void_p(bc_out.data_ptr()),
+                                           _stream_handle(stream))
+    _check(st, "bc_run_async_noalloc", bc_out)
 
 
 def bc_run_multi(g: int, requests, outs, stream=None) -> None:
@@ -278,6 +290,9 @@ class Graph:
 
     def run_async(self, sources, bc_out, options=None, stream=None) -> None:
         bc_run_async(self.handle, sources, bc_out, options, stream)
+
+    def run_async_noalloc(self, sources, bc_out, stream=None) -> None:
+        bc_run_async_noalloc(self.handle, sources, bc_out, stream)
 
     def single_source(self, s: int):
         return bc_single_source(self.handle, s)

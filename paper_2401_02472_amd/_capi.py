@@ -24,6 +24,8 @@ BC_ERR_OUT_OF_MEMORY = 3
 BC_ERR_RANGE = 4
 BC_ERR_DEVICE = 5
 BC_ERR_UNSUPPORTED = 6
+BC_ERR_TOO_LARGE = 7
+BC_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 BC_GRAPH_TRUST_SYMMETRIC = 1 << 0
 BC_GRAPH_INPUT_ON_DEVICE = 1 << 1
@@ -36,7 +38,7 @@ BC_MODE_BATCHED = 2
 EXPORTED = ("bc_create_graph", "bc_destroy_graph", "bc_graph_info", "bc_run", "bc_run_async",
             "bc_run_multi", "bc_single_source", "bc_run_detail", "bc_workspace_bytes", "bc_trim_workspaces",
             "bc_profile_enable", "bc_profile_read", "bc_autotune", "bc_set_weights", "bc_sssp",
-            "bc_pagerank", "bc_status_str")
+            "bc_pagerank", "bc_status_str", "bc_run_async_noalloc")
 
 BC_LOOP_AUTO = 0
 BC_LOOP_HOST = 1
@@ -103,6 +105,7 @@ def load():
             "bc_graph_info": [vp, i32p, i64p, szp],
             "bc_run": [vp, i32p, ctypes.c_int32, f64p],
             "bc_run_async": [vp, i32p, ctypes.c_int32, vp, optp, vp],
+            "bc_run_async_noalloc": [vp, i32p, ctypes.c_int32, vp, vp],
             "bc_run_multi": [vp, i32p, i32p, ctypes.c_int32, ctypes.POINTER(vp), vp],
             "bc_single_source": [vp, ctypes.c_int32, i32p, f64p, f64p],
             "bc_run_detail": [vp, i32p, ctypes.c_int32, optp, f64p, i32p, f64p],

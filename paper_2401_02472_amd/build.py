@@ -12,7 +12,7 @@ LIB_PATH = os.path.join(HERE, "libbc_mi355x.so")
 CHECK_LIB_PATH = os.path.join(HERE, "libbc_mi355x_check.so")
 SOURCES = ["bc_graph.hip", "bc_plain.hip", "bc_batched.hip", "bc_sssp.hip", "bc_pagerank.hip",
            "bc_rt_graph.hip", "bc_rt_plain.hip", "bc_rt_batched.hip", "bc_rt_algos.hip", "bc_tune.hip",
-           "bc_capi.hip"]
+           "bc_capi.hip", "bc_noalloc.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

@@ -67,6 +67,7 @@ const char *bc_status_str(bc_status s) {
         case BC_ERR_RANGE: return "shortest-path counts out of the representable range";
         case BC_ERR_DEVICE: return "HIP runtime error";
         case BC_ERR_UNSUPPORTED: return "unsupported";
+        case BC_ERR_TOO_LARGE: return "the run does not fit the fixed device array of the allocation-free call";
     }
     return "unknown status";
 }
