@@ -166,10 +166,13 @@ bc_status bc_run(bc_graph_t g, const int32_t *sources, int32_t k, double *bc_out
  *   bc_out_dev  [n] device, overwritten with BC_S when the stream reaches the
  *               end of the call's work
  *   opt         NULL = defaults
- * The call may wait on `stream` to poll the BFS depth (the level loop is driven
- * from the host in chunks of opt->level_chunk levels), so it returns after the
- * forward passes of all sources have been issued; BC_ERR_RANGE is reported
- * only after a wait, i.e. always by the time the call returns.
+ * Not asynchronous in practice: the level loop is driven from the host, which
+ * waits on `stream` (hipStreamSynchronize) after every chunk of forward levels
+ * of every batch (one-source path: after every chunk of opt->level_chunk
+ * levels) to read the BFS depth, and again at the end of the call; the call
+ * returns when all of its work has finished (with concurrent parts, on the
+ * library's internal streams too).  BC_ERR_RANGE is therefore always known by
+ * the time the call returns.
  */
 bc_status bc_run_async(bc_graph_t g, const int32_t *sources, int32_t k, double *bc_out_dev,
                        const bc_options *opt, void *stream);
@@ -248,8 +251,17 @@ bc_status bc_run_detail(bc_graph_t g, const int32_t *sources, int32_t k, const b
  * estimate (a deeper graph grows it).  opt may be NULL. */
 bc_status bc_workspace_bytes(bc_graph_t g, int32_t k, const bc_options *opt, size_t *bytes);
 
-/* Free pooled workspaces that are idle.  Safe while other runs are in flight. */
+/* Free pooled workspaces that are idle (the one-source and batched pools'
+ * idle entries, and the device-resident loop's pool when no run holds it).
+ * Safe while other runs are in flight. */
 bc_status bc_trim_workspaces(bc_graph_t g);
+
+/* Device bytes the graph's BC workspace pools hold right now (idle or in use:
+ * one-source and batched workspaces with their level arrays, the
+ * device-resident loop's pool and tables), for admission control alongside
+ * bc_workspace_bytes.  Excludes the graph itself (bc_graph_info), the SSSP and
+ * PageRank workspaces, and a call's transient buffers. */
+bc_status bc_workspace_held(bc_graph_t g, size_t *bytes);
 
 /*
  * Measurement support, for benchmark and profiling tools.  While enabled on a

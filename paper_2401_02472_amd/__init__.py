@@ -26,6 +26,7 @@ __all__ = [
     "bc_run_async_noalloc",
     "bc_run_multi",
     "bc_single_source", "bc_run_detail", "bc_workspace_bytes", "bc_trim_workspaces",
+    "bc_workspace_held",
     "bc_profile_enable", "bc_profile_read", "bc_set_weights", "bc_sssp", "bc_pagerank",
     "bc_status_str",
     "make_options", "Graph",
@@ -243,6 +244,14 @@ def bc_trim_workspaces(g: int) -> None:
     _check(_capi.load().bc_trim_workspaces(ctypes.c_void_p(g)), "bc_trim_workspaces")
 
 
+def bc_workspace_held(g: int) -> int:
+    """Device bytes the graph's BC workspace pools hold now."""
+    out = ctypes.c_size_t()
+    _check(_capi.load().bc_workspace_held(ctypes.c_void_p(g), ctypes.byref(out)),
+           "bc_workspace_held")
+    return out.value
+
+
 def bc_profile_enable(g: int, on=True) -> None:
     """Measurement off (False / 0) or on (True / 1, or a sampling period P > 1)."""
     _check(_capi.load().bc_profile_enable(ctypes.c_void_p(g), int(on)), "bc_profile_enable")
@@ -308,6 +317,12 @@ class Graph:
 
     def workspace_bytes(self, k: int, options=None) -> int:
         return bc_workspace_bytes(self.handle, k, options)
+
+    def workspace_held(self) -> int:
+        return bc_workspace_held(self.handle)
+
+    def trim_workspaces(self) -> None:
+        bc_trim_workspaces(self.handle)
 
     def profile_enable(self, on=True) -> None:
         bc_profile_enable(self.handle, on)

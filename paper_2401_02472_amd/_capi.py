@@ -38,7 +38,8 @@ BC_MODE_BATCHED = 2
 EXPORTED = ("bc_create_graph", "bc_destroy_graph", "bc_graph_info", "bc_run", "bc_run_async",
             "bc_run_multi", "bc_single_source", "bc_run_detail", "bc_workspace_bytes", "bc_trim_workspaces",
             "bc_profile_enable", "bc_profile_read", "bc_autotune", "bc_set_weights", "bc_sssp",
-            "bc_pagerank", "bc_status_str", "bc_run_async_noalloc")
+            "bc_pagerank", "bc_status_str", "bc_run_async_noalloc",
+            "bc_workspace_held")
 
 BC_LOOP_AUTO = 0
 BC_LOOP_HOST = 1
@@ -111,6 +112,7 @@ def load():
             "bc_run_detail": [vp, i32p, ctypes.c_int32, optp, f64p, i32p, f64p],
             "bc_workspace_bytes": [vp, ctypes.c_int32, optp, szp],
             "bc_trim_workspaces": [vp],
+            "bc_workspace_held": [vp, szp],
             "bc_profile_enable": [vp, ctypes.c_int32],
             "bc_profile_read": [vp, ctypes.POINTER(bc_profile), ctypes.c_int32],
             "bc_autotune": [vp, i32p, ctypes.c_int32, vp, ctypes.POINTER(bc_tuning)],

@@ -696,8 +696,11 @@ __global__ __launch_bounds__(kDoneBlock) void k_batch_level_done(BatchDev d, int
 // ---- sparse forward step ------------------------------------------------------
 
 // Mark every neighbour of the level-L frontier (the vertices with F_L != 0,
-// found by scanning F_L 64 vertices per wave; their arcs 8 per lane per
-// round).  Marks are idempotent byte stores.
+// found by scanning F_L 64 vertices per wave).  The arcs of a wave's frontier
+// vertices are flattened into runs of 64 (one arc per lane, kProbe runs per
+// round), so a group with many small frontier vertices (a deep graph's
+// frontier rings) takes as many rounds as it has arcs / 512, not one round
+// per vertex.  Marks are idempotent byte stores.
 __global__ __launch_bounds__(kBlock) void k_batch_sparse_mark(BatchDev d, int32_t L) {
     if (L > d.ctrl[kCtlDeepest] || L + 1 >= d.lcap || !d.ctrl[kCtlMode]) return;
     const int lane = lane_id();
@@ -707,24 +710,27 @@ __global__ __launch_bounds__(kBlock) void k_batch_sparse_mark(BatchDev d, int32_
     const int32_t nwaves = gridDim.x * kWavesPerBlock;
     for (int32_t gi = wave; gi < groups; gi += nwaves) {
         const int32_t me = gi * kWave + lane;
-        const bool on = me < d.n && FL[me] != 0ull;
-        uint64_t todo = __ballot(on);
-        while (todo) {
-            const int t = __ffsll((unsigned long long)todo) - 1;
-            todo &= todo - 1;
-            const int32_t v = gi * kWave + t;
-            const int32_t rs = d.row_ptr[v], re = d.row_ptr[v + 1];
-            for (int32_t cb = rs; cb < re; cb += kProbe * kWave) {
-                int32_t nb[kProbe];
+        int32_t rs = 0, cnt = 0;
+        if (me < d.n && FL[me] != 0ull) {
+            rs = d.row_ptr[me];
+            cnt = d.row_ptr[me + 1] - rs;
+        }
+        uint32_t total;
+        const uint32_t excl = wave_excl_scan((uint32_t)cnt, total);
+        for (uint32_t c0 = 0; c0 < total; c0 += kWave * kProbe) {
+            int32_t nb[kProbe];
 #pragma unroll
-                for (int u = 0; u < kProbe; ++u) {
-                    const int32_t e = cb + u * kWave + lane;
-                    nb[u] = e < re ? d.col_idx[e] : -1;
-                }
-#pragma unroll
-                for (int u = 0; u < kProbe; ++u)
-                    if (nb[u] >= 0) d.cand[nb[u]] = 1;
+            for (int u = 0; u < kProbe; ++u) {
+                const uint32_t a = c0 + (uint32_t)(u * kWave + lane);
+                const int o = owner_lane(excl, a);
+                // cross-lane reads first, with every lane active
+                const int32_t o_rs = __shfl(rs, o);
+                const uint32_t o_excl = __shfl(excl, o);
+                nb[u] = a < total ? d.col_idx[o_rs + (int32_t)(a - o_excl)] : -1;
             }
+#pragma unroll
+            for (int u = 0; u < kProbe; ++u)
+                if (nb[u] >= 0) d.cand[nb[u]] = 1;
         }
     }
 }

@@ -268,9 +268,35 @@ bc_status bc_profile_read(bc_graph_t g, bc_profile *out, int32_t reset) {
     return BC_OK;
 }
 
+bc_status bc_workspace_held(bc_graph_t g, size_t *bytes) {
+    if (!g || !bytes) return BC_ERR_INVALID_ARG;
+    size_t b = 0;
+    {
+        std::lock_guard<std::mutex> lk(g->mu);
+        for (const PlainWS *ws : g->plain_pool) b += ws->bytes + ws->trunc_cap * sizeof(int32_t);
+        for (const BatchWS *ws : g->batch_pool)
+            b += ws->bytes + (ws->lcap ? batch_level_bytes(g, ws->lcap) : 0) + ws->src_cap;
+    }
+    {
+        std::lock_guard<std::mutex> lk(g->fused_mu);
+        const auto &f = g->fused;
+        if (f.block)
+            b += f.bytes + (size_t)f.cap * (sizeof(BatchDev) + sizeof(int2));
+        if (f.d_total) b += (size_t)std::max<int32_t>(g->n, 1) * sizeof(double);
+        b += f.lanes_cap;
+    }
+    *bytes = b;
+    return BC_OK;
+}
+
 bc_status bc_trim_workspaces(bc_graph_t g) {
     if (!g) return BC_ERR_INVALID_ARG;
     DeviceGuard dg(g->device);
+    {
+        // the device-loop pool, unless a run holds it
+        std::unique_lock<std::mutex> lk(g->fused_mu, std::try_to_lock);
+        if (lk.owns_lock()) fused_release(g);
+    }
     std::vector<PlainWS *> idle;
     std::vector<BatchWS *> idle_b;
     {

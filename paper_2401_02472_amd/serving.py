@@ -10,9 +10,14 @@ the next launch of their graph; launches of different slots run concurrently
 on their own HIP streams, so work of different graphs and requests overlaps
 on the device.
 
-Admission: a launch reserves its workspace bytes (`bc_workspace_bytes`) plus
-its output arrays against the budget and releases them when it completes; a
-request that could never fit alone is rejected with BC_ERR_OUT_OF_MEMORY.
+Admission counts the device memory the launches really hold: the library
+keeps each graph's workspaces pooled after a launch (`bc_workspace_held`), so
+the budget covers every graph's pool, the workspaces of launches in flight
+(`bc_workspace_bytes`, of which a graph's idle pool covers what it can) and
+the output arrays.  When a launch does not fit, the pools of idle graphs are
+freed (`bc_trim_workspaces`), least recently used first; if it still does not
+fit it waits for launches to finish.  A request that could never fit alone is
+rejected with BC_ERR_OUT_OF_MEMORY.
 
 Each result is the same whether the request runs alone or in a mix: a
 request of at most 64 sources never straddles two batches and every lane's
@@ -58,11 +63,22 @@ class GpuExecutor:
         self.streams = [torch.cuda.Stream() for _ in range(slots)]
 
     def bytes_needed(self, graph_id, k: int, nreq: int) -> int:
+        """Workspace plus output bytes of one launch."""
         from . import BC_MODE_BATCHED, make_options
         G = self.graphs[graph_id]
         # bc_run_multi runs its batches as one part (or in the device loop)
         ws = G.workspace_bytes(max(k, 1), make_options(BC_MODE_BATCHED, concurrency=1))
-        return int(ws) + nreq * 8 * G.n
+        return int(ws) + self.output_bytes(graph_id, nreq)
+
+    def output_bytes(self, graph_id, nreq: int) -> int:
+        return nreq * 8 * self.graphs[graph_id].n
+
+    def held_bytes(self, graph_id) -> int:
+        """Device bytes the graph's workspace pools hold now."""
+        return int(self.graphs[graph_id].workspace_held())
+
+    def trim(self, graph_id) -> None:
+        self.graphs[graph_id].trim_workspaces()
 
     def run(self, slot: int, graph_id, requests):
         import torch
@@ -97,7 +113,11 @@ class BCServer:
         self._lock = threading.Condition()
         self._queues = collections.OrderedDict((g, collections.deque()) for g in graphs)
         self._free_slots = list(range(self.slots))
-        self._reserved = 0
+        self._reserved = 0           # workspace + output bytes of launches in flight
+        self._inflight_ws = collections.Counter()   # per graph: workspace bytes in flight
+        self._out_reserved = 0
+        self._last_used = {g: 0.0 for g in graphs}  # completion time (pool LRU)
+        self.trims = 0
         self._closing = False
         self._workers = []
         self.completed = []          # finished requests (for statistics)
@@ -134,9 +154,35 @@ class BCServer:
                 w.join()
 
     # -- scheduler ---------------------------------------------------------
+    def _held(self):
+        fn = getattr(self.executor, "held_bytes", None)
+        return {g: (int(fn(g)) if fn else 0) for g in self._queues}
+
+    def _split(self, gid, k, nreq):
+        """(workspace, output) bytes of a launch."""
+        need = self.executor.bytes_needed(gid, k, nreq)
+        fn = getattr(self.executor, "output_bytes", None)
+        out = int(fn(gid, nreq)) if fn else 0
+        return need - out, out
+
+    def _projected(self, held, gid, ws, out):
+        """Device bytes in use once a launch of `ws` workspace and `out`
+        output bytes starts on gid: every graph's pool (the part launches in
+        flight do not use stays held), the workspaces in flight, the outputs;
+        the new launch reuses what gid's idle pool holds."""
+        total = self._out_reserved + out
+        for g, h in held.items():
+            busy = self._inflight_ws[g]
+            idle = max(0, h - busy)
+            total += busy + idle
+            if g == gid:
+                total += max(0, ws - idle)
+        return total
+
     def _pick(self):
         """Graph whose oldest queued request has waited longest, and the
-        requests of that graph that fit one launch and the budget."""
+        requests of that graph that fit one launch and the budget (after
+        freeing idle graphs' pools, least recently used first)."""
         best, best_t = None, None
         for gid, q in self._queues.items():
             if q and (best_t is None or q[0].arrival < best_t):
@@ -144,21 +190,36 @@ class BCServer:
         if best is None:
             return None
         q = self._queues[best]
+        held = self._held()
+        # the first request alone must fit: free idle pools until it does
+        ws0, out0 = self._split(best, q[0].k, 1)
+        if self._projected(held, best, ws0, out0) > self.budget:
+            trim = getattr(self.executor, "trim", None)
+            idle = sorted((g for g in held if held[g] > 0 and self._inflight_ws[g] == 0),
+                          key=lambda g: self._last_used[g])
+            for g in idle:
+                if trim is None:
+                    break
+                trim(g)
+                self.trims += 1
+                held = self._held()
+                if self._projected(held, best, ws0, out0) <= self.budget:
+                    break
         take, lanes = [], 0
         for r in q:
             if take and lanes + r.k > self.max_lanes:
                 break
             trial = take + [r]
-            need = self.executor.bytes_needed(best, lanes + r.k, len(trial))
-            if self._reserved + need > self.budget:
+            ws, out = self._split(best, lanes + r.k, len(trial))
+            if self._projected(held, best, ws, out) > self.budget:
                 break
             take, lanes = trial, lanes + r.k
         if not take:
             return None
-        need = self.executor.bytes_needed(best, lanes, len(take))
+        ws, out = self._split(best, lanes, len(take))
         for _ in take:
             q.popleft()
-        return best, take, need
+        return best, take, (ws, out)
 
     def _schedule(self):
         with self._lock:
@@ -169,7 +230,9 @@ class BCServer:
                         break
                     gid, reqs, need = picked
                     slot = self._free_slots.pop()
-                    self._reserved += need
+                    self._reserved += need[0] + need[1]
+                    self._inflight_ws[gid] += need[0]
+                    self._out_reserved += need[1]
                     self.max_reserved = max(self.max_reserved, self._reserved)
                     self.launches += 1
                     w = threading.Thread(target=self._run, args=(slot, gid, reqs, need),
@@ -199,7 +262,10 @@ class BCServer:
                 r.future.set_exception(err)
         with self._lock:
             self.completed.extend(reqs)
-            self._reserved -= need
+            self._reserved -= need[0] + need[1]
+            self._inflight_ws[gid] -= need[0]
+            self._out_reserved -= need[1]
+            self._last_used[gid] = t1
             self._free_slots.append(slot)
             self._workers = [w for w in self._workers if w is not threading.current_thread()]
             self._lock.notify_all()

@@ -82,3 +82,64 @@ def test_server_mix_equals_alone():
     finally:
         for G in Gs.values():
             G.close()
+
+
+def test_server_keeps_resident_pools_within_budget():
+    """The library keeps each graph's workspaces pooled after a launch; the
+    server counts them against its budget and frees idle graphs' pools (least
+    recently used first) when a launch would not fit.  Device memory in use,
+    measured after every launch, stays within the budget."""
+    import threading
+
+    import torch
+    from paper_2401_02472_amd.serving import GpuExecutor
+
+    specs = [(17, 1), (17, 2), (16, 3), (15, 4)]
+    graphs = {f"s{sc}-{sd}": gg.rmat(sc, 16, seed=sd) for sc, sd in specs}
+    Gs = {k: bcm.Graph(g.n, g.row_ptr, g.col_idx) for k, g in graphs.items()}
+    try:
+        opt = bcm.make_options(bcm.BC_MODE_BATCHED, concurrency=1)
+        ws = {k: G.workspace_bytes(64, opt) for k, G in Gs.items()}
+        # one launch on the largest graph fits; every graph's pool at once does not
+        budget = int(1.6 * max(ws.values()))
+        assert sum(ws.values()) > budget
+        torch.cuda.synchronize()
+        free, total = torch.cuda.mem_get_info()
+        base = total - free
+        peak = {"used": 0, "held": 0}
+        lock = threading.Lock()
+
+        class Watch(GpuExecutor):
+            def run(self, slot, gid, reqs):
+                out = super().run(slot, gid, reqs)
+                f, t = torch.cuda.mem_get_info()
+                held = sum(G.workspace_held() for G in Gs.values())
+                with lock:
+                    peak["used"] = max(peak["used"], t - f - base)
+                    peak["held"] = max(peak["held"], held)
+                return out
+
+        srv = BCServer(Gs, budget=budget, slots=3, max_lanes=64, executor=Watch(Gs, 3))
+        rng = np.random.default_rng(11)
+        sub = []
+        for i in range(40):
+            gid = list(graphs)[int(rng.integers(len(graphs)))]
+            k = int(rng.choice([1, 8, 64]))
+            src = gg.sample_sources(graphs[gid], k, seed=500 + i)
+            sub.append((gid, src, srv.submit(gid, src)))
+        for gid, src, fut in sub:
+            fut.result(timeout=120)
+        srv.close()
+        print(f"# budget {budget / 2**20:.0f} MiB, pools at most {peak['held'] / 2**20:.0f} MiB, "
+              f"device memory at most {peak['used'] / 2**20:.0f} MiB above the start, "
+              f"{srv.trims} pool trims", flush=True)
+        assert srv.trims > 0
+        assert peak["held"] <= budget
+        # outputs are in the budget; torch may cache their blocks, and the
+        # device allocator rounds allocations up
+        assert peak["used"] <= budget + (64 << 20)
+        for gid, src, fut in sub[:6]:
+            check_bc(fut.result(), oracle_bc(graphs[gid], src))
+    finally:
+        for G in Gs.values():
+            G.close()
