@@ -462,6 +462,11 @@ def main() -> int:
                     help="batched forward: sparse step below nnz/D frontier arcs (0 = the "
                          "graph's setting, -1 = never)")
     ap.add_argument("--sources", type=int, default=0, help="use only the first N sources")
+    ap.add_argument("--group-cut", type=int, default=0,
+                    help="batched work items: vertices above this degree become chunk items "
+                         "(0 = the graph's setting)")
+    ap.add_argument("--chunk", type=int, default=0,
+                    help="batched work items: arcs per chunk item (0 = the graph's setting)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target oracle CPU time for the cpu_baseline sample (0 = skip)")
     ap.add_argument("--compare-plain", type=int, default=32,
@@ -548,6 +553,8 @@ def main() -> int:
         # plain / batched crossover, timed on the first 64 sources
         tuning = G.autotune(sources)
         print(f"# autotune: {tuning}", file=sys.stderr, flush=True)
+    if args.group_cut or args.chunk:
+        G.set_work_items(args.group_cut or 64, args.chunk or 512)
     # end to end in the paper's convention (before the warm-up, so that the
     # timed steps are the last runs in a profiler trace)
     end_to_end = None
@@ -710,6 +717,8 @@ def main() -> int:
                    "mode": args.mode, "path": path, "batch_width": args.batch_width or
                    ((tuning["batch_width"] if tuning else 64) if path.startswith("batched") else 1),
                    "sparse_div": args.sparse_div or (tuning["sparse_div"] if tuning else 64),
+                   "group_cut": args.group_cut or (tuning["group_cut"] if tuning else 64),
+                   "chunk": args.chunk or (tuning["chunk"] if tuning else 512),
                    "concurrency": args.concurrency,
                    "autotune": tuning, "graph": g.params},
         "plain_comparison": plain_cmp,

@@ -96,8 +96,10 @@ enum {
 
 typedef struct bc_options {
     int32_t mode;        /* BC_MODE_*                                                   */
-    int32_t batch_width; /* batched mode: sources per batch, 1..64 (0 = the graph's
-                            setting: bc_autotune's choice, else 64)                      */
+    int32_t batch_width; /* batched mode: sources per batch, 1..128 (0 = the graph's
+                            setting: bc_autotune's choice, else 64); above 64 a batch
+                            keeps two 64-bit lane words per vertex (host-driven loop;
+                            bc_run_multi always batches 64)                             */
     int32_t level_chunk; /* plain mode: forward levels launched per host poll, 1..1024
                             (0 = 8)                                                     */
     int32_t sparse_div;  /* batched mode: a forward level whose frontier has fewer than
@@ -320,13 +322,23 @@ bc_status bc_profile_read(bc_graph_t g, bc_profile *out, int32_t reset);
 
 /*
  * Autotuner (the choices the library makes for BC_MODE_AUTO).  Times, on the
- * first min(k, 64) of `sources`, the batched path at widths 64 and 32 and at
- * several sparse_div values, and the one-source-at-a-time path on up to 4 of
- * them; stores the fastest batched settings in the graph, together with the
- * source count from which BC_MODE_AUTO takes the batched path (the batch's
- * time over one plain source's).  Later runs on g with BC_MODE_AUTO (and
- * batch_width / sparse_div 0) use them; results stay within the usual
- * rounding of the settings chosen.  Runs on `stream` and waits for it.
+ * first min(k, 128) of `sources`, the sparse_div values at width 64 (on up to
+ * 64 of them), then on the same batch the degree thresholds of the batched
+ * path's work items (the cut above which a vertex is split into chunk items:
+ * 64, 32, 128; the chunk size: 512, 256, 1024 arcs), then widths 64, 32 and
+ * 128 on the whole sample, and the
+ * one-source-at-a-time path on up to 4 sources; stores the fastest batched
+ * settings in the graph, together with the source count from which
+ * BC_MODE_AUTO takes the batched path (one batch's time over one plain
+ * source's).  Later runs on g with BC_MODE_AUTO (and batch_width / sparse_div
+ * 0) use them; results stay within the usual rounding of the settings chosen.
+ * The choice is remembered for the process, keyed by the graph's shape (n, arc
+ * count, direction, and its vertex counts per power-of-two degree class, each
+ * in 64ths of n); a later call on a graph of the same shape takes it without
+ * timing (out->cached = 1).  With the environment variable
+ * BC_MI355X_TUNE_CACHE naming a file, choices are also read from and appended
+ * to that file (one text line per shape), so they persist across processes.
+ * Runs on `stream` and waits for it.
  *   sources  [k] host, k >= 1
  *   out      NULL or receives the choice and the measured times
  * Errors: BC_ERR_INVALID_ARG, BC_ERR_OUT_OF_MEMORY, BC_ERR_DEVICE (the graph's
@@ -338,13 +350,34 @@ typedef struct bc_tuning {
     int32_t sparse_div;         /* chosen sparse_div (-1 = never)                     */
     int32_t min_batched;        /* BC_MODE_AUTO is batched from this many sources
                                    (INT32_MAX: never)                                 */
-    int32_t sample;             /* sources timed                                      */
+    int32_t sample;             /* sources timed (0: taken from the cache)            */
     double plain_ms_per_source; /* one-source-at-a-time path, per source              */
-    double batch_ms;            /* one batch of the sample with the chosen settings   */
+    double batch_ms;            /* the sample with the chosen settings                */
+    int32_t cached;             /* 1: the choice came from the tuning cache           */
+    int32_t group_cut;          /* vertices of higher degree are split into chunk
+                                   items; the rest go 64 to a group item             */
+    int32_t chunk;              /* arcs per chunk item                                */
+    int32_t reserved;
 } bc_tuning;
 
 bc_status bc_autotune(bc_graph_t g, const int32_t *sources, int32_t k, void *stream,
                       bc_tuning *out);
+
+/*
+ * Set the degree thresholds of the batched path's work items explicitly (the
+ * ones bc_autotune chooses): vertices of degree above group_cut (for a
+ * directed graph, of larger in- or out-degree above it) are split into chunk
+ * items of `chunk` arcs, one wavefront each, the others are taken 64 to a
+ * group item with their arcs flattened into runs of 64.  Defaults 64 and 512.
+ *   group_cut  >= 1
+ *   chunk      a multiple of 64 in [64, 4096], >= group_cut
+ * Frees the graph's idle pooled batched workspaces (their partial rows follow
+ * the item count).  Results stay within the usual rounding of the settings.
+ * Errors: BC_ERR_INVALID_ARG, BC_ERR_OUT_OF_MEMORY, BC_ERR_DEVICE (the
+ * previous thresholds stay).  Not to be called while other runs on g are in
+ * flight.
+ */
+bc_status bc_set_work_items(bc_graph_t g, int32_t group_cut, int32_t chunk);
 
 /*
  * Single-source shortest paths over weighted arcs, the paper's second

@@ -26,7 +26,7 @@ __all__ = [
     "bc_run_async_noalloc",
     "bc_run_multi",
     "bc_single_source", "bc_run_detail", "bc_workspace_bytes", "bc_trim_workspaces",
-    "bc_workspace_held",
+    "bc_workspace_held", "bc_autotune", "bc_set_work_items",
     "bc_profile_enable", "bc_profile_read", "bc_set_weights", "bc_sssp", "bc_pagerank",
     "bc_status_str",
     "make_options", "Graph",
@@ -229,7 +229,14 @@ def bc_autotune(g: int, sources, stream=None) -> dict:
                                     _stream_handle(stream), ctypes.byref(t)), "bc_autotune")
     return {"batch_width": t.batch_width, "sparse_div": t.sparse_div,
             "min_batched": t.min_batched, "sample": t.sample,
-            "plain_ms_per_source": t.plain_ms_per_source, "batch_ms": t.batch_ms}
+            "plain_ms_per_source": t.plain_ms_per_source, "batch_ms": t.batch_ms,
+            "cached": bool(t.cached), "group_cut": t.group_cut, "chunk": t.chunk}
+
+
+def bc_set_work_items(g: int, group_cut: int, chunk: int) -> None:
+    """Degree thresholds of the batched path's work items (defaults 64, 512)."""
+    _check(_capi.load().bc_set_work_items(ctypes.c_void_p(g), int(group_cut), int(chunk)),
+           "bc_set_work_items")
 
 
 def bc_workspace_bytes(g: int, k: int, options=None) -> int:
@@ -317,6 +324,9 @@ class Graph:
 
     def workspace_bytes(self, k: int, options=None) -> int:
         return bc_workspace_bytes(self.handle, k, options)
+
+    def set_work_items(self, group_cut: int, chunk: int) -> None:
+        bc_set_work_items(self.handle, group_cut, chunk)
 
     def workspace_held(self) -> int:
         return bc_workspace_held(self.handle)

@@ -39,7 +39,7 @@ EXPORTED = ("bc_create_graph", "bc_destroy_graph", "bc_graph_info", "bc_run", "b
             "bc_run_multi", "bc_single_source", "bc_run_detail", "bc_workspace_bytes", "bc_trim_workspaces",
             "bc_profile_enable", "bc_profile_read", "bc_autotune", "bc_set_weights", "bc_sssp",
             "bc_pagerank", "bc_status_str", "bc_run_async_noalloc",
-            "bc_workspace_held")
+            "bc_workspace_held", "bc_set_work_items")
 
 BC_LOOP_AUTO = 0
 BC_LOOP_HOST = 1
@@ -66,7 +66,9 @@ class bc_options(ctypes.Structure):
 class bc_tuning(ctypes.Structure):
     _fields_ = [("batch_width", ctypes.c_int32), ("sparse_div", ctypes.c_int32),
                 ("min_batched", ctypes.c_int32), ("sample", ctypes.c_int32),
-                ("plain_ms_per_source", ctypes.c_double), ("batch_ms", ctypes.c_double)]
+                ("plain_ms_per_source", ctypes.c_double), ("batch_ms", ctypes.c_double),
+                ("cached", ctypes.c_int32), ("group_cut", ctypes.c_int32),
+                ("chunk", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class bc_profile(ctypes.Structure):
@@ -116,6 +118,7 @@ def load():
             "bc_profile_enable": [vp, ctypes.c_int32],
             "bc_profile_read": [vp, ctypes.POINTER(bc_profile), ctypes.c_int32],
             "bc_autotune": [vp, i32p, ctypes.c_int32, vp, ctypes.POINTER(bc_tuning)],
+            "bc_set_work_items": [vp, ctypes.c_int32, ctypes.c_int32],
             "bc_set_weights": [vp, i32p],
             "bc_sssp": [vp, ctypes.c_int32, vp, vp],
             "bc_pagerank": [vp, ctypes.c_double, ctypes.c_double, ctypes.c_int32, vp, i32p, vp],

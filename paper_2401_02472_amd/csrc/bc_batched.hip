@@ -27,12 +27,12 @@
 // several work items, and the deepest level, are completed by a finalising
 // pass.
 //
-// Work items: a vertex of degree > 64 is split into chunks of 512 arcs (8 per
-// lane, loaded together), one wavefront per chunk; each chunk of a vertex with
-// several chunks leaves a partial row of per-source sums (forward: parent
-// counts, reverse: child coefficients), which the next kernel adds in chunk
-// order.  Vertices of degree <= 64 are taken 64
-// at a time: the wavefront flattens their arcs into runs of 64 (one arc per
+// Work items: a vertex of degree above a cut (64 unless tuned) is split into
+// chunks of arcs (512 unless tuned; 8 per lane loaded together per round), one
+// wavefront per chunk; each chunk of a vertex with several chunks leaves a
+// partial row of per-source sums (forward: parent counts, reverse: child
+// coefficients), which the next kernel adds in chunk order.  Vertices at or
+// below the cut are taken 64 at a time: the wavefront flattens their arcs into runs of 64 (one arc per
 // lane) and walks the hits either arc by arc (one row for all sources per
 // load) or, where arcs carry few sources each (deep, sparse levels), source by
 // source: each run's 64 x 64 arc-by-source hit matrix is transposed with lane
@@ -89,7 +89,7 @@ __device__ __forceinline__ void report_work(unsigned long long *stats, int base,
 
 // Walk the lanes set in `hit` (each holding a neighbour id `nb` and a lane
 // mask `m`), kUnroll rows at a time; lane s adds val[nb][s] when s is in m.
-template <typename V>
+template <int H, typename V>
 __device__ __forceinline__ void gather_hits(uint64_t hit, int32_t nb, uint64_t m,
                                             const V *val, double &acc, Work &wk) {
     const int lane = lane_id();
@@ -115,7 +115,7 @@ __device__ __forceinline__ void gather_hits(uint64_t hit, int32_t nb, uint64_t m
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
             raw[u] = 0;
-            if (on[u]) raw[u] = val[(size_t)vj[u] * kWave + lane];
+            if (on[u]) raw[u] = val[(size_t)vj[u] * (H * kWave) + lane];
         }
         double x[kUnroll];
 #pragma unroll
@@ -132,7 +132,7 @@ __device__ __forceinline__ void gather_hits(uint64_t hit, int32_t nb, uint64_t m
 // rows together: x[u] = val[nb_u][lane] when lane is in m_u, else 0.  The
 // owners and masks come back wave-uniform (oj[u] = -1 past the last hit), so
 // the caller can fold the values into per-owner sums in arc order.
-template <typename V>
+template <int H, typename V>
 __device__ __forceinline__ void gather_run(uint64_t &hit, int32_t nb, uint64_t m, int o,
                                            const V *val, double (&x)[kUnroll],
                                            uint64_t (&mj)[kUnroll], int (&oj)[kUnroll],
@@ -160,7 +160,7 @@ __device__ __forceinline__ void gather_run(uint64_t &hit, int32_t nb, uint64_t m
     for (int u = 0; u < kUnroll; ++u) {
         const bool on = (mj[u] >> lane) & 1ull;
         raw[u] = 0;
-        if (on) raw[u] = val[(size_t)vj[u] * kWave + lane];
+        if (on) raw[u] = val[(size_t)vj[u] * (H * kWave) + lane];
         wk.hits += on ? 1u : 0u;
     }
 #pragma unroll
@@ -174,7 +174,7 @@ __device__ __forceinline__ void gather_run(uint64_t &hit, int32_t nb, uint64_t m
 // take(owner, value) in arc order.  `col` comes from the transpose of the
 // run's per-arc source masks, so a load serves 64 sources on different arcs
 // instead of the sources of one arc.
-template <typename V, typename Take>
+template <int H, typename V, typename Take>
 __device__ __forceinline__ void walk_own(uint64_t col, int32_t nb, int o, const V *val, Work &wk,
                                          Take &&take) {
     const int lane = lane_id();
@@ -199,7 +199,7 @@ __device__ __forceinline__ void walk_own(uint64_t col, int32_t nb, int o, const 
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
             raw[u] = 0;
-            if (on[u]) raw[u] = val[(size_t)vj[u] * kWave + lane];
+            if (on[u]) raw[u] = val[(size_t)vj[u] * (H * kWave) + lane];
         }
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
@@ -211,7 +211,7 @@ __device__ __forceinline__ void walk_own(uint64_t col, int32_t nb, int o, const 
 
 // Probe the arcs first + 64*u + lane (u < kProbe, below `end`) of one vertex:
 // m = mask[neighbour] & keep, then gather val rows for the hits.
-template <typename V>
+template <int H, typename V>
 __device__ __forceinline__ uint64_t probe_chunk(const int32_t *col, int32_t first, int32_t end,
                                                 const uint64_t *mask, uint64_t keep,
                                                 const V *val, double &acc, Work &wk) {
@@ -225,12 +225,12 @@ __device__ __forceinline__ uint64_t probe_chunk(const int32_t *col, int32_t firs
         wk.arcs += e < end ? 1u : 0u;
     }
 #pragma unroll
-    for (int u = 0; u < kProbe; ++u) m[u] = nb[u] >= 0 ? (mask[nb[u]] & keep) : 0ull;
+    for (int u = 0; u < kProbe; ++u) m[u] = nb[u] >= 0 ? (mask[(size_t)nb[u] * H] & keep) : 0ull;
     uint64_t any = 0;
 #pragma unroll
     for (int u = 0; u < kProbe; ++u) {
         any |= m[u];
-        gather_hits(__ballot(m[u] != 0ull), nb[u], m[u], val, acc, wk);
+        gather_hits<H>(__ballot(m[u] != 0ull), nb[u], m[u], val, acc, wk);
     }
     return wave_or(any);
 }
@@ -275,9 +275,44 @@ __device__ __forceinline__ double sig_at(const BatchDev &d, size_t at) {
 // Scale of level L for this lane: 1 unless the extended range is on.  Sums of
 // level-L rows are multiplied by it when stored (forward) or completed
 // (reverse); a power of two, so the product is exact.
-template <bool N>
+template <bool N, int H>
 __device__ __forceinline__ double level_scale(const BatchDev &d, int32_t L) {
-    return (!N && d.xs) ? d.xs[(size_t)L * kWave + lane_id()] : 1.0;
+    return (!N && d.xs) ? d.xs[(size_t)L * (H * kWave) + lane_id()] : 1.0;
+}
+
+// ---- batches of up to 128 sources ------------------------------------------
+
+// A batch keeps H lane words per vertex: H = 1 for up to 64 sources, H = 2
+// for up to 128.  Word h of vertex v's masks is at v*H + h (the words of a
+// vertex share a cache line), half h of its rows at (v*H + h)*64 (a row of
+// H*64 values), and each half has its own BC array.  A wave runs each work
+// item once per half on the half's view of the workspace: the arc ids, offsets
+// and the mask lines of the second pass come from cache.
+template <int H>
+__device__ __forceinline__ BatchDev half_view(const BatchDev &d, int h) {
+    BatchDev e = d;
+    if (H > 1 && h > 0) {
+        e.vis += h;
+        e.F += h;
+        e.reach += h;
+        e.sigma += (size_t)h * kWave;
+        e.sigma32 += (size_t)h * kWave;
+        e.coef += (size_t)h * kWave;
+        e.partial += (size_t)h * kWave;
+        e.bc += (size_t)h * (size_t)d.n;
+        if (e.xs) {
+            e.xs += (size_t)h * kWave;
+            e.xmax += (size_t)h * kWave;
+            e.xe += (size_t)h * kWave;
+        }
+    }
+    return e;
+}
+
+// The lanes of half h in use: lane s stands for source 64*h + s of the batch.
+__device__ __forceinline__ uint64_t half_full(int32_t nlanes, int h) {
+    const int32_t k = nlanes - kWave * h;
+    return k >= kWave ? ~0ull : (k <= 0 ? 0ull : ((1ull << k) - 1ull));
 }
 
 // ---- forward ---------------------------------------------------------------
@@ -292,16 +327,22 @@ struct Front {
     double smax = 0.0;  // the lane's largest stored count (wide rows)
 };
 
-// Also records, in extended range, each lane's largest count stored for
-// level L+1 (one atomic max per lane and wave that stored any).
-template <bool N>
+// Also records, in extended range, each half's lane's largest count stored
+// for level L+1 (one atomic max per lane, half and wave that stored any).
+// d is the whole workspace (not a half's view).
+template <bool N, int H>
 __device__ __forceinline__ void report_front(const BatchDev &d, int set, int32_t L,
-                                             const Front &fr) {
+                                             const Front (&fr)[H]) {
     BC_FULL_EXEC();
-    if (!N && d.xmax && fr.smax > 0.0)
-        atomicMax(&d.xmax[(size_t)(L + 1) * kWave + lane_id()],
-                  (unsigned long long)__double_as_longlong(fr.smax));
-    unsigned long long c = fr.cnt, a = fr.arcs;
+    unsigned long long c = 0, a = 0;
+#pragma unroll
+    for (int h = 0; h < H; ++h) {
+        if (!N && d.xmax && fr[h].smax > 0.0)
+            atomicMax(&d.xmax[((size_t)(L + 1) * H + h) * kWave + lane_id()],
+                      (unsigned long long)__double_as_longlong(fr[h].smax));
+        c += fr[h].cnt;
+        a += fr[h].arcs;
+    }
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) {
         c += __shfl_xor(c, off);
@@ -324,7 +365,7 @@ __device__ __forceinline__ void store_sigma(const BatchDev &d, size_t at, double
 }
 
 // Chunk item of a vertex of degree > 64 (xsc: the lane's scale of level L).
-template <bool N>
+template <bool N, int H>
 __device__ __forceinline__ void fwd_chunk(const BatchDev &d, int32_t L, uint32_t item,
                                           uint64_t full, double xsc, Work &wk, Front &fr) {
     const int lane = lane_id();
@@ -332,30 +373,33 @@ __device__ __forceinline__ void fwd_chunk(const BatchDev &d, int32_t L, uint32_t
     const int32_t w = info.x, j = info.y;
     const int32_t rs = d.row_ptr_in[w], re = d.row_ptr_in[w + 1];
     const bool multi = w < d.multi_end;
-    uint64_t *FN = d.F + (size_t)(L + 1) * (size_t)d.n;
-    const uint64_t vis = d.vis[w];
+    uint64_t *FN = d.F + (size_t)(L + 1) * (size_t)d.n * H;
+    const uint64_t vis = d.vis[(size_t)w * H];
     const uint64_t unvis = ~vis & full;
     if (lane == 0 && j == 0) ++wk.verts;
     // (vis of a split vertex changes only in the completion kernel, so all of
     // its chunks agree here; with nothing to discover none writes a row and
     // the completion skips the vertex)
     if (unvis == 0ull) {
-        if (!multi && lane == 0) FN[w] = 0ull;
+        if (!multi && lane == 0) FN[(size_t)w * H] = 0ull;
         return;
     }
-    const uint64_t *FL = d.F + (size_t)L * (size_t)d.n;
-    const int32_t cb = rs + j * kChunk;
+    const uint64_t *FL = d.F + (size_t)L * (size_t)d.n * H;
+    // the item's arcs, kProbe * 64 per round (an item holds d.chunk of them)
+    const int32_t cb = rs + j * d.chunk, ce = min(re, cb + d.chunk);
     double acc = 0.0;
-    const uint64_t nw = probe_chunk(d.col_idx_in, cb, min(re, cb + kChunk), FL, unvis,
-                                    SigRows<N>::rows(d), acc, wk);
+    uint64_t nw = 0;
+    for (int32_t c0 = cb; c0 < ce; c0 += kProbe * kWave)
+        nw |= probe_chunk<H>(d.col_idx_in, c0, min(ce, c0 + kProbe * kWave), FL, unvis,
+                             SigRows<N>::rows(d), acc, wk);
     const bool mine = (nw >> lane) & 1ull;
     if (mine && (!multi || j == 0)) ++wk.owners;
     if (!multi) {
-        if (mine) store_sigma<N>(d, (size_t)w * kWave + lane, acc * xsc, fr);
+        if (mine) store_sigma<N>(d, (size_t)w * (H * kWave) + lane, acc * xsc, fr);
         if (lane == 0) {
-            FN[w] = nw;
+            FN[(size_t)w * H] = nw;
             if (nw) {
-                d.vis[w] = vis | nw;
+                d.vis[(size_t)w * H] = vis | nw;
                 ++fr.cnt;
                 fr.arcs += (unsigned long long)(re - rs);
             }
@@ -363,8 +407,8 @@ __device__ __forceinline__ void fwd_chunk(const BatchDev &d, int32_t L, uint32_t
     } else {
         // every lane's sum (0 without parents in this chunk), for the
         // completion kernel to add in chunk order
-        d.partial[(size_t)item * kWave + lane] = acc;
-        if (nw && lane == 0) atomicOr((unsigned long long *)&d.reach[w], (unsigned long long)nw);
+        d.partial[(size_t)item * (H * kWave) + lane] = acc;
+        if (nw && lane == 0) atomicOr((unsigned long long *)&d.reach[(size_t)w * H], (unsigned long long)nw);
     }
 }
 
@@ -373,7 +417,7 @@ __device__ __forceinline__ void fwd_chunk(const BatchDev &d, int32_t L, uint32_t
 // time (the wave switches owner in arc order); an owner's counts, F_{L+1} and
 // vis entries are stored when the next owner starts.  For groups whose arcs
 // carry many sources each.
-template <bool N>
+template <bool N, int H>
 __device__ __forceinline__ void fwd_runs_rows(const BatchDev &d, const uint64_t *FL, uint64_t *FN,
                                               int32_t me, int32_t rs, int32_t cnt, uint32_t excl,
                                               uint32_t total, uint64_t unvis, uint64_t full,
@@ -389,12 +433,12 @@ __device__ __forceinline__ void fwd_runs_rows(const BatchDev &d, const uint64_t 
             const uint64_t w_vis = ~shfl64(unvis, cur) & full;
             const int32_t w_deg = __shfl(cnt, cur);
             if ((nw >> lane) & 1ull) {
-                store_sigma<N>(d, (size_t)w * kWave + lane, acc * xsc, fr);
+                store_sigma<N>(d, (size_t)w * (H * kWave) + lane, acc * xsc, fr);
                 ++wk.owners;
             }
             if (lane == 0) {
-                FN[w] = nw;
-                d.vis[w] = w_vis | nw;
+                FN[(size_t)w * H] = nw;
+                d.vis[(size_t)w * H] = w_vis | nw;
                 ++fr.cnt;
                 fr.arcs += (unsigned long long)w_deg;
             }
@@ -419,7 +463,7 @@ __device__ __forceinline__ void fwd_runs_rows(const BatchDev &d, const uint64_t 
 #pragma unroll
         for (int r = 0; r < kRounds; ++r) {
             const uint64_t o_keep = shfl64(unvis, o[r]);
-            m[r] = live[r] ? FL[nb[r]] & o_keep : 0ull;
+            m[r] = live[r] ? FL[(size_t)nb[r] * H] & o_keep : 0ull;
             wk.arcs += live[r] ? 1u : 0u;
         }
 #pragma unroll
@@ -431,7 +475,7 @@ __device__ __forceinline__ void fwd_runs_rows(const BatchDev &d, const uint64_t 
                 double x[kUnroll];
                 uint64_t mj[kUnroll];
                 int oj[kUnroll];
-                gather_run(hit, nb[r], m[r], o[r], SigRows<N>::rows(d), x, mj, oj, wk);
+                gather_run<H>(hit, nb[r], m[r], o[r], SigRows<N>::rows(d), x, mj, oj, wk);
 #pragma unroll
                 for (int u = 0; u < kUnroll; ++u) {
                     if (oj[u] < 0) break;
@@ -454,7 +498,7 @@ __device__ __forceinline__ void fwd_runs_rows(const BatchDev &d, const uint64_t 
 // running sum and owner and walks its parent arcs in arc order (owners
 // ascending; see walk_own); F_{L+1} and vis are written per vertex at the end.
 // For groups whose arcs carry few sources each (deep, sparse levels).
-template <bool N>
+template <bool N, int H>
 __device__ __forceinline__ void fwd_runs_lanes(const BatchDev &d, const uint64_t *FL, uint64_t *FN,
                                                int32_t base, const int32_t *list, int32_t me,
                                                uint64_t vis, int32_t rs, int32_t cnt,
@@ -467,7 +511,7 @@ __device__ __forceinline__ void fwd_runs_lanes(const BatchDev &d, const uint64_t
     auto flush = [&]() {
         if (cur >= 0) {
             const int32_t w = list ? list[base + cur] : base + cur;
-            store_sigma<N>(d, (size_t)w * kWave + lane, acc * xsc, fr);
+            store_sigma<N>(d, (size_t)w * (H * kWave) + lane, acc * xsc, fr);
             ++wk.owners;
         }
     };
@@ -499,21 +543,21 @@ __device__ __forceinline__ void fwd_runs_lanes(const BatchDev &d, const uint64_t
 #pragma unroll
         for (int r = 0; r < kRounds; ++r) {
             const uint64_t o_keep = shfl64(unvis, o[r]);
-            m[r] = live[r] ? FL[nb[r]] & o_keep : 0ull;
+            m[r] = live[r] ? FL[(size_t)nb[r] * H] & o_keep : 0ull;
             wk.arcs += live[r] ? 1u : 0u;
         }
 #pragma unroll
         for (int r = 0; r < kRounds; ++r)
             if (__ballot(m[r] != 0ull))
-                walk_own(transpose64(m[r]), nb[r], o[r], SigRows<N>::rows(d), wk, take);
+                walk_own<H>(transpose64(m[r]), nb[r], o[r], SigRows<N>::rows(d), wk, take);
     }
     flush();
     // lane i: the sources that reached its vertex at L+1
     const uint64_t nw = transpose64(owners);
     if (me >= 0) {
-        FN[me] = nw;
+        FN[(size_t)me * H] = nw;
         if (nw) {
-            d.vis[me] = vis | nw;
+            d.vis[(size_t)me * H] = vis | nw;
             ++fr.cnt;
             fr.arcs += (unsigned long long)cnt;
         }
@@ -527,13 +571,13 @@ __device__ __forceinline__ void fwd_runs_lanes(const BatchDev &d, const uint64_t
 // the arcs of the vertices that still have unvisited lanes into runs of 64;
 // the first run's masks choose the walk: by rows when its hit arcs carry at
 // least kDenseArc sources on average, else by lanes.
-template <bool N>
+template <bool N, int H>
 __device__ __forceinline__ void
 fwd_group(const BatchDev &d, int32_t L, int32_t base, const int32_t *list, int32_t count,
           uint64_t full, double xsc, Work &wk, Front &fr) {
     const int lane = lane_id();
-    const uint64_t *FL = d.F + (size_t)L * (size_t)d.n;
-    uint64_t *FN = d.F + (size_t)(L + 1) * (size_t)d.n;
+    const uint64_t *FL = d.F + (size_t)L * (size_t)d.n * H;
+    uint64_t *FN = d.F + (size_t)(L + 1) * (size_t)d.n * H;
     int32_t me = -1;
     if (list) {
         if (base + lane < count) me = list[base + lane];
@@ -543,7 +587,7 @@ fwd_group(const BatchDev &d, int32_t L, int32_t base, const int32_t *list, int32
     uint64_t vis = full;
     int32_t rs = 0, cnt = 0;
     if (me >= 0) {
-        vis = d.vis[me];
+        vis = d.vis[(size_t)me * H];
         rs = d.row_ptr_in[me];
         const int32_t re = d.row_ptr_in[me + 1];
         cnt = vis != full ? re - rs : 0;
@@ -560,21 +604,21 @@ fwd_group(const BatchDev &d, int32_t L, int32_t base, const int32_t *list, int32
         const uint32_t o_excl = __shfl(excl, o);
         const uint64_t o_keep = shfl64(unvis, o);
         uint64_t m = 0ull;
-        if (a < total) m = FL[d.col_idx_in[o_rs + (int32_t)(a - o_excl)]] & o_keep;
+        if (a < total) m = FL[(size_t)d.col_idx_in[o_rs + (int32_t)(a - o_excl)] * H] & o_keep;
         const int hits = __popcll((unsigned long long)__ballot(m != 0ull));
         rows = wave_sum_int(__popcll((unsigned long long)m)) >= kDenseArc * hits;
     }
     if (rows) {
-        if (!list && me >= 0) FN[me] = 0ull;
-        fwd_runs_rows<N>(d, FL, FN, me, rs, cnt, excl, total, unvis, full, xsc, wk, fr);
+        if (!list && me >= 0) FN[(size_t)me * H] = 0ull;
+        fwd_runs_rows<N, H>(d, FL, FN, me, rs, cnt, excl, total, unvis, full, xsc, wk, fr);
     } else {
-        fwd_runs_lanes<N>(d, FL, FN, base, list, me, vis, rs, cnt, excl, total, unvis, xsc, wk,
+        fwd_runs_lanes<N, H>(d, FL, FN, base, list, me, vis, rs, cnt, excl, total, unvis, xsc, wk,
                           fr);
     }
 }
 
-template <bool N>
-__global__ __launch_bounds__(kBlock) void k_batch_forward(BatchDev d, int32_t L, uint64_t full) {
+template <bool N, int H>
+__global__ __launch_bounds__(kBlock) void k_batch_forward(BatchDev d, int32_t L, int32_t nlanes) {
     // nothing past the deepest level found so far (F_L is empty), no room, or
     // this level takes the sparse step
     if (L > d.ctrl[kCtlDeepest] || L + 1 >= d.lcap || d.ctrl[kCtlMode]) return;
@@ -582,29 +626,37 @@ __global__ __launch_bounds__(kBlock) void k_batch_forward(BatchDev d, int32_t L,
     const uint32_t groups = (uint32_t)((d.n - d.big_end + kWave - 1) / kWave);
     const uint32_t wave = (blockIdx.x * kBlock + threadIdx.x) / kWave;
     const uint32_t nwaves = gridDim.x * kWavesPerBlock;
-    const double xsc = level_scale<N>(d, L);
     Work wk;
-    Front fr;
+    Front fr[H];
+    // one pass per half over the item (constant h: the step is inlined twice)
+    const double x0 = level_scale<N, H>(half_view<H>(d, 0), L);
+    const double x1 = H > 1 ? level_scale<N, H>(half_view<H>(d, H - 1), L) : 1.0;
+    auto step = [&](uint32_t it, int h, double xsc, Front &f) __attribute__((always_inline)) {
+        const BatchDev dh = half_view<H>(d, h);
+        const uint64_t full = half_full(nlanes, h);
+        if (it < items) fwd_chunk<N, H>(dh, L, it, full, xsc, wk, f);
+        else fwd_group<N, H>(dh, L, d.big_end + (int32_t)(it - items) * kWave, nullptr, 0, full,
+                             xsc, wk, f);
+    };
     for (uint32_t it = wave; it < items + groups; it += nwaves) {
-        if (it < items) fwd_chunk<N>(d, L, it, full, xsc, wk, fr);
-        else fwd_group<N>(d, L, d.big_end + (int32_t)(it - items) * kWave, nullptr, 0, full, xsc,
-                          wk, fr);
+        step(it, 0, x0, fr[0]);
+        if (H > 1) step(it, 1, x1, fr[H - 1]);
     }
-    report_front<N>(d, 0, L, fr);
+    report_front<N, H>(d, 0, L, fr);
     if (d.stats) report_work(d.stats, 0, 12, wk);
 }
 
 // After a forward iteration: completes the split vertices (their counts = the
 // chunks' partial rows added in chunk order, F_{L+1}, vis) and counts them
 // into the new frontier.
-template <bool N>
+template <bool N, int H>
 __device__ __forceinline__ void finish_split(const BatchDev &d, int32_t L, int32_t wave,
                                              int32_t nwaves, double xsc, Front &fr) {
-    uint64_t *FN = d.F + (size_t)(L + 1) * (size_t)d.n;
+    uint64_t *FN = d.F + (size_t)(L + 1) * (size_t)d.n * H;
     const int lane = lane_id();
     for (int32_t w = wave; w < d.multi_end; w += nwaves) {
-        const uint64_t nw = d.reach[w];
-        if (lane == 0) FN[w] = nw;
+        const uint64_t nw = d.reach[(size_t)w * H];
+        if (lane == 0) FN[(size_t)w * H] = nw;
         if (nw == 0ull) continue;
         const uint32_t i0 = d.item_first_in[w], i1 = d.item_first_in[w + 1];
         double t = 0.0;
@@ -612,30 +664,33 @@ __device__ __forceinline__ void finish_split(const BatchDev &d, int32_t L, int32
         for (; i + 8 <= i1; i += 8) {  // 8 rows in flight
             double x[8];
 #pragma unroll
-            for (int q = 0; q < 8; ++q) x[q] = d.partial[(size_t)(i + q) * kWave + lane];
+            for (int q = 0; q < 8; ++q) x[q] = d.partial[(size_t)(i + q) * (H * kWave) + lane];
 #pragma unroll
             for (int q = 0; q < 8; ++q) t += x[q];
         }
-        for (; i < i1; ++i) t += d.partial[(size_t)i * kWave + lane];
-        if ((nw >> lane) & 1ull) store_sigma<N>(d, (size_t)w * kWave + lane, t * xsc, fr);
+        for (; i < i1; ++i) t += d.partial[(size_t)i * (H * kWave) + lane];
+        if ((nw >> lane) & 1ull) store_sigma<N>(d, (size_t)w * (H * kWave) + lane, t * xsc, fr);
         if (lane == 0) {
-            d.vis[w] |= nw;
-            d.reach[w] = 0ull;
+            d.vis[(size_t)w * H] |= nw;
+            d.reach[(size_t)w * H] = 0ull;
             ++fr.cnt;
             fr.arcs += (unsigned long long)(d.row_ptr[w + 1] - d.row_ptr[w]);
         }
     }
 }
 
-template <bool N>
-__global__ __launch_bounds__(kBlock) void k_batch_forward_finish(BatchDev d, int32_t L,
-                                                                 uint64_t full) {
+template <bool N, int H>
+__global__ __launch_bounds__(kBlock) void k_batch_forward_finish(BatchDev d, int32_t L) {
     if (L > d.ctrl[kCtlDeepest] || L + 1 >= d.lcap) return;
-    Front fr;
-    finish_split<N>(d, L, (blockIdx.x * kBlock + threadIdx.x) / kWave,
-                    gridDim.x * kWavesPerBlock, level_scale<N>(d, L), fr);
-    report_front<N>(d, 2, L, fr);
-    (void)full;
+    Front fr[H];
+    auto step = [&](int h, Front &f) __attribute__((always_inline)) {
+        const BatchDev dh = half_view<H>(d, h);
+        finish_split<N, H>(dh, L, (blockIdx.x * kBlock + threadIdx.x) / kWave,
+                           gridDim.x * kWavesPerBlock, level_scale<N, H>(dh, L), f);
+    };
+    step(0, fr[0]);
+    if (H > 1) step(1, fr[H - 1]);
+    report_front<N, H>(d, 2, L, fr);
 }
 
 // Bookkeeping between iterations (one block): adds up the frontier slots of
@@ -645,6 +700,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_forward_finish(BatchDev d, int
 // of the kernel of frontier set s.
 constexpr int kDoneBlock = 1024;
 
+template <int H>
 __global__ __launch_bounds__(kDoneBlock) void k_batch_level_done(BatchDev d, int32_t L,
                                                                  int32_t w0, int32_t w1,
                                                                  int32_t w2) {
@@ -675,12 +731,12 @@ __global__ __launch_bounds__(kDoneBlock) void k_batch_level_done(BatchDev d, int
     }
     // extended range: level L+1's scale from its largest stored counts (k = 0
     // below 2^512, so ordinary counts are never rescaled), and its exponent
-    if (live && d.xs && t < kWave) {
-        const size_t at = (size_t)(L + 1) * kWave + t;
+    if (live && d.xs && t < H * kWave) {
+        const size_t at = (size_t)(L + 1) * (H * kWave) + t;
         const double m = __longlong_as_double((long long)d.xmax[at]);
         const int k = m >= 0x1p512 ? ilogb(m) : 0;
         d.xs[at] = ldexp(1.0, -k);
-        d.xe[at] = d.xe[at - kWave] - ilogb(d.xs[at - kWave]);
+        d.xe[at] = d.xe[at - H * kWave] - ilogb(d.xs[at - H * kWave]);
     }
     if (t == 0) {
         if (live && sc[0] != 0) {
@@ -701,17 +757,23 @@ __global__ __launch_bounds__(kDoneBlock) void k_batch_level_done(BatchDev d, int
 // round), so a group with many small frontier vertices (a deep graph's
 // frontier rings) takes as many rounds as it has arcs / 512, not one round
 // per vertex.  Marks are idempotent byte stores.
+template <int H>
 __global__ __launch_bounds__(kBlock) void k_batch_sparse_mark(BatchDev d, int32_t L) {
     if (L > d.ctrl[kCtlDeepest] || L + 1 >= d.lcap || !d.ctrl[kCtlMode]) return;
     const int lane = lane_id();
-    const uint64_t *FL = d.F + (size_t)L * (size_t)d.n;
+    const uint64_t *FL = d.F + (size_t)L * (size_t)d.n * H;
     const int32_t groups = (d.n + kWave - 1) / kWave;
     const int32_t wave = (blockIdx.x * kBlock + threadIdx.x) / kWave;
     const int32_t nwaves = gridDim.x * kWavesPerBlock;
     for (int32_t gi = wave; gi < groups; gi += nwaves) {
         const int32_t me = gi * kWave + lane;
         int32_t rs = 0, cnt = 0;
-        if (me < d.n && FL[me] != 0ull) {
+        uint64_t f = 0ull;
+        if (me < d.n) {
+#pragma unroll
+            for (int h = 0; h < H; ++h) f |= FL[(size_t)me * H + h];
+        }
+        if (f != 0ull) {
             rs = d.row_ptr[me];
             cnt = d.row_ptr[me + 1] - rs;
         }
@@ -737,15 +799,16 @@ __global__ __launch_bounds__(kBlock) void k_batch_sparse_mark(BatchDev d, int32_
 
 // Turn the marks into the candidate lists (one thread per 16 vertices), clear
 // them, and clear F_{L+1} (the sparse pull writes only the candidates').
+template <int H>
 __global__ __launch_bounds__(kBlock) void k_batch_sparse_compact(BatchDev d, int32_t L,
-                                                                 uint64_t full) {
+                                                                 int32_t nlanes) {
     if (L > d.ctrl[kCtlDeepest] || L + 1 >= d.lcap || !d.ctrl[kCtlMode]) return;
     // list space is taken once per block (the waves' counts added in LDS):
     // one atomic per block and list instead of one per wave
     __shared__ uint32_t s_small[kWavesPerBlock], s_items[kWavesPerBlock], s_base[2];
     const int lane = lane_id();
     const int wib = threadIdx.x / kWave;
-    uint64_t *FN = d.F + (size_t)(L + 1) * (size_t)d.n;
+    uint64_t *FN = d.F + (size_t)(L + 1) * (size_t)d.n * H;
     const int32_t groups = (d.n + 15) >> 4;
     const int32_t stride = gridDim.x * kBlock;
     // the loop runs the same number of times in every wave of the block
@@ -758,7 +821,10 @@ __global__ __launch_bounds__(kBlock) void k_batch_sparse_compact(BatchDev d, int
 #pragma unroll
         for (int j = 0; j < 16; ++j) {
             const int32_t v = (wb << 4) + j * kWave + lane;
-            if (v < d.n) FN[v] = 0ull;
+            if (v < d.n) {
+#pragma unroll
+                for (int h = 0; h < H; ++h) FN[(size_t)v * H + h] = 0ull;
+            }
         }
         uint32_t bits = 0;
         {
@@ -772,8 +838,14 @@ __global__ __launch_bounds__(kBlock) void k_batch_sparse_compact(BatchDev d, int
         if (bits) reinterpret_cast<uint4 *>(d.cand)[i] = make_uint4(0u, 0u, 0u, 0u);
         // vertices visited from every source have nothing to discover
 #pragma unroll
-        for (int j = 0; j < 16; ++j)
-            if (((bits >> j) & 1u) && d.vis[(i << 4) + j] == full) bits &= ~(1u << j);
+        for (int j = 0; j < 16; ++j) {
+            if (!((bits >> j) & 1u)) continue;
+            bool all = true;
+#pragma unroll
+            for (int h = 0; h < H; ++h)
+                all = all && d.vis[(size_t)((i << 4) + j) * H + h] == half_full(nlanes, h);
+            if (all) bits &= ~(1u << j);
+        }
         // vertices of degree <= 64 go to the candidate list; larger ones
         // contribute their chunk items to the item list
         uint32_t nsmall = 0, nitems = 0;
@@ -837,23 +909,30 @@ __global__ __launch_bounds__(kBlock) void k_batch_sparse_compact(BatchDev d, int
 }
 
 // Pull over the candidates only (groups of 64 list entries).
-template <bool N>
+template <bool N, int H>
 __global__ __launch_bounds__(kBlock) void k_batch_sparse_pull(BatchDev d, int32_t L,
-                                                              uint64_t full) {
+                                                              int32_t nlanes) {
     if (L > d.ctrl[kCtlDeepest] || L + 1 >= d.lcap || !d.ctrl[kCtlMode]) return;
     const int32_t c = d.ctrl[kCtlCand];
     const int32_t ni = d.ctrl[kCtlItems];
     const int32_t groups = (c + kWave - 1) / kWave;
     const int32_t wave = (blockIdx.x * kBlock + threadIdx.x) / kWave;
     const int32_t nwaves = gridDim.x * kWavesPerBlock;
-    const double xsc = level_scale<N>(d, L);
     Work wk;
-    Front fr;
+    Front fr[H];
+    const double x0 = level_scale<N, H>(half_view<H>(d, 0), L);
+    const double x1 = H > 1 ? level_scale<N, H>(half_view<H>(d, H - 1), L) : 1.0;
+    auto step = [&](int32_t it, int h, double xsc, Front &f) __attribute__((always_inline)) {
+        const BatchDev dh = half_view<H>(d, h);
+        const uint64_t full = half_full(nlanes, h);
+        if (it < ni) fwd_chunk<N, H>(dh, L, (uint32_t)d.ilist[it], full, xsc, wk, f);
+        else fwd_group<N, H>(dh, L, (it - ni) * kWave, d.clist, c, full, xsc, wk, f);
+    };
     for (int32_t it = wave; it < ni + groups; it += nwaves) {
-        if (it < ni) fwd_chunk<N>(d, L, (uint32_t)d.ilist[it], full, xsc, wk, fr);
-        else fwd_group<N>(d, L, (it - ni) * kWave, d.clist, c, full, xsc, wk, fr);
+        step(it, 0, x0, fr[0]);
+        if (H > 1) step(it, 1, x1, fr[H - 1]);
     }
-    report_front<N>(d, 1, L, fr);
+    report_front<N, H>(d, 1, L, fr);
     if (d.stats) report_work(d.stats, 0, 12, wk);
 }
 
@@ -884,7 +963,7 @@ __device__ __forceinline__ void add_segments(const BatchDev &d, int32_t v, doubl
 // lane) for the caller to add later; segments are added at once.  With wide
 // rows a c beyond double's range (possible only with scaled counts) raises
 // the range flag.
-template <bool N>
+template <bool N, int H>
 __device__ __forceinline__ double settle_deferred(const BatchDev &d, int32_t v, uint64_t mv,
                                                   double sig, double acc) {
     BC_FULL_EXEC();
@@ -893,7 +972,7 @@ __device__ __forceinline__ double settle_deferred(const BatchDev &d, int32_t v, 
     const double delta = on ? sig * acc : 0.0;
     if (on) {
         const double c = (1.0 + delta) / sig;
-        d.coef[(size_t)v * kWave + lane] = c;
+        d.coef[(size_t)v * (H * kWave) + lane] = c;
         if (!N && !(c <= 0x1.fffffffffffffp+1023)) atomicOr(&d.ctrl[kCtlRange], 1);
     }
     if (d.nseg == 0) return wave_sum(delta);
@@ -901,42 +980,43 @@ __device__ __forceinline__ double settle_deferred(const BatchDev &d, int32_t v, 
     return 0.0;
 }
 
-template <bool N>
+template <bool N, int H>
 __device__ __forceinline__ void settle(const BatchDev &d, int32_t v, uint64_t mv, double sig,
                                        double acc) {
-    const double tot = settle_deferred<N>(d, v, mv, sig, acc);
+    const double tot = settle_deferred<N, H>(d, v, mv, sig, acc);
     if (lane_id() == 0 && tot != 0.0) d.bc[v] += tot;
 }
 
 // Chunk item of a vertex of degree > 64: sums of c over children; a vertex
 // with one chunk is completed here, a split vertex leaves the item's partial
 // row for the finalising pass.
-template <bool N>
+template <bool N, int H>
 __device__ __forceinline__ void bwd_chunk(const BatchDev &d, int32_t L, uint32_t item,
                                           double xsc, Work &wk) {
     const int lane = lane_id();
     const int2 info = d.item_info[item];
     const int32_t v = info.x, j = info.y;
-    const uint64_t mv = d.F[(size_t)L * (size_t)d.n + v];
+    const uint64_t mv = d.F[((size_t)L * (size_t)d.n + v) * H];
     if (lane == 0 && j == 0) ++wk.verts;
     if (mv == 0ull) return;
-    const uint64_t *FC = d.F + (size_t)(L + 1) * (size_t)d.n;
+    const uint64_t *FC = d.F + (size_t)(L + 1) * (size_t)d.n * H;
     const int32_t rs = d.row_ptr[v], re = d.row_ptr[v + 1];
-    const int32_t cb = rs + j * kChunk;
+    const int32_t cb = rs + j * d.chunk, ce = min(re, cb + d.chunk);
     const bool on = (mv >> lane) & 1ull;
-    const double sig = (on && v >= d.multi_end) ? sig_at<N>(d, (size_t)v * kWave + lane) : 1.0;
+    const double sig = (on && v >= d.multi_end) ? sig_at<N>(d, (size_t)v * (H * kWave) + lane) : 1.0;
     double acc = 0.0;
-    (void)probe_chunk(d.col_idx, cb, min(re, cb + kChunk), FC, mv, d.coef, acc, wk);
+    for (int32_t c0 = cb; c0 < ce; c0 += kProbe * kWave)
+        (void)probe_chunk<H>(d.col_idx, c0, min(ce, c0 + kProbe * kWave), FC, mv, d.coef, acc, wk);
     if (on && j == 0) ++wk.owners;
-    if (v < d.multi_end) d.partial[(size_t)item * kWave + lane] = acc;
-    else settle<N>(d, v, mv, sig, acc * xsc);
+    if (v < d.multi_end) d.partial[(size_t)item * (H * kWave) + lane] = acc;
+    else settle<N, H>(d, v, mv, sig, acc * xsc);
 }
 
 // The runs of a reverse group, arc by arc: up to kUnroll hit arcs' c rows
 // loaded for all 64 sources at once, folded into one owner's sum at a time
 // (the wave switches owner in arc order) and each owner completed when the
 // next one starts.  For groups whose owners carry many sources each.
-template <bool N>
+template <bool N, int H>
 __device__ __forceinline__ void bwd_runs_rows(const BatchDev &d, const uint64_t *FC, int32_t base,
                                               uint64_t mv, int32_t rs, uint32_t excl,
                                               uint32_t total, double xsc, Work &wk,
@@ -947,7 +1027,7 @@ __device__ __forceinline__ void bwd_runs_rows(const BatchDev &d, const uint64_t 
     double cur_sig = 1.0;   // sigma of the owner being accumulated (its lanes)
     auto flush = [&]() {
         if (cur < 0) return;
-        const double tot = settle_deferred<N>(d, base + cur, shfl64(mv, cur), cur_sig, acc * xsc);
+        const double tot = settle_deferred<N, H>(d, base + cur, shfl64(mv, cur), cur_sig, acc * xsc);
         if (lane == cur) my_bc = tot;  // all lanes active here
     };
     for (uint32_t c0 = 0; c0 < total; c0 += kWave * kRounds) {
@@ -967,7 +1047,7 @@ __device__ __forceinline__ void bwd_runs_rows(const BatchDev &d, const uint64_t 
 #pragma unroll
         for (int r = 0; r < kRounds; ++r) {
             const uint64_t o_keep = shfl64(mv, o[r]);
-            m[r] = live[r] ? FC[nb[r]] & o_keep : 0ull;
+            m[r] = live[r] ? FC[(size_t)nb[r] * H] & o_keep : 0ull;
             wk.arcs += live[r] ? 1u : 0u;
         }
 #pragma unroll
@@ -977,7 +1057,7 @@ __device__ __forceinline__ void bwd_runs_rows(const BatchDev &d, const uint64_t 
                 double x[kUnroll];
                 uint64_t mj[kUnroll];
                 int oj[kUnroll];
-                gather_run(hit, nb[r], m[r], o[r], d.coef, x, mj, oj, wk);
+                gather_run<H>(hit, nb[r], m[r], o[r], d.coef, x, mj, oj, wk);
 #pragma unroll
                 for (int u = 0; u < kUnroll; ++u) {
                     if (oj[u] < 0) break;
@@ -987,7 +1067,7 @@ __device__ __forceinline__ void bwd_runs_rows(const BatchDev &d, const uint64_t 
                         acc = 0.0;
                         pending &= ~(1ull << cur);
                         const bool on = (shfl64(mv, cur) >> lane) & 1ull;
-                        cur_sig = on ? sig_at<N>(d, (size_t)(base + cur) * kWave + lane) : 1.0;
+                        cur_sig = on ? sig_at<N>(d, (size_t)(base + cur) * (H * kWave) + lane) : 1.0;
                     }
                     acc += x[u];
                 }
@@ -1004,7 +1084,7 @@ __device__ __forceinline__ void bwd_runs_rows(const BatchDev &d, const uint64_t 
 // written only where it sits at L).  The owners are completed afterwards, one
 // wave-wide settle each, from those sums and their sigma rows.  For groups
 // whose owners carry few sources each (deep, sparse levels).
-template <bool N>
+template <bool N, int H>
 __device__ __forceinline__ void bwd_runs_lanes(const BatchDev &d, const uint64_t *FC, int32_t base,
                                                uint64_t mv, int32_t rs, uint32_t excl,
                                                uint32_t total, double xsc, Work &wk,
@@ -1014,7 +1094,7 @@ __device__ __forceinline__ void bwd_runs_lanes(const BatchDev &d, const uint64_t
     double acc = 0.0;
     uint64_t owners = 0;      // owner lanes this lane found children for
     auto flush = [&]() {
-        if (cur >= 0) d.coef[(size_t)(base + cur) * kWave + lane] = acc * xsc;
+        if (cur >= 0) d.coef[(size_t)(base + cur) * (H * kWave) + lane] = acc * xsc;
     };
     auto take = [&](int ow, double x) {
         if (ow != cur) {
@@ -1042,13 +1122,13 @@ __device__ __forceinline__ void bwd_runs_lanes(const BatchDev &d, const uint64_t
 #pragma unroll
         for (int r = 0; r < kRounds; ++r) {
             const uint64_t o_keep = shfl64(mv, o[r]);
-            m[r] = live[r] ? FC[nb[r]] & o_keep : 0ull;
+            m[r] = live[r] ? FC[(size_t)nb[r] * H] & o_keep : 0ull;
             wk.arcs += live[r] ? 1u : 0u;
         }
 #pragma unroll
         for (int r = 0; r < kRounds; ++r)
             if (__ballot(m[r] != 0ull))
-                walk_own(transpose64(m[r]), nb[r], o[r], d.coef, wk, take);
+                walk_own<H>(transpose64(m[r]), nb[r], o[r], d.coef, wk, take);
     }
     flush();
     // lane t: the sources for which owner t has children
@@ -1073,30 +1153,30 @@ __device__ __forceinline__ void bwd_runs_lanes(const BatchDev &d, const uint64_t
             mt[u] = t[u] < 0 ? 0ull : shfl64(mv, tt);
             const uint64_t tu = shfl64(touched, tt);
             const bool on = (mt[u] >> lane) & 1ull;
-            const size_t at = (size_t)(base + tt) * kWave + lane;
+            const size_t at = (size_t)(base + tt) * (H * kWave) + lane;
             x[u] = (on && ((tu >> lane) & 1ull)) ? d.coef[at] : 0.0;
             sg[u] = on ? sig_at<N>(d, at) : 1.0;
         }
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
             if (t[u] < 0) break;  // wave-uniform
-            const double tot = settle_deferred<N>(d, base + t[u], mt[u], sg[u], x[u]);
+            const double tot = settle_deferred<N, H>(d, base + t[u], mt[u], sg[u], x[u]);
             if (lane == t[u]) my_bc = tot;
         }
     }
 }
 
-template <bool N>
+template <bool N, int H>
 __device__ __forceinline__ void bwd_group(const BatchDev &d, int32_t L, int32_t base, double xsc,
                                           Work &wk) {
     const int lane = lane_id();
-    const uint64_t *FL = d.F + (size_t)L * (size_t)d.n;
-    const uint64_t *FC = d.F + (size_t)(L + 1) * (size_t)d.n;
+    const uint64_t *FL = d.F + (size_t)L * (size_t)d.n * H;
+    const uint64_t *FC = d.F + (size_t)(L + 1) * (size_t)d.n * H;
     const int32_t me = base + lane;
     uint64_t mv = 0;
     int32_t rs = 0, cnt = 0;
     if (me < d.n) {
-        mv = FL[me];
+        mv = FL[(size_t)me * H];
         rs = d.row_ptr[me];
         const int32_t re = d.row_ptr[me + 1];
         cnt = mv ? re - rs : 0;
@@ -1113,9 +1193,9 @@ __device__ __forceinline__ void bwd_group(const BatchDev &d, int32_t L, int32_t 
     // stalls the wave)
     double my_bc = 0.0;
     if (pairs >= kDenseOwner * __popcll(pending))
-        bwd_runs_rows<N>(d, FC, base, mv, rs, excl, total, xsc, wk, pending, my_bc);
+        bwd_runs_rows<N, H>(d, FC, base, mv, rs, excl, total, xsc, wk, pending, my_bc);
     else
-        bwd_runs_lanes<N>(d, FC, base, mv, rs, excl, total, xsc, wk, pending, my_bc);
+        bwd_runs_lanes<N, H>(d, FC, base, mv, rs, excl, total, xsc, wk, pending, my_bc);
     // owners without any child: delta = 0, c = 1 / sigma, nothing for BC
     while (pending) {
         int32_t vj[kUnroll];
@@ -1134,25 +1214,31 @@ __device__ __forceinline__ void bwd_group(const BatchDev &d, int32_t L, int32_t 
         double sig[kUnroll];
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u)
-            sig[u] = on[u] ? sig_at<N>(d, (size_t)vj[u] * kWave + lane) : 1.0;
+            sig[u] = on[u] ? sig_at<N>(d, (size_t)vj[u] * (H * kWave) + lane) : 1.0;
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u)
-            if (on[u]) d.coef[(size_t)vj[u] * kWave + lane] = 1.0 / sig[u];
+            if (on[u]) d.coef[(size_t)vj[u] * (H * kWave) + lane] = 1.0 / sig[u];
     }
     if (my_bc != 0.0) d.bc[base + lane] += my_bc;
 }
 
-template <bool N>
+template <bool N, int H>
 __global__ __launch_bounds__(kBlock) void k_batch_reverse(BatchDev d, int32_t L) {
     const uint32_t items = d.items;
     const uint32_t groups = (uint32_t)((d.n - d.big_end + kWave - 1) / kWave);
     const uint32_t wave = (blockIdx.x * kBlock + threadIdx.x) / kWave;
     const uint32_t nwaves = gridDim.x * kWavesPerBlock;
-    const double xsc = level_scale<N>(d, L);
     Work wk;
+    const double x0 = level_scale<N, H>(half_view<H>(d, 0), L);
+    const double x1 = H > 1 ? level_scale<N, H>(half_view<H>(d, H - 1), L) : 1.0;
+    auto step = [&](uint32_t it, int h, double xsc) __attribute__((always_inline)) {
+        const BatchDev dh = half_view<H>(d, h);
+        if (it < items) bwd_chunk<N, H>(dh, L, it, xsc, wk);
+        else bwd_group<N, H>(dh, L, d.big_end + (int32_t)(it - items) * kWave, xsc, wk);
+    };
     for (uint32_t it = wave; it < items + groups; it += nwaves) {
-        if (it < items) bwd_chunk<N>(d, L, it, xsc, wk);
-        else bwd_group<N>(d, L, d.big_end + (int32_t)(it - items) * kWave, xsc, wk);
+        step(it, 0, x0);
+        if (H > 1) step(it, 1, x1);
     }
     if (d.stats) report_work(d.stats, 6, 13, wk);
 }
@@ -1162,31 +1248,31 @@ __global__ __launch_bounds__(kBlock) void k_batch_reverse(BatchDev d, int32_t L)
 // rows of their chunks added in chunk order, or, with leaf set (the deepest
 // level), every vertex, with sum 0.  delta = sigma * sum, c = (1 + delta) /
 // sigma, BC[v] += the lanes' deltas.
-template <bool N>
+template <bool N, int H>
 __device__ __forceinline__ void
 finalize_level(const BatchDev &d, int32_t L, int32_t leaf, int32_t wave, int32_t nwaves) {
     const int lane = lane_id();
-    const uint64_t *FL = d.F + (size_t)L * (size_t)d.n;
+    const uint64_t *FL = d.F + (size_t)L * (size_t)d.n * H;
     if (!leaf) {
         // split vertices, one wave each: the chunks' partial rows added in
         // chunk order (8 rows in flight), then delta, c and BC
         for (int32_t v = wave; v < d.multi_end; v += nwaves) {
-            const uint64_t mv = FL[v];
+            const uint64_t mv = FL[(size_t)v * H];
             if (mv == 0ull) continue;
             const bool on = (mv >> lane) & 1ull;
-            const double sig = on ? sig_at<N>(d, (size_t)v * kWave + lane) : 1.0;
+            const double sig = on ? sig_at<N>(d, (size_t)v * (H * kWave) + lane) : 1.0;
             const uint32_t i0 = d.item_first[v], i1 = d.item_first[v + 1];
             double t = 0.0;
             uint32_t i = i0;
             for (; i + 8 <= i1; i += 8) {
                 double x[8];
 #pragma unroll
-                for (int q = 0; q < 8; ++q) x[q] = d.partial[(size_t)(i + q) * kWave + lane];
+                for (int q = 0; q < 8; ++q) x[q] = d.partial[(size_t)(i + q) * (H * kWave) + lane];
 #pragma unroll
                 for (int q = 0; q < 8; ++q) t += x[q];
             }
-            for (; i < i1; ++i) t += d.partial[(size_t)i * kWave + lane];
-            settle<N>(d, v, mv, sig, t * level_scale<N>(d, L));
+            for (; i < i1; ++i) t += d.partial[(size_t)i * (H * kWave) + lane];
+            settle<N, H>(d, v, mv, sig, t * level_scale<N, H>(d, L));
         }
         return;
     }
@@ -1194,7 +1280,7 @@ finalize_level(const BatchDev &d, int32_t L, int32_t leaf, int32_t wave, int32_t
     const int32_t groups = (vend + kWave - 1) / kWave;
     for (int32_t gi = wave; gi < groups; gi += nwaves) {
         const int32_t me = gi * kWave + lane;
-        const uint64_t m_me = me < vend ? FL[me] : 0ull;
+        const uint64_t m_me = me < vend ? FL[(size_t)me * H] : 0ull;
         uint64_t todo = __ballot(m_me != 0ull);
         while (todo) {
             // kFinal vertices per round: their rows are loaded together and
@@ -1218,7 +1304,7 @@ finalize_level(const BatchDev &d, int32_t L, int32_t leaf, int32_t wave, int32_t
 #pragma unroll
             for (int u = 0; u < kFinal; ++u) {
                 const bool on = (mj[u] >> lane) & 1ull;
-                const size_t at = (size_t)(vj[u] < 0 ? 0 : vj[u]) * kWave + lane;
+                const size_t at = (size_t)(vj[u] < 0 ? 0 : vj[u]) * (H * kWave) + lane;
                 sig[u] = on ? sig_at<N>(d, at) : 1.0;
                 sum[u] = 0.0;  // the deepest level has no children
             }
@@ -1227,7 +1313,7 @@ finalize_level(const BatchDev &d, int32_t L, int32_t leaf, int32_t wave, int32_t
             for (int u = 0; u < kFinal; ++u) {
                 const bool on = (mj[u] >> lane) & 1ull;
                 delta[u] = on ? sig[u] * sum[u] : 0.0;
-                if (on) d.coef[(size_t)vj[u] * kWave + lane] = (1.0 + delta[u]) / sig[u];
+                if (on) d.coef[(size_t)vj[u] * (H * kWave) + lane] = (1.0 + delta[u]) / sig[u];
             }
             if (d.nseg == 0) {
                 // lane u receives vertex u's sum over the lanes
@@ -1251,10 +1337,12 @@ finalize_level(const BatchDev &d, int32_t L, int32_t leaf, int32_t wave, int32_t
     }
 }
 
-template <bool N>
+template <bool N, int H>
 __global__ __launch_bounds__(kBlock) void k_batch_finalize(BatchDev d, int32_t L, int32_t leaf) {
-    finalize_level<N>(d, L, leaf, (blockIdx.x * kBlock + threadIdx.x) / kWave,
-                      gridDim.x * kWavesPerBlock);
+    const int32_t wave = (blockIdx.x * kBlock + threadIdx.x) / kWave;
+    finalize_level<N, H>(half_view<H>(d, 0), L, leaf, wave, gridDim.x * kWavesPerBlock);
+    if (H > 1)
+        finalize_level<N, H>(half_view<H>(d, H - 1), L, leaf, wave, gridDim.x * kWavesPerBlock);
 }
 
 // ---- device-resident level loop (small graphs) -----------------------------
@@ -1269,7 +1357,8 @@ __global__ __launch_bounds__(kBlock) void k_batch_finalize(BatchDev d, int32_t L
 // out wrong on gfx950, varying from run to run, while the level masks and
 // path counts stayed exact).  ctrl of the batch receives the depth and the flags
 // (truncation: the host runs the call again with a longer level array).  No
-// extended range here: the host runs graphs that need it on its own loop.
+// extended range and no 128-source batches here: the host runs those on its
+// own loop.
 constexpr int kFusedBlock = 1024;
 constexpr int kFusedWaves = kFusedBlock / kWave;
 
@@ -1317,12 +1406,12 @@ __global__ __launch_bounds__(kFusedBlock) void k_batch_fused(const BatchDev *dev
         if (t == 0) s_found = 0;
         Front fr;
         for (uint32_t it = wave; it < items_in + groups; it += kFusedWaves) {
-            if (it < items_in) fwd_chunk<N>(d, L, it, full, 1.0, wkf, fr);
-            else fwd_group<N>(d, L, d.big_end + (int32_t)(it - items_in) * kWave, nullptr, 0,
+            if (it < items_in) fwd_chunk<N, 1>(d, L, it, full, 1.0, wkf, fr);
+            else fwd_group<N, 1>(d, L, d.big_end + (int32_t)(it - items_in) * kWave, nullptr, 0,
                               full, 1.0, wkf, fr);
         }
         __syncthreads();
-        finish_split<N>(d, L, wave, kFusedWaves, 1.0, fr);
+        finish_split<N, 1>(d, L, wave, kFusedWaves, 1.0, fr);
         uint32_t c = fr.cnt;
 #pragma unroll
         for (int off = 32; off >= 1; off >>= 1) c += __shfl_xor(c, off);
@@ -1342,12 +1431,12 @@ __global__ __launch_bounds__(kFusedBlock) void k_batch_fused(const BatchDev *dev
     for (int32_t L = deepest; L >= 1; --L) {
         if (L != deepest) {
             for (uint32_t it = wave; it < items + groups; it += kFusedWaves) {
-                if (it < items) bwd_chunk<N>(d, L, it, 1.0, wkr);
-                else bwd_group<N>(d, L, d.big_end + (int32_t)(it - items) * kWave, 1.0, wkr);
+                if (it < items) bwd_chunk<N, 1>(d, L, it, 1.0, wkr);
+                else bwd_group<N, 1>(d, L, d.big_end + (int32_t)(it - items) * kWave, 1.0, wkr);
             }
             __syncthreads();
         }
-        finalize_level<N>(d, L, L == deepest ? 1 : 0, wave, kFusedWaves);
+        finalize_level<N, 1>(d, L, L == deepest ? 1 : 0, wave, kFusedWaves);
         __syncthreads();
     }
     if (d.stats) {
@@ -1359,15 +1448,15 @@ __global__ __launch_bounds__(kFusedBlock) void k_batch_fused(const BatchDev *dev
 // ---- batch set-up and export ------------------------------------------------
 
 // vis = 0 and F_0 = 0 everywhere; the split vertices' reach masks cleared.
-template <bool N>
+template <bool N, int H>
 __global__ void k_batch_clear(BatchDev d) {
     const int32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
     const int32_t stride = gridDim.x * blockDim.x;
-    for (int32_t i = tid; i < d.n; i += stride) {
+    for (int64_t i = tid; i < (int64_t)d.n * H; i += stride) {
         d.vis[i] = 0ull;
         d.F[i] = 0ull;
     }
-    for (int32_t i = tid; i < d.multi_end; i += stride) d.reach[i] = 0ull;
+    for (int64_t i = tid; i < (int64_t)d.multi_end * H; i += stride) d.reach[i] = 0ull;
     const int32_t groups = (d.n + 15) >> 4;
     for (int32_t i = tid; i < groups; i += stride)
         reinterpret_cast<uint4 *>(d.cand)[i] = make_uint4(0u, 0u, 0u, 0u);
@@ -1375,8 +1464,8 @@ __global__ void k_batch_clear(BatchDev d) {
     if (blockIdx.x == 0 && threadIdx.x < kCtlInts && threadIdx.x != kCtlRange)
         d.ctrl[threadIdx.x] = 0;
     if (d.xmax) {  // extended range: no maxima yet, level 0 (the sources) unscaled
-        for (int64_t i = tid; i < (int64_t)d.lcap * kWave; i += stride) d.xmax[i] = 0ull;
-        if (tid < kWave) {
+        for (int64_t i = tid; i < (int64_t)d.lcap * (H * kWave); i += stride) d.xmax[i] = 0ull;
+        if (tid < H * kWave) {
             d.xs[tid] = 1.0;
             d.xe[tid] = 0;
         }
@@ -1385,38 +1474,40 @@ __global__ void k_batch_clear(BatchDev d) {
 
 // Seed lane s with its source; the first iteration's step is chosen from the
 // distinct sources' arc count.
-template <bool N>
+template <bool N, int H>
 __global__ void k_batch_seed(BatchDev d, const int32_t *src, int32_t nlanes) {
-    const int lane = threadIdx.x;
-    int32_t s = -1;
-    bool first = false;
-    if (lane < nlanes) {
-        s = src[lane];
-        atomicOr((unsigned long long *)&d.vis[s], 1ull << lane);
-        const unsigned long long old =
-            atomicOr((unsigned long long *)&d.F[s], 1ull << lane);
-        first = old == 0ull;  // exactly one lane per distinct source
-        SigRows<N>::rows(d)[(size_t)s * kWave + lane] = 1;
+    const int lane = threadIdx.x;  // source lane + 64 h of half h
+    unsigned long long arcs = 0;
+#pragma unroll
+    for (int h = 0; h < H; ++h) {
+        const int32_t t = lane + kWave * h;
+        if (t < nlanes) {
+            const int32_t s = src[t];
+            atomicOr((unsigned long long *)&d.vis[(size_t)s * H + h], 1ull << lane);
+            const unsigned long long old =
+                atomicOr((unsigned long long *)&d.F[(size_t)s * H + h], 1ull << lane);
+            // exactly one lane per distinct source of the half
+            if (old == 0ull) arcs += (unsigned long long)(d.row_ptr[s + 1] - d.row_ptr[s]);
+            SigRows<N>::rows(d)[((size_t)s * H + h) * kWave + lane] = 1;
+        }
     }
-    const int32_t deg = first ? d.row_ptr[s + 1] - d.row_ptr[s] : 0;
-    unsigned long long arcs = (unsigned long long)deg;
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) arcs += __shfl_xor(arcs, off);
     if (lane == 0) d.ctrl[kCtlMode] = (int64_t)arcs < d.sparse_arcs ? 1 : 0;
 }
 
 // dist[s][v] and sigma[s][v] of lane s (internal vertex order), s < nlanes.
-template <bool N>
+template <bool N, int H>
 __global__ void k_batch_export(BatchDev d, int32_t deepest, int32_t nlanes, int32_t *dist,
                                double *sigma) {
     for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < d.n;
          v += gridDim.x * blockDim.x) {
-        const uint64_t vis = d.vis[v];
         for (int32_t s = 0; s < nlanes; ++s) {
+            const int h = s / kWave, b = s % kWave;  // half and lane of source s
             int32_t lev = -1;
-            if ((vis >> s) & 1ull) {
+            if ((d.vis[(size_t)v * H + h] >> b) & 1ull) {
                 for (int32_t L = 0; L <= deepest; ++L)
-                    if ((d.F[(size_t)L * d.n + v] >> s) & 1ull) {
+                    if ((d.F[((size_t)L * d.n + v) * H + h] >> b) & 1ull) {
                         lev = L;
                         break;
                     }
@@ -1425,8 +1516,9 @@ __global__ void k_batch_export(BatchDev d, int32_t deepest, int32_t nlanes, int3
             if (sigma) {
                 // extended range: the stored value times 2^xe (infinite past
                 // double's range)
-                double x = lev >= 0 ? sig_at<N>(d, (size_t)v * kWave + s) : 0.0;
-                if (lev >= 0 && d.xe) x = ldexp(x, d.xe[(size_t)lev * kWave + s]);
+                const size_t at = ((size_t)v * H + h) * kWave + b;
+                double x = lev >= 0 ? sig_at<N>(d, at) : 0.0;
+                if (lev >= 0 && d.xe) x = ldexp(x, d.xe[((size_t)lev * H + h) * kWave + b]);
                 sigma[(size_t)s * d.n + v] = x;
             }
         }
@@ -1446,48 +1538,53 @@ constexpr int kSparseGrid = kMaxGridBlocks;  // blocks of the sparse mark / pull
 unsigned int exec_partial_batched() { return exec_partial_take(); }
 #endif
 
+// The kernel instance for the workspace's row format (narrow uint32 or wide
+// double sigma rows) and lane words per vertex (1: up to 64 sources, 2: up to
+// 128).
+#define BC_PICK(k, d)                                                    \
+    ((d).H == 2 ? ((d).narrow ? k<true, 2> : k<false, 2>)                \
+                : ((d).narrow ? k<true, 1> : k<false, 1>))
+#define BC_PICK_H(k, d) ((d).H == 2 ? k<2> : k<1>)
+
 hipError_t batch_start(const BatchDev &d, const int32_t *src_dev, int32_t nlanes,
                        hipStream_t stream) {
-    int grid = (d.n + kBlock - 1) / kBlock;
+    int grid = (int)(((int64_t)d.n * d.H + kBlock - 1) / kBlock);
     grid = grid < 1 ? 1 : (grid > 4096 ? 4096 : grid);
-    hipLaunchKernelGGL(d.narrow ? k_batch_clear<true> : k_batch_clear<false>,
-                       dim3(grid), dim3(kBlock), 0, stream, d);
+    hipLaunchKernelGGL(BC_PICK(k_batch_clear, d), dim3(grid), dim3(kBlock), 0, stream, d);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(d.narrow ? k_batch_seed<true> : k_batch_seed<false>,
-                       dim3(1), dim3(kWave), 0, stream, d, src_dev, nlanes);
+    hipLaunchKernelGGL(BC_PICK(k_batch_seed, d), dim3(1), dim3(kWave), 0, stream, d, src_dev,
+                       nlanes);
     return hipGetLastError();
 }
 
-hipError_t batch_forward(const BatchDev &d, int32_t level, uint64_t full, hipStream_t stream) {
+hipError_t batch_forward(const BatchDev &d, int32_t level, int32_t nlanes, hipStream_t stream) {
     // both steps are launched; each returns at once unless the mode chosen on
     // the device for this level is its own
     const int64_t groups = (d.n - d.big_end + kWave - 1) / kWave;
-    hipLaunchKernelGGL(d.narrow ? k_batch_forward<true> : k_batch_forward<false>,
-                       dim3(grid_of(d.items_in + groups)), dim3(kBlock), 0, stream,
-                       d, level, full);
+    hipLaunchKernelGGL(BC_PICK(k_batch_forward, d), dim3(grid_of(d.items_in + groups)),
+                       dim3(kBlock), 0, stream, d, level, nlanes);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (d.sparse_arcs == 0) return hipSuccess;  // the sparse step is switched off
-    hipLaunchKernelGGL(k_batch_sparse_mark, dim3(kSparseGrid), dim3(kBlock), 0, stream, d, level);
+    hipLaunchKernelGGL(BC_PICK_H(k_batch_sparse_mark, d), dim3(kSparseGrid), dim3(kBlock), 0,
+                       stream, d, level);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_batch_sparse_compact, dim3(grid_of(((d.n + 15) / 16 + kWave - 1) / kWave)),
-                       dim3(kBlock), 0, stream, d, level, full);
+    hipLaunchKernelGGL(BC_PICK_H(k_batch_sparse_compact, d),
+                       dim3(grid_of(((d.n + 15) / 16 + kWave - 1) / kWave)), dim3(kBlock), 0,
+                       stream, d, level, nlanes);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(d.narrow ? k_batch_sparse_pull<true> : k_batch_sparse_pull<false>,
-                       dim3(kSparseGrid), dim3(kBlock), 0, stream, d, level,
-                       full);
+    hipLaunchKernelGGL(BC_PICK(k_batch_sparse_pull, d), dim3(kSparseGrid), dim3(kBlock), 0, stream,
+                       d, level, nlanes);
     return hipGetLastError();
 }
 
-hipError_t batch_forward_done(const BatchDev &d, int32_t level, uint64_t full,
-                              hipStream_t stream) {
+hipError_t batch_forward_done(const BatchDev &d, int32_t level, hipStream_t stream) {
     if (d.multi_end > 0) {
-        hipLaunchKernelGGL(d.narrow ? k_batch_forward_finish<true> : k_batch_forward_finish<false>,
-                           dim3(grid_of(d.multi_end)), dim3(kBlock), 0,
-                           stream, d, level, full);
+        hipLaunchKernelGGL(BC_PICK(k_batch_forward_finish, d), dim3(grid_of(d.multi_end)),
+                           dim3(kBlock), 0, stream, d, level);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -1495,16 +1592,15 @@ hipError_t batch_forward_done(const BatchDev &d, int32_t level, uint64_t full,
     const int32_t w0 = grid_of(d.items_in + groups) * kWavesPerBlock;
     const int32_t w1 = kSparseGrid * kWavesPerBlock;
     const int32_t w2 = d.multi_end > 0 ? grid_of(d.multi_end) * kWavesPerBlock : 0;
-    hipLaunchKernelGGL(k_batch_level_done, dim3(1), dim3(kDoneBlock), 0, stream, d, level, w0, w1,
-                       w2);
+    hipLaunchKernelGGL(BC_PICK_H(k_batch_level_done, d), dim3(1), dim3(kDoneBlock), 0, stream, d,
+                       level, w0, w1, w2);
     return hipGetLastError();
 }
 
 hipError_t batch_reverse(const BatchDev &d, int32_t level, hipStream_t stream) {
     const int64_t groups = (d.n - d.big_end + kWave - 1) / kWave;
-    hipLaunchKernelGGL(d.narrow ? k_batch_reverse<true> : k_batch_reverse<false>,
-                       dim3(grid_of(d.items + groups)), dim3(kBlock), 0, stream,
-                       d, level);
+    hipLaunchKernelGGL(BC_PICK(k_batch_reverse, d), dim3(grid_of(d.items + groups)), dim3(kBlock),
+                       0, stream, d, level);
     return hipGetLastError();
 }
 
@@ -1512,8 +1608,8 @@ hipError_t batch_finalize(const BatchDev &d, int32_t level, bool deepest, hipStr
     // deepest level: every vertex, 64 per wave; otherwise one wave per split vertex
     const int64_t waves = deepest ? (d.n + kWave - 1) / kWave : d.multi_end;
     if (waves == 0) return hipSuccess;
-    hipLaunchKernelGGL(d.narrow ? k_batch_finalize<true> : k_batch_finalize<false>,
-                       dim3(grid_of(waves)), dim3(kBlock), 0, stream, d, level, deepest ? 1 : 0);
+    hipLaunchKernelGGL(BC_PICK(k_batch_finalize, d), dim3(grid_of(waves)), dim3(kBlock), 0, stream,
+                       d, level, deepest ? 1 : 0);
     return hipGetLastError();
 }
 
@@ -1529,9 +1625,8 @@ hipError_t batch_export(const BatchDev &d, int32_t deepest, int32_t nlanes, int3
                         double *sigma, hipStream_t stream) {
     int grid = (d.n + kBlock - 1) / kBlock;
     grid = grid < 1 ? 1 : (grid > 4096 ? 4096 : grid);
-    hipLaunchKernelGGL(d.narrow ? k_batch_export<true> : k_batch_export<false>,
-                       dim3(grid), dim3(kBlock), 0, stream, d, deepest, nlanes,
-                       dist, sigma);
+    hipLaunchKernelGGL(BC_PICK(k_batch_export, d), dim3(grid), dim3(kBlock), 0, stream, d,
+                       deepest, nlanes, dist, sigma);
     return hipGetLastError();
 }
 

@@ -35,7 +35,7 @@ int32_t sparse_div_of(const bc_graph_s *g, const bc_options *opt) {
 bc_status check_options(const bc_options *opt) {
     if (!opt) return BC_OK;
     if (opt->mode < BC_MODE_AUTO || opt->mode > BC_MODE_BATCHED) return BC_ERR_INVALID_ARG;
-    if (opt->batch_width < 0 || opt->batch_width > 64) return BC_ERR_INVALID_ARG;
+    if (opt->batch_width < 0 || opt->batch_width > 2 * kWave) return BC_ERR_INVALID_ARG;
     if (opt->level_chunk < 0 || opt->level_chunk > 1024) return BC_ERR_INVALID_ARG;
     if (opt->sparse_div < -1 || opt->sparse_div > (1 << 20)) return BC_ERR_INVALID_ARG;
     if (opt->concurrency < 0 || opt->concurrency > kMaxParts) return BC_ERR_INVALID_ARG;
@@ -239,8 +239,9 @@ bc_status bc_workspace_bytes(bc_graph_t g, int32_t k, const bc_options *opt, siz
     }
     const int32_t width = batch_width_of(g, opt);
     const int32_t nb = (k + width - 1) / width;
+    const int32_t H = width > kWave ? 2 : 1;
     const int32_t lcap = std::max(16, g->batch_depth_hint.load() + 8);
-    if (use_fused(g, opt ? opt->level_loop : 0, nb)) {
+    if (use_fused(g, opt ? opt->level_loop : 0, nb, width)) {
         // the device-loop pool: per-batch workspaces, BC arrays and control words
         const int32_t cap = fused_cap(g, nb, lcap);
         const size_t n = (size_t)std::max<int32_t>(g->n, 1);
@@ -248,8 +249,8 @@ bc_status bc_workspace_bytes(bc_graph_t g, int32_t k, const bc_options *opt, siz
                                 kCtlInts * sizeof(int32_t)) + n * sizeof(double);
     } else {
         // one workspace per concurrent part
-        const int32_t parts = parts_of(g, opt ? opt->concurrency : 0, nb);
-        *bytes = (size_t)parts * (batch_ws_bytes(g) + batch_level_bytes(g, lcap));
+        const int32_t parts = parts_of(g, opt ? opt->concurrency : 0, nb, H);
+        *bytes = (size_t)parts * (batch_ws_bytes(g, H) + batch_level_bytes(g, lcap, H));
     }
     return BC_OK;
 }
@@ -275,7 +276,7 @@ bc_status bc_workspace_held(bc_graph_t g, size_t *bytes) {
         std::lock_guard<std::mutex> lk(g->mu);
         for (const PlainWS *ws : g->plain_pool) b += ws->bytes + ws->trunc_cap * sizeof(int32_t);
         for (const BatchWS *ws : g->batch_pool)
-            b += ws->bytes + (ws->lcap ? batch_level_bytes(g, ws->lcap) : 0) + ws->src_cap;
+            b += ws->bytes + (ws->lcap ? batch_level_bytes(g, ws->lcap, ws->H) : 0) + ws->src_cap;
     }
     {
         std::lock_guard<std::mutex> lk(g->fused_mu);

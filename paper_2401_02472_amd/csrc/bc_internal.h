@@ -84,7 +84,8 @@ struct PlainDev {
     double *bc;           // [n] accumulated BC
 };
 
-// Device view of one batched workspace (up to 64 sources, one per lane).
+// Device view of one batched workspace (up to 64 sources, one per lane, with
+// H = 1; up to 128 with H = 2, a wave running each work item once per half).
 // Vertices [0, big_end) (degree > 64) are processed as chunk items of kChunk
 // arcs; of those, [0, multi_end) (degree > kChunk) span several items.
 // item_info[i] = (vertex, chunk index); item_first[v] = first item of v.  For
@@ -99,8 +100,10 @@ constexpr int kMaxParts = 8;
 
 struct BatchDev {
     int32_t n;
+    int32_t H;             // lane words per vertex: 1 (up to 64 sources) or 2 (up to 128)
     int32_t lcap;          // levels the F array holds
     int32_t big_end, multi_end;
+    int32_t chunk;         // arcs per chunk item (a multiple of 64, at most 4096)
     uint32_t items;        // chunk items of the vertices below big_end
     const int32_t *row_ptr;
     const int32_t *col_idx;
@@ -114,14 +117,17 @@ struct BatchDev {
     const int32_t *col_idx_in;
     const int2 *item_info_in;
     const uint32_t *item_first_in;
-    uint64_t *vis;         // [n] sources that reached v
-    uint64_t *F;           // [lcap][n] F[L][v]: sources at distance L from v
-    double *sigma;         // [n][64] path counts as doubles (wide rows)
-    uint32_t *sigma32;     // [n][64] the same memory as exact uint32 counts (narrow rows)
+    // Per-source arrays have H lane words (or 64-value rows) per vertex,
+    // interleaved: word h of vertex v at v*H + h, half h of its row at
+    // (v*H + h)*64; bit / lane s of half h stands for source 64*h + s.
+    uint64_t *vis;         // [n][H] sources that reached v
+    uint64_t *F;           // [lcap][n][H] F[L][v]: sources at distance L from v
+    double *sigma;         // [n][H][64] path counts as doubles (wide rows)
+    uint32_t *sigma32;     // [n][H][64] the same memory as exact uint32 counts (narrow rows)
     int32_t narrow;        // 1: sigma32 rows are in use
-    double *coef;          // [n][64] (1 + delta) / sigma
-    uint64_t *reach;       // [multi_end] sources reaching a split vertex this iteration
-    double *partial;       // [max(items, items_in)][64] per-chunk-item sums: the
+    double *coef;          // [n][H][64] (1 + delta) / sigma
+    uint64_t *reach;       // [multi_end][H] sources reaching a split vertex this iteration
+    double *partial;       // [max(items, items_in)][H][64] per-chunk-item sums: the
                            // forward pass's parent counts of split vertices
                            // (items_in), the reverse pass's child sums (items)
     int32_t *ctrl;         // see kCtl* below
@@ -136,7 +142,7 @@ struct BatchDev {
     int64_t sparse_arcs;   // a level runs sparse when its frontier has fewer arcs
     unsigned long long *stats;  // NULL, or work counters when measuring (see
                                 // kStatWords)
-    double *bc;            // [n] accumulated BC (internal order), when nseg == 0
+    double *bc;            // [H][n] accumulated BC per half (internal order), when nseg == 0
     // Several requests in one batch (nseg > 0): lanes [seg_start[g],
     // seg_start[g+1]) feed seg_out[g], an [n] array in caller vertex order.
     int32_t nseg;
@@ -148,9 +154,9 @@ struct BatchDev {
     // from them and stored times xs[L][s] = 2^-k, k chosen from the largest
     // stored value of level L (xmax[L][s], the bits of a positive double) so
     // that counts of any size stay inside double's range.
-    double *xs;                 // [lcap][64]
-    int32_t *xe;                // [lcap][64]
-    unsigned long long *xmax;   // [lcap][64]
+    double *xs;                 // [lcap][H][64]
+    int32_t *xe;                // [lcap][H][64]
+    unsigned long long *xmax;   // [lcap][H][64]
 };
 
 // BatchDev::ctrl layout (int32 words).
@@ -183,14 +189,13 @@ unsigned int exec_partial_pagerank();
 #endif
 
 // Launchers (bc_batched.hip).  All are asynchronous on `stream`.
-// Clear the batch state and seed lane s with source src_dev[s], s < nlanes.
+// Clear the batch state and seed source s with src_dev[s], s < nlanes (<= 64 H).
 hipError_t batch_start(const BatchDev &d, const int32_t *src_dev, int32_t nlanes,
                        hipStream_t stream);
-// Forward iteration L -> L+1 (full = mask of the lanes in use), then
-// batch_forward_done (completes split vertices, depth bookkeeping).
-hipError_t batch_forward(const BatchDev &d, int32_t level, uint64_t full, hipStream_t stream);
-hipError_t batch_forward_done(const BatchDev &d, int32_t level, uint64_t full,
-                              hipStream_t stream);
+// Forward iteration L -> L+1 (nlanes sources in use), then batch_forward_done
+// (completes split vertices, depth bookkeeping).
+hipError_t batch_forward(const BatchDev &d, int32_t level, int32_t nlanes, hipStream_t stream);
+hipError_t batch_forward_done(const BatchDev &d, int32_t level, hipStream_t stream);
 // Reverse iteration of level L (>= 1): child sums (not for the deepest
 // level), then batch_finalize (delta, c, BC).
 hipError_t batch_reverse(const BatchDev &d, int32_t level, hipStream_t stream);

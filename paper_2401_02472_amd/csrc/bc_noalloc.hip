@@ -76,16 +76,16 @@ bool layout_of(const bc_graph_s *g, Layout &L) {
     L.coef = take(n * kWave * sizeof(double));
     L.ctrl = take(kBatchCtrlInts * sizeof(int32_t));
     L.bc = take(n * sizeof(double));
-    L.reach = take((size_t)std::max(g->multi_end, 1) * sizeof(uint64_t));
+    L.reach = take((size_t)std::max(g->bci.multi_end, 1) * sizeof(uint64_t));
     L.partial = take(partial_rows(g) * kWave * sizeof(double));
     L.clist = take(n * sizeof(int32_t));
-    L.ilist = take((size_t)std::max<uint32_t>(g->items_in, 1) * sizeof(int32_t));
+    L.ilist = take((size_t)std::max<uint32_t>(g->bci.items_in, 1) * sizeof(int32_t));
     L.cand = take(((n + 15) / 16) * 16);
     L.front = take((size_t)kFrontSets * kFrontWaves * 2 * sizeof(unsigned long long));
     L.lanes = take(kWave * sizeof(int32_t));
     L.levels = at;
     if (at >= kScratchBytes) return false;
-    const size_t per_level = batch_level_bytes(g, 1);
+    const size_t per_level = batch_level_bytes(g, 1, 1);
     // a graph's depth is at most n - 1: n + 1 levels always suffice
     const size_t fit = (kScratchBytes - at) / per_level;
     L.lcap = (int32_t)std::min<size_t>(fit, (size_t)g->n + 1);
@@ -115,18 +115,12 @@ extern "C" bc_status bc_run_async_noalloc(bc_graph_t g, const int32_t *sources, 
     // the workspace, as batch_ws_create lays it out, inside the array
     BatchDev d{};
     d.n = g->n;
+    d.H = 1;
     d.row_ptr = g->d_row_ptr;
     d.col_idx = g->d_col_idx;
-    d.big_end = g->big_end;
-    d.multi_end = g->multi_end;
-    d.items = g->items;
-    d.item_info = g->d_item_info;
-    d.item_first = g->d_item_first;
-    d.items_in = g->items_in;
+    set_items(g, d);
     d.row_ptr_in = g->d_row_ptr_in;
     d.col_idx_in = g->d_col_idx_in;
-    d.item_info_in = g->d_item_info_in;
-    d.item_first_in = g->d_item_first_in;
     d.vis = (uint64_t *)(base + L.vis);
     d.sigma = (double *)(base + L.sigma);
     d.sigma32 = reinterpret_cast<uint32_t *>(d.sigma);

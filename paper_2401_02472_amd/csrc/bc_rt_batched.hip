@@ -8,31 +8,47 @@ namespace bcx {
 // Chunk items with a partial row: both passes' items (the forward pass runs
 // over the arcs into each vertex, the reverse pass over the arcs out of it).
 size_t partial_rows(const bc_graph_s *g) {
-    return (size_t)std::max<uint32_t>(std::max(g->items, g->items_in), 1);
+    return (size_t)std::max<uint32_t>(std::max(g->bci.items, g->bci.items_in), 1);
 }
 
-size_t batch_ws_bytes(const bc_graph_s *g) {
+// The batched path's work items of a workspace: the graph's current tables.
+void set_items(const bc_graph_s *g, BatchDev &d) {
+    const auto &t = g->bci;
+    d.big_end = t.big_end;
+    d.multi_end = t.multi_end;
+    d.chunk = t.chunk;
+    d.items = t.items;
+    d.item_info = t.info;
+    d.item_first = t.first;
+    d.items_in = t.items_in;
+    d.item_info_in = t.info_in;
+    d.item_first_in = t.first_in;
+}
+
+size_t batch_ws_bytes(const bc_graph_s *g, int32_t H) {
     const size_t n = (size_t)std::max<int32_t>(g->n, 1);
+    const size_t lanes = (size_t)H * kWave;
     size_t b = 0;
-    b += align_up(n * sizeof(uint64_t));                 // vis
-    b += 2 * align_up(n * kWave * sizeof(double));       // sigma, coef rows
+    b += align_up(n * H * sizeof(uint64_t));             // vis
+    b += 2 * align_up(n * lanes * sizeof(double));       // sigma, coef rows
     b += align_up(kBatchCtrlInts * sizeof(int32_t));     // ctrl
-    b += align_up(n * sizeof(double));                   // bc
-    b += align_up((size_t)std::max(g->multi_end, 1) * sizeof(uint64_t));  // reach
-    b += align_up(partial_rows(g) * kWave * sizeof(double));  // chunk partial rows
+    b += align_up(n * H * sizeof(double));               // bc, one array per half
+    b += align_up((size_t)std::max(g->bci.multi_end, 1) * H * sizeof(uint64_t));  // reach
+    b += align_up(partial_rows(g) * lanes * sizeof(double));  // chunk partial rows
     b += align_up(kStatWords * sizeof(unsigned long long));     // work counters
     b += align_up(n * sizeof(int32_t));                  // candidate list
     // item list of the sparse step (the forward pass's items)
-    b += align_up((size_t)std::max<uint32_t>(g->items_in, 1) * sizeof(int32_t));
+    b += align_up((size_t)std::max<uint32_t>(g->bci.items_in, 1) * sizeof(int32_t));
     b += align_up((size_t)kFrontSets * kFrontWaves * 2 * sizeof(unsigned long long));
     b += align_up(((n + 15) / 16) * 16);                 // candidate marks
     return b;
 }
 
-// F[lcap][n] and the extended-range tables xs, xmax, xe ([lcap][64] each).
-size_t batch_level_bytes(const bc_graph_s *g, int32_t lcap) {
-    return (size_t)lcap * ((size_t)std::max<int32_t>(g->n, 1) * sizeof(uint64_t) +
-                           kWave * (sizeof(double) + sizeof(unsigned long long) + sizeof(int32_t)));
+// F[lcap][n][H] and the extended-range tables xs, xmax, xe ([lcap][H][64] each).
+size_t batch_level_bytes(const bc_graph_s *g, int32_t lcap, int32_t H) {
+    return (size_t)lcap * H *
+           ((size_t)std::max<int32_t>(g->n, 1) * sizeof(uint64_t) +
+            kWave * (sizeof(double) + sizeof(unsigned long long) + sizeof(int32_t)));
 }
 
 void batch_ws_destroy(BatchWS *ws) {
@@ -49,10 +65,11 @@ void batch_ws_destroy(BatchWS *ws) {
     delete ws;
 }
 
-bc_status batch_ws_create(bc_graph_s *g, BatchWS **out) {
+bc_status batch_ws_create(bc_graph_s *g, int32_t H, BatchWS **out) {
     BatchWS *ws = new (std::nothrow) BatchWS();
     if (!ws) return BC_ERR_OUT_OF_MEMORY;
-    ws->bytes = batch_ws_bytes(g);
+    ws->H = H;
+    ws->bytes = batch_ws_bytes(g, H);
     hipError_t e = hipMalloc(&ws->block, ws->bytes);
     if (e == hipSuccess)
         e = hipHostMalloc((void **)&ws->h_ctrl, kBatchCtrlInts * sizeof(int32_t),
@@ -70,32 +87,27 @@ bc_status batch_ws_create(bc_graph_s *g, BatchWS **out) {
         return (void *)r;
     };
     BatchDev &d = ws->dev;
+    const size_t lanes = (size_t)H * kWave;
     d.n = g->n;
+    d.H = H;
     d.row_ptr = g->d_row_ptr;
     d.col_idx = g->d_col_idx;
-    d.vis = (uint64_t *)take(n * sizeof(uint64_t));
-    d.sigma = (double *)take(n * kWave * sizeof(double));
+    d.vis = (uint64_t *)take(n * H * sizeof(uint64_t));
+    d.sigma = (double *)take(n * lanes * sizeof(double));
     d.sigma32 = reinterpret_cast<uint32_t *>(d.sigma);
     d.narrow = 1;
-    d.coef = (double *)take(n * kWave * sizeof(double));
+    d.coef = (double *)take(n * lanes * sizeof(double));
     d.ctrl = (int32_t *)take(kBatchCtrlInts * sizeof(int32_t));
-    d.bc = (double *)take(n * sizeof(double));
-    d.reach = (uint64_t *)take((size_t)std::max(g->multi_end, 1) * sizeof(uint64_t));
-    d.partial = (double *)take(partial_rows(g) * kWave * sizeof(double));
-    d.big_end = g->big_end;
-    d.multi_end = g->multi_end;
-    d.items = g->items;
-    d.item_info = g->d_item_info;
-    d.item_first = g->d_item_first;
-    d.items_in = g->items_in;
+    d.bc = (double *)take(n * H * sizeof(double));
+    d.reach = (uint64_t *)take((size_t)std::max(g->bci.multi_end, 1) * H * sizeof(uint64_t));
+    d.partial = (double *)take(partial_rows(g) * lanes * sizeof(double));
+    set_items(g, d);
     d.row_ptr_in = g->d_row_ptr_in;
     d.col_idx_in = g->d_col_idx_in;
-    d.item_info_in = g->d_item_info_in;
-    d.item_first_in = g->d_item_first_in;
     ws->d_stats = (unsigned long long *)take(kStatWords * sizeof(unsigned long long));
     d.stats = nullptr;
     d.clist = (int32_t *)take(n * sizeof(int32_t));
-    d.ilist = (int32_t *)take((size_t)std::max<uint32_t>(g->items_in, 1) * sizeof(int32_t));
+    d.ilist = (int32_t *)take((size_t)std::max<uint32_t>(g->bci.items_in, 1) * sizeof(int32_t));
     d.cand = (uint8_t *)take(((n + 15) / 16) * 16);
     d.front = (unsigned long long *)take((size_t)kFrontSets * kFrontWaves * 2 *
                                          sizeof(unsigned long long));
@@ -112,21 +124,22 @@ bc_status batch_grow_levels(bc_graph_s *g, BatchWS *ws, int32_t lcap) {
     if (ws->F) (void)hipFree(ws->F);
     ws->F = nullptr;
     ws->lcap = 0;
-    BC_TRY_HIP(hipMalloc(&ws->F, batch_level_bytes(g, lcap)));
+    const int32_t H = ws->H;
+    BC_TRY_HIP(hipMalloc(&ws->F, batch_level_bytes(g, lcap, H)));
     ws->lcap = lcap;
     ws->dev.F = ws->F;
     ws->dev.lcap = lcap;
-    ws->xs = (double *)(ws->F + (size_t)lcap * (size_t)std::max<int32_t>(g->n, 1));
-    ws->xmax = (unsigned long long *)(ws->xs + (size_t)lcap * kWave);
-    ws->xe = (int32_t *)(ws->xmax + (size_t)lcap * kWave);
+    ws->xs = (double *)(ws->F + (size_t)lcap * H * (size_t)std::max<int32_t>(g->n, 1));
+    ws->xmax = (unsigned long long *)(ws->xs + (size_t)lcap * H * kWave);
+    ws->xe = (int32_t *)(ws->xmax + (size_t)lcap * H * kWave);
     return BC_OK;
 }
 
-bc_status batch_acquire(bc_graph_s *g, hipStream_t stream, BatchWS **out) {
+bc_status batch_acquire(bc_graph_s *g, int32_t H, hipStream_t stream, BatchWS **out) {
     {
         std::lock_guard<std::mutex> lk(g->mu);
         for (BatchWS *ws : g->batch_pool) {
-            if (!ws->busy) {
+            if (!ws->busy && ws->H == H) {
                 ws->busy = true;
                 *out = ws;
                 BC_TRY_HIP(hipStreamWaitEvent(stream, ws->done, 0));
@@ -135,7 +148,7 @@ bc_status batch_acquire(bc_graph_s *g, hipStream_t stream, BatchWS **out) {
         }
     }
     BatchWS *ws = nullptr;
-    bc_status st = batch_ws_create(g, &ws);
+    bc_status st = batch_ws_create(g, H, &ws);
     if (st != BC_OK) return st;
     ws->busy = true;
     std::lock_guard<std::mutex> lk(g->mu);
@@ -177,7 +190,6 @@ hipError_t drive_batch(bc_graph_s *g, BatchDev &d, const ExtTables &ext, const i
                        unsigned long long *d_stats, int32_t stride, BatchOutcome &how,
                        int32_t &deepest) {
     const int32_t n = g->n;
-    const uint64_t full = nl >= 64 ? ~0ull : ((1ull << nl) - 1ull);
     const bool prof = d_stats != nullptr;
     auto measure = [&](int32_t L) {
         const bool m = prof && L % stride == 0;
@@ -200,10 +212,10 @@ hipError_t drive_batch(bc_graph_s *g, BatchDev &d, const ExtTables &ext, const i
         for (int32_t L = L0; L < Lend && e == hipSuccess; ++L) {
             measure(L);
             e = timer.begin(BC_PROF_FORWARD, stream);
-            if (e == hipSuccess) e = batch_forward(d, L, full, stream);
+            if (e == hipSuccess) e = batch_forward(d, L, nl, stream);
             if (e == hipSuccess) e = timer.end(stream);
             if (e == hipSuccess) e = timer.begin(BC_PROF_COMPACT, stream);
-            if (e == hipSuccess) e = batch_forward_done(d, L, full, stream);
+            if (e == hipSuccess) e = batch_forward_done(d, L, stream);
             if (e == hipSuccess) e = timer.end(stream);
         }
         if (e == hipSuccess)
@@ -263,8 +275,12 @@ bc_status run_batch_plan(bc_graph_s *g, const std::vector<int32_t> &s_int,
                          const std::vector<double *> &seg_out, double *bc_out,
                          hipStream_t stream, const int32_t *export_row, int32_t *dist,
                          double *sigma, int32_t sparse_div) {
+    // two lane words per vertex when a batch has more than 64 sources (never
+    // with request segments: their lanes are summed within one 64-lane word)
+    int32_t H = 1;
+    for (const BatchPlan &bp : plan) H = std::max(H, bp.nlanes > kWave ? 2 : 1);
     BatchWS *ws = nullptr;
-    bc_status st = batch_acquire(g, stream, &ws);
+    bc_status st = batch_acquire(g, H, stream, &ws);
     if (st != BC_OK) return st;
     auto fail = [&](bc_status s2) {
         batch_release(g, ws, stream);
@@ -276,8 +292,9 @@ bc_status run_batch_plan(bc_graph_s *g, const std::vector<int32_t> &s_int,
     ws->dev.stats = prof ? ws->d_stats : nullptr;
     ws->timer.on = prof;
     ws->timer.used = 0;
-    // frontier arcs below which a level takes the sparse step (0: never)
-    ws->dev.sparse_arcs = sparse_div < 0 ? 0 : g->nnz / std::max(sparse_div, 1);
+    // frontier arcs below which a level takes the sparse step (0: never); the
+    // halves of a two-word batch count their frontiers separately
+    ws->dev.sparse_arcs = sparse_div < 0 ? 0 : H * (g->nnz / std::max(sparse_div, 1));
     if (prof) {
         hipError_t ez = hipMemsetAsync(ws->d_stats, 0, kStatWords * sizeof(unsigned long long), stream);
         if (ez != hipSuccess) return fail(from_hip(ez));
@@ -311,8 +328,9 @@ bc_status run_batch_plan(bc_graph_s *g, const std::vector<int32_t> &s_int,
         }
     } tmp_guard{x_dist, x_sigma};
     hipError_t e = hipSuccess;
-    if (dist) e = hipMalloc(&x_dist, (size_t)kWave * (size_t)n * sizeof(int32_t));
-    if (e == hipSuccess && sigma) e = hipMalloc(&x_sigma, (size_t)kWave * (size_t)n * sizeof(double));
+    if (dist) e = hipMalloc(&x_dist, (size_t)H * kWave * (size_t)n * sizeof(int32_t));
+    if (e == hipSuccess && sigma)
+        e = hipMalloc(&x_sigma, (size_t)H * kWave * (size_t)n * sizeof(double));
     if (e == hipSuccess && k > 0)
         e = hipMemcpyAsync(d_lanes, s_int.data(), (size_t)k * sizeof(int32_t),
                            hipMemcpyHostToDevice, stream);
@@ -323,7 +341,7 @@ bc_status run_batch_plan(bc_graph_s *g, const std::vector<int32_t> &s_int,
         e = hipMemcpyAsync(d_seg_out, seg_out.data(), seg_ptrs * sizeof(double *),
                            hipMemcpyHostToDevice, stream);
     if (e == hipSuccess && bc_out)
-        e = hipMemsetAsync(ws->dev.bc, 0, (size_t)n * sizeof(double), stream);
+        e = hipMemsetAsync(ws->dev.bc, 0, (size_t)H * n * sizeof(double), stream);
     if (e == hipSuccess)  // the batches' kernels only ever set the range flag
         e = hipMemsetAsync(ws->dev.ctrl + kCtlRange, 0, sizeof(int32_t), stream);
     if (e != hipSuccess) return fail(from_hip(e));
@@ -369,7 +387,9 @@ bc_status run_batch_plan(bc_graph_s *g, const std::vector<int32_t> &s_int,
         ++bi;
     }
     ws->dev.nseg = 0;
-    if (bc_out) e = gather_f64(n, g->d_perm, ws->dev.bc, bc_out, stream);
+    // the halves' BC arrays added (half 0 + half 1, in place)
+    if (bc_out && H > 1) e = sum_parts(n, ws->dev.bc, H, ws->dev.bc, stream);
+    if (e == hipSuccess && bc_out) e = gather_f64(n, g->d_perm, ws->dev.bc, bc_out, stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(ws->h_ctrl, ws->dev.ctrl, kBatchCtrlInts * sizeof(int32_t),
                            hipMemcpyDeviceToHost, stream);
@@ -388,7 +408,7 @@ bc_status run_batch_plan(bc_graph_s *g, const std::vector<int32_t> &s_int,
 // split-vertex rows, partial rows, the level array).
 size_t fused_batch_bytes(const bc_graph_s *g, int32_t lcap) {
     const size_t n = (size_t)std::max<int32_t>(g->n, 1);
-    const size_t multi = (size_t)std::max(g->multi_end, 1);
+    const size_t multi = (size_t)std::max(g->bci.multi_end, 1);
     return align_up(n * sizeof(uint64_t)) + 2 * align_up(n * kWave * sizeof(double)) +
            align_up(multi * sizeof(uint64_t)) + align_up(partial_rows(g) * kWave * sizeof(double)) +
            align_up((size_t)lcap * n * sizeof(uint64_t));
@@ -467,18 +487,12 @@ bc_status fused_reserve(bc_graph_s *g, int32_t cap, int32_t lcap) {
     for (int32_t b = 0; b < cap; ++b) {
         BatchDev &d = f.h_devs[(size_t)b];
         d.n = g->n;
+        d.H = 1;
         d.row_ptr = g->d_row_ptr;
         d.col_idx = g->d_col_idx;
-        d.big_end = g->big_end;
-        d.multi_end = g->multi_end;
-        d.items = g->items;
-        d.item_info = g->d_item_info;
-        d.item_first = g->d_item_first;
-        d.items_in = g->items_in;
+        set_items(g, d);
         d.row_ptr_in = g->d_row_ptr_in;
         d.col_idx_in = g->d_col_idx_in;
-        d.item_info_in = g->d_item_info_in;
-        d.item_first_in = g->d_item_first_in;
         d.iperm = g->d_iperm;
         d.nnz = g->nnz;
         d.lcap = lcap;
@@ -488,7 +502,7 @@ bc_status fused_reserve(bc_graph_s *g, int32_t cap, int32_t lcap) {
         d.sigma = (double *)take(n * kWave * sizeof(double));
         d.sigma32 = reinterpret_cast<uint32_t *>(d.sigma);
         d.coef = (double *)take(n * kWave * sizeof(double));
-        d.reach = (uint64_t *)take((size_t)std::max(g->multi_end, 1) * sizeof(uint64_t));
+        d.reach = (uint64_t *)take((size_t)std::max(g->bci.multi_end, 1) * sizeof(uint64_t));
         d.partial = (double *)take(partial_rows(g) * kWave * sizeof(double));
         d.F = (uint64_t *)take((size_t)lcap * n * sizeof(uint64_t));
     }
@@ -654,8 +668,9 @@ bc_status fused_run(bc_graph_s *g, const std::vector<int32_t> &s_int,
 // 2 ms + 50 ns per arc on the device loop and, amortised over the host loop's
 // concurrent parts, 0.8 ms + 0.15 ns per arc on the host loop.  AUTO picks
 // the loop with the lower estimate for the call's batch count.
-bool use_fused(const bc_graph_s *g, int32_t level_loop, int32_t nbatches) {
+bool use_fused(const bc_graph_s *g, int32_t level_loop, int32_t nbatches, int32_t width) {
     if (g->sigma_ext.load()) return false;  // extended range: host loop only
+    if (width > kWave) return false;        // one lane word per vertex only
     if (level_loop == BC_LOOP_DEVICE) return true;
     if (level_loop == BC_LOOP_HOST) return false;
     const double arcs = (double)g->nnz;
@@ -670,10 +685,10 @@ bool use_fused(const bc_graph_s *g, int32_t level_loop, int32_t nbatches) {
 // from run to run).  Parts overlap one another's small kernels and host
 // polls; beyond the process's 4 hardware queues they gain nothing, and the
 // large graphs' level kernels already fill the device.
-int32_t parts_of(const bc_graph_s *g, int32_t concurrency, int32_t nbatches) {
+int32_t parts_of(const bc_graph_s *g, int32_t concurrency, int32_t nbatches, int32_t H) {
     int32_t p = concurrency;
     if (p <= 0) {
-        const size_t ws = batch_ws_bytes(g) + batch_level_bytes(g, 16);
+        const size_t ws = batch_ws_bytes(g, H) + batch_level_bytes(g, 16, H);
         p = ws <= ((size_t)1 << 30) ? 4 : (ws <= ((size_t)16 << 30) ? 2 : 1);
     }
     return std::max(1, std::min(p, nbatches));
@@ -716,13 +731,13 @@ bc_status batched_run(bc_graph_s *g, const int32_t *sources, int32_t k, double *
     for (int32_t i = 0; i < k; ++i) s_int[(size_t)i] = g->h_perm[(size_t)sources[order[(size_t)i]]];
     std::vector<BatchPlan> plan;
     for (int32_t b0 = 0; b0 < k; b0 += width) plan.push_back({b0, std::min(width, k - b0), 0, 0});
-    if (use_fused(g, level_loop, (int32_t)plan.size())) {
+    if (use_fused(g, level_loop, (int32_t)plan.size(), width)) {
         // a count beyond double's range sends the call to the host loop
         const bc_status st =
             fused_run(g, s_int, plan, {}, {}, bc_out, stream, order.data(), dist, sigma);
         if (st != BC_ERR_RANGE || !g->sigma_ext.load()) return st;
     }
-    const int32_t P = parts_of(g, concurrency, (int32_t)plan.size());
+    const int32_t P = parts_of(g, concurrency, (int32_t)plan.size(), width > kWave ? 2 : 1);
     if (P <= 1)
         return run_batch_plan(g, s_int, plan, {}, {}, bc_out, stream, order.data(), dist, sigma,
                               sparse_div);
@@ -839,7 +854,7 @@ bc_status multi_run(bc_graph_s *g, const int32_t *sources, const int32_t *req_st
     // request spans two batches (no two workgroups add to one output)
     bool spans = false;
     for (int32_t r = 0; r < nreq; ++r) spans |= req_start[r + 1] - req_start[r] > kWave;
-    if (!spans && use_fused(g, BC_LOOP_AUTO, (int32_t)plan.size())) {
+    if (!spans && use_fused(g, BC_LOOP_AUTO, (int32_t)plan.size(), kWave)) {
         const bc_status st = fused_run(g, s_int, plan, seg_start, seg_out, nullptr, stream,
                                        nullptr, nullptr, nullptr);
         if (st != BC_ERR_RANGE || !g->sigma_ext.load()) return st;

@@ -45,7 +45,28 @@ bc_status validate_csr(int32_t n, const int32_t *row_ptr, const int32_t *col_idx
 
 // The graph's device arrays (the reversed CSR and its items only when they
 // are arrays of their own, i.e. for a directed graph).
+// The BC tables back to the default ones (freeing owned arrays).
+void reset_bc_items(bc_graph_s *g) {
+    auto &t = g->bci;
+    if (t.owned) {
+        (void)hipFree(t.info);
+        (void)hipFree(t.first);
+        if (t.info_in != t.info) (void)hipFree(t.info_in);
+        if (t.first_in != t.first) (void)hipFree(t.first_in);
+    }
+    t = bc_graph_s::BcItems{};
+    t.big_end = g->big_end;
+    t.multi_end = g->multi_end;
+    t.items = g->items;
+    t.items_in = g->items_in;
+    t.info = g->d_item_info;
+    t.first = g->d_item_first;
+    t.info_in = g->d_item_info_in;
+    t.first_in = g->d_item_first_in;
+}
+
 void free_graph_arrays(bc_graph_s *g) {
+    if (g->bci.owned) reset_bc_items(g);
     if (g->directed) {
         if (g->d_row_ptr_in) (void)hipFree(g->d_row_ptr_in);
         if (g->d_col_idx_in) (void)hipFree(g->d_col_idx_in);
@@ -78,6 +99,88 @@ void free_graph_arrays(bc_graph_s *g) {
     g->d_row_ptr = g->d_col_idx = g->d_perm = g->d_iperm = nullptr;
     g->d_item_info = nullptr;
     g->d_item_first = nullptr;
+}
+
+bc_status set_bc_items(bc_graph_s *g, int32_t cut, int32_t chunk) {
+    const int32_t n = g->n;
+    if (cut < 1 || chunk < kWave || chunk % kWave != 0 || chunk > 4096 || chunk < cut)
+        return BC_ERR_INVALID_ARG;
+    if (cut == g->bci.cut && chunk == g->bci.chunk) return BC_OK;
+    // idle pooled workspaces go (their partial rows follow the items); the
+    // device-loop pool too
+    (void)bc_trim_workspaces(g);
+    if (cut == kB1MaxDeg && chunk == kChunk) {
+        reset_bc_items(g);
+        return BC_OK;
+    }
+    // degrees in the internal order (out-arcs; in-arcs of a directed graph)
+    std::vector<int32_t> rp((size_t)n + 1), rp_in;
+    BC_TRY_HIP(hipMemcpy(rp.data(), g->d_row_ptr, rp.size() * sizeof(int32_t),
+                         hipMemcpyDeviceToHost));
+    if (g->directed) {
+        rp_in.resize((size_t)n + 1);
+        BC_TRY_HIP(hipMemcpy(rp_in.data(), g->d_row_ptr_in, rp_in.size() * sizeof(int32_t),
+                             hipMemcpyDeviceToHost));
+    }
+    auto out_deg = [&](int32_t u) { return rp[(size_t)u + 1] - rp[(size_t)u]; };
+    auto in_deg = [&](int32_t u) {
+        return g->directed ? rp_in[(size_t)u + 1] - rp_in[(size_t)u] : out_deg(u);
+    };
+    auto key_deg = [&](int32_t u) { return std::max(out_deg(u), in_deg(u)); };
+    bc_graph_s::BcItems t;
+    t.cut = cut;
+    t.chunk = chunk;
+    std::vector<int2> info, info_in;
+    std::vector<uint32_t> first, first_in;
+    // internal ids are key-degree-descending: the vertices above the cut are
+    // a prefix, each with at least one item per direction
+    for (int32_t u = 0; u < n; ++u) {
+        if (key_deg(u) <= cut) break;
+        t.big_end = u + 1;
+        if (key_deg(u) > chunk) t.multi_end = u + 1;
+        first.push_back((uint32_t)info.size());
+        for (int32_t j = 0; j == 0 || (int64_t)j * chunk < out_deg(u); ++j)
+            info.push_back(make_int2(u, j));
+        if (g->directed) {
+            first_in.push_back((uint32_t)info_in.size());
+            for (int32_t j = 0; j == 0 || (int64_t)j * chunk < in_deg(u); ++j)
+                info_in.push_back(make_int2(u, j));
+        }
+    }
+    first.push_back((uint32_t)info.size());
+    if (g->directed) first_in.push_back((uint32_t)info_in.size());
+    t.items = (uint32_t)info.size();
+    t.items_in = g->directed ? (uint32_t)info_in.size() : t.items;
+    hipError_t e = hipSuccess;
+    auto upload = [&](const std::vector<int2> &in_info, const std::vector<uint32_t> &in_first,
+                      int2 **d_info, uint32_t **d_first) {
+        if (e == hipSuccess) e = hipMalloc(d_info, std::max<size_t>(in_info.size(), 1) * sizeof(int2));
+        if (e == hipSuccess) e = hipMalloc(d_first, in_first.size() * sizeof(uint32_t));
+        if (e == hipSuccess && !in_info.empty())
+            e = hipMemcpy(*d_info, in_info.data(), in_info.size() * sizeof(int2),
+                          hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy(*d_first, in_first.data(), in_first.size() * sizeof(uint32_t),
+                          hipMemcpyHostToDevice);
+    };
+    upload(info, first, &t.info, &t.first);
+    if (g->directed) {
+        upload(info_in, first_in, &t.info_in, &t.first_in);
+    } else {
+        t.info_in = t.info;
+        t.first_in = t.first;
+    }
+    t.owned = true;
+    if (e != hipSuccess) {
+        if (t.info) (void)hipFree(t.info);
+        if (t.first) (void)hipFree(t.first);
+        if (g->directed && t.info_in) (void)hipFree(t.info_in);
+        if (g->directed && t.first_in) (void)hipFree(t.first_in);
+        return from_hip(e);
+    }
+    reset_bc_items(g);  // frees the previous owned tables
+    g->bci = t;
+    return BC_OK;
 }
 
 }  // namespace bcx
@@ -152,7 +255,13 @@ bc_status bc_create_graph(int32_t n, const int32_t *row_ptr, const int32_t *col_
 
     // Internal order: key degree descending, ties by caller id (counting sort).
     int32_t maxdeg = 0;
-    for (int32_t v = 0; v < n; ++v) maxdeg = std::max(maxdeg, key_deg(v));
+    for (int32_t v = 0; v < n; ++v) {
+        const int32_t kd = key_deg(v);
+        maxdeg = std::max(maxdeg, kd);
+        int c = 0;
+        while (c < 32 && ((int64_t)1 << c) <= kd) ++c;
+        g->deg_class[c]++;
+    }
     std::vector<int64_t> start((size_t)maxdeg + 2, 0);
     for (int32_t v = 0; v < n; ++v) start[(size_t)(maxdeg - key_deg(v)) + 1]++;
     for (size_t i = 1; i < start.size(); ++i) start[i] += start[i - 1];
@@ -279,9 +388,11 @@ bc_status bc_create_graph(int32_t n, const int32_t *row_ptr, const int32_t *col_
         return from_hip(e);
     }
     g->device_bytes = (directed ? 2 : 1) * (rp_bytes + ci_bytes) + 2 * pm_bytes;
+    reset_bc_items(g);
     *out = g;
     return BC_OK;
 }
+
 
 bc_status bc_destroy_graph(bc_graph_t g) {
     if (!g) return BC_OK;

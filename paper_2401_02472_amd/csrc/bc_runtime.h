@@ -84,9 +84,11 @@ struct PlainWS {
     bool busy = false;
 };
 
-// Batched workspace: lane-major sigma / c rows for 64 sources, masks, and a
-// level array that grows when a batch runs deeper than it holds.
+// Batched workspace: lane-major sigma / c rows for 64 sources (128 with two
+// lane words per vertex), masks, and a level array that grows when a batch
+// runs deeper than it holds.
 struct BatchWS {
+    int32_t H = 1;             // lane words per vertex (1: 64 sources, 2: 128)
     LaunchTimer timer;
     unsigned long long *d_stats = nullptr;  // kStatWords counters
     void *block = nullptr;     // vis, sigma, coef, ctrl, bc
@@ -182,6 +184,19 @@ struct bc_graph_s {
     int2 *d_item_info_in = nullptr;
     uint32_t *d_item_first_in = nullptr;
     uint64_t total_chunks3 = 0;
+    // The batched BC path's work items: vertices of degree above `cut` (a
+    // prefix of the internal order) in chunks of `chunk` arcs, the ones above
+    // `chunk` spanning several items.  They start as the tables above (cut 64,
+    // chunk 512), which SSSP and PageRank keep; bc_autotune may rebuild them
+    // with other thresholds (owned: separate device arrays).
+    struct BcItems {
+        int32_t cut = 64, chunk = 512;
+        int32_t big_end = 0, multi_end = 0;
+        uint32_t items = 0, items_in = 0;
+        int2 *info = nullptr, *info_in = nullptr;
+        uint32_t *first = nullptr, *first_in = nullptr;
+        bool owned = false;
+    } bci;
     // single-source shortest paths: arc weights (internal arc order; NULL =
     // every arc weighs 1) and a workspace used by one call at a time
     int32_t *d_weight = nullptr;
@@ -210,6 +225,9 @@ struct bc_graph_s {
     std::atomic<int32_t> tuned_width{bcx::kWave};
     std::atomic<int32_t> tuned_sparse_div{bcx::kDefaultSparseDiv};
     std::atomic<int32_t> tuned_min_batched{16};
+    // vertex counts per degree class (0: degree 0, c >= 1: degree in
+    // [2^(c-1), 2^c)), the shape key of the autotuner's cache
+    int64_t deg_class[33] = {};
     // set once a path count did not fit the batched path's uint32 sigma rows:
     // later batches start with double rows
     std::atomic<bool> sigma_wide{false};
@@ -265,14 +283,15 @@ bc_status bfs_levels(bc_graph_s *g, int32_t s, std::vector<int32_t> &out);
 
 // ---- batched runtime (bc_rt_batched.hip) ----
 size_t partial_rows(const bc_graph_s *g);
-size_t batch_ws_bytes(const bc_graph_s *g);
-size_t batch_level_bytes(const bc_graph_s *g, int32_t lcap);
+void set_items(const bc_graph_s *g, BatchDev &d);
+size_t batch_ws_bytes(const bc_graph_s *g, int32_t H);
+size_t batch_level_bytes(const bc_graph_s *g, int32_t lcap, int32_t H);
 void batch_ws_destroy(BatchWS *ws);
 size_t fused_batch_bytes(const bc_graph_s *g, int32_t lcap);
 int32_t fused_cap(const bc_graph_s *g, int32_t nbatches, int32_t lcap);
 void fused_release(bc_graph_s *g);
-bool use_fused(const bc_graph_s *g, int32_t level_loop, int32_t nbatches);
-int32_t parts_of(const bc_graph_s *g, int32_t concurrency, int32_t nbatches);
+bool use_fused(const bc_graph_s *g, int32_t level_loop, int32_t nbatches, int32_t width);
+int32_t parts_of(const bc_graph_s *g, int32_t concurrency, int32_t nbatches, int32_t H);
 bc_status batched_run(bc_graph_s *g, const int32_t *sources, int32_t k, double *bc_out,
                       int32_t width, int32_t sparse_div, int32_t concurrency,
                       int32_t level_loop, hipStream_t stream, int32_t *dist, double *sigma);
@@ -292,6 +311,11 @@ hipError_t drive_batch(bc_graph_s *g, BatchDev &d, const ExtTables &ext, const i
 
 // ---- graph residency (bc_rt_graph.hip) ----
 void free_graph_arrays(bc_graph_s *g);
+// Rebuild the batched BC path's work items with degree cut `cut` (vertices of
+// higher degree become chunk items) and `chunk` arcs per item; frees every
+// pooled batched workspace (their partial rows follow the item count).  No run
+// on g may be in flight.
+bc_status set_bc_items(bc_graph_s *g, int32_t cut, int32_t chunk);
 
 // ---- policy and argument checks (bc_capi.hip) ----
 void plain_overflowed(bc_graph_s *g);

@@ -79,6 +79,7 @@ def test_invalid_arguments_rejected():
     assert lib.bc_run(None, None, 0, None) == bcm.BC_ERR_INVALID_ARG
     assert lib.bc_graph_info(None, None, None, None) == bcm.BC_ERR_INVALID_ARG
     assert lib.bc_autotune(None, None, 1, None, None) == bcm.BC_ERR_INVALID_ARG
+    assert lib.bc_set_work_items(None, 64, 512) == bcm.BC_ERR_INVALID_ARG
     assert lib.bc_set_weights(None, None) == bcm.BC_ERR_INVALID_ARG
     assert lib.bc_sssp(None, 0, None, None) == bcm.BC_ERR_INVALID_ARG
     assert lib.bc_pagerank(None, 0.85, 0.0, 10, None, None, None) == bcm.BC_ERR_INVALID_ARG
@@ -92,7 +93,9 @@ def test_options_layout_matches_header():
     assert [f[0] for f in _capi.bc_options._fields_] == ["mode", "batch_width", "level_chunk",
                                                         "sparse_div", "concurrency", "level_loop",
                                                         "reserved"]
-    assert ctypes.sizeof(_capi.bc_tuning) == 32
+    # width, sparse_div, min_batched, sample, two doubles, cached, group_cut,
+    # chunk, reserved
+    assert ctypes.sizeof(_capi.bc_tuning) == 48
     o = bcm.make_options(bcm.BC_MODE_BATCHED, 32, 0, sparse_div=-1, concurrency=3,
                          level_loop=bcm.BC_LOOP_DEVICE)
     assert (o.mode, o.batch_width, o.sparse_div, o.concurrency, o.level_loop,

@@ -262,15 +262,63 @@ def test_autotune_then_auto_mode():
     src = gg.sample_sources(g, 100, seed=15)
     with bcm.Graph(g.n, g.row_ptr, g.col_idx) as G:
         t = G.autotune(src)
-        assert t["batch_width"] in (32, 64)
+        assert t["batch_width"] in (32, 64, 128)
         assert t["sparse_div"] in (-1, 16, 64, 256)
         assert t["min_batched"] >= 2
-        assert t["sample"] == 64
+        assert t["sample"] == 100 and not t["cached"]
+        assert t["group_cut"] in (32, 64, 128) and t["chunk"] in (256, 512, 1024)
         assert t["plain_ms_per_source"] > 0 and t["batch_ms"] > 0
         for k in (3, 100):
             want = oracle_bc(g, src[:k])
             check_bc(G.run(src[:k]), want)
             check_bc(run_mode(G, src[:k], bcm.BC_MODE_AUTO), want)
+    # a graph of the same shape takes the remembered choice without timing
+    with bcm.Graph(g.n, g.row_ptr, g.col_idx) as G2:
+        t2 = G2.autotune(src)
+        assert t2["cached"] and t2["sample"] == 0
+        for f in ("batch_width", "sparse_div", "min_batched"):
+            assert t2[f] == t[f]
+        check_bc(run_mode(G2, src, bcm.BC_MODE_AUTO), oracle_bc(g, src))
+
+
+def _shape_line(g, width, div, min_batched, cut=64, chunk=512):
+    """A tuning-cache line for g's shape: n, arcs, direction, and the vertex
+    counts per degree class (class c: degree of bit length c) in 64ths of n."""
+    deg = np.diff(g.row_ptr).astype(np.int64)
+    directed = bool(g.params.get("directed"))
+    if directed:  # the larger of the out- and in-degree
+        deg = np.maximum(deg, np.bincount(g.col_idx, minlength=g.n).astype(np.int64))
+    cls = np.zeros(33, np.int64)
+    for d in deg:
+        cls[min(int(d).bit_length(), 32)] += 1
+    q = [int(np.floor(64.0 * c / g.n + 0.5)) for c in cls]
+    return (f"bc-tune 1 {g.n} {g.nnz} {int(directed)} " + " ".join(map(str, q)) +
+            f" {width} {div} {min_batched} {cut} {chunk} 1.5 2.5\n")
+
+
+def test_autotune_cache_file(tmp_path, monkeypatch):
+    """With BC_MI355X_TUNE_CACHE set, choices are appended to the file, and a
+    shape found there is taken from it (last line for the shape wins)."""
+    path = tmp_path / "tune.txt"
+    monkeypatch.setenv("BC_MI355X_TUNE_CACHE", str(path))
+    g = gg.rmat(12, 16, seed=42)
+    src = gg.sample_sources(g, 40, seed=43)
+    path.write_text(_shape_line(g, 64, 64, 9) + _shape_line(g, 32, 256, 7, cut=32, chunk=1024))
+    with bcm.Graph(g.n, g.row_ptr, g.col_idx) as G:
+        t = G.autotune(src)
+        assert t["cached"] and (t["batch_width"], t["sparse_div"], t["min_batched"]) == (32, 256, 7)
+        assert (t["group_cut"], t["chunk"]) == (32, 1024)
+        check_bc(run_mode(G, src, bcm.BC_MODE_AUTO), oracle_bc(g, src))
+    h = gg.rmat(11, 16, seed=44)
+    src_h = gg.sample_sources(h, 20, seed=45)
+    with bcm.Graph(h.n, h.row_ptr, h.col_idx) as G:
+        t = G.autotune(src_h)
+        assert not t["cached"]
+    lines = path.read_text().splitlines()
+    assert len(lines) == 3 and lines[2].startswith(f"bc-tune 1 {h.n} {h.nnz} 0 ")
+    fields = lines[2].split()
+    assert int(fields[-7]) == t["batch_width"] and int(fields[-6]) == t["sparse_div"]
+    assert int(fields[-4]) == t["group_cut"] and int(fields[-3]) == t["chunk"]
 
 
 def _diamond_chain(k, fan=0):
@@ -510,3 +558,139 @@ def test_split_hub_sums_past_2_53_repeat_bit_for_bit(loop):
         od, osg, _, _ = oracle.single_source(g.row_ptr, g.col_idx, int(s), with_delta=False)
         assert np.array_equal(dist[i], od)
         check_sigma(sigma[i], osg)
+
+
+# ---- batches of up to 128 sources (two lane words per vertex) ----------------
+
+WIDE_GRAPHS = [gg.rmat(13, 16, seed=51), gg.grid_road(80, 80, seed=52), gg.star(5000),
+               gg.complete(150), gg.erdos_renyi(6000, 12, seed=53)]
+
+
+@pytest.mark.parametrize("g", WIDE_GRAPHS, ids=lambda g: g.name)
+@pytest.mark.parametrize("k", [128, 100, 200, 257], ids=lambda k: f"k{k}")
+def test_width_128_batches(g, k):
+    """Batches of up to 128 sources (a full one, a short one, 128 + 72 and
+    128 + 128 + 1): BC against the oracle, and dist / sigma of lanes in both
+    halves of the first batch (sources 0, 63, 64, last)."""
+    src = gg.sample_sources(g, min(k, g.n), seed=54 + k)
+    check_bc(batched(G_of(g), src, batch_width=128, level_loop=bcm.BC_LOOP_HOST),
+             oracle_bc(g, src))
+    lanes = sorted({0, 63, min(64, src.size - 1), min(127, src.size - 1), src.size - 1})
+    opt = bcm.make_options(bcm.BC_MODE_BATCHED, batch_width=128, level_loop=bcm.BC_LOOP_HOST)
+    _, dist, sigma = G_of(g).run_detail(src, opt)
+    for i in lanes:
+        od, osg, _, _ = oracle.single_source(g.row_ptr, g.col_idx, int(src[i]), with_delta=False)
+        assert np.array_equal(dist[i], od), f"dist of lane {i}"
+        check_sigma(sigma[i], osg)
+
+
+_GRAPHS = {}
+
+
+def G_of(g):
+    """One resident graph per test graph (module lifetime)."""
+    if id(g) not in _GRAPHS:
+        _GRAPHS[id(g)] = bcm.Graph(g.n, g.row_ptr, g.col_idx)
+    return _GRAPHS[id(g)]
+
+
+@pytest.mark.parametrize("div", [-1, 16, 4096], ids=lambda d: f"div{d}")
+def test_width_128_sparse_steps_and_parts(div):
+    """Width 128 with the scan-all step only, the frontier-driven step often,
+    and nearly always; two concurrent parts; results repeat bit for bit."""
+    g = gg.rmat(14, 16, seed=55)
+    src = gg.sample_sources(g, 256, seed=56)
+    with bcm.Graph(g.n, g.row_ptr, g.col_idx) as G:
+        a = batched(G, src, batch_width=128, sparse_div=div, concurrency=2,
+                    level_loop=bcm.BC_LOOP_HOST)
+        b = batched(G, src, batch_width=128, sparse_div=div, concurrency=2,
+                    level_loop=bcm.BC_LOOP_HOST)
+    assert np.array_equal(a, b)
+    check_bc(a, oracle_bc(g, src))
+
+
+def test_width_128_wide_rows_and_extended_range():
+    """Counts past 2^32 (the batch reruns with double rows) and past double's
+    range (level-scaled counts) with 128-source batches."""
+    lat = gg.grid_full(60, 60)
+    src = gg.sample_sources(lat, 120, seed=57)
+    with bcm.Graph(lat.n, lat.row_ptr, lat.col_idx) as G:
+        check_bc(batched(G, src, batch_width=128, level_loop=bcm.BC_LOOP_HOST),
+                 oracle_bc(lat, src))
+    ch = gg.diamond_chain(520, 4)
+    src_ch = gg.sample_sources(ch, 100, seed=58)
+    with bcm.Graph(ch.n, ch.row_ptr, ch.col_idx) as G:
+        check_bc(batched(G, src_ch, batch_width=128, level_loop=bcm.BC_LOOP_HOST),
+                 oracle_bc_ext(ch, src_ch))
+
+
+def test_width_128_directed_and_device_loop_request():
+    """A directed graph at width 128, and a device-loop request at width 128
+    (run on the host loop: the device loop keeps one lane word)."""
+    g = gg.rmat(12, 16, seed=59, directed=True)
+    src = gg.sample_sources(g, 150, seed=60)
+    want, st = oracle.bc(g.row_ptr, g.col_idx, src, directed=True)
+    assert st == oracle.OK
+    with bcm.Graph(g.n, g.row_ptr, g.col_idx, flags=bcm.BC_GRAPH_DIRECTED) as G:
+        check_bc(batched(G, src, batch_width=128, level_loop=bcm.BC_LOOP_HOST), want)
+    u = gg.rmat(12, 8, seed=61)
+    src_u = gg.sample_sources(u, 130, seed=62)
+    with bcm.Graph(u.n, u.row_ptr, u.col_idx) as G:
+        check_bc(batched(G, src_u, batch_width=128, level_loop=bcm.BC_LOOP_DEVICE),
+                 oracle_bc(u, src_u))
+
+
+@pytest.mark.parametrize("cut,chunk", [(32, 256), (128, 1024), (64, 64), (16, 2048)],
+                         ids=lambda v: str(v))
+def test_work_item_thresholds(cut, chunk, tmp_path, monkeypatch):
+    """Other degree thresholds for the batched work items (taken from a tuning
+    cache line): a lower or higher cut between group and chunk items, chunks
+    of 64 to 2048 arcs (hubs split into many chunks, or into few).  BC against
+    the oracle on the host loop at widths 64 and 128, on the device loop, and
+    on a directed graph."""
+    path = tmp_path / "tune.txt"
+    monkeypatch.setenv("BC_MI355X_TUNE_CACHE", str(path))
+    seed = 80 + cut + chunk
+    g = gg.rmat(13, 16, seed=seed)
+    dg = gg.rmat(12, 16, seed=seed, directed=True)
+    path.write_text(_shape_line(g, 64, 16, 2, cut=cut, chunk=chunk) +
+                    _shape_line(dg, 64, 16, 2, cut=cut, chunk=chunk))
+    src = gg.sample_sources(g, 150, seed=seed + 1)
+    want = oracle_bc(g, src)
+    with bcm.Graph(g.n, g.row_ptr, g.col_idx) as G:
+        t = G.autotune(src)
+        assert t["cached"] and (t["group_cut"], t["chunk"]) == (cut, chunk)
+        for width in (64, 128):
+            check_bc(batched(G, src, batch_width=width, level_loop=bcm.BC_LOOP_HOST), want)
+        check_bc(batched(G, src, level_loop=bcm.BC_LOOP_DEVICE), want)
+        _, dist, sigma = G.run_detail(src[:2], bcm.make_options(bcm.BC_MODE_BATCHED))
+    for i in range(2):
+        od, osg, _, _ = oracle.single_source(g.row_ptr, g.col_idx, int(src[i]), with_delta=False)
+        assert np.array_equal(dist[i], od)
+        check_sigma(sigma[i], osg)
+    dsrc = gg.sample_sources(dg, 70, seed=seed + 2)
+    dwant, st = oracle.bc(dg.row_ptr, dg.col_idx, dsrc, directed=True)
+    assert st == oracle.OK
+    with bcm.Graph(dg.n, dg.row_ptr, dg.col_idx, flags=bcm.BC_GRAPH_DIRECTED) as G:
+        t = G.autotune(dsrc)
+        assert t["cached"] and (t["group_cut"], t["chunk"]) == (cut, chunk)
+        check_bc(batched(G, dsrc, level_loop=bcm.BC_LOOP_HOST), dwant)
+
+
+def test_set_work_items_explicit():
+    """bc_set_work_items: other thresholds give the oracle's BC; invalid ones
+    are rejected and leave the previous ones in place."""
+    g = gg.rmat(13, 16, seed=91)
+    src = gg.sample_sources(g, 80, seed=92)
+    want = oracle_bc(g, src)
+    with bcm.Graph(g.n, g.row_ptr, g.col_idx) as G:
+        for cut, chunk in [(128, 256), (40, 1024), (64, 512)]:
+            G.set_work_items(cut, chunk)
+            check_bc(batched(G, src, level_loop=bcm.BC_LOOP_HOST), want)
+        G.set_work_items(100, 128)
+        for bad in [(0, 512), (64, 100), (64, 8192), (600, 512)]:
+            with pytest.raises(bcm.BCError) as ei:
+                G.set_work_items(*bad)
+            assert ei.value.status == bcm.BC_ERR_INVALID_ARG
+        check_bc(batched(G, src, level_loop=bcm.BC_LOOP_HOST), want)
+        check_bc(batched(G, src, level_loop=bcm.BC_LOOP_DEVICE), want)
