@@ -618,7 +618,7 @@ fwd_group(const BatchDev &d, int32_t L, int32_t base, const int32_t *list, int32
 }
 
 template <bool N, int H>
-__global__ __launch_bounds__(kBlock) void k_batch_forward(BatchDev d, int32_t L, int32_t nlanes) {
+__global__ __launch_bounds__(kBlock, kLevelWaves) void k_batch_forward(BatchDev d, int32_t L, int32_t nlanes) {
     // nothing past the deepest level found so far (F_L is empty), no room, or
     // this level takes the sparse step
     if (L > d.ctrl[kCtlDeepest] || L + 1 >= d.lcap || d.ctrl[kCtlMode]) return;
@@ -910,7 +910,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_sparse_compact(BatchDev d, int
 
 // Pull over the candidates only (groups of 64 list entries).
 template <bool N, int H>
-__global__ __launch_bounds__(kBlock) void k_batch_sparse_pull(BatchDev d, int32_t L,
+__global__ __launch_bounds__(kBlock, kLevelWaves) void k_batch_sparse_pull(BatchDev d, int32_t L,
                                                               int32_t nlanes) {
     if (L > d.ctrl[kCtlDeepest] || L + 1 >= d.lcap || !d.ctrl[kCtlMode]) return;
     const int32_t c = d.ctrl[kCtlCand];
@@ -1223,7 +1223,7 @@ __device__ __forceinline__ void bwd_group(const BatchDev &d, int32_t L, int32_t 
 }
 
 template <bool N, int H>
-__global__ __launch_bounds__(kBlock) void k_batch_reverse(BatchDev d, int32_t L) {
+__global__ __launch_bounds__(kBlock, kLevelWaves) void k_batch_reverse(BatchDev d, int32_t L) {
     const uint32_t items = d.items;
     const uint32_t groups = (uint32_t)((d.n - d.big_end + kWave - 1) / kWave);
     const uint32_t wave = (blockIdx.x * kBlock + threadIdx.x) / kWave;

@@ -176,6 +176,11 @@ enum {
 // those kernels stores (vertices, arcs) of the new frontier it found in its
 // own slot, and the bookkeeping kernel adds them up (no shared counter).
 constexpr int kMaxGridBlocks = 2048;
+// Waves per SIMD the batched level kernels (forward, sparse pull, reverse)
+// are compiled for: at most 96 VGPRs each, a few values spilled.  Their waves
+// mostly wait on memory, and the fifth wave per SIMD gave 6-7 % on the
+// scale-22 R-MAT (no change on the ER and grid graphs); six spill too much.
+constexpr int kLevelWaves = 5;
 constexpr int kFrontWaves = kMaxGridBlocks * kWavesPerBlock;
 constexpr int kFrontSets = 3;
 

@@ -69,6 +69,7 @@ bc_status batch_ws_create(bc_graph_s *g, int32_t H, BatchWS **out) {
     BatchWS *ws = new (std::nothrow) BatchWS();
     if (!ws) return BC_ERR_OUT_OF_MEMORY;
     ws->H = H;
+    ws->gen = g->bci_gen.load();
     ws->bytes = batch_ws_bytes(g, H);
     hipError_t e = hipMalloc(&ws->block, ws->bytes);
     if (e == hipSuccess)
@@ -139,7 +140,7 @@ bc_status batch_acquire(bc_graph_s *g, int32_t H, hipStream_t stream, BatchWS **
     {
         std::lock_guard<std::mutex> lk(g->mu);
         for (BatchWS *ws : g->batch_pool) {
-            if (!ws->busy && ws->H == H) {
+            if (!ws->busy && ws->H == H && ws->gen == g->bci_gen.load()) {
                 ws->busy = true;
                 *out = ws;
                 BC_TRY_HIP(hipStreamWaitEvent(stream, ws->done, 0));
@@ -456,7 +457,7 @@ int32_t fused_cap(const bc_graph_s *g, int32_t nbatches, int32_t lcap) {
 // existing pool at least that large is kept.
 bc_status fused_reserve(bc_graph_s *g, int32_t cap, int32_t lcap) {
     auto &f = g->fused;
-    if (f.block && f.cap >= cap && f.lcap >= lcap) return BC_OK;
+    if (f.block && f.cap >= cap && f.lcap >= lcap && f.gen == g->bci_gen.load()) return BC_OK;
     fused_release_pool(g);
     const size_t n = (size_t)std::max<int32_t>(g->n, 1);
     const size_t per = fused_batch_bytes(g, lcap);
@@ -475,6 +476,7 @@ bc_status fused_reserve(bc_graph_s *g, int32_t cap, int32_t lcap) {
     }
     f.cap = cap;
     f.lcap = lcap;
+    f.gen = g->bci_gen.load();
     char *p = (char *)f.block;
     auto take = [&](size_t bytes) {
         char *r = p;

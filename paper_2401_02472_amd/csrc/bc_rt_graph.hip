@@ -111,6 +111,7 @@ bc_status set_bc_items(bc_graph_s *g, int32_t cut, int32_t chunk) {
     (void)bc_trim_workspaces(g);
     if (cut == kB1MaxDeg && chunk == kChunk) {
         reset_bc_items(g);
+        g->bci_gen.fetch_add(1);
         return BC_OK;
     }
     // degrees in the internal order (out-arcs; in-arcs of a directed graph)
@@ -180,6 +181,7 @@ bc_status set_bc_items(bc_graph_s *g, int32_t cut, int32_t chunk) {
     }
     reset_bc_items(g);  // frees the previous owned tables
     g->bci = t;
+    g->bci_gen.fetch_add(1);
     return BC_OK;
 }
 

@@ -103,6 +103,7 @@ struct BatchWS {
     int32_t *h_ctrl = nullptr; // pinned mirror of ctrl
     hipEvent_t done = nullptr;
     bool busy = false;
+    int32_t gen = 0;           // the graph's work-item tables it was built for
     BatchDev dev{};
 };
 
@@ -197,6 +198,9 @@ struct bc_graph_s {
         uint32_t *first = nullptr, *first_in = nullptr;
         bool owned = false;
     } bci;
+    // bumped whenever the tables change: pooled workspaces built for other
+    // tables (their partial rows and item pointers) are not reused
+    std::atomic<int32_t> bci_gen{0};
     // single-source shortest paths: arc weights (internal arc order; NULL =
     // every arc weighs 1) and a workspace used by one call at a time
     int32_t *d_weight = nullptr;
@@ -243,6 +247,7 @@ struct bc_graph_s {
         void *block = nullptr;
         size_t bytes = 0;
         int32_t cap = 0, lcap = 0;
+        int32_t gen = 0;            // the work-item tables the pool was built for
         BatchDev *d_devs = nullptr;
         int32_t *h_ctrl = nullptr;  // pinned [cap][kCtlInts]
         int32_t *d_ctrl = nullptr;  // [cap][kCtlInts]
