@@ -93,6 +93,17 @@ def read_traffic(kernel: str, workload: str, src_hash: str):
     return float(m_val.group(1))
 
 
+def traffic_point(traffic, avg_ms: float) -> dict:
+    """The counter side of the roofline: fabric bytes per launch (from the
+    committed counter summary) over the live average launch time, and its
+    fraction of peak.  The L2's misses include MALL hits, so this bounds the
+    HBM rate from above; well above `achieved` it measures over-fetch."""
+    if traffic is None or avg_ms <= 0:
+        return {"traffic_gbps": None, "traffic_frac": None}
+    gbps = traffic / (avg_ms / 1e3) / 1e9
+    return {"traffic_gbps": round(gbps, 1), "traffic_frac": round(gbps / HBM_PEAK_GBS, 4)}
+
+
 def cpu_baseline(g, sources, target_s: float):
     import numpy as np
 
@@ -343,6 +354,7 @@ def sssp_bench(args) -> int:
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": read_traffic("k_sssp_pass", "sssp-rmat-s22-ef16", src_hash),
+            **traffic_point(read_traffic("k_sssp_pass", "sssp-rmat-s22-ef16", src_hash), avg_ms),
             "kernel": "k_sssp_pass", "alg_bytes_per_launch": int(alg),
             "avg_launch_ms": round(avg_ms, 5), "launches": pc["launches"],
             "passes_per_source": round(pc["launches"] / (args.steps * len(sources)), 2),
@@ -423,6 +435,7 @@ def pagerank_bench(args) -> int:
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": read_traffic("k_pr_pull", "pagerank-rmat-s22-ef16", src_hash),
+            **traffic_point(read_traffic("k_pr_pull", "pagerank-rmat-s22-ef16", src_hash), avg_ms),
             "kernel": "k_pr_pull", "alg_bytes_per_launch": int(alg),
             "avg_launch_ms": round(avg_ms, 5), "launches": pc["launches"],
             "kernel_source_hash": src_hash}
@@ -648,6 +661,7 @@ def main() -> int:
         return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": read_traffic(kernel_name, args.workload, src_hash),
+                **traffic_point(read_traffic(kernel_name, args.workload, src_hash), avg_ms),
                 "kernel": kernel_name, "alg_bytes_per_launch": round(per_launch),
                 "avg_launch_ms": round(avg_ms, 5), "launches": pc["launches"],
                 "kernel_ms_per_step": round(kernel_ms_step, 3),
