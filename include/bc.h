@@ -193,7 +193,8 @@ bc_status bc_run_async(bc_graph_t g, const int32_t *sources, int32_t k, double *
  * graph's setting, as for bc_run_async with NULL options), so results agree
  * with bc_run_async up to the rounding of a different grouping of sources.
  * The workspace needs about 1,050 bytes per vertex plus 8 bytes per vertex and
- * level (64 MiB hold graphs of about 55,000 vertices at 16 levels).  The call
+ * level, plus 512 bytes per chunk item of the graph's work items (64 MiB hold
+ * graphs of about 55,000 vertices of low degree at 16 levels).  The call
  * waits on `stream` like bc_run_async and has finished its work on return.
  * Calls that overlap on one device share the array and race: the caller
  * serialises them.  Errors: as bc_run_async; BC_ERR_TOO_LARGE, before any
@@ -325,7 +326,8 @@ bc_status bc_profile_read(bc_graph_t g, bc_profile *out, int32_t reset);
  * first min(k, 128) of `sources`, the sparse_div values at width 64 (on up to
  * 64 of them), then on the same batch the degree thresholds of the batched
  * path's work items (the cut above which a vertex is split into chunk items:
- * 64, 32, 128; the chunk size: 512, 256, 1024 arcs), then widths 64, 32 and
+ * the graph's current one, then 4, 8, 16, 32, 64, 128; the chunk size: the
+ * current one, then 64, 128, 256, 512, 1024 arcs), then widths 64, 32 and
  * 128 on the whole sample, and the
  * one-source-at-a-time path on up to 4 sources; stores the fastest batched
  * settings in the graph, together with the source count from which
@@ -368,7 +370,11 @@ bc_status bc_autotune(bc_graph_t g, const int32_t *sources, int32_t k, void *str
  * ones bc_autotune chooses): vertices of degree above group_cut (for a
  * directed graph, of larger in- or out-degree above it) are split into chunk
  * items of `chunk` arcs, one wavefront each, the others are taken 64 to a
- * group item with their arcs flattened into runs of 64.  Defaults 64 and 512.
+ * group item with their arcs flattened into runs of 64.  Defaults 64 and 512,
+ * or 8 and 128 for a graph of fewer than 8192 groups of 64 vertices (fewer
+ * than 524,225 vertices), which has too few group items to fill the device.
+ * The host-driven level loop uses them; the device-resident loop (one
+ * workgroup per batch) always works on 64 and 512.
  *   group_cut  >= 1
  *   chunk      a multiple of 64 in [64, 4096], >= group_cut
  * Frees the graph's idle pooled batched workspaces (their partial rows follow

@@ -24,8 +24,15 @@ bool use_batched(const bc_graph_s *g, const bc_options *opt, int32_t k) {
     return k >= g->tuned_min_batched.load();
 }
 
-int32_t batch_width_of(const bc_graph_s *g, const bc_options *opt) {
-    return (opt && opt->batch_width > 0) ? opt->batch_width : g->tuned_width.load();
+int32_t batch_width_of(const bc_graph_s *g, const bc_options *opt, int32_t k) {
+    if (opt && opt->batch_width > 0) return opt->batch_width;
+    const int32_t w = g->tuned_width.load();
+    // a tuned width above 64 was timed on a sample that runs on the host
+    // loop; where 64-wide batches of the whole run take the device-resident
+    // loop (one lane word per vertex), those are the faster choice
+    const int32_t loop = opt ? opt->level_loop : BC_LOOP_AUTO;
+    if (w > kWave && k > 0 && use_fused(g, loop, (k + kWave - 1) / kWave, kWave)) return kWave;
+    return w;
 }
 
 int32_t sparse_div_of(const bc_graph_s *g, const bc_options *opt) {
@@ -86,7 +93,7 @@ bc_status bc_run_async(bc_graph_t g, const int32_t *sources, int32_t k, double *
         if (st != BC_ERR_RANGE) return st;
         plain_overflowed(g);
     }
-    return batched_run(g, sources, k, bc_out_dev, batch_width_of(g, opt), sparse_div_of(g, opt),
+    return batched_run(g, sources, k, bc_out_dev, batch_width_of(g, opt, k), sparse_div_of(g, opt),
                        opt ? opt->concurrency : 0, opt ? opt->level_loop : 0,
                        (hipStream_t)stream, nullptr, nullptr);
 }
@@ -105,7 +112,7 @@ bc_status bc_run(bc_graph_t g, const int32_t *sources, int32_t k, double *bc_out
         if (st == BC_ERR_RANGE) plain_overflowed(g);
     }
     if (st == BC_ERR_RANGE)
-        st = batched_run(g, sources, k, d_bc, batch_width_of(g, nullptr), sparse_div_of(g, nullptr),
+        st = batched_run(g, sources, k, d_bc, batch_width_of(g, nullptr, k), sparse_div_of(g, nullptr),
                          0, 0, nullptr, nullptr, nullptr);
     if (st == BC_OK || st == BC_ERR_RANGE) {
         hipError_t e = hipMemcpy(bc_out, d_bc, (size_t)g->n * sizeof(double),
@@ -158,7 +165,7 @@ bc_status bc_run_detail(bc_graph_t g, const int32_t *sources, int32_t k, const b
         if (st == BC_ERR_RANGE) plain_overflowed(g);
     }
     if (st == BC_ERR_RANGE)
-        st = batched_run(g, sources, k, d_bc, batch_width_of(g, opt), sparse_div_of(g, opt),
+        st = batched_run(g, sources, k, d_bc, batch_width_of(g, opt, k), sparse_div_of(g, opt),
                          opt ? opt->concurrency : 0, opt ? opt->level_loop : 0, nullptr, d_dist,
                          d_sigma);
     if (st == BC_OK || st == BC_ERR_RANGE) {
@@ -237,7 +244,7 @@ bc_status bc_workspace_bytes(bc_graph_t g, int32_t k, const bc_options *opt, siz
         *bytes = plain_ws_bytes(g);
         return BC_OK;
     }
-    const int32_t width = batch_width_of(g, opt);
+    const int32_t width = batch_width_of(g, opt, k);
     const int32_t nb = (k + width - 1) / width;
     const int32_t H = width > kWave ? 2 : 1;
     const int32_t lcap = std::max(16, g->batch_depth_hint.load() + 8);

@@ -92,6 +92,17 @@ struct PlainDev {
 // a directed graph the degree is the larger of the in- and out-degree, and a
 // vertex below big_end has at least one item in either direction.
 constexpr int kChunk = 512;
+// Host-loop work items of graphs with fewer than kFineGroups groups of 64
+// vertices: a cut of kFineCut arcs and chunks of kFineChunk.  Such a graph has
+// too few group items to fill the device (one wave each), and a dense group's
+// arcs make a long chain of dependent gathers in its one wave; vertices of
+// more than kFineCut arcs as chunk items spread the arcs over more waves.
+// Measured on R-MAT (edge factor 16, 64 sources, host loop): scale 12 2.18 ->
+// 0.74 ms, 14 2.14 -> 0.92, 16 2.52 -> 1.05, 18 3.52 -> 1.90; at scale 20
+// (16K groups) the 64 / 512 items stay faster (6.1 against 7.6 ms).
+constexpr int kFineCut = 8;
+constexpr int kFineChunk = 128;
+constexpr int kFineGroups = 8192;
 // Default threshold of the batched forward step: a level whose frontier has
 // fewer than nnz / kDefaultSparseDiv arcs expands from the frontier.
 constexpr int kDefaultSparseDiv = 64;

@@ -76,6 +76,7 @@ bool layout_of(const bc_graph_s *g, Layout &L) {
     L.coef = take(n * kWave * sizeof(double));
     L.ctrl = take(kBatchCtrlInts * sizeof(int32_t));
     L.bc = take(n * sizeof(double));
+    // the host-driven loop's work items, as in bc_run_async
     L.reach = take((size_t)std::max(g->bci.multi_end, 1) * sizeof(uint64_t));
     L.partial = take(partial_rows(g) * kWave * sizeof(double));
     L.clist = take(n * sizeof(int32_t));
@@ -154,7 +155,7 @@ extern "C" bc_status bc_run_async_noalloc(bc_graph_t g, const int32_t *sources, 
     int32_t h_ctrl[kBatchCtrlInts] = {};
     int32_t lanes[kWave];
     LaunchTimer timer;  // off: no events
-    const int32_t width = std::min(batch_width_of(g, nullptr), (int32_t)kWave);
+    const int32_t width = std::min(batch_width_of(g, nullptr, k), (int32_t)kWave);
     int32_t range = 0, run_depth = 0;
     for (int32_t b0 = 0; b0 < k;) {
         const int32_t nl = std::min(width, k - b0);

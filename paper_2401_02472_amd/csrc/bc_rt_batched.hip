@@ -7,13 +7,14 @@ namespace bcx {
 
 // Chunk items with a partial row: both passes' items (the forward pass runs
 // over the arcs into each vertex, the reverse pass over the arcs out of it).
-size_t partial_rows(const bc_graph_s *g) {
-    return (size_t)std::max<uint32_t>(std::max(g->bci.items, g->bci.items_in), 1);
+size_t partial_rows(const bc_graph_s::BcItems &t) {
+    return (size_t)std::max<uint32_t>(std::max(t.items, t.items_in), 1);
 }
 
-// The batched path's work items of a workspace: the graph's current tables.
-void set_items(const bc_graph_s *g, BatchDev &d) {
-    const auto &t = g->bci;
+size_t partial_rows(const bc_graph_s *g) { return partial_rows(g->bci); }
+
+// The batched path's work items of a workspace: tables t.
+void set_items(const bc_graph_s::BcItems &t, BatchDev &d) {
     d.big_end = t.big_end;
     d.multi_end = t.multi_end;
     d.chunk = t.chunk;
@@ -24,6 +25,9 @@ void set_items(const bc_graph_s *g, BatchDev &d) {
     d.item_info_in = t.info_in;
     d.item_first_in = t.first_in;
 }
+
+// ... the graph's current tables (the host-driven loop's).
+void set_items(const bc_graph_s *g, BatchDev &d) { set_items(g->bci, d); }
 
 size_t batch_ws_bytes(const bc_graph_s *g, int32_t H) {
     const size_t n = (size_t)std::max<int32_t>(g->n, 1);
@@ -409,9 +413,10 @@ bc_status run_batch_plan(bc_graph_s *g, const std::vector<int32_t> &s_int,
 // split-vertex rows, partial rows, the level array).
 size_t fused_batch_bytes(const bc_graph_s *g, int32_t lcap) {
     const size_t n = (size_t)std::max<int32_t>(g->n, 1);
-    const size_t multi = (size_t)std::max(g->bci.multi_end, 1);
+    const bc_graph_s::BcItems t = base_items(g);
+    const size_t multi = (size_t)std::max(t.multi_end, 1);
     return align_up(n * sizeof(uint64_t)) + 2 * align_up(n * kWave * sizeof(double)) +
-           align_up(multi * sizeof(uint64_t)) + align_up(partial_rows(g) * kWave * sizeof(double)) +
+           align_up(multi * sizeof(uint64_t)) + align_up(partial_rows(t) * kWave * sizeof(double)) +
            align_up((size_t)lcap * n * sizeof(uint64_t));
 }
 
@@ -457,7 +462,7 @@ int32_t fused_cap(const bc_graph_s *g, int32_t nbatches, int32_t lcap) {
 // existing pool at least that large is kept.
 bc_status fused_reserve(bc_graph_s *g, int32_t cap, int32_t lcap) {
     auto &f = g->fused;
-    if (f.block && f.cap >= cap && f.lcap >= lcap && f.gen == g->bci_gen.load()) return BC_OK;
+    if (f.block && f.cap >= cap && f.lcap >= lcap) return BC_OK;
     fused_release_pool(g);
     const size_t n = (size_t)std::max<int32_t>(g->n, 1);
     const size_t per = fused_batch_bytes(g, lcap);
@@ -476,7 +481,7 @@ bc_status fused_reserve(bc_graph_s *g, int32_t cap, int32_t lcap) {
     }
     f.cap = cap;
     f.lcap = lcap;
-    f.gen = g->bci_gen.load();
+    const bc_graph_s::BcItems items = base_items(g);
     char *p = (char *)f.block;
     auto take = [&](size_t bytes) {
         char *r = p;
@@ -492,7 +497,7 @@ bc_status fused_reserve(bc_graph_s *g, int32_t cap, int32_t lcap) {
         d.H = 1;
         d.row_ptr = g->d_row_ptr;
         d.col_idx = g->d_col_idx;
-        set_items(g, d);
+        set_items(items, d);
         d.row_ptr_in = g->d_row_ptr_in;
         d.col_idx_in = g->d_col_idx_in;
         d.iperm = g->d_iperm;
@@ -504,8 +509,8 @@ bc_status fused_reserve(bc_graph_s *g, int32_t cap, int32_t lcap) {
         d.sigma = (double *)take(n * kWave * sizeof(double));
         d.sigma32 = reinterpret_cast<uint32_t *>(d.sigma);
         d.coef = (double *)take(n * kWave * sizeof(double));
-        d.reach = (uint64_t *)take((size_t)std::max(g->bci.multi_end, 1) * sizeof(uint64_t));
-        d.partial = (double *)take(partial_rows(g) * kWave * sizeof(double));
+        d.reach = (uint64_t *)take((size_t)std::max(items.multi_end, 1) * sizeof(uint64_t));
+        d.partial = (double *)take(partial_rows(items) * kWave * sizeof(double));
         d.F = (uint64_t *)take((size_t)lcap * n * sizeof(uint64_t));
     }
     return BC_OK;

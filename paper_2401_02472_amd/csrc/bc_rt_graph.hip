@@ -46,15 +46,8 @@ bc_status validate_csr(int32_t n, const int32_t *row_ptr, const int32_t *col_idx
 // The graph's device arrays (the reversed CSR and its items only when they
 // are arrays of their own, i.e. for a directed graph).
 // The BC tables back to the default ones (freeing owned arrays).
-void reset_bc_items(bc_graph_s *g) {
-    auto &t = g->bci;
-    if (t.owned) {
-        (void)hipFree(t.info);
-        (void)hipFree(t.first);
-        if (t.info_in != t.info) (void)hipFree(t.info_in);
-        if (t.first_in != t.first) (void)hipFree(t.first_in);
-    }
-    t = bc_graph_s::BcItems{};
+bc_graph_s::BcItems base_items(const bc_graph_s *g) {
+    bc_graph_s::BcItems t{};
     t.big_end = g->big_end;
     t.multi_end = g->multi_end;
     t.items = g->items;
@@ -63,6 +56,18 @@ void reset_bc_items(bc_graph_s *g) {
     t.first = g->d_item_first;
     t.info_in = g->d_item_info_in;
     t.first_in = g->d_item_first_in;
+    return t;
+}
+
+void reset_bc_items(bc_graph_s *g) {
+    auto &t = g->bci;
+    if (t.owned) {
+        (void)hipFree(t.info);
+        (void)hipFree(t.first);
+        if (t.info_in != t.info) (void)hipFree(t.info_in);
+        if (t.first_in != t.first) (void)hipFree(t.first_in);
+    }
+    t = base_items(g);
 }
 
 void free_graph_arrays(bc_graph_s *g) {
@@ -391,6 +396,15 @@ bc_status bc_create_graph(int32_t n, const int32_t *row_ptr, const int32_t *col_
     }
     g->device_bytes = (directed ? 2 : 1) * (rp_bytes + ci_bytes) + 2 * pm_bytes;
     reset_bc_items(g);
+    // a graph of few 64-vertex groups takes finer host-loop work items
+    if (n > 0 && (n + kWave - 1) / kWave < kFineGroups) {
+        const bc_status st = set_bc_items(g, kFineCut, kFineChunk);
+        if (st != BC_OK) {
+            free_graph_arrays(g);
+            delete g;
+            return st;
+        }
+    }
     *out = g;
     return BC_OK;
 }

@@ -188,8 +188,10 @@ struct bc_graph_s {
     // The batched BC path's work items: vertices of degree above `cut` (a
     // prefix of the internal order) in chunks of `chunk` arcs, the ones above
     // `chunk` spanning several items.  They start as the tables above (cut 64,
-    // chunk 512), which SSSP and PageRank keep; bc_autotune may rebuild them
-    // with other thresholds (owned: separate device arrays).
+    // chunk 512), which SSSP, PageRank and the device-resident loop keep; a
+    // small graph then takes finer ones (kFineCut, kFineChunk), and
+    // bc_autotune or bc_set_work_items may rebuild them with other thresholds
+    // (owned: separate device arrays).
     struct BcItems {
         int32_t cut = 64, chunk = 512;
         int32_t big_end = 0, multi_end = 0;
@@ -247,7 +249,6 @@ struct bc_graph_s {
         void *block = nullptr;
         size_t bytes = 0;
         int32_t cap = 0, lcap = 0;
-        int32_t gen = 0;            // the work-item tables the pool was built for
         BatchDev *d_devs = nullptr;
         int32_t *h_ctrl = nullptr;  // pinned [cap][kCtlInts]
         int32_t *d_ctrl = nullptr;  // [cap][kCtlInts]
@@ -287,7 +288,9 @@ bc_status plain_run(bc_graph_s *g, const int32_t *sources, int32_t k, double *bc
 bc_status bfs_levels(bc_graph_s *g, int32_t s, std::vector<int32_t> &out);
 
 // ---- batched runtime (bc_rt_batched.hip) ----
-size_t partial_rows(const bc_graph_s *g);
+size_t partial_rows(const bc_graph_s::BcItems &t);
+size_t partial_rows(const bc_graph_s *g);  // of the graph's current tables
+void set_items(const bc_graph_s::BcItems &t, BatchDev &d);
 void set_items(const bc_graph_s *g, BatchDev &d);
 size_t batch_ws_bytes(const bc_graph_s *g, int32_t H);
 size_t batch_level_bytes(const bc_graph_s *g, int32_t lcap, int32_t H);
@@ -321,11 +324,14 @@ void free_graph_arrays(bc_graph_s *g);
 // pooled batched workspace (their partial rows follow the item count).  No run
 // on g may be in flight.
 bc_status set_bc_items(bc_graph_s *g, int32_t cut, int32_t chunk);
+// The tables built at creation (cut 64, chunk 512): the device-resident loop
+// always runs on them (its 16 waves per batch gain nothing from finer items).
+bc_graph_s::BcItems base_items(const bc_graph_s *g);
 
 // ---- policy and argument checks (bc_capi.hip) ----
 void plain_overflowed(bc_graph_s *g);
 bool use_batched(const bc_graph_s *g, const bc_options *opt, int32_t k);
-int32_t batch_width_of(const bc_graph_s *g, const bc_options *opt);
+int32_t batch_width_of(const bc_graph_s *g, const bc_options *opt, int32_t k);
 int32_t sparse_div_of(const bc_graph_s *g, const bc_options *opt);
 bc_status check_options(const bc_options *opt);
 bc_status check_sources(const bc_graph_s *g, const int32_t *sources, int32_t k);

@@ -242,23 +242,27 @@ bc_status bc_autotune(bc_graph_t g, const int32_t *sources, int32_t k, void *str
     // degree thresholds of the work items: the cut above which a vertex is
     // split into chunk items (the rest go 64 to a group item), then the
     // chunk size, each on the same batch
-    int32_t best_cut = kB1MaxDeg, best_chunk = kChunk;
+    // (the graph's current thresholds were timed above; small graphs start
+    // from the finer ones)
+    int32_t best_cut = prev_cut, best_chunk = prev_chunk;
     auto items_ms = [&](int32_t cut, int32_t chunk, double &ms) {
         bc_status s2 = set_bc_items(g, cut, chunk);
         if (s2 == BC_OK) s2 = batched(m64, kWave, best_div, ms);
         return s2;
     };
-    for (int32_t cut : {32, 128}) {
+    for (int32_t cut : {4, 8, 16, 32, 64, 128}) {
         if (st != BC_OK) break;
+        if (cut == prev_cut || cut > best_chunk) continue;
         double ms = 0;
-        st = items_ms(cut, kChunk, ms);
+        st = items_ms(cut, best_chunk, ms);
         if (st == BC_OK && ms < div_ms * kTuneMargin) {
             div_ms = ms;
             best_cut = cut;
         }
     }
-    for (int32_t chunk : {256, 1024}) {
+    for (int32_t chunk : {64, 128, 256, 512, 1024}) {
         if (st != BC_OK) break;
+        if (chunk == prev_chunk || chunk < best_cut) continue;
         double ms = 0;
         st = items_ms(best_cut, chunk, ms);
         if (st == BC_OK && ms < div_ms * kTuneMargin) {

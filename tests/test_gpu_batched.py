@@ -266,7 +266,8 @@ def test_autotune_then_auto_mode():
         assert t["sparse_div"] in (-1, 16, 64, 256)
         assert t["min_batched"] >= 2
         assert t["sample"] == 100 and not t["cached"]
-        assert t["group_cut"] in (32, 64, 128) and t["chunk"] in (256, 512, 1024)
+        assert t["group_cut"] in (4, 8, 16, 32, 64, 128)
+        assert t["chunk"] in (64, 128, 256, 512, 1024) and t["chunk"] >= t["group_cut"]
         assert t["plain_ms_per_source"] > 0 and t["batch_ms"] > 0
         for k in (3, 100):
             want = oracle_bc(g, src[:k])
@@ -694,3 +695,26 @@ def test_set_work_items_explicit():
             assert ei.value.status == bcm.BC_ERR_INVALID_ARG
         check_bc(batched(G, src, level_loop=bcm.BC_LOOP_HOST), want)
         check_bc(batched(G, src, level_loop=bcm.BC_LOOP_DEVICE), want)
+
+
+@pytest.mark.parametrize("g", [gg.rmat(13, 16, seed=93), gg.erdos_renyi(6000, 16, seed=94),
+                               gg.star(700)], ids=lambda g: g.name)
+def test_small_graph_default_items_both_loops(g):
+    """A small graph's host loop runs on the finer default work items (cut 8,
+    chunks of 128 arcs: hubs split into many chunks), the device-resident loop
+    on the creation-time ones (64 / 512): both give the oracle's BC, each
+    repeats bit for bit, and so do the 64 / 512 items on the host loop."""
+    src = gg.sample_sources(g, 100, seed=95)
+    want = oracle_bc(g, src)
+    with bcm.Graph(g.n, g.row_ptr, g.col_idx) as G:
+        host = batched(G, src, level_loop=bcm.BC_LOOP_HOST)
+        check_bc(host, want)
+        assert np.array_equal(host, batched(G, src, level_loop=bcm.BC_LOOP_HOST))
+        dev = batched(G, src, level_loop=bcm.BC_LOOP_DEVICE)
+        check_bc(dev, want)
+        assert np.array_equal(dev, batched(G, src, level_loop=bcm.BC_LOOP_DEVICE))
+        G.set_work_items(64, 512)
+        coarse = batched(G, src, level_loop=bcm.BC_LOOP_HOST)
+        check_bc(coarse, want)
+        # the device loop does not depend on the host loop's items
+        assert np.array_equal(dev, batched(G, src, level_loop=bcm.BC_LOOP_DEVICE))
