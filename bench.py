@@ -487,6 +487,9 @@ def main() -> int:
                          "(0 = skip) and report the ratio")
     ap.add_argument("--concurrency", type=int, default=0,
                     help="batches run at once (0 = the library's choice)")
+    ap.add_argument("--level-loop", choices=("auto", "host", "device", "graph"), default="auto",
+                    help="who drives the batched level loop (graph: the host loop with its "
+                         "level chunks replayed as captured HIP graphs)")
     ap.add_argument("--no-end-to-end", action="store_true",
                     help="skip the run with host transfers")
     ap.add_argument("--no-autotune", action="store_true",
@@ -540,8 +543,10 @@ def main() -> int:
     k = int(len(sources))
     mode = {"auto": bcm.BC_MODE_AUTO, "plain": bcm.BC_MODE_PLAIN,
             "batched": bcm.BC_MODE_BATCHED}[args.mode]
+    loop = {"auto": bcm.BC_LOOP_AUTO, "host": bcm.BC_LOOP_HOST, "device": bcm.BC_LOOP_DEVICE,
+            "graph": bcm.BC_LOOP_GRAPH}[args.level_loop]
     opt = bcm.make_options(mode, args.batch_width, sparse_div=args.sparse_div,
-                           concurrency=args.concurrency)
+                           concurrency=args.concurrency, level_loop=loop)
 
     gflags = (bcm.BC_GRAPH_DIRECTED if g.params.get("directed")
               else bcm.BC_GRAPH_TRUST_SYMMETRIC)
@@ -675,7 +680,8 @@ def main() -> int:
     # the other parts' kernels running beside it, so it is not the kernel's own.
     one_part = path == "batched" and args.concurrency != 1
     if one_part:
-        opt1 = bcm.make_options(mode, args.batch_width, sparse_div=args.sparse_div, concurrency=1)
+        opt1 = bcm.make_options(mode, args.batch_width, sparse_div=args.sparse_div, concurrency=1,
+                                level_loop=loop)
         roof_prof, roof_ms, roof_steps = measured(opt1)
     else:
         roof_prof, roof_ms, roof_steps = prof, meas_ms, meas_steps
@@ -733,7 +739,7 @@ def main() -> int:
                    "sparse_div": args.sparse_div or (tuning["sparse_div"] if tuning else 64),
                    "group_cut": args.group_cut or (tuning["group_cut"] if tuning else 64),
                    "chunk": args.chunk or (tuning["chunk"] if tuning else 512),
-                   "concurrency": args.concurrency,
+                   "concurrency": args.concurrency, "level_loop": args.level_loop,
                    "autotune": tuning, "graph": g.params},
         "plain_comparison": plain_cmp,
         "profile_level_stride": stride,

@@ -122,11 +122,17 @@ typedef struct bc_options {
  * or many batches.  AUTO picks the loop with the lower estimated time for the
  * call's batch count (a batch on one compute unit against a batch across the
  * device; e.g. DEVICE from about 6 batches at 53K arcs, 27 at 425K, 87 at
- * 1.8M).  A graph in extended range always takes HOST. */
+ * 1.8M).  A graph in extended range always takes HOST (or GRAPH).  GRAPH:
+ * the HOST loop with each chunk of level steps (the levels between two depth
+ * polls, forward and reverse) captured once per workspace as a HIP graph and
+ * replayed for every batch (the kernels read the chunk's base level from the
+ * device), so a chunk costs one launch on the host; results are bit-identical
+ * to HOST.  Runs measured with bc_profile_enable launch every step. */
 enum {
     BC_LOOP_AUTO = 0,
     BC_LOOP_HOST = 1,
-    BC_LOOP_DEVICE = 2
+    BC_LOOP_DEVICE = 2,
+    BC_LOOP_GRAPH = 3
 };
 
 /*

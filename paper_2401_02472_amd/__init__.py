@@ -19,7 +19,7 @@ from ._capi import (BC_ERR_DEVICE, BC_ERR_INVALID_ARG, BC_ERR_INVALID_GRAPH,  # 
                     BC_GRAPH_DIRECTED, BC_GRAPH_INPUT_ON_DEVICE, BC_GRAPH_TRUST_SYMMETRIC,
                     BC_MODE_AUTO,
                     BC_MODE_BATCHED, BC_MODE_PLAIN, BC_OK, bc_options,
-                    BC_LOOP_AUTO, BC_LOOP_HOST, BC_LOOP_DEVICE)
+                    BC_LOOP_AUTO, BC_LOOP_HOST, BC_LOOP_DEVICE, BC_LOOP_GRAPH)
 
 __all__ = [
     "BCError", "bc_create_graph", "bc_destroy_graph", "bc_graph_info", "bc_run", "bc_run_async",

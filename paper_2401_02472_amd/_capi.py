@@ -44,6 +44,7 @@ EXPORTED = ("bc_create_graph", "bc_destroy_graph", "bc_graph_info", "bc_run", "b
 BC_LOOP_AUTO = 0
 BC_LOOP_HOST = 1
 BC_LOOP_DEVICE = 2
+BC_LOOP_GRAPH = 3
 
 BC_PROF_FORWARD = 0
 BC_PROF_COMPACT = 1

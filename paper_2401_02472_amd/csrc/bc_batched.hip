@@ -315,6 +315,12 @@ __device__ __forceinline__ uint64_t half_full(int32_t nlanes, int h) {
     return k >= kWave ? ~0ull : (k <= 0 ? 0ull : ((1ull << k) - 1ull));
 }
 
+// The level a kernel argument names (dir +1 forward, -1 reverse; see
+// kRelLevel).
+__device__ __forceinline__ int32_t level_arg(const BatchDev &d, int32_t L, int32_t dir) {
+    return L < kRelLevel ? L : d.ctrl[kCtlLevel] + dir * (L - kRelLevel);
+}
+
 // ---- forward ---------------------------------------------------------------
 
 // Size of the next frontier (vertices and arcs), counted per lane and stored
@@ -619,6 +625,7 @@ fwd_group(const BatchDev &d, int32_t L, int32_t base, const int32_t *list, int32
 
 template <bool N, int H>
 __global__ __launch_bounds__(kBlock, kLevelWaves) void k_batch_forward(BatchDev d, int32_t L, int32_t nlanes) {
+    L = level_arg(d, L, 1);
     // nothing past the deepest level found so far (F_L is empty), no room, or
     // this level takes the sparse step
     if (L > d.ctrl[kCtlDeepest] || L + 1 >= d.lcap || d.ctrl[kCtlMode]) return;
@@ -681,6 +688,7 @@ __device__ __forceinline__ void finish_split(const BatchDev &d, int32_t L, int32
 
 template <bool N, int H>
 __global__ __launch_bounds__(kBlock) void k_batch_forward_finish(BatchDev d, int32_t L) {
+    L = level_arg(d, L, 1);
     if (L > d.ctrl[kCtlDeepest] || L + 1 >= d.lcap) return;
     Front fr[H];
     auto step = [&](int h, Front &f) __attribute__((always_inline)) {
@@ -705,6 +713,7 @@ __global__ __launch_bounds__(kDoneBlock) void k_batch_level_done(BatchDev d, int
                                                                  int32_t w0, int32_t w1,
                                                                  int32_t w2) {
     __shared__ unsigned long long sc[kDoneBlock], sa[kDoneBlock];
+    L = level_arg(d, L, 1);
     const int t = threadIdx.x;
     const bool live = !(L > d.ctrl[kCtlDeepest] || L + 1 >= d.lcap);
     const int mode = d.ctrl[kCtlMode];
@@ -759,6 +768,7 @@ __global__ __launch_bounds__(kDoneBlock) void k_batch_level_done(BatchDev d, int
 // per vertex.  Marks are idempotent byte stores.
 template <int H>
 __global__ __launch_bounds__(kBlock) void k_batch_sparse_mark(BatchDev d, int32_t L) {
+    L = level_arg(d, L, 1);
     if (L > d.ctrl[kCtlDeepest] || L + 1 >= d.lcap || !d.ctrl[kCtlMode]) return;
     const int lane = lane_id();
     const uint64_t *FL = d.F + (size_t)L * (size_t)d.n * H;
@@ -802,6 +812,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_sparse_mark(BatchDev d, int32_
 template <int H>
 __global__ __launch_bounds__(kBlock) void k_batch_sparse_compact(BatchDev d, int32_t L,
                                                                  int32_t nlanes) {
+    L = level_arg(d, L, 1);
     if (L > d.ctrl[kCtlDeepest] || L + 1 >= d.lcap || !d.ctrl[kCtlMode]) return;
     // list space is taken once per block (the waves' counts added in LDS):
     // one atomic per block and list instead of one per wave
@@ -912,6 +923,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_sparse_compact(BatchDev d, int
 template <bool N, int H>
 __global__ __launch_bounds__(kBlock, kLevelWaves) void k_batch_sparse_pull(BatchDev d, int32_t L,
                                                               int32_t nlanes) {
+    L = level_arg(d, L, 1);
     if (L > d.ctrl[kCtlDeepest] || L + 1 >= d.lcap || !d.ctrl[kCtlMode]) return;
     const int32_t c = d.ctrl[kCtlCand];
     const int32_t ni = d.ctrl[kCtlItems];
@@ -1224,6 +1236,9 @@ __device__ __forceinline__ void bwd_group(const BatchDev &d, int32_t L, int32_t 
 
 template <bool N, int H>
 __global__ __launch_bounds__(kBlock, kLevelWaves) void k_batch_reverse(BatchDev d, int32_t L) {
+    // levels 1 .. deepest-1 have children (a replayed chunk passes others)
+    L = level_arg(d, L, -1);
+    if (L < 1 || L >= d.ctrl[kCtlDeepest]) return;
     const uint32_t items = d.items;
     const uint32_t groups = (uint32_t)((d.n - d.big_end + kWave - 1) / kWave);
     const uint32_t wave = (blockIdx.x * kBlock + threadIdx.x) / kWave;
@@ -1339,6 +1354,11 @@ finalize_level(const BatchDev &d, int32_t L, int32_t leaf, int32_t wave, int32_t
 
 template <bool N, int H>
 __global__ __launch_bounds__(kBlock) void k_batch_finalize(BatchDev d, int32_t L, int32_t leaf) {
+    if (leaf < 0) {  // relative level: levels 1 .. deepest, the deepest a leaf
+        L = level_arg(d, L, -1);
+        if (L < 1 || L > d.ctrl[kCtlDeepest]) return;
+        leaf = L == d.ctrl[kCtlDeepest] ? 1 : 0;
+    }
     const int32_t wave = (blockIdx.x * kBlock + threadIdx.x) / kWave;
     finalize_level<N, H>(half_view<H>(d, 0), L, leaf, wave, gridDim.x * kWavesPerBlock);
     if (H > 1)
@@ -1610,6 +1630,29 @@ hipError_t batch_finalize(const BatchDev &d, int32_t level, bool deepest, hipStr
     if (waves == 0) return hipSuccess;
     hipLaunchKernelGGL(BC_PICK(k_batch_finalize, d), dim3(grid_of(waves)), dim3(kBlock), 0, stream,
                        d, level, deepest ? 1 : 0);
+    return hipGetLastError();
+}
+
+__global__ void k_level_advance(int32_t *ctrl, int32_t delta) { ctrl[kCtlLevel] += delta; }
+
+__global__ void k_level_from_deepest(int32_t *ctrl) { ctrl[kCtlLevel] = ctrl[kCtlDeepest]; }
+
+hipError_t batch_finalize_rel(const BatchDev &d, int32_t level_rel, hipStream_t stream) {
+    // grid for the deepest level (every vertex); other levels use its first
+    // multi_end waves
+    const int64_t waves = std::max<int64_t>((d.n + kWave - 1) / kWave, d.multi_end);
+    hipLaunchKernelGGL(BC_PICK(k_batch_finalize, d), dim3(grid_of(waves)), dim3(kBlock), 0, stream,
+                       d, level_rel, -1);
+    return hipGetLastError();
+}
+
+hipError_t batch_level_advance(const BatchDev &d, int32_t delta, hipStream_t stream) {
+    hipLaunchKernelGGL(k_level_advance, dim3(1), dim3(1), 0, stream, d.ctrl, delta);
+    return hipGetLastError();
+}
+
+hipError_t batch_level_from_deepest(const BatchDev &d, hipStream_t stream) {
+    hipLaunchKernelGGL(k_level_from_deepest, dim3(1), dim3(1), 0, stream, d.ctrl);
     return hipGetLastError();
 }
 

@@ -46,7 +46,7 @@ bc_status check_options(const bc_options *opt) {
     if (opt->level_chunk < 0 || opt->level_chunk > 1024) return BC_ERR_INVALID_ARG;
     if (opt->sparse_div < -1 || opt->sparse_div > (1 << 20)) return BC_ERR_INVALID_ARG;
     if (opt->concurrency < 0 || opt->concurrency > kMaxParts) return BC_ERR_INVALID_ARG;
-    if (opt->level_loop < BC_LOOP_AUTO || opt->level_loop > BC_LOOP_DEVICE)
+    if (opt->level_loop < BC_LOOP_AUTO || opt->level_loop > BC_LOOP_GRAPH)
         return BC_ERR_INVALID_ARG;
     for (int i = 0; i < 2; ++i)
         if (opt->reserved[i] != 0) return BC_ERR_INVALID_ARG;

@@ -179,8 +179,15 @@ enum {
     kCtlCand = 4,      // candidates listed by the sparse step
     kCtlItems = 5,     // chunk items listed by the sparse step
     kCtlNarrow = 6,    // a path count does not fit the uint32 sigma rows
+    kCtlLevel = 7,     // base level of a replayed chunk of level steps
     kCtlInts = 8
 };
+
+// A level argument of kRelLevel + i is relative: a chunk of level steps
+// captured once (a HIP graph) and replayed for any base level reads the base
+// from ctrl[kCtlLevel]; step i of a forward chunk runs level base + i, of a
+// reverse chunk level base - i.  Smaller arguments are the level itself.
+constexpr int32_t kRelLevel = 1 << 30;
 
 // Per-wave frontier counts of one forward iteration: set 0 the scan-all step,
 // set 1 the sparse step, set 2 the completion of split vertices; each wave of
@@ -216,6 +223,13 @@ hipError_t batch_forward_done(const BatchDev &d, int32_t level, hipStream_t stre
 // level), then batch_finalize (delta, c, BC).
 hipError_t batch_reverse(const BatchDev &d, int32_t level, hipStream_t stream);
 hipError_t batch_finalize(const BatchDev &d, int32_t level, bool deepest, hipStream_t stream);
+// Replayed chunks: batch_finalize for a relative level (the kernel finds on
+// the device whether it is the deepest one, or no level at all); the chunk's
+// base moved by `delta` levels; the reverse pass's base set to the deepest
+// level found.
+hipError_t batch_finalize_rel(const BatchDev &d, int32_t level_rel, hipStream_t stream);
+hipError_t batch_level_advance(const BatchDev &d, int32_t delta, hipStream_t stream);
+hipError_t batch_level_from_deepest(const BatchDev &d, hipStream_t stream);
 // dist [nlanes][n] (int32) and sigma [nlanes][n] of the batch, internal order.
 // Every batch of a call in one launch, one workgroup per batch (graphs small
 // enough for one compute unit per batch); devs_dev[b] is batch b's workspace,

@@ -186,14 +186,82 @@ bc_status ensure_landmarks(bc_graph_s *g) {
     return BC_OK;
 }
 
+constexpr size_t kMaxChunkGraphs = 16;
+
+ChunkGraphs::~ChunkGraphs() {
+    for (Entry &e : entries)
+        if (e.exec) (void)hipGraphExecDestroy(e.exec);
+    if (cap) (void)hipStreamDestroy(cap);
+}
+
+hipError_t ChunkGraphs::replay(const BatchDev &d, int32_t dir, int32_t K, int32_t nlanes,
+                               hipStream_t stream) {
+    Entry *hit = nullptr;
+    for (Entry &en : entries)
+        if (en.dir == dir && en.K == K && en.nlanes == nlanes &&
+            std::memcmp(&en.d, &d, sizeof(BatchDev)) == 0) {
+            hit = &en;
+            break;
+        }
+    if (!hit) {
+        if (!cap) {
+            const hipError_t ec = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+            if (ec != hipSuccess) return ec;
+        }
+        // kernel launches only (no memset nodes): K relative steps, then the
+        // base moved by K levels
+        hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return e;
+        for (int32_t i = 0; i < K && e == hipSuccess; ++i) {
+            const int32_t L = kRelLevel + i;
+            if (dir > 0) {
+                e = batch_forward(d, L, nlanes, cap);
+                if (e == hipSuccess) e = batch_forward_done(d, L, cap);
+            } else {
+                e = batch_reverse(d, L, cap);
+                if (e == hipSuccess) e = batch_finalize_rel(d, L, cap);
+            }
+        }
+        if (e == hipSuccess) e = batch_level_advance(d, dir * K, cap);
+        hipGraph_t graph = nullptr;
+        const hipError_t ee = hipStreamEndCapture(cap, &graph);
+        if (e == hipSuccess) e = ee;
+        hipGraphExec_t exec = nullptr;
+        if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) return e;
+        if (entries.size() >= kMaxChunkGraphs) {
+            // every earlier launch of the workspace's graphs is ordered before
+            // this stream's current work (the workspace is acquired on it)
+            e = hipStreamSynchronize(stream);
+            if (e != hipSuccess) {
+                (void)hipGraphExecDestroy(exec);
+                return e;
+            }
+            (void)hipGraphExecDestroy(entries.front().exec);
+            entries.erase(entries.begin());
+        }
+        Entry en;
+        en.dir = dir;
+        en.K = K;
+        en.nlanes = nlanes;
+        en.d = d;
+        en.exec = exec;
+        entries.push_back(en);
+        hit = &entries.back();
+    }
+    return hipGraphLaunch(hit->exec, stream);
+}
+
 // One batch: clear and seed, the forward levels in chunks with one host poll
 // per chunk, then the reverse levels.  A path count that needs double rows
 // (or the extended range) switches the graph to them and asks for a rerun; a
-// level array too short for the batch asks for a longer one.
+// level array too short for the batch asks for a longer one.  With cg, each
+// chunk of levels is one replayed graph instead of its launches.
 hipError_t drive_batch(bc_graph_s *g, BatchDev &d, const ExtTables &ext, const int32_t *lanes_dev,
                        int32_t nl, int32_t *h_ctrl, hipStream_t stream, LaunchTimer &timer,
                        unsigned long long *d_stats, int32_t stride, BatchOutcome &how,
-                       int32_t &deepest) {
+                       int32_t &deepest, ChunkGraphs *cg) {
     const int32_t n = g->n;
     const bool prof = d_stats != nullptr;
     auto measure = [&](int32_t L) {
@@ -214,7 +282,10 @@ hipError_t drive_batch(bc_graph_s *g, BatchDev &d, const ExtTables &ext, const i
     for (;;) {
         const int32_t K = std::max(2, g->batch_depth_hint.load() + 2);
         const int32_t Lend = std::min(L0 + K, d.lcap - 1);
-        for (int32_t L = L0; L < Lend && e == hipSuccess; ++L) {
+        // (a replayed chunk runs levels L0 .. L0+K-1; those past the level
+        // array's end return at once, as the host loop would not launch them)
+        if (cg) e = cg->replay(d, 1, K, nl, stream);
+        for (int32_t L = L0; !cg && L < Lend && e == hipSuccess; ++L) {
             measure(L);
             e = timer.begin(BC_PROF_FORWARD, stream);
             if (e == hipSuccess) e = batch_forward(d, L, nl, stream);
@@ -246,6 +317,15 @@ hipError_t drive_batch(bc_graph_s *g, BatchDev &d, const ExtTables &ext, const i
         }
         if (deepest < Lend || Lend >= n) break;
         L0 = Lend;
+    }
+    if (cg) {
+        // chunks of K levels from the deepest one down (levels below 1 return
+        // at once); the first chunk's base is the deepest level
+        const int32_t K = std::max(2, g->batch_depth_hint.load() + 2);
+        if (deepest >= 1) e = batch_level_from_deepest(d, stream);
+        for (int32_t done = 0; done < deepest && e == hipSuccess; done += K)
+            e = cg->replay(d, -1, K, 0, stream);
+        return e;
     }
     for (int32_t L = deepest; L >= 1 && e == hipSuccess; --L) {
         measure(L);
@@ -279,7 +359,7 @@ bc_status run_batch_plan(bc_graph_s *g, const std::vector<int32_t> &s_int,
                          const std::vector<int32_t> &seg_start,  // per segment table: nseg+1
                          const std::vector<double *> &seg_out, double *bc_out,
                          hipStream_t stream, const int32_t *export_row, int32_t *dist,
-                         double *sigma, int32_t sparse_div) {
+                         double *sigma, int32_t sparse_div, bool graphs) {
     // two lane words per vertex when a batch has more than 64 sources (never
     // with request segments: their lanes are summed within one 64-lane word)
     int32_t H = 1;
@@ -367,8 +447,10 @@ bc_status run_batch_plan(bc_graph_s *g, const std::vector<int32_t> &s_int,
         BatchOutcome how = BatchOutcome::Done;
         int32_t deepest = 0;
         const ExtTables ext{ws->xs, ws->xmax, ws->xe};
+        // (measured runs launch every step: the events go around each launch)
         e = drive_batch(g, d, ext, d_lanes + bp.first, nl, ws->h_ctrl, stream, ws->timer,
-                        prof ? ws->d_stats : nullptr, stride, how, deepest);
+                        prof ? ws->d_stats : nullptr, stride, how, deepest,
+                        graphs && !prof ? &ws->graphs : nullptr);
         if (e != hipSuccess) return fail(from_hip(e));
         if (how == BatchOutcome::Rerun) continue;
         if (how == BatchOutcome::Grow) {  // level array full: grow it, run the batch again
@@ -679,7 +761,7 @@ bool use_fused(const bc_graph_s *g, int32_t level_loop, int32_t nbatches, int32_
     if (g->sigma_ext.load()) return false;  // extended range: host loop only
     if (width > kWave) return false;        // one lane word per vertex only
     if (level_loop == BC_LOOP_DEVICE) return true;
-    if (level_loop == BC_LOOP_HOST) return false;
+    if (level_loop == BC_LOOP_HOST || level_loop == BC_LOOP_GRAPH) return false;
     const double arcs = (double)g->nnz;
     const double device = 2e-3 + 50e-9 * arcs;
     const double host = 0.8e-3 + 0.15e-9 * arcs;
@@ -747,7 +829,7 @@ bc_status batched_run(bc_graph_s *g, const int32_t *sources, int32_t k, double *
     const int32_t P = parts_of(g, concurrency, (int32_t)plan.size(), width > kWave ? 2 : 1);
     if (P <= 1)
         return run_batch_plan(g, s_int, plan, {}, {}, bc_out, stream, order.data(), dist, sigma,
-                              sparse_div);
+                              sparse_div, level_loop == BC_LOOP_GRAPH);
     // P parts of consecutive batches, each on its own stream and workspace,
     // ordered after the caller's earlier work; BC = the parts' sum in part
     // order, on the caller's stream
@@ -784,7 +866,7 @@ bc_status batched_run(bc_graph_s *g, const int32_t *sources, int32_t k, double *
             std::vector<BatchPlan> sub(plan.begin() + b0, plan.begin() + b1);
             status[(size_t)i] = run_batch_plan(g, s_int, sub, {}, {}, parts + (size_t)i * n,
                                                streams[(size_t)i], order.data(), dist, sigma,
-                                               sparse_div);
+                                               sparse_div, level_loop == BC_LOOP_GRAPH);
             if (hipEventRecord(ev_done[(size_t)i], streams[(size_t)i]) != hipSuccess &&
                 status[(size_t)i] == BC_OK)
                 status[(size_t)i] = BC_ERR_DEVICE;
@@ -872,7 +954,7 @@ bc_status multi_run(bc_graph_s *g, const int32_t *sources, const int32_t *req_st
         }
     }
     return run_batch_plan(g, s_int, plan, seg_start, seg_out, nullptr, stream, nullptr, nullptr,
-                          nullptr, g->tuned_sparse_div.load());
+                          nullptr, g->tuned_sparse_div.load(), false);
 }
 
 // Mode selection: BC_MODE_AUTO picks the batched path from the graph's

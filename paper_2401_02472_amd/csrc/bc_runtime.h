@@ -84,6 +84,24 @@ struct PlainWS {
     bool busy = false;
 };
 
+// Chunks of level steps captured as HIP graphs for replay (BC_LOOP_GRAPH):
+// K forward steps (or K reverse steps) with relative levels, then the move of
+// the chunk's base level.  A captured graph holds its kernels' arguments, so
+// each is kept with the workspace view and lane count it was captured for.
+struct ChunkGraphs {
+    struct Entry {
+        int32_t dir = 0, K = 0, nlanes = 0;
+        BatchDev d{};
+        hipGraphExec_t exec = nullptr;
+    };
+    hipStream_t cap = nullptr;   // capture stream (nothing runs on it)
+    std::vector<Entry> entries;  // most recently captured last
+    ~ChunkGraphs();
+    // Launch the chunk on `stream`, capturing it first if needed.
+    hipError_t replay(const BatchDev &d, int32_t dir, int32_t K, int32_t nlanes,
+                      hipStream_t stream);
+};
+
 // Batched workspace: lane-major sigma / c rows for 64 sources (128 with two
 // lane words per vertex), masks, and a level array that grows when a batch
 // runs deeper than it holds.
@@ -105,6 +123,7 @@ struct BatchWS {
     bool busy = false;
     int32_t gen = 0;           // the graph's work-item tables it was built for
     BatchDev dev{};
+    ChunkGraphs graphs;        // replayed level chunks (BC_LOOP_GRAPH)
 };
 
 class DeviceGuard {
@@ -312,10 +331,11 @@ struct ExtTables {
     int32_t *xe;
 };
 enum class BatchOutcome { Done, Rerun, Grow };
+// cg: replay the level chunks as captured graphs (NULL: launch every step).
 hipError_t drive_batch(bc_graph_s *g, BatchDev &d, const ExtTables &ext, const int32_t *lanes_dev,
                        int32_t nl, int32_t *h_ctrl, hipStream_t stream, LaunchTimer &timer,
                        unsigned long long *d_stats, int32_t stride, BatchOutcome &how,
-                       int32_t &deepest);
+                       int32_t &deepest, ChunkGraphs *cg);
 
 // ---- graph residency (bc_rt_graph.hip) ----
 void free_graph_arrays(bc_graph_s *g);

@@ -718,3 +718,49 @@ def test_small_graph_default_items_both_loops(g):
         check_bc(coarse, want)
         # the device loop does not depend on the host loop's items
         assert np.array_equal(dev, batched(G, src, level_loop=bcm.BC_LOOP_DEVICE))
+
+
+def _graph_cases():
+    return [
+        # several batches (ragged last one) in two concurrent parts
+        ("rmat13", gg.rmat(13, 16, seed=96), 150, 2, False),
+        # ~100 levels: chunks of two levels on the first run (no depth hint
+        # yet), one chunk once the hint is known
+        ("road64", gg.grid_road(64, 64, seed=97), 64, 1, False),
+        # path counts pass 2^32 on the way: the batch reruns with double rows
+        ("lattice40", gg.grid_full(40, 40), 40, 1, False),
+        # counts beyond double's range: level-scaled (extended-range) counts
+        ("diamonds", gg.diamond_chain(520, 4), 3, 1, True),
+        ("directed", gg.gnp_directed(900, 0.01, 98), 80, 1, False),
+    ]
+
+
+@pytest.mark.parametrize("name,g,k,conc,ext", [pytest.param(*c, id=c[0]) for c in _graph_cases()])
+def test_graph_loop_replays_match_host_loop(name, g, k, conc, ext):
+    """BC_LOOP_GRAPH replays captured chunks of level steps (HIP graphs whose
+    kernels take the chunk's base level from the device): each replay, with
+    eager host-loop runs and other sources in between, gives exactly the host
+    loop's BC, which matches the oracle."""
+    src = gg.sample_sources(g, min(k, g.n), seed=99)
+    if name == "diamonds":
+        src = np.array([0, g.n - 1, 7], np.int32)
+    other = gg.sample_sources(g, min(k, g.n) // 2 + 1, seed=100)
+    directed = name == "directed"
+    if directed:
+        want, st = oracle.bc(g.row_ptr, g.col_idx, np.asarray(src, np.int32), directed=True)
+        assert st == oracle.OK
+    else:
+        want = oracle_bc_ext(g, src) if ext else oracle_bc(g, src)
+    flags = bcm.BC_GRAPH_DIRECTED if directed else 0
+    with bcm.Graph(g.n, g.row_ptr, g.col_idx, flags=flags) as G:
+        host = batched(G, src, level_loop=bcm.BC_LOOP_HOST, concurrency=conc)
+        check_bc(host, want)
+        host_other = batched(G, other, level_loop=bcm.BC_LOOP_HOST, concurrency=conc)
+        for rep in range(3):
+            got = batched(G, src, level_loop=bcm.BC_LOOP_GRAPH, concurrency=conc)
+            assert np.array_equal(got, host), f"replay {rep}"
+            # eager work and another source set (another lane count) between replays
+            assert np.array_equal(batched(G, src, level_loop=bcm.BC_LOOP_HOST, concurrency=conc),
+                                  host)
+            got_o = batched(G, other, level_loop=bcm.BC_LOOP_GRAPH, concurrency=conc)
+            assert np.array_equal(got_o, host_other), f"replay {rep}, other sources"
