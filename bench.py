@@ -79,9 +79,10 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def read_traffic(kernel: str, workload: str, src_hash: str):
+def read_traffic(kernel: str, workload: str, src_hash: str, width: int = 0):
     """HBM bytes per launch from a committed counter summary, if it was taken
-    on the current kernel sources (else None)."""
+    on the current kernel sources and, given a batch width, at that width
+    (else None)."""
     path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_counters.md")
     if not os.path.exists(path):
         return None
@@ -89,6 +90,9 @@ def read_traffic(kernel: str, workload: str, src_hash: str):
     m_hash = re.search(r"kernel_source_hash:\s*(\w+)", text)
     m_val = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
     if not m_hash or not m_val or m_hash.group(1) != src_hash:
+        return None
+    m_w = re.search(r"--batch-width (\d+)", text)
+    if width and m_w and int(m_w.group(1)) != width:
         return None
     return float(m_val.group(1))
 
@@ -639,6 +643,9 @@ def main() -> int:
     levels_per_step = prof["levels"] / meas_steps
 
     src_hash = kernel_source_hash()
+    # the batch width of the run (counter summaries taken at another width do
+    # not describe its kernels)
+    width = args.batch_width or (tuning["batch_width"] if tuning else 64)
 
     def roofline_of(prof, path, ms_step, steps):
         """Dominant kernel of a profile and its roofline point."""
@@ -665,8 +672,8 @@ def main() -> int:
             f"{kernel_name}: {kernel_ms_step:.3f} ms of launches per {ms_step:.3f} ms step")
         return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": read_traffic(kernel_name, args.workload, src_hash),
-                **traffic_point(read_traffic(kernel_name, args.workload, src_hash), avg_ms),
+                "traffic": read_traffic(kernel_name, args.workload, src_hash, width),
+                **traffic_point(read_traffic(kernel_name, args.workload, src_hash, width), avg_ms),
                 "kernel": kernel_name, "alg_bytes_per_launch": round(per_launch),
                 "avg_launch_ms": round(avg_ms, 5), "launches": pc["launches"],
                 "kernel_ms_per_step": round(kernel_ms_step, 3),

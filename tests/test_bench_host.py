@@ -42,3 +42,15 @@ def test_counter_summaries_are_read_only_on_their_own_sources(path, kernel, work
     assert bench.read_traffic(kernel, workload, h) == pytest.approx(v)
     assert bench.read_traffic(kernel, workload, "0" * 16) is None
     assert bench.read_traffic(kernel, workload + "-absent", h) is None
+
+
+@pytest.mark.parametrize("path,kernel,workload", _summaries())
+def test_counter_summaries_are_read_only_at_their_batch_width(path, kernel, workload):
+    text = open(path).read()
+    m = re.search(r"--batch-width (\d+)", text)
+    if not m:
+        pytest.skip("summary of a kernel without batches")
+    h = re.search(r"kernel_source_hash:\s*(\w+)", text).group(1)
+    w = int(m.group(1))
+    assert bench.read_traffic(kernel, workload, h, w) is not None
+    assert bench.read_traffic(kernel, workload, h, 2 * w) is None
