@@ -258,17 +258,29 @@ def serving_bench(args) -> int:
     launches = srv.launches
     srv.close()
     # the same mix under a small workspace budget: admission queues launches
+    # and frees idle graphs' pools.  Its own saturation (a burst under that
+    # budget) sets the arrival rate: at the large budget's rate the small one
+    # would be overloaded and the latencies would only measure the backlog.
     stress = None
     if args.serving_stress_gib > 0:
         srv2 = BCServer(Gs, budget=int(args.serving_stress_gib) << 30, slots=args.slots,
                         max_lanes=256)
+        burst2 = [make_request(800_000 + i) for i in range(args.serving_burst)]
+        t = time.perf_counter()
+        for f in [srv2.submit(gid, src) for gid, src in burst2]:
+            f.result()
+        sat2_dt = time.perf_counter() - t
+        sat2_rate = len(burst2) / sat2_dt
+        sat2_gteps = sum(src.size * graphs[gid].nnz for gid, src in burst2) / sat2_dt / 1e9
         reqs = [make_request(900_000 + i) for i in range(args.serving_requests)]
-        wall_s, lat_s = poisson_run(srv2, args.serving_load * sat_rate, reqs)
+        wall_s, lat_s = poisson_run(srv2, args.serving_load * sat2_rate, reqs)
         work_s = sum(src.size * graphs[gid].nnz for gid, src in reqs)
-        stress = {"hbm_budget_gib": args.serving_stress_gib,
+        stress = {"hbm_budget_gib": args.serving_stress_gib, "load": args.serving_load,
+                  "saturation_gteps": round(sat2_gteps, 3),
                   "gteps": round(work_s / wall_s / 1e9, 3), "p50_ms": round(lat_s["p50_ms"], 3),
                   "p99_ms": round(lat_s["p99_ms"], 3), "max_reserved_gib":
-                  round(srv2.max_reserved / 2**30, 2), "launches": srv2.launches}
+                  round(srv2.max_reserved / 2**30, 2), "launches": srv2.launches,
+                  "trims": srv2.trims}
         srv2.close()
     work = sum(src.size * graphs[gid].nnz for gid, src in stream_reqs)
     value = work / wall / 1e9
