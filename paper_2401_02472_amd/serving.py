@@ -14,10 +14,11 @@ Admission counts the device memory the launches really hold: the library
 keeps each graph's workspaces pooled after a launch (`bc_workspace_held`), so
 the budget covers every graph's pool, the workspaces of launches in flight
 (`bc_workspace_bytes`, of which a graph's idle pool covers what it can) and
-the output arrays.  When a launch does not fit, the pools of idle graphs are
-freed (`bc_trim_workspaces`), least recently used first; if it still does not
-fit it waits for launches to finish.  A request that could never fit alone is
-rejected with BC_ERR_OUT_OF_MEMORY.
+the output arrays.  When a launch does not fit but would once idle graphs'
+pools are freed (`bc_trim_workspaces`), they are freed until it fits, those of
+graphs with no queued request first, each group least recently used first;
+otherwise it waits for launches in flight to finish.  A request that could
+never fit alone is rejected with BC_ERR_OUT_OF_MEMORY.
 
 Each result is the same whether the request runs alone or in a mix: a
 request of at most 64 sources never straddles two batches and every lane's
@@ -182,7 +183,7 @@ class BCServer:
     def _pick(self):
         """Graph whose oldest queued request has waited longest, and the
         requests of that graph that fit one launch and the budget (after
-        freeing idle graphs' pools, least recently used first)."""
+        freeing idle graphs' pools: those with nothing queued first)."""
         best, best_t = None, None
         for gid, q in self._queues.items():
             if q and (best_t is None or q[0].arrival < best_t):
@@ -195,8 +196,17 @@ class BCServer:
         ws0, out0 = self._split(best, q[0].k, 1)
         if self._projected(held, best, ws0, out0) > self.budget:
             trim = getattr(self.executor, "trim", None)
-            idle = sorted((g for g in held if held[g] > 0 and self._inflight_ws[g] == 0),
-                          key=lambda g: self._last_used[g])
+            # idle pools of graphs with nothing queued go first (least recently
+            # used first), then those whose requests wait (their next launch
+            # would build the pool again); never the pool this launch reuses
+            idle = sorted((g for g in held
+                           if g != best and held[g] > 0 and self._inflight_ws[g] == 0),
+                          key=lambda g: (len(self._queues[g]) > 0, self._last_used[g]))
+            # trim only if that lets the launch start now; otherwise it waits
+            # for launches in flight, and the pools stay for their graphs
+            if self._projected({g: (0 if g in idle else h) for g, h in held.items()},
+                               best, ws0, out0) > self.budget:
+                idle = []
             for g in idle:
                 if trim is None:
                     break

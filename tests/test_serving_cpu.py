@@ -107,3 +107,76 @@ def test_close_drains_the_queue(graphs):
     futs = [srv.submit("c", [i]) for i in range(10)]
     srv.close()
     assert all(f.done() for f in futs)
+
+
+def test_trims_idle_pools_of_graphs_without_queued_requests_first(graphs):
+    """A launch that does not fit frees idle pools: first those of graphs with
+    nothing queued, then (least recently used first) those whose requests wait;
+    never the pool of the graph being launched."""
+    class PoolExecutor(FakeExecutor):
+        def __init__(self, graphs, held):
+            super().__init__(graphs)
+            self.held = dict(held)
+            self.trimmed = []
+
+        def held_bytes(self, gid):
+            return self.held[gid]
+
+        def trim(self, gid):
+            self.trimmed.append(gid)
+            self.held[gid] = 0
+
+    # a launch of 8 sources on "a" needs 8100 bytes; the pools of "b" and "c"
+    # hold 5000 each, so one of them must go for it to fit 13500
+    ex = PoolExecutor(graphs, {"a": 0, "b": 5000, "c": 5000})
+    srv = BCServer(graphs, budget=13500, slots=0, executor=ex)  # no slot: nothing runs
+    try:
+        srv.submit("a", np.arange(8, dtype=np.int32))
+        srv.submit("b", np.arange(4, dtype=np.int32))
+        with srv._lock:
+            srv._last_used.update({"a": 3.0, "b": 1.0, "c": 2.0})  # "b" least recent
+            picked = srv._pick()
+        assert picked is not None and picked[0] == "a"
+        assert ex.trimmed == ["c"]      # "b" has a queued request: kept
+        # next the oldest request is "b"'s (4100 bytes); "b"'s own idle pool is
+        # not trimmed for its launch (it covers part of the workspace): "a"'s
+        # goes, although "a" has a request waiting
+        ex.held.update({"a": 5000, "b": 3000, "c": 0})
+        ex.trimmed.clear()
+        srv.submit("a", np.arange(8, dtype=np.int32) + 8)
+        with srv._lock:
+            srv.budget = 8000
+            picked = srv._pick()
+        assert picked is not None and picked[0] == "b"
+        assert ex.trimmed == ["a"]
+    finally:
+        srv.close(wait=False)
+
+
+def test_no_trim_when_the_launch_would_still_wait(graphs):
+    """Pools are not freed for a launch that would not fit even with every idle
+    pool gone (launches in flight hold the memory): it waits instead."""
+    class PoolExecutor(FakeExecutor):
+        def __init__(self, graphs, held):
+            super().__init__(graphs)
+            self.held = dict(held)
+            self.trimmed = []
+
+        def held_bytes(self, gid):
+            return self.held[gid]
+
+        def trim(self, gid):
+            self.trimmed.append(gid)
+            self.held[gid] = 0
+
+    ex = PoolExecutor(graphs, {"a": 0, "b": 2000, "c": 2000})
+    srv = BCServer(graphs, budget=13500, slots=0, executor=ex)
+    try:
+        srv.submit("a", np.arange(8, dtype=np.int32))   # 8100 bytes
+        with srv._lock:
+            srv._inflight_ws["c"] = 0
+            srv._out_reserved = 9000    # memory held by launches in flight
+            picked = srv._pick()
+        assert picked is None and ex.trimmed == []
+    finally:
+        srv.close(wait=False)
