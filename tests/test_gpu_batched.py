@@ -764,3 +764,24 @@ def test_graph_loop_replays_match_host_loop(name, g, k, conc, ext):
                                   host)
             got_o = batched(G, other, level_loop=bcm.BC_LOOP_GRAPH, concurrency=conc)
             assert np.array_equal(got_o, host_other), f"replay {rep}, other sources"
+
+
+def test_graph_loop_exports_per_source_state():
+    """bc_run_detail on the graph-replayed loop: dist and sigma of every source
+    and BC equal the host loop's, bit for bit, and match the oracle."""
+    g = gg.rmat(12, 16, seed=101)
+    src = gg.sample_sources(g, 70, seed=102)       # two batches, the second ragged
+    with bcm.Graph(g.n, g.row_ptr, g.col_idx) as G:
+        host = G.run_detail(src, bcm.make_options(bcm.BC_MODE_BATCHED,
+                                                  level_loop=bcm.BC_LOOP_HOST))
+        for _ in range(2):
+            rep = G.run_detail(src, bcm.make_options(bcm.BC_MODE_BATCHED,
+                                                     level_loop=bcm.BC_LOOP_GRAPH))
+            for a, b in zip(host, rep):
+                assert np.array_equal(a, b)
+    bc_h, dist_h, sigma_h = host[0], host[1], host[2]
+    check_bc(bc_h, oracle_bc(g, src))
+    for i in (0, 69):
+        od, osg, _, _ = oracle.single_source(g.row_ptr, g.col_idx, int(src[i]), with_delta=False)
+        assert np.array_equal(dist_h[i], od)
+        check_sigma(sigma_h[i], osg)
