@@ -529,9 +529,9 @@ def main() -> int:
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: this build runs on a single MI355X and has no "
-              "multi-GPU path (sources would shard across GPUs with one BC all-reduce; "
-              "see DESIGN.md).", file=sys.stderr)
+        print("bench.py measures one GPU: the library runs on a single MI355X and has no "
+              "multi-GPU path (sources would shard across GPUs, each holding the whole "
+              "graph, with one all-reduce of BC at the end).", file=sys.stderr)
         return 2
 
     import numpy as np
