@@ -232,6 +232,40 @@ bc_status bc_run_multi(bc_graph_t g, const int32_t *sources, const int32_t *req_
                        int32_t nreq, double *const *bc_outs, void *stream);
 
 /*
+ * BC of several graphs in one call (Section "Background", ComputeBC, on each
+ * graph): graph i from its ks[i] sources into bc_outs_dev[i].  The 64-source
+ * batches of the graphs that join go in one device-resident launch, one
+ * workgroup per batch (two launches when some graphs keep double rows), so
+ * many small graphs of uneven size share a launch; the others run after it on
+ * the host-driven loop.  level_loop: BC_LOOP_DEVICE, every graph joins;
+ * BC_LOOP_HOST, none does; BC_LOOP_AUTO, the graphs with the shortest batches
+ * join, as many as minimise the estimated time of the launch (its slowest
+ * batch) plus the host-loop runs of the rest (the cost model of
+ * BC_LOOP_AUTO).  Each graph's result is bit-identical to bc_run_async on that
+ * graph with BC_MODE_BATCHED, batch_width 64 and the loop reported in
+ * loops[i]; a graph that joins but cannot stay (extended range, more batches
+ * than its device-loop pool holds at once) or whose batches call for a rerun
+ * (double rows, a longer level array) runs on its own afterwards, as such a
+ * call would.
+ *   graphs       [ngraphs] host array of distinct graphs on one device
+ *   sources      [ngraphs] host array of host arrays: sources[i] holds ks[i]
+ *                sources of graph i (NULL allowed where ks[i] == 0)
+ *   ks           [ngraphs] host, ks[i] >= 0
+ *   bc_outs_dev  [ngraphs] host array of device pointers, bc_outs_dev[i] to n_i
+ *                doubles, overwritten with BC (caller vertex order)
+ *   level_loop   BC_LOOP_AUTO, BC_LOOP_HOST or BC_LOOP_DEVICE
+ *   loops        NULL or [ngraphs] host: BC_LOOP_DEVICE or BC_LOOP_HOST per graph
+ * Uses each graph's device-loop pool (as bc_run_async with BC_LOOP_DEVICE) and
+ * allocates the launch's tables (device memory); waits on `stream`.  Errors:
+ * BC_ERR_INVALID_ARG (a NULL array or output, a graph given twice, graphs on
+ * different devices, a source out of range, another level_loop), then as
+ * bc_run_async.
+ */
+bc_status bc_run_graphs(const bc_graph_t *graphs, int32_t ngraphs, const int32_t *const *sources,
+                        const int32_t *ks, double *const *bc_outs_dev, int32_t level_loop,
+                        int32_t *loops, void *stream);
+
+/*
  * One source, full per-vertex state (host outputs), for parity checks, from
  * the one-source-at-a-time path in double (no extended range: counts beyond
  * DBL_MAX give BC_ERR_RANGE, with dist still exact).  Undirected graphs only:

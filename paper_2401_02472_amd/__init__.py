@@ -24,7 +24,7 @@ from ._capi import (BC_ERR_DEVICE, BC_ERR_INVALID_ARG, BC_ERR_INVALID_GRAPH,  # 
 __all__ = [
     "BCError", "bc_create_graph", "bc_destroy_graph", "bc_graph_info", "bc_run", "bc_run_async",
     "bc_run_async_noalloc",
-    "bc_run_multi",
+    "bc_run_multi", "bc_run_graphs",
     "bc_single_source", "bc_run_detail", "bc_workspace_bytes", "bc_trim_workspaces",
     "bc_workspace_held", "bc_autotune", "bc_set_work_items",
     "bc_profile_enable", "bc_profile_read", "bc_set_weights", "bc_sssp", "bc_pagerank",
@@ -160,6 +160,29 @@ def bc_run_multi(g: int, requests, outs, stream=None) -> None:
                                    _ptr(start, ctypes.c_int32), len(srcs), ptrs,
                                    _stream_handle(stream))
     _check(st, "bc_run_multi", outs)
+
+
+def bc_run_graphs(graphs, sources, outs, level_loop: int = BC_LOOP_AUTO, stream=None) -> list:
+    """BC of several graphs in one call (the batches of the graphs that join in
+    one device-resident launch): graphs are Graph objects or handles,
+    sources[i] the source array of graph i, outs[i] a float64 device tensor of
+    n_i entries.  Returns the loop each graph ran on (BC_LOOP_DEVICE or
+    BC_LOOP_HOST)."""
+    handles = [g.handle if isinstance(g, Graph) else int(g) for g in graphs]
+    srcs = [_i32(s) for s in sources]
+    if not (len(handles) == len(srcs) == len(outs)):
+        raise ValueError("graphs, sources and outs differ in length")
+    m = max(len(handles), 1)
+    h_arr = (ctypes.c_void_p * m)(*handles)
+    s_arr = (ctypes.c_void_p * m)(*[s.ctypes.data if s.size else None for s in srcs])
+    ks = np.ascontiguousarray([s.size for s in srcs] or [0], dtype=np.int32)
+    o_arr = (ctypes.c_void_p * m)(*[o.data_ptr() for o in outs])
+    loops = np.zeros(m, dtype=np.int32)
+    st = _capi.load().bc_run_graphs(h_arr, len(handles), s_arr, _ptr(ks, ctypes.c_int32), o_arr,
+                                    int(level_loop), _ptr(loops, ctypes.c_int32),
+                                    _stream_handle(stream))
+    _check(st, "bc_run_graphs", outs)
+    return [int(x) for x in loops[:len(handles)]]
 
 
 def bc_set_weights(g: int, weight) -> None:

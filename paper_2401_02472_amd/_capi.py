@@ -39,7 +39,7 @@ EXPORTED = ("bc_create_graph", "bc_destroy_graph", "bc_graph_info", "bc_run", "b
             "bc_run_multi", "bc_single_source", "bc_run_detail", "bc_workspace_bytes", "bc_trim_workspaces",
             "bc_profile_enable", "bc_profile_read", "bc_autotune", "bc_set_weights", "bc_sssp",
             "bc_pagerank", "bc_status_str", "bc_run_async_noalloc",
-            "bc_workspace_held", "bc_set_work_items")
+            "bc_workspace_held", "bc_set_work_items", "bc_run_graphs")
 
 BC_LOOP_AUTO = 0
 BC_LOOP_HOST = 1
@@ -111,6 +111,8 @@ def load():
             "bc_run_async": [vp, i32p, ctypes.c_int32, vp, optp, vp],
             "bc_run_async_noalloc": [vp, i32p, ctypes.c_int32, vp, vp],
             "bc_run_multi": [vp, i32p, i32p, ctypes.c_int32, ctypes.POINTER(vp), vp],
+            "bc_run_graphs": [ctypes.POINTER(vp), ctypes.c_int32, ctypes.POINTER(vp), i32p,
+                              ctypes.POINTER(vp), ctypes.c_int32, i32p, vp],
             "bc_single_source": [vp, ctypes.c_int32, i32p, f64p, f64p],
             "bc_run_detail": [vp, i32p, ctypes.c_int32, optp, f64p, i32p, f64p],
             "bc_workspace_bytes": [vp, ctypes.c_int32, optp, szp],

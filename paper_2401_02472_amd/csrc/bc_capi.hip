@@ -198,6 +198,28 @@ bc_status bc_run_multi(bc_graph_t g, const int32_t *sources, const int32_t *req_
     return multi_run(g, sources, req_start, nreq, bc_outs, (hipStream_t)stream);
 }
 
+bc_status bc_run_graphs(const bc_graph_t *graphs, int32_t ngraphs, const int32_t *const *sources,
+                        const int32_t *ks, double *const *bc_outs_dev, int32_t level_loop,
+                        int32_t *loops, void *stream) {
+    if (ngraphs < 0 || (ngraphs > 0 && (!graphs || !sources || !ks || !bc_outs_dev)))
+        return BC_ERR_INVALID_ARG;
+    if (level_loop != BC_LOOP_AUTO && level_loop != BC_LOOP_HOST && level_loop != BC_LOOP_DEVICE)
+        return BC_ERR_INVALID_ARG;
+    for (int32_t i = 0; i < ngraphs; ++i) {
+        bc_graph_s *g = graphs[i];
+        if (!g || ks[i] < 0 || (!bc_outs_dev[i] && g->n > 0)) return BC_ERR_INVALID_ARG;
+        if (g->device != graphs[0]->device) return BC_ERR_INVALID_ARG;
+        for (int32_t j = 0; j < i; ++j)
+            if (graphs[j] == g) return BC_ERR_INVALID_ARG;  // each graph once
+        const bc_status st = check_sources(g, sources[i], ks[i]);
+        if (st != BC_OK) return st;
+    }
+    if (ngraphs == 0) return BC_OK;
+    DeviceGuard dg(graphs[0]->device);
+    return run_graphs(graphs, ngraphs, sources, ks, bc_outs_dev, level_loop, loops,
+                      (hipStream_t)stream);
+}
+
 bc_status bc_single_source(bc_graph_t g, int32_t s, int32_t *dist, double *sigma,
                            double *delta) {
     if (!g || ((!dist || !sigma) && g->n > 0)) return BC_ERR_INVALID_ARG;

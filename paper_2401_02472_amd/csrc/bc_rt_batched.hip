@@ -751,6 +751,214 @@ bc_status fused_run(bc_graph_s *g, const std::vector<int32_t> &s_int,
     return range ? BC_ERR_RANGE : BC_OK;
 }
 
+bc_status make_plan(bc_graph_s *g, const int32_t *sources, int32_t k, int32_t width,
+                    std::vector<int32_t> &order, std::vector<int32_t> &s_int,
+                    std::vector<BatchPlan> &plan);
+
+// Several graphs' batches in one device-resident launch (one per row width):
+// each graph's plan is batched_run's at width 64 and each batch runs on its
+// graph's pool, so every graph's BC is bit-identical to its own device-loop
+// run.  A graph that cannot join (extended range, more batches than its pool
+// holds at once) or whose batches call for a rerun (wider rows, a longer
+// level array, counts past double's range) runs on its own afterwards, as
+// bc_run_async with the device-resident loop would run it.
+bc_status run_graphs(bc_graph_s *const *gs, int32_t ng, const int32_t *const *sources,
+                     const int32_t *ks, double *const *outs, int32_t level_loop,
+                     int32_t *loops, hipStream_t stream) {
+    // BC_LOOP_AUTO: the graphs that join are the prefix, by one batch's
+    // estimated device-loop time, that minimises the launch (its slowest
+    // batch: the batches run side by side, one workgroup each) plus the
+    // host-loop estimates of the graphs left out (the cost model of use_fused)
+    std::vector<char> join((size_t)ng, level_loop == BC_LOOP_HOST ? 0 : 1);
+    if (level_loop == BC_LOOP_AUTO) {
+        std::vector<int32_t> idx;
+        for (int32_t i = 0; i < ng; ++i)
+            if (gs[i]->n > 0 && ks[i] > 0) idx.push_back(i);
+        auto dev_t = [&](int32_t i) { return 2e-3 + 50e-9 * (double)gs[i]->nnz; };
+        auto host_t = [&](int32_t i) {
+            return std::ceil((double)ks[i] / kWave) * (0.8e-3 + 0.15e-9 * (double)gs[i]->nnz);
+        };
+        std::stable_sort(idx.begin(), idx.end(),
+                         [&](int32_t a, int32_t b) { return dev_t(a) < dev_t(b); });
+        double rest = 0.0;
+        for (int32_t i : idx) rest += host_t(i);
+        double best = rest;  // nothing joins
+        size_t best_j = 0;
+        for (size_t j = 0; j < idx.size(); ++j) {
+            rest -= host_t(idx[j]);
+            const double t = dev_t(idx[j]) + rest;
+            if (t < best) {
+                best = t;
+                best_j = j + 1;
+            }
+        }
+        std::fill(join.begin(), join.end(), 0);
+        for (size_t j = 0; j < best_j; ++j) join[(size_t)idx[j]] = 1;
+    }
+    struct Part {
+        int32_t i = 0;                  // graph index
+        std::vector<int32_t> order, s_int;
+        std::vector<BatchPlan> plan;
+        int32_t lane0 = 0;              // first lane in the combined lane array
+        bool narrow = true;             // row width, read once for the call
+        bool alone = false;
+    };
+    std::vector<Part> parts;
+    std::vector<int32_t> alone;
+    bc_status st = BC_OK;
+    for (int32_t i = 0; i < ng && st == BC_OK; ++i) {
+        bc_graph_s *g = gs[i];
+        if (g->n == 0) continue;
+        const int32_t lcap = std::max(16, g->batch_depth_hint.load() + 8);
+        const int32_t nb = (ks[i] + kWave - 1) / kWave;
+        if (!join[(size_t)i] || ks[i] == 0 || g->sigma_ext.load() || fused_cap(g, nb, lcap) < nb) {
+            alone.push_back(i);
+            continue;
+        }
+        Part p;
+        p.i = i;
+        st = make_plan(g, sources[i], ks[i], kWave, p.order, p.s_int, p.plan);
+        parts.push_back(std::move(p));
+    }
+    if (st != BC_OK) return st;
+    // every pool of the launch held, locked in address order
+    std::vector<bc_graph_s *> locked;
+    for (const Part &p : parts) locked.push_back(gs[p.i]);
+    std::sort(locked.begin(), locked.end());
+    std::vector<std::unique_lock<std::mutex>> locks;
+    for (bc_graph_s *g : locked) locks.emplace_back(g->fused_mu);
+    int32_t lanes = 0, batches = 0;
+    for (Part &p : parts) {
+        bc_graph_s *g = gs[p.i];
+        const int32_t lcap = std::max(16, g->batch_depth_hint.load() + 8);
+        st = fused_reserve(g, (int32_t)p.plan.size(), lcap);
+        if (st == BC_OK && !g->fused.d_total)
+            st = from_hip(hipMalloc(&g->fused.d_total, (size_t)g->n * sizeof(double)));
+        if (st != BC_OK) return st;
+        p.lane0 = lanes;
+        p.narrow = !g->sigma_wide.load();
+        lanes += (int32_t)p.s_int.size();
+        batches += (int32_t)p.plan.size();
+    }
+    int32_t *d_lanes = nullptr;
+    BatchDev *d_devs = nullptr;
+    int2 *d_bt = nullptr;
+    struct Tmp {
+        int32_t *&a;
+        BatchDev *&b;
+        int2 *&c;
+        ~Tmp() {
+            if (a) (void)hipFree(a);
+            if (b) (void)hipFree(b);
+            if (c) (void)hipFree(c);
+        }
+    } tmp_guard{d_lanes, d_devs, d_bt};
+    hipError_t e = hipSuccess;
+    if (batches > 0) {
+        e = hipMalloc(&d_lanes, (size_t)std::max(lanes, 1) * sizeof(int32_t));
+        if (e == hipSuccess) e = hipMalloc(&d_devs, (size_t)batches * sizeof(BatchDev));
+        if (e == hipSuccess) e = hipMalloc(&d_bt, (size_t)batches * sizeof(int2));
+    }
+    // host tables: lanes, batch views and (first lane, lane count) per batch,
+    // the narrow-row graphs' batches first
+    std::vector<int32_t> h_lanes((size_t)std::max(lanes, 1));
+    std::vector<BatchDev> h_devs;
+    std::vector<int2> h_bt;
+    int32_t n_narrow = 0;
+    for (int pass = 0; pass < 2 && e == hipSuccess; ++pass) {
+        for (Part &p : parts) {
+            bc_graph_s *g = gs[p.i];
+            const bool narrow = p.narrow;
+            if (narrow != (pass == 0)) continue;
+            auto &f = g->fused;
+            std::copy(p.s_int.begin(), p.s_int.end(), h_lanes.begin() + p.lane0);
+            for (size_t b = 0; b < p.plan.size(); ++b) {
+                BatchDev d = f.h_devs[b];
+                d.narrow = narrow ? 1 : 0;
+                d.stats = nullptr;
+                d.nseg = 0;
+                d.seg_start = nullptr;
+                d.seg_out = nullptr;
+                h_devs.push_back(d);
+                h_bt.push_back(make_int2(p.lane0 + p.plan[b].first, p.plan[b].nlanes));
+            }
+            if (pass == 0) n_narrow += (int32_t)p.plan.size();
+        }
+    }
+    if (h_devs.size() != (size_t)batches || h_bt.size() != (size_t)batches) return BC_ERR_DEVICE;
+    if (e == hipSuccess && batches > 0)
+        e = hipMemcpyAsync(d_lanes, h_lanes.data(), (size_t)lanes * sizeof(int32_t),
+                           hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess && batches > 0)
+        e = hipMemcpyAsync(d_devs, h_devs.data(), (size_t)batches * sizeof(BatchDev),
+                           hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess && batches > 0)
+        e = hipMemcpyAsync(d_bt, h_bt.data(), (size_t)batches * sizeof(int2),
+                           hipMemcpyHostToDevice, stream);
+    // the launches: narrow rows, then double rows
+    if (e == hipSuccess && n_narrow > 0)
+        e = batch_fused(d_devs, n_narrow, true, d_lanes, d_bt, stream);
+    if (e == hipSuccess && batches > n_narrow)
+        e = batch_fused(d_devs + n_narrow, batches - n_narrow, false, d_lanes, d_bt + n_narrow,
+                        stream);
+    for (Part &p : parts) {
+        if (e != hipSuccess) break;
+        auto &f = gs[p.i]->fused;
+        e = hipMemcpyAsync(f.h_ctrl, f.d_ctrl, p.plan.size() * kCtlInts * sizeof(int32_t),
+                           hipMemcpyDeviceToHost, stream);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return from_hip(e);
+    bool range = false;
+    for (Part &p : parts) {
+        bc_graph_s *g = gs[p.i];
+        auto &f = g->fused;
+        const int32_t nb = (int32_t)p.plan.size();
+        bool redo = false, over = false;
+        int32_t depth = 0;
+        for (int32_t b = 0; b < nb; ++b) {
+            const int32_t *c = f.h_ctrl + (size_t)b * kCtlInts;
+            if (c[kCtlNarrow]) {  // a path count needs double rows
+                g->sigma_wide.store(true);
+                redo = true;
+            }
+            if (c[kCtlTrunc]) redo = true;  // a batch ran deeper than the level array
+            over |= c[kCtlRange] != 0;
+            depth = std::max(depth, c[kCtlDeepest]);
+        }
+        if (over) g->sigma_ext.store(true);  // beyond double: level-scaled, host loop
+        if (redo || over) {
+            p.alone = true;
+            continue;
+        }
+        g->batch_depth_hint.store(depth);
+        e = sum_parts(g->n, f.d_bc, nb, f.d_total, stream, false);
+        if (e == hipSuccess) e = gather_f64(g->n, g->d_perm, f.d_total, outs[p.i], stream);
+        if (e != hipSuccess) return from_hip(e);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return from_hip(e);
+    locks.clear();
+    for (const Part &p : parts)
+        if (p.alone) alone.push_back(p.i);
+    std::sort(alone.begin(), alone.end());
+    for (int32_t i = 0; loops && i < ng; ++i) loops[i] = BC_LOOP_DEVICE;
+    for (int32_t i : alone) {
+        bc_graph_s *g = gs[i];
+        // as the graph would run alone with the loop it was given (a graph
+        // left out of the launch: the host loop)
+        const int32_t loop = join[(size_t)i] ? BC_LOOP_DEVICE : BC_LOOP_HOST;
+        if (loops) loops[i] = use_fused(g, loop, (ks[i] + kWave - 1) / kWave, kWave)
+                                  ? BC_LOOP_DEVICE : BC_LOOP_HOST;
+        const bc_status s2 = batched_run(g, sources[i], ks[i], outs[i], kWave,
+                                         g->tuned_sparse_div.load(), 0, loop, stream,
+                                         nullptr, nullptr);
+        if (s2 == BC_ERR_RANGE) range = true;
+        else if (s2 != BC_OK) return s2;
+    }
+    return range ? BC_ERR_RANGE : BC_OK;
+}
+
 // The device-resident loop runs a batch on one compute unit (up to 256
 // batches at once); the host-driven loop runs a batch across the device.
 // Measured on MI355X (R-MAT graphs of 53K to 7.6M arcs): one batch takes about
@@ -794,15 +1002,17 @@ bc_status get_streams(bc_graph_s *g, int32_t p, std::vector<hipStream_t> &out) {
     return BC_OK;
 }
 
-bc_status batched_run(bc_graph_s *g, const int32_t *sources, int32_t k, double *bc_out,
-                      int32_t width, int32_t sparse_div, int32_t concurrency,
-                      int32_t level_loop, hipStream_t stream, int32_t *dist, double *sigma) {
-    // Batch composition: sources sorted by their distances to the two
-    // landmarks, so that the 64 sources of a batch lie close together and see
-    // most vertices at the same level (their frontier masks share lanes, the
-    // row gathers are dense).  BC is a sum over sources, so any grouping gives
-    // the same result up to rounding; the order depends only on the inputs.
-    std::vector<int32_t> order((size_t)k);
+// Batch composition: sources sorted by their distances to the two landmarks,
+// so that the sources of a batch lie close together and see most vertices at
+// the same level (their frontier masks share lanes, the row gathers are
+// dense).  BC is a sum over sources, so any grouping gives the same result up
+// to rounding; the order depends only on the inputs.  order[i] = caller index
+// of lane i of the run, s_int = its internal source ids, plan = batches of
+// `width` lanes.
+bc_status make_plan(bc_graph_s *g, const int32_t *sources, int32_t k, int32_t width,
+                    std::vector<int32_t> &order, std::vector<int32_t> &s_int,
+                    std::vector<BatchPlan> &plan) {
+    order.assign((size_t)k, 0);
     for (int32_t i = 0; i < k; ++i) order[(size_t)i] = i;
     if (k > width && !g->directed) {  // the landmarks' BFS runs undirected
         bc_status st = ensure_landmarks(g);
@@ -816,10 +1026,22 @@ bc_status batched_run(bc_graph_s *g, const int32_t *sources, int32_t k, double *
         std::stable_sort(order.begin(), order.end(),
                          [&](int32_t x, int32_t y) { return key(x) < key(y); });
     }
-    std::vector<int32_t> s_int((size_t)k);
+    s_int.assign((size_t)k, 0);
     for (int32_t i = 0; i < k; ++i) s_int[(size_t)i] = g->h_perm[(size_t)sources[order[(size_t)i]]];
-    std::vector<BatchPlan> plan;
+    plan.clear();
     for (int32_t b0 = 0; b0 < k; b0 += width) plan.push_back({b0, std::min(width, k - b0), 0, 0});
+    return BC_OK;
+}
+
+bc_status batched_run(bc_graph_s *g, const int32_t *sources, int32_t k, double *bc_out,
+                      int32_t width, int32_t sparse_div, int32_t concurrency,
+                      int32_t level_loop, hipStream_t stream, int32_t *dist, double *sigma) {
+    std::vector<int32_t> order, s_int;
+    std::vector<BatchPlan> plan;
+    {
+        const bc_status st0 = make_plan(g, sources, k, width, order, s_int, plan);
+        if (st0 != BC_OK) return st0;
+    }
     if (use_fused(g, level_loop, (int32_t)plan.size(), width)) {
         // a count beyond double's range sends the call to the host loop
         const bc_status st =

@@ -324,6 +324,9 @@ bc_status batched_run(bc_graph_s *g, const int32_t *sources, int32_t k, double *
                       int32_t level_loop, hipStream_t stream, int32_t *dist, double *sigma);
 bc_status multi_run(bc_graph_s *g, const int32_t *sources, const int32_t *req_start,
                     int32_t nreq, double *const *outs, hipStream_t stream);
+bc_status run_graphs(bc_graph_s *const *gs, int32_t ng, const int32_t *const *sources,
+                     const int32_t *ks, double *const *outs, int32_t level_loop,
+                     int32_t *loops, hipStream_t stream);
 // Extended-range tables of a batch workspace ([lcap][64] each).
 struct ExtTables {
     double *xs;
