@@ -170,6 +170,85 @@ def reached_arcs(g, sources):
     return int(comp_arcs[label[np.asarray(sources, np.int64)]].sum())
 
 
+def graphs_bench(args) -> int:
+    """graphs-mix: 16 small R-MAT graphs (scales 10-12, edge factor 16, 64
+    sources each) in one bc_run_graphs call per step (BC_LOOP_AUTO picks the
+    graphs whose batches share one device-resident launch), against one
+    bc_run_async call per graph (BC_MODE_AUTO) on the same sources.  GTEPS =
+    sum of k * nnz over the graphs / step time."""
+    import numpy as np
+    import torch
+
+    import graphgen as gg
+    import paper_2401_02472_amd as bcm
+
+    torch.cuda.set_device(0)
+    bcm.load_library()
+    graphs = [gg.rmat(sc, 16, seed=10 * sc + j) for sc in (10, 11, 12) for j in range(6)][:16]
+    srcs = [gg.sample_sources(g, 64, seed=3) for g in graphs]
+    Gs = [bcm.Graph(g.n, g.row_ptr, g.col_idx, flags=bcm.BC_GRAPH_TRUST_SYMMETRIC) for g in graphs]
+    outs = [torch.empty(g.n, dtype=torch.float64, device="cuda") for g in graphs]
+    work = sum(s.size * g.nnz for s, g in zip(srcs, graphs))
+    auto = bcm.make_options(bcm.BC_MODE_AUTO)
+
+    def one_call():
+        return bcm.bc_run_graphs(Gs, srcs, outs, level_loop=bcm.BC_LOOP_AUTO)
+
+    def per_graph():
+        for G, src, o in zip(Gs, srcs, outs):
+            G.run_async(src, o, auto)
+
+    def timed(fn):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        ms = []
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            t = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            ms.append((time.perf_counter() - t) * 1e3)
+        return (time.perf_counter() - t0) * 1e3 / args.steps, ms
+
+    loops = one_call()
+    ms_step, step_ms = timed(one_call)
+    ms_each, _ = timed(per_graph)
+    q = np.percentile(step_ms, [50, 99])
+    cpu = None
+    if args.cpu_seconds > 0:  # the oracle over the graphs, one after another
+        import oracle
+        threads = min(os.cpu_count() or 1, 16, oracle.max_threads())
+        t = time.perf_counter()
+        done = 0
+        for g, src in zip(graphs, srcs):
+            oracle.bc(g.row_ptr, g.col_idx, src, threads=threads)
+            done += src.size * g.nnz
+            if time.perf_counter() - t > args.cpu_seconds:
+                break
+        dt = time.perf_counter() - t
+        cpu = {"value": round(done / dt / 1e9, 4), "unit": "GTEPS", "cores": threads,
+               "kind": "oracle", "sample": f"the graphs in order until {args.cpu_seconds} s, "
+                                           f"{dt:.2f} s on {threads} threads"}
+    rec = {
+        "metric": METRIC, "value": round(work / (ms_step / 1e3) / 1e9, 3), "unit": "GTEPS",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "graphs-mix", "graphs": len(graphs), "scales": [10, 11, 12],
+                   "edgefactor": 16, "sources_per_graph": 64, "level_loop": "auto",
+                   "joined": int(sum(1 for x in loops if x == bcm.BC_LOOP_DEVICE))},
+        "p50_ms": round(float(q[0]), 3), "p99_ms": round(float(q[1]), 3),
+        "per_graph_calls": {"ms_per_step": round(ms_each, 3),
+                            "gteps": round(work / (ms_each / 1e3) / 1e9, 3)},
+        "roofline": None, "cpu_baseline": cpu,
+    }
+    for G in Gs:
+        G.close()
+    print(json.dumps(rec), flush=True)
+    return 0
+
+
 def serving_bench(args) -> int:
     """Serving mix: Poisson stream of BC requests over 16 resident R-MAT graphs
     (scales 14-20 with two seeds each, plus 21 and 22; edge factor 16); each
@@ -545,6 +624,8 @@ def main() -> int:
         return 2
     if args.workload == "serving-mix":
         return serving_bench(args)
+    if args.workload == "graphs-mix":
+        return graphs_bench(args)
     if args.workload == "sssp-rmat-s22-ef16":
         return sssp_bench(args)
     if args.workload == "pagerank-rmat-s22-ef16":
