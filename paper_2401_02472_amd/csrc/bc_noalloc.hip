@@ -167,8 +167,9 @@ extern "C" bc_status bc_run_async_noalloc(bc_graph_t g, const int32_t *sources, 
         if (e != hipSuccess) return from_hip(e);
         BatchOutcome how = BatchOutcome::Done;
         int32_t deepest = 0;
+        // (the array's sigma rows are double-sized)
         e = drive_batch(g, d, ext, d_lanes, nl, h_ctrl, stream, timer, nullptr, 1, how, deepest,
-                        nullptr);
+                        nullptr, true);
         if (e != hipSuccess) return from_hip(e);
         if (how == BatchOutcome::Rerun) continue;           // same memory, wider rows
         if (how == BatchOutcome::Grow) return BC_ERR_TOO_LARGE;  // deeper than the array holds

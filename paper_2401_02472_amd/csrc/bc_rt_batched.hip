@@ -29,12 +29,17 @@ void set_items(const bc_graph_s::BcItems &t, BatchDev &d) {
 // ... the graph's current tables (the host-driven loop's).
 void set_items(const bc_graph_s *g, BatchDev &d) { set_items(g->bci, d); }
 
-size_t batch_ws_bytes(const bc_graph_s *g, int32_t H) {
+// Rows of the graph's counts: double once a count passed 32 bits (or the
+// extended range is on), uint32 before.
+bool sigma_rows_wide(const bc_graph_s *g) { return g->sigma_wide.load() || g->sigma_ext.load(); }
+
+size_t batch_ws_bytes_rows(const bc_graph_s *g, int32_t H, bool wide) {
     const size_t n = (size_t)std::max<int32_t>(g->n, 1);
     const size_t lanes = (size_t)H * kWave;
     size_t b = 0;
     b += align_up(n * H * sizeof(uint64_t));             // vis
-    b += 2 * align_up(n * lanes * sizeof(double));       // sigma, coef rows
+    b += align_up(n * lanes * (wide ? sizeof(double) : sizeof(uint32_t)));  // sigma rows
+    b += align_up(n * lanes * sizeof(double));           // coef rows
     b += align_up(kBatchCtrlInts * sizeof(int32_t));     // ctrl
     b += align_up(n * H * sizeof(double));               // bc, one array per half
     b += align_up((size_t)std::max(g->bci.multi_end, 1) * H * sizeof(uint64_t));  // reach
@@ -46,6 +51,10 @@ size_t batch_ws_bytes(const bc_graph_s *g, int32_t H) {
     b += align_up((size_t)kFrontSets * kFrontWaves * 2 * sizeof(unsigned long long));
     b += align_up(((n + 15) / 16) * 16);                 // candidate marks
     return b;
+}
+
+size_t batch_ws_bytes(const bc_graph_s *g, int32_t H) {
+    return batch_ws_bytes_rows(g, H, sigma_rows_wide(g));
 }
 
 // F[lcap][n][H] and the extended-range tables xs, xmax, xe ([lcap][H][64] each).
@@ -64,6 +73,7 @@ void batch_ws_destroy(BatchWS *ws) {
     ws->timer.destroy();
     if (ws->F) (void)hipFree(ws->F);
     if (ws->d_src) (void)hipFree(ws->d_src);
+    if (ws->wide_sigma) (void)hipFree(ws->wide_sigma);
     if (ws->block) (void)hipFree(ws->block);
     if (ws->h_ctrl) (void)hipHostFree(ws->h_ctrl);
     delete ws;
@@ -74,7 +84,8 @@ bc_status batch_ws_create(bc_graph_s *g, int32_t H, BatchWS **out) {
     if (!ws) return BC_ERR_OUT_OF_MEMORY;
     ws->H = H;
     ws->gen = g->bci_gen.load();
-    ws->bytes = batch_ws_bytes(g, H);
+    ws->wide = sigma_rows_wide(g);  // read once: the layout below follows it
+    ws->bytes = batch_ws_bytes_rows(g, H, ws->wide);
     hipError_t e = hipMalloc(&ws->block, ws->bytes);
     if (e == hipSuccess)
         e = hipHostMalloc((void **)&ws->h_ctrl, kBatchCtrlInts * sizeof(int32_t),
@@ -98,7 +109,7 @@ bc_status batch_ws_create(bc_graph_s *g, int32_t H, BatchWS **out) {
     d.row_ptr = g->d_row_ptr;
     d.col_idx = g->d_col_idx;
     d.vis = (uint64_t *)take(n * H * sizeof(uint64_t));
-    d.sigma = (double *)take(n * lanes * sizeof(double));
+    d.sigma = (double *)take(n * lanes * (ws->wide ? sizeof(double) : sizeof(uint32_t)));
     d.sigma32 = reinterpret_cast<uint32_t *>(d.sigma);
     d.narrow = 1;
     d.coef = (double *)take(n * lanes * sizeof(double));
@@ -121,6 +132,19 @@ bc_status batch_ws_create(bc_graph_s *g, int32_t H, BatchWS **out) {
     d.F = nullptr;
     d.lcap = 0;
     *out = ws;
+    return BC_OK;
+}
+
+// Double-sized sigma rows for a workspace built with uint32 ones (its own
+// region stays unused).
+bc_status batch_widen(bc_graph_s *g, BatchWS *ws) {
+    if (ws->wide) return BC_OK;
+    const size_t bytes = (size_t)std::max<int32_t>(g->n, 1) * ws->H * kWave * sizeof(double);
+    BC_TRY_HIP(hipMalloc(&ws->wide_sigma, bytes));
+    ws->wide = true;
+    ws->bytes += bytes;
+    ws->dev.sigma = (double *)ws->wide_sigma;
+    ws->dev.sigma32 = reinterpret_cast<uint32_t *>(ws->wide_sigma);
     return BC_OK;
 }
 
@@ -261,7 +285,7 @@ hipError_t ChunkGraphs::replay(const BatchDev &d, int32_t dir, int32_t K, int32_
 hipError_t drive_batch(bc_graph_s *g, BatchDev &d, const ExtTables &ext, const int32_t *lanes_dev,
                        int32_t nl, int32_t *h_ctrl, hipStream_t stream, LaunchTimer &timer,
                        unsigned long long *d_stats, int32_t stride, BatchOutcome &how,
-                       int32_t &deepest, ChunkGraphs *cg) {
+                       int32_t &deepest, ChunkGraphs *cg, bool wide_ok) {
     const int32_t n = g->n;
     const bool prof = d_stats != nullptr;
     auto measure = [&](int32_t L) {
@@ -270,12 +294,17 @@ hipError_t drive_batch(bc_graph_s *g, BatchDev &d, const ExtTables &ext, const i
         d.stats = m ? d_stats : nullptr;
     };
     const bool use_ext = g->sigma_ext.load();
-    d.narrow = (use_ext || g->sigma_wide.load()) ? 0 : 1;
+    const bool wide = use_ext || g->sigma_wide.load();
+    how = BatchOutcome::Done;
+    deepest = 0;
+    if (wide && !wide_ok) {  // uint32-sized rows cannot take double counts
+        how = BatchOutcome::NeedWide;
+        return hipSuccess;
+    }
+    d.narrow = wide ? 0 : 1;
     d.xs = use_ext ? ext.xs : nullptr;
     d.xmax = use_ext ? ext.xmax : nullptr;
     d.xe = use_ext ? ext.xe : nullptr;
-    how = BatchOutcome::Done;
-    deepest = 0;
     hipError_t e = batch_start(d, lanes_dev, nl, stream);
     if (e != hipSuccess) return e;
     int32_t L0 = 0;
@@ -450,8 +479,13 @@ bc_status run_batch_plan(bc_graph_s *g, const std::vector<int32_t> &s_int,
         // (measured runs launch every step: the events go around each launch)
         e = drive_batch(g, d, ext, d_lanes + bp.first, nl, ws->h_ctrl, stream, ws->timer,
                         prof ? ws->d_stats : nullptr, stride, how, deepest,
-                        graphs && !prof ? &ws->graphs : nullptr);
+                        graphs && !prof ? &ws->graphs : nullptr, ws->wide);
         if (e != hipSuccess) return fail(from_hip(e));
+        if (how == BatchOutcome::NeedWide) {  // double rows from now on
+            st = batch_widen(g, ws);
+            if (st != BC_OK) return fail(st);
+            continue;
+        }
         if (how == BatchOutcome::Rerun) continue;
         if (how == BatchOutcome::Grow) {  // level array full: grow it, run the batch again
             st = batch_grow_levels(g, ws, ws->lcap * 2);

@@ -122,6 +122,10 @@ struct BatchWS {
     hipEvent_t done = nullptr;
     bool busy = false;
     int32_t gen = 0;           // the graph's work-item tables it was built for
+    // sigma rows sized for doubles (else for uint32: a graph whose counts fit
+    // 32 bits); widened by a separate allocation when the graph needs it
+    bool wide = true;
+    void *wide_sigma = nullptr;
     BatchDev dev{};
     ChunkGraphs graphs;        // replayed level chunks (BC_LOOP_GRAPH)
 };
@@ -333,12 +337,17 @@ struct ExtTables {
     unsigned long long *xmax;
     int32_t *xe;
 };
-enum class BatchOutcome { Done, Rerun, Grow };
+// Rerun: run the batch again (the graph's rows became wider); Grow: with a
+// longer level array; NeedWide: the graph takes double rows and the
+// workspace's sigma rows are uint32-sized: widen them, then run the batch.
+enum class BatchOutcome { Done, Rerun, Grow, NeedWide };
 // cg: replay the level chunks as captured graphs (NULL: launch every step).
+// wide_ok: d's sigma rows hold doubles (else uint32 only: a graph that takes
+// double rows gets NeedWide before anything is launched).
 hipError_t drive_batch(bc_graph_s *g, BatchDev &d, const ExtTables &ext, const int32_t *lanes_dev,
                        int32_t nl, int32_t *h_ctrl, hipStream_t stream, LaunchTimer &timer,
                        unsigned long long *d_stats, int32_t stride, BatchOutcome &how,
-                       int32_t &deepest, ChunkGraphs *cg);
+                       int32_t &deepest, ChunkGraphs *cg, bool wide_ok);
 
 // ---- graph residency (bc_rt_graph.hip) ----
 void free_graph_arrays(bc_graph_s *g);

@@ -785,3 +785,33 @@ def test_graph_loop_exports_per_source_state():
         od, osg, _, _ = oracle.single_source(g.row_ptr, g.col_idx, int(src[i]), with_delta=False)
         assert np.array_equal(dist_h[i], od)
         check_sigma(sigma_h[i], osg)
+
+
+def _disjoint_union(a, b):
+    ra = np.repeat(np.arange(a.n), np.diff(a.row_ptr))
+    rb = np.repeat(np.arange(b.n), np.diff(b.row_ptr)) + a.n
+    src = np.concatenate([ra, rb])
+    dst = np.concatenate([a.col_idx, b.col_idx + a.n])
+    keep = src < dst
+    return gg.csr_from_edges(a.n + b.n, src[keep], dst[keep])
+
+
+@pytest.mark.parametrize("conc", [1, 2])
+def test_uint32_sized_workspaces_widen_when_counts_pass_32_bits(conc):
+    """Workspaces start with uint32-sized sigma rows; when a batch's counts
+    pass 32 bits the graph switches to double rows and every workspace that
+    runs a later batch (of this call, of another part, or pooled for the next
+    call) is widened first.  Sources on an R-MAT component (counts fit) and on
+    a 40 x 40 lattice (they do not), in separate batches."""
+    g = _disjoint_union(gg.rmat(10, 8, seed=31), gg.grid_full(40, 40))
+    rng = np.random.default_rng(32)
+    src = np.concatenate([rng.choice(1024, 130, replace=False),
+                          1024 + rng.choice(1600, 60, replace=False)]).astype(np.int32)
+    want = oracle_bc(g, src)
+    with bcm.Graph(g.n, g.row_ptr, g.col_idx) as G:
+        first = batched(G, src, concurrency=conc, level_loop=bcm.BC_LOOP_HOST)
+        check_bc(first, want)
+        # the pooled workspaces (some built narrow) serve the next calls
+        again = batched(G, src, concurrency=conc, level_loop=bcm.BC_LOOP_HOST)
+        check_bc(again, want)
+        check_bc(batched(G, src[:64], level_loop=bcm.BC_LOOP_HOST), oracle_bc(g, src[:64]))
