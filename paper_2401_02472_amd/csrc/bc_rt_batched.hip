@@ -801,8 +801,9 @@ bc_status run_graphs(bc_graph_s *const *gs, int32_t ng, const int32_t *const *so
                      int32_t *loops, hipStream_t stream) {
     // BC_LOOP_AUTO: the graphs that join are the prefix, by one batch's
     // estimated device-loop time, that minimises the launch (its slowest
-    // batch: the batches run side by side, one workgroup each) plus the
-    // host-loop estimates of the graphs left out (the cost model of use_fused)
+    // batch, times the rounds of 256 batches: the batches run side by side,
+    // one workgroup each) plus the host-loop estimates of the graphs left out
+    // (the cost model of use_fused)
     std::vector<char> join((size_t)ng, level_loop == BC_LOOP_HOST ? 0 : 1);
     if (level_loop == BC_LOOP_AUTO) {
         std::vector<int32_t> idx;
@@ -818,9 +819,11 @@ bc_status run_graphs(bc_graph_s *const *gs, int32_t ng, const int32_t *const *so
         for (int32_t i : idx) rest += host_t(i);
         double best = rest;  // nothing joins
         size_t best_j = 0;
+        double batches = 0.0;
         for (size_t j = 0; j < idx.size(); ++j) {
             rest -= host_t(idx[j]);
-            const double t = dev_t(idx[j]) + rest;
+            batches += std::ceil((double)ks[idx[j]] / kWave);
+            const double t = dev_t(idx[j]) * std::ceil(batches / 256.0) + rest;
             if (t < best) {
                 best = t;
                 best_j = j + 1;
