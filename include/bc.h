@@ -291,7 +291,10 @@ bc_status bc_run_detail(bc_graph_t g, const int32_t *sources, int32_t k, const b
 /* Device bytes one run with k sources and the given options would take for its
  * workspaces (for admission control): one per concurrent part, or the
  * device-resident loop's per-batch pool, at the graph's current level-array
- * estimate (a deeper graph grows it).  opt may be NULL. */
+ * estimate (a deeper graph grows it) and row width: while the graph's path
+ * counts have fitted 32 bits, host-loop workspaces hold uint32 sigma rows, and
+ * the run in which a count first passes 32 bits adds double rows (512 bytes
+ * per vertex and 64 sources) to each part's workspace.  opt may be NULL. */
 bc_status bc_workspace_bytes(bc_graph_t g, int32_t k, const bc_options *opt, size_t *bytes);
 
 /* Free pooled workspaces that are idle (the one-source and batched pools'
