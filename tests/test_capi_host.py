@@ -83,6 +83,16 @@ def test_invalid_arguments_rejected():
     assert lib.bc_set_weights(None, None) == bcm.BC_ERR_INVALID_ARG
     assert lib.bc_sssp(None, 0, None, None) == bcm.BC_ERR_INVALID_ARG
     assert lib.bc_pagerank(None, 0.85, 0.0, 10, None, None, None) == bcm.BC_ERR_INVALID_ARG
+    # several graphs: a negative count, NULL arrays, a NULL graph, another loop
+    assert lib.bc_run_graphs(None, -1, None, None, None, 0, None, None) == bcm.BC_ERR_INVALID_ARG
+    assert lib.bc_run_graphs(None, 1, None, None, None, 0, None, None) == bcm.BC_ERR_INVALID_ARG
+    one = (ctypes.c_void_p * 1)(None)
+    k = np.zeros(1, np.int32)
+    assert lib.bc_run_graphs(one, 1, one, k.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), one,
+                             0, None, None) == bcm.BC_ERR_INVALID_ARG
+    assert lib.bc_run_graphs(None, 0, None, None, None, bcm.BC_LOOP_GRAPH, None, None) == \
+        bcm.BC_ERR_INVALID_ARG
+    assert lib.bc_run_graphs(None, 0, None, None, None, 0, None, None) == bcm.BC_OK
     assert lib.bc_destroy_graph(None) == bcm.BC_OK
 
 
