@@ -193,10 +193,7 @@ constexpr int32_t kRelLevel = 1 << 30;
 // set 1 the sparse step, set 2 the completion of split vertices; each wave of
 // those kernels stores (vertices, arcs) of the new frontier it found in its
 // own slot, and the bookkeeping kernel adds them up (no shared counter).
-// 4096 workgroups of 256 (16,384 waves, about three rounds of the device at five
-// waves per SIMD): finer-grained than 2048 for the uneven hub items (R-MAT scale
-// 22: 68.4 -> 66.0 ms per 256 sources; the grid 22.5 -> 22.1 ms; ER unchanged).
-constexpr int kMaxGridBlocks = 4096;
+constexpr int kMaxGridBlocks = 2048;
 // Waves per SIMD the batched level kernels (forward, sparse pull, reverse)
 // are compiled for: at most 96 VGPRs each, a few values spilled.  Their waves
 // mostly wait on memory, and the fifth wave per SIMD gave 6-7 % on the
