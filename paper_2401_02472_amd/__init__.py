@@ -56,6 +56,35 @@ def _i32(a) -> np.ndarray:
     return np.ascontiguousarray(np.asarray(a), dtype=np.int32)
 
 
+def _device_tensor(t, dtype: str, where: str):
+    """Checks that `t` is a contiguous torch tensor of `dtype` ("float64" or
+    "int32") in device memory: the library reads or writes it through its
+    raw pointer, so a wrong element size or a host buffer would be accessed
+    out of bounds on the device."""
+    import torch
+    want = {"float64": torch.float64, "int32": torch.int32}[dtype]
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{where}: expected a torch tensor, got {type(t).__name__}")
+    if t.dtype != want:
+        raise TypeError(f"{where}: expected a {want} tensor, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{where}: the tensor must be contiguous")
+    if not t.is_cuda:
+        raise ValueError(f"{where}: the tensor must be in device memory")
+    return t
+
+
+def _fits(t, n: int, where: str):
+    """Checks that the device tensor `t` holds at least n entries; returns its pointer."""
+    if t.numel() < n:
+        raise ValueError(f"{where}: the tensor holds {t.numel()} entries, {n} are written")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _graph_n(g) -> int:
+    return bc_graph_info(g)[0]
+
+
 def _ptr(a: np.ndarray, ctype):
     return a.ctypes.data_as(ctypes.POINTER(ctype))
 
@@ -90,11 +119,23 @@ def bc_create_graph(n: int, row_ptr, col_idx, flags: int = 0, stream=None) -> in
     lib = _capi.load()
     out = ctypes.c_void_p()
     if flags & BC_GRAPH_INPUT_ON_DEVICE:
+        _device_tensor(row_ptr, "int32", "bc_create_graph row_ptr")
+        _device_tensor(col_idx, "int32", "bc_create_graph col_idx")
+        if n >= 0:
+            _fits(row_ptr, n + 1, "bc_create_graph row_ptr")
+            import torch
+            torch.cuda.synchronize(row_ptr.device)
+            _fits(col_idx, max(int(row_ptr[n].item()), 0), "bc_create_graph col_idx")
         rp_p, ci_p = ctypes.c_void_p(row_ptr.data_ptr()), ctypes.c_void_p(col_idx.data_ptr())
         keep = None
         st_h = _stream_handle(stream)
     else:
         rp, ci = _i32(row_ptr), _i32(col_idx)
+        # the library reads n + 1 offsets and row_ptr[n] column ids
+        if n >= 0 and rp.size < n + 1:
+            raise ValueError(f"bc_create_graph: row_ptr holds {rp.size} offsets, {n + 1} needed")
+        if n >= 0 and ci.size < max(int(rp[n]), 0):
+            raise ValueError(f"bc_create_graph: col_idx holds {ci.size} ids, row_ptr[n] = {int(rp[n])}")
         keep = (rp, ci)
         rp_p, ci_p = ctypes.c_void_p(rp.ctypes.data), ctypes.c_void_p(ci.ctypes.data)
         st_h = ctypes.c_void_p(0) if stream is None else _stream_handle(stream)
@@ -130,10 +171,11 @@ def bc_run_async(g: int, sources, bc_out, options=None, stream=None) -> None:
     """BC into `bc_out` (a float64 device tensor of n entries), ordered on `stream`
     (default: torch's current stream)."""
     src = _i32(sources)
+    _device_tensor(bc_out, "float64", "bc_run_async bc_out")
+    out_p = _fits(bc_out, _graph_n(g), "bc_run_async bc_out")
     opt = ctypes.byref(options) if options is not None else None
     st = _capi.load().bc_run_async(ctypes.c_void_p(g), _ptr(src, ctypes.c_int32), int(src.size),
-                                   ctypes.c_void_p(bc_out.data_ptr()), opt,
-                                   _stream_handle(stream))
+                                   out_p, opt, _stream_handle(stream))
     _check(st, "bc_run_async", bc_out)
 
 
@@ -141,9 +183,10 @@ def bc_run_async_noalloc(g: int, sources, bc_out, stream=None) -> None:
     """bc_run_async without any allocation: the run's device buffers come from
     the library's fixed per-device array (BC_NOALLOC_SCRATCH_BYTES)."""
     src = _i32(sources)
+    _device_tensor(bc_out, "float64", "bc_run_async_noalloc bc_out")
+    out_p = _fits(bc_out, _graph_n(g), "bc_run_async_noalloc bc_out")
     st = _capi.load().bc_run_async_noalloc(ctypes.c_void_p(g), _ptr(src, ctypes.c_int32),
-                                           int(src.size), ctypes.c_void_p(bc_out.data_ptr()),
-                                           _stream_handle(stream))
+                                           int(src.size), out_p, _stream_handle(stream))
     _check(st, "bc_run_async_noalloc", bc_out)
 
 
@@ -151,11 +194,17 @@ def bc_run_multi(g: int, requests, outs, stream=None) -> None:
     """Several requests (a list of source arrays) in one call; outs[r] is a float64
     device tensor of n entries that receives request r's BC."""
     srcs = [_i32(r) for r in requests]
+    if len(outs) != len(srcs):
+        raise ValueError("bc_run_multi: requests and outs differ in length")
+    for o in outs:
+        _device_tensor(o, "float64", "bc_run_multi outs")
+    n = _graph_n(g) if outs else 0
+    ptrs = (ctypes.c_void_p * max(len(srcs), 1))(*[_fits(o, n, "bc_run_multi outs")
+                                                   for o in outs])
     start = np.zeros(len(srcs) + 1, dtype=np.int32)
     start[1:] = np.cumsum([s.size for s in srcs])
     flat = np.concatenate(srcs) if srcs else np.zeros(0, np.int32)
     flat = np.ascontiguousarray(flat, dtype=np.int32)
-    ptrs = (ctypes.c_void_p * max(len(srcs), 1))(*[o.data_ptr() for o in outs])
     st = _capi.load().bc_run_multi(ctypes.c_void_p(g), _ptr(flat, ctypes.c_int32),
                                    _ptr(start, ctypes.c_int32), len(srcs), ptrs,
                                    _stream_handle(stream))
@@ -172,11 +221,14 @@ def bc_run_graphs(graphs, sources, outs, level_loop: int = BC_LOOP_AUTO, stream=
     srcs = [_i32(s) for s in sources]
     if not (len(handles) == len(srcs) == len(outs)):
         raise ValueError("graphs, sources and outs differ in length")
+    for o in outs:
+        _device_tensor(o, "float64", "bc_run_graphs outs")
     m = max(len(handles), 1)
     h_arr = (ctypes.c_void_p * m)(*handles)
     s_arr = (ctypes.c_void_p * m)(*[s.ctypes.data if s.size else None for s in srcs])
     ks = np.ascontiguousarray([s.size for s in srcs] or [0], dtype=np.int32)
-    o_arr = (ctypes.c_void_p * m)(*[o.data_ptr() for o in outs])
+    o_arr = (ctypes.c_void_p * m)(*[_fits(o, _graph_n(h), "bc_run_graphs outs")
+                                    for h, o in zip(handles, outs)])
     loops = np.zeros(m, dtype=np.int32)
     st = _capi.load().bc_run_graphs(h_arr, len(handles), s_arr, _ptr(ks, ctypes.c_int32), o_arr,
                                     int(level_loop), _ptr(loops, ctypes.c_int32),
@@ -188,6 +240,9 @@ def bc_run_graphs(graphs, sources, outs, level_loop: int = BC_LOOP_AUTO, stream=
 def bc_set_weights(g: int, weight) -> None:
     """Arc weights for SSSP (int32 >= 0, in the order of the graph's col_idx)."""
     w = _i32(weight)
+    nnz = bc_graph_info(g)[1]
+    if w.size != nnz:  # the library reads one weight per arc
+        raise ValueError(f"bc_set_weights: {w.size} weights for {nnz} arcs")
     _check(_capi.load().bc_set_weights(ctypes.c_void_p(g), _ptr(w, ctypes.c_int32)),
            "bc_set_weights")
 
@@ -195,8 +250,9 @@ def bc_set_weights(g: int, weight) -> None:
 def bc_sssp(g: int, source: int, dist_out, stream=None) -> None:
     """Shortest-path distances from `source` into dist_out (int32 device tensor of
     n entries; -1 where unreachable)."""
-    st = _capi.load().bc_sssp(ctypes.c_void_p(g), int(source),
-                              ctypes.c_void_p(dist_out.data_ptr()), _stream_handle(stream))
+    _device_tensor(dist_out, "int32", "bc_sssp dist_out")
+    out_p = _fits(dist_out, _graph_n(g), "bc_sssp dist_out")
+    st = _capi.load().bc_sssp(ctypes.c_void_p(g), int(source), out_p, _stream_handle(stream))
     _check(st, "bc_sssp", dist_out)
 
 
@@ -204,10 +260,11 @@ def bc_pagerank(g: int, pr_out, damping: float = 0.85, tol: float = 1e-10, max_i
                 stream=None) -> int:
     """PageRank into pr_out (float64 device tensor of n entries); returns the
     iterations run."""
+    _device_tensor(pr_out, "float64", "bc_pagerank pr_out")
+    out_p = _fits(pr_out, _graph_n(g), "bc_pagerank pr_out")
     it = ctypes.c_int32(0)
     st = _capi.load().bc_pagerank(ctypes.c_void_p(g), float(damping), float(tol), int(max_iter),
-                                  ctypes.c_void_p(pr_out.data_ptr()), ctypes.byref(it),
-                                  _stream_handle(stream))
+                                  out_p, ctypes.byref(it), _stream_handle(stream))
     _check(st, "bc_pagerank", pr_out)
     return int(it.value)
 

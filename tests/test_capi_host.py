@@ -159,3 +159,42 @@ def test_directed_flag_keeps_structure_checks():
     assert st == bcm.BC_ERR_INVALID_GRAPH
     st, _ = _create(2, [0, 2, 1], [1, 0], flags=bcm.BC_GRAPH_DIRECTED)
     assert st == bcm.BC_ERR_INVALID_GRAPH
+
+
+def test_binding_checks_device_tensors_before_any_call():
+    # the wrappers pass raw pointers, so an output of the wrong element size or
+    # in host memory is refused before the library is reached (handle 0 is never
+    # looked up: these checks come first)
+    import torch
+    cases = [
+        (lambda t: bcm.bc_run_async(0, [0], t), "float64"),
+        (lambda t: bcm.bc_run_async_noalloc(0, [0], t), "float64"),
+        (lambda t: bcm.bc_run_multi(0, [[0]], [t]), "float64"),
+        (lambda t: bcm.bc_run_graphs([0], [[0]], [t]), "float64"),
+        (lambda t: bcm.bc_sssp(0, 0, t), "int32"),
+        (lambda t: bcm.bc_pagerank(0, t), "float64"),
+    ]
+    for call, dtype in cases:
+        other = torch.float32 if dtype == "float64" else torch.int64
+        good = getattr(torch, dtype)
+        with pytest.raises(TypeError):
+            call(np.zeros(8))                                   # not a tensor
+        with pytest.raises(TypeError):
+            call(torch.zeros(8, dtype=other))                   # wrong element size
+        with pytest.raises(ValueError, match="contiguous"):
+            call(torch.zeros(16, dtype=good)[::2])
+        with pytest.raises(ValueError, match="device memory"):
+            call(torch.zeros(8, dtype=good))                    # host tensor
+    with pytest.raises(ValueError, match="differ in length"):
+        bcm.bc_run_multi(0, [[0], [1]], [])
+
+
+def test_binding_checks_host_csr_extents():
+    # the library reads n + 1 offsets and row_ptr[n] column ids from host memory
+    with pytest.raises(ValueError, match="row_ptr"):
+        bcm.bc_create_graph(3, np.array([0, 1, 2], np.int32), np.array([1, 0], np.int32))
+    with pytest.raises(ValueError, match="col_idx"):
+        bcm.bc_create_graph(2, np.array([0, 1, 3], np.int32), np.array([1, 0], np.int32))
+    # a CSR of the right extents still reaches the library's own checks
+    st, _ = _create(2, [0, 1, 2], [1, 5])
+    assert st == bcm.BC_ERR_INVALID_GRAPH

@@ -143,3 +143,37 @@ def test_invalid_calls_are_rejected():
             bcm.bc_run_graphs([G], [np.array([0], np.int32)], [out], level_loop=bcm.BC_LOOP_GRAPH)
         assert ei.value.status == bcm.BC_ERR_INVALID_ARG
         bcm.bc_run_graphs([], [], [])                # nothing to do
+
+
+def test_binding_refuses_short_buffers():
+    # outputs shorter than the graph and inputs shorter than the CSR the
+    # library would read are refused before any launch; the buffers are left
+    # as they were
+    import torch
+    g = gg.rmat(8, 8, seed=9)
+    with bcm.Graph(g.n, g.row_ptr, g.col_idx) as G:
+        short = torch.full((g.n - 1,), -1.0, dtype=torch.float64, device="cuda")
+        for call in (lambda: bcm.bc_run_async(G.handle, [0], short),
+                     lambda: bcm.bc_run_async_noalloc(G.handle, [0], short),
+                     lambda: bcm.bc_run_multi(G.handle, [[0]], [short]),
+                     lambda: bcm.bc_run_graphs([G], [[0]], [short]),
+                     lambda: bcm.bc_pagerank(G.handle, short)):
+            with pytest.raises(ValueError, match="entries"):
+                call()
+        with pytest.raises(ValueError, match="entries"):
+            bcm.bc_sssp(G.handle, 0, torch.zeros(g.n - 1, dtype=torch.int32, device="cuda"))
+        with pytest.raises(ValueError, match="weights"):
+            G.set_weights(np.ones(g.col_idx.size - 1, np.int32))
+        torch.cuda.synchronize()
+        assert bool((short == -1.0).all())
+        # a full-length output still runs
+        out = torch.empty(g.n, dtype=torch.float64, device="cuda")
+        bcm.bc_run_async(G.handle, [0, 1], out)
+        torch.cuda.synchronize()
+        check_bc(out.cpu().numpy(), oracle_bc(g, np.array([0, 1], np.int32)))
+    rp = torch.from_numpy(g.row_ptr).cuda()
+    ci = torch.from_numpy(g.col_idx).cuda()
+    with pytest.raises(ValueError, match="col_idx"):
+        bcm.bc_create_graph(g.n, rp, ci[:-1], flags=bcm.BC_GRAPH_INPUT_ON_DEVICE)
+    with pytest.raises(ValueError, match="row_ptr"):
+        bcm.bc_create_graph(g.n, rp[:-1], ci, flags=bcm.BC_GRAPH_INPUT_ON_DEVICE)
