@@ -37,7 +37,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-from . import BC_ERR_OUT_OF_MEMORY, BCError
+from . import BC_ERR_INVALID_ARG, BC_ERR_OUT_OF_MEMORY, BCError
 
 
 @dataclass
@@ -133,6 +133,12 @@ class BCServer:
         req = Request(graph_id, src, time.perf_counter())
         if graph_id not in self._queues:
             req.future.set_exception(KeyError(f"unknown graph {graph_id!r}"))
+            return req.future
+        # a source outside the graph fails the request here: inside a launch
+        # it would fail every request batched with it
+        n = getattr(self.graphs[graph_id], "n", None)
+        if n is not None and src.size and (int(src.min()) < 0 or int(src.max()) >= int(n)):
+            req.future.set_exception(BCError(BC_ERR_INVALID_ARG, "submit"))
             return req.future
         need = self.executor.bytes_needed(graph_id, req.k, 1)
         if need > self.budget:

@@ -180,3 +180,22 @@ def test_no_trim_when_the_launch_would_still_wait(graphs):
         assert picked is None and ex.trimmed == []
     finally:
         srv.close(wait=False)
+
+
+def test_source_outside_the_graph_fails_only_its_request(graphs):
+    from paper_2401_02472_amd import BC_ERR_INVALID_ARG
+    ex = FakeExecutor(graphs, delay=0.05)
+    srv = BCServer(graphs, budget=10**9, slots=1, max_lanes=256, executor=ex)
+    g = graphs["a"]
+    good = [np.array([i, i + 1], np.int32) for i in range(4)]
+    futs = [srv.submit("a", s) for s in good[:2]]
+    bad = [srv.submit("a", [0, g.n]), srv.submit("a", [-1])]
+    futs += [srv.submit("a", s) for s in good[2:]]
+    for f in bad:
+        with pytest.raises(BCError) as ei:
+            f.result(timeout=5)
+        assert ei.value.status == BC_ERR_INVALID_ARG
+    for s, f in zip(good, futs):
+        np.testing.assert_array_equal(f.result(timeout=10), oracle.bc(g.row_ptr, g.col_idx, s)[0])
+    srv.close()
+    assert sum(ex.launch_sizes) == len(good)
