@@ -54,3 +54,16 @@ def test_counter_summaries_are_read_only_at_their_batch_width(path, kernel, work
     w = int(m.group(1))
     assert bench.read_traffic(kernel, workload, h, w) is not None
     assert bench.read_traffic(kernel, workload, h, 2 * w) is None
+
+
+@pytest.mark.parametrize("argv,env", [(["--gpus", "2"], {}), (["--gpus", "8"], {}),
+                                      ([], {"WORLD_SIZE": "4"})])
+def test_more_than_one_gpu_is_refused_before_any_device_work(argv, env):
+    import subprocess
+    import sys
+    e = dict(os.environ, **env)
+    r = subprocess.run([sys.executable, os.path.join(bench.ROOT, "bench.py"), *argv],
+                       capture_output=True, text=True, env=e, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout == ""
