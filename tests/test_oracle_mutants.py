@@ -8,7 +8,6 @@ that part of the oracle unchecked.
 import os
 import subprocess
 
-import numpy as np
 import pytest
 
 import graphgen as gg
